@@ -1,0 +1,326 @@
+"""FP64 CPU oracle for the Habitat-GS sensor-rendering path (arXiv 2604.12626).
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the package smoke check and the
+benchmark's CPU-baseline leg are the only callers.  The product (the HIP
+library and its binding) never imports this module, and this module imports
+nothing from the product.
+
+The arithmetic lives in ``gs_oracle.c`` (plain C, double precision, OpenMP);
+this file builds it with gcc, loads it with ctypes and marshals numpy arrays.
+
+Each function names the passage it follows:
+  * Sec. 2.2 / Sec. 3.2 of the paper: explicit anisotropic 3D Gaussians
+    rendered by tile-based rasterization into colour and depth; scene and all
+    avatars in one rasterization pass.
+  * Sec. 3.1 / Sec. 3.3: canonical avatar Gaussians posed by linear blend
+    skinning with per-frame joint matrices.
+The numeric readings where the paper is silent (camera axes, pixel centres,
+near plane 0.2, low-pass 0.3, 3-sigma radius, rect rule, SH convention,
+thresholds as FP32 values) are listed in the design notes.
+
+Parity pins: every function here is checked by ``tests/test_oracle_*.py``
+against closed forms, invariants, brute force and independent derivations.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gs_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+PROJ_STRIDE = 32
+MAXC = 8
+CAND_STRIDE = 10
+
+# The compositing thresholds are FP32 values promoted to double.
+ALPHA_MAX = float(np.float32(0.99))
+ALPHA_MIN = float(np.float32(1.0 / 255.0))
+T_MIN = float(np.float32(1e-4))
+
+
+def build(force: bool = True) -> str:
+    """Compile gs_oracle.c with gcc into liboracle.so (next to the source)."""
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=gnu11", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    build(force=False)
+    lib = ctypes.CDLL(_LIB_PATH)
+    P = ctypes.c_void_p
+    i64, i32, f64 = ctypes.c_int64, ctypes.c_int, ctypes.c_double
+    lib.or_sh_basis.argtypes = [i32, P, P, P]
+    lib.or_project.argtypes = [i64, i32, P, P, P, P, P, P, P, P, P, P]
+    lib.or_bin.argtypes = [i64, P, P, i32, i32, i32, i32, P, P, P, i64, P]
+    lib.or_bin.restype = i64
+    lib.or_composite.argtypes = [i32, P, P, P, P, P, P, P]
+    lib.or_render_view.argtypes = [i64, P, P, P, P, P, P, P]
+    lib.or_backward_2d.argtypes = [i64, P, P, P, P, P, P]
+    lib.or_backward_3d.argtypes = [i64, i32, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P]
+    lib.or_lbs.argtypes = [i64, P, P, P, P, P, P, i32, P, P]
+    lib.or_lbs_backward.argtypes = [i64, P, P, P, P, P, P, i32, P, P, P, P, P]
+    lib.or_version.restype = i32
+    lib.or_cov3d.argtypes = [i64, P, P, P]
+    _ = f64
+    _lib = lib
+    return lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f32(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float32)
+
+
+def params(width, height, near=0.2, lowpass=0.3, sigma_cut=3.0, fov_clamp=1.3, bg=(0.0, 0.0, 0.0), tile=16,
+           d_skip=1e-4, d_stop=1e-4, d_near=1e-5, d_int=1e-5, d_tie=1e-6, max_flips=3):
+    """Rendering constants plus the oracle's decision margins (all double).
+
+    The constants near/lowpass/sigma_cut/fov_clamp are FP32 values on the GPU
+    side; they are promoted from FP32 here too so both sides use one value."""
+    f = lambda x: float(np.float32(x))
+    return np.array([width, height, f(near), f(lowpass), f(sigma_cut), f(fov_clamp), ALPHA_MAX, ALPHA_MIN, T_MIN,
+                     f(bg[0]), f(bg[1]), f(bg[2]), tile, d_skip, d_stop, d_near, d_int, d_tie, max_flips],
+                    dtype=np.float64)
+
+
+def cam_array(cam):
+    """Camera as 16 doubles: R (row-major world->camera, OpenCV axes), t, fx, fy, cx, cy.
+
+    Accepts the 16-float32 camera record the GPU path reads; promoted exactly."""
+    return np.ascontiguousarray(np.asarray(cam, dtype=np.float32).astype(np.float64).reshape(16))
+
+
+def sh_basis(D, dirs):
+    """Real SH (Condon-Shortley phase, l-major, m=-l..l) and gradients at unit directions."""
+    lib = _load()
+    dirs = np.ascontiguousarray(dirs, dtype=np.float64).reshape(-1, 3)
+    K = (D + 1) ** 2
+    Y = np.zeros((len(dirs), K))
+    dY = np.zeros((len(dirs), K, 3))
+    for i in range(len(dirs)):
+        y = np.zeros(K)
+        dy = np.zeros((K, 3))
+        lib.or_sh_basis(D, _p(dirs[i]), _p(y), _p(dy))
+        Y[i], dY[i] = y, dy
+    return Y, dY
+
+
+def cov3d(log_scales, quats):
+    """O1/O2: 3D covariance rows (xx, xy, xz, yy, yz, zz) in double."""
+    lib = _load()
+    lsc, q = _f32(log_scales).reshape(-1, 3), _f32(quats).reshape(-1, 4)
+    out = np.zeros((len(lsc), 6))
+    lib.or_cov3d(len(lsc), _p(lsc), _p(q), _p(out))
+    return out
+
+
+def project(g, cam, prm):
+    """Per-Gaussian projection of one gaussian set into one camera (O1-O9).
+
+    g: dict with means [n,3], log_scales [n,3], quats [n,4], opacity [n],
+    sh [n,K,3], sh_degree, optional cov6 [n,6] and use_cov6 [n] (uint8).
+    Returns the [n, PROJ_STRIDE] double table (column meaning in gs_oracle.c)."""
+    lib = _load()
+    n = len(g["means"])
+    D = int(g["sh_degree"])
+    means = _f32(g["means"])
+    lsc = _f32(g.get("log_scales"))
+    quats = _f32(g.get("quats"))
+    cov6 = _f32(g.get("cov6"))
+    use = g.get("use_cov6")
+    use = None if use is None else np.ascontiguousarray(use, dtype=np.uint8)
+    opac = _f32(g["opacity"])
+    sh = _f32(g["sh"])
+    out = np.zeros((n, PROJ_STRIDE))
+    lib.or_project(n, D, _p(means), _p(lsc), _p(quats), _p(cov6), _p(use), _p(opac), _p(sh), _p(cam_array(cam)),
+                   _p(prm), _p(out))
+    return out
+
+
+def bin_records(rec, visible, W, H, n_views, tile=16, capacity=None):
+    """Plain binning of FP32 records: tiles_touched, sorted keys/vals, ranges, K."""
+    lib = _load()
+    rec = np.ascontiguousarray(rec, dtype=np.float32).reshape(-1, 12)
+    m = len(rec)
+    vis = np.ascontiguousarray(visible, dtype=np.uint8)
+    TX, TY = (W + tile - 1) // tile, (H + tile - 1) // tile
+    tt = np.zeros(m, np.uint32)
+    # first pass for K
+    if capacity is None:
+        ranges = np.zeros((n_views * TX * TY, 2), np.uint32)
+        K = lib.or_bin(m, _p(rec), _p(vis), W, H, tile, n_views, _p(tt), None, None, 0, _p(ranges))
+        capacity = K
+    keys = np.zeros(max(capacity, 1), np.uint64)
+    vals = np.zeros(max(capacity, 1), np.uint32)
+    ranges = np.zeros((n_views * TX * TY, 2), np.uint32)
+    K = lib.or_bin(m, _p(rec), _p(vis), W, H, tile, n_views, _p(tt), _p(keys), _p(vals), capacity, _p(ranges))
+    return tt, keys[:min(K, capacity)], vals[:min(K, capacity)], ranges, K
+
+
+def composite(rec, vals, ranges, n_views, prm, want_cands=True):
+    """O11 compositing of FP32 records along given per-tile lists.
+
+    Returns img [V,H,W,10] (r, g, b, depth, alpha, T, n_contrib, flips,
+    composited count, composited-set signature), ncand [V,H,W] and the
+    candidate table [V,H,W,MAXC,10] (NaN rows unused) or None."""
+    lib = _load()
+    W, H = int(prm[0]), int(prm[1])
+    rec = np.ascontiguousarray(rec, dtype=np.float32).reshape(-1, 12)
+    vals = np.ascontiguousarray(vals, dtype=np.uint32)
+    ranges = np.ascontiguousarray(ranges, dtype=np.uint32)
+    img = np.zeros((n_views, H, W, CAND_STRIDE))
+    ncand = np.zeros((n_views, H, W), np.int32)
+    cands = np.zeros((n_views, H, W, MAXC, CAND_STRIDE)) if want_cands else None
+    lib.or_composite(n_views, _p(rec), _p(vals if len(vals) else np.zeros(1, np.uint32)), _p(ranges), _p(prm),
+                     _p(img), _p(ncand), _p(cands))
+    return img, ncand, cands
+
+
+def render_view(proj, prm, want_cands=True):
+    """Independent FP64 render of one view from the oracle's own projection.
+
+    Returns img [H,W,10], ncand [H,W], flags [H,W] (bit0 rect/visibility
+    ambiguity, bit1 depth near-tie), cands or None, pairs."""
+    lib = _load()
+    W, H = int(prm[0]), int(prm[1])
+    proj = np.ascontiguousarray(proj, dtype=np.float64)
+    img = np.zeros((H, W, CAND_STRIDE))
+    ncand = np.zeros((H, W), np.int32)
+    flags = np.zeros((H, W), np.uint8)
+    cands = np.zeros((H, W, MAXC, CAND_STRIDE)) if want_cands else None
+    pairs = np.zeros(1, np.int64)
+    lib.or_render_view(len(proj), _p(proj), _p(prm), _p(img), _p(ncand), _p(flags), _p(cands), _p(pairs))
+    return img, ncand, flags, cands, int(pairs[0])
+
+
+def concat_segments(segs):
+    """Union of gaussian sets in segment order (the instance order of a view).
+
+    Segments given by covariance (cov6) and by scale/rotation may be mixed; the
+    result carries use_cov6 per Gaussian.  Pure data marshalling."""
+    D = max(int(s["sh_degree"]) for s in segs)
+    K = (D + 1) ** 2
+    out = {"sh_degree": D}
+    n = [len(s["means"]) for s in segs]
+    out["means"] = np.concatenate([_f32(s["means"]) for s in segs])
+    out["opacity"] = np.concatenate([_f32(s["opacity"]) for s in segs])
+    shs = []
+    for s in segs:
+        sh = _f32(s["sh"]).reshape(len(s["means"]), -1, 3)
+        pad = np.zeros((sh.shape[0], K, 3), np.float32)
+        pad[:, :sh.shape[1]] = sh
+        shs.append(pad)
+    out["sh"] = np.concatenate(shs)
+    out["log_scales"] = np.concatenate([_f32(s["log_scales"]) if s.get("log_scales") is not None
+                                        else np.zeros((k, 3), np.float32) for s, k in zip(segs, n)])
+    out["quats"] = np.concatenate([_f32(s["quats"]) if s.get("quats") is not None
+                                   else np.tile(np.float32([1, 0, 0, 0]), (k, 1)) for s, k in zip(segs, n)])
+    if any(s.get("cov6") is not None for s in segs):
+        out["cov6"] = np.concatenate([_f32(s["cov6"]) if s.get("cov6") is not None else np.zeros((k, 6), np.float32)
+                                      for s, k in zip(segs, n)])
+        out["use_cov6"] = np.concatenate([np.full(k, s.get("cov6") is not None, np.uint8) for s, k in zip(segs, n)])
+    return out
+
+
+def render(g, cam, prm, want_cands=True):
+    """Project + render one view of gaussian set g (or a list of segments)."""
+    if isinstance(g, (list, tuple)):
+        g = concat_segments(g)
+    proj = project(g, cam, prm)
+    return (proj,) + render_view(proj, prm, want_cands)
+
+
+def backward(g, cams, prm, d_rgb, d_depth, d_alpha):
+    """O12 adjoint summed over the views in `cams` (all of the same gaussian set).
+
+    d_rgb [V,H,W,3], d_depth [V,H,W], d_alpha [V,H,W].  Returns a dict of
+    double gradients with the input layouts (means, log_scales, quats, opacity,
+    sh, cov6 when present)."""
+    lib = _load()
+    if isinstance(g, (list, tuple)):
+        g = concat_segments(g)
+    n = len(g["means"])
+    D = int(g["sh_degree"])
+    K = (D + 1) ** 2
+    means, lsc, quats = _f32(g["means"]), _f32(g.get("log_scales")), _f32(g.get("quats"))
+    cov6 = _f32(g.get("cov6"))
+    use = g.get("use_cov6")
+    use = None if use is None else np.ascontiguousarray(use, dtype=np.uint8)
+    opac, sh = _f32(g["opacity"]), _f32(g["sh"])
+    out = {"means": np.zeros((n, 3)), "log_scales": np.zeros((n, 3)), "quats": np.zeros((n, 4)),
+           "opacity": np.zeros(n), "sh": np.zeros((n, K, 3)), "cov6": np.zeros((n, 6))}
+    cams = np.asarray(cams, dtype=np.float32).reshape(-1, 16)
+    for v in range(len(cams)):
+        cam = cam_array(cams[v])
+        proj = np.zeros((n, PROJ_STRIDE))
+        lib.or_project(n, D, _p(means), _p(lsc), _p(quats), _p(cov6), _p(use), _p(opac), _p(sh), _p(cam), _p(prm),
+                       _p(proj))
+        g2d = np.zeros((n, 10))
+        dr = _f32(d_rgb[v])
+        dd = _f32(d_depth[v])
+        da = _f32(d_alpha[v])
+        lib.or_backward_2d(n, _p(proj), _p(prm), _p(dr), _p(dd), _p(da), _p(g2d))
+        lib.or_backward_3d(n, D, _p(means), _p(lsc), _p(quats), _p(cov6), _p(use), _p(opac), _p(sh), _p(cam), _p(prm),
+                           _p(g2d), _p(out["means"]), _p(out["log_scales"]), _p(out["quats"]), _p(out["opacity"]),
+                           _p(out["sh"]), _p(out["cov6"]))
+    return out
+
+
+def backward_2d(proj, prm, d_rgb, d_depth, d_alpha):
+    """Per-Gaussian screen-space adjoints [n,10] (u, v, A, B, C, o, r, g, b, z) of one view."""
+    lib = _load()
+    n = len(proj)
+    g2d = np.zeros((n, 10))
+    lib.or_backward_2d(n, _p(np.ascontiguousarray(proj)), _p(prm), _p(_f32(d_rgb)), _p(_f32(d_depth)),
+                       _p(_f32(d_alpha)), _p(g2d))
+    return g2d
+
+
+def dense_weights(joint_idx, weights, n_joints):
+    """Scatter sparse (joint index, weight) pairs into dense [n, J] rows (marshalling)."""
+    n = len(joint_idx)
+    w = np.zeros((n, n_joints), np.float64)
+    for k in range(joint_idx.shape[1]):
+        np.add.at(w, (np.arange(n), joint_idx[:, k].astype(np.int64)), weights[:, k].astype(np.float64))
+    return w
+
+
+def lbs(means, log_scales, quats, w_dense, avatar_of, skin, n_joints):
+    """O13 linear blend skinning with dense weights: (means' [n,3], cov6' [n,6]) in double."""
+    lib = _load()
+    n = len(means)
+    mo = np.zeros((n, 3))
+    co = np.zeros((n, 6))
+    w = np.ascontiguousarray(w_dense, dtype=np.float64)
+    lib.or_lbs(n, _p(_f32(means)), _p(_f32(log_scales)), _p(_f32(quats)), _p(w),
+               _p(np.ascontiguousarray(avatar_of, dtype=np.int32)), _p(_f32(skin)), n_joints, _p(mo), _p(co))
+    return mo, co
+
+
+def lbs_backward(means, log_scales, quats, w_dense, avatar_of, skin, n_joints, d_means_out, d_cov6_out):
+    """Adjoint of lbs w.r.t. canonical means, log-scales and quaternions (double)."""
+    lib = _load()
+    n = len(means)
+    dm = np.zeros((n, 3))
+    ds = np.zeros((n, 3))
+    dq = np.zeros((n, 4))
+    w = np.ascontiguousarray(w_dense, dtype=np.float64)
+    lib.or_lbs_backward(n, _p(_f32(means)), _p(_f32(log_scales)), _p(_f32(quats)), _p(w),
+                        _p(np.ascontiguousarray(avatar_of, dtype=np.int32)), _p(_f32(skin)), n_joints,
+                        _p(_f32(d_means_out)), _p(_f32(d_cov6_out)), _p(dm), _p(ds), _p(dq))
+    return dm, ds, dq

@@ -1,0 +1,290 @@
+"""Pins of the oracle's hand-derived adjoint (gradients of an image loss with
+respect to means, log-scales, quaternions, opacities and SH coefficients) and
+of its linear-blend-skinning step (Sec. 3.3 of the paper: canonical Gaussians
+posed by LBS with per-frame joint matrices).
+
+Two independent opinions on the adjoint: FP64 central finite differences of
+the oracle's own forward (discrete decisions checked unchanged) and torch
+FP64 autograd of a separately written dense renderer.  CPU only."""
+import math
+
+import numpy as np
+import pytest
+import torch
+from scipy.spatial.transform import Rotation
+
+from paper_2604_12626_amd import synth
+
+F32 = np.float32
+
+
+def _scene(seed, n, D, cam_fx=40.0):
+    rng = np.random.default_rng(seed)
+    g = synth.gaussians_cube(n, rng, sh_degree=D, center=(0.0, 0.0, 3.0))
+    g["log_scales"] += F32(1.6)  # a few px wide in a 32 x 32 image
+    g["means"][:, :2] *= F32(0.8)
+    cam = synth.look_camera([0.05, -0.03, 0.0], math.pi / 2 - 0.02, 0.03, cam_fx, cam_fx * 1.1, 16.0, 15.5)
+    # look_camera yaw/pitch are z-up; rotate the cube scene into view: place means in front of that camera
+    R = cam[:9].astype(np.float64).reshape(3, 3)
+    t = cam[9:12].astype(np.float64)
+    m = g["means"].astype(np.float64)
+    g["means"] = ((m - t) @ R).astype(F32)  # camera-space cube -> world
+    return g, cam
+
+
+def _loss(orc, g, cam, prm, G):
+    pr, img, _, _, _, _ = orc.render(g, cam, prm, want_cands=False)
+    L = (G[0] * img[..., :3]).sum() + (G[1] * img[..., 3]).sum() + (G[2] * img[..., 4]).sum()
+    sig = (pr[:, [0, 12, 13, 14, 15]].copy(), img[..., 6].copy(), img[..., 8].copy(), img[..., 9].copy())
+    return L, sig
+
+
+def _same(a, b):
+    return all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+def test_adjoint_matches_central_finite_differences(orc):
+    g, cam = _scene(11, 10, 3)
+    W = H = 32
+    prm = orc.params(W, H, bg=(0.2, 0.1, 0.4))
+    rng = np.random.default_rng(12)
+    G = (rng.standard_normal((H, W, 3)), rng.standard_normal((H, W)), rng.standard_normal((H, W)))
+    grads = orc.backward(g, cam[None], prm, G[0][None], G[1][None], G[2][None])
+    _, sig0 = _loss(orc, g, cam, prm, G)
+    checked = rejected = 0
+    for field, comps in [("means", 3), ("log_scales", 3), ("quats", 4), ("opacity", 1), ("sh", 48)]:
+        scale = np.abs(grads[field]).max()
+        assert scale > 0, field
+        for i in range(len(g["means"])):
+            for c in (range(comps) if comps <= 4 else rng.choice(comps, 6, replace=False)):
+                arr = g[field].reshape(len(g["means"]), -1)
+                x0 = float(arr[i, c])
+                h = 2e-4 * max(abs(x0), 0.05)
+                gp = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in g.items()}
+                gm = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in g.items()}
+                gp[field].reshape(len(g["means"]), -1)[i, c] = F32(x0 + h)
+                gm[field].reshape(len(g["means"]), -1)[i, c] = F32(x0 - h)
+                hp = float(gp[field].reshape(len(g["means"]), -1)[i, c])
+                hm = float(gm[field].reshape(len(g["means"]), -1)[i, c])
+                Lp, sp = _loss(orc, gp, cam, prm, G)
+                Lm, sm = _loss(orc, gm, cam, prm, G)
+                if not (_same(sp, sig0) and _same(sm, sig0)):
+                    rejected += 1
+                    continue
+                fd = (Lp - Lm) / (hp - hm)
+                ad = grads[field].reshape(len(g["means"]), -1)[i, c]
+                assert abs(fd - ad) <= 2e-5 * scale + 2e-4 * abs(ad), (field, i, c, fd, ad)
+                checked += 1
+    assert checked > 5 * rejected and checked >= 150
+
+
+# --------------------------------------------------------------------------
+# torch autograd of an independently written dense renderer (SH degree 1)
+# --------------------------------------------------------------------------
+def _torch_render(p, cam, W, H, prm):
+    dt = torch.float64
+    R = torch.tensor(cam[:9].astype(np.float64).reshape(3, 3), dtype=dt)
+    t = torch.tensor(cam[9:12].astype(np.float64), dtype=dt)
+    fx, fy, cx, cy = (float(x) for x in cam[12:16])
+    near, lp, sc, fc, amax, amin, tmin = (float(prm[k]) for k in (2, 3, 4, 5, 6, 7, 8))
+    bg = torch.tensor(prm[9:12], dtype=dt)
+    q = p["quats"] / p["quats"].norm(dim=1, keepdim=True)
+    w, x, y, z = q.unbind(1)
+    Rq = torch.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                      2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                      2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], 1).reshape(-1, 3, 3)
+    M = Rq * torch.exp(p["log_scales"])[:, None, :]
+    Sig = M @ M.transpose(1, 2)
+    tc = p["means"] @ R.T + t
+    tx, ty, tz = tc.unbind(1)
+    u = fx * tx / tz + cx
+    v = fy * ty / tz + cy
+    limx, limy = fc * 0.5 * W / fx, fc * 0.5 * H / fy
+    xr = torch.clamp(tx / tz, -limx, limx)
+    yr = torch.clamp(ty / tz, -limy, limy)
+    zero = torch.zeros_like(tz)
+    J = torch.stack([fx / tz, zero, -fx * xr / tz, zero, fy / tz, -fy * yr / tz], 1).reshape(-1, 2, 3)
+    Tm = J @ R
+    S2 = Tm @ Sig @ Tm.transpose(1, 2) + lp * torch.eye(2, dtype=dt)
+    a, b, c = S2[:, 0, 0], S2[:, 0, 1], S2[:, 1, 1]
+    det = a * c - b * b
+    A, B, C = c / det, -b / det, a / det
+    m = 0.5 * (a + c)
+    lam = m + torch.sqrt(torch.clamp(m * m - det, min=0.1))
+    r = torch.ceil(sc * torch.sqrt(lam)).detach().long()
+    cpos = -R.T @ t
+    d = p["means"] - cpos
+    d = d / d.norm(dim=1, keepdim=True)
+    c0, c1 = 0.5 / math.sqrt(math.pi), math.sqrt(3 / (4 * math.pi))
+    Y = torch.stack([torch.full_like(d[:, 0], c0), -c1 * d[:, 1], c1 * d[:, 2], -c1 * d[:, 0]], 1)
+    rgb = torch.clamp((Y[:, :, None] * p["sh"]).sum(1) + 0.5, min=0.0)
+    TX, TY = (W + 15) // 16, (H + 15) // 16
+    ix, iy = torch.floor(u).detach().long(), torch.floor(v).detach().long()
+    x0 = torch.clamp(torch.div(ix - r, 16, rounding_mode="floor"), min=0)
+    x1 = torch.clamp(torch.div(ix + r, 16, rounding_mode="floor") + 1, max=TX)
+    y0 = torch.clamp(torch.div(iy - r, 16, rounding_mode="floor"), min=0)
+    y1 = torch.clamp(torch.div(iy + r, 16, rounding_mode="floor") + 1, max=TY)
+    vis = (tz > near) & (x0 < x1) & (y0 < y1)
+    order = sorted([i for i in range(len(tz)) if vis[i]], key=lambda i: (float(tz[i].detach()), i))
+    px = torch.arange(W, dtype=dt)[None, :].expand(H, W) + 0.5
+    py = torch.arange(H, dtype=dt)[:, None].expand(H, W) + 0.5
+    txp, typ = (px.long() // 16), (py.long() // 16)
+    T = torch.ones(H, W, dtype=dt)
+    done = torch.zeros(H, W, dtype=torch.bool)
+    col = torch.zeros(H, W, 3, dtype=dt)
+    dep = torch.zeros(H, W, dtype=dt)
+    for i in order:
+        inrect = (txp >= x0[i]) & (txp < x1[i]) & (typ >= y0[i]) & (typ < y1[i])
+        dx, dy = px - u[i], py - v[i]
+        P = torch.clamp(-0.5 * (A[i] * dx * dx + C[i] * dy * dy) - B[i] * dx * dy, max=0.0)
+        al = torch.clamp(p["opacity"][i] * torch.exp(P), max=amax)
+        live = inrect & ~done & (al >= amin)
+        stop = live & (T * (1 - al) < tmin)
+        done = done | stop
+        use = live & ~stop
+        wgt = torch.where(use, al * T, torch.zeros_like(T))
+        col = col + wgt[..., None] * rgb[i]
+        dep = dep + wgt * tz[i]
+        T = torch.where(use, T * (1 - al), T)
+    col = col + T[..., None] * bg
+    return col, dep, 1 - T
+
+
+def test_adjoint_matches_torch_autograd_of_dense_renderer(orc):
+    g, cam = _scene(21, 12, 1)
+    W, H = 32, 32
+    prm = orc.params(W, H, bg=(0.3, 0.0, 0.1))
+    rng = np.random.default_rng(22)
+    # the output adjoints enter as FP32 arrays (the layout the GPU path takes)
+    G = tuple(x.astype(F32).astype(np.float64) for x in
+              (rng.standard_normal((H, W, 3)), rng.standard_normal((H, W)), rng.standard_normal((H, W))))
+    p = {k: torch.tensor(g[k].astype(np.float64), requires_grad=True)
+         for k in ("means", "log_scales", "quats", "opacity", "sh")}
+    col, dep, al = _torch_render(p, cam, W, H, prm)
+    pr, img, _, _, _, _ = orc.render(g, cam, prm, want_cands=False)
+    assert np.abs(col.detach().numpy() - img[..., :3]).max() < 1e-12
+    assert np.abs(dep.detach().numpy() - img[..., 3]).max() < 1e-12
+    L = (torch.tensor(G[0]) * col).sum() + (torch.tensor(G[1]) * dep).sum() + (torch.tensor(G[2]) * al).sum()
+    L.backward()
+    ours = orc.backward(g, cam[None], prm, G[0][None], G[1][None], G[2][None])
+    for k in ("means", "log_scales", "quats", "opacity", "sh"):
+        ref = p[k].grad.numpy().reshape(ours[k].shape)
+        assert np.abs(ref).max() > 0, k
+        assert np.allclose(ours[k], ref, rtol=1e-9, atol=1e-11 * np.abs(ref).max()), k
+
+
+def test_single_gaussian_closed_form_derivatives(orc):
+    """dC/dc = alpha T and, below the clamp, dC/do = c G; above it 0."""
+    for o, clamped in [(0.5, False), (0.9999, True)]:
+        g = {"means": np.array([[0.01, 0.01, 2.0]], F32), "log_scales": np.full((1, 3), math.log(0.05), F32),
+             "quats": np.array([[1, 0, 0, 0]], F32), "opacity": np.array([o], F32),
+             "sh": np.array([[[0.4, 0.1, -0.3]]], F32), "sh_degree": 0}
+        cam = synth.identity_camera(100.0, 100.0, 16.0, 16.0)
+        prm = orc.params(32, 32)
+        G = np.zeros((1, 32, 32, 3))
+        G[0, 16, 16, 0] = 1.0
+        gr = orc.backward(g, cam[None], prm, G, np.zeros((1, 32, 32)), np.zeros((1, 32, 32)))
+        pr = orc.project(g, cam, prm)[0]
+        dx, dy = 16.5 - pr[1], 16.5 - pr[2]
+        Gv = math.exp(-0.5 * (pr[4] * dx * dx + pr[6] * dy * dy) - pr[5] * dx * dy)
+        a = min(orc.ALPHA_MAX, float(F32(o)) * Gv)
+        Y0 = 0.5 / math.sqrt(math.pi)
+        assert abs(gr["sh"][0, 0, 0] - a * Y0) < 1e-14
+        want_do = 0.0 if clamped else pr[8] * Gv
+        assert abs(gr["opacity"][0] - want_do) < 1e-14
+
+
+# --------------------------------------------------------------------------
+# O13: linear blend skinning and the synthetic forward kinematics
+# --------------------------------------------------------------------------
+def _avatar(n=64, seed=31):
+    rng = np.random.default_rng(seed)
+    return synth.avatar_canonical(n, rng, sh_degree=0)
+
+
+def _full(c):
+    return np.array([[c[0], c[1], c[2]], [c[1], c[3], c[4]], [c[2], c[4], c[5]]])
+
+
+def test_lbs_identity_and_rigid(orc):
+    av = _avatar()
+    n, J = len(av["means"]), synth.N_JOINTS
+    w = orc.dense_weights(av["joint_idx"], av["weights"], J)
+    aof = np.zeros(n, np.int32)
+    eye = np.tile(np.eye(3, 4).reshape(12), (1, J, 1)).astype(F32)
+    mo, co = orc.lbs(av["means"], av["log_scales"], av["quats"], w, aof, eye, J)
+    wsum = w.sum(1)
+    assert np.allclose(mo, av["means"] * wsum[:, None], rtol=1e-6)
+    cov = orc.cov3d(av["log_scales"], av["quats"])
+    assert np.allclose(co, cov * (wsum ** 2)[:, None], rtol=1e-5, atol=1e-14)
+    # all weight on one rigid joint: exact rigid transform
+    Rr = Rotation.from_rotvec([0.3, -0.7, 0.2]).as_matrix()
+    tr = np.array([1.0, -2.0, 0.5])
+    M = np.zeros((1, J, 12), F32)
+    M[0, 5] = np.concatenate([Rr, tr[:, None]], 1).reshape(12)
+    w1 = np.zeros((n, J))
+    w1[:, 5] = 1.0
+    mo, co = orc.lbs(av["means"], av["log_scales"], av["quats"], w1, aof, M, J)
+    Rf, tf = M[0, 5].astype(np.float64).reshape(3, 4)[:, :3], M[0, 5].astype(np.float64).reshape(3, 4)[:, 3]
+    assert np.allclose(mo, av["means"].astype(np.float64) @ Rf.T + tf, rtol=1e-14, atol=1e-14)
+    for i in range(n):
+        assert np.allclose(_full(co[i]), Rf @ _full(cov[i]) @ Rf.T, rtol=1e-12, atol=1e-18)
+    # the same rigid matrix on every joint with weights summing to one: mean' = M mean
+    Mall = np.repeat(M[:, 5:6], J, axis=1)
+    wn = w / wsum[:, None]
+    mo, _ = orc.lbs(av["means"], av["log_scales"], av["quats"], wn, aof, Mall, J)
+    assert np.allclose(mo, av["means"].astype(np.float64) @ Rf.T + tf, rtol=1e-12, atol=1e-12)
+
+
+def test_forward_kinematics_rest_and_bone_lengths():
+    pose0 = np.zeros((synth.N_JOINTS, 3))
+    skin = synth.skinning_matrices(pose0, np.eye(3), np.zeros(3))
+    assert np.allclose(skin, np.tile(np.eye(3, 4).reshape(12), (synth.N_JOINTS, 1)), atol=1e-15)
+    # rigid root only: every joint matrix equals the root transform
+    Rr = Rotation.from_rotvec([0.0, 0.0, 1.1]).as_matrix()
+    skin = synth.skinning_matrices(pose0, Rr, np.array([2.0, 3.0, 0.0]))
+    ref = np.concatenate([Rr, np.array([[2.0], [3.0], [0.0]])], 1).reshape(12)
+    assert np.allclose(skin, np.tile(ref, (synth.N_JOINTS, 1)), atol=1e-14)
+    # random pose: posed joints keep the rest bone lengths
+    rng = np.random.default_rng(5)
+    pose, Rz, pos = synth.avatar_pose(rng)
+    skin = synth.skinning_matrices(pose, Rz, pos).reshape(-1, 3, 4)
+    posed = np.einsum("kij,kj->ki", skin[:, :, :3], synth.REST) + skin[:, :, 3]
+    for k in range(1, synth.N_JOINTS):
+        p = synth.PARENTS[k]
+        assert abs(np.linalg.norm(posed[k] - posed[p]) - np.linalg.norm(synth.REST[k] - synth.REST[p])) < 1e-12
+    # rotation parts are rotations
+    for k in range(synth.N_JOINTS):
+        assert np.allclose(skin[k, :, :3] @ skin[k, :, :3].T, np.eye(3), atol=1e-12)
+
+
+def test_lbs_backward_by_finite_differences(orc):
+    av = _avatar(24, 41)
+    n, J = len(av["means"]), synth.N_JOINTS
+    rng = np.random.default_rng(42)
+    pose, Rz, pos = synth.avatar_pose(rng)
+    skin = synth.skinning_matrices(pose, Rz, pos)[None].astype(F32)
+    w = orc.dense_weights(av["joint_idx"], av["weights"], J)
+    aof = np.zeros(n, np.int32)
+    Gm = rng.standard_normal((n, 3)).astype(F32)
+    Gc = rng.standard_normal((n, 6)).astype(F32)
+    dm, ds, dq = orc.lbs_backward(av["means"], av["log_scales"], av["quats"], w, aof, skin, J, Gm, Gc)
+
+    def L(means, lsc, q):
+        mo, co = orc.lbs(means, lsc, q, w, aof, skin, J)
+        return (Gm * mo).sum() + (Gc * co).sum()
+
+    for name, arr, ref in [("means", av["means"], dm), ("log_scales", av["log_scales"], ds), ("quats", av["quats"], dq)]:
+        for i in range(0, n, 3):
+            for c in range(arr.shape[1]):
+                x0 = float(arr[i, c])
+                h = 1e-3 * max(abs(x0), 0.1)
+                ap, am = arr.copy(), arr.copy()
+                ap[i, c] = F32(x0 + h)
+                am[i, c] = F32(x0 - h)
+                args_p = {"means": av["means"], "log_scales": av["log_scales"], "quats": av["quats"]}
+                args_m = dict(args_p)
+                args_p[name], args_m[name] = ap, am
+                fd = (L(args_p["means"], args_p["log_scales"], args_p["quats"]) -
+                      L(args_m["means"], args_m["log_scales"], args_m["quats"])) / (float(ap[i, c]) - float(am[i, c]))
+                assert abs(fd - ref[i, c]) <= 1e-6 * np.abs(ref).max() + 1e-5 * abs(ref[i, c]), (name, i, c)

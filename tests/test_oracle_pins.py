@@ -1,0 +1,448 @@
+"""Pins of the FP64 oracle's forward path against things other than itself:
+library routines (scipy rotations and spherical harmonics), closed forms,
+Monte-Carlo, exact rational brute force, an independent dense renderer and a
+50-digit evaluation.  CPU only.
+
+Each test names the step of the method it pins (Sec. 2.2 / Sec. 3.2 of the
+paper: explicit anisotropic 3D Gaussians, tile-based rasterization into colour
+and depth)."""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+from scipy import special
+from scipy.spatial.transform import Rotation
+
+from paper_2604_12626_amd import synth
+
+F32 = np.float32
+
+
+def _gauss(n, means, lsc=None, quats=None, opacity=None, sh=None, D=0):
+    means = np.asarray(means, F32).reshape(n, 3)
+    K = (D + 1) ** 2
+    return {"means": means,
+            "log_scales": np.asarray(lsc if lsc is not None else np.full((n, 3), -3.0), F32).reshape(n, 3),
+            "quats": np.asarray(quats if quats is not None else np.tile([1, 0, 0, 0], (n, 1)), F32).reshape(n, 4),
+            "opacity": np.asarray(opacity if opacity is not None else np.full(n, 0.5), F32).reshape(n),
+            "sh": np.asarray(sh if sh is not None else np.zeros((n, K, 3)), F32).reshape(n, K, 3),
+            "sh_degree": D}
+
+
+# --------------------------------------------------------------------------
+# O1 / O2: rotation and 3D covariance
+# --------------------------------------------------------------------------
+def test_covariance_matches_library_rotation(orc):
+    rng = np.random.default_rng(0)
+    q = rng.standard_normal((64, 4)).astype(F32)
+    lsc = rng.normal(-1.0, 0.7, (64, 3)).astype(F32)
+    cov = orc.cov3d(lsc, q)
+    for i in range(64):
+        R = Rotation.from_quat(q[i].astype(np.float64)[[1, 2, 3, 0]]).as_matrix()
+        S = R @ np.diag(np.exp(2.0 * lsc[i].astype(np.float64))) @ R.T
+        ref = S[[0, 0, 0, 1, 1, 2], [0, 1, 2, 1, 2, 2]]
+        assert np.allclose(cov[i], ref, rtol=1e-12, atol=1e-15 * np.abs(S).max())
+
+
+def test_covariance_eigenstructure_and_quaternion_special_cases(orc):
+    lsc = np.array([[0.5, -0.2, -1.0]] * 4, F32)
+    s45 = math.sqrt(0.5)
+    q = np.array([[1, 0, 0, 0], [-1, 0, 0, 0], [s45, 0, 0, s45], [3.0, 0, 0, 0]], F32)
+    cov = orc.cov3d(lsc, q)
+    full = lambda c: np.array([[c[0], c[1], c[2]], [c[1], c[3], c[4]], [c[2], c[4], c[5]]])
+    e2s = np.exp(2.0 * lsc[0].astype(np.float64))
+    # identity rotation, -q == q, |q| irrelevant
+    assert np.allclose(full(cov[0]), np.diag(e2s), rtol=1e-14)
+    assert np.array_equal(cov[0], cov[1])
+    assert np.allclose(cov[0], cov[3], rtol=1e-14)
+    # 90 degrees about z maps e_x to e_y: the x extent moves to y
+    S = full(cov[2])
+    assert abs(S[1, 1] - e2s[0]) < 1e-6 and abs(S[0, 0] - e2s[1]) < 1e-6 and abs(S[2, 2] - e2s[2]) < 1e-12
+    # eigenvalues are exp(2 s)
+    assert np.allclose(np.sort(np.linalg.eigvalsh(S)), np.sort(e2s), rtol=1e-12)
+    # degenerate quaternion -> identity
+    c0 = orc.cov3d(lsc[:1], np.zeros((1, 4), F32))
+    assert np.allclose(full(c0[0]), np.diag(e2s), rtol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# O3-O7: near plane, projection, EWA covariance, radius
+# --------------------------------------------------------------------------
+def test_ewa_closed_form_on_axis(orc):
+    f, z, s = 100.0, 2.0, 0.05
+    g = _gauss(1, [0.0, 0.0, z], lsc=[[math.log(s)] * 3])
+    cam = synth.identity_camera(f, f, 16.0, 16.0)
+    prm = orc.params(32, 32)
+    pr = orc.project(g, cam, prm)[0]
+    sig_f32 = float(np.exp(np.float64(F32(math.log(s)))))
+    var = (f * sig_f32 / z) ** 2 + float(F32(0.3))
+    assert pr[0] == 1.0
+    assert pr[1] == 16.0 and pr[2] == 16.0 and pr[3] == z
+    assert np.allclose(pr[26:29], [var, 0.0, var], rtol=1e-13, atol=1e-13)
+    assert np.allclose(pr[4:7], [1 / var, 0.0, 1 / var], rtol=1e-13, atol=1e-13)
+    # isotropic: the eigenvalue gap is 0, so lambda = var + sqrt(0.1) (the floor under the root)
+    lam = var + math.sqrt(0.1)
+    assert abs(pr[16] - lam) < 1e-12 * lam
+    assert pr[11] == math.ceil(3.0 * math.sqrt(lam))
+    # anisotropic on-axis: lambda is the larger variance once the gap exceeds the floor
+    g2 = _gauss(1, [0.0, 0.0, z], lsc=[[math.log(0.2), math.log(0.01), math.log(0.01)]])
+    pr2 = orc.project(g2, cam, prm)[0]
+    vx = (f * float(np.exp(np.float64(F32(math.log(0.2))))) / z) ** 2 + float(F32(0.3))
+    assert abs(pr2[16] - vx) < 1e-9 * vx
+    assert pr2[11] == math.ceil(3.0 * math.sqrt(vx))
+
+
+def test_ewa_monte_carlo_pins_jacobian(orc):
+    """Sample N(mu, Sigma), project every sample exactly with the pinhole; the
+    sample covariance of (u, v) converges to J W Sigma W^T J^T."""
+    rng = np.random.default_rng(1)
+    cam = synth.look_camera([1.0, 2.0, 1.5], 0.4, 0.15, 200.0, 180.0, 64.0, 48.0)
+    R = cam[:9].astype(np.float64).reshape(3, 3)
+    t = cam[9:12].astype(np.float64)
+    fwd = R[2]
+    mu = np.array([1.0, 2.0, 1.5]) + 2.5 * fwd + 0.4 * R[0] - 0.3 * R[1]
+    q = np.array([0.8, 0.3, -0.4, 0.2], F32)
+    lsc = np.array([-3.5, -4.2, -3.9], F32)
+    g = _gauss(1, mu, lsc=lsc[None], quats=q[None])
+    prm = orc.params(128, 96)
+    pr = orc.project(g, cam, prm)[0]
+    Rq = Rotation.from_quat(q.astype(np.float64)[[1, 2, 3, 0]]).as_matrix()
+    Sig = Rq @ np.diag(np.exp(2 * lsc.astype(np.float64))) @ Rq.T
+    x = rng.multivariate_normal(g["means"][0].astype(np.float64), Sig, size=1_000_000)
+    tc = x @ R.T + t
+    u = cam[12] * tc[:, 0] / tc[:, 2]
+    v = cam[13] * tc[:, 1] / tc[:, 2]
+    C = np.cov(np.stack([u, v]))
+    lp = float(F32(0.3))
+    S2 = np.array([[pr[26] - lp, pr[27]], [pr[27], pr[28] - lp]])
+    assert np.linalg.norm(C - S2) < 1e-2 * np.linalg.norm(S2)
+    # the projected mean is the pinhole image of the mean
+    tm = R @ g["means"][0].astype(np.float64) + t
+    assert abs(pr[1] - (cam[12] * tm[0] / tm[2] + cam[14])) < 1e-12
+    assert abs(pr[2] - (cam[13] * tm[1] / tm[2] + cam[15])) < 1e-12
+    # conic is the inverse of the 2D covariance
+    Q = np.array([[pr[4], pr[5]], [pr[5], pr[6]]])
+    assert np.allclose(Q @ np.array([[pr[26], pr[27]], [pr[27], pr[28]]]), np.eye(2), atol=1e-12)
+
+
+def test_near_plane_and_nonfinite_cull(orc):
+    g = _gauss(4, [[0, 0, 0.19], [0, 0, 0.21], [np.nan, 0, 2.0], [0, 0, np.inf]])
+    pr = orc.project(g, synth.identity_camera(50, 50, 16, 16), orc.params(32, 32))
+    assert list(pr[:, 0]) == [0.0, 1.0, 0.0, 0.0]
+
+
+def test_rect_matches_exact_brute_force(orc):
+    """O8: the tiles a visible record touches are exactly those whose pixel
+    extent [16t, 16t+16) meets the closed square [u-r, u+r] (exact rationals)."""
+    rng = np.random.default_rng(2)
+    W, H = 100, 70  # ragged: 7 x 5 tiles
+    rec, vis = synth.synthetic_records(rng, [300], W, H, r_median=6.0)
+    rec[:5, 0] = [16.0, 31.999998, -3.0, 100.0, 47.5]  # integer / boundary-adjacent means
+    tt, keys, vals, ranges, K = orc.bin_records(rec, vis, W, H, 1)
+    TX, TY = 7, 5
+    for i in range(len(rec)):
+        r = int(rec[i, 3:4].view(np.int32)[0])
+        u, v = Fraction(float(rec[i, 0])), Fraction(float(rec[i, 1]))
+        want = set()
+        if vis[i]:
+            for ty in range(TY):
+                for tx in range(TX):
+                    if 16 * tx <= u + r and u - r < 16 * tx + 16 and 16 * ty <= v + r and v - r < 16 * ty + 16:
+                        want.add(ty * TX + tx)
+        got = set((keys[vals == i] >> np.uint64(32)).astype(np.int64).tolist())
+        assert got == want, i
+        assert tt[i] == len(want)
+
+
+# --------------------------------------------------------------------------
+# O9: spherical harmonics
+# --------------------------------------------------------------------------
+def _real_sh_scipy(l, m, d):
+    th = math.acos(max(-1.0, min(1.0, d[2])))
+    ph = math.atan2(d[1], d[0])
+    Yc = special.sph_harm_y(l, abs(m), th, ph)
+    if m > 0:
+        return math.sqrt(2.0) * Yc.real
+    if m < 0:
+        return math.sqrt(2.0) * Yc.imag
+    return Yc.real
+
+
+def test_sh_matches_library_complex_harmonics(orc):
+    rng = np.random.default_rng(3)
+    d = rng.standard_normal((40, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    Y, _ = orc.sh_basis(3, d)
+    for i in range(len(d)):
+        for l in range(4):
+            for m in range(-l, l + 1):
+                assert abs(Y[i, l * l + l + m] - _real_sh_scipy(l, m, d[i])) < 1e-13
+
+
+def test_sh_addition_theorem_and_orthonormality(orc):
+    rng = np.random.default_rng(4)
+    d = rng.standard_normal((100, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    Y, _ = orc.sh_basis(3, d)
+    for l in range(4):
+        s = (Y[:, l * l:(l + 1) ** 2] ** 2).sum(1)
+        assert np.allclose(s, (2 * l + 1) / (4 * math.pi), rtol=1e-13)
+    # Gauss-Legendre in cos(theta) x uniform phi: exact for these degrees
+    zt, wt = np.polynomial.legendre.leggauss(12)
+    ph = np.arange(16) * 2 * math.pi / 16
+    dirs, wts = [], []
+    for z, w in zip(zt, wt):
+        s = math.sqrt(1 - z * z)
+        for p in ph:
+            dirs.append([s * math.cos(p), s * math.sin(p), z])
+            wts.append(w * 2 * math.pi / 16)
+    Yq, _ = orc.sh_basis(3, np.array(dirs))
+    G = (Yq * np.array(wts)[:, None]).T @ Yq
+    assert np.abs(G - np.eye(16)).max() < 1e-13
+
+
+def test_sh_degree0_and_degree1_closed_forms(orc):
+    d = np.array([[0.36, -0.48, 0.8]])
+    Y, _ = orc.sh_basis(1, d)
+    c0 = 0.5 / math.sqrt(math.pi)
+    c1 = math.sqrt(3.0 / (4.0 * math.pi))
+    assert np.allclose(Y[0], [c0, -c1 * d[0, 1], c1 * d[0, 2], -c1 * d[0, 0]], rtol=1e-15)
+    # degree-0 colour: c = k0 / (2 sqrt(pi)) + 1/2, clamped at 0
+    g = _gauss(2, [[0, 0, 2], [0.1, 0, 2]], sh=[[[0.3, -0.2, -2.0]], [[1.0, 0.0, 0.0]]])
+    pr = orc.project(g, synth.identity_camera(50, 50, 16, 16), orc.params(32, 32))
+    k = g["sh"][0, 0].astype(np.float64)
+    assert np.allclose(pr[0, 8:11], np.maximum(0.0, k * c0 + 0.5), rtol=1e-15)
+
+
+def test_sh_gradient_by_finite_differences(orc):
+    rng = np.random.default_rng(5)
+    d = rng.standard_normal((10, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    _, dY = orc.sh_basis(3, d)
+    h = 1e-6
+    for i in range(len(d)):
+        for j in range(3):
+            e = np.zeros(3)
+            e[j] = h
+            Yp, _ = orc.sh_basis(3, d[i] + e)
+            Ym, _ = orc.sh_basis(3, d[i] - e)
+            assert np.allclose((Yp - Ym)[0] / (2 * h), dY[i, :, j], atol=1e-8)
+
+
+# --------------------------------------------------------------------------
+# O10: binning and order
+# --------------------------------------------------------------------------
+def test_binning_invariants(orc):
+    rng = np.random.default_rng(6)
+    counts = [120, 0, 75, 200]
+    rec, vis = synth.synthetic_records(rng, counts, 80, 48)
+    tt, keys, vals, ranges, K = orc.bin_records(rec, vis, 80, 48, len(counts))
+    assert K == tt.sum() == len(keys)
+    # sorted by (key, value)
+    order = np.lexsort((vals, keys))
+    assert np.array_equal(order, np.arange(K))
+    # the value multiset is each instance repeated tiles_touched times
+    assert np.array_equal(np.bincount(vals, minlength=len(rec)), tt.astype(np.int64))
+    # low key bits are the record's fp32 depth bits; high bits the global tile of its view
+    assert np.array_equal((keys & np.uint64(0xFFFFFFFF)).astype(np.uint32), rec[vals, 2].view(np.uint32))
+    views = rec[vals, 11].view(np.int32)
+    T = 5 * 3
+    assert np.array_equal((keys >> np.uint64(32)).astype(np.int64) // T, views)
+    # ranges
+    tiles = (keys >> np.uint64(32)).astype(np.int64)
+    for t in range(len(counts) * T):
+        b, e = ranges[t]
+        idx = np.nonzero(tiles == t)[0]
+        if len(idx) == 0:
+            assert b == e == 0
+        else:
+            assert (b, e) == (idx[0], idx[-1] + 1)
+    # a capacity below K truncates the pairs but still reports K
+    tt2, k2, v2, _, K2 = orc.bin_records(rec, vis, 80, 48, len(counts), capacity=K // 2)
+    assert K2 == K and np.array_equal(k2, keys[:K // 2]) and np.array_equal(v2, vals[:K // 2])
+
+
+# --------------------------------------------------------------------------
+# O11: compositing closed forms and invariants
+# --------------------------------------------------------------------------
+def _rec(u, v, z, r, A, B, C, o, rgb, view=0):
+    x = np.zeros(12, F32)
+    x[0], x[1], x[2] = u, v, z
+    x[3:4] = np.array([r], np.int32).view(F32)
+    x[4], x[5], x[6], x[7] = A, B, C, o
+    x[8:11] = rgb
+    x[11:12] = np.array([view], np.int32).view(F32)
+    return x
+
+
+def _composite_records(orc, recs, W=16, H=16, bg=(0, 0, 0)):
+    rec = np.stack(recs)
+    vis = np.ones(len(rec), np.uint8)
+    _, keys, vals, ranges, _ = orc.bin_records(rec, vis, W, H, 1)
+    prm = orc.params(W, H, bg=bg)
+    img, ncand, cands = orc.composite(rec, vals, ranges, 1, prm)
+    return img[0], ncand[0], cands[0]
+
+
+def test_single_gaussian_closed_form(orc):
+    o, s2 = F32(0.7), 9.0
+    r = _rec(7.5, 8.5, 2.0, 20, 1 / s2, 0.0, 1 / s2, o, [0.2, 0.5, 0.9])
+    img, _, _ = _composite_records(orc, [r])
+    A = float(F32(1 / s2))
+    for y in range(16):
+        for x in range(16):
+            dx, dy = x + 0.5 - 7.5, y + 0.5 - 8.5
+            a = min(orc.ALPHA_MAX, float(o) * math.exp(-0.5 * A * (dx * dx + dy * dy)))
+            if a < orc.ALPHA_MIN:
+                a = 0.0
+            assert np.allclose(img[y, x, :3], a * r[8:11].astype(np.float64), rtol=1e-14, atol=1e-300)
+            assert abs(img[y, x, 3] - 2.0 * a) < 1e-14 and abs(img[y, x, 4] - a) < 1e-15
+
+
+def test_two_gaussians_closed_form_and_background(orc):
+    r1 = _rec(8.0, 8.0, 1.0, 20, 0.05, 0.01, 0.08, 0.6, [1.0, 0.0, 0.0])
+    r2 = _rec(6.0, 9.0, 3.0, 20, 0.02, -0.005, 0.03, 0.8, [0.0, 1.0, 0.5])
+    bg = (0.25, 0.5, 0.125)
+    img, _, _ = _composite_records(orc, [r2, r1], bg=bg)  # input order is irrelevant
+
+    def alpha(r, x, y):
+        dx, dy = x + 0.5 - float(r[0]), y + 0.5 - float(r[1])
+        A, B, C = (float(r[k]) for k in (4, 5, 6))
+        a = min(orc.ALPHA_MAX, float(r[7]) * math.exp(-0.5 * (A * dx * dx + C * dy * dy) - B * dx * dy))
+        return 0.0 if a < orc.ALPHA_MIN else a
+
+    for (y, x) in [(8, 8), (0, 0), (15, 3), (9, 6)]:
+        a1, a2 = alpha(r1, x, y), alpha(r2, x, y)
+        Tf = (1 - a1) * (1 - a2)
+        want = a1 * r1[8:11].astype(np.float64) + a2 * (1 - a1) * r2[8:11].astype(np.float64) + Tf * np.array(bg)
+        assert np.allclose(img[y, x, :3], want, rtol=1e-13)
+        assert abs(img[y, x, 3] - (a1 * 1.0 + a2 * (1 - a1) * 3.0)) < 1e-13
+        assert abs(img[y, x, 5] - Tf) < 1e-15
+
+
+def test_opaque_stack_stops_with_fp32_thresholds(orc):
+    """Two centred opaque Gaussians: with the FP32 thresholds the second one
+    would drive T to 9.99998e-5 < fl32(1e-4), so it is not composited."""
+    r1 = _rec(8.5, 8.5, 1.0, 20, 1.0, 0.0, 1.0, 1.0, [0.4, 0.6, 0.8])
+    r2 = _rec(8.5, 8.5, 2.0, 20, 1.0, 0.0, 1.0, 1.0, [1.0, 1.0, 1.0])
+    img, _, _ = _composite_records(orc, [r1, r2])
+    a = float(F32(0.99))
+    assert np.allclose(img[8, 8, :3], a * r1[8:11].astype(np.float64), rtol=1e-15)
+    assert img[8, 8, 4] == 1.0 - (1.0 - a) and img[8, 8, 6] == 1
+    # with the decimal constants the second Gaussian would have been composited
+    T1 = 1 - 0.99
+    assert not (T1 * (1 - 0.99) < 1e-4)
+    assert (1 - a) * (1 - a) < orc.T_MIN
+
+
+def _dense_reference(pr, prm):
+    """Per-pixel dense composite: for each pixel every visible Gaussian whose
+    rect covers the pixel's tile, ordered by (depth, index)."""
+    W, H = int(prm[0]), int(prm[1])
+    out = np.zeros((H, W, 5))
+    vis = np.nonzero(pr[:, 0] > 0)[0]
+    order = vis[np.lexsort((vis, pr[vis, 3]))]
+    for y in range(H):
+        for x in range(W):
+            tx, ty = x // 16, y // 16
+            T, c, d = 1.0, np.zeros(3), 0.0
+            for i in order:
+                if not (pr[i, 12] <= tx < pr[i, 13] and pr[i, 14] <= ty < pr[i, 15]):
+                    continue
+                dx, dy = x + 0.5 - pr[i, 1], y + 0.5 - pr[i, 2]
+                P = min(0.0, -0.5 * (pr[i, 4] * dx * dx + pr[i, 6] * dy * dy) - pr[i, 5] * dx * dy)
+                a = min(prm[6], pr[i, 7] * math.exp(P))
+                if a < prm[7]:
+                    continue
+                if T * (1 - a) < prm[8]:
+                    break
+                c += pr[i, 8:11] * a * T
+                d += pr[i, 3] * a * T
+                T *= 1 - a
+            out[y, x, :3] = c + T * prm[9:12]
+            out[y, x, 3] = d
+            out[y, x, 4] = 1 - T
+    return out
+
+
+def test_tile_lists_equal_dense_per_pixel_reference(orc):
+    rng = np.random.default_rng(7)
+    g = synth.gaussians_cube(200, rng, sh_degree=1)
+    g["log_scales"] += F32(1.0)
+    cam = synth.identity_camera(40.0, 40.0, 16.0, 16.0)
+    prm = orc.params(32, 32, bg=(0.1, 0.2, 0.3))
+    pr, img, _, _, _, _ = orc.render(g, cam, prm)
+    ref = _dense_reference(pr, prm)
+    assert np.abs(img[..., :5] - ref).max() < 1e-12
+    assert (pr[:, 0] > 0).sum() > 100
+
+
+def test_fp64_matches_50_digit_evaluation(orc):
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 50
+    recs = [_rec(7.0, 8.0, 1.0 + k, 20, 0.05 + 0.01 * k, 0.003 * k, 0.04, 0.3 + 0.15 * k, [0.3, 0.6, 0.9])
+            for k in range(4)]
+    img, _, _ = _composite_records(orc, recs)
+    for (y, x) in [(8, 7), (2, 3), (14, 12)]:
+        T, c = mp.mpf(1), mp.mpf(0)
+        for r in recs:
+            dx, dy = mp.mpf(x) + mp.mpf("0.5") - mp.mpf(float(r[0])), mp.mpf(y) + mp.mpf("0.5") - mp.mpf(float(r[1]))
+            P = -(mp.mpf(float(r[4])) * dx * dx + mp.mpf(float(r[6])) * dy * dy) / 2 - mp.mpf(float(r[5])) * dx * dy
+            a = min(mp.mpf(orc.ALPHA_MAX), mp.mpf(float(r[7])) * mp.e ** P)
+            if a < mp.mpf(orc.ALPHA_MIN):
+                continue
+            if T * (1 - a) < mp.mpf(orc.T_MIN):
+                break
+            c += mp.mpf(float(r[8])) * a * T
+            T *= 1 - a
+        assert abs(img[y, x, 0] - float(c)) < 1e-12
+        assert abs(img[y, x, 5] - float(T)) < 1e-12
+
+
+def test_composite_invariants_and_permutation(orc):
+    hyp = pytest.importorskip("hypothesis")
+    from hypothesis import given, settings, strategies as st
+
+    @settings(max_examples=25, deadline=None)
+    @given(st.integers(0, 2**31 - 1), st.integers(1, 40))
+    def check(seed, n):
+        rng = np.random.default_rng(seed)
+        rec, _ = synth.synthetic_records(rng, [n], 32, 32, tie_frac=0.0, r_median=10.0)
+        vis = np.ones(n, np.uint8)
+        _, _, vals, ranges, _ = orc.bin_records(rec, vis, 32, 32, 1)
+        prm = orc.params(32, 32)
+        img, _, _ = orc.composite(rec, vals, ranges, 1, prm, want_cands=False)
+        img = img[0]
+        alpha, T = img[..., 4], img[..., 5]
+        assert np.all(alpha >= 0) and np.all(alpha <= 1 - orc.T_MIN + 1e-15)
+        assert np.allclose(alpha, 1 - T, atol=1e-15)
+        assert np.all(img[..., :3] >= 0)
+        has = alpha > 0
+        if has.any():
+            z = rec[:, 2].astype(np.float64)
+            dn = img[..., 3][has] / alpha[has]
+            assert np.all(dn >= z.min() * (1 - 1e-12)) and np.all(dn <= z.max() * (1 + 1e-12))
+        perm = rng.permutation(n)
+        rec2 = rec[perm].copy()
+        _, _, vals2, ranges2, _ = orc.bin_records(rec2, vis, 32, 32, 1)
+        img2, _, _ = orc.composite(rec2, vals2, ranges2, 1, prm, want_cands=False)
+        if len(np.unique(rec[:, 2])) == n:
+            assert np.array_equal(img2[0][..., :6], img[..., :6])
+
+    check()
+
+
+def test_candidate_enumeration_covers_near_threshold_skip(orc):
+    """A Gaussian whose alpha lands within the skip margin of 1/255 yields two
+    candidates at that pixel: with and without its contribution."""
+    # centred Gaussian, o chosen so that alpha at the pixel centre equals alpha_min * (1 + 1e-6)
+    A = 0.02
+    dx = 4.0
+    a_target = orc.ALPHA_MIN * (1 + 1e-6)
+    o = a_target / math.exp(-0.5 * A * dx * dx)
+    r = _rec(8.5 - dx, 8.5, 1.0, 20, A, 0.0, A, o, [1.0, 1.0, 1.0])
+    img, ncand, cands = _composite_records(orc, [r])
+    assert ncand[8, 8] == 2
+    vals = sorted(cands[8, 8, :2, 4])
+    assert vals[0] == 0.0 and abs(vals[1] - orc.ALPHA_MIN) < 1e-8
