@@ -1,0 +1,363 @@
+#!/usr/bin/env python3
+"""Benchmark of the Habitat-GS sensor-rendering hot path on one MI355X.
+
+Headline (`value`): forward frames/s of one 640x480 view of a 1M-Gaussian SH3
+room scene (synthetic stand-in for an indoor 3DGS capture), the whole
+per-frame path -- projection + SH, scan/emit, onesweep sort, ranges,
+compositing -- replayed as one captured HIP graph with inputs resident in
+HBM.  Further lines of the metric (fwd+bwd, batched multi-view vs plain
+per-view, avatars) are reported under "extras".
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras]
+                       [--no-cpu-baseline] [--profile]
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_NONPACKED_TFLOPS = 78.6  # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz; packed FP32 is not used
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile", action="store_true", help="headline workload only, for rocprofv3 runs")
+    ap.add_argument("--copy-calib", action="store_true", help="also run a 512 MiB device copy (counter scale)")
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def to_dev(g, dev):
+    import torch
+    return {k: (torch.from_numpy(np.ascontiguousarray(v)).to(dev) if isinstance(v, np.ndarray) else v)
+            for k, v in g.items()}
+
+
+class Timer:
+    """HIP events on torch's current stream (the stream libgs launches on)."""
+
+    def __init__(self):
+        import torch
+        self.torch = torch
+        self.acc = {}
+
+    def run(self, name, fn):
+        torch = self.torch
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        self.acc.setdefault(name, []).append((a, b))
+
+    def means_ms(self):
+        self.torch.cuda.synchronize()
+        return {k: float(np.mean([a.elapsed_time(b) for a, b in v])) for k, v in self.acc.items()}
+
+
+def sh_bytes(D):
+    return 12 * (D + 1) ** 2
+
+
+def algorithmic_bytes(N, n_vis, K, passes, V, HW, T, D):
+    """Bytes each stage must move at minimum (reads + writes), per call."""
+    return {
+        # means of every Gaussian (near-plane cull) + scale/rotation/opacity and SH of the
+        # visible ones + tiles_touched of all + the 48-B record of the visible ones
+        "project": N * 12 + n_vis * (32 + sh_bytes(D)) + N * 4 + n_vis * 48,
+        # scan (tiles_touched read twice, offsets written), emission (counts, offsets,
+        # the 16-B head + view of visible records, 12 B per key), histogram (8 B per key),
+        # P passes of 24 B per key, ranges (8 B per key + 8 B per tile)
+        "bin_sort": N * 16 + n_vis * 20 + K * 12 + K * 8 + passes * K * 24 + K * 8 + V * T * 8,
+        # values + gathered 48-B records + 28 B of outputs per pixel
+        "composite": K * 52 + V * HW * 28,
+    }
+
+
+def bench_forward(args, dev, timer_steps):
+    import torch
+    from paper_2604_12626_amd import render, synth
+    cfg = synth.config(1)
+    g = cfg["segments"][0]
+    N, D = len(g["means"]), g["sh_degree"]
+    W, H = cfg["W"], cfg["H"]
+    segs = [to_dev(g, dev)]
+    cams = torch.from_numpy(cfg["cams"]).to(dev)
+    vs = [[0]]
+    r = render.Renderer(W, H, capacity=1 << 22, device=dev)
+    f = r.render(segs, cams, vs)  # sizes the key capacity (grows on overflow)
+    torch.cuda.synchronize()
+    K = int(f.num.item())
+    n_vis = int((f.tiles_touched > 0).sum().item())
+    # graph of the whole forward frame
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        for _ in range(2):
+            r.enqueue(segs, cams, vs, f)
+    torch.cuda.current_stream().wait_stream(stream)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        r.enqueue(segs, cams, vs, f)
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    assert int(f.overflow.item()) == 0, "key capacity overflow during the timed region"
+    ms = (t1 - t0) * 1e3 / args.steps
+    # per-stage durations (eager launches bracketed by events on the same stream)
+    tm = Timer()
+    for _ in range(timer_steps):
+        tm.run("project", lambda: r.project(segs, cams, vs, f))
+        tm.run("bin_sort", lambda: r.bin_sort(f, 1))
+        tm.run("composite", lambda: r.composite(f, 1))
+    stages = tm.means_ms()
+    T = r.T
+    tile_bits = max(1, int(np.ceil(np.log2(T))))
+    passes = (32 + tile_bits + 7) // 8
+    nbytes = algorithmic_bytes(N, n_vis, K, passes, 1, W * H, T, D)
+    info = {"N": N, "n_vis": n_vis, "K": K, "sort_passes": passes, "stage_ms": stages, "alg_bytes": nbytes,
+            "capacity": r.capacity}
+    return ms, info, (r, f, segs, cams, vs)
+
+
+def bench_fwd_bwd(args, dev, steps):
+    import torch
+    from paper_2604_12626_amd import render, synth
+    cfg = synth.config(1)
+    g = cfg["segments"][0]
+    segs = [to_dev(g, dev)]
+    cams = torch.from_numpy(cfg["cams"]).to(dev)
+    vs = [[0]]
+    r = render.Renderer(cfg["W"], cfg["H"], capacity=1 << 22, device=dev)
+    f = r.render(segs, cams, vs)
+    target = torch.rand_like(f.rgb)
+
+    def step():
+        f2 = r.render(segs, cams, vs, sync_check=False)
+        d_rgb = 2.0 * (f2.rgb - target)
+        r.backward(segs, cams, vs, f2, d_rgb, None, None)
+
+    for _ in range(max(2, args.warmup // 2)):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def bench_batched(args, dev, steps, n_views=16):
+    """n_views views at 640x480 of the 1M room: one batched call vs the same
+    views rendered one call at a time (plain)."""
+    import torch
+    from paper_2604_12626_amd import render, synth
+    cfg = synth.config(4)
+    room = to_dev(cfg["segments"][0], dev)
+    cams = torch.from_numpy(cfg["cams"][:n_views]).to(dev)
+    W, H = cfg["W"], cfg["H"]
+    rb = render.Renderer(W, H, capacity=1 << 24, device=dev)
+    vs = [[0]] * n_views
+    fb = rb.render([room], cams, vs)
+    graph = _capture(lambda: rb.enqueue([room], cams, vs, fb))
+    ms_b = _time_graph(graph, args.warmup, steps)
+    plain = []
+    for v in range(n_views):
+        rp = render.Renderer(W, H, capacity=1 << 22, device=dev)
+        fp = rp.render([room], cams[v:v + 1], [[0]])
+        plain.append(_capture(lambda rp=rp, fp=fp, v=v: rp.enqueue([room], cams[v:v + 1], [[0]], fp)))
+    for gph in plain:
+        gph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for gph in plain:
+            gph.replay()
+    torch.cuda.synchronize()
+    ms_p = (time.perf_counter() - t0) * 1e3 / steps
+    return ms_b, ms_p, n_views
+
+
+def bench_avatars(args, dev, steps):
+    """Workload with avatars: LBS of 8 x 50k avatar Gaussians, then 16 views at
+    640x480 of room + avatars in one call (one graph)."""
+    import torch
+    from paper_2604_12626_amd import binding as B, render, synth
+    cfg = synth.config(4)
+    room = to_dev(cfg["segments"][0], dev)
+    av = to_dev(cfg["avatars"], dev)
+    skin = torch.from_numpy(cfg["skin"]).to(dev)
+    n_av = av["means"].shape[0]
+    posed = {"means": torch.empty(n_av, 3, device=dev), "cov6": torch.empty(n_av, 6, device=dev),
+             "opacity": av["opacity"], "sh": av["sh"], "sh_degree": 3}
+    cams = torch.from_numpy(cfg["cams"]).to(dev)
+    vs = cfg["view_segs"]
+    r = render.Renderer(cfg["W"], cfg["H"], capacity=1 << 24, device=dev)
+
+    def lbs():
+        B.deform_lbs(av["means"], av["log_scales"], av["quats"], av["joint_idx"], av["weights"], av["avatar_of"],
+                     skin, posed["means"], posed["cov6"])
+
+    lbs()
+    f = r.render([room, posed], cams, vs)
+
+    def frame():
+        lbs()
+        r.enqueue([room, posed], cams, vs, f)
+
+    graph = _capture(frame)
+    ms = _time_graph(graph, args.warmup, steps)
+    return ms, len(vs)
+
+
+def _capture(fn):
+    import torch
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        fn()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    torch.cuda.synchronize()
+    return g
+
+
+def _time_graph(g, warmup, steps):
+    import torch
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.replay()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def cpu_baseline():
+    """The FP64 oracle (as it stands) on a bounded sample of the headline
+    workload: projection of all 1M Gaussians plus compositing of a horizontal
+    band of tiles; frames/s scaled by the fraction of tiles rendered."""
+    import oracle
+    from paper_2604_12626_amd import synth
+    cfg = synth.config(1)
+    g = cfg["segments"][0]
+    W, H = cfg["W"], cfg["H"]
+    band_rows = 6  # of 30 tile rows
+    prm = oracle.params(W, H, max_flips=0)
+    t0 = time.perf_counter()
+    proj = oracle.project(g, cfg["cams"][0], prm)
+    t1 = time.perf_counter()
+    # sample: tile rows 12..17 (the middle of the image, where the room is densest)
+    y0 = 12 * 16
+    sub = proj.copy()
+    sub[:, 2] -= y0
+    sub[:, 14] -= 12
+    sub[:, 15] -= 12
+    keep = (sub[:, 0] > 0) & (sub[:, 15] > 0) & (sub[:, 14] < band_rows)
+    sub[~keep, 0] = 0
+    sub[:, 14] = np.maximum(sub[:, 14], 0)
+    sub[:, 15] = np.minimum(sub[:, 15], band_rows)
+    prm2 = oracle.params(W, band_rows * 16, max_flips=0)
+    t2 = time.perf_counter()
+    oracle.render_view(sub, prm2, want_cands=False)
+    t3 = time.perf_counter()
+    frac = band_rows / ((H + 15) // 16)
+    frame_s = (t1 - t0) + (t3 - t2) / frac
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": 1.0 / frame_s, "unit": "frames/s", "cores": cores, "kind": "oracle",
+            "sample": "FP64 oracle: projection of all 1M Gaussians + compositing of 6 of 30 tile rows "
+                      "(640x96 px band) of the 640x480 view, extrapolated to the full frame; "
+                      "%.1f s of CPU work" % ((t1 - t0) + (t3 - t2))}
+
+
+def copy_calibration(dev):
+    import torch
+    n = 512 << 20
+    a = torch.empty(n // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return n
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only (this build renders on a single MI355X); "
+              "--gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    from paper_2604_12626_amd import binding
+    binding.load()
+    dev = torch.device("cuda:0")
+    if args.copy_calib:
+        log("copy calibration: 512 MiB x 3")
+        copy_calibration(dev)
+    log("forward: 640x480, 1M Gaussians, SH3")
+    ms, info, _ = bench_forward(args, dev, timer_steps=max(5, args.steps // 2))
+    fps = 1e3 / ms
+    st = info["stage_ms"]
+    dom = max(st, key=st.get)
+    nbytes = info["alg_bytes"][dom]
+    achieved = nbytes / (st[dom] * 1e-3) / 1e9
+    roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "alg_bytes_per_launch": nbytes, "avg_launch_ms": st[dom]}
+    extras = {"stage_ms": st, "N": info["N"], "visible": info["n_vis"], "tile_instances": info["K"],
+              "sort_passes": info["sort_passes"],
+              "stage_hbm_frac": {k: info["alg_bytes"][k] / (st[k] * 1e-3) / 1e9 / HBM_PEAK_GBS for k in st}}
+    if not args.profile and not args.no_extras:
+        steps2 = max(5, args.steps // 5)
+        log("fwd+bwd")
+        extras["fwd_bwd_fps"] = 1e3 / bench_fwd_bwd(args, dev, steps2)
+        log("batched vs plain")
+        ms_b, ms_p, nv = bench_batched(args, dev, steps2)
+        extras["batched_16x640x480_fps"] = nv * 1e3 / ms_b
+        extras["plain_16x640x480_fps"] = nv * 1e3 / ms_p
+        log("avatars")
+        ms_a, nva = bench_avatars(args, dev, steps2)
+        extras["avatars_16x640x480_fps"] = nva * 1e3 / ms_a
+    out = {"metric": "frames/s 640x480 1M-Gaussian SH3: fwd, fwd+bwd, batched vs plain", "value": fps,
+           "unit": "frames/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic (seeded room-shaped 3DGS scene; no dataset)",
+           "config": {"workload": "room1M_640x480_sh3: 1 view, 1M Gaussians, SH degree 3, forward",
+                      "global_batch": 1, "parallelism": "none (1 GPU)"},
+           "roofline": roof, "extras": extras}
+    if not args.profile and not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

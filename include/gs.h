@@ -1,0 +1,261 @@
+/*
+ * gs.h -- C ABI of the MI355X (gfx950) tile-based 3D Gaussian Splatting
+ * sensor renderer: the rendering and avatar-deformation hot path of
+ * Habitat-GS (arXiv 2604.12626).
+ *
+ * The paper renders scenes stored as explicit anisotropic 3D Gaussians with
+ * tile-based rasterization (Sec. 2.2, Sec. 3.2), deforms canonical avatar
+ * Gaussians to the current pose with linear blend skinning every frame
+ * (Sec. 3.1, Sec. 3.3) and rasterizes all avatars in one pass together with
+ * the scene, producing colour and depth (Sec. 3.2).  The five calls below are
+ * that path:
+ *
+ *   gs_deform_lbs       canonical avatar Gaussians -> posed means + covariances
+ *   gs_project          EWA projection, SH colour, tile rect per (view, Gaussian)
+ *   gs_bin_sort         tile binning: scan, (tile, depth) key emission, onesweep
+ *                       LSD radix sort, per-tile ranges
+ *   gs_composite        per-tile front-to-back alpha compositing -> RGB, depth, alpha
+ *   gs_render_backward  gradients of an image loss w.r.t. the Gaussian parameters
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Memory.  Every array argument is a DEVICE pointer owned by the caller,
+ *    unless the comment says "host".  The library never allocates or frees
+ *    device memory and keeps no device state between calls; scratch space is
+ *    a caller-provided workspace whose size the *_workspace_bytes() helpers
+ *    report.
+ *  - Asynchrony.  Each call validates its arguments on the host, then only
+ *    enqueues kernels on `stream` (a hipStream_t; NULL is the default
+ *    stream) and returns.  Results are ready when the stream reaches them.
+ *  - Errors.  A call returns GS_OK or an error status.  Invalid arguments
+ *    return before anything is enqueued.  A failed launch returns GS_ERR_HIP.
+ *    gs_last_error() gives a thread-local message for the last failure.  No
+ *    C++ exception crosses this boundary.  Data-dependent overflow (more tile
+ *    instances than the key buffers hold) is reported on the device (see
+ *    gs_bin_sort) so that no call needs a host synchronisation.
+ *  - Layouts.  Row-major, one row per Gaussian: means [n][3],
+ *    log_scales [n][3], quats [n][4] as (w, x, y, z), opacity [n] (activated,
+ *    in (0,1)), sh [n][(D+1)^2][3] (real SH, Condon-Shortley phase, l-major,
+ *    m = -l..l), cov6 [n][6] as (xx, xy, xz, yy, yz, zz).  Images are
+ *    [view][y][x] with RGB interleaved: rgb [V][H][W][3], depth [V][H][W],
+ *    alpha [V][H][W].  Dtypes are FP32 except where noted.
+ *  - Instances.  One call renders V views.  Each view draws a set of
+ *    gaussian segments (bit s of view_seg_mask[v] set = segment s drawn;
+ *    a scene and the posed avatars are two segments of one view, Sec. 3.2).
+ *    Instance g = base[v] + offset of segment s within view v + i numbers the
+ *    pair (view v, Gaussian i of segment s), with segments in ascending index
+ *    order inside a view and base[v] = sum of the previous views' counts; see
+ *    gs_instance_offsets().
+ */
+#ifndef GS_H_
+#define GS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* A hipStream_t, passed as an opaque handle (NULL = default stream). */
+typedef void *gs_stream_t;
+
+typedef enum gs_status {
+    GS_OK = 0,
+    GS_ERR_INVALID_ARGUMENT = 1,   /* a pointer, size or parameter is invalid */
+    GS_ERR_UNSUPPORTED = 2,        /* valid but outside this build's limits */
+    GS_ERR_WORKSPACE_TOO_SMALL = 3,
+    GS_ERR_HIP = 4                 /* a HIP runtime call or launch failed */
+} gs_status;
+
+#define GS_TILE 16            /* tile edge in pixels (part of the image definition) */
+#define GS_REC_FLOATS 12      /* projected record: 3 x float4, see gs_projected */
+#define GS_MAX_SEGMENTS 32    /* bits of view_seg_mask */
+#define GS_MAX_VIEWS 4096
+#define GS_MAX_SH_DEGREE 3
+#define GS_MAX_CAPACITY ((1LL << 30) - 1) /* tile-instance limit of one gs_bin_sort call */
+
+/* Pinhole camera, world -> camera with OpenCV axes (x right, y down, z
+ * forward): p_cam = R p_world + t, R row-major.  Pixel (x, y) samples the
+ * image-plane point (x + 1/2, y + 1/2); u = fx X/Z + cx, v = fy Y/Z + cy.
+ * 64 bytes; the cameras of a call live in a device array of n_views. */
+typedef struct gs_camera {
+    float R[9];
+    float t[3];
+    float fx, fy, cx, cy;
+} gs_camera;
+
+/* Rendering constants (host struct, by pointer).  Defaults in brackets are
+ * those of the 3DGS lineage the paper cites; gs_default_params() fills them. */
+typedef struct gs_params {
+    int32_t width, height; /* image size shared by all views of a call */
+    float near_plane;      /* cull if !(z_cam > near_plane)        [0.2] */
+    float lowpass;         /* added to the 2D covariance diagonal  [0.3] */
+    float sigma_cut;       /* radius = ceil(sigma_cut sqrt(lambda_max)) [3] */
+    float fov_clamp;       /* Jacobian tangent clamp, x half-FOV   [1.3] */
+    float alpha_max;       /* alpha = min(alpha_max, o G)          [0.99] */
+    float alpha_min;       /* skip the entry if alpha < alpha_min  [1/255] */
+    float t_min;           /* stop before T(1-alpha) < t_min       [1e-4] */
+    float bg[3];           /* background colour, added as T_final bg [0] */
+} gs_params;
+
+/* One gaussian segment (device pointers).  If cov6 is non-NULL it gives the
+ * 3D covariance directly (posed avatars) and log_scales/quats are ignored. */
+typedef struct gs_gaussians {
+    int64_t n;
+    int32_t sh_degree; /* 0..3 */
+    int32_t reserved;
+    const float *means, *log_scales, *quats, *cov6, *opacity, *sh;
+} gs_gaussians;
+
+/* Gradients of one segment, same layouts as gs_gaussians (device pointers).
+ * cov6 is written when the segment was given by cov6, log_scales and quats
+ * otherwise; the unused ones may be NULL. */
+typedef struct gs_gaussians_grad {
+    float *means, *log_scales, *quats, *cov6, *opacity, *sh;
+} gs_gaussians_grad;
+
+/* Projected instances (device arrays of n_instances).
+ *  tiles_touched[g]: number of tiles of g's rect; 0 = culled.
+ *  rec[g] (12 floats, 16-byte aligned, written only when g is visible):
+ *    [0] u  [1] v  [2] camera-space depth z  [3] radius (int32 bits)
+ *    [4] A  [5] B  [6] C   (conic = inverse 2D covariance [[A,B],[B,C]])
+ *    [7] opacity  [8..10] rgb  [11] view (int32 bits) */
+typedef struct gs_projected {
+    int64_t n_instances;
+    uint32_t *tiles_touched;
+    float *rec;
+} gs_projected;
+
+/* ---------------------------------------------------------------------- */
+/* helpers                                                                 */
+/* ---------------------------------------------------------------------- */
+const char *gs_status_string(gs_status s);
+const char *gs_last_error(void); /* thread-local; "" if none */
+int32_t gs_version(void);
+void gs_default_params(gs_params *p, int32_t width, int32_t height);
+
+/* Host helper: offsets[v] = first instance of view v, offsets[n_views] =
+ * total (host arrays; offsets has n_views + 1 entries). */
+gs_status gs_instance_offsets(const gs_gaussians *segs, int32_t n_segs, int32_t n_views,
+                              const uint32_t *view_seg_mask, int64_t *offsets);
+
+/* ---------------------------------------------------------------------- */
+/* avatars: linear blend skinning (Sec. 3.3)                               */
+/* ---------------------------------------------------------------------- */
+/* For each canonical avatar Gaussian i: A_i = sum_k weights[i][k] *
+ * skin_mats[avatar_of[i]][joint_idx[i][k]] (a blend of 3x4 joint matrices,
+ * k < 4; the weights are used as given), then
+ *   means_out[i] = A3 means_c[i] + a,   cov6_out[i] = A3 Sigma A3^T,
+ * Sigma = R(q) diag(exp(2 s)) R(q)^T from log_scales_c / quats_c.
+ *  joint_idx uint8 [n][4], weights [n][4], avatar_of int32 [n],
+ *  skin_mats [n_avatars][n_joints][12] (row-major 3x4), n_joints <= 255.
+ * Outputs [n][3] and [n][6] feed gs_project as a cov6 segment.  The joint
+ * matrices are read from device memory at run time, so a captured graph
+ * replays with new poses.  Errors: GS_ERR_INVALID_ARGUMENT for NULL arrays
+ * with n > 0 or non-positive joint/avatar counts. */
+gs_status gs_deform_lbs(int64_t n, const float *means_c, const float *log_scales_c, const float *quats_c,
+                        const uint8_t *joint_idx, const float *weights, const int32_t *avatar_of,
+                        const float *skin_mats, int32_t n_avatars, int32_t n_joints, float *means_out,
+                        float *cov6_out, gs_stream_t stream);
+
+/* Adjoint of gs_deform_lbs w.r.t. the canonical means, log-scales and
+ * quaternions, given d_means_out [n][3] and d_cov6_out [n][6] (for example
+ * the cov6 gradients gs_render_backward writes).  Outputs are overwritten.
+ * Joint matrices and weights are held fixed. */
+gs_status gs_deform_lbs_backward(int64_t n, const float *means_c, const float *log_scales_c,
+                                 const float *quats_c, const uint8_t *joint_idx, const float *weights,
+                                 const int32_t *avatar_of, const float *skin_mats, int32_t n_avatars,
+                                 int32_t n_joints, const float *d_means_out, const float *d_cov6_out,
+                                 float *d_means_c, float *d_log_scales_c, float *d_quats_c, gs_stream_t stream);
+
+/* ---------------------------------------------------------------------- */
+/* rasterizer (Sec. 2.2, Sec. 3.2)                                         */
+/* ---------------------------------------------------------------------- */
+/* Projection of every (view, Gaussian) instance: camera-space mean, cull if
+ * !(z > near_plane); EWA 2D covariance J W Sigma W^T J^T + lowpass I with the
+ * tangent-clamped Jacobian; conic; radius ceil(sigma_cut sqrt(lambda_max))
+ * (0.1 floor under the eigenvalue root); rect of the tiles meeting the
+ * square [u-r, u+r] x [v-r, v+r]; SH colour max(0, sum Y_lm(d) k_lm + 1/2)
+ * with d the world-space direction from the camera centre.  Reads each
+ * Gaussian's attributes once for all views that draw its segment.
+ *  segs: host array of n_segs (<= GS_MAX_SEGMENTS) segment descriptors.
+ *  cams: device array of n_views gs_camera.
+ *  view_seg_mask: host array of n_views masks.
+ *  out: n_instances must equal the total of gs_instance_offsets(); writes
+ *       tiles_touched for every instance and rec for visible ones.
+ * Errors: GS_ERR_INVALID_ARGUMENT (NULL/size mismatch, sh_degree > 3,
+ * width/height <= 0, empty mask bits beyond n_segs), GS_ERR_UNSUPPORTED
+ * (more than 2^32 - 1 instances). */
+gs_status gs_project(const gs_gaussians *segs, int32_t n_segs, const gs_camera *cams, int32_t n_views,
+                     const uint32_t *view_seg_mask, const gs_params *p, gs_projected *out, gs_stream_t stream);
+
+/* Workspace bytes gs_bin_sort needs for n_instances projected instances,
+ * `capacity` key slots and n_views views of p->width x p->height. */
+size_t gs_bin_sort_workspace(int64_t n_instances, int64_t capacity, int32_t n_views, const gs_params *p);
+
+/* Tile binning of the projected instances:
+ *   1. exclusive scan of tiles_touched -> per-instance key offsets, K;
+ *   2. every visible instance g emits one key per tile of its rect, in
+ *      row-major tile order: key = ((view * T + tile) << 32) | bits(fp32 z),
+ *      value = g  (T = tiles per view; z > 0 so the bits order like z);
+ *   3. stable LSD radix sort of (key, value) over the significant key bits
+ *      (a hand-written onesweep pass per 8-bit digit), so ties in depth keep
+ *      ascending instance order;
+ *   4. tile_ranges[t] = [first, last + 1) of tile t's run, (0, 0) if empty.
+ *  keys uint64 [capacity], vals uint32 [capacity]: sorted output.
+ *  tile_ranges uint32 [n_views * T][2].
+ *  d_num_instances (int64, device): K.  d_overflow (int32, device): set to 1
+ *  when K > capacity (then only the first `capacity` keys are emitted and the
+ *  order and ranges are invalid), else 0.  The caller re-runs with a larger
+ *  capacity; nothing here synchronises with the host.
+ * Errors: GS_ERR_INVALID_ARGUMENT, GS_ERR_WORKSPACE_TOO_SMALL,
+ * GS_ERR_UNSUPPORTED (capacity > GS_MAX_CAPACITY, n_views * T > 2^31). */
+gs_status gs_bin_sort(const gs_projected *proj, int32_t n_views, const gs_params *p, void *ws, size_t ws_bytes,
+                      uint64_t *keys, uint32_t *vals, int64_t capacity, uint32_t *tile_ranges,
+                      int64_t *d_num_instances, int32_t *d_overflow, gs_stream_t stream);
+
+/* Workspace bytes gs_composite needs (the persistent tile queue). */
+size_t gs_composite_workspace(int32_t n_views, const gs_params *p);
+
+/* Per-tile front-to-back compositing.  For each pixel p = (x + 1/2, y + 1/2)
+ * and each entry i of its tile's sorted list: G = exp(-1/2 d^T Q d) with
+ * d = p - (u, v); alpha = min(alpha_max, o G); skip if alpha < alpha_min;
+ * stop (without compositing i) if T (1 - alpha) < t_min; else C += c alpha T,
+ * D += z alpha T, T *= 1 - alpha.  Outputs rgb = C + T bg, depth = D (z-depth
+ * accumulated, un-normalised), alpha = 1 - T; optional t_final = T and
+ * n_contrib = 1 + list position of the last composited entry (the state the
+ * backward pass starts from; pass NULL to skip them).
+ * The tiles are processed by a persistent grid that pops (view, tile) work
+ * items from a counter in `ws` (cleared by this call).
+ * Errors: GS_ERR_INVALID_ARGUMENT, GS_ERR_WORKSPACE_TOO_SMALL. */
+gs_status gs_composite(const gs_projected *proj, const uint32_t *vals, const uint32_t *tile_ranges,
+                       int32_t n_views, const gs_params *p, void *ws, size_t ws_bytes, float *rgb, float *depth,
+                       float *alpha, float *t_final, uint32_t *n_contrib, gs_stream_t stream);
+
+/* Workspace bytes gs_render_backward needs for n_instances instances. */
+size_t gs_render_backward_workspace(int64_t n_instances);
+
+/* Gradients of L(rgb, depth, alpha) given dL/drgb [V][H][W][3],
+ * dL/ddepth [V][H][W], dL/dalpha [V][H][W] (any may be NULL = zero), for the
+ * forward described by the same segs/cams/masks/params and its outputs
+ * (proj, vals, tile_ranges, t_final, n_contrib).  The transmittance of each
+ * pixel is recovered back to front from t_final (T_i = T_{i+1} / (1 -
+ * alpha_i)); the discrete decisions of the forward (cull, rect, skip, stop,
+ * clamp) are held fixed, so this is the derivative almost everywhere, and it
+ * is zero through the alpha clamp.  Gradients are summed over the views that
+ * draw a segment and written densely (zeros for Gaussians no view sees).
+ *  grads: host array of n_segs gradient descriptors (device pointers),
+ *  overwritten.  ws: per-instance screen-space accumulators.
+ * Errors: as gs_project, plus GS_ERR_WORKSPACE_TOO_SMALL. */
+gs_status gs_render_backward(const gs_gaussians *segs, int32_t n_segs, const gs_camera *cams, int32_t n_views,
+                             const uint32_t *view_seg_mask, const gs_params *p, const gs_projected *proj,
+                             const uint32_t *vals, const uint32_t *tile_ranges, const float *t_final,
+                             const uint32_t *n_contrib, const float *d_rgb, const float *d_depth,
+                             const float *d_alpha, void *ws, size_t ws_bytes, const gs_gaussians_grad *grads,
+                             gs_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GS_H_ */

@@ -34,7 +34,7 @@ _SRC = os.path.join(_HERE, "gs_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-PROJ_STRIDE = 32
+PROJ_STRIDE = 40
 MAXC = 8
 CAND_STRIDE = 10
 

@@ -44,7 +44,7 @@
 
 #define OR_MAXL 8
 #define OR_MAXK ((OR_MAXL + 1) * (OR_MAXL + 1))
-#define OR_PROJ_STRIDE 32
+#define OR_PROJ_STRIDE 40
 #define OR_MAXC 8 /* candidate results per pixel */
 #define OR_CAND_STRIDE 10
 
@@ -267,7 +267,7 @@ typedef struct {
     double tc[3], u, v, xr, yr;
     int clx, cly;
     double J[6], T[6], S2[3], det, conic[3], lam;
-    int radius, rect[4], arect[4];
+    int radius, rect[4], arect[4], irect[4];
     double dir[3], dist, raw[3], rgb[3], opacity;
     double m_near, m_rad, m_u, m_v;
 } oproj;
@@ -435,6 +435,7 @@ static void project_one(const oprm *p, const ocam *cam, int D, const float *mean
         rs[1] = radius_of(nearbyint(rr) + 0.5);
     }
     memcpy(o->arect, o->rect, sizeof(o->rect));
+    memcpy(o->irect, o->rect, sizeof(o->rect));
     int any_empty = rect_empty(o->rect), all_empty = rect_empty(o->rect);
     for (int a0 = 0; a0 < 2; ++a0)
         for (int a1 = 0; a1 < 2; ++a1)
@@ -442,6 +443,10 @@ static void project_one(const oprm *p, const ocam *cam, int D, const float *mean
                 int rc[4];
                 rect_of(ixs[a0], iys[a1], rs[a2], TX, TY, p->tile, rc);
                 if (memcmp(rc, o->rect, sizeof(rc)) != 0) o->amb = 1;
+                if (rc[0] > o->irect[0]) o->irect[0] = rc[0];
+                if (rc[1] < o->irect[1]) o->irect[1] = rc[1];
+                if (rc[2] > o->irect[2]) o->irect[2] = rc[2];
+                if (rc[3] < o->irect[3]) o->irect[3] = rc[3];
                 if (!rect_empty(rc)) {
                     if (all_empty) {
                         memcpy(o->arect, rc, sizeof(rc));
@@ -457,7 +462,10 @@ static void project_one(const oprm *p, const ocam *cam, int D, const float *mean
                 }
             }
     (void)any_empty;
-    if (fabs(o->m_near) <= p->d_near) o->amb = 1;
+    if (fabs(o->m_near) <= p->d_near) {
+        o->amb = 1;
+        memset(o->irect, 0, sizeof(o->irect)); /* the alternative is "not visible" */
+    }
     if (rect_empty(o->rect)) {
         o->vis = 0;
         return;
@@ -506,7 +514,8 @@ void or_cov3d(int64_t n, const float *lsc, const float *quats, double *cov6)
  *  0 vis, 1 u, 2 v, 3 depth, 4 A, 5 B, 6 C, 7 opacity, 8..10 rgb, 11 radius,
  *  12..15 rect x0 x1 y0 y1, 16 lambda, 17 near margin, 18 radius margin,
  *  19 u margin, 20 v margin, 21 ambiguous, 22..25 union rect, 26..28 a b c,
- *  29..31 raw colour before the clamp. */
+ *  29..31 raw colour before the clamp, 32..35 intersection of the rects over
+ *  the ambiguous alternatives (empty if an alternative is "culled"). */
 void or_project(int64_t n, int D, const float *means, const float *lsc, const float *quats, const float *cov6,
                 const uint8_t *use_cov6, const float *opacity, const float *sh, const double *camp,
                 const double *prm, double *out)
@@ -548,6 +557,7 @@ void or_project(int64_t n, int D, const float *means, const float *lsc, const fl
         r[29] = o.raw[0];
         r[30] = o.raw[1];
         r[31] = o.raw[2];
+        for (int k = 0; k < 4; ++k) r[32 + k] = o.irect[k];
     }
 }
 
@@ -933,9 +943,11 @@ static void build_lists(const oprm *p, int64_t n, const double *proj, int64_t **
 /* Full FP64 forward render of one view from the oracle's own projection
  * (proj: the output of or_project for the same view).  Also flags pixels
  * whose result depends on a decision inside its margin that the compositing
- * enumeration does not cover: a rect or visibility ambiguity of a Gaussian
- * whose alternative rect covers the pixel's tile (bit 0), or a depth near-tie
- * between consecutive entries of the tile's list (bit 1).
+ * enumeration does not cover: a Gaussian whose rect or visibility is
+ * ambiguous and whose alpha at the pixel reaches the skip threshold in a
+ * tile that only some alternatives cover (bit 0), or two entries of the
+ * pixel's list with depths within the tie margin that both reach the skip
+ * threshold before the pixel stops (bit 1).
  * img [H][W][10]; ncand [H][W]; flags [H][W]; cands optional [H][W][MAXC][10];
  * pairs_out (nullable): number of (pixel, entry) evaluations of the primary
  * path before its stop. */
@@ -947,11 +959,12 @@ void or_render_view(int64_t n, const double *proj, const double *prm, double *im
     int64_t *lp, *li;
     build_lists(&p, n, proj, &lp, &li);
     memset(flags, 0, (size_t)p.H * p.W);
-    uint8_t *tflag = calloc((size_t)(T > 0 ? T : 1), 1);
+    /* rect / visibility ambiguity: a pixel in a tile that some alternative
+     * rect covers and another does not, where the Gaussian's alpha reaches the
+     * skip threshold (within its margin) */
     for (int64_t i = 0; i < n; ++i) {
         const double *r = proj + OR_PROJ_STRIDE * i;
         if (r[21] == 0.0) continue;
-        /* ambiguous Gaussian: every tile of its primary or alternative rects */
         int x0 = (int)r[22], x1 = (int)r[23], y0 = (int)r[24], y1 = (int)r[25];
         if (r[0] != 0.0) {
             if (r[12] < x0) x0 = (int)r[12];
@@ -959,14 +972,20 @@ void or_render_view(int64_t n, const double *proj, const double *prm, double *im
             if (r[14] < y0) y0 = (int)r[14];
             if (r[15] > y1) y1 = (int)r[15];
         }
+        if (r[1] != r[1] || r[6] != r[6]) continue; /* no 2D footprint (culled at the near plane) */
         for (int ty = y0; ty < y1; ++ty)
-            for (int tx = x0; tx < x1; ++tx) tflag[ty * TX + tx] |= 1;
+            for (int tx = x0; tx < x1; ++tx) {
+                const int core = tx >= (int)r[32] && tx < (int)r[33] && ty >= (int)r[34] && ty < (int)r[35];
+                if (core) continue;
+                for (int py = ty * p.tile; py < (ty + 1) * p.tile && py < p.H; ++py)
+                    for (int px = tx * p.tile; px < (tx + 1) * p.tile && px < p.W; ++px) {
+                        const double ddx = px + 0.5 - r[1], ddy = py + 0.5 - r[2];
+                        double P = -0.5 * (r[4] * ddx * ddx + r[6] * ddy * ddy) - r[5] * ddx * ddy;
+                        if (P > 0.0) P = 0.0;
+                        if (r[7] * exp(P) >= p.alpha_min * (1.0 - p.d_skip)) flags[(size_t)py * p.W + px] |= 1;
+                    }
+            }
     }
-    for (int t = 0; t < T; ++t)
-        for (int64_t j = lp[t] + 1; j < lp[t + 1]; ++j) {
-            const double z0 = proj[OR_PROJ_STRIDE * li[j - 1] + 3], z1 = proj[OR_PROJ_STRIDE * li[j] + 3];
-            if (fabs(z1 - z0) <= p.d_tie * (z1 > z0 ? z1 : z0)) tflag[t] |= 2;
-        }
     int64_t pairs = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(+ : pairs)
     for (int t = 0; t < T; ++t) {
@@ -987,17 +1006,23 @@ void or_render_view(int64_t n, const double *proj, const double *prm, double *im
         }
         const int tx = t % TX, ty = t / TX;
         composite_tile(&p, ents, len, tx, ty, img, ncand, cands);
-        /* count primary-path evaluations */
+        /* primary-path evaluation count, and depth near-ties between two
+         * entries that both reach the skip threshold at the pixel before it
+         * stops (their order decides the result) */
         for (int py = ty * p.tile; py < (ty + 1) * p.tile && py < p.H; ++py)
             for (int px = tx * p.tile; px < (tx + 1) * p.tile && px < p.W; ++px) {
-                double T_ = 1.0;
-                int j = 0;
+                double T_ = 1.0, zlast = -1.0;
+                int j = 0, tie = 0;
                 for (; j < len; ++j) {
                     const double ddx = px + 0.5 - ents[j].u, ddy = py + 0.5 - ents[j].v;
                     double P = -0.5 * (ents[j].A * ddx * ddx + ents[j].C * ddy * ddy) - ents[j].B * ddx * ddy;
                     if (P > 0.0) P = 0.0;
                     double a = ents[j].o * exp(P);
                     if (a > p.alpha_max) a = p.alpha_max;
+                    if (a < p.alpha_min * (1.0 - p.d_skip)) continue;
+                    if (zlast > 0.0 && fabs(ents[j].z - zlast) <= p.d_tie * (ents[j].z > zlast ? ents[j].z : zlast))
+                        tie = 1;
+                    zlast = ents[j].z;
                     if (a < p.alpha_min) continue;
                     const double Tn = T_ * (1.0 - a);
                     if (Tn < p.t_min) {
@@ -1007,12 +1032,11 @@ void or_render_view(int64_t n, const double *proj, const double *prm, double *im
                     T_ = Tn;
                 }
                 pairs += j;
-                if (tflag[t]) flags[(size_t)py * p.W + px] = tflag[t];
+                if (tie) flags[(size_t)py * p.W + px] |= 2;
             }
         free(ents);
     }
     if (pairs_out) *pairs_out = pairs;
-    free(tflag);
     free(lp);
     free(li);
 }

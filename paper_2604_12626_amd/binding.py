@@ -1,0 +1,255 @@
+"""ctypes binding of libgs.so (the C ABI in include/gs.h) for torch tensors.
+
+Argument marshalling only: every step of the rendering path runs in the HIP
+kernels of libgs.so.  Device memory and streams come from PyTorch (ROCm); each
+call enqueues on torch's current stream.  If the library is missing this
+module raises when first used -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgs.so")
+
+GS_OK, GS_ERR_INVALID_ARGUMENT, GS_ERR_UNSUPPORTED, GS_ERR_WORKSPACE_TOO_SMALL, GS_ERR_HIP = range(5)
+TILE = 16
+REC_FLOATS = 12
+MAX_SEGMENTS = 32
+MAX_CAPACITY = (1 << 30) - 1
+G2D = 10
+
+P = ctypes.c_void_p
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_float * 9), ("t", ctypes.c_float * 3), ("fx", ctypes.c_float),
+                ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("near_plane", ctypes.c_float),
+                ("lowpass", ctypes.c_float), ("sigma_cut", ctypes.c_float), ("fov_clamp", ctypes.c_float),
+                ("alpha_max", ctypes.c_float), ("alpha_min", ctypes.c_float), ("t_min", ctypes.c_float),
+                ("bg", ctypes.c_float * 3)]
+
+
+class Gaussians(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("sh_degree", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("means", P), ("log_scales", P), ("quats", P), ("cov6", P), ("opacity", P), ("sh", P)]
+
+
+class GaussiansGrad(ctypes.Structure):
+    _fields_ = [("means", P), ("log_scales", P), ("quats", P), ("cov6", P), ("opacity", P), ("sh", P)]
+
+
+class Projected(ctypes.Structure):
+    _fields_ = [("n_instances", ctypes.c_int64), ("tiles_touched", P), ("rec", P)]
+
+
+EXPORTS = ["gs_status_string", "gs_last_error", "gs_version", "gs_default_params", "gs_instance_offsets",
+           "gs_deform_lbs", "gs_deform_lbs_backward", "gs_project", "gs_bin_sort_workspace", "gs_bin_sort",
+           "gs_composite_workspace", "gs_composite", "gs_render_backward_workspace", "gs_render_backward"]
+
+_lib = None
+
+
+class GSError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (status, msg))
+        self.status = status
+
+
+def load():
+    """Load libgs.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libgs.so is not built (%s); run __graft_entry__.build() or "
+                           "python -m paper_2604_12626_amd.build" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    i32, i64, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    lib.gs_status_string.restype = ctypes.c_char_p
+    lib.gs_status_string.argtypes = [ctypes.c_int]
+    lib.gs_last_error.restype = ctypes.c_char_p
+    lib.gs_version.restype = i32
+    lib.gs_default_params.argtypes = [ctypes.POINTER(Params), i32, i32]
+    lib.gs_instance_offsets.argtypes = [ctypes.POINTER(Gaussians), i32, i32, P, P]
+    lib.gs_deform_lbs.argtypes = [i64, P, P, P, P, P, P, P, i32, i32, P, P, P]
+    lib.gs_deform_lbs_backward.argtypes = [i64, P, P, P, P, P, P, P, i32, i32, P, P, P, P, P, P]
+    lib.gs_project.argtypes = [ctypes.POINTER(Gaussians), i32, P, i32, P, ctypes.POINTER(Params),
+                               ctypes.POINTER(Projected), P]
+    lib.gs_bin_sort_workspace.restype = sz
+    lib.gs_bin_sort_workspace.argtypes = [i64, i64, i32, ctypes.POINTER(Params)]
+    lib.gs_bin_sort.argtypes = [ctypes.POINTER(Projected), i32, ctypes.POINTER(Params), P, sz, P, P, i64, P, P, P, P]
+    lib.gs_composite_workspace.restype = sz
+    lib.gs_composite_workspace.argtypes = [i32, ctypes.POINTER(Params)]
+    lib.gs_composite.argtypes = [ctypes.POINTER(Projected), P, P, i32, ctypes.POINTER(Params), P, sz, P, P, P, P, P,
+                                 P]
+    lib.gs_render_backward_workspace.restype = sz
+    lib.gs_render_backward_workspace.argtypes = [i64]
+    lib.gs_render_backward.argtypes = [ctypes.POINTER(Gaussians), i32, P, i32, P, ctypes.POINTER(Params),
+                                       ctypes.POINTER(Projected), P, P, P, P, P, P, P, P, sz,
+                                       ctypes.POINTER(GaussiansGrad), P]
+    for f in ("gs_deform_lbs", "gs_deform_lbs_backward", "gs_project", "gs_bin_sort", "gs_composite",
+              "gs_render_backward", "gs_instance_offsets"):
+        getattr(lib, f).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(st):
+    if st != GS_OK:
+        lib = load()
+        raise GSError(lib.gs_status_string(st).decode(), lib.gs_last_error().decode())
+
+
+def ptr(t):
+    """Device (or host) address of a tensor, or None."""
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def stream_handle(device=None):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def make_params(width, height, bg=(0.0, 0.0, 0.0), **overrides):
+    lib = load()
+    p = Params()
+    lib.gs_default_params(ctypes.byref(p), int(width), int(height))
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    p.bg[0], p.bg[1], p.bg[2] = (float(x) for x in bg)
+    return p
+
+
+def _req(t, dtype, what):
+    if t is None:
+        return
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (what, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % what)
+
+
+def make_segment(g):
+    """gs_gaussians for a dict of device tensors (means, log_scales, quats, opacity, sh[, cov6], sh_degree)."""
+    for k in ("means", "log_scales", "quats", "opacity", "sh", "cov6"):
+        _req(g.get(k), torch.float32, k)
+    s = Gaussians()
+    s.n = int(g["means"].shape[0])
+    s.sh_degree = int(g["sh_degree"])
+    s.means = ptr(g["means"])
+    s.log_scales = ptr(g.get("log_scales"))
+    s.quats = ptr(g.get("quats"))
+    s.cov6 = ptr(g.get("cov6"))
+    s.opacity = ptr(g["opacity"])
+    s.sh = ptr(g["sh"])
+    return s
+
+
+def seg_array(segs):
+    arr = (Gaussians * len(segs))()
+    for i, g in enumerate(segs):
+        arr[i] = make_segment(g)
+    return arr
+
+
+def mask_array(view_segs):
+    """uint32 masks from per-view lists of segment indices."""
+    m = (ctypes.c_uint32 * len(view_segs))()
+    for v, ss in enumerate(view_segs):
+        x = 0
+        for s in ss:
+            x |= 1 << int(s)
+        m[v] = x
+    return m
+
+
+def instance_offsets(segs, view_segs):
+    lib = load()
+    arr = seg_array(segs)
+    masks = mask_array(view_segs)
+    off = (ctypes.c_int64 * (len(view_segs) + 1))()
+    _check(lib.gs_instance_offsets(arr, len(segs), len(view_segs), masks, off))
+    return list(off)
+
+
+def project(segs, cams, view_segs, params, tiles_touched, rec):
+    """gs_project: cams is a [V,16] float32 device tensor."""
+    lib = load()
+    _req(cams, torch.float32, "cams")
+    arr = seg_array(segs)
+    masks = mask_array(view_segs)
+    out = Projected(int(rec.shape[0]), ptr(tiles_touched), ptr(rec))
+    _check(lib.gs_project(arr, len(segs), ptr(cams), len(view_segs), masks, ctypes.byref(params), ctypes.byref(out),
+                          stream_handle()))
+
+
+def bin_sort_workspace(n_instances, capacity, n_views, params):
+    return int(load().gs_bin_sort_workspace(int(n_instances), int(capacity), int(n_views), ctypes.byref(params)))
+
+
+def bin_sort(tiles_touched, rec, n_views, params, ws, keys, vals, ranges, d_num, d_overflow):
+    lib = load()
+    proj = Projected(int(rec.shape[0]), ptr(tiles_touched), ptr(rec))
+    _check(lib.gs_bin_sort(ctypes.byref(proj), int(n_views), ctypes.byref(params), ptr(ws), ws.numel() * ws.element_size(),
+                           ptr(keys), ptr(vals), int(keys.shape[0]), ptr(ranges), ptr(d_num), ptr(d_overflow),
+                           stream_handle()))
+
+
+def composite_workspace(n_views, params):
+    return int(load().gs_composite_workspace(int(n_views), ctypes.byref(params)))
+
+
+def composite(rec, vals, ranges, n_views, params, ws, rgb, depth, alpha, t_final=None, n_contrib=None):
+    lib = load()
+    proj = Projected(int(rec.shape[0]), None, ptr(rec))
+    _check(lib.gs_composite(ctypes.byref(proj), ptr(vals), ptr(ranges), int(n_views), ctypes.byref(params), ptr(ws),
+                            ws.numel() * ws.element_size(), ptr(rgb), ptr(depth), ptr(alpha), ptr(t_final),
+                            ptr(n_contrib), stream_handle()))
+
+
+def render_backward_workspace(n_instances):
+    return int(load().gs_render_backward_workspace(int(n_instances)))
+
+
+def render_backward(segs, cams, view_segs, params, tiles_touched, rec, vals, ranges, t_final, n_contrib, d_rgb,
+                    d_depth, d_alpha, ws, grads):
+    """grads: list (per segment) of dicts of output tensors (means, log_scales, quats, cov6, opacity, sh)."""
+    lib = load()
+    arr = seg_array(segs)
+    masks = mask_array(view_segs)
+    garr = (GaussiansGrad * len(segs))()
+    for i, g in enumerate(grads):
+        garr[i] = GaussiansGrad(ptr(g.get("means")), ptr(g.get("log_scales")), ptr(g.get("quats")), ptr(g.get("cov6")),
+                                ptr(g.get("opacity")), ptr(g.get("sh")))
+    proj = Projected(int(rec.shape[0]), ptr(tiles_touched), ptr(rec))
+    _check(lib.gs_render_backward(arr, len(segs), ptr(cams), len(view_segs), masks, ctypes.byref(params),
+                                  ctypes.byref(proj), ptr(vals), ptr(ranges), ptr(t_final), ptr(n_contrib), ptr(d_rgb),
+                                  ptr(d_depth), ptr(d_alpha), ptr(ws), ws.numel() * ws.element_size(), garr,
+                                  stream_handle()))
+
+
+def deform_lbs(means_c, log_scales_c, quats_c, joint_idx, weights, avatar_of, skin_mats, means_out, cov6_out):
+    lib = load()
+    A, J = int(skin_mats.shape[0]), int(skin_mats.shape[1])
+    _check(lib.gs_deform_lbs(int(means_c.shape[0]), ptr(means_c), ptr(log_scales_c), ptr(quats_c), ptr(joint_idx),
+                             ptr(weights), ptr(avatar_of), ptr(skin_mats), A, J, ptr(means_out), ptr(cov6_out),
+                             stream_handle()))
+
+
+def deform_lbs_backward(means_c, log_scales_c, quats_c, joint_idx, weights, avatar_of, skin_mats, d_means_out,
+                        d_cov6_out, d_means, d_log_scales, d_quats):
+    lib = load()
+    A, J = int(skin_mats.shape[0]), int(skin_mats.shape[1])
+    _check(lib.gs_deform_lbs_backward(int(means_c.shape[0]), ptr(means_c), ptr(log_scales_c), ptr(quats_c),
+                                      ptr(joint_idx), ptr(weights), ptr(avatar_of), ptr(skin_mats), A, J,
+                                      ptr(d_means_out), ptr(d_cov6_out), ptr(d_means), ptr(d_log_scales),
+                                      ptr(d_quats), stream_handle()))

@@ -1,0 +1,457 @@
+// Host side of the C ABI declared in include/gs.h: argument validation,
+// workspace layout, instance bookkeeping and kernel launches.  Nothing here
+// allocates device memory or synchronises with the device.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "gs_internal.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+gs_status fail(gs_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+gs_status hip_fail(hipError_t e, const char *where) {
+    return fail(GS_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+void clear_error() { g_last_error.clear(); }
+
+bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+int tiles_x(const gs_params *p) { return (p->width + GS_TILE - 1) / GS_TILE; }
+int tiles_y(const gs_params *p) { return (p->height + GS_TILE - 1) / GS_TILE; }
+
+gs_status check_params(const gs_params *p) {
+    if (!p) return fail(GS_ERR_INVALID_ARGUMENT, "params is NULL");
+    if (p->width <= 0 || p->height <= 0 || p->width > 32768 || p->height > 32768)
+        return fail(GS_ERR_INVALID_ARGUMENT, "image size %dx%d outside [1, 32768]", p->width, p->height);
+    if (!(p->alpha_max > 0.f && p->alpha_max < 1.f) || !(p->alpha_min >= 0.f) || !(p->t_min >= 0.f) ||
+        !(p->near_plane > 0.f) || !(p->lowpass >= 0.f) || !(p->sigma_cut > 0.f) || !(p->fov_clamp > 0.f))
+        return fail(GS_ERR_INVALID_ARGUMENT, "rendering constants out of range");
+    return GS_OK;
+}
+
+gs_status check_segments(const gs_gaussians *segs, int32_t n_segs) {
+    if (n_segs < 1 || n_segs > GS_MAX_SEGMENTS)
+        return fail(GS_ERR_INVALID_ARGUMENT, "n_segs=%d outside [1, %d]", n_segs, GS_MAX_SEGMENTS);
+    if (!segs) return fail(GS_ERR_INVALID_ARGUMENT, "segs is NULL");
+    for (int s = 0; s < n_segs; ++s) {
+        const gs_gaussians &g = segs[s];
+        if (g.n < 0) return fail(GS_ERR_INVALID_ARGUMENT, "segment %d: n < 0", s);
+        if (g.sh_degree < 0 || g.sh_degree > GS_MAX_SH_DEGREE)
+            return fail(GS_ERR_INVALID_ARGUMENT, "segment %d: sh_degree %d outside [0, 3]", s, g.sh_degree);
+        if (g.n == 0) continue;
+        if (!g.means || !g.opacity || !g.sh)
+            return fail(GS_ERR_INVALID_ARGUMENT, "segment %d: means/opacity/sh is NULL", s);
+        if (!g.cov6 && (!g.log_scales || !g.quats))
+            return fail(GS_ERR_INVALID_ARGUMENT, "segment %d: needs cov6 or log_scales + quats", s);
+        if (!g.cov6 && !aligned(g.quats, 16))
+            return fail(GS_ERR_INVALID_ARGUMENT, "segment %d: quats must be 16-byte aligned", s);
+        const int K3 = 3 * (g.sh_degree + 1) * (g.sh_degree + 1);
+        if (K3 % 4 == 0 && !aligned(g.sh, 16))
+            return fail(GS_ERR_INVALID_ARGUMENT, "segment %d: sh must be 16-byte aligned", s);
+        if (!aligned(g.means, 4) || !aligned(g.opacity, 4) || !aligned(g.sh, 4) || (g.cov6 && !aligned(g.cov6, 4)))
+            return fail(GS_ERR_INVALID_ARGUMENT, "segment %d: arrays must be 4-byte aligned", s);
+    }
+    return GS_OK;
+}
+
+gs_status check_views(const gs_camera *cams, int32_t n_views, const uint32_t *mask, int32_t n_segs) {
+    if (n_views < 1 || n_views > GS_MAX_VIEWS)
+        return fail(GS_ERR_INVALID_ARGUMENT, "n_views=%d outside [1, %d]", n_views, GS_MAX_VIEWS);
+    if (!cams || !mask) return fail(GS_ERR_INVALID_ARGUMENT, "cams/view_seg_mask is NULL");
+    if (!aligned(cams, 4)) return fail(GS_ERR_INVALID_ARGUMENT, "cams must be 4-byte aligned");
+    const uint32_t allowed = n_segs >= 32 ? 0xFFFFFFFFu : ((1u << n_segs) - 1u);
+    for (int v = 0; v < n_views; ++v)
+        if (mask[v] & ~allowed)
+            return fail(GS_ERR_INVALID_ARGUMENT, "view %d draws segment bits 0x%x beyond n_segs=%d", v, mask[v], n_segs);
+    return GS_OK;
+}
+
+// offsets[v] (host) for every view, offsets[n_views] = total
+void instance_offsets(const gs_gaussians *segs, int32_t n_segs, int32_t n_views, const uint32_t *mask,
+                      int64_t *off) {
+    int64_t acc = 0;
+    for (int v = 0; v < n_views; ++v) {
+        off[v] = acc;
+        for (int s = 0; s < n_segs; ++s)
+            if (mask[v] & (1u << s)) acc += segs[s].n;
+    }
+    off[n_views] = acc;
+}
+
+int64_t seg_offset_in_view(const gs_gaussians *segs, uint32_t mask, int s) {
+    int64_t o = 0;
+    for (int t = 0; t < s; ++t)
+        if (mask & (1u << t)) o += segs[t].n;
+    return o;
+}
+
+std::mutex g_dev_mu;
+int g_cu_count[64] = {0};
+
+int cu_count() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    if (g_cu_count[dev] == 0) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+        g_cu_count[dev] = n;
+    }
+    return g_cu_count[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *gs_status_string(gs_status s) {
+    switch (s) {
+        case GS_OK: return "GS_OK";
+        case GS_ERR_INVALID_ARGUMENT: return "GS_ERR_INVALID_ARGUMENT";
+        case GS_ERR_UNSUPPORTED: return "GS_ERR_UNSUPPORTED";
+        case GS_ERR_WORKSPACE_TOO_SMALL: return "GS_ERR_WORKSPACE_TOO_SMALL";
+        case GS_ERR_HIP: return "GS_ERR_HIP";
+    }
+    return "GS_ERR_UNKNOWN";
+}
+
+const char *gs_last_error(void) { return g_last_error.c_str(); }
+
+int32_t gs_version(void) { return 1; }
+
+void gs_default_params(gs_params *p, int32_t width, int32_t height) {
+    if (!p) return;
+    p->width = width;
+    p->height = height;
+    p->near_plane = 0.2f;
+    p->lowpass = 0.3f;
+    p->sigma_cut = 3.0f;
+    p->fov_clamp = 1.3f;
+    p->alpha_max = 0.99f;
+    p->alpha_min = 1.0f / 255.0f;
+    p->t_min = 1e-4f;
+    p->bg[0] = p->bg[1] = p->bg[2] = 0.0f;
+}
+
+gs_status gs_instance_offsets(const gs_gaussians *segs, int32_t n_segs, int32_t n_views,
+                              const uint32_t *view_seg_mask, int64_t *offsets) {
+    clear_error();
+    gs_status st;
+    if ((st = check_segments(segs, n_segs)) != GS_OK) return st;
+    if (n_views < 1 || n_views > GS_MAX_VIEWS || !view_seg_mask || !offsets)
+        return fail(GS_ERR_INVALID_ARGUMENT, "bad views/mask/offsets");
+    instance_offsets(segs, n_segs, n_views, view_seg_mask, offsets);
+    return GS_OK;
+}
+
+// ---------------------------------------------------------------------------
+gs_status gs_deform_lbs(int64_t n, const float *means_c, const float *log_scales_c, const float *quats_c,
+                        const uint8_t *joint_idx, const float *weights, const int32_t *avatar_of,
+                        const float *skin_mats, int32_t n_avatars, int32_t n_joints, float *means_out,
+                        float *cov6_out, gs_stream_t stream) {
+    clear_error();
+    if (n < 0) return fail(GS_ERR_INVALID_ARGUMENT, "n < 0");
+    if (n_avatars < 1 || n_joints < 1 || n_joints > 256)
+        return fail(GS_ERR_INVALID_ARGUMENT, "n_avatars=%d / n_joints=%d invalid", n_avatars, n_joints);
+    if (n == 0) return GS_OK;
+    if (!means_c || !log_scales_c || !quats_c || !joint_idx || !weights || !avatar_of || !skin_mats || !means_out ||
+        !cov6_out)
+        return fail(GS_ERR_INVALID_ARGUMENT, "NULL array");
+    if (!aligned(quats_c, 16) || !aligned(weights, 16) || !aligned(skin_mats, 16) || !aligned(joint_idx, 4))
+        return fail(GS_ERR_INVALID_ARGUMENT, "quats/weights/skin_mats need 16-byte, joint_idx 4-byte alignment");
+    gs::LbsArgs a = {};
+    a.n = n;
+    a.means = means_c;
+    a.log_scales = log_scales_c;
+    a.quats = quats_c;
+    a.joint_idx = joint_idx;
+    a.weights = weights;
+    a.avatar_of = avatar_of;
+    a.skin = skin_mats;
+    a.n_avatars = n_avatars;
+    a.n_joints = n_joints;
+    a.means_out = means_out;
+    a.cov6_out = cov6_out;
+    hipError_t e = gs::launch_lbs(a, false, (hipStream_t)stream);
+    return e == hipSuccess ? GS_OK : hip_fail(e, "gs_deform_lbs");
+}
+
+gs_status gs_deform_lbs_backward(int64_t n, const float *means_c, const float *log_scales_c, const float *quats_c,
+                                 const uint8_t *joint_idx, const float *weights, const int32_t *avatar_of,
+                                 const float *skin_mats, int32_t n_avatars, int32_t n_joints,
+                                 const float *d_means_out, const float *d_cov6_out, float *d_means_c,
+                                 float *d_log_scales_c, float *d_quats_c, gs_stream_t stream) {
+    clear_error();
+    if (n < 0) return fail(GS_ERR_INVALID_ARGUMENT, "n < 0");
+    if (n_avatars < 1 || n_joints < 1 || n_joints > 256)
+        return fail(GS_ERR_INVALID_ARGUMENT, "n_avatars=%d / n_joints=%d invalid", n_avatars, n_joints);
+    if (n == 0) return GS_OK;
+    if (!means_c || !log_scales_c || !quats_c || !joint_idx || !weights || !avatar_of || !skin_mats ||
+        !d_means_out || !d_cov6_out || !d_means_c || !d_log_scales_c || !d_quats_c)
+        return fail(GS_ERR_INVALID_ARGUMENT, "NULL array");
+    if (!aligned(quats_c, 16) || !aligned(weights, 16) || !aligned(skin_mats, 16) || !aligned(joint_idx, 4) ||
+        !aligned(d_quats_c, 16))
+        return fail(GS_ERR_INVALID_ARGUMENT, "quats/weights/skin_mats/d_quats need 16-byte alignment");
+    gs::LbsArgs a = {};
+    a.n = n;
+    a.means = means_c;
+    a.log_scales = log_scales_c;
+    a.quats = quats_c;
+    a.joint_idx = joint_idx;
+    a.weights = weights;
+    a.avatar_of = avatar_of;
+    a.skin = skin_mats;
+    a.n_avatars = n_avatars;
+    a.n_joints = n_joints;
+    a.d_means_out = d_means_out;
+    a.d_cov6_out = d_cov6_out;
+    a.d_means = d_means_c;
+    a.d_log_scales = d_log_scales_c;
+    a.d_quats = d_quats_c;
+    hipError_t e = gs::launch_lbs(a, true, (hipStream_t)stream);
+    return e == hipSuccess ? GS_OK : hip_fail(e, "gs_deform_lbs_backward");
+}
+
+// ---------------------------------------------------------------------------
+gs_status gs_project(const gs_gaussians *segs, int32_t n_segs, const gs_camera *cams, int32_t n_views,
+                     const uint32_t *view_seg_mask, const gs_params *p, gs_projected *out, gs_stream_t stream) {
+    clear_error();
+    gs_status st;
+    if ((st = check_params(p)) != GS_OK) return st;
+    if ((st = check_segments(segs, n_segs)) != GS_OK) return st;
+    if ((st = check_views(cams, n_views, view_seg_mask, n_segs)) != GS_OK) return st;
+    if (!out) return fail(GS_ERR_INVALID_ARGUMENT, "out is NULL");
+    std::vector<int64_t> off(n_views + 1);
+    instance_offsets(segs, n_segs, n_views, view_seg_mask, off.data());
+    if (out->n_instances != off[n_views])
+        return fail(GS_ERR_INVALID_ARGUMENT, "out->n_instances=%lld but the views draw %lld instances",
+                    (long long)out->n_instances, (long long)off[n_views]);
+    if (off[n_views] > 0xFFFFFFFFll) return fail(GS_ERR_UNSUPPORTED, "more than 2^32-1 instances");
+    if (off[n_views] == 0) return GS_OK;
+    if (!out->tiles_touched || !out->rec) return fail(GS_ERR_INVALID_ARGUMENT, "out arrays are NULL");
+    if (!aligned(out->rec, 16)) return fail(GS_ERR_INVALID_ARGUMENT, "rec must be 16-byte aligned");
+    for (int s = 0; s < n_segs; ++s) {
+        std::vector<int> views;
+        for (int v = 0; v < n_views; ++v)
+            if (view_seg_mask[v] & (1u << s)) views.push_back(v);
+        for (size_t c = 0; c < views.size(); c += gs::kProjViews) {
+            gs::ProjectArgs a = {};
+            a.seg = segs[s];
+            a.cams = cams;
+            a.tiles_touched = out->tiles_touched;
+            a.rec = reinterpret_cast<float4 *>(out->rec);
+            a.nv = (int)std::min(views.size() - c, (size_t)gs::kProjViews);
+            for (int k = 0; k < a.nv; ++k) {
+                const int v = views[c + k];
+                a.view[k] = v;
+                a.base[k] = off[v] + seg_offset_in_view(segs, view_seg_mask[v], s);
+            }
+            a.W = p->width;
+            a.H = p->height;
+            a.TX = tiles_x(p);
+            a.TY = tiles_y(p);
+            a.near_plane = p->near_plane;
+            a.lowpass = p->lowpass;
+            a.sigma_cut = p->sigma_cut;
+            a.fov_clamp = p->fov_clamp;
+            hipError_t e = gs::launch_project(a, (hipStream_t)stream);
+            if (e != hipSuccess) return hip_fail(e, "gs_project");
+        }
+    }
+    return GS_OK;
+}
+
+// ---------------------------------------------------------------------------
+size_t gs_bin_sort_workspace(int64_t n_instances, int64_t capacity, int32_t n_views, const gs_params *p) {
+    if (!p || n_views < 1 || capacity < 1 || n_instances < 0) return 0;
+    const int64_t T = (int64_t)tiles_x(p) * tiles_y(p);
+    return gs::make_sort_plan(n_instances, capacity, T * n_views).total;
+}
+
+gs_status gs_bin_sort(const gs_projected *proj, int32_t n_views, const gs_params *p, void *ws, size_t ws_bytes,
+                      uint64_t *keys, uint32_t *vals, int64_t capacity, uint32_t *tile_ranges,
+                      int64_t *d_num_instances, int32_t *d_overflow, gs_stream_t stream) {
+    clear_error();
+    gs_status st;
+    if ((st = check_params(p)) != GS_OK) return st;
+    if (!proj || proj->n_instances < 0) return fail(GS_ERR_INVALID_ARGUMENT, "proj is NULL or has n < 0");
+    if (n_views < 1 || n_views > GS_MAX_VIEWS) return fail(GS_ERR_INVALID_ARGUMENT, "n_views=%d", n_views);
+    if (capacity < 1) return fail(GS_ERR_INVALID_ARGUMENT, "capacity < 1");
+    if (capacity > GS_MAX_CAPACITY) return fail(GS_ERR_UNSUPPORTED, "capacity above %lld", (long long)GS_MAX_CAPACITY);
+    if (proj->n_instances > 0 && (!proj->tiles_touched || !proj->rec || !aligned(proj->rec, 16)))
+        return fail(GS_ERR_INVALID_ARGUMENT, "proj arrays NULL or rec not 16-byte aligned");
+    if (!keys || !vals || !tile_ranges || !d_num_instances || !d_overflow || !ws)
+        return fail(GS_ERR_INVALID_ARGUMENT, "NULL output or workspace");
+    if (!aligned(keys, 8) || !aligned(tile_ranges, 8) || !aligned(d_num_instances, 8) || !aligned(ws, 256))
+        return fail(GS_ERR_INVALID_ARGUMENT, "keys/ranges/counter need 8-byte, ws 256-byte alignment");
+    const int64_t T = (int64_t)tiles_x(p) * tiles_y(p);
+    if (T * n_views > (1ll << 31)) return fail(GS_ERR_UNSUPPORTED, "more than 2^31 tiles");
+    const gs::SortPlan plan = gs::make_sort_plan(proj->n_instances, capacity, T * n_views);
+    if (ws_bytes < plan.total)
+        return fail(GS_ERR_WORKSPACE_TOO_SMALL, "workspace %zu < %zu bytes", ws_bytes, plan.total);
+    hipError_t e = gs::run_bin_sort(plan, proj->tiles_touched, reinterpret_cast<const float4 *>(proj->rec),
+                                    tiles_x(p), tiles_y(p), static_cast<char *>(ws), keys, vals, tile_ranges,
+                                    d_num_instances, d_overflow, (hipStream_t)stream);
+    return e == hipSuccess ? GS_OK : hip_fail(e, "gs_bin_sort");
+}
+
+// ---------------------------------------------------------------------------
+size_t gs_composite_workspace(int32_t n_views, const gs_params *p) {
+    (void)n_views;
+    (void)p;
+    return 256;
+}
+
+gs_status gs_composite(const gs_projected *proj, const uint32_t *vals, const uint32_t *tile_ranges,
+                       int32_t n_views, const gs_params *p, void *ws, size_t ws_bytes, float *rgb, float *depth,
+                       float *alpha, float *t_final, uint32_t *n_contrib, gs_stream_t stream) {
+    clear_error();
+    gs_status st;
+    if ((st = check_params(p)) != GS_OK) return st;
+    if (!proj || !vals || !tile_ranges || !rgb || !depth || !alpha || !ws)
+        return fail(GS_ERR_INVALID_ARGUMENT, "NULL argument");
+    if (n_views < 1 || n_views > GS_MAX_VIEWS) return fail(GS_ERR_INVALID_ARGUMENT, "n_views=%d", n_views);
+    if (proj->n_instances > 0 && (!proj->rec || !aligned(proj->rec, 16)))
+        return fail(GS_ERR_INVALID_ARGUMENT, "rec NULL or not 16-byte aligned");
+    if (!aligned(tile_ranges, 8) || !aligned(ws, 4)) return fail(GS_ERR_INVALID_ARGUMENT, "misaligned ranges/ws");
+    if (ws_bytes < gs_composite_workspace(n_views, p)) return fail(GS_ERR_WORKSPACE_TOO_SMALL, "workspace too small");
+    gs::CompositeArgs a = {};
+    a.rec = reinterpret_cast<const float4 *>(proj->rec);
+    a.vals = vals;
+    a.ranges = reinterpret_cast<const uint2 *>(tile_ranges);
+    a.counter = static_cast<uint32_t *>(ws);
+    a.W = p->width;
+    a.H = p->height;
+    a.TX = tiles_x(p);
+    a.T = tiles_x(p) * tiles_y(p);
+    a.n_items = (int64_t)a.T * n_views;
+    a.alpha_max = p->alpha_max;
+    a.alpha_min = p->alpha_min;
+    a.t_min = p->t_min;
+    a.bg0 = p->bg[0];
+    a.bg1 = p->bg[1];
+    a.bg2 = p->bg[2];
+    a.rgb = rgb;
+    a.depth = depth;
+    a.alpha = alpha;
+    a.t_final = t_final;
+    a.n_contrib = n_contrib;
+    hipError_t e = gs::launch_fill_u32(a.counter, 0u, 1, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "gs_composite");
+    int64_t grid = (int64_t)cu_count() * 8;
+    if (grid > a.n_items) grid = a.n_items;
+    e = gs::launch_composite(a, (int)grid, (hipStream_t)stream);
+    return e == hipSuccess ? GS_OK : hip_fail(e, "gs_composite");
+}
+
+// ---------------------------------------------------------------------------
+size_t gs_render_backward_workspace(int64_t n_instances) {
+    if (n_instances < 0) return 0;
+    return (size_t)(n_instances > 0 ? n_instances : 1) * gs::kG2D * sizeof(float);
+}
+
+gs_status gs_render_backward(const gs_gaussians *segs, int32_t n_segs, const gs_camera *cams, int32_t n_views,
+                             const uint32_t *view_seg_mask, const gs_params *p, const gs_projected *proj,
+                             const uint32_t *vals, const uint32_t *tile_ranges, const float *t_final,
+                             const uint32_t *n_contrib, const float *d_rgb, const float *d_depth,
+                             const float *d_alpha, void *ws, size_t ws_bytes, const gs_gaussians_grad *grads,
+                             gs_stream_t stream) {
+    clear_error();
+    gs_status st;
+    if ((st = check_params(p)) != GS_OK) return st;
+    if ((st = check_segments(segs, n_segs)) != GS_OK) return st;
+    if ((st = check_views(cams, n_views, view_seg_mask, n_segs)) != GS_OK) return st;
+    if (!proj || !vals || !tile_ranges || !t_final || !n_contrib || !ws || !grads)
+        return fail(GS_ERR_INVALID_ARGUMENT, "NULL argument");
+    std::vector<int64_t> off(n_views + 1);
+    instance_offsets(segs, n_segs, n_views, view_seg_mask, off.data());
+    if (proj->n_instances != off[n_views])
+        return fail(GS_ERR_INVALID_ARGUMENT, "proj->n_instances does not match the views");
+    if (ws_bytes < gs_render_backward_workspace(proj->n_instances))
+        return fail(GS_ERR_WORKSPACE_TOO_SMALL, "workspace too small");
+    for (int s = 0; s < n_segs; ++s) {
+        if (segs[s].n == 0) continue;
+        const gs_gaussians_grad &g = grads[s];
+        if (!g.means || !g.opacity || !g.sh) return fail(GS_ERR_INVALID_ARGUMENT, "segment %d: NULL gradient", s);
+        if (!segs[s].cov6 && g.quats && !aligned(g.quats, 16))
+            return fail(GS_ERR_INVALID_ARGUMENT, "segment %d: quats gradient must be 16-byte aligned", s);
+    }
+    hipStream_t sm = (hipStream_t)stream;
+    float *g2d = static_cast<float *>(ws);
+    hipError_t e = gs::launch_fill_u32(reinterpret_cast<uint32_t *>(g2d), 0u, proj->n_instances * gs::kG2D, sm);
+    if (e != hipSuccess) return hip_fail(e, "gs_render_backward");
+    gs::BackwardTileArgs b = {};
+    b.rec = reinterpret_cast<const float4 *>(proj->rec);
+    b.vals = vals;
+    b.ranges = reinterpret_cast<const uint2 *>(tile_ranges);
+    b.t_final = t_final;
+    b.n_contrib = n_contrib;
+    b.d_rgb = d_rgb;
+    b.d_depth = d_depth;
+    b.d_alpha = d_alpha;
+    b.g2d = g2d;
+    b.W = p->width;
+    b.H = p->height;
+    b.TX = tiles_x(p);
+    b.T = tiles_x(p) * tiles_y(p);
+    b.n_items = (int64_t)b.T * n_views;
+    b.alpha_max = p->alpha_max;
+    b.alpha_min = p->alpha_min;
+    b.bg0 = p->bg[0];
+    b.bg1 = p->bg[1];
+    b.bg2 = p->bg[2];
+    if (proj->n_instances > 0) {
+        e = gs::launch_backward_tiles(b, sm);
+        if (e != hipSuccess) return hip_fail(e, "gs_render_backward (tiles)");
+    }
+    for (int s = 0; s < n_segs; ++s) {
+        std::vector<int> views;
+        for (int v = 0; v < n_views; ++v)
+            if (view_seg_mask[v] & (1u << s)) views.push_back(v);
+        size_t c = 0;
+        do {
+            gs::BackwardProjectArgs a = {};
+            a.seg = segs[s];
+            a.grad = grads[s];
+            a.cams = cams;
+            a.tiles_touched = proj->tiles_touched;
+            a.g2d = g2d;
+            a.nv = (int)std::min(views.size() - c, (size_t)gs::kProjViews);
+            for (int k = 0; k < a.nv; ++k) {
+                const int v = views[c + k];
+                a.view[k] = v;
+                a.base[k] = off[v] + seg_offset_in_view(segs, view_seg_mask[v], s);
+            }
+            a.first = (c == 0) ? 1 : 0;
+            a.W = p->width;
+            a.H = p->height;
+            a.near_plane = p->near_plane;
+            a.lowpass = p->lowpass;
+            a.sigma_cut = p->sigma_cut;
+            a.fov_clamp = p->fov_clamp;
+            e = gs::launch_backward_project(a, sm);
+            if (e != hipSuccess) return hip_fail(e, "gs_render_backward (projection)");
+            c += gs::kProjViews;
+        } while (c < views.size());
+    }
+    return GS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,381 @@
+// gs_render_backward kernels.
+//
+// B1 (per tile, 256 threads = one per pixel): walks the tile's list back to
+// front from the last composited entry, recomputing each alpha with exactly
+// the forward's FP32 expression (so every skip/stop/clamp decision repeats),
+// recovering the transmittance by T_i = T_{i+1} / (1 - alpha_i), and forming
+// the screen-space adjoint of each entry (u, v, conic, opacity, colour,
+// depth).  Per entry the 64 lanes of a wave are summed with cross-lane adds
+// and one lane issues the global float atomics; entries no lane of the wave
+// reached are skipped with a ballot.
+//
+// B2 (per Gaussian of a segment, scene-major): chains the screen-space
+// adjoints of every view that drew the Gaussian through the projection to the
+// 3D parameters and writes the dense gradients once (no atomics).
+#include "gs_ewa.hpp"
+
+namespace gs {
+
+
+
+constexpr int kBwdBatch = 256;
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const BackwardTileArgs a) {
+    __shared__ float s_u[kBwdBatch], s_v[kBwdBatch], s_a[kBwdBatch], s_b[kBwdBatch], s_c[kBwdBatch],
+        s_o[kBwdBatch], s_z[kBwdBatch], s_r[kBwdBatch], s_g[kBwdBatch], s_bl[kBwdBatch], s_A[kBwdBatch],
+        s_B[kBwdBatch], s_C[kBwdBatch];
+    __shared__ uint32_t s_gid[kBwdBatch];
+    __shared__ uint32_t s_maxlast;
+    const int tid = threadIdx.x;
+    const int64_t item = blockIdx.x;
+    const int view = (int)(item / a.T);
+    const int tile = (int)(item - (int64_t)view * a.T);
+    const int px = (tile % a.TX) * kTile + (tid & (kTile - 1));
+    const int py = (tile / a.TX) * kTile + (tid >> 4);
+    const bool inside = px < a.W && py < a.H;
+    const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+    const uint2 range = a.ranges[item];
+
+    float T = 1.0f, Tfin = 1.0f;
+    uint32_t last = 0;
+    float dR = 0.f, dG = 0.f, dB = 0.f, dD = 0.f, dA = 0.f;
+    if (inside) {
+        const size_t pix = ((size_t)view * a.H + py) * a.W + px;
+        Tfin = a.t_final[pix];
+        T = Tfin;
+        last = a.n_contrib[pix];
+        if (a.d_rgb) {
+            dR = a.d_rgb[3 * pix];
+            dG = a.d_rgb[3 * pix + 1];
+            dB = a.d_rgb[3 * pix + 2];
+        }
+        if (a.d_depth) dD = a.d_depth[pix];
+        if (a.d_alpha) dA = a.d_alpha[pix];
+    }
+    if (tid == 0) s_maxlast = 0u;
+    __syncthreads();
+    if (last) atomicMax(&s_maxlast, last);
+    __syncthreads();
+    const uint32_t maxlast = min(s_maxlast, range.y - range.x);
+    // suffix colour / depth behind the current entry (background at the end)
+    float Sr = a.bg0, Sg = a.bg1, Sb = a.bg2, Sd = 0.0f;
+    const int lane = tid & 63;
+
+    // batches [lo, hi) of list positions, from the back
+    for (int64_t hi = (int64_t)maxlast; hi > 0; hi -= kBwdBatch) {
+        const int64_t lo = hi - kBwdBatch > 0 ? hi - kBwdBatch : 0;
+        const int nb = (int)(hi - lo);
+        if (tid < nb) {
+            const uint32_t g = a.vals[range.x + (uint32_t)lo + tid];
+            const float4 q0 = a.rec[3 * (size_t)g], q1 = a.rec[3 * (size_t)g + 1], q2 = a.rec[3 * (size_t)g + 2];
+            const Entry e = make_entry(q0, q1, q2);
+            s_u[tid] = e.u;
+            s_v[tid] = e.v;
+            s_a[tid] = e.a;
+            s_b[tid] = e.b;
+            s_c[tid] = e.c;
+            s_o[tid] = e.o;
+            s_z[tid] = e.z;
+            s_r[tid] = e.r;
+            s_g[tid] = e.g;
+            s_bl[tid] = e.bl;
+            s_A[tid] = q1.x;
+            s_B[tid] = q1.y;
+            s_C[tid] = q1.z;
+            s_gid[tid] = g;
+        }
+        __syncthreads();
+        for (int k = nb - 1; k >= 0; --k) {
+            const uint32_t pos = (uint32_t)(lo + k);  // list position of this entry
+            float gu = 0.f, gv = 0.f, gA = 0.f, gB = 0.f, gC = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gb = 0.f, gz = 0.f;
+            bool contrib = false;
+            if (pos < last) {  // pos < maxlast <= list length
+                const float dx = fx - s_u[k], dy = fy - s_v[k];
+                const float p2 = entry_power2(s_a[k], s_b[k], s_c[k], dx, dy);
+                const float G = exp2f(p2);
+                const float oG = s_o[k] * G;
+                const float al = fminf(a.alpha_max, oG);
+                if (!(al < a.alpha_min)) {
+                    contrib = true;
+                    const float one_m = 1.0f - al;
+                    T = T / one_m;  // transmittance in front of this entry
+                    const float w = al * T;
+                    gr = dR * w;
+                    gg = dG * w;
+                    gb = dB * w;
+                    gz = dD * w;
+                    const float dal = T * (dR * (s_r[k] - Sr) + dG * (s_g[k] - Sg) + dB * (s_bl[k] - Sb) +
+                                           dD * (s_z[k] - Sd)) +
+                                      dA * Tfin / one_m;
+                    if (!(oG > a.alpha_max)) {
+                        go = dal * G;
+                        // dL/dP with P the natural-log exponent (dG/dP = G)
+                        const float dP = dal * s_o[k] * G;
+                        gu = dP * (s_A[k] * dx + s_B[k] * dy);
+                        gv = dP * (s_B[k] * dx + s_C[k] * dy);
+                        gA = -0.5f * dP * dx * dx;
+                        gB = -dP * dx * dy;
+                        gC = -0.5f * dP * dy * dy;
+                    }
+                    Sr = al * s_r[k] + one_m * Sr;
+                    Sg = al * s_g[k] + one_m * Sg;
+                    Sb = al * s_bl[k] + one_m * Sb;
+                    Sd = al * s_z[k] + one_m * Sd;
+                }
+            }
+            if (__ballot(contrib) == 0ull) continue;
+            gu = wave_sum(gu);
+            gv = wave_sum(gv);
+            gA = wave_sum(gA);
+            gB = wave_sum(gB);
+            gC = wave_sum(gC);
+            go = wave_sum(go);
+            gr = wave_sum(gr);
+            gg = wave_sum(gg);
+            gb = wave_sum(gb);
+            gz = wave_sum(gz);
+            if (lane == 0) {
+                float *dst = a.g2d + (size_t)s_gid[k] * kG2D;
+                atomicAdd(dst + kGU, gu);
+                atomicAdd(dst + kGV, gv);
+                atomicAdd(dst + kGA, gA);
+                atomicAdd(dst + kGB, gB);
+                atomicAdd(dst + kGC, gC);
+                atomicAdd(dst + kGO, go);
+                atomicAdd(dst + kGR, gr);
+                atomicAdd(dst + kGG, gg);
+                atomicAdd(dst + kGBl, gb);
+                atomicAdd(dst + kGZ, gz);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_backward_tiles(const BackwardTileArgs &a, hipStream_t s) {
+    if (a.n_items == 0) return hipSuccess;
+    hipLaunchKernelGGL(backward_tile_kernel, dim3((unsigned)a.n_items), dim3(kTilePixels), 0, s, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// B2: screen-space adjoints -> 3D parameters
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void __launch_bounds__(256) backward_project_kernel(const BackwardProjectArgs a) {
+    constexpr int K = (D + 1) * (D + 1);
+    __shared__ float s_cam[kProjViews * kCamStride];
+    for (int k = threadIdx.x; k < a.nv * 16; k += blockDim.x) {
+        const int vi = k >> 4, f = k & 15;
+        s_cam[vi * kCamStride + f] = reinterpret_cast<const float *>(a.cams + a.view[vi])[f];
+    }
+    __syncthreads();
+    for (int vi = threadIdx.x; vi < a.nv; vi += blockDim.x) {
+        float *c = s_cam + vi * kCamStride;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) c[16 + j] = -(c[j] * c[9] + c[3 + j] * c[10] + c[6 + j] * c[11]);
+    }
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.seg.n) return;
+
+    const float mx = a.seg.means[3 * i + 0], my = a.seg.means[3 * i + 1], mz = a.seg.means[3 * i + 2];
+    float S[6];
+    Rot rot;
+    float sc[3];
+    const bool use_cov6 = a.seg.cov6 != nullptr;
+    if (use_cov6) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) S[k] = a.seg.cov6[6 * i + k];
+    } else {
+        const float4 q = reinterpret_cast<const float4 *>(a.seg.quats)[i];
+        rot = quat_rot(q.x, q.y, q.z, q.w);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) sc[k] = expf(a.seg.log_scales[3 * i + k]);
+        cov_from_rot_scale(rot.R, sc, S);
+    }
+
+    float dmu[3] = {0.f, 0.f, 0.f};
+    float dS[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // symmetric adjoint of Sigma (xx, xy, xz, yy, yz, zz)
+    float dsh[3 * K];
+#pragma unroll
+    for (int k = 0; k < 3 * K; ++k) dsh[k] = 0.f;
+    float dop = 0.f;
+    float sh[3 * K];
+    bool have_sh = false;
+
+    for (int vi = 0; vi < a.nv; ++vi) {
+        const int64_t inst = a.base[vi] + i;
+        if (a.tiles_touched[inst] == 0u) continue;
+        const float *g = a.g2d + (size_t)inst * kG2D;
+        float gl[kG2D];
+#pragma unroll
+        for (int k = 0; k < kG2D; ++k) gl[k] = g[k];
+        const float *cam = s_cam + vi * kCamStride;
+        ViewProj p;
+        // the same FP32 projection as the forward; the instance is known to be
+        // visible (tiles_touched > 0), so every field used below is computed
+        const int TX = (a.W + kTile - 1) / kTile, TY = (a.H + kTile - 1) / kTile;
+        (void)ewa_project(cam, mx, my, mz, S, a.W, a.H, TX, TY, a.near_plane, a.lowpass, a.sigma_cut, a.fov_clamp, p);
+        dop += gl[kGO];
+        // ---- colour -> SH coefficients and view direction
+        if (!have_sh) {
+            const float *src = a.seg.sh + (size_t)(3 * K) * i;
+#pragma unroll
+            for (int k = 0; k < 3 * K; ++k) sh[k] = src[k];
+            have_sh = true;
+        }
+        float dx0 = mx - cam[16], dy0 = my - cam[17], dz0 = mz - cam[18];
+        const float inv_dist = 1.0f / sqrtf(dx0 * dx0 + dy0 * dy0 + dz0 * dz0);
+        const float x = dx0 * inv_dist, y = dy0 * inv_dist, z = dz0 * inv_dist;
+        float Y[K];
+        float3 dY[K];
+        sh_basis<D>(x, y, z, Y);
+        sh_basis_grad<D>(x, y, z, dY);
+        float dc[3] = {gl[kGR], gl[kGG], gl[kGBl]};
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            float acc = 0.0f;  // same accumulation order as the forward
+#pragma unroll
+            for (int k = 0; k < K; ++k) acc += Y[k] * sh[3 * k + ch];
+            if (!(acc + 0.5f > 0.0f)) dc[ch] = 0.0f;
+        }
+        float ddx = 0.f, ddy = 0.f, ddz = 0.f;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const float cdot = dc[0] * sh[3 * k] + dc[1] * sh[3 * k + 1] + dc[2] * sh[3 * k + 2];
+            ddx += cdot * dY[k].x;
+            ddy += cdot * dY[k].y;
+            ddz += cdot * dY[k].z;
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) dsh[3 * k + ch] += dc[ch] * Y[k];
+        }
+        const float dd = x * ddx + y * ddy + z * ddz;
+        dmu[0] += (ddx - x * dd) * inv_dist;
+        dmu[1] += (ddy - y * dd) * inv_dist;
+        dmu[2] += (ddz - z * dd) * inv_dist;
+        // ---- conic -> 2D covariance: dS2 = -Q Gm Q, Gm = [[gA, gB/2], [gB/2, gC]]
+        const float qa = p.A, qb = p.B, qc = p.C;
+        const float ga = gl[kGA], gbh = 0.5f * gl[kGB], gc = gl[kGC];
+        // Q Gm
+        const float m00 = qa * ga + qb * gbh, m01 = qa * gbh + qb * gc;
+        const float m10 = qb * ga + qc * gbh, m11 = qb * gbh + qc * gc;
+        const float s00 = -(m00 * qa + m01 * qb);
+        const float s01 = -(m00 * qb + m01 * qc);
+        const float s11 = -(m10 * qb + m11 * qc);
+        // ---- 2D covariance -> Sigma and T:  S2 = T Sigma T^T + lp I
+        const float *T0 = p.T0, *T1 = p.T1;
+        // dSigma += T^T dS2 T
+        float U[3][2];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            U[r][0] = T0[r] * s00 + T1[r] * s01;
+            U[r][1] = T0[r] * s01 + T1[r] * s11;
+        }
+        dS[0] += U[0][0] * T0[0] + U[0][1] * T1[0];
+        dS[1] += U[0][0] * T0[1] + U[0][1] * T1[1];
+        dS[2] += U[0][0] * T0[2] + U[0][1] * T1[2];
+        dS[3] += U[1][0] * T0[1] + U[1][1] * T1[1];
+        dS[4] += U[1][0] * T0[2] + U[1][1] * T1[2];
+        dS[5] += U[2][0] * T0[2] + U[2][1] * T1[2];
+        // dT = 2 dS2 T Sigma
+        float TS0[3], TS1[3];
+        TS0[0] = T0[0] * S[0] + T0[1] * S[1] + T0[2] * S[2];
+        TS0[1] = T0[0] * S[1] + T0[1] * S[3] + T0[2] * S[4];
+        TS0[2] = T0[0] * S[2] + T0[1] * S[4] + T0[2] * S[5];
+        TS1[0] = T1[0] * S[0] + T1[1] * S[1] + T1[2] * S[2];
+        TS1[1] = T1[0] * S[1] + T1[1] * S[3] + T1[2] * S[4];
+        TS1[2] = T1[0] * S[2] + T1[1] * S[4] + T1[2] * S[5];
+        float dT0[3], dT1[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            dT0[c] = 2.f * (s00 * TS0[c] + s01 * TS1[c]);
+            dT1[c] = 2.f * (s01 * TS0[c] + s11 * TS1[c]);
+        }
+        // T = J W: dJ = dT W^T;  J00 = fx/z, J02 = -fx xr/z, J11 = fy/z, J12 = -fy yr/z
+        const float *R = cam;
+        const float dJ00 = dT0[0] * R[0] + dT0[1] * R[1] + dT0[2] * R[2];
+        const float dJ02 = dT0[0] * R[6] + dT0[1] * R[7] + dT0[2] * R[8];
+        const float dJ11 = dT1[0] * R[3] + dT1[1] * R[4] + dT1[2] * R[5];
+        const float dJ12 = dT1[0] * R[6] + dT1[1] * R[7] + dT1[2] * R[8];
+        const float fxc = cam[12], fyc = cam[13];
+        const float tz = p.tz, iz = 1.0f / tz, iz2 = iz * iz;
+        float dtx = 0.f, dty = 0.f, dtz = 0.f;
+        dtz += -fxc * iz2 * dJ00 - fyc * iz2 * dJ11;
+        dtz += dJ02 * fxc * p.xr * iz2 + dJ12 * fyc * p.yr * iz2;
+        if (!p.clx) {
+            dtx += dJ02 * (-fxc * iz) * iz;
+            dtz += dJ02 * (-fxc * iz) * (-p.tx * iz2);
+        }
+        if (!p.cly) {
+            dty += dJ12 * (-fyc * iz) * iz;
+            dtz += dJ12 * (-fyc * iz) * (-p.ty * iz2);
+        }
+        // ---- projected mean and depth
+        dtx += gl[kGU] * fxc * iz;
+        dty += gl[kGV] * fyc * iz;
+        dtz += -gl[kGU] * fxc * p.tx * iz2 - gl[kGV] * fyc * p.ty * iz2 + gl[kGZ];
+        dmu[0] += R[0] * dtx + R[3] * dty + R[6] * dtz;
+        dmu[1] += R[1] * dtx + R[4] * dty + R[7] * dtz;
+        dmu[2] += R[2] * dtx + R[5] * dty + R[8] * dtz;
+    }
+
+    const gs_gaussians_grad &G = a.grad;
+    const bool first = a.first != 0;
+    auto put = [&](float *dst, float v) {
+        if (first) *dst = v;
+        else *dst += v;
+    };
+#pragma unroll
+    for (int k = 0; k < 3; ++k) put(&G.means[3 * i + k], dmu[k]);
+    put(&G.opacity[i], dop);
+    {
+        float *dst = G.sh + (size_t)(3 * K) * i;
+#pragma unroll
+        for (int k = 0; k < 3 * K; ++k) put(&dst[k], dsh[k]);
+    }
+    if (use_cov6) {
+        if (G.cov6) {
+            // an off-diagonal cov6 entry stands for both symmetric entries
+            put(&G.cov6[6 * i + 0], dS[0]);
+            put(&G.cov6[6 * i + 1], 2.0f * dS[1]);
+            put(&G.cov6[6 * i + 2], 2.0f * dS[2]);
+            put(&G.cov6[6 * i + 3], dS[3]);
+            put(&G.cov6[6 * i + 4], 2.0f * dS[4]);
+            put(&G.cov6[6 * i + 5], dS[5]);
+        }
+    } else {
+        // adjoint of every entry of the full symmetric Sigma
+        const float full[9] = {dS[0], dS[1], dS[2], dS[1], dS[3], dS[4], dS[2], dS[4], dS[5]};
+        float dls[3], dq[4];
+        cov_backward(rot, sc, full, dls, dq);
+        if (G.log_scales) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) put(&G.log_scales[3 * i + k], dls[k]);
+        }
+        if (G.quats) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) put(&G.quats[4 * i + k], dq[k]);
+        }
+    }
+}
+
+hipError_t launch_backward_project(const BackwardProjectArgs &a, hipStream_t s) {
+    if (a.seg.n == 0) return hipSuccess;
+    const unsigned grid = (unsigned)((a.seg.n + 255) / 256);
+    switch (a.seg.sh_degree) {
+        case 0: hipLaunchKernelGGL(backward_project_kernel<0>, dim3(grid), dim3(256), 0, s, a); break;
+        case 1: hipLaunchKernelGGL(backward_project_kernel<1>, dim3(grid), dim3(256), 0, s, a); break;
+        case 2: hipLaunchKernelGGL(backward_project_kernel<2>, dim3(grid), dim3(256), 0, s, a); break;
+        default: hipLaunchKernelGGL(backward_project_kernel<3>, dim3(grid), dim3(256), 0, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace gs

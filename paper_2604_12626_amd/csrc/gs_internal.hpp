@@ -1,0 +1,331 @@
+// Internal definitions shared by the gfx950 kernels of libgs (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gs.h"
+
+namespace gs {
+
+constexpr int kTile = GS_TILE;
+constexpr int kTilePixels = kTile * kTile;     // 256 pixels = 4 wave64 per tile
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kCoordClamp = 1048576.0f;       // |u|, |v| clamped to 2^20 before floor
+constexpr float kRadiusCap = 16777216.0f;       // 2^24: covers every tile of any image
+constexpr int kProjViews = 64;                  // views handled by one projection launch
+
+// screen-space gradient slots accumulated per instance by the backward pass
+enum { kGU = 0, kGV, kGA, kGB, kGC, kGO, kGR, kGG, kGBl, kGZ, kG2D };
+
+// ---------------------------------------------------------------------------
+// launch argument blocks (passed by value as kernel arguments)
+// ---------------------------------------------------------------------------
+struct ProjectArgs {
+    gs_gaussians seg;
+    const gs_camera *cams;
+    uint32_t *tiles_touched;
+    float4 *rec;
+    int64_t base[kProjViews];  // first instance of this segment in each view
+    int32_t view[kProjViews];  // view index
+    int32_t nv;
+    int32_t W, H, TX, TY;
+    float near_plane, lowpass, sigma_cut, fov_clamp;
+};
+
+struct BackwardProjectArgs {
+    gs_gaussians seg;
+    gs_gaussians_grad grad;
+    const gs_camera *cams;
+    const uint32_t *tiles_touched;
+    const float *g2d;  // [instances][kG2D]
+    int64_t base[kProjViews];
+    int32_t view[kProjViews];
+    int32_t nv;
+    int32_t first;     // 1: overwrite the gradients, 0: accumulate (later chunk of views)
+    int32_t W, H;
+    float near_plane, lowpass, sigma_cut, fov_clamp;
+};
+
+struct CompositeArgs {
+    const float4 *rec;
+    const uint32_t *vals;
+    const uint2 *ranges;
+    uint32_t *counter;
+    int64_t n_items;  // n_views * T
+    int32_t W, H, TX, T;
+    float alpha_max, alpha_min, t_min;
+    float bg0, bg1, bg2;
+    float *rgb, *depth, *alpha, *t_final;
+    uint32_t *n_contrib;
+};
+
+struct BackwardTileArgs {
+    const float4 *rec;
+    const uint32_t *vals;
+    const uint2 *ranges;
+    const float *t_final;
+    const uint32_t *n_contrib;
+    const float *d_rgb, *d_depth, *d_alpha;
+    float *g2d;  // [instances][kG2D]
+    int64_t n_items;
+    int32_t W, H, TX, T;
+    float alpha_max, alpha_min;
+    float bg0, bg1, bg2;
+};
+
+struct LbsArgs {
+    int64_t n;
+    const float *means, *log_scales, *quats;
+    const uint8_t *joint_idx;
+    const float *weights;
+    const int32_t *avatar_of;
+    const float *skin;
+    int32_t n_avatars, n_joints;
+    float *means_out, *cov6_out;
+    // backward
+    const float *d_means_out, *d_cov6_out;
+    float *d_means, *d_log_scales, *d_quats;
+};
+
+struct SortPlan {
+    int64_t n, capacity, n_tiles_total;
+    int tile_bits, passes;
+    int64_t scan_blocks, sort_parts;
+    // workspace layout (byte offsets)
+    size_t off_offsets, off_part, off_keys2, off_vals2, off_hist, off_status, off_ticket, total;
+};
+
+// launchers (one per translation unit)
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+hipError_t launch_project(const ProjectArgs &a, hipStream_t s);
+SortPlan make_sort_plan(int64_t n, int64_t capacity, int64_t n_tiles_total);
+hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec, int TX, int TY, char *ws,
+                        uint64_t *keys, uint32_t *vals, uint32_t *ranges, int64_t *d_num, int32_t *d_overflow,
+                        hipStream_t s);
+hipError_t launch_composite(const CompositeArgs &a, int grid, hipStream_t s);
+hipError_t launch_backward_tiles(const BackwardTileArgs &a, hipStream_t s);
+hipError_t launch_backward_project(const BackwardProjectArgs &a, hipStream_t s);
+hipError_t launch_lbs(const LbsArgs &a, bool backward, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// small device helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int floor_div_tile(int a) { return a >> 4; }  // floor(a / 16), arithmetic shift
+
+struct Rect {
+    int x0, x1, y0, y1;
+};
+
+// Tiles whose pixel extent [16 t, 16 t + 16) meets the closed square
+// [u - r, u + r] x [v - r, v + r]; exact for an integer r given floor(u), floor(v).
+__device__ __forceinline__ Rect tile_rect(float u, float v, int r, int TX, int TY) {
+    const int ix = (int)floorf(fminf(fmaxf(u, -kCoordClamp), kCoordClamp));
+    const int iy = (int)floorf(fminf(fmaxf(v, -kCoordClamp), kCoordClamp));
+    Rect R;
+    R.x0 = max(0, floor_div_tile(ix - r));
+    R.x1 = min(TX, floor_div_tile(ix + r) + 1);
+    R.y0 = max(0, floor_div_tile(iy - r));
+    R.y1 = min(TY, floor_div_tile(iy + r) + 1);
+    return R;
+}
+
+// Real spherical harmonics up to l = 3 with the Condon-Shortley phase, l-major,
+// m = -l..l, evaluated at a unit direction (x, y, z) as polynomials.
+// Constants: sqrt((2l+1)/(4 pi) (l-|m|)!/(l+|m|)!) times the polynomial
+// normalisation, e.g. Y_1,-1 = -sqrt(3/(4 pi)) y.
+struct SH {
+    static constexpr float C0 = 0.28209479177387814f;   // 1/(2 sqrt(pi))
+    static constexpr float C1 = 0.48860251190291992f;   // sqrt(3/(4 pi))
+    static constexpr float C2a = 1.0925484305920792f;   // sqrt(15/(4 pi))
+    static constexpr float C2b = 0.31539156525252005f;  // sqrt(5/(16 pi))
+    static constexpr float C2c = 0.54627421529603959f;  // sqrt(15/(16 pi))
+    static constexpr float C3a = 0.59004358992664352f;  // sqrt(35/(32 pi))
+    static constexpr float C3b = 2.8906114426405538f;   // sqrt(105/(4 pi))
+    static constexpr float C3c = 0.45704579946446572f;  // sqrt(21/(32 pi))
+    static constexpr float C3d = 0.37317633259011540f;  // sqrt(7/(16 pi))
+    static constexpr float C3e = 1.4453057213202769f;   // sqrt(105/(16 pi))
+};
+
+template <int D>
+__device__ __forceinline__ void sh_basis(float x, float y, float z, float *Y) {
+    Y[0] = SH::C0;
+    if (D >= 1) {
+        Y[1] = -SH::C1 * y;
+        Y[2] = SH::C1 * z;
+        Y[3] = -SH::C1 * x;
+    }
+    if (D >= 2) {
+        const float xx = x * x, yy = y * y, zz = z * z;
+        Y[4] = SH::C2a * x * y;
+        Y[5] = -SH::C2a * y * z;
+        Y[6] = SH::C2b * (2.0f * zz - xx - yy);
+        Y[7] = -SH::C2a * x * z;
+        Y[8] = SH::C2c * (xx - yy);
+        if (D >= 3) {
+            Y[9] = -SH::C3a * y * (3.0f * xx - yy);
+            Y[10] = SH::C3b * x * y * z;
+            Y[11] = -SH::C3c * y * (4.0f * zz - xx - yy);
+            Y[12] = SH::C3d * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+            Y[13] = -SH::C3c * x * (4.0f * zz - xx - yy);
+            Y[14] = SH::C3e * z * (xx - yy);
+            Y[15] = -SH::C3a * x * (xx - 3.0f * yy);
+        }
+    }
+}
+
+// Gradient of the polynomials of sh_basis w.r.t. (x, y, z): dY[k] = (dx, dy, dz).
+template <int D>
+__device__ __forceinline__ void sh_basis_grad(float x, float y, float z, float3 *dY) {
+    dY[0] = make_float3(0.f, 0.f, 0.f);
+    if (D >= 1) {
+        dY[1] = make_float3(0.f, -SH::C1, 0.f);
+        dY[2] = make_float3(0.f, 0.f, SH::C1);
+        dY[3] = make_float3(-SH::C1, 0.f, 0.f);
+    }
+    if (D >= 2) {
+        const float xx = x * x, yy = y * y, zz = z * z;
+        dY[4] = make_float3(SH::C2a * y, SH::C2a * x, 0.f);
+        dY[5] = make_float3(0.f, -SH::C2a * z, -SH::C2a * y);
+        dY[6] = make_float3(-2.f * SH::C2b * x, -2.f * SH::C2b * y, 4.f * SH::C2b * z);
+        dY[7] = make_float3(-SH::C2a * z, 0.f, -SH::C2a * x);
+        dY[8] = make_float3(2.f * SH::C2c * x, -2.f * SH::C2c * y, 0.f);
+        if (D >= 3) {
+            dY[9] = make_float3(-SH::C3a * 6.f * x * y, -SH::C3a * (3.f * xx - 3.f * yy), 0.f);
+            dY[10] = make_float3(SH::C3b * y * z, SH::C3b * x * z, SH::C3b * x * y);
+            dY[11] = make_float3(SH::C3c * 2.f * x * y, -SH::C3c * (4.f * zz - xx - 3.f * yy), -SH::C3c * 8.f * y * z);
+            dY[12] = make_float3(-SH::C3d * 6.f * x * z, -SH::C3d * 6.f * y * z, SH::C3d * (6.f * zz - 3.f * xx - 3.f * yy));
+            dY[13] = make_float3(-SH::C3c * (4.f * zz - 3.f * xx - yy), SH::C3c * 2.f * x * y, -SH::C3c * 8.f * x * z);
+            dY[14] = make_float3(SH::C3e * 2.f * x * z, -SH::C3e * 2.f * y * z, SH::C3e * (xx - yy));
+            dY[15] = make_float3(-SH::C3a * (3.f * xx - 3.f * yy), SH::C3a * 6.f * x * y, 0.f);
+        }
+    }
+}
+
+// Unit quaternion (w, x, y, z) -> rotation matrix (row-major).  A quaternion
+// with |q|^2 < 1e-24 stands for the identity.
+struct Rot {
+    float R[9];
+    float q[4];   // normalised
+    float inv_n;  // 1/|q|, 0 for the identity fallback
+};
+
+__device__ __forceinline__ Rot quat_rot(float w, float x, float y, float z) {
+    Rot o;
+    const float n2 = w * w + x * x + y * y + z * z;
+    if (!(n2 >= 1e-24f)) {
+        w = 1.f;
+        x = y = z = 0.f;
+        o.inv_n = 0.f;
+    } else {
+        const float inv = 1.0f / sqrtf(n2);
+        w *= inv;
+        x *= inv;
+        y *= inv;
+        z *= inv;
+        o.inv_n = inv;
+    }
+    o.q[0] = w;
+    o.q[1] = x;
+    o.q[2] = y;
+    o.q[3] = z;
+    o.R[0] = 1.f - 2.f * (y * y + z * z);
+    o.R[1] = 2.f * (x * y - w * z);
+    o.R[2] = 2.f * (x * z + w * y);
+    o.R[3] = 2.f * (x * y + w * z);
+    o.R[4] = 1.f - 2.f * (x * x + z * z);
+    o.R[5] = 2.f * (y * z - w * x);
+    o.R[6] = 2.f * (x * z - w * y);
+    o.R[7] = 2.f * (y * z + w * x);
+    o.R[8] = 1.f - 2.f * (x * x + y * y);
+    return o;
+}
+
+// Sigma = R diag(s^2) R^T as (xx, xy, xz, yy, yz, zz)
+__device__ __forceinline__ void cov_from_rot_scale(const float *R, const float *s, float *c6) {
+    float M[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) M[3 * i + j] = R[3 * i + j] * s[j];
+    c6[0] = M[0] * M[0] + M[1] * M[1] + M[2] * M[2];
+    c6[1] = M[0] * M[3] + M[1] * M[4] + M[2] * M[5];
+    c6[2] = M[0] * M[6] + M[1] * M[7] + M[2] * M[8];
+    c6[3] = M[3] * M[3] + M[4] * M[4] + M[5] * M[5];
+    c6[4] = M[3] * M[6] + M[4] * M[7] + M[5] * M[8];
+    c6[5] = M[6] * M[6] + M[7] * M[7] + M[8] * M[8];
+}
+
+// Adjoint of Sigma = (R S)(R S)^T w.r.t. log-scales and the raw quaternion,
+// given the symmetric adjoint dS (full 3x3, row-major).
+__device__ __forceinline__ void cov_backward(const Rot &rot, const float *s, const float *dS, float *dlog_s,
+                                             float *dq) {
+    float M[9], dM[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) M[3 * i + j] = rot.R[3 * i + j] * s[j];
+    // dM = (dS + dS^T) M
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            float acc = 0.f;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) acc += (dS[3 * i + k] + dS[3 * k + i]) * M[3 * k + j];
+            dM[3 * i + j] = acc;
+        }
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        dlog_s[k] = s[k] * (rot.R[k] * dM[k] + rot.R[3 + k] * dM[3 + k] + rot.R[6 + k] * dM[6 + k]);
+    if (rot.inv_n == 0.f) {
+        dq[0] = dq[1] = dq[2] = dq[3] = 0.f;
+        return;
+    }
+    float dR[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) dR[3 * i + j] = dM[3 * i + j] * s[j];
+    const float w = rot.q[0], x = rot.q[1], y = rot.q[2], z = rot.q[3];
+    float g[4];
+    g[0] = 2.f * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+    g[1] = 2.f * (y * dR[1] + z * dR[2] + y * dR[3] - 2.f * x * dR[4] - w * dR[5] + z * dR[6] + w * dR[7] -
+                  2.f * x * dR[8]);
+    g[2] = 2.f * (-2.f * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] + z * dR[7] -
+                  2.f * y * dR[8]);
+    g[3] = 2.f * (-2.f * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.f * z * dR[4] + y * dR[5] + x * dR[6] +
+                  y * dR[7]);
+    const float qd = w * g[0] + x * g[1] + y * g[2] + z * g[3];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) dq[c] = (g[c] - rot.q[c] * qd) * rot.inv_n;
+}
+
+// Compositing entry as staged in LDS: exponent coefficients pre-scaled by
+// log2(e) so that G = exp2(a dx^2 + c dy^2 + b dx dy).
+struct Entry {
+    float u, v, a, b, c, o, z, r, g, bl;
+};
+
+__device__ __forceinline__ Entry make_entry(const float4 q0, const float4 q1, const float4 q2) {
+    Entry e;
+    e.u = q0.x;
+    e.v = q0.y;
+    e.z = q0.z;
+    e.a = -0.5f * kLog2e * q1.x;
+    e.b = -kLog2e * q1.y;
+    e.c = -0.5f * kLog2e * q1.z;
+    e.o = q1.w;
+    e.r = q2.x;
+    e.g = q2.y;
+    e.bl = q2.z;
+    return e;
+}
+
+// exponent (base 2) at pixel offset (dx, dy); clamped to <= 0
+__device__ __forceinline__ float entry_power2(float a, float b, float c, float dx, float dy) {
+    const float p = a * dx * dx + c * dy * dy + b * dx * dy;
+    return fminf(p, 0.0f);
+}
+
+}  // namespace gs

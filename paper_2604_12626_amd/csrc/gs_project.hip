@@ -1,0 +1,111 @@
+// gs_project kernel: per (view, Gaussian) EWA projection, SH colour and tile
+// rect.  One thread per Gaussian of a segment; the thread reads the
+// Gaussian's attributes once and projects it into every view of the launch
+// (the cameras are staged in LDS), so a scene drawn by many views is read from
+// HBM once.  Attribute reads are row-per-Gaussian (means 12 B, scales 12 B,
+// quats 16 B, SH 12 (D+1)^2 B contiguous), so a Gaussian culled in every view
+// never pulls its SH rows.
+#include "gs_ewa.hpp"
+
+namespace gs {
+
+template <int D>
+__global__ void __launch_bounds__(256) project_kernel(const ProjectArgs a) {
+    constexpr int K = (D + 1) * (D + 1);
+    __shared__ float s_cam[kProjViews * kCamStride];
+    for (int k = threadIdx.x; k < a.nv * 16; k += blockDim.x) {
+        const int vi = k >> 4, f = k & 15;
+        s_cam[vi * kCamStride + f] = reinterpret_cast<const float *>(a.cams + a.view[vi])[f];
+    }
+    __syncthreads();
+    for (int vi = threadIdx.x; vi < a.nv; vi += blockDim.x) {
+        float *c = s_cam + vi * kCamStride;
+        // camera centre -R^T t
+#pragma unroll
+        for (int j = 0; j < 3; ++j) c[16 + j] = -(c[j] * c[9] + c[3 + j] * c[10] + c[6 + j] * c[11]);
+    }
+    __syncthreads();
+
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.seg.n) return;
+
+    const float mx = a.seg.means[3 * i + 0], my = a.seg.means[3 * i + 1], mz = a.seg.means[3 * i + 2];
+    float S[6];
+    if (a.seg.cov6) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) S[k] = a.seg.cov6[6 * i + k];
+    } else {
+        const float4 q = reinterpret_cast<const float4 *>(a.seg.quats)[i];
+        const Rot rot = quat_rot(q.x, q.y, q.z, q.w);
+        float s[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) s[k] = expf(a.seg.log_scales[3 * i + k]);
+        cov_from_rot_scale(rot.R, s, S);
+    }
+    const float opac = a.seg.opacity[i];
+
+    float sh[3 * K];
+    bool have_sh = false;
+    for (int vi = 0; vi < a.nv; ++vi) {
+        const int64_t inst = a.base[vi] + i;
+        const float *cam = s_cam + vi * kCamStride;
+        ViewProj p;
+        if (!ewa_project(cam, mx, my, mz, S, a.W, a.H, a.TX, a.TY, a.near_plane, a.lowpass, a.sigma_cut,
+                         a.fov_clamp, p)) {
+            a.tiles_touched[inst] = 0u;
+            continue;
+        }
+        if (!have_sh) {
+            const float *src = a.seg.sh + (size_t)(3 * K) * i;
+            if ((3 * K) % 4 == 0) {
+#pragma unroll
+                for (int k = 0; k < 3 * K / 4; ++k) {
+                    const float4 t = reinterpret_cast<const float4 *>(src)[k];
+                    sh[4 * k + 0] = t.x;
+                    sh[4 * k + 1] = t.y;
+                    sh[4 * k + 2] = t.z;
+                    sh[4 * k + 3] = t.w;
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < 3 * K; ++k) sh[k] = src[k];
+            }
+            have_sh = true;
+        }
+        // view direction in world space, from the camera centre to the mean
+        float dx = mx - cam[16], dy = my - cam[17], dz = mz - cam[18];
+        const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+        dx *= inv;
+        dy *= inv;
+        dz *= inv;
+        float Y[K];
+        sh_basis<D>(dx, dy, dz, Y);
+        float col[3];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            float acc = 0.0f;
+#pragma unroll
+            for (int k = 0; k < K; ++k) acc += Y[k] * sh[3 * k + ch];
+            col[ch] = fmaxf(acc + 0.5f, 0.0f);
+        }
+        float4 *r = a.rec + 3 * inst;
+        r[0] = make_float4(p.u, p.v, p.tz, __int_as_float(p.radius));
+        r[1] = make_float4(p.A, p.B, p.C, opac);
+        r[2] = make_float4(col[0], col[1], col[2], __int_as_float(a.view[vi]));
+        a.tiles_touched[inst] = (uint32_t)((p.rect.x1 - p.rect.x0) * (p.rect.y1 - p.rect.y0));
+    }
+}
+
+hipError_t launch_project(const ProjectArgs &a, hipStream_t s) {
+    if (a.seg.n == 0 || a.nv == 0) return hipSuccess;
+    const unsigned grid = (unsigned)((a.seg.n + 255) / 256);
+    switch (a.seg.sh_degree) {
+        case 0: hipLaunchKernelGGL(project_kernel<0>, dim3(grid), dim3(256), 0, s, a); break;
+        case 1: hipLaunchKernelGGL(project_kernel<1>, dim3(grid), dim3(256), 0, s, a); break;
+        case 2: hipLaunchKernelGGL(project_kernel<2>, dim3(grid), dim3(256), 0, s, a); break;
+        default: hipLaunchKernelGGL(project_kernel<3>, dim3(grid), dim3(256), 0, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace gs

@@ -1,0 +1,452 @@
+// gs_bin_sort kernels: scan of tiles_touched, (tile, depth) key emission,
+// onesweep LSD radix sort (8-bit digits, decoupled look-back across
+// partitions) and per-tile ranges.
+//
+// Onesweep on CDNA4: a partition of 4096 keys per 256-thread workgroup (four
+// wave64, 16 keys per lane).  Ranks inside a wave come from eight ballots per
+// key (the lanes holding the same digit), so ranking is stable: stripes are
+// processed in index order and lanes inside a stripe are in index order.
+// Partitions are numbered by an atomic ticket in launch order, so a
+// workgroup only ever waits for partitions that already run (forward
+// progress).  Each partition publishes per-digit counts in one 32-bit word
+// (2 flag bits + 30 count bits) with agent-scope atomics, because the eight
+// XCDs have private L2s; a waiting lane sleeps between polls.  The scatter is
+// staged through LDS so that each digit's run is written contiguously.
+#include "gs_internal.hpp"
+
+namespace gs {
+
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanBlock * kScanItems;  // 4096 instances per block
+
+constexpr int kSortBlock = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortPart = kSortBlock * kSortItems;  // 4096 keys per partition
+constexpr int kRadixBits = 8;
+constexpr int kBins = 1 << kRadixBits;
+constexpr int kMaxPasses = 8;
+constexpr uint32_t kFlagAgg = 1u << 30;
+constexpr uint32_t kFlagIncl = 2u << 30;
+constexpr uint32_t kCountMask = (1u << 30) - 1u;
+
+// ---------------------------------------------------------------------------
+// fill (used instead of memset nodes so a captured graph replays correctly)
+// ---------------------------------------------------------------------------
+__global__ void fill_u32_kernel(uint32_t *p, uint32_t v, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// scan of tiles_touched (reduce, scan of block sums, downsweep)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t block_reduce_u64(uint64_t v, uint64_t *s_tmp) {
+    // wave reduction then across the four waves
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (l == 0) s_tmp[w] = v;
+    __syncthreads();
+    uint64_t t = 0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += s_tmp[k];
+    return t;  // valid in thread 0
+}
+
+__global__ void __launch_bounds__(kScanBlock) scan_reduce_kernel(const uint32_t *tt, int64_t n, uint64_t *part) {
+    __shared__ uint64_t s_tmp[4];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    uint64_t acc = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = base + k * kScanBlock + threadIdx.x;
+        if (i < n) acc += tt[i];
+    }
+    const uint64_t t = block_reduce_u64(acc, s_tmp);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// one workgroup of 1024 threads: exclusive scan of the block sums in place;
+// writes K and the overflow flag
+__global__ void __launch_bounds__(1024) scan_partials_kernel(uint64_t *part, int64_t nparts, int64_t capacity,
+                                                             int64_t *d_num, int32_t *d_overflow) {
+    __shared__ uint64_t s[1024];
+    uint64_t carry = 0;
+    for (int64_t base = 0; base < nparts; base += 1024) {
+        const int64_t i = base + threadIdx.x;
+        const uint64_t v = (i < nparts) ? part[i] : 0;
+        s[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            const uint64_t t = (threadIdx.x >= (unsigned)off) ? s[threadIdx.x - off] : 0;
+            __syncthreads();
+            s[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (i < nparts) part[i] = carry + s[threadIdx.x] - v;
+        carry += s[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        *d_num = (int64_t)carry;
+        *d_overflow = ((int64_t)carry > capacity) ? 1 : 0;
+    }
+}
+
+// block-local exclusive scan (blocked arrangement: thread t owns items
+// [t*16, t*16+16) of the block's 4096) plus the block's global prefix;
+// offsets saturate at 2^32-1 (emission stops at the capacity anyway)
+__global__ void __launch_bounds__(kScanBlock) scan_down_kernel(const uint32_t *tt, int64_t n, const uint64_t *part,
+                                                               uint32_t *offsets) {
+    __shared__ uint64_t s[kScanBlock];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint64_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = base + k;
+        v[k] = (i < n) ? tt[i] : 0u;
+        sum += v[k];
+    }
+    s[threadIdx.x] = sum;
+    __syncthreads();
+    for (int off = 1; off < kScanBlock; off <<= 1) {
+        const uint64_t t = (threadIdx.x >= (unsigned)off) ? s[threadIdx.x - off] : 0;
+        __syncthreads();
+        s[threadIdx.x] += t;
+        __syncthreads();
+    }
+    uint64_t run = part[blockIdx.x] + s[threadIdx.x] - sum;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = base + k;
+        if (i < n) offsets[i] = run > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)run;
+        run += v[k];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// key emission
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) emit_kernel(const uint32_t *tt, const uint32_t *offsets, const float4 *rec,
+                                                   int64_t n, int TX, int TY, int64_t capacity, uint64_t *keys,
+                                                   uint32_t *vals) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    if (tt[g] == 0u) return;
+    int64_t k = offsets[g];
+    if (k >= capacity) return;
+    const float4 q0 = rec[3 * g];
+    const int view = __float_as_int(rec[3 * g + 2].w);
+    const Rect R = tile_rect(q0.x, q0.y, __float_as_int(q0.w), TX, TY);
+    const uint64_t depth_bits = (uint64_t)__float_as_uint(q0.z);
+    const uint64_t tbase = (uint64_t)view * (uint64_t)(TX * TY);
+    for (int ty = R.y0; ty < R.y1; ++ty)
+        for (int tx = R.x0; tx < R.x1; ++tx) {
+            if (k >= capacity) return;
+            keys[k] = ((tbase + (uint64_t)(ty * TX + tx)) << 32) | depth_bits;
+            vals[k] = (uint32_t)g;
+            ++k;
+        }
+}
+
+// ---------------------------------------------------------------------------
+// onesweep radix sort
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t sort_count(const int64_t *d_num, int64_t capacity) {
+    const int64_t k = *d_num;
+    return k < capacity ? k : capacity;
+}
+
+// global digit histograms of all passes in one read of the keys
+__global__ void __launch_bounds__(256) sort_hist_kernel(const uint64_t *keys, const int64_t *d_num, int64_t capacity,
+                                                        int passes, int bit0, uint32_t *hist /*[passes][256]*/) {
+    __shared__ uint32_t s_h[kMaxPasses * kBins];
+    for (int k = threadIdx.x; k < passes * kBins; k += blockDim.x) s_h[k] = 0u;
+    __syncthreads();
+    const int64_t K = sort_count(d_num, capacity);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t key = keys[i];
+        for (int p = 0; p < passes; ++p) atomicAdd(&s_h[p * kBins + ((key >> (bit0 + p * kRadixBits)) & (kBins - 1))], 1u);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < passes * kBins; k += blockDim.x)
+        if (s_h[k]) atomicAdd(&hist[k], s_h[k]);
+}
+
+// exclusive scan of each pass's histogram (one workgroup of 256 threads)
+__global__ void __launch_bounds__(kBins) sort_hist_scan_kernel(uint32_t *hist, int passes) {
+    __shared__ uint32_t s[kBins];
+    for (int p = 0; p < passes; ++p) {
+        const uint32_t v = hist[p * kBins + threadIdx.x];
+        s[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < kBins; off <<= 1) {
+            const uint32_t t = (threadIdx.x >= (unsigned)off) ? s[threadIdx.x - off] : 0u;
+            __syncthreads();
+            s[threadIdx.x] += t;
+            __syncthreads();
+        }
+        hist[p * kBins + threadIdx.x] = s[threadIdx.x] - v;
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ uint32_t lds_exclusive_scan_256(uint32_t v, uint32_t *s) {
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < kBins; off <<= 1) {
+        const uint32_t t = (threadIdx.x >= (unsigned)off) ? s[threadIdx.x - off] : 0u;
+        __syncthreads();
+        s[threadIdx.x] += t;
+        __syncthreads();
+    }
+    return s[threadIdx.x] - v;
+}
+
+__global__ void __launch_bounds__(kSortBlock) onesweep_kernel(const uint64_t *__restrict__ keys_in,
+                                                              const uint32_t *__restrict__ vals_in,
+                                                              uint64_t *__restrict__ keys_out,
+                                                              uint32_t *__restrict__ vals_out, const int64_t *d_num,
+                                                              int64_t capacity, int shift,
+                                                              const uint32_t *digit_base /*[256]*/,
+                                                              uint32_t *status /*[parts][256]*/, uint32_t *ticket) {
+    __shared__ uint32_t s_part;
+    __shared__ uint32_t s_wh[4][kBins];      // per-wave digit counts -> prefix across waves
+    __shared__ uint32_t s_local[kBins];      // block-local exclusive digit start
+    __shared__ uint32_t s_glob[kBins];       // global start of the digit for this partition
+    __shared__ uint32_t s_scan[kBins];
+    __shared__ uint64_t s_keys[kSortPart];
+    __shared__ uint32_t s_vals[kSortPart];
+
+    const int64_t K = sort_count(d_num, capacity);
+    if (threadIdx.x == 0) s_part = atomicAdd(ticket, 1u);
+    for (int k = threadIdx.x; k < 4 * kBins; k += kSortBlock) (&s_wh[0][0])[k] = 0u;
+    __syncthreads();
+    const uint32_t part = s_part;
+    const int64_t start = (int64_t)part * kSortPart;
+    if (start >= K) return;  // uniform across the workgroup
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint64_t key[kSortItems];
+    uint32_t val[kSortItems];
+    uint32_t rank[kSortItems];
+    uint32_t dig[kSortItems];
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+        const int64_t idx = start + (int64_t)wave * (kSortItems * 64) + j * 64 + lane;
+        const bool valid = idx < K;
+        key[j] = valid ? keys_in[idx] : ~0ull;
+        val[j] = valid ? vals_in[idx] : 0u;
+        const uint32_t d = (uint32_t)(key[j] >> shift) & (kBins - 1);
+        dig[j] = valid ? d : 0xFFFFFFFFu;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < kRadixBits; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        uint32_t r = 0;
+        if (valid) {
+            const uint32_t below = __popcll(peers & lt_mask);
+            const uint32_t prev = s_wh[wave][d];
+            r = prev + below;
+            __builtin_amdgcn_wave_barrier();
+            if (below == 0) s_wh[wave][d] = prev + (uint32_t)__popcll(peers);
+        } else {
+            __builtin_amdgcn_wave_barrier();
+        }
+        __builtin_amdgcn_wave_barrier();
+        rank[j] = r;
+    }
+    __syncthreads();
+    // per digit (thread = digit): prefix across waves and block total
+    const uint32_t d = threadIdx.x;
+    const uint32_t c0 = s_wh[0][d], c1 = s_wh[1][d], c2 = s_wh[2][d], c3 = s_wh[3][d];
+    const uint32_t total = c0 + c1 + c2 + c3;
+    s_wh[0][d] = 0u;
+    s_wh[1][d] = c0;
+    s_wh[2][d] = c0 + c1;
+    s_wh[3][d] = c0 + c1 + c2;
+    // decoupled look-back for this digit
+    uint32_t *st = status + (size_t)part * kBins + d;
+    uint32_t prefix = 0u;
+    if (part == 0) {
+        __hip_atomic_store(st, kFlagIncl | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+        __hip_atomic_store(st, kFlagAgg | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int64_t p = (int64_t)part - 1;
+        while (true) {
+            const uint32_t w = __hip_atomic_load(status + (size_t)p * kBins + d, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t flag = w & ~kCountMask;
+            if (flag == 0u) {
+                __builtin_amdgcn_s_sleep(1);
+                continue;
+            }
+            prefix += w & kCountMask;
+            if (flag == kFlagIncl) break;
+            --p;
+        }
+        __hip_atomic_store(st, kFlagIncl | (prefix + total), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    s_glob[d] = digit_base[d] + prefix;
+    const uint32_t local = lds_exclusive_scan_256(total, s_scan);
+    s_local[d] = local;
+    __syncthreads();
+    // stage into LDS in block-local sorted order
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+        if (dig[j] != 0xFFFFFFFFu) {
+            const uint32_t pos = s_local[dig[j]] + s_wh[wave][dig[j]] + rank[j];
+            s_keys[pos] = key[j];
+            s_vals[pos] = val[j];
+        }
+    }
+    __syncthreads();
+    const int64_t nvalid64 = K - start;
+    const int nvalid = nvalid64 < kSortPart ? (int)nvalid64 : kSortPart;
+    for (int q = threadIdx.x; q < nvalid; q += kSortBlock) {
+        const uint64_t kk = s_keys[q];
+        const uint32_t dd = (uint32_t)(kk >> shift) & (kBins - 1);
+        const uint32_t dst = s_glob[dd] + (uint32_t)q - s_local[dd];
+        keys_out[dst] = kk;
+        vals_out[dst] = s_vals[q];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// tile ranges
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) ranges_kernel(const uint64_t *keys, const int64_t *d_num, int64_t capacity,
+                                                     const int32_t *d_overflow, uint32_t *ranges,
+                                                     uint64_t n_tiles_total) {
+    if (*d_overflow) return;
+    const int64_t K = sort_count(d_num, capacity);
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    const uint64_t t = keys[k] >> 32;
+    if (t >= n_tiles_total) return;
+    if (k == 0 || (keys[k - 1] >> 32) != t) ranges[2 * t] = (uint32_t)k;
+    if (k == K - 1 || (keys[k + 1] >> 32) != t) ranges[2 * t + 1] = (uint32_t)(k + 1);
+}
+
+// ---------------------------------------------------------------------------
+// host side of the pipeline
+// ---------------------------------------------------------------------------
+
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+SortPlan make_sort_plan(int64_t n, int64_t capacity, int64_t n_tiles_total) {
+    SortPlan p;
+    p.n = n;
+    p.capacity = capacity;
+    p.n_tiles_total = n_tiles_total;
+    int tb = 1;
+    while ((1ll << tb) < n_tiles_total) ++tb;
+    p.tile_bits = tb;
+    p.passes = (32 + tb + kRadixBits - 1) / kRadixBits;
+    p.scan_blocks = (n + kScanTile - 1) / kScanTile;
+    if (p.scan_blocks < 1) p.scan_blocks = 1;
+    p.sort_parts = (capacity + kSortPart - 1) / kSortPart;
+    if (p.sort_parts < 1) p.sort_parts = 1;
+    size_t o = 0;
+    p.off_offsets = o;
+    o = align256(o + sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
+    p.off_part = o;
+    o = align256(o + sizeof(uint64_t) * (size_t)p.scan_blocks);
+    p.off_keys2 = o;
+    o = align256(o + sizeof(uint64_t) * (size_t)(capacity > 0 ? capacity : 1));
+    p.off_vals2 = o;
+    o = align256(o + sizeof(uint32_t) * (size_t)(capacity > 0 ? capacity : 1));
+    // hist, status and tickets are contiguous so one fill clears them
+    p.off_hist = o;
+    o = o + sizeof(uint32_t) * (size_t)kMaxPasses * kBins;
+    p.off_ticket = o;
+    o = o + sizeof(uint32_t) * (size_t)kMaxPasses * 64;
+    p.off_status = o;
+    o = o + sizeof(uint32_t) * (size_t)p.passes * (size_t)p.sort_parts * kBins;
+    p.total = align256(o);
+    return p;
+}
+
+hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec, int TX, int TY, char *ws,
+                        uint64_t *keys, uint32_t *vals, uint32_t *ranges, int64_t *d_num, int32_t *d_overflow,
+                        hipStream_t s) {
+    hipError_t e;
+    uint32_t *offsets = reinterpret_cast<uint32_t *>(ws + P.off_offsets);
+    uint64_t *part = reinterpret_cast<uint64_t *>(ws + P.off_part);
+    uint64_t *keys2 = reinterpret_cast<uint64_t *>(ws + P.off_keys2);
+    uint32_t *vals2 = reinterpret_cast<uint32_t *>(ws + P.off_vals2);
+    uint32_t *hist = reinterpret_cast<uint32_t *>(ws + P.off_hist);
+    uint32_t *ticket = reinterpret_cast<uint32_t *>(ws + P.off_ticket);
+    uint32_t *status = reinterpret_cast<uint32_t *>(ws + P.off_status);
+    const size_t clear_words = (P.off_status - P.off_hist) / 4 + (size_t)P.passes * P.sort_parts * kBins;
+
+    if ((e = launch_fill_u32(hist, 0u, (int64_t)clear_words, s)) != hipSuccess) return e;
+    if ((e = launch_fill_u32(ranges, 0u, 2 * P.n_tiles_total, s)) != hipSuccess) return e;
+    // 1. scan
+    if (P.n > 0) {
+        hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)P.scan_blocks), dim3(kScanBlock), 0, s, tt, P.n, part);
+    }
+    hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(1024), 0, s, part, P.n > 0 ? P.scan_blocks : 0,
+                       P.capacity, d_num, d_overflow);
+    if (P.n > 0) {
+        hipLaunchKernelGGL(scan_down_kernel, dim3((unsigned)P.scan_blocks), dim3(kScanBlock), 0, s, tt, P.n, part,
+                           offsets);
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // 2. emit into the buffer that the last pass does not write to
+    const bool odd = (P.passes & 1) != 0;
+    uint64_t *k_a = odd ? keys2 : keys;
+    uint32_t *v_a = odd ? vals2 : vals;
+    uint64_t *k_b = odd ? keys : keys2;
+    uint32_t *v_b = odd ? vals : vals2;
+    if (P.n > 0) {
+        hipLaunchKernelGGL(emit_kernel, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, s, tt, offsets, rec, P.n,
+                           TX, TY, P.capacity, k_a, v_a);
+    }
+    // 3. onesweep passes over the significant bits
+    {
+        int64_t hb = (P.capacity + 255) / 256;
+        if (hb > 2048) hb = 2048;
+        if (hb < 1) hb = 1;
+        hipLaunchKernelGGL(sort_hist_kernel, dim3((unsigned)hb), dim3(256), 0, s, k_a, d_num, P.capacity, P.passes,
+                           0, hist);
+        hipLaunchKernelGGL(sort_hist_scan_kernel, dim3(1), dim3(kBins), 0, s, hist, P.passes);
+    }
+    for (int p = 0; p < P.passes; ++p) {
+        hipLaunchKernelGGL(onesweep_kernel, dim3((unsigned)P.sort_parts), dim3(kSortBlock), 0, s, k_a, v_a, k_b, v_b,
+                           d_num, P.capacity, p * kRadixBits, hist + p * kBins,
+                           status + (size_t)p * P.sort_parts * kBins, ticket + p * 64);
+        uint64_t *tk = k_a;
+        k_a = k_b;
+        k_b = tk;
+        uint32_t *tv = v_a;
+        v_a = v_b;
+        v_b = tv;
+    }
+    // k_a now holds the sorted keys (== keys)
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // 4. ranges
+    {
+        const int64_t blocks = (P.capacity + 255) / 256;
+        if (blocks > 0)
+            hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)blocks), dim3(256), 0, s, k_a, d_num, P.capacity,
+                               d_overflow, ranges, (uint64_t)P.n_tiles_total);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace gs

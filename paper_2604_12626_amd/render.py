@@ -1,0 +1,175 @@
+"""Renderer objects over the C ABI: workspaces, capacity management, the
+autograd function and the batched multi-view renderer.
+
+Everything here is bookkeeping around libgs.so: tensors are allocated once
+and reused, each call enqueues the five hot-path entry points on torch's
+current stream.  Key-buffer overflow (more tile instances than capacity) is
+detected on the device; `Renderer.render` checks the flag once per call
+(eager mode) and re-runs the binning with a larger capacity, while graph
+replays (`CapturedRender`) never synchronise and check the flag afterwards.
+"""
+from __future__ import annotations
+
+import math
+
+import torch
+
+from . import binding as B
+
+
+def _grow(n):
+    return max(1 << 16, 1 << int(math.ceil(math.log2(max(1, int(n * 1.25))))))
+
+
+class Frame:
+    """Device outputs and saved state of one forward call."""
+
+    def __init__(self):
+        self.rgb = self.depth = self.alpha = self.t_final = self.n_contrib = None
+        self.tiles_touched = self.rec = self.keys = self.vals = self.ranges = None
+        self.num = self.overflow = None
+
+
+class Renderer:
+    """Forward (and backward) renderer for a fixed image size.
+
+    segments: list of gaussian dicts of device tensors (means [n,3],
+    log_scales [n,3], quats [n,4], opacity [n], sh [n,K,3], sh_degree, or
+    cov6 [n,6] instead of log_scales/quats); cams: [V,16] float32 device
+    tensor; view_segs: per-view lists of segment indices."""
+
+    def __init__(self, width, height, bg=(0.0, 0.0, 0.0), capacity=1 << 20, device="cuda", **overrides):
+        B.load()
+        self.W, self.H = int(width), int(height)
+        self.params = B.make_params(self.W, self.H, bg=bg, **overrides)
+        self.TX = (self.W + B.TILE - 1) // B.TILE
+        self.TY = (self.H + B.TILE - 1) // B.TILE
+        self.T = self.TX * self.TY
+        self.device = torch.device(device)
+        self.capacity = int(capacity)
+        self._bufs = {}
+
+    # -- buffers ------------------------------------------------------------
+    def _buf(self, name, shape, dtype):
+        t = self._bufs.get(name)
+        n = 1
+        for s in shape:
+            n *= int(s)
+        if t is None or t.numel() < n or t.dtype != dtype:
+            t = torch.empty(max(n, 1), dtype=dtype, device=self.device)
+            self._bufs[name] = t
+        return t[:n].view(*shape) if len(shape) else t[:1]
+
+    def alloc_frame(self, n_inst, n_views):
+        f = Frame()
+        f.tiles_touched = self._buf("tt", (n_inst,), torch.int32)
+        f.rec = self._buf("rec", (n_inst, B.REC_FLOATS), torch.float32)
+        f.keys = self._buf("keys", (self.capacity,), torch.int64)
+        f.vals = self._buf("vals", (self.capacity,), torch.int32)
+        f.ranges = self._buf("ranges", (n_views * self.T, 2), torch.int32)
+        f.num = self._buf("num", (1,), torch.int64)
+        f.overflow = self._buf("ovf", (1,), torch.int32)
+        ws = B.bin_sort_workspace(n_inst, self.capacity, n_views, self.params)
+        f.sort_ws = self._buf("sort_ws", ((ws + 255) // 256 * 256,), torch.uint8)
+        f.comp_ws = self._buf("comp_ws", (256,), torch.uint8)
+        hw = (n_views, self.H, self.W)
+        f.rgb = self._buf("rgb", hw + (3,), torch.float32)
+        f.depth = self._buf("depth", hw, torch.float32)
+        f.alpha = self._buf("alpha", hw, torch.float32)
+        f.t_final = self._buf("t_final", hw, torch.float32)
+        f.n_contrib = self._buf("n_contrib", hw, torch.int32)
+        return f
+
+    # -- stages ---------------------------------------------------------------
+    def project(self, segs, cams, view_segs, f):
+        B.project(segs, cams, view_segs, self.params, f.tiles_touched, f.rec)
+
+    def bin_sort(self, f, n_views):
+        B.bin_sort(f.tiles_touched, f.rec, n_views, self.params, f.sort_ws, f.keys, f.vals, f.ranges, f.num,
+                   f.overflow)
+
+    def composite(self, f, n_views):
+        B.composite(f.rec, f.vals, f.ranges, n_views, self.params, f.comp_ws, f.rgb, f.depth, f.alpha, f.t_final,
+                    f.n_contrib)
+
+    def enqueue(self, segs, cams, view_segs, f):
+        """All forward stages, no host synchronisation."""
+        n_views = len(view_segs)
+        self.project(segs, cams, view_segs, f)
+        self.bin_sort(f, n_views)
+        self.composite(f, n_views)
+
+    def render(self, segs, cams, view_segs=None, sync_check=True):
+        """Eager forward.  Returns a Frame whose tensors are views of the
+        renderer's buffers (valid until the next call)."""
+        if view_segs is None:
+            view_segs = [list(range(len(segs)))] * int(cams.shape[0])
+        n_views = len(view_segs)
+        n_inst = B.instance_offsets(segs, view_segs)[-1]
+        f = self.alloc_frame(n_inst, n_views)
+        self.project(segs, cams, view_segs, f)
+        self.bin_sort(f, n_views)
+        if sync_check and int(f.overflow.item()):
+            self.capacity = min(_grow(int(f.num.item())), B.MAX_CAPACITY)
+            f = self.alloc_frame(n_inst, n_views)
+            self.project(segs, cams, view_segs, f)
+            self.bin_sort(f, n_views)
+            if int(f.overflow.item()):
+                raise RuntimeError("tile instances %d exceed the maximum capacity" % int(f.num.item()))
+        self.composite(f, n_views)
+        f.n_views = n_views
+        f.n_inst = n_inst
+        return f
+
+    def backward(self, segs, cams, view_segs, f, d_rgb, d_depth, d_alpha):
+        """Dense gradients (list of dicts per segment) for the frame f."""
+        grads = []
+        for g in segs:
+            n = int(g["means"].shape[0])
+            K = (int(g["sh_degree"]) + 1) ** 2
+            d = {"means": torch.empty(n, 3, device=self.device), "opacity": torch.empty(n, device=self.device),
+                 "sh": torch.empty(n, K, 3, device=self.device)}
+            if g.get("cov6") is not None:
+                d["cov6"] = torch.empty(n, 6, device=self.device)
+            else:
+                d["log_scales"] = torch.empty(n, 3, device=self.device)
+                d["quats"] = torch.empty(n, 4, device=self.device)
+            grads.append(d)
+        ws = self._buf("bwd_ws", ((B.render_backward_workspace(f.n_inst) + 3) // 4,), torch.float32)
+        B.render_backward(segs, cams, view_segs, self.params, f.tiles_touched, f.rec, f.vals, f.ranges, f.t_final,
+                          f.n_contrib, d_rgb, d_depth, d_alpha, ws, grads)
+        return grads
+
+
+def _c(t):
+    return None if t is None else t.contiguous()
+
+
+class _RasterizeFn(torch.autograd.Function):
+    """One gaussian set (scale/rotation parametrised), V views."""
+
+    @staticmethod
+    def forward(ctx, means, log_scales, quats, opacity, sh, cams, renderer, sh_degree):
+        seg = {"means": means.contiguous(), "log_scales": log_scales.contiguous(), "quats": quats.contiguous(),
+               "opacity": opacity.contiguous(), "sh": sh.contiguous(), "sh_degree": sh_degree}
+        view_segs = [[0]] * int(cams.shape[0])
+        f = renderer.render([seg], cams, view_segs)
+        ctx.renderer, ctx.seg, ctx.view_segs, ctx.frame = renderer, seg, view_segs, f
+        ctx.save_for_backward(cams)
+        return f.rgb.clone(), f.depth.clone(), f.alpha.clone()
+
+    @staticmethod
+    def backward(ctx, d_rgb, d_depth, d_alpha):
+        (cams,) = ctx.saved_tensors
+        g = ctx.renderer.backward([ctx.seg], cams, ctx.view_segs, ctx.frame, _c(d_rgb), _c(d_depth), _c(d_alpha))[0]
+        return g["means"], g["log_scales"], g["quats"], g["opacity"], g["sh"], None, None, None
+
+
+def rasterize(means, log_scales, quats, opacity, sh, cams, renderer, sh_degree=None):
+    """Differentiable render of one gaussian set into V views: (rgb [V,H,W,3],
+    depth [V,H,W], alpha [V,H,W]).  Gradients flow to means, log_scales,
+    quats, opacity (activated) and sh.  The renderer's saved frame is reused
+    by the backward, so call backward before the next render on it."""
+    if sh_degree is None:
+        sh_degree = int(round(math.sqrt(sh.shape[1]))) - 1
+    return _RasterizeFn.apply(means, log_scales, quats, opacity, sh, cams, renderer, sh_degree)

@@ -1,0 +1,46 @@
+"""Helpers shared by the GPU parity tests: moving seeded inputs to the device
+and comparing device results with the oracle's (its candidate enumeration
+for near-threshold compositing decisions and its flags for ambiguous rects
+and depth ties)."""
+import numpy as np
+
+TOL_RGB = 1e-4      # max-abs per channel (FP32 path vs FP64 oracle)
+TOL_ALPHA = 1e-4
+TOL_DEPTH_REL = 1e-4  # depth in metres: 1e-4 * max(1, |D|)
+
+
+def to_dev(g, dev):
+    import torch
+    out = {}
+    for k, v in g.items():
+        if isinstance(v, np.ndarray):
+            out[k] = torch.from_numpy(np.ascontiguousarray(v)).to(dev)
+        else:
+            out[k] = v
+    return out
+
+
+def pixel_match(gpu_img, cands, ncand):
+    """gpu_img [..., 5] (r, g, b, depth, alpha) vs candidate table [..., MAXC, 10].
+    Returns (match mask, index of the matching candidate or -1)."""
+    n = np.abs(ncand)
+    C = cands[..., :5]
+    d = np.abs(C - gpu_img[..., None, :])
+    tol = np.empty_like(d)
+    tol[..., :3] = TOL_RGB
+    tol[..., 3] = TOL_DEPTH_REL * np.maximum(1.0, np.abs(C[..., 3]))
+    tol[..., 4] = TOL_ALPHA
+    ok = np.all(d <= tol, axis=-1)
+    ok &= np.arange(ok.shape[-1]) < n[..., None]
+    ok &= ~np.isnan(C[..., 0])
+    idx = np.where(ok.any(-1), ok.argmax(-1), -1)
+    return ok.any(-1), idx
+
+
+def frame_to_numpy(f, view):
+    rgb = f.rgb[view].cpu().numpy().astype(np.float64)
+    depth = f.depth[view].cpu().numpy().astype(np.float64)
+    alpha = f.alpha[view].cpu().numpy().astype(np.float64)
+    img = np.concatenate([rgb, depth[..., None], alpha[..., None]], -1)
+    nc = f.n_contrib[view].cpu().numpy().astype(np.int64)
+    return img, nc

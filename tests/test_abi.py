@@ -1,0 +1,124 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/gs.h declares, and host-side validation rejects bad arguments with
+the documented status before anything is enqueued."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "gs.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gs_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2604_12626_amd import binding
+    return binding.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+    from paper_2604_12626_amd import binding
+    assert set(binding.EXPORTS) == set(names)
+
+
+def test_struct_layouts_match_header(lib):
+    from paper_2604_12626_amd import binding as B
+    assert ctypes.sizeof(B.Camera) == 64
+    assert ctypes.sizeof(B.Params) == 4 * 12
+    assert ctypes.sizeof(B.Gaussians) == 8 + 4 + 4 + 6 * 8
+    assert ctypes.sizeof(B.Projected) == 24
+
+
+def test_status_strings_and_defaults(lib):
+    from paper_2604_12626_amd import binding as B
+    assert lib.gs_status_string(0) == b"GS_OK"
+    assert lib.gs_status_string(3) == b"GS_ERR_WORKSPACE_TOO_SMALL"
+    p = B.make_params(640, 480)
+    assert (p.width, p.height) == (640, 480)
+    assert p.alpha_max == pytest.approx(0.99) and p.alpha_min == pytest.approx(1 / 255) and p.t_min == pytest.approx(1e-4)
+    assert p.near_plane == pytest.approx(0.2) and p.lowpass == pytest.approx(0.3) and p.sigma_cut == 3.0
+
+
+def _err(lib):
+    return lib.gs_last_error().decode()
+
+
+def test_validation_rejects_bad_arguments_without_a_gpu(lib):
+    from paper_2604_12626_amd import binding as B
+    p = B.make_params(64, 64)
+    seg = B.Gaussians()
+    seg.n, seg.sh_degree = 10, 0
+    seg.means = seg.opacity = seg.sh = ctypes.c_void_p(0x1000)
+    seg.log_scales = ctypes.c_void_p(0x2000)
+    seg.quats = ctypes.c_void_p(0x3000)
+    cams = ctypes.c_void_p(0x4000)
+    mask = (ctypes.c_uint32 * 1)(1)
+    out = B.Projected(10, ctypes.c_void_p(0x5000), ctypes.c_void_p(0x6000))
+    # no segments
+    assert lib.gs_project(None, 0, cams, 1, mask, ctypes.byref(p), ctypes.byref(out), None) == B.GS_ERR_INVALID_ARGUMENT
+    # SH degree 4
+    seg.sh_degree = 4
+    assert lib.gs_project(ctypes.byref(seg), 1, cams, 1, mask, ctypes.byref(p), ctypes.byref(out), None) == \
+        B.GS_ERR_INVALID_ARGUMENT
+    assert "sh_degree" in _err(lib)
+    seg.sh_degree = 0
+    # mask bit beyond n_segs
+    bad = (ctypes.c_uint32 * 1)(2)
+    assert lib.gs_project(ctypes.byref(seg), 1, cams, 1, bad, ctypes.byref(p), ctypes.byref(out), None) == \
+        B.GS_ERR_INVALID_ARGUMENT
+    # instance count mismatch
+    out.n_instances = 11
+    assert lib.gs_project(ctypes.byref(seg), 1, cams, 1, mask, ctypes.byref(p), ctypes.byref(out), None) == \
+        B.GS_ERR_INVALID_ARGUMENT
+    assert "n_instances" in _err(lib)
+    # misaligned quaternions
+    out.n_instances = 10
+    seg.quats = ctypes.c_void_p(0x3004)
+    assert lib.gs_project(ctypes.byref(seg), 1, cams, 1, mask, ctypes.byref(p), ctypes.byref(out), None) == \
+        B.GS_ERR_INVALID_ARGUMENT
+    # bad image size
+    p2 = B.make_params(0, 64)
+    assert lib.gs_project(ctypes.byref(seg), 1, cams, 1, mask, ctypes.byref(p2), ctypes.byref(out), None) == \
+        B.GS_ERR_INVALID_ARGUMENT
+
+
+def test_bin_sort_capacity_and_workspace_errors(lib):
+    from paper_2604_12626_amd import binding as B
+    p = B.make_params(640, 480)
+    proj = B.Projected(100, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000))
+    a = ctypes.c_void_p(0x10000)
+    ws_need = lib.gs_bin_sort_workspace(100, 1000, 1, ctypes.byref(p))
+    assert ws_need > 0
+    st = lib.gs_bin_sort(ctypes.byref(proj), 1, ctypes.byref(p), a, ws_need - 1, a, a, 1000, a, a, a, None)
+    assert st == B.GS_ERR_WORKSPACE_TOO_SMALL
+    st = lib.gs_bin_sort(ctypes.byref(proj), 1, ctypes.byref(p), a, ws_need, a, a, 1 << 30, a, a, a, None)
+    assert st == B.GS_ERR_UNSUPPORTED
+    st = lib.gs_bin_sort(ctypes.byref(proj), 1, ctypes.byref(p), a, ws_need, a, a, 0, a, a, a, None)
+    assert st == B.GS_ERR_INVALID_ARGUMENT
+    # workspace grows with capacity (ping-pong key/value buffers)
+    assert lib.gs_bin_sort_workspace(100, 2000, 1, ctypes.byref(p)) >= ws_need + 1000 * 12
+
+
+def test_lbs_and_composite_validation(lib):
+    from paper_2604_12626_amd import binding as B
+    a = ctypes.c_void_p(0x10000)
+    assert lib.gs_deform_lbs(-1, a, a, a, a, a, a, a, 1, 24, a, a, None) == B.GS_ERR_INVALID_ARGUMENT
+    assert lib.gs_deform_lbs(10, a, a, a, a, a, a, a, 1, 0, a, a, None) == B.GS_ERR_INVALID_ARGUMENT
+    assert lib.gs_deform_lbs(10, None, a, a, a, a, a, a, 1, 24, a, a, None) == B.GS_ERR_INVALID_ARGUMENT
+    assert lib.gs_deform_lbs(0, None, None, None, None, None, None, None, 1, 24, None, None, None) == B.GS_OK
+    p = B.make_params(64, 64)
+    proj = B.Projected(10, None, a)
+    st = lib.gs_composite(ctypes.byref(proj), a, a, 1, ctypes.byref(p), a, 8, a, a, a, None, None, None)
+    assert st == B.GS_ERR_WORKSPACE_TOO_SMALL
+    st = lib.gs_composite(ctypes.byref(proj), None, a, 1, ctypes.byref(p), a, 256, a, a, a, None, None, None)
+    assert st == B.GS_ERR_INVALID_ARGUMENT

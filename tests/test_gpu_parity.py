@@ -1,0 +1,290 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars: integer/index results (tile rects, keys, values, ranges, counts)
+bit-exact; images within 1e-4 max-abs (depth 1e-4 * max(1, |D|)) of one of
+the oracle's enumerated results for near-threshold decisions; pixels the
+oracle flags (ambiguous rect / depth near-tie) are excluded and counted."""
+import sys
+import zlib
+
+import numpy as np
+import pytest
+
+from paper_2604_12626_amd import synth
+
+from parity import TOL_RGB, frame_to_numpy, pixel_match, to_dev
+
+pytestmark = pytest.mark.gpu
+
+F32 = np.float32
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2604_12626_amd import binding
+    binding.load()
+    return torch.device("cuda:0")
+
+
+def _project_gpu(dev, segs, cams, view_segs, W, H):
+    import torch
+    from paper_2604_12626_amd import binding as B
+    tsegs = [to_dev(g, dev) for g in segs]
+    tc = torch.from_numpy(np.ascontiguousarray(cams, dtype=F32)).to(dev)
+    n_inst = B.instance_offsets(tsegs, view_segs)[-1]
+    tt = torch.zeros(n_inst, dtype=torch.int32, device=dev)
+    rec = torch.zeros(n_inst, 12, dtype=torch.float32, device=dev)
+    prm = B.make_params(W, H)
+    B.project(tsegs, tc, view_segs, prm, tt, rec)
+    torch.cuda.synchronize()
+    return tt.cpu().numpy().view(np.uint32), rec.cpu().numpy()
+
+
+PROJECT_CASES = [
+    ("cube10k_128x128_sh0", lambda: synth.config(0)),
+    ("room50k_640x480_sh3", lambda: synth.config(1, scale=0.05)),
+    ("room30k_200x150_sh3_ragged", lambda: dict(synth.config(1, scale=0.03), W=200, H=150,
+                                                cams=synth.camera_room(np.random.default_rng(9), 200, 150)[None])),
+]
+
+
+@pytest.mark.parametrize("name,make", PROJECT_CASES, ids=[c[0] for c in PROJECT_CASES])
+def test_project_parity(dev, orc, name, make):
+    cfg = make()
+    W, H = cfg["W"], cfg["H"]
+    g = cfg["segments"][0]
+    say("project parity:", name, len(g["means"]))
+    tt, rec = _project_gpu(dev, [g], cfg["cams"][:1], [[0]], W, H)
+    prm = orc.params(W, H)
+    pr = orc.project(g, cfg["cams"][0], prm)
+    vis_o, amb = pr[:, 0] > 0, pr[:, 21] > 0
+    vis_g = tt > 0
+    assert np.all((vis_o == vis_g) | amb), np.nonzero((vis_o != vis_g) & ~amb)[0][:10]
+    both = vis_o & vis_g
+    assert both.sum() > 100
+    r, o = rec[both].astype(np.float64), pr[both]
+    # tiles and radius: exact unless the oracle flags an integer decision in its margin
+    sure = ~amb[both]
+    assert np.array_equal(tt[both][sure], ((o[:, 13] - o[:, 12]) * (o[:, 15] - o[:, 14]))[sure].astype(np.uint32))
+    rad_g = rec[both][:, 3].view(np.int32)
+    rad_sure = o[:, 18] > 1e-5
+    assert np.array_equal(rad_g[rad_sure], o[rad_sure, 11].astype(np.int32))
+    # continuous values, against an FP32 error model of the camera transform:
+    # each camera coordinate carries ~eps * (sum_j |R_ij mu_j| + |t_i|)
+    cam = cfg["cams"][0].astype(np.float64)
+    R, t = cam[:9].reshape(3, 3), cam[9:12]
+    mu = g["means"][both].astype(np.float64)
+    mag = np.abs(mu) @ np.abs(R).T + np.abs(t)
+    eps = 4 * 2.0 ** -24
+    tz = o[:, 3]
+    tol_u = eps * (np.abs(o[:, 1] - cam[14]) * mag[:, 2] + cam[12] * mag[:, 0]) / tz + 8 * eps * np.abs(o[:, 1]) + 1e-5
+    tol_v = eps * (np.abs(o[:, 2] - cam[15]) * mag[:, 2] + cam[13] * mag[:, 1]) / tz + 8 * eps * np.abs(o[:, 2]) + 1e-5
+    assert np.all(np.abs(r[:, 0] - o[:, 1]) <= tol_u)
+    assert np.all(np.abs(r[:, 1] - o[:, 2]) <= tol_v)
+    assert np.all(np.abs(r[:, 2] - o[:, 3]) <= eps * mag[:, 2])
+    scale = np.abs(o[:, 4]) + np.abs(o[:, 6])
+    cerr = np.max(np.abs(r[:, 4:7] - o[:, 4:7]), axis=1) / scale
+    say("  conic rel err: max %.3g p99.9 %.3g" % (cerr.max(), np.quantile(cerr, 0.999)))
+    assert np.quantile(cerr, 0.999) < 1e-4 and cerr.max() < 1e-2
+    assert np.array_equal(r[:, 7], o[:, 7])
+    assert np.abs(r[:, 8:11] - o[:, 8:11]).max() <= 1e-5
+    assert np.all(rec[both][:, 11].view(np.int32) == 0)
+
+
+BIN_CASES = [
+    ("1view_128x128_5k", [5000], 128, 128),
+    ("4views_ragged_100x70", [3000, 0, 2500, 10], 100, 70),
+    ("single_instance", [1], 16, 16),
+    ("empty", [0], 32, 32),
+    ("1view_640x480_200k", [200000], 640, 480),
+    ("16views_256x256_60k", [4000] * 15 + [100], 256, 256),
+]
+
+
+@pytest.mark.parametrize("name,counts,W,H", BIN_CASES, ids=[c[0] for c in BIN_CASES])
+def test_bin_sort_bit_exact(dev, orc, name, counts, W, H):
+    import torch
+    from paper_2604_12626_amd import binding as B
+    rng = np.random.default_rng(zlib.crc32(name.encode()))
+    rec, vis = synth.synthetic_records(rng, counts, W, H)
+    V = len(counts)
+    tt_o, keys_o, vals_o, ranges_o, K = orc.bin_records(rec, vis, W, H, V)
+    say("bin_sort:", name, "instances", len(rec), "K", K)
+    prm = B.make_params(W, H)
+    for cap, expect_ovf in [(K + 1000, 0), (max(1, K // 2), 1 if K > max(1, K // 2) else 0)]:
+        tt = torch.from_numpy(tt_o.view(np.int32).copy()).to(dev)
+        r = torch.from_numpy(rec).to(dev)
+        keys = torch.zeros(cap, dtype=torch.int64, device=dev)
+        vals = torch.zeros(cap, dtype=torch.int32, device=dev)
+        T = ((W + 15) // 16) * ((H + 15) // 16)
+        ranges = torch.full((V * T, 2), 7, dtype=torch.int32, device=dev)
+        num = torch.zeros(1, dtype=torch.int64, device=dev)
+        ovf = torch.full((1,), 5, dtype=torch.int32, device=dev)
+        ws = torch.empty(B.bin_sort_workspace(len(rec), cap, V, prm), dtype=torch.uint8, device=dev)
+        B.bin_sort(tt, r, V, prm, ws, keys, vals, ranges, num, ovf)
+        torch.cuda.synchronize()
+        assert int(num.item()) == K and int(ovf.item()) == expect_ovf
+        if expect_ovf:
+            assert np.all(ranges.cpu().numpy() == 0)
+            continue
+        assert np.array_equal(keys.cpu().numpy()[:K].view(np.uint64), keys_o)
+        assert np.array_equal(vals.cpu().numpy()[:K].view(np.uint32), vals_o)
+        assert np.array_equal(ranges.cpu().numpy().view(np.uint32), ranges_o)
+
+
+COMPOSITE_CASES = [
+    ("1view_96x80_4k", [4000], 96, 80, 8.0),
+    ("2views_256x160_35k", [20000, 15000], 256, 160, 6.0),
+    ("1view_64x64_big_radii", [600], 64, 64, 30.0),
+]
+
+
+@pytest.mark.parametrize("name,counts,W,H,rmed", COMPOSITE_CASES, ids=[c[0] for c in COMPOSITE_CASES])
+def test_composite_parity(dev, orc, name, counts, W, H, rmed):
+    import torch
+    from paper_2604_12626_amd import binding as B
+    rng = np.random.default_rng(zlib.crc32(name.encode()))
+    rec, vis = synth.synthetic_records(rng, counts, W, H, r_median=rmed)
+    V = len(counts)
+    tt_o, keys_o, vals_o, ranges_o, K = orc.bin_records(rec, vis, W, H, V)
+    say("composite:", name, "K", K)
+    prm_o = orc.params(W, H, bg=(0.1, 0.2, 0.3))
+    img_o, ncand, cands = orc.composite(rec, vals_o, ranges_o, V, prm_o)
+    prm = B.make_params(W, H, bg=(0.1, 0.2, 0.3))
+    T = ((W + 15) // 16) * ((H + 15) // 16)
+    tt = torch.from_numpy(tt_o.view(np.int32).copy()).to(dev)
+    r = torch.from_numpy(rec).to(dev)
+    keys = torch.zeros(K + 16, dtype=torch.int64, device=dev)
+    vals = torch.zeros(K + 16, dtype=torch.int32, device=dev)
+    ranges = torch.zeros((V * T, 2), dtype=torch.int32, device=dev)
+    num = torch.zeros(1, dtype=torch.int64, device=dev)
+    ovf = torch.zeros(1, dtype=torch.int32, device=dev)
+    ws = torch.empty(B.bin_sort_workspace(len(rec), K + 16, V, prm), dtype=torch.uint8, device=dev)
+    B.bin_sort(tt, r, V, prm, ws, keys, vals, ranges, num, ovf)
+    rgb = torch.zeros(V, H, W, 3, device=dev)
+    depth = torch.zeros(V, H, W, device=dev)
+    alpha = torch.zeros(V, H, W, device=dev)
+    tfin = torch.zeros(V, H, W, device=dev)
+    ncon = torch.zeros(V, H, W, dtype=torch.int32, device=dev)
+    cws = torch.empty(256, dtype=torch.uint8, device=dev)
+    B.composite(r, vals, ranges, V, prm, cws, rgb, depth, alpha, tfin, ncon)
+    torch.cuda.synchronize()
+    gimg = np.concatenate([rgb.cpu().numpy(), depth.cpu().numpy()[..., None], alpha.cpu().numpy()[..., None]],
+                          -1).astype(np.float64)
+    ok, idx = pixel_match(gimg, cands, ncand)
+    say("  max |rgb - primary| = %.3g, alternative-branch pixels: %d" % (
+        np.abs(gimg[..., :3] - img_o[..., :3]).max(), int((idx > 0).sum())))
+    assert ok.all(), np.argwhere(~ok)[:5]
+    nsel = np.take_along_axis(cands[..., 6], np.maximum(idx, 0)[..., None], -1)[..., 0]
+    assert np.array_equal(ncon.cpu().numpy(), nsel.astype(np.int32))
+    assert np.allclose(tfin.cpu().numpy(), 1 - alpha.cpu().numpy(), atol=1e-6)
+
+
+RENDER_CASES = [
+    ("cube10k_128x128_sh0", lambda: synth.config(0)),
+    ("room50k_640x480_sh3", lambda: synth.config(1, scale=0.05)),
+    ("room20k_256x256_sh3", lambda: synth.config(2, scale=0.04)),
+]
+
+
+@pytest.mark.parametrize("name,make", RENDER_CASES, ids=[c[0] for c in RENDER_CASES])
+def test_render_end_to_end(dev, orc, name, make):
+    import torch
+    from paper_2604_12626_amd import render
+    cfg = make()
+    W, H = cfg["W"], cfg["H"]
+    g = cfg["segments"][0]
+    say("render end-to-end:", name)
+    r = render.Renderer(W, H, capacity=1 << 18, device=dev)
+    cams = torch.from_numpy(cfg["cams"][:1]).to(dev)
+    f = r.render([to_dev(g, dev)], cams, [[0]])
+    torch.cuda.synchronize()
+    gimg, _ = frame_to_numpy(f, 0)
+    prm = orc.params(W, H)
+    _, img_o, ncand, flags, cands, pairs = orc.render(g, cfg["cams"][0], prm)
+    ok, idx = pixel_match(gimg, cands, ncand)
+    bad = ~ok & (flags == 0)
+    frac_flag = float((flags != 0).mean())
+    say("  pairs %d, flagged %.4f%%, mismatched unflagged %d, max|rgb diff| unflagged %.3g" % (
+        pairs, 100 * frac_flag, int(bad.sum()), np.abs(gimg[..., :3] - img_o[..., :3])[flags == 0].max()))
+    assert not bad.any(), np.argwhere(bad)[:5]
+    assert frac_flag < 0.01
+
+
+def test_render_deterministic_and_batched_equals_plain(dev):
+    import torch
+    from paper_2604_12626_amd import render
+    cfg = synth.config(3, scale=0.02)
+    W, H = cfg["W"], cfg["H"]
+    views = [0, 1, 2, 9, 10]
+    segs = [to_dev(g, dev) for g in cfg["segments"]]
+    cams = torch.from_numpy(cfg["cams"][views]).to(dev)
+    vs = [cfg["view_segs"][v] for v in views]
+    say("batched vs plain: views", views)
+    r = render.Renderer(W, H, capacity=1 << 18, device=dev)
+    f = r.render(segs, cams, vs)
+    a1 = (f.rgb.clone(), f.depth.clone(), f.alpha.clone())
+    f = r.render(segs, cams, vs)
+    a2 = (f.rgb.clone(), f.depth.clone(), f.alpha.clone())
+    for x, y in zip(a1, a2):
+        assert torch.equal(x, y)
+    for k, v in enumerate(views):
+        r1 = render.Renderer(W, H, capacity=1 << 18, device=dev)
+        f1 = r1.render([segs[vs[k][0]]], cams[k:k + 1], [[0]])
+        assert torch.equal(f1.rgb[0], a1[0][k]) and torch.equal(f1.depth[0], a1[1][k])
+        assert torch.equal(f1.alpha[0], a1[2][k])
+
+
+def test_union_equals_concatenation(dev):
+    import torch
+    from paper_2604_12626_amd import render
+    rng = np.random.default_rng(77)
+    a = synth.gaussians_room(20000, rng, sh_degree=3)
+    b = synth.gaussians_room(7000, rng, sh_degree=3)
+    cat = {k: (np.concatenate([a[k], b[k]]) if isinstance(a[k], np.ndarray) else a[k]) for k in a}
+    cam = synth.camera_room(rng, 160, 128)
+    cams = torch.from_numpy(cam[None]).to(dev)
+    r = render.Renderer(160, 128, capacity=1 << 18, device=dev)
+    f = r.render([to_dev(a, dev), to_dev(b, dev)], cams, [[0, 1]])
+    u = (f.rgb.clone(), f.depth.clone(), f.alpha.clone())
+    f = r.render([to_dev(cat, dev)], cams, [[0]])
+    assert torch.equal(u[0], f.rgb) and torch.equal(u[1], f.depth) and torch.equal(u[2], f.alpha)
+
+
+def test_full_size_room_keys_are_a_valid_binning(dev):
+    """Config of the benchmark (1M Gaussians, 640x480, SH3): keys sorted, values
+    a permutation of the instance multiset, ranges consistent, K = sum tiles."""
+    import torch
+    from paper_2604_12626_amd import render
+    cfg = synth.config(1)
+    g = cfg["segments"][0]
+    say("full-size binning properties: room1M 640x480")
+    r = render.Renderer(640, 480, capacity=1 << 22, device=dev)
+    f = r.render([to_dev(g, dev)], torch.from_numpy(cfg["cams"]).to(dev), [[0]])
+    torch.cuda.synchronize()
+    K = int(f.num.item())
+    tt = f.tiles_touched.cpu().numpy().view(np.uint32).astype(np.int64)
+    assert K == tt.sum() and int(f.overflow.item()) == 0
+    keys = f.keys.cpu().numpy()[:K].view(np.uint64)
+    vals = f.vals.cpu().numpy()[:K].view(np.uint32)
+    assert np.all(keys[1:] >= keys[:-1])
+    eq = keys[1:] == keys[:-1]
+    assert np.all(vals[1:][eq] > vals[:-1][eq])  # ties in ascending instance order
+    assert np.array_equal(np.bincount(vals, minlength=len(tt)), tt)
+    rec = f.rec.cpu().numpy()
+    assert np.array_equal((keys & np.uint64(0xFFFFFFFF)).astype(np.uint32), rec[vals, 2].view(np.uint32))
+    ranges = f.ranges.cpu().numpy().view(np.uint32)
+    tiles = (keys >> np.uint64(32)).astype(np.int64)
+    starts = np.searchsorted(tiles, np.arange(1200), "left")
+    ends = np.searchsorted(tiles, np.arange(1200), "right")
+    empty = starts == ends
+    assert np.array_equal(ranges[~empty, 0], starts[~empty]) and np.array_equal(ranges[~empty, 1], ends[~empty])
+    assert np.all(ranges[empty] == 0)
+    say("  K = %d, visible = %d" % (K, int((tt > 0).sum())))
