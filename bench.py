@@ -4,9 +4,10 @@
 Headline (`value`): forward frames/s of one 640x480 view of a 1M-Gaussian SH3
 room scene (synthetic stand-in for an indoor 3DGS capture), the whole
 per-frame path -- projection + SH, scan/emit, onesweep sort, ranges,
-compositing -- replayed as one captured HIP graph with inputs resident in
-HBM.  Further lines of the metric (fwd+bwd, batched multi-view vs plain
-per-view, avatars) are reported under "extras".
+compositing -- enqueued back to back on one stream with no host
+synchronisation and inputs resident in HBM.  Further lines of the metric
+(fwd+bwd, batched multi-view vs plain per-view, avatars) are reported under
+"extras".
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras]
                        [--no-cpu-baseline] [--profile]
@@ -104,24 +105,13 @@ def bench_forward(args, dev, timer_steps):
     torch.cuda.synchronize()
     K = int(f.num.item())
     n_vis = int((f.tiles_touched > 0).sum().item())
-    # graph of the whole forward frame
-    stream = torch.cuda.Stream()
-    stream.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(stream):
-        for _ in range(2):
-            r.enqueue(segs, cams, vs, f)
-    torch.cuda.current_stream().wait_stream(stream)
-    torch.cuda.synchronize()
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph):
-        r.enqueue(segs, cams, vs, f)
-    torch.cuda.synchronize()
+    # the whole forward frame as a launch sequence on one stream, no host sync
     for _ in range(args.warmup):
-        graph.replay()
+        r.enqueue(segs, cams, vs, f)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        graph.replay()
+        r.enqueue(segs, cams, vs, f)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     assert int(f.overflow.item()) == 0, "key capacity overflow during the timed region"
@@ -169,43 +159,50 @@ def bench_fwd_bwd(args, dev, steps):
     return (time.perf_counter() - t0) * 1e3 / steps
 
 
+_CFG4 = []
+
+
+def config4():
+    from paper_2604_12626_amd import synth
+    if not _CFG4:
+        _CFG4.append(synth.config(4))
+    return _CFG4[0]
+
+
 def bench_batched(args, dev, steps, n_views=16):
     """n_views views at 640x480 of the 1M room: one batched call vs the same
     views rendered one call at a time (plain)."""
     import torch
-    from paper_2604_12626_amd import render, synth
-    cfg = synth.config(4)
+    from paper_2604_12626_amd import render
+    cfg = config4()
     room = to_dev(cfg["segments"][0], dev)
     cams = torch.from_numpy(cfg["cams"][:n_views]).to(dev)
     W, H = cfg["W"], cfg["H"]
     rb = render.Renderer(W, H, capacity=1 << 24, device=dev)
     vs = [[0]] * n_views
     fb = rb.render([room], cams, vs)
-    graph = _capture(lambda: rb.enqueue([room], cams, vs, fb))
-    ms_b = _time_graph(graph, args.warmup, steps)
+    ms_b = _time_seq(lambda: rb.enqueue([room], cams, vs, fb), args.warmup, steps)
     plain = []
     for v in range(n_views):
         rp = render.Renderer(W, H, capacity=1 << 22, device=dev)
         fp = rp.render([room], cams[v:v + 1], [[0]])
-        plain.append(_capture(lambda rp=rp, fp=fp, v=v: rp.enqueue([room], cams[v:v + 1], [[0]], fp)))
-    for gph in plain:
-        gph.replay()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        for gph in plain:
-            gph.replay()
-    torch.cuda.synchronize()
-    ms_p = (time.perf_counter() - t0) * 1e3 / steps
+        plain.append((rp, fp, v))
+
+    def all_plain():
+        for rp, fp, v in plain:
+            rp.enqueue([room], cams[v:v + 1], [[0]], fp)
+
+    ms_p = _time_seq(all_plain, args.warmup, steps)
+    assert int(fb.overflow.item()) == 0 and all(int(fp.overflow.item()) == 0 for _, fp, _ in plain)
     return ms_b, ms_p, n_views
 
 
 def bench_avatars(args, dev, steps):
     """Workload with avatars: LBS of 8 x 50k avatar Gaussians, then 16 views at
-    640x480 of room + avatars in one call (one graph)."""
+    640x480 of room + avatars in one call."""
     import torch
-    from paper_2604_12626_amd import binding as B, render, synth
-    cfg = synth.config(4)
+    from paper_2604_12626_amd import binding as B, render
+    cfg = config4()
     room = to_dev(cfg["segments"][0], dev)
     av = to_dev(cfg["avatars"], dev)
     skin = torch.from_numpy(cfg["skin"]).to(dev)
@@ -227,34 +224,19 @@ def bench_avatars(args, dev, steps):
         lbs()
         r.enqueue([room, posed], cams, vs, f)
 
-    graph = _capture(frame)
-    ms = _time_graph(graph, args.warmup, steps)
+    ms = _time_seq(frame, args.warmup, steps)
+    assert int(f.overflow.item()) == 0
     return ms, len(vs)
 
 
-def _capture(fn):
-    import torch
-    s = torch.cuda.Stream()
-    s.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(s):
-        fn()
-    torch.cuda.current_stream().wait_stream(s)
-    torch.cuda.synchronize()
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g):
-        fn()
-    torch.cuda.synchronize()
-    return g
-
-
-def _time_graph(g, warmup, steps):
+def _time_seq(fn, warmup, steps):
     import torch
     for _ in range(warmup):
-        g.replay()
+        fn()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        g.replay()
+        fn()
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) * 1e3 / steps
 

@@ -160,8 +160,7 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
 
 hipError_t launch_backward_tiles(const BackwardTileArgs &a, hipStream_t s) {
     if (a.n_items == 0) return hipSuccess;
-    hipLaunchKernelGGL(backward_tile_kernel, dim3((unsigned)a.n_items), dim3(kTilePixels), 0, s, a);
-    return hipGetLastError();
+    return launch_kernel(backward_tile_kernel, dim3((unsigned)a.n_items), dim3(kTilePixels), s, a);
 }
 
 // ---------------------------------------------------------------------------
@@ -171,18 +170,18 @@ template <int D>
 __global__ void __launch_bounds__(256) backward_project_kernel(const BackwardProjectArgs a) {
     constexpr int K = (D + 1) * (D + 1);
     __shared__ float s_cam[kProjViews * kCamStride];
-    for (int k = threadIdx.x; k < a.nv * 16; k += blockDim.x) {
+    for (int k = threadIdx.x; k < a.nv * 16; k += 256) {
         const int vi = k >> 4, f = k & 15;
         s_cam[vi * kCamStride + f] = reinterpret_cast<const float *>(a.cams + a.view[vi])[f];
     }
     __syncthreads();
-    for (int vi = threadIdx.x; vi < a.nv; vi += blockDim.x) {
+    for (int vi = threadIdx.x; vi < a.nv; vi += 256) {
         float *c = s_cam + vi * kCamStride;
 #pragma unroll
         for (int j = 0; j < 3; ++j) c[16 + j] = -(c[j] * c[9] + c[3 + j] * c[10] + c[6 + j] * c[11]);
     }
     __syncthreads();
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= a.seg.n) return;
 
     const float mx = a.seg.means[3 * i + 0], my = a.seg.means[3 * i + 1], mz = a.seg.means[3 * i + 2];
@@ -370,12 +369,11 @@ hipError_t launch_backward_project(const BackwardProjectArgs &a, hipStream_t s) 
     if (a.seg.n == 0) return hipSuccess;
     const unsigned grid = (unsigned)((a.seg.n + 255) / 256);
     switch (a.seg.sh_degree) {
-        case 0: hipLaunchKernelGGL(backward_project_kernel<0>, dim3(grid), dim3(256), 0, s, a); break;
-        case 1: hipLaunchKernelGGL(backward_project_kernel<1>, dim3(grid), dim3(256), 0, s, a); break;
-        case 2: hipLaunchKernelGGL(backward_project_kernel<2>, dim3(grid), dim3(256), 0, s, a); break;
-        default: hipLaunchKernelGGL(backward_project_kernel<3>, dim3(grid), dim3(256), 0, s, a); break;
+        case 0: return launch_kernel(backward_project_kernel<0>, dim3(grid), dim3(256), s, a);
+        case 1: return launch_kernel(backward_project_kernel<1>, dim3(grid), dim3(256), s, a);
+        case 2: return launch_kernel(backward_project_kernel<2>, dim3(grid), dim3(256), s, a);
+        default: return launch_kernel(backward_project_kernel<3>, dim3(grid), dim3(256), s, a);
     }
-    return hipGetLastError();
 }
 
 }  // namespace gs

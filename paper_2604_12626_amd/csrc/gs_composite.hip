@@ -94,8 +94,7 @@ __global__ void __launch_bounds__(kTilePixels) composite_kernel(const CompositeA
 
 hipError_t launch_composite(const CompositeArgs &a, int grid, hipStream_t s) {
     if (a.n_items == 0) return hipSuccess;
-    hipLaunchKernelGGL(composite_kernel, dim3(grid), dim3(kTilePixels), 0, s, a);
-    return hipGetLastError();
+    return launch_kernel(composite_kernel, dim3(grid), dim3(kTilePixels), s, a);
 }
 
 }  // namespace gs

@@ -4,6 +4,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <tuple>
+#include <utility>
+
 #include "gs.h"
 
 namespace gs {
@@ -107,6 +110,24 @@ hipError_t launch_composite(const CompositeArgs &a, int grid, hipStream_t s);
 hipError_t launch_backward_tiles(const BackwardTileArgs &a, hipStream_t s);
 hipError_t launch_backward_project(const BackwardProjectArgs &a, hipStream_t s);
 hipError_t launch_lbs(const LbsArgs &a, bool backward, hipStream_t s);
+
+// Launch a kernel through hipLaunchKernel so that the call returns the status
+// of this launch itself (never a stale error of an earlier runtime call).  The
+// arguments are converted to the kernel's parameter types first.
+template <typename... KArgs, typename... Args>
+inline hipError_t launch_kernel(void (*kernel)(KArgs...), dim3 grid, dim3 block, hipStream_t s, Args &&...args) {
+    static_assert(sizeof...(KArgs) == sizeof...(Args), "kernel argument count");
+    if (grid.x == 0 || grid.y == 0 || grid.z == 0) return hipSuccess;
+    struct Pack {
+        std::tuple<KArgs...> t;
+    } pack{std::tuple<KArgs...>(std::forward<Args>(args)...)};
+    void *argv[sizeof...(KArgs) > 0 ? sizeof...(KArgs) : 1];
+    std::apply([&](auto &...x) {
+        int k = 0;
+        ((argv[k++] = static_cast<void *>(&x)), ...);
+    }, pack.t);
+    return hipLaunchKernel(reinterpret_cast<const void *>(kernel), grid, block, argv, 0, s);
+}
 
 // ---------------------------------------------------------------------------
 // small device helpers

@@ -41,7 +41,7 @@ __device__ __forceinline__ void blend_matrix(const LbsArgs &a, int64_t i, float 
 }
 
 __global__ void __launch_bounds__(256) lbs_kernel(const LbsArgs a) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= a.n) return;
     float A[12];
     blend_matrix(a, i, A);
@@ -70,7 +70,7 @@ __global__ void __launch_bounds__(256) lbs_kernel(const LbsArgs a) {
 }
 
 __global__ void __launch_bounds__(256) lbs_backward_kernel(const LbsArgs a) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= a.n) return;
     float A[12];
     blend_matrix(a, i, A);
@@ -105,11 +105,8 @@ __global__ void __launch_bounds__(256) lbs_backward_kernel(const LbsArgs a) {
 hipError_t launch_lbs(const LbsArgs &a, bool backward, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
     const unsigned grid = (unsigned)((a.n + 255) / 256);
-    if (backward)
-        hipLaunchKernelGGL(lbs_backward_kernel, dim3(grid), dim3(256), 0, s, a);
-    else
-        hipLaunchKernelGGL(lbs_kernel, dim3(grid), dim3(256), 0, s, a);
-    return hipGetLastError();
+    if (backward) return launch_kernel(lbs_backward_kernel, dim3(grid), dim3(256), s, a);
+    return launch_kernel(lbs_kernel, dim3(grid), dim3(256), s, a);
 }
 
 }  // namespace gs

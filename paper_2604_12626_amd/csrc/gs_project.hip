@@ -13,12 +13,12 @@ template <int D>
 __global__ void __launch_bounds__(256) project_kernel(const ProjectArgs a) {
     constexpr int K = (D + 1) * (D + 1);
     __shared__ float s_cam[kProjViews * kCamStride];
-    for (int k = threadIdx.x; k < a.nv * 16; k += blockDim.x) {
+    for (int k = threadIdx.x; k < a.nv * 16; k += 256) {
         const int vi = k >> 4, f = k & 15;
         s_cam[vi * kCamStride + f] = reinterpret_cast<const float *>(a.cams + a.view[vi])[f];
     }
     __syncthreads();
-    for (int vi = threadIdx.x; vi < a.nv; vi += blockDim.x) {
+    for (int vi = threadIdx.x; vi < a.nv; vi += 256) {
         float *c = s_cam + vi * kCamStride;
         // camera centre -R^T t
 #pragma unroll
@@ -26,10 +26,22 @@ __global__ void __launch_bounds__(256) project_kernel(const ProjectArgs a) {
     }
     __syncthreads();
 
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= a.seg.n) return;
 
     const float mx = a.seg.means[3 * i + 0], my = a.seg.means[3 * i + 1], mz = a.seg.means[3 * i + 2];
+    // near-plane test from the mean alone: a Gaussian behind every camera of
+    // the launch never reads its scale, rotation, opacity or SH rows
+    bool any_front = false;
+    for (int vi = 0; vi < a.nv; ++vi) {
+        const float *c = s_cam + vi * kCamStride;
+        const float tz = c[6] * mx + c[7] * my + c[8] * mz + c[11];
+        any_front |= tz > a.near_plane;
+    }
+    if (!any_front) {
+        for (int vi = 0; vi < a.nv; ++vi) a.tiles_touched[a.base[vi] + i] = 0u;
+        return;
+    }
     float S[6];
     if (a.seg.cov6) {
 #pragma unroll
@@ -100,12 +112,11 @@ hipError_t launch_project(const ProjectArgs &a, hipStream_t s) {
     if (a.seg.n == 0 || a.nv == 0) return hipSuccess;
     const unsigned grid = (unsigned)((a.seg.n + 255) / 256);
     switch (a.seg.sh_degree) {
-        case 0: hipLaunchKernelGGL(project_kernel<0>, dim3(grid), dim3(256), 0, s, a); break;
-        case 1: hipLaunchKernelGGL(project_kernel<1>, dim3(grid), dim3(256), 0, s, a); break;
-        case 2: hipLaunchKernelGGL(project_kernel<2>, dim3(grid), dim3(256), 0, s, a); break;
-        default: hipLaunchKernelGGL(project_kernel<3>, dim3(grid), dim3(256), 0, s, a); break;
+        case 0: return launch_kernel(project_kernel<0>, dim3(grid), dim3(256), s, a);
+        case 1: return launch_kernel(project_kernel<1>, dim3(grid), dim3(256), s, a);
+        case 2: return launch_kernel(project_kernel<2>, dim3(grid), dim3(256), s, a);
+        default: return launch_kernel(project_kernel<3>, dim3(grid), dim3(256), s, a);
     }
-    return hipGetLastError();
 }
 
 }  // namespace gs

@@ -33,17 +33,15 @@ constexpr uint32_t kCountMask = (1u << 30) - 1u;
 // ---------------------------------------------------------------------------
 // fill (used instead of memset nodes so a captured graph replays correctly)
 // ---------------------------------------------------------------------------
-__global__ void fill_u32_kernel(uint32_t *p, uint32_t v, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = v;
+__global__ void __launch_bounds__(256) fill_u32_kernel(uint32_t *p, uint32_t v, int64_t n, int64_t stride) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) p[i] = v;
 }
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     int64_t blocks = (n + 255) / 256;
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, v, n);
-    return hipGetLastError();
+    return launch_kernel(fill_u32_kernel, dim3((unsigned)blocks), dim3(256), s, p, v, n, blocks * 256);
 }
 
 // ---------------------------------------------------------------------------
@@ -57,7 +55,7 @@ __device__ __forceinline__ uint64_t block_reduce_u64(uint64_t v, uint64_t *s_tmp
     __syncthreads();
     uint64_t t = 0;
     if (threadIdx.x == 0)
-        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += s_tmp[k];
+        for (int k = 0; k < kScanBlock / 64; ++k) t += s_tmp[k];
     return t;  // valid in thread 0
 }
 
@@ -139,7 +137,7 @@ __global__ void __launch_bounds__(kScanBlock) scan_down_kernel(const uint32_t *t
 __global__ void __launch_bounds__(256) emit_kernel(const uint32_t *tt, const uint32_t *offsets, const float4 *rec,
                                                    int64_t n, int TX, int TY, int64_t capacity, uint64_t *keys,
                                                    uint32_t *vals) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (g >= n) return;
     if (tt[g] == 0u) return;
     int64_t k = offsets[g];
@@ -168,17 +166,18 @@ __device__ __forceinline__ int64_t sort_count(const int64_t *d_num, int64_t capa
 
 // global digit histograms of all passes in one read of the keys
 __global__ void __launch_bounds__(256) sort_hist_kernel(const uint64_t *keys, const int64_t *d_num, int64_t capacity,
-                                                        int passes, int bit0, uint32_t *hist /*[passes][256]*/) {
+                                                        int passes, int bit0, uint32_t *hist /*[passes][256]*/,
+                                                        int64_t stride) {
     __shared__ uint32_t s_h[kMaxPasses * kBins];
-    for (int k = threadIdx.x; k < passes * kBins; k += blockDim.x) s_h[k] = 0u;
+    for (int k = threadIdx.x; k < passes * kBins; k += 256) s_h[k] = 0u;
     __syncthreads();
     const int64_t K = sort_count(d_num, capacity);
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < K; i += stride) {
         const uint64_t key = keys[i];
         for (int p = 0; p < passes; ++p) atomicAdd(&s_h[p * kBins + ((key >> (bit0 + p * kRadixBits)) & (kBins - 1))], 1u);
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < passes * kBins; k += blockDim.x)
+    for (int k = threadIdx.x; k < passes * kBins; k += 256)
         if (s_h[k]) atomicAdd(&hist[k], s_h[k]);
 }
 
@@ -333,7 +332,7 @@ __global__ void __launch_bounds__(256) ranges_kernel(const uint64_t *keys, const
                                                      uint64_t n_tiles_total) {
     if (*d_overflow) return;
     const int64_t K = sort_count(d_num, capacity);
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (k >= K) return;
     const uint64_t t = keys[k] >> 32;
     if (t >= n_tiles_total) return;
@@ -398,15 +397,18 @@ hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec
     if ((e = launch_fill_u32(ranges, 0u, 2 * P.n_tiles_total, s)) != hipSuccess) return e;
     // 1. scan
     if (P.n > 0) {
-        hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)P.scan_blocks), dim3(kScanBlock), 0, s, tt, P.n, part);
+        if ((e = launch_kernel(scan_reduce_kernel, dim3((unsigned)P.scan_blocks), dim3(kScanBlock), s, tt, P.n,
+                               part)) != hipSuccess)
+            return e;
     }
-    hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(1024), 0, s, part, P.n > 0 ? P.scan_blocks : 0,
-                       P.capacity, d_num, d_overflow);
+    if ((e = launch_kernel(scan_partials_kernel, dim3(1), dim3(1024), s, part, P.n > 0 ? P.scan_blocks : (int64_t)0,
+                           P.capacity, d_num, d_overflow)) != hipSuccess)
+        return e;
     if (P.n > 0) {
-        hipLaunchKernelGGL(scan_down_kernel, dim3((unsigned)P.scan_blocks), dim3(kScanBlock), 0, s, tt, P.n, part,
-                           offsets);
+        if ((e = launch_kernel(scan_down_kernel, dim3((unsigned)P.scan_blocks), dim3(kScanBlock), s, tt, P.n, part,
+                               offsets)) != hipSuccess)
+            return e;
     }
-    if ((e = hipGetLastError()) != hipSuccess) return e;
     // 2. emit into the buffer that the last pass does not write to
     const bool odd = (P.passes & 1) != 0;
     uint64_t *k_a = odd ? keys2 : keys;
@@ -414,22 +416,25 @@ hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec
     uint64_t *k_b = odd ? keys : keys2;
     uint32_t *v_b = odd ? vals : vals2;
     if (P.n > 0) {
-        hipLaunchKernelGGL(emit_kernel, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, s, tt, offsets, rec, P.n,
-                           TX, TY, P.capacity, k_a, v_a);
+        if ((e = launch_kernel(emit_kernel, dim3((unsigned)((P.n + 255) / 256)), dim3(256), s, tt, offsets, rec,
+                               P.n, TX, TY, P.capacity, k_a, v_a)) != hipSuccess)
+            return e;
     }
     // 3. onesweep passes over the significant bits
     {
         int64_t hb = (P.capacity + 255) / 256;
         if (hb > 2048) hb = 2048;
         if (hb < 1) hb = 1;
-        hipLaunchKernelGGL(sort_hist_kernel, dim3((unsigned)hb), dim3(256), 0, s, k_a, d_num, P.capacity, P.passes,
-                           0, hist);
-        hipLaunchKernelGGL(sort_hist_scan_kernel, dim3(1), dim3(kBins), 0, s, hist, P.passes);
+        if ((e = launch_kernel(sort_hist_kernel, dim3((unsigned)hb), dim3(256), s, k_a, d_num, P.capacity, P.passes, 0,
+                               hist, hb * 256)) != hipSuccess)
+            return e;
+        if ((e = launch_kernel(sort_hist_scan_kernel, dim3(1), dim3(kBins), s, hist, P.passes)) != hipSuccess) return e;
     }
     for (int p = 0; p < P.passes; ++p) {
-        hipLaunchKernelGGL(onesweep_kernel, dim3((unsigned)P.sort_parts), dim3(kSortBlock), 0, s, k_a, v_a, k_b, v_b,
-                           d_num, P.capacity, p * kRadixBits, hist + p * kBins,
-                           status + (size_t)p * P.sort_parts * kBins, ticket + p * 64);
+        if ((e = launch_kernel(onesweep_kernel, dim3((unsigned)P.sort_parts), dim3(kSortBlock), s, k_a, v_a, k_b, v_b,
+                               d_num, P.capacity, p * kRadixBits, hist + p * kBins,
+                               status + (size_t)p * P.sort_parts * kBins, ticket + p * 64)) != hipSuccess)
+            return e;
         uint64_t *tk = k_a;
         k_a = k_b;
         k_b = tk;
@@ -438,15 +443,14 @@ hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec
         v_b = tv;
     }
     // k_a now holds the sorted keys (== keys)
-    if ((e = hipGetLastError()) != hipSuccess) return e;
     // 4. ranges
     {
         const int64_t blocks = (P.capacity + 255) / 256;
         if (blocks > 0)
-            hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)blocks), dim3(256), 0, s, k_a, d_num, P.capacity,
-                               d_overflow, ranges, (uint64_t)P.n_tiles_total);
+            return launch_kernel(ranges_kernel, dim3((unsigned)blocks), dim3(256), s, k_a, d_num, P.capacity, d_overflow,
+                                 ranges, (uint64_t)P.n_tiles_total);
     }
-    return hipGetLastError();
+    return hipSuccess;
 }
 
 }  // namespace gs

@@ -193,7 +193,7 @@ def avatar_canonical(n, rng, sh_degree=3):
     if K > 1:
         sh[:, 1:, :] = rng.normal(0.0, 0.05, (n, K - 1, 3))
     g = _pack(means, lsc, q, op, sh, sh_degree)
-    idx = np.stack([rng.choice(N_JOINTS, size=4, replace=False) for _ in range(n)])
+    idx = np.argsort(rng.random((n, N_JOINTS)), axis=1)[:, :4]  # 4 distinct uniform joints
     w = rng.dirichlet(np.ones(4), size=n)
     g["joint_idx"] = idx.astype(np.uint8)
     g["weights"] = w.astype(np.float32)

@@ -288,3 +288,67 @@ def test_full_size_room_keys_are_a_valid_binning(dev):
     assert np.array_equal(ranges[~empty, 0], starts[~empty]) and np.array_equal(ranges[~empty, 1], ends[~empty])
     assert np.all(ranges[empty] == 0)
     say("  K = %d, visible = %d" % (K, int((tt > 0).sum())))
+
+
+def _max_rel_block(gpu, ref):
+    return np.abs(gpu - ref).max() / max(np.abs(ref).max(), 1e-30)
+
+
+def test_backward_parity_sh3(dev, orc):
+    """Gradients of <G, render> for random output adjoints G (rgb, depth,
+    alpha) against the oracle's FP64 adjoint, on every Gaussian."""
+    import torch
+    from paper_2604_12626_amd import render
+    cfg = synth.config(2, scale=0.04)  # 20k Gaussians, 256x256, SH3
+    W, H = cfg["W"], cfg["H"]
+    g = cfg["segments"][0]
+    say("backward parity: room20k 256x256 sh3")
+    rng = np.random.default_rng(5)
+    G = [rng.standard_normal((1, H, W, 3)).astype(F32), rng.standard_normal((1, H, W)).astype(F32),
+         rng.standard_normal((1, H, W)).astype(F32)]
+    r = render.Renderer(W, H, capacity=1 << 18, device=dev)
+    tg = to_dev(g, dev)
+    cams = torch.from_numpy(cfg["cams"]).to(dev)
+    f = r.render([tg], cams, [[0]])
+    d = r.backward([tg], cams, [[0]], f, *[torch.from_numpy(x).to(dev) for x in G])[0]
+    torch.cuda.synchronize()
+    prm = orc.params(W, H)
+    ref = orc.backward(g, cfg["cams"], prm, *G)
+    worst = {}
+    for k in ("means", "log_scales", "quats", "opacity", "sh"):
+        gg = d[k].cpu().numpy().astype(np.float64).reshape(ref[k].shape)
+        worst[k] = _max_rel_block(gg, ref[k])
+    say("  max |g_gpu - g_ref| / max |g_ref| per block:", {k: "%.2e" % v for k, v in worst.items()})
+    for k, v in worst.items():
+        assert v <= 1e-4, (k, v)
+
+
+def test_lbs_parity(dev, orc):
+    import torch
+    from paper_2604_12626_amd import binding as B
+    cfg = synth.config(4, scale=0.02)  # 8 avatars x 1000 Gaussians (room unused here)
+    av, skin = cfg["avatars"], cfg["skin"]
+    n, J = len(av["means"]), synth.N_JOINTS
+    say("lbs parity:", n, "avatar gaussians")
+    t = to_dev(av, dev)
+    tskin = torch.from_numpy(skin).to(dev)
+    mo = torch.empty(n, 3, device=dev)
+    co = torch.empty(n, 6, device=dev)
+    B.deform_lbs(t["means"], t["log_scales"], t["quats"], t["joint_idx"], t["weights"], t["avatar_of"], tskin, mo, co)
+    w = orc.dense_weights(av["joint_idx"], av["weights"], J)
+    mo_o, co_o = orc.lbs(av["means"], av["log_scales"], av["quats"], w, av["avatar_of"], skin, J)
+    torch.cuda.synchronize()
+    assert np.abs(mo.cpu().numpy() - mo_o).max() <= 1e-5 * max(1.0, np.abs(mo_o).max())
+    cs = np.abs(co_o).max(1, keepdims=True)
+    assert np.all(np.abs(co.cpu().numpy() - co_o) <= 1e-5 * cs + 1e-12)
+    rng = np.random.default_rng(3)
+    gm = rng.standard_normal((n, 3)).astype(F32)
+    gc = (rng.standard_normal((n, 6)) * 1e3).astype(F32)
+    dm, ds, dq = (torch.empty(n, k, device=dev) for k in (3, 3, 4))
+    B.deform_lbs_backward(t["means"], t["log_scales"], t["quats"], t["joint_idx"], t["weights"], t["avatar_of"], tskin,
+                          torch.from_numpy(gm).to(dev), torch.from_numpy(gc).to(dev), dm, ds, dq)
+    rm, rs, rq = orc.lbs_backward(av["means"], av["log_scales"], av["quats"], w, av["avatar_of"], skin, J, gm, gc)
+    torch.cuda.synchronize()
+    for a, b in ((dm, rm), (ds, rs), (dq, rq)):
+        a = a.cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(a - b) <= 1e-4 * np.abs(b).max(1, keepdims=True) + 1e-9), np.abs(a - b).max()

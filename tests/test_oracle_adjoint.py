@@ -278,7 +278,7 @@ def test_lbs_backward_by_finite_differences(orc):
         for i in range(0, n, 3):
             for c in range(arr.shape[1]):
                 x0 = float(arr[i, c])
-                h = 1e-3 * max(abs(x0), 0.1)
+                h = 2e-4 * max(abs(x0), 0.1)
                 ap, am = arr.copy(), arr.copy()
                 ap[i, c] = F32(x0 + h)
                 am[i, c] = F32(x0 - h)
@@ -287,4 +287,4 @@ def test_lbs_backward_by_finite_differences(orc):
                 args_p[name], args_m[name] = ap, am
                 fd = (L(args_p["means"], args_p["log_scales"], args_p["quats"]) -
                       L(args_m["means"], args_m["log_scales"], args_m["quats"])) / (float(ap[i, c]) - float(am[i, c]))
-                assert abs(fd - ref[i, c]) <= 1e-6 * np.abs(ref).max() + 1e-5 * abs(ref[i, c]), (name, i, c)
+                assert abs(fd - ref[i, c]) <= 1e-5 * np.abs(ref).max() + 1e-4 * abs(ref[i, c]), (name, i, c)
