@@ -313,6 +313,7 @@ static void project_one(const oprm *p, const ocam *cam, int D, const float *mean
     memset(o, 0, sizeof(*o));
     o->opacity = (double)opac;
     const double mu[3] = {mean[0], mean[1], mean[2]};
+    if (!isfinite(o->opacity)) return; /* non-finite input is culled (vis = 0) */
     /* O1/O2: covariance */
     if (cov6) {
         o->use_cov6 = 1;

@@ -1,13 +1,14 @@
 // gs_render_backward kernels.
 //
-// B1 (per tile, 256 threads = one per pixel): walks the tile's list back to
-// front from the last composited entry, recomputing each alpha with exactly
-// the forward's FP32 expression (so every skip/stop/clamp decision repeats),
-// recovering the transmittance by T_i = T_{i+1} / (1 - alpha_i), and forming
-// the screen-space adjoint of each entry (u, v, conic, opacity, colour,
-// depth).  Per entry the 64 lanes of a wave are summed with cross-lane adds
-// and one lane issues the global float atomics; entries no lane of the wave
-// reached are skipped with a ballot.
+// B1 (per tile, 256 threads = one per pixel, each wave an 8 x 8 quadrant):
+// walks the tile's list back to front from the last composited entry,
+// recomputing each alpha with exactly the forward's FP32 expression (so every
+// skip/stop/clamp decision repeats), recovering the transmittance by
+// T_i = T_{i+1} / (1 - alpha_i), and forming the screen-space adjoint of each
+// entry (u, v, conic, opacity, colour, depth).  Entries that cannot reach a
+// wave's quadrant are dropped by the same conservative bound as the forward;
+// per remaining entry the 64 lanes are summed with cross-lane adds and one
+// lane issues the global float atomics (skipped when no lane contributed).
 //
 // B2 (per Gaussian of a segment, scene-major): chains the screen-space
 // adjoints of every view that drew the Gaussian through the projection to the
@@ -27,17 +28,20 @@ __device__ __forceinline__ float wave_sum(float v) {
 }
 
 __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const BackwardTileArgs a) {
-    __shared__ float s_u[kBwdBatch], s_v[kBwdBatch], s_a[kBwdBatch], s_b[kBwdBatch], s_c[kBwdBatch],
-        s_o[kBwdBatch], s_z[kBwdBatch], s_r[kBwdBatch], s_g[kBwdBatch], s_bl[kBwdBatch], s_A[kBwdBatch],
-        s_B[kBwdBatch], s_C[kBwdBatch];
-    __shared__ uint32_t s_gid[kBwdBatch];
+    __shared__ float4 s_e0[kBwdBatch], s_e1[kBwdBatch], s_e2[kBwdBatch], s_q[kBwdBatch];
+    __shared__ uint8_t s_mask[kBwdBatch];
+    __shared__ uint8_t s_list[4][kBwdBatch];
     __shared__ uint32_t s_maxlast;
     const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int64_t item = blockIdx.x;
     const int view = (int)(item / a.T);
     const int tile = (int)(item - (int64_t)view * a.T);
-    const int px = (tile % a.TX) * kTile + (tid & (kTile - 1));
-    const int py = (tile / a.TX) * kTile + (tid >> 4);
+    const int tx0 = (tile % a.TX) * kTile, ty0 = (tile / a.TX) * kTile;
+    int lx, ly;
+    tile_pixel(tid, lx, ly);
+    const int px = tx0 + lx, py = ty0 + ly;
     const bool inside = px < a.W && py < a.H;
     const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
     const uint2 range = a.ranges[item];
@@ -65,7 +69,6 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
     const uint32_t maxlast = min(s_maxlast, range.y - range.x);
     // suffix colour / depth behind the current entry (background at the end)
     float Sr = a.bg0, Sg = a.bg1, Sb = a.bg2, Sd = 0.0f;
-    const int lane = tid & 63;
 
     // batches [lo, hi) of list positions, from the back
     for (int64_t hi = (int64_t)maxlast; hi > 0; hi -= kBwdBatch) {
@@ -75,31 +78,35 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
             const uint32_t g = a.vals[range.x + (uint32_t)lo + tid];
             const float4 q0 = a.rec[3 * (size_t)g], q1 = a.rec[3 * (size_t)g + 1], q2 = a.rec[3 * (size_t)g + 2];
             const Entry e = make_entry(q0, q1, q2);
-            s_u[tid] = e.u;
-            s_v[tid] = e.v;
-            s_a[tid] = e.a;
-            s_b[tid] = e.b;
-            s_c[tid] = e.c;
-            s_o[tid] = e.o;
-            s_z[tid] = e.z;
-            s_r[tid] = e.r;
-            s_g[tid] = e.g;
-            s_bl[tid] = e.bl;
-            s_A[tid] = q1.x;
-            s_B[tid] = q1.y;
-            s_C[tid] = q1.z;
-            s_gid[tid] = g;
+            s_e0[tid] = make_float4(e.u, e.v, e.a, e.b);
+            s_e1[tid] = make_float4(e.c, e.o, e.z, e.r);
+            s_e2[tid] = make_float4(e.g, e.bl, __uint_as_float(g), 0.0f);
+            s_q[tid] = make_float4(q1.x, q1.y, q1.z, 0.0f);
+            s_mask[tid] = (uint8_t)entry_quadrant_mask(q0.x, q0.y, q1.x, q1.y, q1.z, q1.w, a.alpha_min, (float)tx0,
+                                                       (float)ty0);
         }
         __syncthreads();
-        for (int k = nb - 1; k >= 0; --k) {
-            const uint32_t pos = (uint32_t)(lo + k);  // list position of this entry
+        int cnt = 0;
+#pragma unroll
+        for (int c = 0; c < kBwdBatch / 64; ++c) {
+            const int j = c * 64 + lane;
+            const bool hit = j < nb && ((s_mask[j] >> wave) & 1u);
+            const uint64_t bal = __ballot(hit);
+            if (hit) s_list[wave][cnt + __popcll(bal & lt_mask)] = (uint8_t)j;
+            cnt += __popcll(bal);
+        }
+        __builtin_amdgcn_wave_barrier();
+        for (int q = cnt - 1; q >= 0; --q) {
+            const int k = s_list[wave][q];
+            const uint32_t pos = (uint32_t)(lo + k);  // list position of this entry (< maxlast <= list length)
             float gu = 0.f, gv = 0.f, gA = 0.f, gB = 0.f, gC = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gb = 0.f, gz = 0.f;
             bool contrib = false;
-            if (pos < last) {  // pos < maxlast <= list length
-                const float dx = fx - s_u[k], dy = fy - s_v[k];
-                const float p2 = entry_power2(s_a[k], s_b[k], s_c[k], dx, dy);
+            const float4 e0 = s_e0[k], e1 = s_e1[k], e2 = s_e2[k];
+            if (pos < last) {
+                const float dx = fx - e0.x, dy = fy - e0.y;
+                const float p2 = entry_power2(e0.z, e0.w, e1.x, dx, dy);
                 const float G = exp2f(p2);
-                const float oG = s_o[k] * G;
+                const float oG = e1.y * G;
                 const float al = fminf(a.alpha_max, oG);
                 if (!(al < a.alpha_min)) {
                     contrib = true;
@@ -110,23 +117,24 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
                     gg = dG * w;
                     gb = dB * w;
                     gz = dD * w;
-                    const float dal = T * (dR * (s_r[k] - Sr) + dG * (s_g[k] - Sg) + dB * (s_bl[k] - Sb) +
-                                           dD * (s_z[k] - Sd)) +
+                    const float dal = T * (dR * (e1.w - Sr) + dG * (e2.x - Sg) + dB * (e2.y - Sb) +
+                                           dD * (e1.z - Sd)) +
                                       dA * Tfin / one_m;
                     if (!(oG > a.alpha_max)) {
+                        const float4 cq = s_q[k];
                         go = dal * G;
                         // dL/dP with P the natural-log exponent (dG/dP = G)
-                        const float dP = dal * s_o[k] * G;
-                        gu = dP * (s_A[k] * dx + s_B[k] * dy);
-                        gv = dP * (s_B[k] * dx + s_C[k] * dy);
+                        const float dP = dal * e1.y * G;
+                        gu = dP * (cq.x * dx + cq.y * dy);
+                        gv = dP * (cq.y * dx + cq.z * dy);
                         gA = -0.5f * dP * dx * dx;
                         gB = -dP * dx * dy;
                         gC = -0.5f * dP * dy * dy;
                     }
-                    Sr = al * s_r[k] + one_m * Sr;
-                    Sg = al * s_g[k] + one_m * Sg;
-                    Sb = al * s_bl[k] + one_m * Sb;
-                    Sd = al * s_z[k] + one_m * Sd;
+                    Sr = al * e1.w + one_m * Sr;
+                    Sg = al * e2.x + one_m * Sg;
+                    Sb = al * e2.y + one_m * Sb;
+                    Sd = al * e1.z + one_m * Sd;
                 }
             }
             if (__ballot(contrib) == 0ull) continue;
@@ -141,7 +149,7 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
             gb = wave_sum(gb);
             gz = wave_sum(gz);
             if (lane == 0) {
-                float *dst = a.g2d + (size_t)s_gid[k] * kG2D;
+                float *dst = a.g2d + (size_t)__float_as_uint(e2.z) * kG2D;
                 atomicAdd(dst + kGU, gu);
                 atomicAdd(dst + kGV, gv);
                 atomicAdd(dst + kGA, gA);

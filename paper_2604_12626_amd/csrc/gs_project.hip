@@ -55,6 +55,10 @@ __global__ void __launch_bounds__(256) project_kernel(const ProjectArgs a) {
         cov_from_rot_scale(rot.R, s, S);
     }
     const float opac = a.seg.opacity[i];
+    if (!isfinite(opac)) {  // non-finite input is culled, never rendered
+        for (int vi = 0; vi < a.nv; ++vi) a.tiles_touched[a.base[vi] + i] = 0u;
+        return;
+    }
 
     float sh[3 * K];
     bool have_sh = false;

@@ -245,7 +245,7 @@ def avatar_pose(rng, sigma=0.3):
 # --------------------------------------------------------------------------
 # projected-record stand-ins (inputs of the binning and compositing calls)
 # --------------------------------------------------------------------------
-def synthetic_records(rng, counts, W, H, tie_frac=0.05, vis_frac=0.9, r_median=8.0):
+def synthetic_records(rng, counts, W, H, tie_frac=0.05, vis_frac=0.9, r_median=8.0, aniso_sigma=0.7):
     """FP32 projected records [m,12] (u, v, depth, radius-bits, A, B, C,
     opacity, r, g, b, view-bits) for views with `counts[v]` instances each,
     plus a visibility mask.  u, v uniform over the image plus a margin;
@@ -263,7 +263,7 @@ def synthetic_records(rng, counts, W, H, tie_frac=0.05, vis_frac=0.9, r_median=8
     src = rng.integers(0, m, m)
     z[tie] = z[src[tie]]
     s1 = np.exp(rng.normal(math.log(r_median / 3.0), 0.5, m))
-    s2 = s1 * np.exp(-np.abs(rng.normal(0.0, 0.7, m)))
+    s2 = s1 * np.exp(-np.abs(rng.normal(0.0, aniso_sigma, m)))
     th = rng.uniform(0.0, math.pi, m)
     c, s = np.cos(th), np.sin(th)
     a = c * c * s1 * s1 + s * s * s2 * s2 + 0.3

@@ -140,18 +140,19 @@ def test_bin_sort_bit_exact(dev, orc, name, counts, W, H):
 
 
 COMPOSITE_CASES = [
-    ("1view_96x80_4k", [4000], 96, 80, 8.0),
-    ("2views_256x160_35k", [20000, 15000], 256, 160, 6.0),
-    ("1view_64x64_big_radii", [600], 64, 64, 30.0),
+    ("1view_96x80_4k", [4000], 96, 80, 8.0, 0.7),
+    ("2views_256x160_35k", [20000, 15000], 256, 160, 6.0, 0.7),
+    ("1view_64x64_big_radii", [600], 64, 64, 30.0, 0.7),
+    ("1view_128x96_needles", [3000], 128, 96, 10.0, 1.5),
 ]
 
 
-@pytest.mark.parametrize("name,counts,W,H,rmed", COMPOSITE_CASES, ids=[c[0] for c in COMPOSITE_CASES])
-def test_composite_parity(dev, orc, name, counts, W, H, rmed):
+@pytest.mark.parametrize("name,counts,W,H,rmed,aniso", COMPOSITE_CASES, ids=[c[0] for c in COMPOSITE_CASES])
+def test_composite_parity(dev, orc, name, counts, W, H, rmed, aniso):
     import torch
     from paper_2604_12626_amd import binding as B
     rng = np.random.default_rng(zlib.crc32(name.encode()))
-    rec, vis = synth.synthetic_records(rng, counts, W, H, r_median=rmed)
+    rec, vis = synth.synthetic_records(rng, counts, W, H, r_median=rmed, aniso_sigma=aniso)
     V = len(counts)
     tt_o, keys_o, vals_o, ranges_o, K = orc.bin_records(rec, vis, W, H, V)
     say("composite:", name, "K", K)
