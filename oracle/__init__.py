@@ -67,7 +67,7 @@ def _load():
     lib.or_bin.restype = i64
     lib.or_composite.argtypes = [i32, P, P, P, P, P, P, P]
     lib.or_render_view.argtypes = [i64, P, P, P, P, P, P, P]
-    lib.or_backward_2d.argtypes = [i64, P, P, P, P, P, P]
+    lib.or_backward_2d.argtypes = [i64, P, P, P, P, P, P, P]
     lib.or_backward_3d.argtypes = [i64, i32, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P]
     lib.or_lbs.argtypes = [i64, P, P, P, P, P, P, i32, P, P]
     lib.or_lbs_backward.argtypes = [i64, P, P, P, P, P, P, i32, P, P, P, P, P]
@@ -250,7 +250,8 @@ def backward(g, cams, prm, d_rgb, d_depth, d_alpha):
 
     d_rgb [V,H,W,3], d_depth [V,H,W], d_alpha [V,H,W].  Returns a dict of
     double gradients with the input layouts (means, log_scales, quats, opacity,
-    sh, cov6 when present)."""
+    sh, cov6 when present) plus "ambiguous" [n] (uint8): Gaussians whose
+    gradient depends on a near-threshold decision (see or_backward_2d)."""
     lib = _load()
     if isinstance(g, (list, tuple)):
         g = concat_segments(g)
@@ -263,7 +264,8 @@ def backward(g, cams, prm, d_rgb, d_depth, d_alpha):
     use = None if use is None else np.ascontiguousarray(use, dtype=np.uint8)
     opac, sh = _f32(g["opacity"]), _f32(g["sh"])
     out = {"means": np.zeros((n, 3)), "log_scales": np.zeros((n, 3)), "quats": np.zeros((n, 4)),
-           "opacity": np.zeros(n), "sh": np.zeros((n, K, 3)), "cov6": np.zeros((n, 6))}
+           "opacity": np.zeros(n), "sh": np.zeros((n, K, 3)), "cov6": np.zeros((n, 6)),
+           "ambiguous": np.zeros(n, np.uint8)}
     cams = np.asarray(cams, dtype=np.float32).reshape(-1, 16)
     for v in range(len(cams)):
         cam = cam_array(cams[v])
@@ -274,7 +276,9 @@ def backward(g, cams, prm, d_rgb, d_depth, d_alpha):
         dr = _f32(d_rgb[v])
         dd = _f32(d_depth[v])
         da = _f32(d_alpha[v])
-        lib.or_backward_2d(n, _p(proj), _p(prm), _p(dr), _p(dd), _p(da), _p(g2d))
+        amb = np.zeros(n, np.uint8)
+        lib.or_backward_2d(n, _p(proj), _p(prm), _p(dr), _p(dd), _p(da), _p(g2d), _p(amb))
+        out["ambiguous"] |= amb
         lib.or_backward_3d(n, D, _p(means), _p(lsc), _p(quats), _p(cov6), _p(use), _p(opac), _p(sh), _p(cam), _p(prm),
                            _p(g2d), _p(out["means"]), _p(out["log_scales"]), _p(out["quats"]), _p(out["opacity"]),
                            _p(out["sh"]), _p(out["cov6"]))
@@ -287,7 +291,7 @@ def backward_2d(proj, prm, d_rgb, d_depth, d_alpha):
     n = len(proj)
     g2d = np.zeros((n, 10))
     lib.or_backward_2d(n, _p(np.ascontiguousarray(proj)), _p(prm), _p(_f32(d_rgb)), _p(_f32(d_depth)),
-                       _p(_f32(d_alpha)), _p(g2d))
+                       _p(_f32(d_alpha)), _p(g2d), None)
     return g2d
 
 

@@ -941,28 +941,12 @@ static void build_lists(const oprm *p, int64_t n, const double *proj, int64_t **
     *list_idx = idx;
 }
 
-/* Full FP64 forward render of one view from the oracle's own projection
- * (proj: the output of or_project for the same view).  Also flags pixels
- * whose result depends on a decision inside its margin that the compositing
- * enumeration does not cover: a Gaussian whose rect or visibility is
- * ambiguous and whose alpha at the pixel reaches the skip threshold in a
- * tile that only some alternatives cover (bit 0), or two entries of the
- * pixel's list with depths within the tie margin that both reach the skip
- * threshold before the pixel stops (bit 1).
- * img [H][W][10]; ncand [H][W]; flags [H][W]; cands optional [H][W][MAXC][10];
- * pairs_out (nullable): number of (pixel, entry) evaluations of the primary
- * path before its stop. */
-void or_render_view(int64_t n, const double *proj, const double *prm, double *img, int32_t *ncand, uint8_t *flags,
-                    double *cands, int64_t *pairs_out)
+/* Pixels where a Gaussian with an ambiguous rect or visibility reaches the
+ * skip threshold (within its margin) in a tile that only some of its
+ * alternative rects cover: bit 0 of flags. */
+static void rect_flags(const oprm *pp, int64_t n, const double *proj, uint8_t *flags)
 {
-    const oprm p = unpack_prm(prm);
-    const int TX = (p.W + p.tile - 1) / p.tile, TY = (p.H + p.tile - 1) / p.tile, T = TX * TY;
-    int64_t *lp, *li;
-    build_lists(&p, n, proj, &lp, &li);
-    memset(flags, 0, (size_t)p.H * p.W);
-    /* rect / visibility ambiguity: a pixel in a tile that some alternative
-     * rect covers and another does not, where the Gaussian's alpha reaches the
-     * skip threshold (within its margin) */
+    const oprm p = *pp;
     for (int64_t i = 0; i < n; ++i) {
         const double *r = proj + OR_PROJ_STRIDE * i;
         if (r[21] == 0.0) continue;
@@ -987,6 +971,28 @@ void or_render_view(int64_t n, const double *proj, const double *prm, double *im
                     }
             }
     }
+}
+
+/* Full FP64 forward render of one view from the oracle's own projection
+ * (proj: the output of or_project for the same view).  Also flags pixels
+ * whose result depends on a decision inside its margin that the compositing
+ * enumeration does not cover: a Gaussian whose rect or visibility is
+ * ambiguous and whose alpha at the pixel reaches the skip threshold in a
+ * tile that only some alternatives cover (bit 0), or two entries of the
+ * pixel's list with depths within the tie margin that both reach the skip
+ * threshold before the pixel stops (bit 1).
+ * img [H][W][10]; ncand [H][W]; flags [H][W]; cands optional [H][W][MAXC][10];
+ * pairs_out (nullable): number of (pixel, entry) evaluations of the primary
+ * path before its stop. */
+void or_render_view(int64_t n, const double *proj, const double *prm, double *img, int32_t *ncand, uint8_t *flags,
+                    double *cands, int64_t *pairs_out)
+{
+    const oprm p = unpack_prm(prm);
+    const int TX = (p.W + p.tile - 1) / p.tile, TY = (p.H + p.tile - 1) / p.tile, T = TX * TY;
+    int64_t *lp, *li;
+    build_lists(&p, n, proj, &lp, &li);
+    memset(flags, 0, (size_t)p.H * p.W);
+    rect_flags(&p, n, proj, flags);
     int64_t pairs = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(+ : pairs)
     for (int t = 0; t < T; ++t) {
@@ -1055,14 +1061,20 @@ static void atomic_add(double *p, double v)
 }
 
 /* Backward of one view from the oracle's own forward (primary decisions held
- * fixed).  g2d: [n][10] accumulated (u, v, A, B, C, opacity, r, g, b, z). */
+ * fixed).  g2d: [n][10] accumulated (u, v, A, B, C, opacity, r, g, b, z).
+ * amb_g (nullable, [n]): set to 1 for every Gaussian that reaches the skip
+ * threshold at a pixel whose compositing holds a decision inside its margin,
+ * a depth near-tie or a rect ambiguity -- its gradient depends on which side
+ * an FP32 implementation takes. */
 void or_backward_2d(int64_t n, const double *proj, const double *prm, const float *d_rgb, const float *d_depth,
-                    const float *d_alpha, double *g2d)
+                    const float *d_alpha, double *g2d, uint8_t *amb_g)
 {
     const oprm p = unpack_prm(prm);
     const int TX = (p.W + p.tile - 1) / p.tile, TY = (p.H + p.tile - 1) / p.tile, T = TX * TY;
     int64_t *lp, *li;
     build_lists(&p, n, proj, &lp, &li);
+    uint8_t *pflags = calloc((size_t)p.H * p.W, 1);
+    rect_flags(&p, n, proj, pflags);
 #pragma omp parallel for schedule(dynamic, 1)
     for (int t = 0; t < T; ++t) {
         const int len = (int)(lp[t + 1] - lp[t]);
@@ -1073,9 +1085,12 @@ void or_backward_2d(int64_t n, const double *proj, const double *prm, const floa
                *ccl = cdy + (len + 1);
         for (int py = ty * p.tile; py < (ty + 1) * p.tile && py < p.H; ++py)
             for (int px = tx * p.tile; px < (tx + 1) * p.tile && px < p.W; ++px) {
-                /* forward, recording composited entries */
-                double Tcur = 1.0;
-                int nc = 0;
+                /* forward, recording composited entries; a decision inside its
+                 * margin, a depth near-tie or a rect ambiguity at this pixel
+                 * makes every entry that reaches the skip threshold here
+                 * ambiguous (its gradient depends on the branch taken) */
+                double Tcur = 1.0, zlast = -1.0;
+                int nc = 0, amb = pflags[(size_t)py * p.W + px] != 0, jend = len;
                 for (int j = 0; j < len; ++j) {
                     const double *r = proj + OR_PROJ_STRIDE * li[lp[t] + j];
                     const double ddx = px + 0.5 - r[1], ddy = py + 0.5 - r[2];
@@ -1088,9 +1103,18 @@ void or_backward_2d(int64_t n, const double *proj, const double *prm, const floa
                         a = p.alpha_max;
                         cl = 1;
                     }
+                    if (fabs(a - p.alpha_min) <= p.d_skip * p.alpha_min) amb = 1;
+                    if (a >= p.alpha_min * (1.0 - p.d_skip)) {
+                        if (zlast > 0.0 && fabs(r[3] - zlast) <= p.d_tie * (r[3] > zlast ? r[3] : zlast)) amb = 1;
+                        zlast = r[3];
+                    }
                     if (a < p.alpha_min) continue;
                     const double Tn = Tcur * (1.0 - a);
-                    if (Tn < p.t_min) break;
+                    if (fabs(Tn - p.t_min) <= p.d_stop * p.t_min) amb = 1;
+                    if (Tn < p.t_min) {
+                        jend = j + 1;
+                        break;
+                    }
                     cj[nc] = j;
                     ca[nc] = a;
                     cT[nc] = Tcur;
@@ -1100,6 +1124,15 @@ void or_backward_2d(int64_t n, const double *proj, const double *prm, const floa
                     ccl[nc] = cl;
                     ++nc;
                     Tcur = Tn;
+                }
+                if (amb && amb_g) {
+                    for (int j = 0; j < jend; ++j) {
+                        const double *r = proj + OR_PROJ_STRIDE * li[lp[t] + j];
+                        const double ddx = px + 0.5 - r[1], ddy = py + 0.5 - r[2];
+                        double P = -0.5 * (r[4] * ddx * ddx + r[6] * ddy * ddy) - r[5] * ddx * ddy;
+                        if (P > 0.0) P = 0.0;
+                        if (r[7] * exp(P) >= p.alpha_min * (1.0 - p.d_skip)) amb_g[li[lp[t] + j]] = 1;
+                    }
                 }
                 const size_t pix = (size_t)py * p.W + px;
                 const double dC[3] = {d_rgb[3 * pix], d_rgb[3 * pix + 1], d_rgb[3 * pix + 2]};
@@ -1135,6 +1168,7 @@ void or_backward_2d(int64_t n, const double *proj, const double *prm, const floa
         free(cj);
         free(ca);
     }
+    free(pflags);
     free(lp);
     free(li);
 }
