@@ -308,7 +308,7 @@ gs_status gs_bin_sort(const gs_projected *proj, int32_t n_views, const gs_params
         return fail(GS_ERR_WORKSPACE_TOO_SMALL, "workspace %zu < %zu bytes", ws_bytes, plan.total);
     hipError_t e = gs::run_bin_sort(plan, proj->tiles_touched, reinterpret_cast<const float4 *>(proj->rec),
                                     tiles_x(p), tiles_y(p), static_cast<char *>(ws), keys, vals, tile_ranges,
-                                    d_num_instances, d_overflow, (hipStream_t)stream);
+                                    d_num_instances, d_overflow, cu_count(), (hipStream_t)stream);
     return e == hipSuccess ? GS_OK : hip_fail(e, "gs_bin_sort");
 }
 

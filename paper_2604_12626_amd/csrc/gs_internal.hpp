@@ -105,7 +105,7 @@ hipError_t launch_project(const ProjectArgs &a, hipStream_t s);
 SortPlan make_sort_plan(int64_t n, int64_t capacity, int64_t n_tiles_total);
 hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec, int TX, int TY, char *ws,
                         uint64_t *keys, uint32_t *vals, uint32_t *ranges, int64_t *d_num, int32_t *d_overflow,
-                        hipStream_t s);
+                        int n_cu, hipStream_t s);
 hipError_t launch_composite(const CompositeArgs &a, int grid, hipStream_t s);
 hipError_t launch_backward_tiles(const BackwardTileArgs &a, hipStream_t s);
 hipError_t launch_backward_project(const BackwardProjectArgs &a, hipStream_t s);

@@ -6,9 +6,9 @@
 // wave64, 16 keys per lane).  Ranks inside a wave come from eight ballots per
 // key (the lanes holding the same digit), so ranking is stable: stripes are
 // processed in index order and lanes inside a stripe are in index order.
-// Partitions are numbered by an atomic ticket in launch order, so a
-// workgroup only ever waits for partitions that already run (forward
-// progress).  Each partition publishes per-digit counts in one 32-bit word
+// A persistent grid takes partitions by an atomic ticket, so a workgroup
+// only ever waits for partitions that a running workgroup already holds
+// (forward progress); the grid is sized to the machine, not the capacity.  Each partition publishes per-digit counts in one 32-bit word
 // (2 flag bits + 30 count bits) with agent-scope atomics, because the eight
 // XCDs have private L2s; a waiting lane sleeps between polls.  The scatter is
 // staged through LDS so that each digit's run is written contiguously.
@@ -227,6 +227,8 @@ __global__ void __launch_bounds__(kSortBlock) onesweep_kernel(const uint64_t *__
     __shared__ uint32_t s_vals[kSortPart];
 
     const int64_t K = sort_count(d_num, capacity);
+  // persistent: take partitions in ticket order until none is left
+  while (true) {
     if (threadIdx.x == 0) s_part = atomicAdd(ticket, 1u);
     for (int k = threadIdx.x; k < 4 * kBins; k += kSortBlock) (&s_wh[0][0])[k] = 0u;
     __syncthreads();
@@ -322,6 +324,8 @@ __global__ void __launch_bounds__(kSortBlock) onesweep_kernel(const uint64_t *__
         keys_out[dst] = kk;
         vals_out[dst] = s_vals[q];
     }
+    __syncthreads();  // LDS is reused by the next partition
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -329,15 +333,15 @@ __global__ void __launch_bounds__(kSortBlock) onesweep_kernel(const uint64_t *__
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) ranges_kernel(const uint64_t *keys, const int64_t *d_num, int64_t capacity,
                                                      const int32_t *d_overflow, uint32_t *ranges,
-                                                     uint64_t n_tiles_total) {
+                                                     uint64_t n_tiles_total, int64_t stride) {
     if (*d_overflow) return;
     const int64_t K = sort_count(d_num, capacity);
-    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (k >= K) return;
-    const uint64_t t = keys[k] >> 32;
-    if (t >= n_tiles_total) return;
-    if (k == 0 || (keys[k - 1] >> 32) != t) ranges[2 * t] = (uint32_t)k;
-    if (k == K - 1 || (keys[k + 1] >> 32) != t) ranges[2 * t + 1] = (uint32_t)(k + 1);
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < K; k += stride) {
+        const uint64_t t = keys[k] >> 32;
+        if (t >= n_tiles_total) continue;
+        if (k == 0 || (keys[k - 1] >> 32) != t) ranges[2 * t] = (uint32_t)k;
+        if (k == K - 1 || (keys[k + 1] >> 32) != t) ranges[2 * t + 1] = (uint32_t)(k + 1);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -382,7 +386,7 @@ SortPlan make_sort_plan(int64_t n, int64_t capacity, int64_t n_tiles_total) {
 
 hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec, int TX, int TY, char *ws,
                         uint64_t *keys, uint32_t *vals, uint32_t *ranges, int64_t *d_num, int32_t *d_overflow,
-                        hipStream_t s) {
+                        int n_cu, hipStream_t s) {
     hipError_t e;
     uint32_t *offsets = reinterpret_cast<uint32_t *>(ws + P.off_offsets);
     uint64_t *part = reinterpret_cast<uint64_t *>(ws + P.off_part);
@@ -422,16 +426,20 @@ hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec
     }
     // 3. onesweep passes over the significant bits
     {
-        int64_t hb = (P.capacity + 255) / 256;
-        if (hb > 2048) hb = 2048;
+        // few blocks, many keys each: every block adds its LDS histogram once
+        int64_t hb = (P.capacity + 4095) / 4096;
+        if (hb > n_cu / 2) hb = n_cu / 2;
         if (hb < 1) hb = 1;
         if ((e = launch_kernel(sort_hist_kernel, dim3((unsigned)hb), dim3(256), s, k_a, d_num, P.capacity, P.passes, 0,
                                hist, hb * 256)) != hipSuccess)
             return e;
         if ((e = launch_kernel(sort_hist_scan_kernel, dim3(1), dim3(kBins), s, hist, P.passes)) != hipSuccess) return e;
     }
+    // persistent grid: two 55-KB workgroups fit a CU
+    int64_t sg = (int64_t)n_cu * 2;
+    if (sg > P.sort_parts) sg = P.sort_parts;
     for (int p = 0; p < P.passes; ++p) {
-        if ((e = launch_kernel(onesweep_kernel, dim3((unsigned)P.sort_parts), dim3(kSortBlock), s, k_a, v_a, k_b, v_b,
+        if ((e = launch_kernel(onesweep_kernel, dim3((unsigned)sg), dim3(kSortBlock), s, k_a, v_a, k_b, v_b,
                                d_num, P.capacity, p * kRadixBits, hist + p * kBins,
                                status + (size_t)p * P.sort_parts * kBins, ticket + p * 64)) != hipSuccess)
             return e;
@@ -445,10 +453,10 @@ hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec
     // k_a now holds the sorted keys (== keys)
     // 4. ranges
     {
-        const int64_t blocks = (P.capacity + 255) / 256;
-        if (blocks > 0)
-            return launch_kernel(ranges_kernel, dim3((unsigned)blocks), dim3(256), s, k_a, d_num, P.capacity, d_overflow,
-                                 ranges, (uint64_t)P.n_tiles_total);
+        int64_t blocks = (P.capacity + 255) / 256;
+        if (blocks > (int64_t)n_cu * 4) blocks = (int64_t)n_cu * 4;
+        return launch_kernel(ranges_kernel, dim3((unsigned)blocks), dim3(256), s, k_a, d_num, P.capacity, d_overflow,
+                             ranges, (uint64_t)P.n_tiles_total, blocks * 256);
     }
     return hipSuccess;
 }
