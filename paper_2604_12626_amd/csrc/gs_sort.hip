@@ -2,16 +2,19 @@
 // onesweep LSD radix sort (8-bit digits, decoupled look-back across
 // partitions) and per-tile ranges.
 //
-// Onesweep on CDNA4: a partition of 4096 keys per 256-thread workgroup (four
-// wave64, 16 keys per lane).  Ranks inside a wave come from eight ballots per
+// Onesweep on CDNA4: a partition of 8192 keys per 512-thread workgroup (eight
+// wave64, 16 keys per lane, ~107 KB of LDS of the 160 KB a CU offers).  Ranks inside a wave come from eight ballots per
 // key (the lanes holding the same digit), so ranking is stable: stripes are
 // processed in index order and lanes inside a stripe are in index order.
 // A persistent grid takes partitions by an atomic ticket, so a workgroup
 // only ever waits for partitions that a running workgroup already holds
 // (forward progress); the grid is sized to the machine, not the capacity.  Each partition publishes per-digit counts in one 32-bit word
 // (2 flag bits + 30 count bits) with agent-scope atomics, because the eight
-// XCDs have private L2s; a waiting lane sleeps between polls.  The scatter is
-// staged through LDS so that each digit's run is written contiguously.
+// XCDs have private L2s.  The look-back reads 16 predecessor statuses per
+// round trip (all partitions of a pass run at once on this size of problem,
+// so a one-at-a-time walk would serialise); a lane that meets an unpublished
+// predecessor sleeps briefly and polls again.  The scatter is staged through
+// LDS so that each digit's run is written contiguously.
 #include "gs_internal.hpp"
 
 namespace gs {
@@ -20,9 +23,12 @@ constexpr int kScanBlock = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanBlock * kScanItems;  // 4096 instances per block
 
-constexpr int kSortBlock = 256;
+constexpr int kSortBlock = 512;
+constexpr int kSortWaves = kSortBlock / 64;
 constexpr int kSortItems = 16;
-constexpr int kSortPart = kSortBlock * kSortItems;  // 4096 keys per partition
+constexpr int kSortPart = kSortBlock * kSortItems;  // 8192 keys per partition
+constexpr int kLookback = 16;                       // predecessor statuses read per round trip
+constexpr int kEmitLane = 32;                       // larger rects are emitted by the whole wave
 constexpr int kRadixBits = 8;
 constexpr int kBins = 1 << kRadixBits;
 constexpr int kMaxPasses = 8;
@@ -138,22 +144,51 @@ __global__ void __launch_bounds__(256) emit_kernel(const uint32_t *tt, const uin
                                                    int64_t n, int TX, int TY, int64_t capacity, uint64_t *keys,
                                                    uint32_t *vals) {
     const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (g >= n) return;
-    if (tt[g] == 0u) return;
-    int64_t k = offsets[g];
-    if (k >= capacity) return;
-    const float4 q0 = rec[3 * g];
-    const int view = __float_as_int(rec[3 * g + 2].w);
-    const Rect R = tile_rect(q0.x, q0.y, __float_as_int(q0.w), TX, TY);
-    const uint64_t depth_bits = (uint64_t)__float_as_uint(q0.z);
-    const uint64_t tbase = (uint64_t)view * (uint64_t)(TX * TY);
-    for (int ty = R.y0; ty < R.y1; ++ty)
-        for (int tx = R.x0; tx < R.x1; ++tx) {
-            if (k >= capacity) return;
-            keys[k] = ((tbase + (uint64_t)(ty * TX + tx)) << 32) | depth_bits;
-            vals[k] = (uint32_t)g;
-            ++k;
+    const int lane = threadIdx.x & 63;
+    const uint32_t t = (g < n) ? tt[g] : 0u;
+    const int64_t k0 = t ? (int64_t)offsets[g] : capacity;
+    const bool live = t && k0 < capacity;
+    Rect R = {0, 0, 0, 0};
+    uint64_t tbase = 0, depth_bits = 0;
+    if (live) {
+        const float4 q0 = rec[3 * g];
+        const int view = __float_as_int(rec[3 * g + 2].w);
+        R = tile_rect(q0.x, q0.y, __float_as_int(q0.w), TX, TY);
+        depth_bits = (uint64_t)__float_as_uint(q0.z);
+        tbase = (uint64_t)view * (uint64_t)(TX * TY);
+    }
+    if (live && t <= (uint32_t)kEmitLane) {
+        int64_t k = k0;
+        for (int ty = R.y0; ty < R.y1; ++ty)
+            for (int tx = R.x0; tx < R.x1; ++tx) {
+                if (k >= capacity) return;
+                keys[k] = ((tbase + (uint64_t)(ty * TX + tx)) << 32) | depth_bits;
+                vals[k] = (uint32_t)g;
+                ++k;
+            }
+    }
+    // rects of more than kEmitLane tiles: the wave emits them one at a time,
+    // 64 consecutive keys per step (row-major tile order as above)
+    uint64_t big = __ballot(live && t > (uint32_t)kEmitLane);
+    while (big) {
+        const int src = __ffsll((unsigned long long)big) - 1;
+        big &= big - 1;
+        const int x0 = __shfl(R.x0, src, 64), x1 = __shfl(R.x1, src, 64);
+        const int y0 = __shfl(R.y0, src, 64), y1 = __shfl(R.y1, src, 64);
+        const int64_t kb = __shfl((long long)k0, src, 64);
+        const uint64_t tb = (uint64_t)__shfl((unsigned long long)tbase, src, 64);
+        const uint64_t db = (uint64_t)__shfl((unsigned long long)depth_bits, src, 64);
+        const uint32_t gg = (uint32_t)__shfl((long long)g, src, 64);
+        const int w = x1 - x0;
+        const int total = w * (y1 - y0);
+        for (int j = lane; j < total; j += 64) {
+            const int64_t k = kb + j;
+            if (k >= capacity) break;
+            const int ty = y0 + j / w, tx = x0 + j % w;
+            keys[k] = ((tb + (uint64_t)(ty * TX + tx)) << 32) | db;
+            vals[k] = gg;
         }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -164,7 +199,10 @@ __device__ __forceinline__ int64_t sort_count(const int64_t *d_num, int64_t capa
     return k < capacity ? k : capacity;
 }
 
-// global digit histograms of all passes in one read of the keys
+// global digit histograms of all passes in one read of the keys; the lanes of
+// a wave holding the same digit are found with ballots and add once (the
+// depth-exponent byte falls in a handful of bins, so plain LDS atomics would
+// serialise)
 __global__ void __launch_bounds__(256) sort_hist_kernel(const uint64_t *keys, const int64_t *d_num, int64_t capacity,
                                                         int passes, int bit0, uint32_t *hist /*[passes][256]*/,
                                                         int64_t stride) {
@@ -172,9 +210,24 @@ __global__ void __launch_bounds__(256) sort_hist_kernel(const uint64_t *keys, co
     for (int k = threadIdx.x; k < passes * kBins; k += 256) s_h[k] = 0u;
     __syncthreads();
     const int64_t K = sort_count(d_num, capacity);
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < K; i += stride) {
-        const uint64_t key = keys[i];
-        for (int p = 0; p < passes; ++p) atomicAdd(&s_h[p * kBins + ((key >> (bit0 + p * kRadixBits)) & (kBins - 1))], 1u);
+    const int lane = threadIdx.x & 63;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int64_t base = (int64_t)blockIdx.x * 256; base < K; base += stride) {
+        const int64_t i = base + threadIdx.x;
+        const bool valid = i < K;
+        const uint64_t key = valid ? keys[i] : 0ull;
+        const uint64_t vmask = __ballot(valid);
+        for (int p = 0; p < passes; ++p) {
+            const uint32_t d = (uint32_t)(key >> (bit0 + p * kRadixBits)) & (kBins - 1);
+            uint64_t peers = vmask;
+#pragma unroll
+            for (int b = 0; b < kRadixBits; ++b) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t m = __ballot(bit);
+                peers &= bit ? m : ~m;
+            }
+            if (valid && (peers & lt_mask) == 0ull) atomicAdd(&s_h[p * kBins + d], (uint32_t)__popcll(peers));
+        }
     }
     __syncthreads();
     for (int k = threadIdx.x; k < passes * kBins; k += 256)
@@ -199,18 +252,6 @@ __global__ void __launch_bounds__(kBins) sort_hist_scan_kernel(uint32_t *hist, i
     }
 }
 
-__device__ __forceinline__ uint32_t lds_exclusive_scan_256(uint32_t v, uint32_t *s) {
-    s[threadIdx.x] = v;
-    __syncthreads();
-    for (int off = 1; off < kBins; off <<= 1) {
-        const uint32_t t = (threadIdx.x >= (unsigned)off) ? s[threadIdx.x - off] : 0u;
-        __syncthreads();
-        s[threadIdx.x] += t;
-        __syncthreads();
-    }
-    return s[threadIdx.x] - v;
-}
-
 __global__ void __launch_bounds__(kSortBlock) onesweep_kernel(const uint64_t *__restrict__ keys_in,
                                                               const uint32_t *__restrict__ vals_in,
                                                               uint64_t *__restrict__ keys_out,
@@ -219,113 +260,149 @@ __global__ void __launch_bounds__(kSortBlock) onesweep_kernel(const uint64_t *__
                                                               const uint32_t *digit_base /*[256]*/,
                                                               uint32_t *status /*[parts][256]*/, uint32_t *ticket) {
     __shared__ uint32_t s_part;
-    __shared__ uint32_t s_wh[4][kBins];      // per-wave digit counts -> prefix across waves
-    __shared__ uint32_t s_local[kBins];      // block-local exclusive digit start
-    __shared__ uint32_t s_glob[kBins];       // global start of the digit for this partition
+    __shared__ uint32_t s_wh[kSortWaves][kBins];  // per-wave digit counts -> prefix across waves
+    __shared__ uint32_t s_local[kBins];           // block-local exclusive digit start
+    __shared__ uint32_t s_glob[kBins];            // global start of the digit for this partition
     __shared__ uint32_t s_scan[kBins];
     __shared__ uint64_t s_keys[kSortPart];
     __shared__ uint32_t s_vals[kSortPart];
 
-    const int64_t K = sort_count(d_num, capacity);
-  // persistent: take partitions in ticket order until none is left
-  while (true) {
-    if (threadIdx.x == 0) s_part = atomicAdd(ticket, 1u);
-    for (int k = threadIdx.x; k < 4 * kBins; k += kSortBlock) (&s_wh[0][0])[k] = 0u;
-    __syncthreads();
-    const uint32_t part = s_part;
-    const int64_t start = (int64_t)part * kSortPart;
-    if (start >= K) return;  // uniform across the workgroup
-
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    uint64_t key[kSortItems];
-    uint32_t val[kSortItems];
-    uint32_t rank[kSortItems];
-    uint32_t dig[kSortItems];
+    const int64_t K = sort_count(d_num, capacity);
+    // persistent: take partitions in ticket order until none is left
+    while (true) {
+        if (tid == 0) s_part = atomicAdd(ticket, 1u);
+        for (int k = tid; k < kSortWaves * kBins; k += kSortBlock) (&s_wh[0][0])[k] = 0u;
+        __syncthreads();
+        const uint32_t part = s_part;
+        const int64_t start = (int64_t)part * kSortPart;
+        if (start >= K) return;  // uniform across the workgroup
+
+        uint64_t key[kSortItems];
+        uint32_t val[kSortItems];
+        uint32_t rank[kSortItems];
+        uint32_t dig[kSortItems];
 #pragma unroll
-    for (int j = 0; j < kSortItems; ++j) {
-        const int64_t idx = start + (int64_t)wave * (kSortItems * 64) + j * 64 + lane;
-        const bool valid = idx < K;
-        key[j] = valid ? keys_in[idx] : ~0ull;
-        val[j] = valid ? vals_in[idx] : 0u;
-        const uint32_t d = (uint32_t)(key[j] >> shift) & (kBins - 1);
-        dig[j] = valid ? d : 0xFFFFFFFFu;
-        uint64_t peers = __ballot(valid);
+        for (int j = 0; j < kSortItems; ++j) {
+            const int64_t idx = start + (int64_t)wave * (kSortItems * 64) + j * 64 + lane;
+            const bool valid = idx < K;
+            key[j] = valid ? keys_in[idx] : ~0ull;
+            val[j] = valid ? vals_in[idx] : 0u;
+            const uint32_t d = (uint32_t)(key[j] >> shift) & (kBins - 1);
+            dig[j] = valid ? d : 0xFFFFFFFFu;
+            uint64_t peers = __ballot(valid);
 #pragma unroll
-        for (int b = 0; b < kRadixBits; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t m = __ballot(bit);
-            peers &= bit ? m : ~m;
-        }
-        uint32_t r = 0;
-        if (valid) {
-            const uint32_t below = __popcll(peers & lt_mask);
-            const uint32_t prev = s_wh[wave][d];
-            r = prev + below;
-            __builtin_amdgcn_wave_barrier();
-            if (below == 0) s_wh[wave][d] = prev + (uint32_t)__popcll(peers);
-        } else {
-            __builtin_amdgcn_wave_barrier();
-        }
-        __builtin_amdgcn_wave_barrier();
-        rank[j] = r;
-    }
-    __syncthreads();
-    // per digit (thread = digit): prefix across waves and block total
-    const uint32_t d = threadIdx.x;
-    const uint32_t c0 = s_wh[0][d], c1 = s_wh[1][d], c2 = s_wh[2][d], c3 = s_wh[3][d];
-    const uint32_t total = c0 + c1 + c2 + c3;
-    s_wh[0][d] = 0u;
-    s_wh[1][d] = c0;
-    s_wh[2][d] = c0 + c1;
-    s_wh[3][d] = c0 + c1 + c2;
-    // decoupled look-back for this digit
-    uint32_t *st = status + (size_t)part * kBins + d;
-    uint32_t prefix = 0u;
-    if (part == 0) {
-        __hip_atomic_store(st, kFlagIncl | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-        __hip_atomic_store(st, kFlagAgg | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        int64_t p = (int64_t)part - 1;
-        while (true) {
-            const uint32_t w = __hip_atomic_load(status + (size_t)p * kBins + d, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
-            const uint32_t flag = w & ~kCountMask;
-            if (flag == 0u) {
-                __builtin_amdgcn_s_sleep(1);
-                continue;
+            for (int b = 0; b < kRadixBits; ++b) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t m = __ballot(bit);
+                peers &= bit ? m : ~m;
             }
-            prefix += w & kCountMask;
-            if (flag == kFlagIncl) break;
-            --p;
+            uint32_t r = 0;
+            if (valid) {
+                const uint32_t below = __popcll(peers & lt_mask);
+                const uint32_t prev = s_wh[wave][d];
+                r = prev + below;
+                __builtin_amdgcn_wave_barrier();
+                if (below == 0) s_wh[wave][d] = prev + (uint32_t)__popcll(peers);
+            } else {
+                __builtin_amdgcn_wave_barrier();
+            }
+            __builtin_amdgcn_wave_barrier();
+            rank[j] = r;
         }
-        __hip_atomic_store(st, kFlagIncl | (prefix + total), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    s_glob[d] = digit_base[d] + prefix;
-    const uint32_t local = lds_exclusive_scan_256(total, s_scan);
-    s_local[d] = local;
-    __syncthreads();
-    // stage into LDS in block-local sorted order
+        __syncthreads();
+        uint32_t total = 0;
+        if (tid < kBins) {
+            const uint32_t d = tid;
+            // prefix across waves (wave order = index order)
+            uint32_t run = 0;
 #pragma unroll
-    for (int j = 0; j < kSortItems; ++j) {
-        if (dig[j] != 0xFFFFFFFFu) {
-            const uint32_t pos = s_local[dig[j]] + s_wh[wave][dig[j]] + rank[j];
-            s_keys[pos] = key[j];
-            s_vals[pos] = val[j];
+            for (int w = 0; w < kSortWaves; ++w) {
+                const uint32_t c = s_wh[w][d];
+                s_wh[w][d] = run;
+                run += c;
+            }
+            total = run;
+            // decoupled look-back: publish the aggregate, then walk back over
+            // the predecessors kLookback at a time until an inclusive prefix
+            uint32_t *col = status + d;
+            uint32_t prefix = 0u;
+            if (part == 0) {
+                __hip_atomic_store(col, kFlagIncl | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                __hip_atomic_store(col + (size_t)part * kBins, kFlagAgg | total, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                int64_t p = (int64_t)part - 1;
+                while (true) {
+                    uint32_t w[kLookback];
+#pragma unroll
+                    for (int i = 0; i < kLookback; ++i)
+                        w[i] = (p - i >= 0) ? __hip_atomic_load(col + (size_t)(p - i) * kBins, __ATOMIC_RELAXED,
+                                                                __HIP_MEMORY_SCOPE_AGENT)
+                                            : kFlagIncl;  // never reached: partition 0 is inclusive
+                    bool stop = false, incl = false;
+                    int consumed = 0;
+#pragma unroll
+                    for (int i = 0; i < kLookback; ++i) {
+                        if (!stop) {
+                            const uint32_t flag = w[i] & ~kCountMask;
+                            if (flag == 0u) {
+                                stop = true;  // not published yet: poll again from here
+                            } else {
+                                prefix += w[i] & kCountMask;
+                                ++consumed;
+                                if (flag == kFlagIncl) {
+                                    incl = true;
+                                    stop = true;
+                                }
+                            }
+                        }
+                    }
+                    if (incl) break;
+                    p -= consumed;
+                    if (consumed < kLookback) __builtin_amdgcn_s_sleep(1);
+                }
+                __hip_atomic_store(col + (size_t)part * kBins, kFlagIncl | (prefix + total), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            }
+            s_glob[d] = digit_base[d] + prefix;
+            s_scan[d] = total;
         }
+        __syncthreads();
+        // block-local exclusive scan of the digit totals
+        for (int off = 1; off < kBins; off <<= 1) {
+            uint32_t t = 0u;
+            if (tid < kBins && tid >= off) t = s_scan[tid - off];
+            __syncthreads();
+            if (tid < kBins) s_scan[tid] += t;
+            __syncthreads();
+        }
+        if (tid < kBins) s_local[tid] = s_scan[tid] - total;
+        __syncthreads();
+        // stage into LDS in block-local sorted order
+#pragma unroll
+        for (int j = 0; j < kSortItems; ++j) {
+            if (dig[j] != 0xFFFFFFFFu) {
+                const uint32_t pos = s_local[dig[j]] + s_wh[wave][dig[j]] + rank[j];
+                s_keys[pos] = key[j];
+                s_vals[pos] = val[j];
+            }
+        }
+        __syncthreads();
+        // each digit's run leaves as one contiguous stretch
+        const int64_t nvalid64 = K - start;
+        const int nvalid = nvalid64 < kSortPart ? (int)nvalid64 : kSortPart;
+        for (int q = tid; q < nvalid; q += kSortBlock) {
+            const uint64_t kk = s_keys[q];
+            const uint32_t dd = (uint32_t)(kk >> shift) & (kBins - 1);
+            const uint32_t dst = s_glob[dd] + (uint32_t)q - s_local[dd];
+            keys_out[dst] = kk;
+            vals_out[dst] = s_vals[q];
+        }
+        __syncthreads();  // LDS is reused by the next partition
     }
-    __syncthreads();
-    const int64_t nvalid64 = K - start;
-    const int nvalid = nvalid64 < kSortPart ? (int)nvalid64 : kSortPart;
-    for (int q = threadIdx.x; q < nvalid; q += kSortBlock) {
-        const uint64_t kk = s_keys[q];
-        const uint32_t dd = (uint32_t)(kk >> shift) & (kBins - 1);
-        const uint32_t dst = s_glob[dd] + (uint32_t)q - s_local[dd];
-        keys_out[dst] = kk;
-        vals_out[dst] = s_vals[q];
-    }
-    __syncthreads();  // LDS is reused by the next partition
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -428,15 +505,15 @@ hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec
     {
         // few blocks, many keys each: every block adds its LDS histogram once
         int64_t hb = (P.capacity + 4095) / 4096;
-        if (hb > n_cu / 2) hb = n_cu / 2;
+        if (hb > n_cu) hb = n_cu;
         if (hb < 1) hb = 1;
         if ((e = launch_kernel(sort_hist_kernel, dim3((unsigned)hb), dim3(256), s, k_a, d_num, P.capacity, P.passes, 0,
                                hist, hb * 256)) != hipSuccess)
             return e;
         if ((e = launch_kernel(sort_hist_scan_kernel, dim3(1), dim3(kBins), s, hist, P.passes)) != hipSuccess) return e;
     }
-    // persistent grid: two 55-KB workgroups fit a CU
-    int64_t sg = (int64_t)n_cu * 2;
+    // persistent grid: one ~107-KB workgroup per CU
+    int64_t sg = (int64_t)n_cu;
     if (sg > P.sort_parts) sg = P.sort_parts;
     for (int p = 0; p < P.passes; ++p) {
         if ((e = launch_kernel(onesweep_kernel, dim3((unsigned)sg), dim3(kSortBlock), s, k_a, v_a, k_b, v_b,
