@@ -116,7 +116,7 @@ typedef struct gs_gaussians_grad {
 } gs_gaussians_grad;
 
 /* Projected instances (device arrays of n_instances).
- *  tiles_touched[g]: number of tiles of g's rect; 0 = culled.
+ *  tiles_touched[g]: number of tiles of g's rect; 0 = culled (16-byte aligned).
  *  rec[g] (12 floats, 16-byte aligned, written only when g is visible):
  *    [0] u  [1] v  [2] camera-space depth z  [3] radius (int32 bits)
  *    [4] A  [5] B  [6] C   (conic = inverse 2D covariance [[A,B],[B,C]])

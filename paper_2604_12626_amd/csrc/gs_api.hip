@@ -295,8 +295,9 @@ gs_status gs_bin_sort(const gs_projected *proj, int32_t n_views, const gs_params
     if (n_views < 1 || n_views > GS_MAX_VIEWS) return fail(GS_ERR_INVALID_ARGUMENT, "n_views=%d", n_views);
     if (capacity < 1) return fail(GS_ERR_INVALID_ARGUMENT, "capacity < 1");
     if (capacity > GS_MAX_CAPACITY) return fail(GS_ERR_UNSUPPORTED, "capacity above %lld", (long long)GS_MAX_CAPACITY);
-    if (proj->n_instances > 0 && (!proj->tiles_touched || !proj->rec || !aligned(proj->rec, 16)))
-        return fail(GS_ERR_INVALID_ARGUMENT, "proj arrays NULL or rec not 16-byte aligned");
+    if (proj->n_instances > 0 && (!proj->tiles_touched || !proj->rec || !aligned(proj->rec, 16) ||
+                                  !aligned(proj->tiles_touched, 16)))
+        return fail(GS_ERR_INVALID_ARGUMENT, "proj arrays NULL or rec/tiles_touched not 16-byte aligned");
     if (!keys || !vals || !tile_ranges || !d_num_instances || !d_overflow || !ws)
         return fail(GS_ERR_INVALID_ARGUMENT, "NULL output or workspace");
     if (!aligned(keys, 8) || !aligned(tile_ranges, 8) || !aligned(d_num_instances, 8) || !aligned(ws, 256))
@@ -355,8 +356,9 @@ gs_status gs_composite(const gs_projected *proj, const uint32_t *vals, const uin
     a.n_contrib = n_contrib;
     hipError_t e = gs::launch_fill_u32(a.counter, 0u, 1, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "gs_composite");
+    // persistent waves: 8 four-wave groups per CU, never more waves than quadrant items
     int64_t grid = (int64_t)cu_count() * 8;
-    if (grid > a.n_items) grid = a.n_items;
+    if (grid * 4 > a.n_items * 4) grid = a.n_items;
     e = gs::launch_composite(a, (int)grid, (hipStream_t)stream);
     return e == hipSuccess ? GS_OK : hip_fail(e, "gs_composite");
 }

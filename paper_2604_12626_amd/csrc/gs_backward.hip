@@ -1,7 +1,8 @@
 // gs_render_backward kernels.
 //
-// B1 (per tile, 256 threads = one per pixel, each wave an 8 x 8 quadrant):
-// walks the tile's list back to front from the last composited entry,
+// B1 (per tile, 256 threads = one per pixel, each wave an independent 8 x 8
+// quadrant with no workgroup barrier): walks the tile's list back to front
+// from the last composited entry of the quadrant, 64 entries at a time,
 // recomputing each alpha with exactly the forward's FP32 expression (so every
 // skip/stop/clamp decision repeats), recovering the transmittance by
 // T_i = T_{i+1} / (1 - alpha_i), and forming the screen-space adjoint of each
@@ -19,7 +20,6 @@ namespace gs {
 
 
 
-constexpr int kBwdBatch = 256;
 
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
@@ -28,22 +28,20 @@ __device__ __forceinline__ float wave_sum(float v) {
 }
 
 __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const BackwardTileArgs a) {
-    __shared__ float4 s_e0[kBwdBatch], s_e1[kBwdBatch], s_e2[kBwdBatch], s_q[kBwdBatch];
-    __shared__ uint8_t s_mask[kBwdBatch];
-    __shared__ uint8_t s_list[4][kBwdBatch];
-    __shared__ uint32_t s_maxlast;
-    const int tid = threadIdx.x;
-    const int wave = tid >> 6, lane = tid & 63;
+    __shared__ float4 s_e0[4][64], s_e1[4][64], s_e2[4][64], s_q[4][64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    float4 *e0s = s_e0[wave], *e1s = s_e1[wave], *e2s = s_e2[wave], *qs = s_q[wave];
+    // one workgroup per (view, tile); wave w owns the 8 x 8 quadrant w, one pixel per lane
     const int64_t item = blockIdx.x;
     const int view = (int)(item / a.T);
     const int tile = (int)(item - (int64_t)view * a.T);
-    const int tx0 = (tile % a.TX) * kTile, ty0 = (tile / a.TX) * kTile;
-    int lx, ly;
-    tile_pixel(tid, lx, ly);
-    const int px = tx0 + lx, py = ty0 + ly;
+    const int qx0 = (tile % a.TX) * kTile + ((wave & 1) << 3);
+    const int qy0 = (tile / a.TX) * kTile + ((wave >> 1) << 3);
+    const int px = qx0 + (lane & 7), py = qy0 + (lane >> 3);
     const bool inside = px < a.W && py < a.H;
     const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+    const float bx0 = (float)qx0 + 0.5f, by0 = (float)qy0 + 0.5f;
     const uint2 range = a.ranges[item];
 
     float T = 1.0f, Tfin = 1.0f;
@@ -62,50 +60,48 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
         if (a.d_depth) dD = a.d_depth[pix];
         if (a.d_alpha) dA = a.d_alpha[pix];
     }
-    if (tid == 0) s_maxlast = 0u;
-    __syncthreads();
-    if (last) atomicMax(&s_maxlast, last);
-    __syncthreads();
-    const uint32_t maxlast = min(s_maxlast, range.y - range.x);
+    uint32_t maxlast = last;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) maxlast = max(maxlast, (uint32_t)__shfl_xor((int)maxlast, off, 64));
+    maxlast = min(maxlast, range.y - range.x);
     // suffix colour / depth behind the current entry (background at the end)
     float Sr = a.bg0, Sg = a.bg1, Sb = a.bg2, Sd = 0.0f;
 
-    // batches [lo, hi) of list positions, from the back
-    for (int64_t hi = (int64_t)maxlast; hi > 0; hi -= kBwdBatch) {
-        const int64_t lo = hi - kBwdBatch > 0 ? hi - kBwdBatch : 0;
-        const int nb = (int)(hi - lo);
-        if (tid < nb) {
-            const uint32_t g = a.vals[range.x + (uint32_t)lo + tid];
-            const float4 q0 = a.rec[3 * (size_t)g], q1 = a.rec[3 * (size_t)g + 1], q2 = a.rec[3 * (size_t)g + 2];
-            const Entry e = make_entry(q0, q1, q2);
-            s_e0[tid] = make_float4(e.u, e.v, e.a, e.b);
-            s_e1[tid] = make_float4(e.c, e.o, e.z, e.r);
-            s_e2[tid] = make_float4(e.g, e.bl, __uint_as_float(g), 0.0f);
-            s_q[tid] = make_float4(q1.x, q1.y, q1.z, 0.0f);
-            s_mask[tid] = (uint8_t)entry_quadrant_mask(q0.x, q0.y, q1.x, q1.y, q1.z, q1.w, a.alpha_min, (float)tx0,
-                                                       (float)ty0);
+    // chunks [lo, hi) of list positions, from the back
+    for (int64_t hi = (int64_t)maxlast; hi > 0; hi -= 64) {
+        const int64_t lo = hi - 64 > 0 ? hi - 64 : 0;
+        const bool valid = lo + lane < hi;
+        bool hit = false;
+        float4 q0, q1, q2;
+        uint32_t g = 0;
+        if (valid) {
+            g = a.vals[range.x + (uint32_t)lo + lane];
+            q0 = a.rec[3 * (size_t)g];
+            q1 = a.rec[3 * (size_t)g + 1];
+            q2 = a.rec[3 * (size_t)g + 2];
+            hit = entry_reaches_box(q0.x, q0.y, q1.x, q1.y, q1.z, q1.w, a.alpha_min, bx0, by0, bx0 + 7.0f,
+                                    by0 + 7.0f);
         }
-        __syncthreads();
-        int cnt = 0;
-#pragma unroll
-        for (int c = 0; c < kBwdBatch / 64; ++c) {
-            const int j = c * 64 + lane;
-            const bool hit = j < nb && ((s_mask[j] >> wave) & 1u);
-            const uint64_t bal = __ballot(hit);
-            if (hit) s_list[wave][cnt + __popcll(bal & lt_mask)] = (uint8_t)j;
-            cnt += __popcll(bal);
+        const uint64_t bal = __ballot(hit);
+        if (hit) {
+            const int pos = __popcll(bal & lt_mask);
+            const Entry e = make_entry(q0, q1, q2);
+            e0s[pos] = make_float4(e.u, e.v, e.a, e.b);
+            e1s[pos] = make_float4(e.c, e.o, e.z, e.r);
+            e2s[pos] = make_float4(e.g, e.bl, __uint_as_float(g), __uint_as_float((uint32_t)(lo + lane)));
+            qs[pos] = make_float4(q1.x, q1.y, q1.z, 0.0f);
         }
         __builtin_amdgcn_wave_barrier();
-        for (int q = cnt - 1; q >= 0; --q) {
-            const int k = s_list[wave][q];
-            const uint32_t pos = (uint32_t)(lo + k);  // list position of this entry (< maxlast <= list length)
+        const int n = __popcll(bal);
+        for (int q = n - 1; q >= 0; --q) {
+            const float4 e0 = e0s[q], e1 = e1s[q], e2 = e2s[q];
+            const uint32_t pos = __float_as_uint(e2.w);  // list position (< maxlast <= list length)
             float gu = 0.f, gv = 0.f, gA = 0.f, gB = 0.f, gC = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gb = 0.f, gz = 0.f;
             bool contrib = false;
-            const float4 e0 = s_e0[k], e1 = s_e1[k], e2 = s_e2[k];
             if (pos < last) {
                 const float dx = fx - e0.x, dy = fy - e0.y;
                 const float p2 = entry_power2(e0.z, e0.w, e1.x, dx, dy);
-                const float G = exp2f(p2);
+                const float G = fast_exp2(p2);
                 const float oG = e1.y * G;
                 const float al = fminf(a.alpha_max, oG);
                 if (!(al < a.alpha_min)) {
@@ -121,7 +117,7 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
                                            dD * (e1.z - Sd)) +
                                       dA * Tfin / one_m;
                     if (!(oG > a.alpha_max)) {
-                        const float4 cq = s_q[k];
+                        const float4 cq = qs[q];
                         go = dal * G;
                         // dL/dP with P the natural-log exponent (dG/dP = G)
                         const float dP = dal * e1.y * G;
@@ -162,7 +158,7 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
                 atomicAdd(dst + kGZ, gz);
             }
         }
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();
     }
 }
 

@@ -343,25 +343,17 @@ __device__ __forceinline__ Entry make_entry(const float4 q0, const float4 q1, co
     return e;
 }
 
-// Pixel of a 16 x 16 tile handled by thread tid: wave w covers the 8 x 8
-// quadrant (w & 1, w >> 1), lanes row-major inside it.
-__device__ __forceinline__ void tile_pixel(int tid, int &lx, int &ly) {
-    const int w = tid >> 6, l = tid & 63;
-    lx = ((w & 1) << 3) + (l & 7);
-    ly = ((w >> 1) << 3) + (l >> 3);
-}
-
-// Conservative per-quadrant reach of an entry: bit w is set unless no pixel
-// centre of quadrant w can get alpha >= alpha_min.  o G >= alpha_min needs
+// Conservative reach of an entry: can it get alpha >= alpha_min at any pixel
+// centre of the box [bx0, bx1] x [by0, by1]?  o G >= alpha_min needs
 // d^T Q d <= 2 tau with tau = ln(o / alpha_min); the test uses the bounding
 // box of that ellipse with tau widened by 1% + 0.1 + 1e-5 cond(Q), which
 // exceeds the FP32 rounding of the exponent the compositing loop evaluates,
 // so culling never changes a result.
-__device__ __forceinline__ uint32_t entry_quadrant_mask(float u, float v, float A, float B, float C, float o,
-                                                        float alpha_min, float tile_x0, float tile_y0) {
-    if (!(o >= alpha_min)) return 0u;  // alpha <= o < alpha_min everywhere
+__device__ __forceinline__ bool entry_reaches_box(float u, float v, float A, float B, float C, float o,
+                                                  float alpha_min, float bx0, float by0, float bx1, float by1) {
+    if (!(o >= alpha_min)) return false;
     const float detq = A * C - B * B;
-    if (!(detq > 0.0f)) return 0xFu;
+    if (!(detq > 0.0f)) return true;
     const float tau = logf(o / alpha_min);
     const float tr = A + C;
     const float cond = tr * tr / detq;
@@ -369,15 +361,12 @@ __device__ __forceinline__ uint32_t entry_quadrant_mask(float u, float v, float 
     const float inv = 2.0f * t2 / detq;
     const float ex = sqrtf(inv * C) * 1.01f + 0.02f;
     const float ey = sqrtf(inv * A) * 1.01f + 0.02f;
-    uint32_t m = 0u;
-#pragma unroll
-    for (int w = 0; w < 4; ++w) {
-        const float qx0 = tile_x0 + (float)((w & 1) << 3) + 0.5f, qx1 = qx0 + 7.0f;
-        const float qy0 = tile_y0 + (float)((w >> 1) << 3) + 0.5f, qy1 = qy0 + 7.0f;
-        if (u + ex >= qx0 && u - ex <= qx1 && v + ey >= qy0 && v - ey <= qy1) m |= 1u << w;
-    }
-    return m;
+    return u + ex >= bx0 && u - ex <= bx1 && v + ey >= by0 && v - ey <= by1;
 }
+
+// 2^x with the hardware instruction (v_exp_f32); the forward and the backward
+// use this same function so that every alpha decision repeats exactly
+__device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 
 // exponent (base 2) at pixel offset (dx, dy); clamped to <= 0
 __device__ __forceinline__ float entry_power2(float a, float b, float c, float dx, float dy) {

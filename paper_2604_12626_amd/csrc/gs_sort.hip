@@ -114,12 +114,21 @@ __global__ void __launch_bounds__(kScanBlock) scan_down_kernel(const uint32_t *t
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     uint32_t v[kScanItems];
     uint64_t sum = 0;
+    if (base + kScanItems <= n) {  // 4 x 16-B loads (tt is 16-B aligned: caller-owned allocation)
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        const int64_t i = base + k;
-        v[k] = (i < n) ? tt[i] : 0u;
-        sum += v[k];
+        for (int k = 0; k < kScanItems / 4; ++k) {
+            const uint4 q = reinterpret_cast<const uint4 *>(tt + base)[k];
+            v[4 * k] = q.x;
+            v[4 * k + 1] = q.y;
+            v[4 * k + 2] = q.z;
+            v[4 * k + 3] = q.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) v[k] = (base + k < n) ? tt[base + k] : 0u;
     }
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) sum += v[k];
     s[threadIdx.x] = sum;
     __syncthreads();
     for (int off = 1; off < kScanBlock; off <<= 1) {
@@ -212,21 +221,29 @@ __global__ void __launch_bounds__(256) sort_hist_kernel(const uint64_t *keys, co
     const int64_t K = sort_count(d_num, capacity);
     const int lane = threadIdx.x & 63;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int64_t base = (int64_t)blockIdx.x * 256; base < K; base += stride) {
-        const int64_t i = base + threadIdx.x;
-        const bool valid = i < K;
-        const uint64_t key = valid ? keys[i] : 0ull;
-        const uint64_t vmask = __ballot(valid);
-        for (int p = 0; p < passes; ++p) {
-            const uint32_t d = (uint32_t)(key >> (bit0 + p * kRadixBits)) & (kBins - 1);
-            uint64_t peers = vmask;
+    constexpr int kHistItems = 8;  // keys per lane per step, loaded together
+    for (int64_t base = (int64_t)blockIdx.x * 256 * kHistItems; base < K; base += stride * kHistItems) {
+        uint64_t key[kHistItems];
 #pragma unroll
-            for (int b = 0; b < kRadixBits; ++b) {
-                const bool bit = (d >> b) & 1u;
-                const uint64_t m = __ballot(bit);
-                peers &= bit ? m : ~m;
+        for (int j = 0; j < kHistItems; ++j) {
+            const int64_t i = base + j * 256 + threadIdx.x;
+            key[j] = i < K ? keys[i] : 0ull;
+        }
+#pragma unroll
+        for (int j = 0; j < kHistItems; ++j) {
+            const bool valid = base + j * 256 + threadIdx.x < K;
+            const uint64_t vmask = __ballot(valid);
+            for (int p = 0; p < passes; ++p) {
+                const uint32_t d = (uint32_t)(key[j] >> (bit0 + p * kRadixBits)) & (kBins - 1);
+                uint64_t peers = vmask;
+#pragma unroll
+                for (int b = 0; b < kRadixBits; ++b) {
+                    const bool bit = (d >> b) & 1u;
+                    const uint64_t m = __ballot(bit);
+                    peers &= bit ? m : ~m;
+                }
+                if (valid && (peers & lt_mask) == 0ull) atomicAdd(&s_h[p * kBins + d], (uint32_t)__popcll(peers));
             }
-            if (valid && (peers & lt_mask) == 0ull) atomicAdd(&s_h[p * kBins + d], (uint32_t)__popcll(peers));
         }
     }
     __syncthreads();
@@ -284,12 +301,19 @@ __global__ void __launch_bounds__(kSortBlock) onesweep_kernel(const uint64_t *__
         uint32_t val[kSortItems];
         uint32_t rank[kSortItems];
         uint32_t dig[kSortItems];
+        // all loads first (independent, in flight together), then the ranking
+        // (whose LDS fences would otherwise serialise one load per stripe)
 #pragma unroll
         for (int j = 0; j < kSortItems; ++j) {
             const int64_t idx = start + (int64_t)wave * (kSortItems * 64) + j * 64 + lane;
             const bool valid = idx < K;
             key[j] = valid ? keys_in[idx] : ~0ull;
             val[j] = valid ? vals_in[idx] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < kSortItems; ++j) {
+            const int64_t idx = start + (int64_t)wave * (kSortItems * 64) + j * 64 + lane;
+            const bool valid = idx < K;
             const uint32_t d = (uint32_t)(key[j] >> shift) & (kBins - 1);
             dig[j] = valid ? d : 0xFFFFFFFFu;
             uint64_t peers = __ballot(valid);
@@ -504,7 +528,7 @@ hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec
     // 3. onesweep passes over the significant bits
     {
         // few blocks, many keys each: every block adds its LDS histogram once
-        int64_t hb = (P.capacity + 4095) / 4096;
+        int64_t hb = (P.capacity + 2047) / 2048;
         if (hb > n_cu) hb = n_cu;
         if (hb < 1) hb = 1;
         if ((e = launch_kernel(sort_hist_kernel, dim3((unsigned)hb), dim3(256), s, k_a, d_num, P.capacity, P.passes, 0,
