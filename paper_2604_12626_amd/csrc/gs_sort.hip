@@ -2,8 +2,9 @@
 // onesweep LSD radix sort (8-bit digits, decoupled look-back across
 // partitions) and per-tile ranges.
 //
-// Onesweep on CDNA4: a partition of 8192 keys per 512-thread workgroup (eight
-// wave64, 16 keys per lane, ~107 KB of LDS of the 160 KB a CU offers).  Ranks inside a wave come from eight ballots per
+// Onesweep on CDNA4: a partition of 4096 keys per 512-thread workgroup (eight
+// wave64, 8 keys per lane), so that a frame's ~1M keys occupy every CU.  The
+// digit counts of every pass come from the emission kernel.  Ranks inside a wave come from eight ballots per
 // key (the lanes holding the same digit), so ranking is stable: stripes are
 // processed in index order and lanes inside a stripe are in index order.
 // A persistent grid takes partitions by an atomic ticket, so a workgroup
@@ -25,13 +26,14 @@ constexpr int kScanTile = kScanBlock * kScanItems;  // 4096 instances per block
 
 constexpr int kSortBlock = 512;
 constexpr int kSortWaves = kSortBlock / 64;
-constexpr int kSortItems = 16;
-constexpr int kSortPart = kSortBlock * kSortItems;  // 8192 keys per partition
+constexpr int kSortItems = 8;
+constexpr int kSortPart = kSortBlock * kSortItems;  // 4096 keys per partition
 constexpr int kLookback = 16;                       // predecessor statuses read per round trip
 constexpr int kEmitLane = 32;                       // larger rects are emitted by the whole wave
 constexpr int kRadixBits = 8;
 constexpr int kBins = 1 << kRadixBits;
 constexpr int kMaxPasses = 8;
+constexpr int kHistStride = kBins + 1;  // per-pass difference array of the digit counts
 constexpr uint32_t kFlagAgg = 1u << 30;
 constexpr uint32_t kFlagIncl = 2u << 30;
 constexpr uint32_t kCountMask = (1u << 30) - 1u;
@@ -41,6 +43,12 @@ constexpr uint32_t kCountMask = (1u << 30) - 1u;
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) fill_u32_kernel(uint32_t *p, uint32_t v, int64_t n, int64_t stride) {
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+// zeroes two buffers in one launch
+__global__ void __launch_bounds__(256) clear2_kernel(uint32_t *a, int64_t na, uint32_t *b, int64_t nb, int64_t stride) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < na; i += stride) a[i] = 0u;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nb; i += stride) b[i] = 0u;
 }
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
@@ -149,9 +157,61 @@ __global__ void __launch_bounds__(kScanBlock) scan_down_kernel(const uint32_t *t
 // ---------------------------------------------------------------------------
 // key emission
 // ---------------------------------------------------------------------------
+// Digit counts are kept as difference arrays (count of digit d = sum of
+// diff[0..d]) so that a run of consecutive digits costs two updates.
+__device__ __forceinline__ void hist_add(uint32_t *h, uint32_t d, uint32_t c) {
+    atomicAdd(&h[d], c);
+    atomicSub(&h[d + 1], c);
+}
+
+// adds the tile digits of one rect row (tiles [t0, t0 + w)) to the per-pass
+// difference arrays of the tile bytes (passes 4 .. passes-1)
+__device__ __forceinline__ void hist_add_row(uint32_t (*h)[kHistStride], int passes, uint64_t t0, uint32_t w) {
+    // lowest tile byte: w consecutive digits, wrapping mod 256
+    {
+        uint32_t *hp = h[4];
+        const uint32_t full = w >> 8, rem = w & 255u, lo = (uint32_t)(t0 & 255u);
+        if (full) {  // every digit, `full` times
+            atomicAdd(&hp[0], full);
+            atomicSub(&hp[256], full);
+        }
+        if (rem) {
+            if (lo + rem <= 256u) {
+                atomicAdd(&hp[lo], 1u);
+                atomicSub(&hp[lo + rem], 1u);
+            } else {
+                atomicAdd(&hp[lo], 1u);
+                atomicSub(&hp[256], 1u);
+                atomicAdd(&hp[0], 1u);
+                atomicSub(&hp[lo + rem - 256u], 1u);
+            }
+        }
+    }
+    // higher tile bytes: constant over runs of 256^b tiles
+    for (int p = 5; p < passes; ++p) {
+        const int sh = 8 * (p - 4);
+        uint64_t t = t0;
+        const uint64_t end = t0 + w;
+        while (t < end) {
+            uint64_t seg = ((t >> sh) + 1) << sh;
+            if (seg > end) seg = end;
+            hist_add(h[p], (uint32_t)(t >> sh) & 255u, (uint32_t)(seg - t));
+            t = seg;
+        }
+    }
+}
+
+// Key emission (one thread per instance; rects of more than kEmitLane tiles
+// are emitted by the whole wave, 64 keys per step) fused with the digit
+// histograms of every sort pass: the four depth bytes are the same for all
+// keys of an instance (counted once with weight tiles_touched) and the tile
+// bytes are counted per rect row.
 __global__ void __launch_bounds__(256) emit_kernel(const uint32_t *tt, const uint32_t *offsets, const float4 *rec,
                                                    int64_t n, int TX, int TY, int64_t capacity, uint64_t *keys,
-                                                   uint32_t *vals) {
+                                                   uint32_t *vals, int passes, uint32_t *hist /*[passes][257]*/) {
+    __shared__ uint32_t s_h[kMaxPasses][kHistStride];
+    for (int k = threadIdx.x; k < kMaxPasses * kHistStride; k += 256) (&s_h[0][0])[k] = 0u;
+    __syncthreads();
     const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const uint32_t t = (g < n) ? tt[g] : 0u;
@@ -165,14 +225,19 @@ __global__ void __launch_bounds__(256) emit_kernel(const uint32_t *tt, const uin
         R = tile_rect(q0.x, q0.y, __float_as_int(q0.w), TX, TY);
         depth_bits = (uint64_t)__float_as_uint(q0.z);
         tbase = (uint64_t)view * (uint64_t)(TX * TY);
+#pragma unroll
+        for (int p = 0; p < 4; ++p) hist_add(s_h[p], (uint32_t)(depth_bits >> (8 * p)) & 255u, t);
+        for (int ty = R.y0; ty < R.y1; ++ty)
+            hist_add_row(s_h, passes, tbase + (uint64_t)(ty * TX + R.x0), (uint32_t)(R.x1 - R.x0));
     }
     if (live && t <= (uint32_t)kEmitLane) {
         int64_t k = k0;
         for (int ty = R.y0; ty < R.y1; ++ty)
             for (int tx = R.x0; tx < R.x1; ++tx) {
-                if (k >= capacity) return;
-                keys[k] = ((tbase + (uint64_t)(ty * TX + tx)) << 32) | depth_bits;
-                vals[k] = (uint32_t)g;
+                if (k < capacity) {
+                    keys[k] = ((tbase + (uint64_t)(ty * TX + tx)) << 32) | depth_bits;
+                    vals[k] = (uint32_t)g;
+                }
                 ++k;
             }
     }
@@ -198,6 +263,11 @@ __global__ void __launch_bounds__(256) emit_kernel(const uint32_t *tt, const uin
             vals[k] = gg;
         }
     }
+    __syncthreads();
+    for (int k = threadIdx.x; k < passes * kHistStride; k += 256) {
+        const uint32_t v = (&s_h[0][0])[k];
+        if (v) atomicAdd(&hist[k], v);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -208,86 +278,44 @@ __device__ __forceinline__ int64_t sort_count(const int64_t *d_num, int64_t capa
     return k < capacity ? k : capacity;
 }
 
-// global digit histograms of all passes in one read of the keys; the lanes of
-// a wave holding the same digit are found with ballots and add once (the
-// depth-exponent byte falls in a handful of bins, so plain LDS atomics would
-// serialise)
-__global__ void __launch_bounds__(256) sort_hist_kernel(const uint64_t *keys, const int64_t *d_num, int64_t capacity,
-                                                        int passes, int bit0, uint32_t *hist /*[passes][256]*/,
-                                                        int64_t stride) {
-    __shared__ uint32_t s_h[kMaxPasses * kBins];
-    for (int k = threadIdx.x; k < passes * kBins; k += 256) s_h[k] = 0u;
-    __syncthreads();
-    const int64_t K = sort_count(d_num, capacity);
-    const int lane = threadIdx.x & 63;
-    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    constexpr int kHistItems = 8;  // keys per lane per step, loaded together
-    for (int64_t base = (int64_t)blockIdx.x * 256 * kHistItems; base < K; base += stride * kHistItems) {
-        uint64_t key[kHistItems];
-#pragma unroll
-        for (int j = 0; j < kHistItems; ++j) {
-            const int64_t i = base + j * 256 + threadIdx.x;
-            key[j] = i < K ? keys[i] : 0ull;
-        }
-#pragma unroll
-        for (int j = 0; j < kHistItems; ++j) {
-            const bool valid = base + j * 256 + threadIdx.x < K;
-            const uint64_t vmask = __ballot(valid);
-            for (int p = 0; p < passes; ++p) {
-                const uint32_t d = (uint32_t)(key[j] >> (bit0 + p * kRadixBits)) & (kBins - 1);
-                uint64_t peers = vmask;
-#pragma unroll
-                for (int b = 0; b < kRadixBits; ++b) {
-                    const bool bit = (d >> b) & 1u;
-                    const uint64_t m = __ballot(bit);
-                    peers &= bit ? m : ~m;
-                }
-                if (valid && (peers & lt_mask) == 0ull) atomicAdd(&s_h[p * kBins + d], (uint32_t)__popcll(peers));
-            }
-        }
-    }
-    __syncthreads();
-    for (int k = threadIdx.x; k < passes * kBins; k += 256)
-        if (s_h[k]) atomicAdd(&hist[k], s_h[k]);
-}
-
-// exclusive scan of each pass's histogram (one workgroup of 256 threads)
-__global__ void __launch_bounds__(kBins) sort_hist_scan_kernel(uint32_t *hist, int passes) {
-    __shared__ uint32_t s[kBins];
-    for (int p = 0; p < passes; ++p) {
-        const uint32_t v = hist[p * kBins + threadIdx.x];
-        s[threadIdx.x] = v;
-        __syncthreads();
-        for (int off = 1; off < kBins; off <<= 1) {
-            const uint32_t t = (threadIdx.x >= (unsigned)off) ? s[threadIdx.x - off] : 0u;
-            __syncthreads();
-            s[threadIdx.x] += t;
-            __syncthreads();
-        }
-        hist[p * kBins + threadIdx.x] = s[threadIdx.x] - v;
-        __syncthreads();
-    }
-}
-
 __global__ void __launch_bounds__(kSortBlock) onesweep_kernel(const uint64_t *__restrict__ keys_in,
                                                               const uint32_t *__restrict__ vals_in,
                                                               uint64_t *__restrict__ keys_out,
                                                               uint32_t *__restrict__ vals_out, const int64_t *d_num,
                                                               int64_t capacity, int shift,
-                                                              const uint32_t *digit_base /*[256]*/,
-                                                              uint32_t *status /*[parts][256]*/, uint32_t *ticket) {
+                                                              const uint32_t *hist_diff /*[257]*/,
+                                                              uint32_t *status /*[parts][256]*/, uint32_t *ticket,
+                                                              const int32_t *d_overflow) {
     __shared__ uint32_t s_part;
     __shared__ uint32_t s_wh[kSortWaves][kBins];  // per-wave digit counts -> prefix across waves
     __shared__ uint32_t s_local[kBins];           // block-local exclusive digit start
     __shared__ uint32_t s_glob[kBins];            // global start of the digit for this partition
     __shared__ uint32_t s_scan[kBins];
+    __shared__ uint32_t s_base[kBins];            // global start of each digit in this pass
     __shared__ uint64_t s_keys[kSortPart];
     __shared__ uint32_t s_vals[kSortPart];
 
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    if (*d_overflow) return;  // keys beyond the capacity were dropped: nothing consistent to sort
     const int64_t K = sort_count(d_num, capacity);
+    // digit counts = prefix sums of the difference array, then their exclusive scan
+    if (tid < kBins) s_scan[tid] = hist_diff[tid];
+    __syncthreads();
+    for (int round = 0; round < 2; ++round) {
+        uint32_t own = 0u;
+        if (tid < kBins) own = s_scan[tid];
+        for (int off = 1; off < kBins; off <<= 1) {
+            uint32_t t = 0u;
+            if (tid < kBins && tid >= off) t = s_scan[tid - off];
+            __syncthreads();
+            if (tid < kBins) s_scan[tid] += t;
+            __syncthreads();
+        }
+        if (round == 1 && tid < kBins) s_base[tid] = s_scan[tid] - own;  // exclusive
+        __syncthreads();
+    }
     // persistent: take partitions in ticket order until none is left
     while (true) {
         if (tid == 0) s_part = atomicAdd(ticket, 1u);
@@ -391,7 +419,7 @@ __global__ void __launch_bounds__(kSortBlock) onesweep_kernel(const uint64_t *__
                 __hip_atomic_store(col + (size_t)part * kBins, kFlagIncl | (prefix + total), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
             }
-            s_glob[d] = digit_base[d] + prefix;
+            s_glob[d] = s_base[d] + prefix;
             s_scan[d] = total;
         }
         __syncthreads();
@@ -476,7 +504,7 @@ SortPlan make_sort_plan(int64_t n, int64_t capacity, int64_t n_tiles_total) {
     o = align256(o + sizeof(uint32_t) * (size_t)(capacity > 0 ? capacity : 1));
     // hist, status and tickets are contiguous so one fill clears them
     p.off_hist = o;
-    o = o + sizeof(uint32_t) * (size_t)kMaxPasses * kBins;
+    o = o + sizeof(uint32_t) * (size_t)kMaxPasses * kHistStride;
     p.off_ticket = o;
     o = o + sizeof(uint32_t) * (size_t)kMaxPasses * 64;
     p.off_status = o;
@@ -498,8 +526,9 @@ hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec
     uint32_t *status = reinterpret_cast<uint32_t *>(ws + P.off_status);
     const size_t clear_words = (P.off_status - P.off_hist) / 4 + (size_t)P.passes * P.sort_parts * kBins;
 
-    if ((e = launch_fill_u32(hist, 0u, (int64_t)clear_words, s)) != hipSuccess) return e;
-    if ((e = launch_fill_u32(ranges, 0u, 2 * P.n_tiles_total, s)) != hipSuccess) return e;
+    if ((e = launch_kernel(clear2_kernel, dim3(1024), dim3(256), s, hist, (int64_t)clear_words, ranges,
+                           2 * P.n_tiles_total, (int64_t)1024 * 256)) != hipSuccess)
+        return e;
     // 1. scan
     if (P.n > 0) {
         if ((e = launch_kernel(scan_reduce_kernel, dim3((unsigned)P.scan_blocks), dim3(kScanBlock), s, tt, P.n,
@@ -522,27 +551,17 @@ hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec
     uint32_t *v_b = odd ? vals : vals2;
     if (P.n > 0) {
         if ((e = launch_kernel(emit_kernel, dim3((unsigned)((P.n + 255) / 256)), dim3(256), s, tt, offsets, rec,
-                               P.n, TX, TY, P.capacity, k_a, v_a)) != hipSuccess)
+                               P.n, TX, TY, P.capacity, k_a, v_a, P.passes, hist)) != hipSuccess)
             return e;
     }
-    // 3. onesweep passes over the significant bits
-    {
-        // few blocks, many keys each: every block adds its LDS histogram once
-        int64_t hb = (P.capacity + 2047) / 2048;
-        if (hb > n_cu) hb = n_cu;
-        if (hb < 1) hb = 1;
-        if ((e = launch_kernel(sort_hist_kernel, dim3((unsigned)hb), dim3(256), s, k_a, d_num, P.capacity, P.passes, 0,
-                               hist, hb * 256)) != hipSuccess)
-            return e;
-        if ((e = launch_kernel(sort_hist_scan_kernel, dim3(1), dim3(kBins), s, hist, P.passes)) != hipSuccess) return e;
-    }
-    // persistent grid: one ~107-KB workgroup per CU
+    // 3. onesweep passes over the significant bits (digit counts come from the emission)
+    // persistent grid: one workgroup per CU (~60 KB of LDS)
     int64_t sg = (int64_t)n_cu;
     if (sg > P.sort_parts) sg = P.sort_parts;
     for (int p = 0; p < P.passes; ++p) {
         if ((e = launch_kernel(onesweep_kernel, dim3((unsigned)sg), dim3(kSortBlock), s, k_a, v_a, k_b, v_b,
-                               d_num, P.capacity, p * kRadixBits, hist + p * kBins,
-                               status + (size_t)p * P.sort_parts * kBins, ticket + p * 64)) != hipSuccess)
+                               d_num, P.capacity, p * kRadixBits, hist + p * kHistStride,
+                               status + (size_t)p * P.sort_parts * kBins, ticket + p * 64, d_overflow)) != hipSuccess)
             return e;
         uint64_t *tk = k_a;
         k_a = k_b;
