@@ -135,6 +135,19 @@ const char *gs_last_error(void); /* thread-local; "" if none */
 int32_t gs_version(void);
 void gs_default_params(gs_params *p, int32_t width, int32_t height);
 
+/* Launch configuration (host-side, process-wide; it changes scheduling only,
+ * never a result).  composite_groups_per_cu: persistent 4-wave groups per
+ * compute unit in gs_composite (1..32, default 8); each wave of the grid pops
+ * (view, tile, quadrant) work items until none is left.  gs_set_tuning(NULL)
+ * restores the defaults; invalid values return GS_ERR_INVALID_ARGUMENT.  Meant
+ * for an autotuner that times the candidates on the target workload. */
+typedef struct gs_tuning {
+    int32_t composite_groups_per_cu;
+    int32_t reserved[7];
+} gs_tuning;
+gs_status gs_set_tuning(const gs_tuning *t);
+void gs_get_tuning(gs_tuning *t);
+
 /* Host helper: offsets[v] = first instance of view v, offsets[n_views] =
  * total (host arrays; offsets has n_views + 1 entries). */
 gs_status gs_instance_offsets(const gs_gaussians *segs, int32_t n_segs, int32_t n_views,

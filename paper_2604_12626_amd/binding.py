@@ -50,7 +50,12 @@ class Projected(ctypes.Structure):
     _fields_ = [("n_instances", ctypes.c_int64), ("tiles_touched", P), ("rec", P)]
 
 
-EXPORTS = ["gs_status_string", "gs_last_error", "gs_version", "gs_default_params", "gs_instance_offsets",
+class Tuning(ctypes.Structure):
+    _fields_ = [("composite_groups_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+
+
+EXPORTS = ["gs_status_string", "gs_last_error", "gs_version", "gs_default_params", "gs_set_tuning", "gs_get_tuning",
+           "gs_instance_offsets",
            "gs_deform_lbs", "gs_deform_lbs_backward", "gs_project", "gs_bin_sort_workspace", "gs_bin_sort",
            "gs_composite_workspace", "gs_composite", "gs_render_backward_workspace", "gs_render_backward"]
 
@@ -95,8 +100,11 @@ def load():
     lib.gs_render_backward.argtypes = [ctypes.POINTER(Gaussians), i32, P, i32, P, ctypes.POINTER(Params),
                                        ctypes.POINTER(Projected), P, P, P, P, P, P, P, P, sz,
                                        ctypes.POINTER(GaussiansGrad), P]
+    lib.gs_set_tuning.argtypes = [ctypes.POINTER(Tuning)]
+    lib.gs_get_tuning.argtypes = [ctypes.POINTER(Tuning)]
+    lib.gs_get_tuning.restype = None
     for f in ("gs_deform_lbs", "gs_deform_lbs_backward", "gs_project", "gs_bin_sort", "gs_composite",
-              "gs_render_backward", "gs_instance_offsets"):
+              "gs_render_backward", "gs_instance_offsets", "gs_set_tuning"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -253,3 +261,23 @@ def deform_lbs_backward(means_c, log_scales_c, quats_c, joint_idx, weights, avat
                                       ptr(joint_idx), ptr(weights), ptr(avatar_of), ptr(skin_mats), A, J,
                                       ptr(d_means_out), ptr(d_cov6_out), ptr(d_means), ptr(d_log_scales),
                                       ptr(d_quats), stream_handle()))
+
+
+def set_tuning(composite_groups_per_cu=None):
+    """Set (or with None restore) the launch configuration; returns the previous one."""
+    lib = load()
+    prev = Tuning()
+    lib.gs_get_tuning(ctypes.byref(prev))
+    if composite_groups_per_cu is None:
+        _check(lib.gs_set_tuning(None))
+    else:
+        t = Tuning()
+        t.composite_groups_per_cu = int(composite_groups_per_cu)
+        _check(lib.gs_set_tuning(ctypes.byref(t)))
+    return {"composite_groups_per_cu": prev.composite_groups_per_cu}
+
+
+def get_tuning():
+    t = Tuning()
+    load().gs_get_tuning(ctypes.byref(t))
+    return {"composite_groups_per_cu": t.composite_groups_per_cu}

@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <atomic>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -102,6 +103,8 @@ int64_t seg_offset_in_view(const gs_gaussians *segs, uint32_t mask, int s) {
     return o;
 }
 
+std::atomic<int> g_comp_groups{8};
+
 std::mutex g_dev_mu;
 int g_cu_count[64] = {0};
 
@@ -148,6 +151,24 @@ void gs_default_params(gs_params *p, int32_t width, int32_t height) {
     p->alpha_min = 1.0f / 255.0f;
     p->t_min = 1e-4f;
     p->bg[0] = p->bg[1] = p->bg[2] = 0.0f;
+}
+
+gs_status gs_set_tuning(const gs_tuning *t) {
+    clear_error();
+    if (!t) {
+        g_comp_groups.store(8);
+        return GS_OK;
+    }
+    if (t->composite_groups_per_cu < 1 || t->composite_groups_per_cu > 32)
+        return fail(GS_ERR_INVALID_ARGUMENT, "composite_groups_per_cu=%d outside [1, 32]", t->composite_groups_per_cu);
+    g_comp_groups.store(t->composite_groups_per_cu);
+    return GS_OK;
+}
+
+void gs_get_tuning(gs_tuning *t) {
+    if (!t) return;
+    memset(t, 0, sizeof(*t));
+    t->composite_groups_per_cu = g_comp_groups.load();
 }
 
 gs_status gs_instance_offsets(const gs_gaussians *segs, int32_t n_segs, int32_t n_views,
@@ -356,9 +377,10 @@ gs_status gs_composite(const gs_projected *proj, const uint32_t *vals, const uin
     a.n_contrib = n_contrib;
     hipError_t e = gs::launch_fill_u32(a.counter, 0u, 1, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "gs_composite");
-    // persistent waves: 8 four-wave groups per CU, never more waves than quadrant items
-    int64_t grid = (int64_t)cu_count() * 8;
-    if (grid * 4 > a.n_items * 4) grid = a.n_items;
+    // persistent waves: a tunable number of four-wave groups per CU, never
+    // more waves than quadrant work items
+    int64_t grid = (int64_t)cu_count() * g_comp_groups.load();
+    if (grid > a.n_items) grid = a.n_items;
     e = gs::launch_composite(a, (int)grid, (hipStream_t)stream);
     return e == hipSuccess ? GS_OK : hip_fail(e, "gs_composite");
 }

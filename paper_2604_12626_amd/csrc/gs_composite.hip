@@ -63,27 +63,25 @@ __global__ void __launch_bounds__(64 * kWavesPerGroup) composite_kernel(const Co
             }
             __builtin_amdgcn_wave_barrier();
             const int n = __popcll(bal);
-            if (!done) {
-                for (int q = 0; q < n; ++q) {
-                    const float4 e0 = e0s[q], e1 = e1s[q];
-                    const float dx = fx - e0.x, dy = fy - e0.y;
-                    const float p2 = entry_power2(e0.z, e0.w, e1.x, dx, dy);
-                    const float al = fminf(a.alpha_max, e1.y * fast_exp2(p2));
-                    if (al < a.alpha_min) continue;
-                    const float Tn = T * (1.0f - al);
-                    if (Tn < a.t_min) {
-                        done = true;
-                        break;
-                    }
-                    const float4 e2 = e2s[q];
-                    const float w = al * T;
-                    cr = fmaf(w, e1.w, cr);
-                    cg = fmaf(w, e2.x, cg);
-                    cb = fmaf(w, e2.y, cb);
-                    dd = fmaf(w, e1.z, dd);
-                    T = Tn;
-                    last = __float_as_uint(e2.z);
-                }
+            // uniform trip count; the per-lane skip / stop / done decisions are
+            // predicates (no divergent exits in the loop)
+            for (int q = 0; q < n; ++q) {
+                const float4 e0 = e0s[q], e1 = e1s[q], e2 = e2s[q];
+                const float dx = fx - e0.x, dy = fy - e0.y;
+                const float p2 = entry_power2(e0.z, e0.w, e1.x, dx, dy);
+                const float al = fminf(a.alpha_max, e1.y * fast_exp2(p2));
+                const float Tn = T * (1.0f - al);
+                const bool take = !done && !(al < a.alpha_min);
+                const bool stop = take && (Tn < a.t_min);
+                const bool use = take && !stop;
+                const float w = use ? al * T : 0.0f;
+                cr = fmaf(w, e1.w, cr);
+                cg = fmaf(w, e2.x, cg);
+                cb = fmaf(w, e2.y, cb);
+                dd = fmaf(w, e1.z, dd);
+                T = use ? Tn : T;
+                last = use ? __float_as_uint(e2.z) : last;
+                done = done || stop;
             }
             __builtin_amdgcn_wave_barrier();
             if (__ballot(!done) == 0ull) break;
