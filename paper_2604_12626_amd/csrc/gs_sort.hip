@@ -450,6 +450,7 @@ __global__ void __launch_bounds__(kSortBlock) onesweep_kernel(const uint64_t *__
             const uint64_t kk = s_keys[q];
             const uint32_t dd = (uint32_t)(kk >> shift) & (kBins - 1);
             const uint32_t dst = s_glob[dd] + (uint32_t)q - s_local[dd];
+            if ((int64_t)dst >= K) continue;  // only reachable with inconsistent digit counts
             keys_out[dst] = kk;
             vals_out[dst] = s_vals[q];
         }
