@@ -228,7 +228,10 @@ gs_status gs_bin_sort(const gs_projected *proj, int32_t n_views, const gs_params
                       uint64_t *keys, uint32_t *vals, int64_t capacity, uint32_t *tile_ranges,
                       int64_t *d_num_instances, int32_t *d_overflow, gs_stream_t stream);
 
-/* Workspace bytes gs_composite needs (the persistent tile queue). */
+/* Workspace bytes gs_composite needs (the persistent tile queues).  The
+ * workspace must be zero-filled before its first use; every call leaves it
+ * zero-filled again, so one zeroing at allocation serves all later calls
+ * (calls sharing a workspace must not overlap). */
 size_t gs_composite_workspace(int32_t n_views, const gs_params *p);
 
 /* Per-tile front-to-back compositing.  For each pixel p = (x + 1/2, y + 1/2)
@@ -239,8 +242,9 @@ size_t gs_composite_workspace(int32_t n_views, const gs_params *p);
  * accumulated, un-normalised), alpha = 1 - T; optional t_final = T and
  * n_contrib = 1 + list position of the last composited entry (the state the
  * backward pass starts from; pass NULL to skip them).
- * The tiles are processed by a persistent grid that pops (view, tile) work
- * items from a counter in `ws` (cleared by this call).
+ * The tiles are processed by a persistent grid that pops (view, tile,
+ * quadrant) work items from counters in `ws` (zero on entry, zero again when
+ * the call completes).
  * Errors: GS_ERR_INVALID_ARGUMENT, GS_ERR_WORKSPACE_TOO_SMALL. */
 gs_status gs_composite(const gs_projected *proj, const uint32_t *vals, const uint32_t *tile_ranges,
                        int32_t n_views, const gs_params *p, void *ws, size_t ws_bytes, float *rgb, float *depth,

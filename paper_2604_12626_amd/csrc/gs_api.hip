@@ -375,8 +375,7 @@ gs_status gs_composite(const gs_projected *proj, const uint32_t *vals, const uin
     a.alpha = alpha;
     a.t_final = t_final;
     a.n_contrib = n_contrib;
-    hipError_t e = gs::launch_fill_u32(a.counter, 0u, 1, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "gs_composite");
+    hipError_t e;
     // persistent waves: a tunable number of four-wave groups per CU, never
     // more waves than quadrant work items
     int64_t grid = (int64_t)cu_count() * g_comp_groups.load();

@@ -10,23 +10,45 @@
 // compacted entries front to back.  There are no workgroup barriers: waves
 // of different quadrants and tiles interleave on a SIMD and hide each other's
 // gather latency.  A wave leaves the list once its 64 pixels have stopped.
+//
+// Work queues are XCD-aware: the (view, tile) items are split into eight
+// contiguous ranges with a counter each, and a workgroup starts on the queue
+// of blockIdx.x mod 8 -- the XCD the dispatcher places it on -- so the four
+// quadrants of a tile, and neighbouring tiles that share Gaussians, are
+// gathered through one L2.  An exhausted queue sends its waves on to the next
+// queues (work stealing).  Placement only affects locality, never results.
+// The last wave to leave returns the counters to zero, so the workspace is
+// ready for the next call without a clearing launch.
 #include "gs_internal.hpp"
 
 namespace gs {
 
 constexpr int kWavesPerGroup = 4;
+constexpr int kQueues = 8;  // one per XCD
 
 __global__ void __launch_bounds__(64 * kWavesPerGroup) composite_kernel(const CompositeArgs a) {
     __shared__ float4 s_e0[kWavesPerGroup][64], s_e1[kWavesPerGroup][64], s_e2[kWavesPerGroup][64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     float4 *e0s = s_e0[wave], *e1s = s_e1[wave], *e2s = s_e2[wave];
-    const int64_t n_work = a.n_items * 4;
+    const int home = (int)(blockIdx.x % kQueues);
+    int visited = 0;  // queues found empty so far (meaningful in lane 0)
     while (true) {
-        int64_t item = 0;
-        if (lane == 0) item = (int64_t)atomicAdd(a.counter, 1u);
-        item = __shfl((long long)item, 0, 64);
-        if (item >= n_work) break;
+        long long item = -1;
+        if (lane == 0) {
+            while (visited < kQueues) {
+                const int q = (home + visited) % kQueues;
+                const int64_t lo = 4 * ((a.n_items * q) / kQueues), hi = 4 * ((a.n_items * (q + 1)) / kQueues);
+                const int64_t k = lo + (int64_t)atomicAdd(a.counter + q, 1u);
+                if (k < hi) {
+                    item = k;
+                    break;
+                }
+                ++visited;
+            }
+        }
+        item = __shfl(item, 0, 64);
+        if (item < 0) break;
         const int64_t titem = item >> 2;
         const int quad = (int)(item & 3);
         const int view = (int)(titem / a.T);
@@ -97,10 +119,18 @@ __global__ void __launch_bounds__(64 * kWavesPerGroup) composite_kernel(const Co
             if (a.n_contrib) a.n_contrib[pix] = last;
         }
     }
+    // every pop of every wave has happened once the last wave gets here
+    if (lane == 0) {
+        const uint32_t left = atomicAdd(a.counter + kQueues, 1u);
+        if (left == a.n_waves - 1u) {
+            for (int q = 0; q <= kQueues; ++q) atomicExch(a.counter + q, 0u);
+        }
+    }
 }
 
-hipError_t launch_composite(const CompositeArgs &a, int grid, hipStream_t s) {
-    if (a.n_items == 0) return hipSuccess;
+hipError_t launch_composite(CompositeArgs a, int grid, hipStream_t s) {
+    if (a.n_items == 0 || grid <= 0) return hipSuccess;
+    a.n_waves = (uint32_t)grid * kWavesPerGroup;
     return launch_kernel(composite_kernel, dim3(grid), dim3(64 * kWavesPerGroup), s, a);
 }
 

@@ -54,8 +54,9 @@ struct CompositeArgs {
     const float4 *rec;
     const uint32_t *vals;
     const uint2 *ranges;
-    uint32_t *counter;
-    int64_t n_items;  // n_views * T
+    uint32_t *counter;  // [8] queue heads + [1] waves finished; zero on entry and on exit
+    int64_t n_items;    // n_views * T
+    uint32_t n_waves;   // waves in the grid (set by the launcher)
     int32_t W, H, TX, T;
     float alpha_max, alpha_min, t_min;
     float bg0, bg1, bg2;
@@ -106,7 +107,7 @@ SortPlan make_sort_plan(int64_t n, int64_t capacity, int64_t n_tiles_total);
 hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec, int TX, int TY, char *ws,
                         uint64_t *keys, uint32_t *vals, uint32_t *ranges, int64_t *d_num, int32_t *d_overflow,
                         int n_cu, hipStream_t s);
-hipError_t launch_composite(const CompositeArgs &a, int grid, hipStream_t s);
+hipError_t launch_composite(CompositeArgs a, int grid, hipStream_t s);
 hipError_t launch_backward_tiles(const BackwardTileArgs &a, hipStream_t s);
 hipError_t launch_backward_project(const BackwardProjectArgs &a, hipStream_t s);
 hipError_t launch_lbs(const LbsArgs &a, bool backward, hipStream_t s);

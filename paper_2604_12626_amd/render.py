@@ -50,13 +50,13 @@ class Renderer:
         self._bufs = {}
 
     # -- buffers ------------------------------------------------------------
-    def _buf(self, name, shape, dtype):
+    def _buf(self, name, shape, dtype, zero=False):
         t = self._bufs.get(name)
         n = 1
         for s in shape:
             n *= int(s)
         if t is None or t.numel() < n or t.dtype != dtype:
-            t = torch.empty(max(n, 1), dtype=dtype, device=self.device)
+            t = (torch.zeros if zero else torch.empty)(max(n, 1), dtype=dtype, device=self.device)
             self._bufs[name] = t
         return t[:n].view(*shape) if len(shape) else t[:1]
 
@@ -71,7 +71,8 @@ class Renderer:
         f.overflow = self._buf("ovf", (1,), torch.int32)
         ws = B.bin_sort_workspace(n_inst, self.capacity, n_views, self.params)
         f.sort_ws = self._buf("sort_ws", ((ws + 255) // 256 * 256,), torch.uint8)
-        f.comp_ws = self._buf("comp_ws", (256,), torch.uint8)
+        # zeroed once; gs_composite leaves its queue counters at zero
+        f.comp_ws = self._buf("comp_ws", (B.composite_workspace(n_views, self.params),), torch.uint8, zero=True)
         hw = (n_views, self.H, self.W)
         f.rgb = self._buf("rgb", hw + (3,), torch.float32)
         f.depth = self._buf("depth", hw, torch.float32)

@@ -174,9 +174,17 @@ def test_composite_parity(dev, orc, name, counts, W, H, rmed, aniso):
     alpha = torch.zeros(V, H, W, device=dev)
     tfin = torch.zeros(V, H, W, device=dev)
     ncon = torch.zeros(V, H, W, dtype=torch.int32, device=dev)
-    cws = torch.empty(256, dtype=torch.uint8, device=dev)
+    cws = torch.zeros(B.composite_workspace(V, prm), dtype=torch.uint8, device=dev)
     B.composite(r, vals, ranges, V, prm, cws, rgb, depth, alpha, tfin, ncon)
     torch.cuda.synchronize()
+    # the call leaves its queue counters at zero, and a second call over the
+    # same workspace gives the same images
+    assert int(cws.to(torch.int32).abs().sum().item()) == 0, "composite workspace not returned to zero"
+    rgb2 = torch.full_like(rgb, -1.0)
+    ncon2 = torch.full_like(ncon, -1)
+    B.composite(r, vals, ranges, V, prm, cws, rgb2, depth, alpha, tfin, ncon2)
+    torch.cuda.synchronize()
+    assert torch.equal(rgb, rgb2) and torch.equal(ncon, ncon2)
     gimg = np.concatenate([rgb.cpu().numpy(), depth.cpu().numpy()[..., None], alpha.cpu().numpy()[..., None]],
                           -1).astype(np.float64)
     ok, idx = pixel_match(gimg, cands, ncand)
