@@ -11,7 +11,7 @@
 // only ever waits for partitions that a running workgroup already holds
 // (forward progress); the grid is sized to the machine, not the capacity.  Each partition publishes per-digit counts in one 32-bit word
 // (2 flag bits + 30 count bits) with agent-scope atomics, because the eight
-// XCDs have private L2s.  The look-back reads 16 predecessor statuses per
+// XCDs have private L2s.  The look-back reads 64 predecessor statuses per
 // round trip (all partitions of a pass run at once on this size of problem,
 // so a one-at-a-time walk would serialise); a lane that meets an unpublished
 // predecessor sleeps briefly and polls again.  The scatter is staged through
@@ -28,7 +28,7 @@ constexpr int kSortBlock = 512;
 constexpr int kSortWaves = kSortBlock / 64;
 constexpr int kSortItems = 8;
 constexpr int kSortPart = kSortBlock * kSortItems;  // 4096 keys per partition
-constexpr int kLookback = 16;                       // predecessor statuses read per round trip
+constexpr int kLookback = 64;                       // predecessor statuses read per round trip
 constexpr int kEmitLane = 32;                       // larger rects are emitted by the whole wave
 constexpr int kRadixBits = 8;
 constexpr int kBins = 1 << kRadixBits;
