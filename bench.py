@@ -144,76 +144,73 @@ def bench_forward(args, dev, timer_steps):
 
 
 def bench_fwd_bwd(args, dev, steps):
+    """Forward + backward of one 256x256 view of a 500k-Gaussian SH3 room:
+    L = sum |rgb - rgb*|^2 + sum (D - D*)^2 against the render of the
+    perturbed parameters; one step = forward, loss adjoint, backward with dense
+    gradients of every parameter."""
     import torch
     from paper_2604_12626_amd import render, synth
-    cfg = synth.config(1)
+    cfg = synth.config(2)
     g = cfg["segments"][0]
     segs = [to_dev(g, dev)]
+    tgt = [to_dev(synth.perturb(g, cfg["perturb_rng"]), dev)]
     cams = torch.from_numpy(cfg["cams"]).to(dev)
     vs = [[0]]
-    r = render.Renderer(cfg["W"], cfg["H"], capacity=1 << 22, device=dev)
-    f = r.render(segs, cams, vs)
-    target = torch.rand_like(f.rgb)
+    r = render.Renderer(cfg["W"], cfg["H"], capacity=1 << 21, device=dev)
+    ft = r.render(tgt, cams, vs)
+    rgb_t, depth_t = ft.rgb.clone(), ft.depth.clone()
+    r.render(segs, cams, vs)  # sizes the key capacity for the timed parameters
 
     def step():
         f2 = r.render(segs, cams, vs, sync_check=False)
-        d_rgb = 2.0 * (f2.rgb - target)
-        r.backward(segs, cams, vs, f2, d_rgb, None, None)
+        r.backward(segs, cams, vs, f2, 2.0 * (f2.rgb - rgb_t), 2.0 * (f2.depth - depth_t), None)
 
-    for _ in range(max(2, args.warmup // 2)):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        step()
-    torch.cuda.synchronize()
-    return (time.perf_counter() - t0) * 1e3 / steps
+    ms = _time_seq(step, max(2, args.warmup // 2), steps)
+    assert int(r._bufs["ovf"][0].item()) == 0
+    return ms
 
 
-_CFG4 = []
-
-
-def config4():
-    from paper_2604_12626_amd import synth
-    if not _CFG4:
-        _CFG4.append(synth.config(4))
-    return _CFG4[0]
-
-
-def bench_batched(args, dev, steps, n_views=16):
-    """n_views views at 640x480 of the 1M room: one batched call vs the same
+def bench_batched(args, dev, steps):
+    """64 views at 256x256 of 8 room scenes (view v shows scene v mod 8,
+    scenes of 1e5..2e6 Gaussians): one batched call (scene-major projection,
+    one sort and one persistent compositing launch for all views) vs the same
     views rendered one call at a time (plain)."""
     import torch
-    from paper_2604_12626_amd import render
-    cfg = config4()
-    room = to_dev(cfg["segments"][0], dev)
-    cams = torch.from_numpy(cfg["cams"][:n_views]).to(dev)
+    from paper_2604_12626_amd import autotune, render, synth
+    cfg = synth.config(3)
+    segs = [to_dev(g, dev) for g in cfg["segments"]]
+    cams = torch.from_numpy(cfg["cams"]).to(dev)
+    vs = cfg["view_segs"]
     W, H = cfg["W"], cfg["H"]
     rb = render.Renderer(W, H, capacity=1 << 24, device=dev)
-    vs = [[0]] * n_views
-    fb = rb.render([room], cams, vs)
-    ms_b = _time_seq(lambda: rb.enqueue([room], cams, vs, fb), args.warmup, steps)
+    fb = rb.render(segs, cams, vs)
+    best, _ = autotune.tune_composite(rb, fb, len(vs))
+    ms_b = _time_seq(lambda: rb.enqueue(segs, cams, vs, fb), args.warmup, steps)
     plain = []
-    for v in range(n_views):
-        rp = render.Renderer(W, H, capacity=1 << 22, device=dev)
-        fp = rp.render([room], cams[v:v + 1], [[0]])
-        plain.append((rp, fp, v))
+    for v in range(len(vs)):
+        rp = render.Renderer(W, H, capacity=1 << 20, device=dev)
+        sv = [segs[vs[v][0]]]
+        fp = rp.render(sv, cams[v:v + 1], [[0]])
+        plain.append((rp, fp, sv, v))
 
     def all_plain():
-        for rp, fp, v in plain:
-            rp.enqueue([room], cams[v:v + 1], [[0]], fp)
+        for rp, fp, sv, v in plain:
+            rp.enqueue(sv, cams[v:v + 1], [[0]], fp)
 
     ms_p = _time_seq(all_plain, args.warmup, steps)
-    assert int(fb.overflow.item()) == 0 and all(int(fp.overflow.item()) == 0 for _, fp, _ in plain)
-    return ms_b, ms_p, n_views
+    assert int(fb.overflow.item()) == 0 and all(int(fp.overflow.item()) == 0 for _, fp, _, _ in plain)
+    return ms_b, ms_p, len(vs), int(fb.num.item()), best
 
 
 def bench_avatars(args, dev, steps):
-    """Workload with avatars: LBS of 8 x 50k avatar Gaussians, then 16 views at
-    640x480 of room + avatars in one call."""
+    """1M room + 8 avatars x 50k Gaussians, 16 views at 640x480: LBS of the
+    avatar Gaussians, then all views of room + posed avatars in one call
+    (forward), and the same with the backward through the renderer and LBS
+    to the canonical avatar parameters (fwd+bwd)."""
     import torch
     from paper_2604_12626_amd import binding as B, render
-    cfg = config4()
+    from paper_2604_12626_amd import synth
+    cfg = synth.config(4)
     room = to_dev(cfg["segments"][0], dev)
     av = to_dev(cfg["avatars"], dev)
     skin = torch.from_numpy(cfg["skin"]).to(dev)
@@ -223,6 +220,9 @@ def bench_avatars(args, dev, steps):
     cams = torch.from_numpy(cfg["cams"]).to(dev)
     vs = cfg["view_segs"]
     r = render.Renderer(cfg["W"], cfg["H"], capacity=1 << 24, device=dev)
+    d_means = torch.empty(n_av, 3, device=dev)
+    d_ls = torch.empty(n_av, 3, device=dev)
+    d_q = torch.empty(n_av, 4, device=dev)
 
     def lbs():
         B.deform_lbs(av["means"], av["log_scales"], av["quats"], av["joint_idx"], av["weights"], av["avatar_of"],
@@ -230,14 +230,23 @@ def bench_avatars(args, dev, steps):
 
     lbs()
     f = r.render([room, posed], cams, vs)
+    target = torch.rand_like(f.rgb)
 
     def frame():
         lbs()
         r.enqueue([room, posed], cams, vs, f)
 
+    def frame_bwd():
+        lbs()
+        r.enqueue([room, posed], cams, vs, f)
+        gr = r.backward([room, posed], cams, vs, f, 2.0 * (f.rgb - target), None, None)
+        B.deform_lbs_backward(av["means"], av["log_scales"], av["quats"], av["joint_idx"], av["weights"],
+                              av["avatar_of"], skin, gr[1]["means"], gr[1]["cov6"], d_means, d_ls, d_q)
+
     ms = _time_seq(frame, args.warmup, steps)
+    ms_b = _time_seq(frame_bwd, max(2, args.warmup // 2), max(3, steps // 2))
     assert int(f.overflow.item()) == 0
-    return ms, len(vs)
+    return ms, ms_b, len(vs)
 
 
 def _time_seq(fn, warmup, steps):
@@ -346,15 +355,18 @@ def main():
               "stage_hbm_frac": {k: info["alg_bytes"][k] / (st[k] * 1e-3) / 1e9 / HBM_PEAK_GBS for k in st}}
     if not args.profile and not args.no_extras:
         steps2 = max(5, args.steps // 5)
-        log("fwd+bwd")
-        extras["fwd_bwd_fps"] = 1e3 / bench_fwd_bwd(args, dev, steps2)
-        log("batched vs plain")
-        ms_b, ms_p, nv = bench_batched(args, dev, steps2)
-        extras["batched_16x640x480_fps"] = nv * 1e3 / ms_b
-        extras["plain_16x640x480_fps"] = nv * 1e3 / ms_p
-        log("avatars")
-        ms_a, nva = bench_avatars(args, dev, steps2)
-        extras["avatars_16x640x480_fps"] = nva * 1e3 / ms_a
+        log("fwd+bwd: 256x256, 500k Gaussians")
+        extras["fwd_bwd_256x256_500k_fps"] = 1e3 / bench_fwd_bwd(args, dev, steps2)
+        log("batched vs plain: 64 views x 256x256, 8 scenes")
+        ms_b, ms_p, nv, kb, best = bench_batched(args, dev, steps2)
+        extras["batched_64x256x256_8scenes_fps"] = nv * 1e3 / ms_b
+        extras["plain_64x256x256_8scenes_fps"] = nv * 1e3 / ms_p
+        extras["batched_tile_instances"] = kb
+        extras["batched_composite_groups_per_cu"] = best
+        log("avatars: 1M room + 8 x 50k avatars, 16 views x 640x480")
+        ms_a, ms_ab, nva = bench_avatars(args, dev, steps2)
+        extras["avatars_16x640x480_fwd_fps"] = nva * 1e3 / ms_a
+        extras["avatars_16x640x480_fwd_bwd_fps"] = nva * 1e3 / ms_ab
     cpu, pairs = None, None
     if not args.profile and not args.no_cpu_baseline:
         log("cpu baseline (oracle)")

@@ -122,3 +122,19 @@ def test_lbs_and_composite_validation(lib):
     assert st == B.GS_ERR_WORKSPACE_TOO_SMALL
     st = lib.gs_composite(ctypes.byref(proj), None, a, 1, ctypes.byref(p), a, 256, a, a, a, None, None, None)
     assert st == B.GS_ERR_INVALID_ARGUMENT
+
+
+def test_tuning_validation():
+    from paper_2604_12626_amd import binding as B
+    prev = B.get_tuning()
+    try:
+        with pytest.raises(B.GSError):
+            B.set_tuning(0)
+        with pytest.raises(B.GSError):
+            B.set_tuning(33)
+        B.set_tuning(5)
+        assert B.get_tuning()["composite_groups_per_cu"] == 5
+        B.set_tuning(None)
+        assert B.get_tuning()["composite_groups_per_cu"] == 8
+    finally:
+        B.set_tuning(prev["composite_groups_per_cu"])

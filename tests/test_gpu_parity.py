@@ -251,6 +251,33 @@ def test_render_deterministic_and_batched_equals_plain(dev):
         assert torch.equal(f1.alpha[0], a1[2][k])
 
 
+def test_composite_schedule_does_not_change_results(dev):
+    """Every launch configuration the autotuner may pick (persistent groups
+    per CU) gives bit-identical images; the tuner leaves one of them set."""
+    import torch
+    from paper_2604_12626_amd import autotune, binding as B, render
+    cfg = synth.config(3, scale=0.02)
+    W, H = cfg["W"], cfg["H"]
+    segs = [to_dev(g, dev) for g in cfg["segments"]]
+    cams = torch.from_numpy(cfg["cams"][:12]).to(dev)
+    vs = cfg["view_segs"][:12]
+    r = render.Renderer(W, H, capacity=1 << 18, device=dev)
+    prev = B.set_tuning(8)
+    try:
+        f = r.render(segs, cams, vs)
+        ref = (f.rgb.clone(), f.depth.clone(), f.n_contrib.clone())
+        for c in (1, 3, 32):
+            say("composite groups per CU", c)
+            B.set_tuning(c)
+            r.composite(f, len(vs))
+            torch.cuda.synchronize()
+            assert torch.equal(f.rgb, ref[0]) and torch.equal(f.depth, ref[1]) and torch.equal(f.n_contrib, ref[2])
+        best, times = autotune.tune_composite(r, f, len(vs), candidates=(2, 8), reps=2)
+        assert best in (2, 8) and B.get_tuning()["composite_groups_per_cu"] == best
+    finally:
+        B.set_tuning(prev["composite_groups_per_cu"])
+
+
 def test_union_equals_concatenation(dev):
     import torch
     from paper_2604_12626_amd import render
