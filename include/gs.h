@@ -136,14 +136,22 @@ int32_t gs_version(void);
 void gs_default_params(gs_params *p, int32_t width, int32_t height);
 
 /* Launch configuration (host-side, process-wide; it changes scheduling only,
- * never a result).  composite_groups_per_cu: persistent 4-wave groups per
- * compute unit in gs_composite (1..32, default 8); each wave of the grid pops
- * (view, tile, quadrant) work items until none is left.  gs_set_tuning(NULL)
- * restores the defaults; invalid values return GS_ERR_INVALID_ARGUMENT.  Meant
- * for an autotuner that times the candidates on the target workload. */
+ * never a result).
+ *  composite_groups_per_cu: persistent 4-wave groups per compute unit in
+ *    gs_composite (1..32, default 8); each wave of the grid pops (view, tile,
+ *    quadrant) work items until none is left.
+ *  sort_partition_keys: keys per onesweep partition in gs_bin_sort (4096 or
+ *    8192, default 8192).
+ *  sort_lookback: predecessor partitions read per round trip of the onesweep
+ *    look-back (16, 32 or 64, default 16).
+ * gs_set_tuning(NULL) restores the defaults; invalid values return
+ * GS_ERR_INVALID_ARGUMENT and change nothing.  Meant for an autotuner that
+ * times the candidates on the target workload. */
 typedef struct gs_tuning {
     int32_t composite_groups_per_cu;
-    int32_t reserved[7];
+    int32_t sort_partition_keys;
+    int32_t sort_lookback;
+    int32_t reserved[5];
 } gs_tuning;
 gs_status gs_set_tuning(const gs_tuning *t);
 void gs_get_tuning(gs_tuning *t);

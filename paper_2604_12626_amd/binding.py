@@ -51,7 +51,11 @@ class Projected(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("composite_groups_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+    _fields_ = [("composite_groups_per_cu", ctypes.c_int32), ("sort_partition_keys", ctypes.c_int32),
+                ("sort_lookback", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+
+
+TUNING_FIELDS = ("composite_groups_per_cu", "sort_partition_keys", "sort_lookback")
 
 
 EXPORTS = ["gs_status_string", "gs_last_error", "gs_version", "gs_default_params", "gs_set_tuning", "gs_get_tuning",
@@ -263,21 +267,29 @@ def deform_lbs_backward(means_c, log_scales_c, quats_c, joint_idx, weights, avat
                                       ptr(d_quats), stream_handle()))
 
 
-def set_tuning(composite_groups_per_cu=None):
-    """Set (or with None restore) the launch configuration; returns the previous one."""
+def set_tuning(composite_groups_per_cu=None, **kw):
+    """Set launch knobs (others keep their current values); with no
+    arguments, restore the defaults.  Returns the previous configuration."""
     lib = load()
-    prev = Tuning()
-    lib.gs_get_tuning(ctypes.byref(prev))
-    if composite_groups_per_cu is None:
+    prev = get_tuning()
+    if composite_groups_per_cu is None and not kw:
         _check(lib.gs_set_tuning(None))
-    else:
-        t = Tuning()
-        t.composite_groups_per_cu = int(composite_groups_per_cu)
-        _check(lib.gs_set_tuning(ctypes.byref(t)))
-    return {"composite_groups_per_cu": prev.composite_groups_per_cu}
+        return prev
+    cur = dict(prev)
+    if composite_groups_per_cu is not None:
+        cur["composite_groups_per_cu"] = composite_groups_per_cu
+    for k, v in kw.items():
+        if k not in TUNING_FIELDS:
+            raise KeyError(k)
+        cur[k] = v
+    t = Tuning()
+    for k in TUNING_FIELDS:
+        setattr(t, k, int(cur[k]))
+    _check(lib.gs_set_tuning(ctypes.byref(t)))
+    return prev
 
 
 def get_tuning():
     t = Tuning()
     load().gs_get_tuning(ctypes.byref(t))
-    return {"composite_groups_per_cu": t.composite_groups_per_cu}
+    return {k: int(getattr(t, k)) for k in TUNING_FIELDS}

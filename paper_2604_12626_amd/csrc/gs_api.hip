@@ -104,6 +104,8 @@ int64_t seg_offset_in_view(const gs_gaussians *segs, uint32_t mask, int s) {
 }
 
 std::atomic<int> g_comp_groups{8};
+std::atomic<int> g_sort_part_keys{8192};
+std::atomic<int> g_sort_lookback{16};
 
 std::mutex g_dev_mu;
 int g_cu_count[64] = {0};
@@ -157,11 +159,19 @@ gs_status gs_set_tuning(const gs_tuning *t) {
     clear_error();
     if (!t) {
         g_comp_groups.store(8);
+        g_sort_part_keys.store(8192);
+        g_sort_lookback.store(16);
         return GS_OK;
     }
     if (t->composite_groups_per_cu < 1 || t->composite_groups_per_cu > 32)
         return fail(GS_ERR_INVALID_ARGUMENT, "composite_groups_per_cu=%d outside [1, 32]", t->composite_groups_per_cu);
+    if (t->sort_partition_keys != 4096 && t->sort_partition_keys != 8192)
+        return fail(GS_ERR_INVALID_ARGUMENT, "sort_partition_keys=%d (4096 or 8192)", t->sort_partition_keys);
+    if (t->sort_lookback != 16 && t->sort_lookback != 32 && t->sort_lookback != 64)
+        return fail(GS_ERR_INVALID_ARGUMENT, "sort_lookback=%d (16, 32 or 64)", t->sort_lookback);
     g_comp_groups.store(t->composite_groups_per_cu);
+    g_sort_part_keys.store(t->sort_partition_keys);
+    g_sort_lookback.store(t->sort_lookback);
     return GS_OK;
 }
 
@@ -169,6 +179,8 @@ void gs_get_tuning(gs_tuning *t) {
     if (!t) return;
     memset(t, 0, sizeof(*t));
     t->composite_groups_per_cu = g_comp_groups.load();
+    t->sort_partition_keys = g_sort_part_keys.load();
+    t->sort_lookback = g_sort_lookback.load();
 }
 
 gs_status gs_instance_offsets(const gs_gaussians *segs, int32_t n_segs, int32_t n_views,
@@ -325,7 +337,9 @@ gs_status gs_bin_sort(const gs_projected *proj, int32_t n_views, const gs_params
         return fail(GS_ERR_INVALID_ARGUMENT, "keys/ranges/counter need 8-byte, ws 256-byte alignment");
     const int64_t T = (int64_t)tiles_x(p) * tiles_y(p);
     if (T * n_views > (1ll << 31)) return fail(GS_ERR_UNSUPPORTED, "more than 2^31 tiles");
-    const gs::SortPlan plan = gs::make_sort_plan(proj->n_instances, capacity, T * n_views);
+    gs::SortPlan plan = gs::make_sort_plan(proj->n_instances, capacity, T * n_views);
+    plan.part_keys = g_sort_part_keys.load();
+    plan.lookback = g_sort_lookback.load();
     if (ws_bytes < plan.total)
         return fail(GS_ERR_WORKSPACE_TOO_SMALL, "workspace %zu < %zu bytes", ws_bytes, plan.total);
     hipError_t e = gs::run_bin_sort(plan, proj->tiles_touched, reinterpret_cast<const float4 *>(proj->rec),
@@ -338,7 +352,7 @@ gs_status gs_bin_sort(const gs_projected *proj, int32_t n_views, const gs_params
 size_t gs_composite_workspace(int32_t n_views, const gs_params *p) {
     (void)n_views;
     (void)p;
-    return 256;
+    return 2048;  // nine counters, one 128-B line each
 }
 
 gs_status gs_composite(const gs_projected *proj, const uint32_t *vals, const uint32_t *tile_ranges,

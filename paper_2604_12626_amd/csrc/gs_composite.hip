@@ -11,20 +11,23 @@
 // of different quadrants and tiles interleave on a SIMD and hide each other's
 // gather latency.  A wave leaves the list once its 64 pixels have stopped.
 //
-// Work queues are XCD-aware: the (view, tile) items are split into eight
-// contiguous ranges with a counter each, and a workgroup starts on the queue
-// of blockIdx.x mod 8 -- the XCD the dispatcher places it on -- so the four
-// quadrants of a tile, and neighbouring tiles that share Gaussians, are
-// gathered through one L2.  An exhausted queue sends its waves on to the next
-// queues (work stealing).  Placement only affects locality, never results.
-// The last wave to leave returns the counters to zero, so the workspace is
-// ready for the next call without a clearing launch.
+// Work queues are XCD-aware: queue q holds the (view, tile) items t with
+// t mod 8 == q (all four quadrants of each), and a workgroup starts on the
+// queue of blockIdx.x mod 8 -- the XCD the dispatcher places it on -- so the
+// four quadrant waves of a tile gather its list through one L2, while every
+// XCD still gets an even share of the image.  An exhausted queue sends its
+// waves on to the other queues (work stealing; a queue seen to be empty by a
+// plain load is skipped without an atomic).  Each queue head sits in its own
+// 128-B line.  Placement only affects locality, never results.  The last
+// workgroup to leave returns the counters to zero, so the workspace is ready
+// for the next call without a clearing launch.
 #include "gs_internal.hpp"
 
 namespace gs {
 
 constexpr int kWavesPerGroup = 4;
-constexpr int kQueues = 8;  // one per XCD
+constexpr int kQueues = 8;         // one per XCD
+constexpr int kCounterStride = 32;  // words between queue heads (one 128-B line each)
 
 __global__ void __launch_bounds__(64 * kWavesPerGroup) composite_kernel(const CompositeArgs a) {
     __shared__ float4 s_e0[kWavesPerGroup][64], s_e1[kWavesPerGroup][64], s_e2[kWavesPerGroup][64];
@@ -38,10 +41,16 @@ __global__ void __launch_bounds__(64 * kWavesPerGroup) composite_kernel(const Co
         if (lane == 0) {
             while (visited < kQueues) {
                 const int q = (home + visited) % kQueues;
-                const int64_t lo = 4 * ((a.n_items * q) / kQueues), hi = 4 * ((a.n_items * (q + 1)) / kQueues);
-                const int64_t k = lo + (int64_t)atomicAdd(a.counter + q, 1u);
-                if (k < hi) {
-                    item = k;
+                // queue q: tiles q, q + 8, q + 16, ... -> 4 quadrant items each
+                const uint32_t size = a.n_items > q ? (uint32_t)(4 * ((a.n_items - q + kQueues - 1) / kQueues)) : 0u;
+                uint32_t *head = a.counter + q * kCounterStride;
+                if (visited > 0 && __hip_atomic_load(head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= size) {
+                    ++visited;
+                    continue;
+                }
+                const uint32_t k = atomicAdd(head, 1u);
+                if (k < size) {
+                    item = (long long)(q + (int64_t)kQueues * (k >> 2)) * 4 + (k & 3);
                     break;
                 }
                 ++visited;
@@ -119,18 +128,19 @@ __global__ void __launch_bounds__(64 * kWavesPerGroup) composite_kernel(const Co
             if (a.n_contrib) a.n_contrib[pix] = last;
         }
     }
-    // every pop of every wave has happened once the last wave gets here
-    if (lane == 0) {
-        const uint32_t left = atomicAdd(a.counter + kQueues, 1u);
-        if (left == a.n_waves - 1u) {
-            for (int q = 0; q <= kQueues; ++q) atomicExch(a.counter + q, 0u);
+    // every pop of every wave has happened once the last workgroup gets here
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t left = atomicAdd(a.counter + kQueues * kCounterStride, 1u);
+        if (left == a.n_groups - 1u) {
+            for (int q = 0; q <= kQueues; ++q) atomicExch(a.counter + q * kCounterStride, 0u);
         }
     }
 }
 
 hipError_t launch_composite(CompositeArgs a, int grid, hipStream_t s) {
     if (a.n_items == 0 || grid <= 0) return hipSuccess;
-    a.n_waves = (uint32_t)grid * kWavesPerGroup;
+    a.n_groups = (uint32_t)grid;
     return launch_kernel(composite_kernel, dim3(grid), dim3(64 * kWavesPerGroup), s, a);
 }
 

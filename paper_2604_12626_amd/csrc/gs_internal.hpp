@@ -54,9 +54,9 @@ struct CompositeArgs {
     const float4 *rec;
     const uint32_t *vals;
     const uint2 *ranges;
-    uint32_t *counter;  // [8] queue heads + [1] waves finished; zero on entry and on exit
+    uint32_t *counter;  // 8 queue heads + workgroups finished, 128 B apart; zero on entry and on exit
     int64_t n_items;    // n_views * T
-    uint32_t n_waves;   // waves in the grid (set by the launcher)
+    uint32_t n_groups;  // workgroups in the grid (set by the launcher)
     int32_t W, H, TX, T;
     float alpha_max, alpha_min, t_min;
     float bg0, bg1, bg2;
@@ -95,9 +95,10 @@ struct LbsArgs {
 struct SortPlan {
     int64_t n, capacity, n_tiles_total;
     int tile_bits, passes;
+    int part_keys, lookback;  // onesweep partition size (4096 / 8192) and look-back window (16 / 32 / 64)
     int64_t scan_blocks, sort_parts;
     // workspace layout (byte offsets)
-    size_t off_offsets, off_part, off_keys2, off_vals2, off_hist, off_status, off_ticket, total;
+    size_t off_offsets, off_part, off_keys2, off_vals2, off_rows, off_hist, off_status, off_ticket, total;
 };
 
 // launchers (one per translation unit)

@@ -26,10 +26,10 @@ constexpr int kScanTile = kScanBlock * kScanItems;  // 4096 instances per block
 
 constexpr int kSortBlock = 512;
 constexpr int kSortWaves = kSortBlock / 64;
-constexpr int kSortItems = 8;
-constexpr int kSortPart = kSortBlock * kSortItems;  // 4096 keys per partition
-constexpr int kLookback = 64;                       // predecessor statuses read per round trip
+constexpr int kMinSortItems = 8;                    // partitions of 4096 or 8192 keys (tunable)
+constexpr int kMinSortPart = kSortBlock * kMinSortItems;
 constexpr int kEmitLane = 32;                       // larger rects are emitted by the whole wave
+constexpr int kEmitGrid = 512;                      // emission workgroups (grid-stride over instances)
 constexpr int kRadixBits = 8;
 constexpr int kBins = 1 << kRadixBits;
 constexpr int kMaxPasses = 8;
@@ -205,69 +205,87 @@ __device__ __forceinline__ void hist_add_row(uint32_t (*h)[kHistStride], int pas
 // are emitted by the whole wave, 64 keys per step) fused with the digit
 // histograms of every sort pass: the four depth bytes are the same for all
 // keys of an instance (counted once with weight tiles_touched) and the tile
-// bytes are counted per rect row.
+// bytes are counted per rect row.  A fixed grid strides over the instances;
+// each workgroup leaves its histograms as one row of `rows` (plain stores),
+// and hist_reduce_kernel sums the rows -- no global atomics.
 __global__ void __launch_bounds__(256) emit_kernel(const uint32_t *tt, const uint32_t *offsets, const float4 *rec,
                                                    int64_t n, int TX, int TY, int64_t capacity, uint64_t *keys,
-                                                   uint32_t *vals, int passes, uint32_t *hist /*[passes][257]*/) {
+                                                   uint32_t *vals, int passes, uint32_t *rows /*[grid][passes*257]*/,
+                                                   int64_t stride) {
     __shared__ uint32_t s_h[kMaxPasses][kHistStride];
     for (int k = threadIdx.x; k < kMaxPasses * kHistStride; k += 256) (&s_h[0][0])[k] = 0u;
     __syncthreads();
-    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int lane = threadIdx.x & 63;
-    const uint32_t t = (g < n) ? tt[g] : 0u;
-    const int64_t k0 = t ? (int64_t)offsets[g] : capacity;
-    const bool live = t && k0 < capacity;
-    Rect R = {0, 0, 0, 0};
-    uint64_t tbase = 0, depth_bits = 0;
-    if (live) {
-        const float4 q0 = rec[3 * g];
-        const int view = __float_as_int(rec[3 * g + 2].w);
-        R = tile_rect(q0.x, q0.y, __float_as_int(q0.w), TX, TY);
-        depth_bits = (uint64_t)__float_as_uint(q0.z);
-        tbase = (uint64_t)view * (uint64_t)(TX * TY);
+    for (int64_t base = (int64_t)blockIdx.x * 256; base < n; base += stride) {  // uniform per workgroup
+        const int64_t g = base + threadIdx.x;
+        const uint32_t t = (g < n) ? tt[g] : 0u;
+        const int64_t k0 = t ? (int64_t)offsets[g] : capacity;
+        const bool live = t && k0 < capacity;
+        Rect R = {0, 0, 0, 0};
+        uint64_t tbase = 0, depth_bits = 0;
+        if (live) {
+            const float4 q0 = rec[3 * g];
+            const int view = __float_as_int(rec[3 * g + 2].w);
+            R = tile_rect(q0.x, q0.y, __float_as_int(q0.w), TX, TY);
+            depth_bits = (uint64_t)__float_as_uint(q0.z);
+            tbase = (uint64_t)view * (uint64_t)(TX * TY);
 #pragma unroll
-        for (int p = 0; p < 4; ++p) hist_add(s_h[p], (uint32_t)(depth_bits >> (8 * p)) & 255u, t);
-        for (int ty = R.y0; ty < R.y1; ++ty)
-            hist_add_row(s_h, passes, tbase + (uint64_t)(ty * TX + R.x0), (uint32_t)(R.x1 - R.x0));
-    }
-    if (live && t <= (uint32_t)kEmitLane) {
-        int64_t k = k0;
-        for (int ty = R.y0; ty < R.y1; ++ty)
-            for (int tx = R.x0; tx < R.x1; ++tx) {
-                if (k < capacity) {
-                    keys[k] = ((tbase + (uint64_t)(ty * TX + tx)) << 32) | depth_bits;
-                    vals[k] = (uint32_t)g;
+            for (int p = 0; p < 4; ++p) hist_add(s_h[p], (uint32_t)(depth_bits >> (8 * p)) & 255u, t);
+            for (int ty = R.y0; ty < R.y1; ++ty)
+                hist_add_row(s_h, passes, tbase + (uint64_t)(ty * TX + R.x0), (uint32_t)(R.x1 - R.x0));
+        }
+        if (live && t <= (uint32_t)kEmitLane) {
+            int64_t k = k0;
+            for (int ty = R.y0; ty < R.y1; ++ty)
+                for (int tx = R.x0; tx < R.x1; ++tx) {
+                    if (k < capacity) {
+                        keys[k] = ((tbase + (uint64_t)(ty * TX + tx)) << 32) | depth_bits;
+                        vals[k] = (uint32_t)g;
+                    }
+                    ++k;
                 }
-                ++k;
+        }
+        // rects of more than kEmitLane tiles: the wave emits them one at a
+        // time, 64 consecutive keys per step (row-major tile order as above)
+        uint64_t big = __ballot(live && t > (uint32_t)kEmitLane);
+        while (big) {
+            const int src = __ffsll((unsigned long long)big) - 1;
+            big &= big - 1;
+            const int x0 = __shfl(R.x0, src, 64), x1 = __shfl(R.x1, src, 64);
+            const int y0 = __shfl(R.y0, src, 64), y1 = __shfl(R.y1, src, 64);
+            const int64_t kb = __shfl((long long)k0, src, 64);
+            const uint64_t tb = (uint64_t)__shfl((unsigned long long)tbase, src, 64);
+            const uint64_t db = (uint64_t)__shfl((unsigned long long)depth_bits, src, 64);
+            const uint32_t gg = (uint32_t)__shfl((long long)g, src, 64);
+            const int w = x1 - x0;
+            const int total = w * (y1 - y0);
+            for (int j = lane; j < total; j += 64) {
+                const int64_t k = kb + j;
+                if (k >= capacity) break;
+                const int ty = y0 + j / w, tx = x0 + j % w;
+                keys[k] = ((tb + (uint64_t)(ty * TX + tx)) << 32) | db;
+                vals[k] = gg;
             }
-    }
-    // rects of more than kEmitLane tiles: the wave emits them one at a time,
-    // 64 consecutive keys per step (row-major tile order as above)
-    uint64_t big = __ballot(live && t > (uint32_t)kEmitLane);
-    while (big) {
-        const int src = __ffsll((unsigned long long)big) - 1;
-        big &= big - 1;
-        const int x0 = __shfl(R.x0, src, 64), x1 = __shfl(R.x1, src, 64);
-        const int y0 = __shfl(R.y0, src, 64), y1 = __shfl(R.y1, src, 64);
-        const int64_t kb = __shfl((long long)k0, src, 64);
-        const uint64_t tb = (uint64_t)__shfl((unsigned long long)tbase, src, 64);
-        const uint64_t db = (uint64_t)__shfl((unsigned long long)depth_bits, src, 64);
-        const uint32_t gg = (uint32_t)__shfl((long long)g, src, 64);
-        const int w = x1 - x0;
-        const int total = w * (y1 - y0);
-        for (int j = lane; j < total; j += 64) {
-            const int64_t k = kb + j;
-            if (k >= capacity) break;
-            const int ty = y0 + j / w, tx = x0 + j % w;
-            keys[k] = ((tb + (uint64_t)(ty * TX + tx)) << 32) | db;
-            vals[k] = gg;
         }
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < passes * kHistStride; k += 256) {
-        const uint32_t v = (&s_h[0][0])[k];
-        if (v) atomicAdd(&hist[k], v);
-    }
+    uint32_t *row = rows + (size_t)blockIdx.x * passes * kHistStride;
+    for (int k = threadIdx.x; k < passes * kHistStride; k += 256) row[k] = (&s_h[0][0])[k];
+}
+
+// hist[c] = sum over the emission workgroups' rows of column c
+__global__ void __launch_bounds__(256) hist_reduce_kernel(const uint32_t *rows, int n_rows, int n_cols,
+                                                          uint32_t *hist) {
+    __shared__ uint32_t s_part[4][64];
+    const int c = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int r0 = threadIdx.x >> 6;  // four row lanes
+    uint32_t acc = 0u;
+    if (c < n_cols)
+        for (int r = r0; r < n_rows; r += 4) acc += rows[(size_t)r * n_cols + c];
+    s_part[r0][threadIdx.x & 63] = acc;
+    __syncthreads();
+    if (threadIdx.x < 64 && c < n_cols) hist[c] = s_part[0][threadIdx.x] + s_part[1][threadIdx.x] +
+                                                  s_part[2][threadIdx.x] + s_part[3][threadIdx.x];
 }
 
 // ---------------------------------------------------------------------------
@@ -278,6 +296,7 @@ __device__ __forceinline__ int64_t sort_count(const int64_t *d_num, int64_t capa
     return k < capacity ? k : capacity;
 }
 
+template <int ITEMS, int LOOKBACK>
 __global__ void __launch_bounds__(kSortBlock) onesweep_kernel(const uint64_t *__restrict__ keys_in,
                                                               const uint32_t *__restrict__ vals_in,
                                                               uint64_t *__restrict__ keys_out,
@@ -292,8 +311,8 @@ __global__ void __launch_bounds__(kSortBlock) onesweep_kernel(const uint64_t *__
     __shared__ uint32_t s_glob[kBins];            // global start of the digit for this partition
     __shared__ uint32_t s_scan[kBins];
     __shared__ uint32_t s_base[kBins];            // global start of each digit in this pass
-    __shared__ uint64_t s_keys[kSortPart];
-    __shared__ uint32_t s_vals[kSortPart];
+    __shared__ uint64_t s_keys[kSortBlock * ITEMS];
+    __shared__ uint32_t s_vals[kSortBlock * ITEMS];
 
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
@@ -322,25 +341,25 @@ __global__ void __launch_bounds__(kSortBlock) onesweep_kernel(const uint64_t *__
         for (int k = tid; k < kSortWaves * kBins; k += kSortBlock) (&s_wh[0][0])[k] = 0u;
         __syncthreads();
         const uint32_t part = s_part;
-        const int64_t start = (int64_t)part * kSortPart;
+        const int64_t start = (int64_t)part * (kSortBlock * ITEMS);
         if (start >= K) return;  // uniform across the workgroup
 
-        uint64_t key[kSortItems];
-        uint32_t val[kSortItems];
-        uint32_t rank[kSortItems];
-        uint32_t dig[kSortItems];
+        uint64_t key[ITEMS];
+        uint32_t val[ITEMS];
+        uint32_t rank[ITEMS];
+        uint32_t dig[ITEMS];
         // all loads first (independent, in flight together), then the ranking
         // (whose LDS fences would otherwise serialise one load per stripe)
 #pragma unroll
-        for (int j = 0; j < kSortItems; ++j) {
-            const int64_t idx = start + (int64_t)wave * (kSortItems * 64) + j * 64 + lane;
+        for (int j = 0; j < ITEMS; ++j) {
+            const int64_t idx = start + (int64_t)wave * (ITEMS * 64) + j * 64 + lane;
             const bool valid = idx < K;
             key[j] = valid ? keys_in[idx] : ~0ull;
             val[j] = valid ? vals_in[idx] : 0u;
         }
 #pragma unroll
-        for (int j = 0; j < kSortItems; ++j) {
-            const int64_t idx = start + (int64_t)wave * (kSortItems * 64) + j * 64 + lane;
+        for (int j = 0; j < ITEMS; ++j) {
+            const int64_t idx = start + (int64_t)wave * (ITEMS * 64) + j * 64 + lane;
             const bool valid = idx < K;
             const uint32_t d = (uint32_t)(key[j] >> shift) & (kBins - 1);
             dig[j] = valid ? d : 0xFFFFFFFFu;
@@ -378,7 +397,7 @@ __global__ void __launch_bounds__(kSortBlock) onesweep_kernel(const uint64_t *__
             }
             total = run;
             // decoupled look-back: publish the aggregate, then walk back over
-            // the predecessors kLookback at a time until an inclusive prefix
+            // the predecessors LOOKBACK at a time until an inclusive prefix
             uint32_t *col = status + d;
             uint32_t prefix = 0u;
             if (part == 0) {
@@ -388,16 +407,16 @@ __global__ void __launch_bounds__(kSortBlock) onesweep_kernel(const uint64_t *__
                                    __HIP_MEMORY_SCOPE_AGENT);
                 int64_t p = (int64_t)part - 1;
                 while (true) {
-                    uint32_t w[kLookback];
+                    uint32_t w[LOOKBACK];
 #pragma unroll
-                    for (int i = 0; i < kLookback; ++i)
+                    for (int i = 0; i < LOOKBACK; ++i)
                         w[i] = (p - i >= 0) ? __hip_atomic_load(col + (size_t)(p - i) * kBins, __ATOMIC_RELAXED,
                                                                 __HIP_MEMORY_SCOPE_AGENT)
                                             : kFlagIncl;  // never reached: partition 0 is inclusive
                     bool stop = false, incl = false;
                     int consumed = 0;
 #pragma unroll
-                    for (int i = 0; i < kLookback; ++i) {
+                    for (int i = 0; i < LOOKBACK; ++i) {
                         if (!stop) {
                             const uint32_t flag = w[i] & ~kCountMask;
                             if (flag == 0u) {
@@ -414,7 +433,7 @@ __global__ void __launch_bounds__(kSortBlock) onesweep_kernel(const uint64_t *__
                     }
                     if (incl) break;
                     p -= consumed;
-                    if (consumed < kLookback) __builtin_amdgcn_s_sleep(1);
+                    if (consumed < LOOKBACK) __builtin_amdgcn_s_sleep(1);
                 }
                 __hip_atomic_store(col + (size_t)part * kBins, kFlagIncl | (prefix + total), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
@@ -435,7 +454,7 @@ __global__ void __launch_bounds__(kSortBlock) onesweep_kernel(const uint64_t *__
         __syncthreads();
         // stage into LDS in block-local sorted order
 #pragma unroll
-        for (int j = 0; j < kSortItems; ++j) {
+        for (int j = 0; j < ITEMS; ++j) {
             if (dig[j] != 0xFFFFFFFFu) {
                 const uint32_t pos = s_local[dig[j]] + s_wh[wave][dig[j]] + rank[j];
                 s_keys[pos] = key[j];
@@ -445,7 +464,7 @@ __global__ void __launch_bounds__(kSortBlock) onesweep_kernel(const uint64_t *__
         __syncthreads();
         // each digit's run leaves as one contiguous stretch
         const int64_t nvalid64 = K - start;
-        const int nvalid = nvalid64 < kSortPart ? (int)nvalid64 : kSortPart;
+        const int nvalid = nvalid64 < kSortBlock * ITEMS ? (int)nvalid64 : kSortBlock * ITEMS;
         for (int q = tid; q < nvalid; q += kSortBlock) {
             const uint64_t kk = s_keys[q];
             const uint32_t dd = (uint32_t)(kk >> shift) & (kBins - 1);
@@ -483,6 +502,8 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 SortPlan make_sort_plan(int64_t n, int64_t capacity, int64_t n_tiles_total) {
     SortPlan p;
+    p.part_keys = kMinSortPart;
+    p.lookback = 16;
     p.n = n;
     p.capacity = capacity;
     p.n_tiles_total = n_tiles_total;
@@ -492,7 +513,7 @@ SortPlan make_sort_plan(int64_t n, int64_t capacity, int64_t n_tiles_total) {
     p.passes = (32 + tb + kRadixBits - 1) / kRadixBits;
     p.scan_blocks = (n + kScanTile - 1) / kScanTile;
     if (p.scan_blocks < 1) p.scan_blocks = 1;
-    p.sort_parts = (capacity + kSortPart - 1) / kSortPart;
+    p.sort_parts = (capacity + kMinSortPart - 1) / kMinSortPart;
     if (p.sort_parts < 1) p.sort_parts = 1;
     size_t o = 0;
     p.off_offsets = o;
@@ -503,6 +524,8 @@ SortPlan make_sort_plan(int64_t n, int64_t capacity, int64_t n_tiles_total) {
     o = align256(o + sizeof(uint64_t) * (size_t)(capacity > 0 ? capacity : 1));
     p.off_vals2 = o;
     o = align256(o + sizeof(uint32_t) * (size_t)(capacity > 0 ? capacity : 1));
+    p.off_rows = o;
+    o = align256(o + sizeof(uint32_t) * (size_t)kEmitGrid * p.passes * kHistStride);
     // hist, status and tickets are contiguous so one fill clears them
     p.off_hist = o;
     o = o + sizeof(uint32_t) * (size_t)kMaxPasses * kHistStride;
@@ -523,6 +546,7 @@ hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec
     uint64_t *keys2 = reinterpret_cast<uint64_t *>(ws + P.off_keys2);
     uint32_t *vals2 = reinterpret_cast<uint32_t *>(ws + P.off_vals2);
     uint32_t *hist = reinterpret_cast<uint32_t *>(ws + P.off_hist);
+    uint32_t *rows = reinterpret_cast<uint32_t *>(ws + P.off_rows);
     uint32_t *ticket = reinterpret_cast<uint32_t *>(ws + P.off_ticket);
     uint32_t *status = reinterpret_cast<uint32_t *>(ws + P.off_status);
     const size_t clear_words = (P.off_status - P.off_hist) / 4 + (size_t)P.passes * P.sort_parts * kBins;
@@ -551,17 +575,35 @@ hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec
     uint64_t *k_b = odd ? keys : keys2;
     uint32_t *v_b = odd ? vals : vals2;
     if (P.n > 0) {
-        if ((e = launch_kernel(emit_kernel, dim3((unsigned)((P.n + 255) / 256)), dim3(256), s, tt, offsets, rec,
-                               P.n, TX, TY, P.capacity, k_a, v_a, P.passes, hist)) != hipSuccess)
+        int64_t eg = (P.n + 255) / 256;
+        if (eg > kEmitGrid) eg = kEmitGrid;
+        if ((e = launch_kernel(emit_kernel, dim3((unsigned)eg), dim3(256), s, tt, offsets, rec, P.n, TX, TY,
+                               P.capacity, k_a, v_a, P.passes, rows, eg * 256)) != hipSuccess)
+            return e;
+        const int cols = P.passes * kHistStride;
+        if ((e = launch_kernel(hist_reduce_kernel, dim3((unsigned)((cols + 63) / 64)), dim3(256), s, rows, (int)eg,
+                               cols, hist)) != hipSuccess)
             return e;
     }
     // 3. onesweep passes over the significant bits (digit counts come from the emission)
-    // persistent grid: one workgroup per CU (~60 KB of LDS)
+    // persistent grid: one workgroup per CU (60 or 110 KB of LDS)
+    using SweepFn = void (*)(const uint64_t *, const uint32_t *, uint64_t *, uint32_t *, const int64_t *, int64_t,
+                             int, const uint32_t *, uint32_t *, uint32_t *, const int32_t *);
+    SweepFn sweep;
+    const int part_keys = (P.part_keys == 2 * kMinSortPart) ? 2 * kMinSortPart : kMinSortPart;
+    if (part_keys == kMinSortPart)
+        sweep = P.lookback >= 64 ? onesweep_kernel<8, 64> : P.lookback >= 32 ? onesweep_kernel<8, 32>
+                                                                              : onesweep_kernel<8, 16>;
+    else
+        sweep = P.lookback >= 64 ? onesweep_kernel<16, 64> : P.lookback >= 32 ? onesweep_kernel<16, 32>
+                                                                               : onesweep_kernel<16, 16>;
     int64_t sg = (int64_t)n_cu;
-    if (sg > P.sort_parts) sg = P.sort_parts;
+    const int64_t parts_used = (P.capacity + part_keys - 1) / part_keys;
+    if (sg > parts_used) sg = parts_used;
+    if (sg < 1) sg = 1;
     for (int p = 0; p < P.passes; ++p) {
-        if ((e = launch_kernel(onesweep_kernel, dim3((unsigned)sg), dim3(kSortBlock), s, k_a, v_a, k_b, v_b,
-                               d_num, P.capacity, p * kRadixBits, hist + p * kHistStride,
+        if ((e = launch_kernel(sweep, dim3((unsigned)sg), dim3(kSortBlock), s, k_a, v_a, k_b, v_b, d_num,
+                               P.capacity, p * kRadixBits, hist + p * kHistStride,
                                status + (size_t)p * P.sort_parts * kBins, ticket + p * 64, d_overflow)) != hipSuccess)
             return e;
         uint64_t *tk = k_a;

@@ -128,13 +128,15 @@ def test_tuning_validation():
     from paper_2604_12626_amd import binding as B
     prev = B.get_tuning()
     try:
-        with pytest.raises(B.GSError):
-            B.set_tuning(0)
-        with pytest.raises(B.GSError):
-            B.set_tuning(33)
-        B.set_tuning(5)
-        assert B.get_tuning()["composite_groups_per_cu"] == 5
-        B.set_tuning(None)
-        assert B.get_tuning()["composite_groups_per_cu"] == 8
+        for bad in ({"composite_groups_per_cu": 0}, {"composite_groups_per_cu": 33},
+                    {"sort_partition_keys": 2048}, {"sort_lookback": 8}):
+            before = B.get_tuning()
+            with pytest.raises(B.GSError):
+                B.set_tuning(**bad)
+            assert B.get_tuning() == before
+        B.set_tuning(5, sort_partition_keys=4096, sort_lookback=64)
+        assert B.get_tuning() == {"composite_groups_per_cu": 5, "sort_partition_keys": 4096, "sort_lookback": 64}
+        B.set_tuning()
+        assert B.get_tuning() == {"composite_groups_per_cu": 8, "sort_partition_keys": 8192, "sort_lookback": 16}
     finally:
-        B.set_tuning(prev["composite_groups_per_cu"])
+        B.set_tuning(**prev)

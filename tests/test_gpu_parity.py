@@ -118,25 +118,39 @@ def test_bin_sort_bit_exact(dev, orc, name, counts, W, H):
     tt_o, keys_o, vals_o, ranges_o, K = orc.bin_records(rec, vis, W, H, V)
     say("bin_sort:", name, "instances", len(rec), "K", K)
     prm = B.make_params(W, H)
-    for cap, expect_ovf in [(K + 1000, 0), (max(1, K // 2), 1 if K > max(1, K // 2) else 0)]:
-        tt = torch.from_numpy(tt_o.view(np.int32).copy()).to(dev)
-        r = torch.from_numpy(rec).to(dev)
-        keys = torch.zeros(cap, dtype=torch.int64, device=dev)
-        vals = torch.zeros(cap, dtype=torch.int32, device=dev)
-        T = ((W + 15) // 16) * ((H + 15) // 16)
-        ranges = torch.full((V * T, 2), 7, dtype=torch.int32, device=dev)
-        num = torch.zeros(1, dtype=torch.int64, device=dev)
-        ovf = torch.full((1,), 5, dtype=torch.int32, device=dev)
-        ws = torch.empty(B.bin_sort_workspace(len(rec), cap, V, prm), dtype=torch.uint8, device=dev)
-        B.bin_sort(tt, r, V, prm, ws, keys, vals, ranges, num, ovf)
-        torch.cuda.synchronize()
-        assert int(num.item()) == K and int(ovf.item()) == expect_ovf
-        if expect_ovf:
-            assert np.all(ranges.cpu().numpy() == 0)
-            continue
-        assert np.array_equal(keys.cpu().numpy()[:K].view(np.uint64), keys_o)
-        assert np.array_equal(vals.cpu().numpy()[:K].view(np.uint32), vals_o)
-        assert np.array_equal(ranges.cpu().numpy().view(np.uint32), ranges_o)
+    # every onesweep configuration the tuner may pick sorts identically
+    runs = [(K + 1000, 0, {}), (K + 1000, 0, {"sort_partition_keys": 4096, "sort_lookback": 64}),
+            (K + 1000, 0, {"sort_partition_keys": 8192, "sort_lookback": 32}),
+            (max(1, K // 2), 1 if K > max(1, K // 2) else 0, {})]
+    prev = B.get_tuning()
+    try:
+        for cap, expect_ovf, knobs in runs:
+            B.set_tuning(**dict(prev, **knobs))
+            _bin_sort_case(dev, B, rec, tt_o, keys_o, vals_o, ranges_o, K, V, W, H, prm, cap, expect_ovf)
+    finally:
+        B.set_tuning(**prev)
+
+
+def _bin_sort_case(dev, B, rec, tt_o, keys_o, vals_o, ranges_o, K, V, W, H, prm, cap, expect_ovf):
+    import torch
+    tt = torch.from_numpy(tt_o.view(np.int32).copy()).to(dev)
+    r = torch.from_numpy(rec).to(dev)
+    keys = torch.zeros(cap, dtype=torch.int64, device=dev)
+    vals = torch.zeros(cap, dtype=torch.int32, device=dev)
+    T = ((W + 15) // 16) * ((H + 15) // 16)
+    ranges = torch.full((V * T, 2), 7, dtype=torch.int32, device=dev)
+    num = torch.zeros(1, dtype=torch.int64, device=dev)
+    ovf = torch.full((1,), 5, dtype=torch.int32, device=dev)
+    ws = torch.empty(B.bin_sort_workspace(len(rec), cap, V, prm), dtype=torch.uint8, device=dev)
+    B.bin_sort(tt, r, V, prm, ws, keys, vals, ranges, num, ovf)
+    torch.cuda.synchronize()
+    assert int(num.item()) == K and int(ovf.item()) == expect_ovf
+    if expect_ovf:
+        assert np.all(ranges.cpu().numpy() == 0)
+        return
+    assert np.array_equal(keys.cpu().numpy()[:K].view(np.uint64), keys_o)
+    assert np.array_equal(vals.cpu().numpy()[:K].view(np.uint32), vals_o)
+    assert np.array_equal(ranges.cpu().numpy().view(np.uint32), ranges_o)
 
 
 COMPOSITE_CASES = [
@@ -275,7 +289,7 @@ def test_composite_schedule_does_not_change_results(dev):
         best, times = autotune.tune_composite(r, f, len(vs), candidates=(2, 8), reps=2)
         assert best in (2, 8) and B.get_tuning()["composite_groups_per_cu"] == best
     finally:
-        B.set_tuning(prev["composite_groups_per_cu"])
+        B.set_tuning(**prev)
 
 
 def test_union_equals_concatenation(dev):
