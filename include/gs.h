@@ -141,7 +141,7 @@ void gs_default_params(gs_params *p, int32_t width, int32_t height);
  *    gs_composite (1..32, default 8); each wave of the grid pops (view, tile,
  *    quadrant) work items until none is left.
  *  sort_partition_keys: keys per onesweep partition in gs_bin_sort (4096 or
- *    8192, default 8192).
+ *    8192, default 4096).
  *  sort_lookback: predecessor partitions read per round trip of the onesweep
  *    look-back (16, 32 or 64, default 16).
  * gs_set_tuning(NULL) restores the defaults; invalid values return

@@ -104,7 +104,7 @@ int64_t seg_offset_in_view(const gs_gaussians *segs, uint32_t mask, int s) {
 }
 
 std::atomic<int> g_comp_groups{8};
-std::atomic<int> g_sort_part_keys{8192};
+std::atomic<int> g_sort_part_keys{4096};
 std::atomic<int> g_sort_lookback{16};
 
 std::mutex g_dev_mu;
@@ -159,7 +159,7 @@ gs_status gs_set_tuning(const gs_tuning *t) {
     clear_error();
     if (!t) {
         g_comp_groups.store(8);
-        g_sort_part_keys.store(8192);
+        g_sort_part_keys.store(4096);
         g_sort_lookback.store(16);
         return GS_OK;
     }

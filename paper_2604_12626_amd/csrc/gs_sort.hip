@@ -28,12 +28,12 @@ constexpr int kSortBlock = 512;
 constexpr int kSortWaves = kSortBlock / 64;
 constexpr int kMinSortItems = 8;                    // partitions of 4096 or 8192 keys (tunable)
 constexpr int kMinSortPart = kSortBlock * kMinSortItems;
-constexpr int kEmitLane = 32;                       // larger rects are emitted by the whole wave
 constexpr int kEmitGrid = 512;                      // emission workgroups (grid-stride over instances)
 constexpr int kRadixBits = 8;
 constexpr int kBins = 1 << kRadixBits;
 constexpr int kMaxPasses = 8;
 constexpr int kHistStride = kBins + 1;  // per-pass difference array of the digit counts
+constexpr int kHistRows = 16;           // partial histogram rows left by hist_reduce_kernel
 constexpr uint32_t kFlagAgg = 1u << 30;
 constexpr uint32_t kFlagIncl = 2u << 30;
 constexpr uint32_t kCountMask = (1u << 30) - 1u;
@@ -201,91 +201,109 @@ __device__ __forceinline__ void hist_add_row(uint32_t (*h)[kHistStride], int pas
     }
 }
 
-// Key emission (one thread per instance; rects of more than kEmitLane tiles
-// are emitted by the whole wave, 64 keys per step) fused with the digit
-// histograms of every sort pass: the four depth bytes are the same for all
-// keys of an instance (counted once with weight tiles_touched) and the tile
-// bytes are counted per rect row.  A fixed grid strides over the instances;
-// each workgroup leaves its histograms as one row of `rows` (plain stores),
-// and hist_reduce_kernel sums the rows -- no global atomics.
+// Key emission fused with the digit histograms of every sort pass.
+// Instances are taken 256 at a time in index order, so the keys of one wave's
+// 64 instances fill one contiguous stretch of the output (their offsets are
+// consecutive): the wave writes that stretch with coalesced stores, lane j
+// taking keys j, j + 64, ..., and finds the instance that owns a key by a
+// binary search over the per-lane key starts kept in LDS.  Histograms: the
+// four depth bytes are the same for all keys of an instance (one update with
+// weight tiles_touched) and the tile bytes are counted per rect row.  A fixed
+// grid strides over the instances; each workgroup leaves its histograms as
+// one row of `rows` (plain stores) for hist_reduce_kernel -- no global
+// atomics on the histogram.
 __global__ void __launch_bounds__(256) emit_kernel(const uint32_t *tt, const uint32_t *offsets, const float4 *rec,
                                                    int64_t n, int TX, int TY, int64_t capacity, uint64_t *keys,
                                                    uint32_t *vals, int passes, uint32_t *rows /*[grid][passes*257]*/,
                                                    int64_t stride) {
     __shared__ uint32_t s_h[kMaxPasses][kHistStride];
+    __shared__ uint32_t s_start[4][64];  // per wave: first key of each lane's instance, relative to the wave's
+    __shared__ uint32_t s_xy[4][64];     // rect origin x0 | y0 << 16
+    __shared__ uint32_t s_w[4][64];      // rect width
+    __shared__ uint32_t s_tb[4][64];     // first tile of the instance's view
+    __shared__ uint32_t s_z[4][64];      // depth bits
     for (int k = threadIdx.x; k < kMaxPasses * kHistStride; k += 256) (&s_h[0][0])[k] = 0u;
     __syncthreads();
-    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int64_t base = (int64_t)blockIdx.x * 256; base < n; base += stride) {  // uniform per workgroup
         const int64_t g = base + threadIdx.x;
         const uint32_t t = (g < n) ? tt[g] : 0u;
         const int64_t k0 = t ? (int64_t)offsets[g] : capacity;
         const bool live = t && k0 < capacity;
-        Rect R = {0, 0, 0, 0};
-        uint64_t tbase = 0, depth_bits = 0;
+        // exclusive prefix of the key counts over the wave
+        uint32_t incl = live ? t : 0u;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += y;
+        }
+        const uint32_t excl = incl - (live ? t : 0u);
+        const uint32_t total = __shfl(incl, 63, 64);
         if (live) {
             const float4 q0 = rec[3 * g];
-            const int view = __float_as_int(rec[3 * g + 2].w);
-            R = tile_rect(q0.x, q0.y, __float_as_int(q0.w), TX, TY);
-            depth_bits = (uint64_t)__float_as_uint(q0.z);
-            tbase = (uint64_t)view * (uint64_t)(TX * TY);
+            const uint32_t view = (uint32_t)__float_as_int(rec[3 * g + 2].w);
+            const Rect R = tile_rect(q0.x, q0.y, __float_as_int(q0.w), TX, TY);
+            const uint32_t depth_bits = __float_as_uint(q0.z);
+            const uint64_t tbase = (uint64_t)view * (uint64_t)(TX * TY);
+            s_xy[wave][lane] = (uint32_t)R.x0 | ((uint32_t)R.y0 << 16);
+            s_w[wave][lane] = (uint32_t)(R.x1 - R.x0);
+            s_tb[wave][lane] = (uint32_t)tbase;
+            s_z[wave][lane] = depth_bits;
 #pragma unroll
-            for (int p = 0; p < 4; ++p) hist_add(s_h[p], (uint32_t)(depth_bits >> (8 * p)) & 255u, t);
+            for (int p = 0; p < 4; ++p) hist_add(s_h[p], (depth_bits >> (8 * p)) & 255u, t);
             for (int ty = R.y0; ty < R.y1; ++ty)
                 hist_add_row(s_h, passes, tbase + (uint64_t)(ty * TX + R.x0), (uint32_t)(R.x1 - R.x0));
         }
-        if (live && t <= (uint32_t)kEmitLane) {
-            int64_t k = k0;
-            for (int ty = R.y0; ty < R.y1; ++ty)
-                for (int tx = R.x0; tx < R.x1; ++tx) {
-                    if (k < capacity) {
-                        keys[k] = ((tbase + (uint64_t)(ty * TX + tx)) << 32) | depth_bits;
-                        vals[k] = (uint32_t)g;
-                    }
-                    ++k;
+        // lane starts are non-decreasing and dead lanes own empty ranges, so
+        // the owner of key j is the last lane whose start is <= j
+        s_start[wave][lane] = excl;
+        __builtin_amdgcn_wave_barrier();
+        const uint64_t lv = __ballot(live);
+        if (lv) {
+            const int first = __ffsll((unsigned long long)lv) - 1;
+            const int64_t kbase = __shfl((long long)k0, first, 64);  // key of the wave's first live lane
+            const int64_t room = capacity - kbase;
+            const uint32_t lim = (int64_t)total < room ? total : (uint32_t)room;
+            for (uint32_t j = lane; j < lim; j += 64) {
+                int lo = 0, hi = 63;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_start[wave][mid] <= j) lo = mid;
+                    else hi = mid - 1;
                 }
-        }
-        // rects of more than kEmitLane tiles: the wave emits them one at a
-        // time, 64 consecutive keys per step (row-major tile order as above)
-        uint64_t big = __ballot(live && t > (uint32_t)kEmitLane);
-        while (big) {
-            const int src = __ffsll((unsigned long long)big) - 1;
-            big &= big - 1;
-            const int x0 = __shfl(R.x0, src, 64), x1 = __shfl(R.x1, src, 64);
-            const int y0 = __shfl(R.y0, src, 64), y1 = __shfl(R.y1, src, 64);
-            const int64_t kb = __shfl((long long)k0, src, 64);
-            const uint64_t tb = (uint64_t)__shfl((unsigned long long)tbase, src, 64);
-            const uint64_t db = (uint64_t)__shfl((unsigned long long)depth_bits, src, 64);
-            const uint32_t gg = (uint32_t)__shfl((long long)g, src, 64);
-            const int w = x1 - x0;
-            const int total = w * (y1 - y0);
-            for (int j = lane; j < total; j += 64) {
-                const int64_t k = kb + j;
-                if (k >= capacity) break;
-                const int ty = y0 + j / w, tx = x0 + j % w;
-                keys[k] = ((tb + (uint64_t)(ty * TX + tx)) << 32) | db;
-                vals[k] = gg;
+                const uint32_t rel = j - s_start[wave][lo];
+                const uint32_t w = s_w[wave][lo], xy = s_xy[wave][lo];
+                const uint32_t ty = (xy >> 16) + rel / w, tx = (xy & 0xFFFFu) + rel % w;
+                const int64_t k = kbase + (int64_t)j;
+                keys[k] = ((uint64_t)(s_tb[wave][lo] + ty * (uint32_t)TX + tx) << 32) | (uint64_t)s_z[wave][lo];
+                vals[k] = (uint32_t)(base + (wave << 6) + lo);
             }
         }
+        __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
     uint32_t *row = rows + (size_t)blockIdx.x * passes * kHistStride;
     for (int k = threadIdx.x; k < passes * kHistStride; k += 256) row[k] = (&s_h[0][0])[k];
 }
 
-// hist[c] = sum over the emission workgroups' rows of column c
+// Partial sums of the emission rows: part[ry][c] = sum of rows[r][c] over the
+// ry-th sixteenth of the rows (64 columns x 4 row lanes per workgroup).  The
+// sort passes add up the kHistRows partials of their own digit column.
 __global__ void __launch_bounds__(256) hist_reduce_kernel(const uint32_t *rows, int n_rows, int n_cols,
-                                                          uint32_t *hist) {
+                                                          uint32_t *part /*[kHistRows][n_cols]*/) {
     __shared__ uint32_t s_part[4][64];
     const int c = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int r0 = threadIdx.x >> 6;  // four row lanes
+    const int rl = threadIdx.x >> 6;
+    const int per = (n_rows + kHistRows - 1) / kHistRows;
+    const int r0 = blockIdx.y * per, r1 = min(n_rows, r0 + per);
     uint32_t acc = 0u;
     if (c < n_cols)
-        for (int r = r0; r < n_rows; r += 4) acc += rows[(size_t)r * n_cols + c];
-    s_part[r0][threadIdx.x & 63] = acc;
+        for (int r = r0 + rl; r < r1; r += 4) acc += rows[(size_t)r * n_cols + c];
+    s_part[rl][threadIdx.x & 63] = acc;
     __syncthreads();
-    if (threadIdx.x < 64 && c < n_cols) hist[c] = s_part[0][threadIdx.x] + s_part[1][threadIdx.x] +
-                                                  s_part[2][threadIdx.x] + s_part[3][threadIdx.x];
+    if (threadIdx.x < 64 && c < n_cols)
+        part[(size_t)blockIdx.y * n_cols + c] =
+            s_part[0][threadIdx.x] + s_part[1][threadIdx.x] + s_part[2][threadIdx.x] + s_part[3][threadIdx.x];
 }
 
 // ---------------------------------------------------------------------------
@@ -302,7 +320,8 @@ __global__ void __launch_bounds__(kSortBlock) onesweep_kernel(const uint64_t *__
                                                               uint64_t *__restrict__ keys_out,
                                                               uint32_t *__restrict__ vals_out, const int64_t *d_num,
                                                               int64_t capacity, int shift,
-                                                              const uint32_t *hist_diff /*[257]*/,
+                                                              const uint32_t *hist_part /*[kHistRows][stride]*/,
+                                                              int hist_stride,
                                                               uint32_t *status /*[parts][256]*/, uint32_t *ticket,
                                                               const int32_t *d_overflow) {
     __shared__ uint32_t s_part;
@@ -319,8 +338,14 @@ __global__ void __launch_bounds__(kSortBlock) onesweep_kernel(const uint64_t *__
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     if (*d_overflow) return;  // keys beyond the capacity were dropped: nothing consistent to sort
     const int64_t K = sort_count(d_num, capacity);
-    // digit counts = prefix sums of the difference array, then their exclusive scan
-    if (tid < kBins) s_scan[tid] = hist_diff[tid];
+    // digit counts = prefix sums of the difference array (the sum of the
+    // partial rows), then their exclusive scan
+    if (tid < kBins) {
+        uint32_t v = 0u;
+#pragma unroll
+        for (int r = 0; r < kHistRows; ++r) v += hist_part[(size_t)r * hist_stride + tid];
+        s_scan[tid] = v;
+    }
     __syncthreads();
     for (int round = 0; round < 2; ++round) {
         uint32_t own = 0u;
@@ -526,9 +551,9 @@ SortPlan make_sort_plan(int64_t n, int64_t capacity, int64_t n_tiles_total) {
     o = align256(o + sizeof(uint32_t) * (size_t)(capacity > 0 ? capacity : 1));
     p.off_rows = o;
     o = align256(o + sizeof(uint32_t) * (size_t)kEmitGrid * p.passes * kHistStride);
-    // hist, status and tickets are contiguous so one fill clears them
+    // histogram partials, status and tickets are contiguous so one fill clears them
     p.off_hist = o;
-    o = o + sizeof(uint32_t) * (size_t)kMaxPasses * kHistStride;
+    o = o + sizeof(uint32_t) * (size_t)kHistRows * kMaxPasses * kHistStride;
     p.off_ticket = o;
     o = o + sizeof(uint32_t) * (size_t)kMaxPasses * 64;
     p.off_status = o;
@@ -581,14 +606,14 @@ hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec
                                P.capacity, k_a, v_a, P.passes, rows, eg * 256)) != hipSuccess)
             return e;
         const int cols = P.passes * kHistStride;
-        if ((e = launch_kernel(hist_reduce_kernel, dim3((unsigned)((cols + 63) / 64)), dim3(256), s, rows, (int)eg,
-                               cols, hist)) != hipSuccess)
+        if ((e = launch_kernel(hist_reduce_kernel, dim3((unsigned)((cols + 63) / 64), kHistRows), dim3(256), s, rows,
+                               (int)eg, cols, hist)) != hipSuccess)
             return e;
     }
     // 3. onesweep passes over the significant bits (digit counts come from the emission)
     // persistent grid: one workgroup per CU (60 or 110 KB of LDS)
     using SweepFn = void (*)(const uint64_t *, const uint32_t *, uint64_t *, uint32_t *, const int64_t *, int64_t,
-                             int, const uint32_t *, uint32_t *, uint32_t *, const int32_t *);
+                             int, const uint32_t *, int, uint32_t *, uint32_t *, const int32_t *);
     SweepFn sweep;
     const int part_keys = (P.part_keys == 2 * kMinSortPart) ? 2 * kMinSortPart : kMinSortPart;
     if (part_keys == kMinSortPart)
@@ -603,7 +628,7 @@ hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec
     if (sg < 1) sg = 1;
     for (int p = 0; p < P.passes; ++p) {
         if ((e = launch_kernel(sweep, dim3((unsigned)sg), dim3(kSortBlock), s, k_a, v_a, k_b, v_b, d_num,
-                               P.capacity, p * kRadixBits, hist + p * kHistStride,
+                               P.capacity, p * kRadixBits, hist + p * kHistStride, P.passes * kHistStride,
                                status + (size_t)p * P.sort_parts * kBins, ticket + p * 64, d_overflow)) != hipSuccess)
             return e;
         uint64_t *tk = k_a;

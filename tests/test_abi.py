@@ -137,6 +137,6 @@ def test_tuning_validation():
         B.set_tuning(5, sort_partition_keys=4096, sort_lookback=64)
         assert B.get_tuning() == {"composite_groups_per_cu": 5, "sort_partition_keys": 4096, "sort_lookback": 64}
         B.set_tuning()
-        assert B.get_tuning() == {"composite_groups_per_cu": 8, "sort_partition_keys": 8192, "sort_lookback": 16}
+        assert B.get_tuning() == {"composite_groups_per_cu": 8, "sort_partition_keys": 4096, "sort_lookback": 16}
     finally:
         B.set_tuning(**prev)

@@ -119,8 +119,8 @@ def test_bin_sort_bit_exact(dev, orc, name, counts, W, H):
     say("bin_sort:", name, "instances", len(rec), "K", K)
     prm = B.make_params(W, H)
     # every onesweep configuration the tuner may pick sorts identically
-    runs = [(K + 1000, 0, {}), (K + 1000, 0, {"sort_partition_keys": 4096, "sort_lookback": 64}),
-            (K + 1000, 0, {"sort_partition_keys": 8192, "sort_lookback": 32}),
+    runs = [(K + 1000, 0, {}), (K + 1000, 0, {"sort_partition_keys": 8192, "sort_lookback": 64}),
+            (K + 1000, 0, {"sort_partition_keys": 4096, "sort_lookback": 32}),
             (max(1, K // 2), 1 if K > max(1, K // 2) else 0, {})]
     prev = B.get_tuning()
     try:
