@@ -28,7 +28,7 @@ constexpr int kSortBlock = 512;
 constexpr int kSortWaves = kSortBlock / 64;
 constexpr int kMinSortItems = 8;                    // partitions of 4096 or 8192 keys (tunable)
 constexpr int kMinSortPart = kSortBlock * kMinSortItems;
-constexpr int kEmitGrid = 512;                      // emission workgroups (grid-stride over instances)
+constexpr int kEmitGrid = 1024;  // emission workgroups at most (grid-stride over scan tiles beyond)
 constexpr int kRadixBits = 8;
 constexpr int kBins = 1 << kRadixBits;
 constexpr int kMaxPasses = 8;
@@ -113,47 +113,6 @@ __global__ void __launch_bounds__(1024) scan_partials_kernel(uint64_t *part, int
     }
 }
 
-// block-local exclusive scan (blocked arrangement: thread t owns items
-// [t*16, t*16+16) of the block's 4096) plus the block's global prefix;
-// offsets saturate at 2^32-1 (emission stops at the capacity anyway)
-__global__ void __launch_bounds__(kScanBlock) scan_down_kernel(const uint32_t *tt, int64_t n, const uint64_t *part,
-                                                               uint32_t *offsets) {
-    __shared__ uint64_t s[kScanBlock];
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-    uint32_t v[kScanItems];
-    uint64_t sum = 0;
-    if (base + kScanItems <= n) {  // 4 x 16-B loads (tt is 16-B aligned: caller-owned allocation)
-#pragma unroll
-        for (int k = 0; k < kScanItems / 4; ++k) {
-            const uint4 q = reinterpret_cast<const uint4 *>(tt + base)[k];
-            v[4 * k] = q.x;
-            v[4 * k + 1] = q.y;
-            v[4 * k + 2] = q.z;
-            v[4 * k + 3] = q.w;
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < kScanItems; ++k) v[k] = (base + k < n) ? tt[base + k] : 0u;
-    }
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) sum += v[k];
-    s[threadIdx.x] = sum;
-    __syncthreads();
-    for (int off = 1; off < kScanBlock; off <<= 1) {
-        const uint64_t t = (threadIdx.x >= (unsigned)off) ? s[threadIdx.x - off] : 0;
-        __syncthreads();
-        s[threadIdx.x] += t;
-        __syncthreads();
-    }
-    uint64_t run = part[blockIdx.x] + s[threadIdx.x] - sum;
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        const int64_t i = base + k;
-        if (i < n) offsets[i] = run > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)run;
-        run += v[k];
-    }
-}
-
 // ---------------------------------------------------------------------------
 // key emission
 // ---------------------------------------------------------------------------
@@ -201,89 +160,126 @@ __device__ __forceinline__ void hist_add_row(uint32_t (*h)[kHistStride], int pas
     }
 }
 
-// Key emission fused with the digit histograms of every sort pass.
-// Instances are taken 256 at a time in index order, so the keys of one wave's
-// 64 instances fill one contiguous stretch of the output (their offsets are
-// consecutive): the wave writes that stretch with coalesced stores, lane j
-// taking keys j, j + 64, ..., and finds the instance that owns a key by a
-// binary search over the per-lane key starts kept in LDS.  Histograms: the
-// four depth bytes are the same for all keys of an instance (one update with
-// weight tiles_touched) and the tile bytes are counted per rect row.  A fixed
-// grid strides over the instances; each workgroup leaves its histograms as
-// one row of `rows` (plain stores) for hist_reduce_kernel -- no global
-// atomics on the histogram.
-__global__ void __launch_bounds__(256) emit_kernel(const uint32_t *tt, const uint32_t *offsets, const float4 *rec,
-                                                   int64_t n, int TX, int TY, int64_t capacity, uint64_t *keys,
-                                                   uint32_t *vals, int passes, uint32_t *rows /*[grid][passes*257]*/,
-                                                   int64_t stride) {
+// Key emission, fused with the downsweep of the scan of tiles_touched and
+// with the digit histograms of every sort pass.  A workgroup takes a scan
+// tile of 4096 instances (thread t owns 16 consecutive ones), issues all of
+// their loads at once, and turns the block-local scan plus the tile's global
+// prefix into each instance's first key.  The keys of one wave's 1024
+// instances fill one contiguous stretch of the output: the wave writes it
+// with coalesced stores, lane j taking keys j, j + 64, ..., and finds the
+// instance that owns a key by a binary search over the instance starts kept
+// in LDS.  Histograms: the four depth bytes are the same for all keys of an
+// instance (one update with weight tiles_touched) and the tile bytes are
+// counted per rect row; each workgroup leaves its histograms as one row of
+// `rows` (plain stores) for hist_reduce_kernel.  Instances whose keys start
+// at or beyond the capacity emit nothing (the overflow flag is already set).
+__global__ void __launch_bounds__(kScanBlock) emit_kernel(const uint32_t *tt, const uint64_t *part,
+                                                          const float4 *rec, int64_t n, int64_t n_tiles_scan,
+                                                          int TX, int TY, int64_t capacity, uint64_t *keys,
+                                                          uint32_t *vals, int passes,
+                                                          uint32_t *rows /*[grid][passes*257]*/, int64_t n_blocks) {
+    constexpr int kWaveInst = 64 * kScanItems;  // 1024 instances per wave
     __shared__ uint32_t s_h[kMaxPasses][kHistStride];
-    __shared__ uint32_t s_start[4][64];  // per wave: first key of each lane's instance, relative to the wave's
-    __shared__ uint32_t s_xy[4][64];     // rect origin x0 | y0 << 16
-    __shared__ uint32_t s_w[4][64];      // rect width
-    __shared__ uint32_t s_tb[4][64];     // first tile of the instance's view
-    __shared__ uint32_t s_z[4][64];      // depth bits
-    for (int k = threadIdx.x; k < kMaxPasses * kHistStride; k += 256) (&s_h[0][0])[k] = 0u;
-    __syncthreads();
+    __shared__ uint64_t s_scan[kScanBlock];
+    __shared__ uint32_t s_start[4][kWaveInst];  // first key of each instance, relative to the wave's first
+    __shared__ uint32_t s_xy[4][kWaveInst];     // rect origin x0 | y0 << 16
+    __shared__ uint32_t s_w[4][kWaveInst];      // rect width
+    __shared__ uint32_t s_tb[4][kWaveInst];     // first tile of the instance's view
+    __shared__ uint32_t s_z[4][kWaveInst];      // depth bits
+    for (int k = threadIdx.x; k < kMaxPasses * kHistStride; k += kScanBlock) (&s_h[0][0])[k] = 0u;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int64_t base = (int64_t)blockIdx.x * 256; base < n; base += stride) {  // uniform per workgroup
-        const int64_t g = base + threadIdx.x;
-        const uint32_t t = (g < n) ? tt[g] : 0u;
-        const int64_t k0 = t ? (int64_t)offsets[g] : capacity;
-        const bool live = t && k0 < capacity;
-        // exclusive prefix of the key counts over the wave
-        uint32_t incl = live ? t : 0u;
+    for (int64_t tile = blockIdx.x; tile < n_tiles_scan; tile += n_blocks) {  // uniform per workgroup
+        const int64_t base = tile * kScanTile + (int64_t)threadIdx.x * kScanItems;
+        uint32_t v[kScanItems];
+        if (base + kScanItems <= n) {  // 4 x 16-B loads (tt is 16-B aligned: caller-owned allocation)
 #pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t y = __shfl_up(incl, off, 64);
-            if (lane >= off) incl += y;
-        }
-        const uint32_t excl = incl - (live ? t : 0u);
-        const uint32_t total = __shfl(incl, 63, 64);
-        if (live) {
-            const float4 q0 = rec[3 * g];
-            const uint32_t view = (uint32_t)__float_as_int(rec[3 * g + 2].w);
-            const Rect R = tile_rect(q0.x, q0.y, __float_as_int(q0.w), TX, TY);
-            const uint32_t depth_bits = __float_as_uint(q0.z);
-            const uint64_t tbase = (uint64_t)view * (uint64_t)(TX * TY);
-            s_xy[wave][lane] = (uint32_t)R.x0 | ((uint32_t)R.y0 << 16);
-            s_w[wave][lane] = (uint32_t)(R.x1 - R.x0);
-            s_tb[wave][lane] = (uint32_t)tbase;
-            s_z[wave][lane] = depth_bits;
-#pragma unroll
-            for (int p = 0; p < 4; ++p) hist_add(s_h[p], (depth_bits >> (8 * p)) & 255u, t);
-            for (int ty = R.y0; ty < R.y1; ++ty)
-                hist_add_row(s_h, passes, tbase + (uint64_t)(ty * TX + R.x0), (uint32_t)(R.x1 - R.x0));
-        }
-        // lane starts are non-decreasing and dead lanes own empty ranges, so
-        // the owner of key j is the last lane whose start is <= j
-        s_start[wave][lane] = excl;
-        __builtin_amdgcn_wave_barrier();
-        const uint64_t lv = __ballot(live);
-        if (lv) {
-            const int first = __ffsll((unsigned long long)lv) - 1;
-            const int64_t kbase = __shfl((long long)k0, first, 64);  // key of the wave's first live lane
-            const int64_t room = capacity - kbase;
-            const uint32_t lim = (int64_t)total < room ? total : (uint32_t)room;
-            for (uint32_t j = lane; j < lim; j += 64) {
-                int lo = 0, hi = 63;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (s_start[wave][mid] <= j) lo = mid;
-                    else hi = mid - 1;
-                }
-                const uint32_t rel = j - s_start[wave][lo];
-                const uint32_t w = s_w[wave][lo], xy = s_xy[wave][lo];
-                const uint32_t ty = (xy >> 16) + rel / w, tx = (xy & 0xFFFFu) + rel % w;
-                const int64_t k = kbase + (int64_t)j;
-                keys[k] = ((uint64_t)(s_tb[wave][lo] + ty * (uint32_t)TX + tx) << 32) | (uint64_t)s_z[wave][lo];
-                vals[k] = (uint32_t)(base + (wave << 6) + lo);
+            for (int k = 0; k < kScanItems / 4; ++k) {
+                const uint4 q = reinterpret_cast<const uint4 *>(tt + base)[k];
+                v[4 * k] = q.x;
+                v[4 * k + 1] = q.y;
+                v[4 * k + 2] = q.z;
+                v[4 * k + 3] = q.w;
             }
+        } else {
+#pragma unroll
+            for (int k = 0; k < kScanItems; ++k) v[k] = (base + k < n) ? tt[base + k] : 0u;
+        }
+        uint64_t sum = 0;
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) sum += v[k];
+        s_scan[threadIdx.x] = sum;
+        __syncthreads();
+        for (int off = 1; off < kScanBlock; off <<= 1) {
+            const uint64_t t = (threadIdx.x >= (unsigned)off) ? s_scan[threadIdx.x - off] : 0;
+            __syncthreads();
+            s_scan[threadIdx.x] += t;
+            __syncthreads();
+        }
+        const uint64_t tile_base = part[tile];
+        const uint64_t wave_excl = (wave > 0) ? s_scan[wave * 64 - 1] : 0ull;  // block-local start of the wave
+        const uint64_t lane_excl = s_scan[threadIdx.x] - sum;
+        const uint64_t wave_total = s_scan[wave * 64 + 63] - wave_excl;
+        const int64_t kw = (int64_t)(tile_base + wave_excl);  // first key of the wave
+        // attributes of the live instances (all loads in flight together)
+        float4 q0[kScanItems];
+        uint32_t view[kScanItems];
+        uint64_t run = lane_excl - wave_excl;  // relative to the wave
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            const bool live = v[k] && (kw + (int64_t)run) < capacity;
+            if (live) {
+                q0[k] = rec[3 * (base + k)];
+                view[k] = (uint32_t)__float_as_int(rec[3 * (base + k) + 2].w);
+            }
+            run += v[k];
+        }
+        run = lane_excl - wave_excl;
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            const int slot = lane * kScanItems + k;
+            const bool live = v[k] && (kw + (int64_t)run) < capacity;
+            s_start[wave][slot] = run > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)run;
+            if (live) {
+                const Rect R = tile_rect(q0[k].x, q0[k].y, __float_as_int(q0[k].w), TX, TY);
+                const uint32_t depth_bits = __float_as_uint(q0[k].z);
+                const uint64_t tbase = (uint64_t)view[k] * (uint64_t)(TX * TY);
+                s_xy[wave][slot] = (uint32_t)R.x0 | ((uint32_t)R.y0 << 16);
+                s_w[wave][slot] = (uint32_t)(R.x1 - R.x0);
+                s_tb[wave][slot] = (uint32_t)tbase;
+                s_z[wave][slot] = depth_bits;
+#pragma unroll
+                for (int p = 0; p < 4; ++p) hist_add(s_h[p], (depth_bits >> (8 * p)) & 255u, v[k]);
+                for (int ty = R.y0; ty < R.y1; ++ty)
+                    hist_add_row(s_h, passes, tbase + (uint64_t)(ty * TX + R.x0), (uint32_t)(R.x1 - R.x0));
+            }
+            run += v[k];
         }
         __builtin_amdgcn_wave_barrier();
+        // the wave's keys: starts are non-decreasing and instances without
+        // keys own empty ranges, so the owner of key j is the last instance
+        // whose start is <= j
+        const int64_t room = capacity - kw;
+        const uint64_t lim = room <= 0 ? 0ull : ((int64_t)wave_total < room ? wave_total : (uint64_t)room);
+        const int64_t ginst = tile * kScanTile + (int64_t)wave * kWaveInst;
+        for (uint32_t j = lane; j < lim; j += 64) {
+            int lo = 0, hi = kWaveInst - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_start[wave][mid] <= j) lo = mid;
+                else hi = mid - 1;
+            }
+            const uint32_t rel = j - s_start[wave][lo];
+            const uint32_t w = s_w[wave][lo], xy = s_xy[wave][lo];
+            const uint32_t ty = (xy >> 16) + rel / w, tx = (xy & 0xFFFFu) + rel % w;
+            const int64_t k = kw + (int64_t)j;
+            keys[k] = ((uint64_t)(s_tb[wave][lo] + ty * (uint32_t)TX + tx) << 32) | (uint64_t)s_z[wave][lo];
+            vals[k] = (uint32_t)(ginst + lo);
+        }
+        __syncthreads();  // s_scan and the per-wave arrays are reused by the next tile
     }
     __syncthreads();
     uint32_t *row = rows + (size_t)blockIdx.x * passes * kHistStride;
-    for (int k = threadIdx.x; k < passes * kHistStride; k += 256) row[k] = (&s_h[0][0])[k];
+    for (int k = threadIdx.x; k < passes * kHistStride; k += kScanBlock) row[k] = (&s_h[0][0])[k];
 }
 
 // Partial sums of the emission rows: part[ry][c] = sum of rows[r][c] over the
@@ -541,8 +537,6 @@ SortPlan make_sort_plan(int64_t n, int64_t capacity, int64_t n_tiles_total) {
     p.sort_parts = (capacity + kMinSortPart - 1) / kMinSortPart;
     if (p.sort_parts < 1) p.sort_parts = 1;
     size_t o = 0;
-    p.off_offsets = o;
-    o = align256(o + sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
     p.off_part = o;
     o = align256(o + sizeof(uint64_t) * (size_t)p.scan_blocks);
     p.off_keys2 = o;
@@ -566,7 +560,6 @@ hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec
                         uint64_t *keys, uint32_t *vals, uint32_t *ranges, int64_t *d_num, int32_t *d_overflow,
                         int n_cu, hipStream_t s) {
     hipError_t e;
-    uint32_t *offsets = reinterpret_cast<uint32_t *>(ws + P.off_offsets);
     uint64_t *part = reinterpret_cast<uint64_t *>(ws + P.off_part);
     uint64_t *keys2 = reinterpret_cast<uint64_t *>(ws + P.off_keys2);
     uint32_t *vals2 = reinterpret_cast<uint32_t *>(ws + P.off_vals2);
@@ -588,22 +581,17 @@ hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec
     if ((e = launch_kernel(scan_partials_kernel, dim3(1), dim3(1024), s, part, P.n > 0 ? P.scan_blocks : (int64_t)0,
                            P.capacity, d_num, d_overflow)) != hipSuccess)
         return e;
-    if (P.n > 0) {
-        if ((e = launch_kernel(scan_down_kernel, dim3((unsigned)P.scan_blocks), dim3(kScanBlock), s, tt, P.n, part,
-                               offsets)) != hipSuccess)
-            return e;
-    }
-    // 2. emit into the buffer that the last pass does not write to
+    // 2. emission (with the scan downsweep) into the buffer that the last pass does not write to
     const bool odd = (P.passes & 1) != 0;
     uint64_t *k_a = odd ? keys2 : keys;
     uint32_t *v_a = odd ? vals2 : vals;
     uint64_t *k_b = odd ? keys : keys2;
     uint32_t *v_b = odd ? vals : vals2;
     if (P.n > 0) {
-        int64_t eg = (P.n + 255) / 256;
+        int64_t eg = P.scan_blocks;
         if (eg > kEmitGrid) eg = kEmitGrid;
-        if ((e = launch_kernel(emit_kernel, dim3((unsigned)eg), dim3(256), s, tt, offsets, rec, P.n, TX, TY,
-                               P.capacity, k_a, v_a, P.passes, rows, eg * 256)) != hipSuccess)
+        if ((e = launch_kernel(emit_kernel, dim3((unsigned)eg), dim3(kScanBlock), s, tt, part, rec, P.n,
+                               P.scan_blocks, TX, TY, P.capacity, k_a, v_a, P.passes, rows, eg)) != hipSuccess)
             return e;
         const int cols = P.passes * kHistStride;
         if ((e = launch_kernel(hist_reduce_kernel, dim3((unsigned)((cols + 63) / 64), kHistRows), dim3(256), s, rows,
