@@ -161,125 +161,154 @@ __device__ __forceinline__ void hist_add_row(uint32_t (*h)[kHistStride], int pas
 }
 
 // Key emission, fused with the downsweep of the scan of tiles_touched and
-// with the digit histograms of every sort pass.  A workgroup takes a scan
-// tile of 4096 instances (thread t owns 16 consecutive ones), issues all of
-// their loads at once, and turns the block-local scan plus the tile's global
-// prefix into each instance's first key.  The keys of one wave's 1024
-// instances fill one contiguous stretch of the output: the wave writes it
-// with coalesced stores, lane j taking keys j, j + 64, ..., and finds the
-// instance that owns a key by a binary search over the instance starts kept
-// in LDS.  Histograms: the four depth bytes are the same for all keys of an
-// instance (one update with weight tiles_touched) and the tile bytes are
-// counted per rect row; each workgroup leaves its histograms as one row of
-// `rows` (plain stores) for hist_reduce_kernel.  Instances whose keys start
-// at or beyond the capacity emit nothing (the overflow flag is already set).
-__global__ void __launch_bounds__(kScanBlock) emit_kernel(const uint32_t *tt, const uint64_t *part,
+// with the digit histograms of every sort pass.  A workgroup of 1024 threads
+// takes a scan tile of 4096 instances (thread t owns 4 consecutive ones) and
+// turns the block-local scan plus the tile's global prefix into each
+// instance's first key.  Each wave (256 instances) compacts its live
+// instances -- visible, with keys below the capacity -- into LDS, in index
+// order, and its lanes then work through that list together: tile rect,
+// histogram updates (the four depth bytes once per instance with weight
+// tiles_touched, the tile bytes per rect row), key layout.  The keys of a
+// wave fill one contiguous stretch of the output, written with coalesced
+// stores: lane j takes keys j, j + 64, ... and finds the owning instance by
+// a binary search over the list's key starts.  Each workgroup leaves its
+// histograms as one row of `rows` (plain stores) for hist_reduce_kernel.
+constexpr int kEmitBlock = 1024;
+constexpr int kEmitItems = kScanTile / kEmitBlock;  // 4 instances per thread
+constexpr int kEmitWaves = kEmitBlock / 64;
+constexpr int kWaveInst = 64 * kEmitItems;          // 256 instances per wave
+
+__global__ void __launch_bounds__(kEmitBlock) emit_kernel(const uint32_t *tt, const uint64_t *part,
                                                           const float4 *rec, int64_t n, int64_t n_tiles_scan,
                                                           int TX, int TY, int64_t capacity, uint64_t *keys,
                                                           uint32_t *vals, int passes,
                                                           uint32_t *rows /*[grid][passes*257]*/, int64_t n_blocks) {
-    constexpr int kWaveInst = 64 * kScanItems;  // 1024 instances per wave
     __shared__ uint32_t s_h[kMaxPasses][kHistStride];
-    __shared__ uint64_t s_scan[kScanBlock];
-    __shared__ uint32_t s_start[4][kWaveInst];  // first key of each instance, relative to the wave's first
-    __shared__ uint32_t s_xy[4][kWaveInst];     // rect origin x0 | y0 << 16
-    __shared__ uint32_t s_w[4][kWaveInst];      // rect width
-    __shared__ uint32_t s_tb[4][kWaveInst];     // first tile of the instance's view
-    __shared__ uint32_t s_z[4][kWaveInst];      // depth bits
-    for (int k = threadIdx.x; k < kMaxPasses * kHistStride; k += kScanBlock) (&s_h[0][0])[k] = 0u;
+    __shared__ uint64_t s_wsum[kEmitWaves];
+    // per wave, per list entry: staged record, then the emission layout
+    __shared__ uint32_t s_a0[kEmitWaves][kWaveInst];  // u bits          -> rect origin x0 | y0 << 16
+    __shared__ uint32_t s_a1[kEmitWaves][kWaveInst];  // v bits          -> rect width
+    __shared__ uint32_t s_a2[kEmitWaves][kWaveInst];  // depth bits
+    __shared__ uint32_t s_a3[kEmitWaves][kWaveInst];  // radius          -> first tile of the view
+    __shared__ uint32_t s_a4[kEmitWaves][kWaveInst];  // view
+    __shared__ uint32_t s_a5[kEmitWaves][kWaveInst];  // instance index
+    __shared__ uint32_t s_a6[kEmitWaves][kWaveInst];  // first key, relative to the wave's first
+    __shared__ uint32_t s_a7[kEmitWaves][kWaveInst];  // tiles_touched
+    for (int k = threadIdx.x; k < kMaxPasses * kHistStride; k += kEmitBlock) (&s_h[0][0])[k] = 0u;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int64_t tile = blockIdx.x; tile < n_tiles_scan; tile += n_blocks) {  // uniform per workgroup
-        const int64_t base = tile * kScanTile + (int64_t)threadIdx.x * kScanItems;
-        uint32_t v[kScanItems];
-        if (base + kScanItems <= n) {  // 4 x 16-B loads (tt is 16-B aligned: caller-owned allocation)
-#pragma unroll
-            for (int k = 0; k < kScanItems / 4; ++k) {
-                const uint4 q = reinterpret_cast<const uint4 *>(tt + base)[k];
-                v[4 * k] = q.x;
-                v[4 * k + 1] = q.y;
-                v[4 * k + 2] = q.z;
-                v[4 * k + 3] = q.w;
-            }
+        const int64_t base = tile * kScanTile + (int64_t)threadIdx.x * kEmitItems;
+        uint32_t v[kEmitItems];
+        if (base + kEmitItems <= n) {  // one 16-B load (tt is 16-B aligned: caller-owned allocation)
+            const uint4 q = *reinterpret_cast<const uint4 *>(tt + base);
+            v[0] = q.x;
+            v[1] = q.y;
+            v[2] = q.z;
+            v[3] = q.w;
         } else {
 #pragma unroll
-            for (int k = 0; k < kScanItems; ++k) v[k] = (base + k < n) ? tt[base + k] : 0u;
+            for (int k = 0; k < kEmitItems; ++k) v[k] = (base + k < n) ? tt[base + k] : 0u;
         }
-        uint64_t sum = 0;
+        // wave-level inclusive scan of the per-thread sums (fits 32 bits:
+        // 256 instances of at most 2^22 tiles), then across the waves in 64 bits
+        uint32_t incl = v[0] + v[1] + v[2] + v[3];
+        const uint32_t own = incl;
 #pragma unroll
-        for (int k = 0; k < kScanItems; ++k) sum += v[k];
-        s_scan[threadIdx.x] = sum;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += y;
+        }
+        const uint32_t wave_total = __shfl(incl, 63, 64);
+        if (lane == 0) s_wsum[wave] = wave_total;
         __syncthreads();
-        for (int off = 1; off < kScanBlock; off <<= 1) {
-            const uint64_t t = (threadIdx.x >= (unsigned)off) ? s_scan[threadIdx.x - off] : 0;
-            __syncthreads();
-            s_scan[threadIdx.x] += t;
-            __syncthreads();
-        }
-        const uint64_t tile_base = part[tile];
-        const uint64_t wave_excl = (wave > 0) ? s_scan[wave * 64 - 1] : 0ull;  // block-local start of the wave
-        const uint64_t lane_excl = s_scan[threadIdx.x] - sum;
-        const uint64_t wave_total = s_scan[wave * 64 + 63] - wave_excl;
-        const int64_t kw = (int64_t)(tile_base + wave_excl);  // first key of the wave
-        // attributes of the live instances (all loads in flight together)
-        float4 q0[kScanItems];
-        uint32_t view[kScanItems];
-        uint64_t run = lane_excl - wave_excl;  // relative to the wave
+        uint64_t wave_excl = 0;
+        for (int k = 0; k < wave; ++k) wave_excl += s_wsum[k];
+        const int64_t kw = (int64_t)(part[tile] + wave_excl);  // first key of the wave
+        const int64_t room = capacity - kw;
+        // live instances of the lane and their place in the wave's list
+        uint32_t start[kEmitItems];
+        uint32_t live_mask = 0u;
+        {
+            uint32_t run = incl - own;
 #pragma unroll
-        for (int k = 0; k < kScanItems; ++k) {
-            const bool live = v[k] && (kw + (int64_t)run) < capacity;
-            if (live) {
+            for (int k = 0; k < kEmitItems; ++k) {
+                start[k] = run;
+                if (v[k] && (int64_t)run < room) live_mask |= 1u << k;
+                run += v[k];
+            }
+        }
+        const uint32_t cnt = __popc(live_mask);
+        uint32_t pos = cnt;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(pos, off, 64);
+            if (lane >= off) pos += y;
+        }
+        const uint32_t n_live = __shfl(pos, 63, 64);
+        pos -= cnt;
+        // stage the live instances' records (all loads in flight together)
+        float4 q0[kEmitItems];
+        uint32_t view[kEmitItems];
+#pragma unroll
+        for (int k = 0; k < kEmitItems; ++k)
+            if (live_mask & (1u << k)) {
                 q0[k] = rec[3 * (base + k)];
                 view[k] = (uint32_t)__float_as_int(rec[3 * (base + k) + 2].w);
             }
-            run += v[k];
-        }
-        run = lane_excl - wave_excl;
 #pragma unroll
-        for (int k = 0; k < kScanItems; ++k) {
-            const int slot = lane * kScanItems + k;
-            const bool live = v[k] && (kw + (int64_t)run) < capacity;
-            s_start[wave][slot] = run > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)run;
-            if (live) {
-                const Rect R = tile_rect(q0[k].x, q0[k].y, __float_as_int(q0[k].w), TX, TY);
-                const uint32_t depth_bits = __float_as_uint(q0[k].z);
-                const uint64_t tbase = (uint64_t)view[k] * (uint64_t)(TX * TY);
-                s_xy[wave][slot] = (uint32_t)R.x0 | ((uint32_t)R.y0 << 16);
-                s_w[wave][slot] = (uint32_t)(R.x1 - R.x0);
-                s_tb[wave][slot] = (uint32_t)tbase;
-                s_z[wave][slot] = depth_bits;
-#pragma unroll
-                for (int p = 0; p < 4; ++p) hist_add(s_h[p], (depth_bits >> (8 * p)) & 255u, v[k]);
-                for (int ty = R.y0; ty < R.y1; ++ty)
-                    hist_add_row(s_h, passes, tbase + (uint64_t)(ty * TX + R.x0), (uint32_t)(R.x1 - R.x0));
+        for (int k = 0; k < kEmitItems; ++k)
+            if (live_mask & (1u << k)) {
+                s_a0[wave][pos] = __float_as_uint(q0[k].x);
+                s_a1[wave][pos] = __float_as_uint(q0[k].y);
+                s_a2[wave][pos] = __float_as_uint(q0[k].z);
+                s_a3[wave][pos] = __float_as_uint(q0[k].w);
+                s_a4[wave][pos] = view[k];
+                s_a5[wave][pos] = (uint32_t)(base + k);
+                s_a6[wave][pos] = start[k];
+                s_a7[wave][pos] = v[k];
+                ++pos;
             }
-            run += v[k];
+        __builtin_amdgcn_wave_barrier();
+        // the list, lanes together: rect, histograms, emission layout
+        for (uint32_t e = lane; e < n_live; e += 64) {
+            const float u = __uint_as_float(s_a0[wave][e]), vv = __uint_as_float(s_a1[wave][e]);
+            const uint32_t depth_bits = s_a2[wave][e];
+            const Rect R = tile_rect(u, vv, (int)s_a3[wave][e], TX, TY);
+            const uint64_t tbase = (uint64_t)s_a4[wave][e] * (uint64_t)(TX * TY);
+            const uint32_t t = s_a7[wave][e];
+#pragma unroll
+            for (int p = 0; p < 4; ++p) hist_add(s_h[p], (depth_bits >> (8 * p)) & 255u, t);
+            for (int ty = R.y0; ty < R.y1; ++ty)
+                hist_add_row(s_h, passes, tbase + (uint64_t)(ty * TX + R.x0), (uint32_t)(R.x1 - R.x0));
+            s_a0[wave][e] = (uint32_t)R.x0 | ((uint32_t)R.y0 << 16);
+            s_a1[wave][e] = (uint32_t)(R.x1 - R.x0);
+            s_a3[wave][e] = (uint32_t)tbase;
         }
         __builtin_amdgcn_wave_barrier();
-        // the wave's keys: starts are non-decreasing and instances without
-        // keys own empty ranges, so the owner of key j is the last instance
-        // whose start is <= j
-        const int64_t room = capacity - kw;
-        const uint64_t lim = room <= 0 ? 0ull : ((int64_t)wave_total < room ? wave_total : (uint64_t)room);
-        const int64_t ginst = tile * kScanTile + (int64_t)wave * kWaveInst;
-        for (uint32_t j = lane; j < lim; j += 64) {
-            int lo = 0, hi = kWaveInst - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (s_start[wave][mid] <= j) lo = mid;
-                else hi = mid - 1;
+        // the wave's keys: list starts increase strictly, so the owner of key
+        // j is the last entry whose start is <= j
+        if (n_live) {
+            const uint32_t lim = (int64_t)wave_total < room ? wave_total : (uint32_t)room;
+            for (uint32_t j = lane; j < lim; j += 64) {
+                int lo = 0, hi = (int)n_live - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_a6[wave][mid] <= j) lo = mid;
+                    else hi = mid - 1;
+                }
+                const uint32_t rel = j - s_a6[wave][lo];
+                const uint32_t w = s_a1[wave][lo], xy = s_a0[wave][lo];
+                const uint32_t ty = (xy >> 16) + rel / w, tx = (xy & 0xFFFFu) + rel % w;
+                const int64_t k = kw + (int64_t)j;
+                keys[k] = ((uint64_t)(s_a3[wave][lo] + ty * (uint32_t)TX + tx) << 32) | (uint64_t)s_a2[wave][lo];
+                vals[k] = s_a5[wave][lo];
             }
-            const uint32_t rel = j - s_start[wave][lo];
-            const uint32_t w = s_w[wave][lo], xy = s_xy[wave][lo];
-            const uint32_t ty = (xy >> 16) + rel / w, tx = (xy & 0xFFFFu) + rel % w;
-            const int64_t k = kw + (int64_t)j;
-            keys[k] = ((uint64_t)(s_tb[wave][lo] + ty * (uint32_t)TX + tx) << 32) | (uint64_t)s_z[wave][lo];
-            vals[k] = (uint32_t)(ginst + lo);
         }
-        __syncthreads();  // s_scan and the per-wave arrays are reused by the next tile
+        __syncthreads();  // s_wsum and the lists are reused by the next tile
     }
     __syncthreads();
     uint32_t *row = rows + (size_t)blockIdx.x * passes * kHistStride;
-    for (int k = threadIdx.x; k < passes * kHistStride; k += kScanBlock) row[k] = (&s_h[0][0])[k];
+    for (int k = threadIdx.x; k < passes * kHistStride; k += kEmitBlock) row[k] = (&s_h[0][0])[k];
 }
 
 // Partial sums of the emission rows: part[ry][c] = sum of rows[r][c] over the
@@ -316,11 +345,11 @@ __global__ void __launch_bounds__(kSortBlock) onesweep_kernel(const uint64_t *__
                                                               uint64_t *__restrict__ keys_out,
                                                               uint32_t *__restrict__ vals_out, const int64_t *d_num,
                                                               int64_t capacity, int shift,
-                                                              const uint32_t *hist_part /*[kHistRows][stride]*/,
-                                                              int hist_stride,
-                                                              uint32_t *status /*[parts][256]*/, uint32_t *ticket,
+                                                              const uint32_t *digit_base /*[256]*/,
+                                                              uint32_t *status /*[256][parts_stride]*/,
+                                                              int64_t parts_stride, uint32_t *ticket,
                                                               const int32_t *d_overflow) {
-    __shared__ uint32_t s_part;
+    __shared__ uint32_t s_part, s_next;
     __shared__ uint32_t s_wh[kSortWaves][kBins];  // per-wave digit counts -> prefix across waves
     __shared__ uint32_t s_local[kBins];           // block-local exclusive digit start
     __shared__ uint32_t s_glob[kBins];            // global start of the digit for this partition
@@ -334,34 +363,14 @@ __global__ void __launch_bounds__(kSortBlock) onesweep_kernel(const uint64_t *__
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     if (*d_overflow) return;  // keys beyond the capacity were dropped: nothing consistent to sort
     const int64_t K = sort_count(d_num, capacity);
-    // digit counts = prefix sums of the difference array (the sum of the
-    // partial rows), then their exclusive scan
-    if (tid < kBins) {
-        uint32_t v = 0u;
-#pragma unroll
-        for (int r = 0; r < kHistRows; ++r) v += hist_part[(size_t)r * hist_stride + tid];
-        s_scan[tid] = v;
-    }
+    // the first ticket and the digit bases, in flight together
+    if (tid == 0) s_part = atomicAdd(ticket, 1u);
+    if (tid < kBins) s_base[tid] = digit_base[tid];
+    for (int k = tid; k < kSortWaves * kBins; k += kSortBlock) (&s_wh[0][0])[k] = 0u;
     __syncthreads();
-    for (int round = 0; round < 2; ++round) {
-        uint32_t own = 0u;
-        if (tid < kBins) own = s_scan[tid];
-        for (int off = 1; off < kBins; off <<= 1) {
-            uint32_t t = 0u;
-            if (tid < kBins && tid >= off) t = s_scan[tid - off];
-            __syncthreads();
-            if (tid < kBins) s_scan[tid] += t;
-            __syncthreads();
-        }
-        if (round == 1 && tid < kBins) s_base[tid] = s_scan[tid] - own;  // exclusive
-        __syncthreads();
-    }
+    uint32_t part = s_part;
     // persistent: take partitions in ticket order until none is left
     while (true) {
-        if (tid == 0) s_part = atomicAdd(ticket, 1u);
-        for (int k = tid; k < kSortWaves * kBins; k += kSortBlock) (&s_wh[0][0])[k] = 0u;
-        __syncthreads();
-        const uint32_t part = s_part;
         const int64_t start = (int64_t)part * (kSortBlock * ITEMS);
         if (start >= K) return;  // uniform across the workgroup
 
@@ -418,20 +427,20 @@ __global__ void __launch_bounds__(kSortBlock) onesweep_kernel(const uint64_t *__
             }
             total = run;
             // decoupled look-back: publish the aggregate, then walk back over
-            // the predecessors LOOKBACK at a time until an inclusive prefix
-            uint32_t *col = status + d;
+            // the predecessors LOOKBACK at a time until an inclusive prefix;
+            // digit d's statuses of consecutive partitions are contiguous
+            uint32_t *col = status + (size_t)d * parts_stride;
             uint32_t prefix = 0u;
             if (part == 0) {
                 __hip_atomic_store(col, kFlagIncl | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             } else {
-                __hip_atomic_store(col + (size_t)part * kBins, kFlagAgg | total, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(col + part, kFlagAgg | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 int64_t p = (int64_t)part - 1;
                 while (true) {
                     uint32_t w[LOOKBACK];
 #pragma unroll
                     for (int i = 0; i < LOOKBACK; ++i)
-                        w[i] = (p - i >= 0) ? __hip_atomic_load(col + (size_t)(p - i) * kBins, __ATOMIC_RELAXED,
+                        w[i] = (p - i >= 0) ? __hip_atomic_load(col + (p - i), __ATOMIC_RELAXED,
                                                                 __HIP_MEMORY_SCOPE_AGENT)
                                             : kFlagIncl;  // never reached: partition 0 is inclusive
                     bool stop = false, incl = false;
@@ -456,7 +465,7 @@ __global__ void __launch_bounds__(kSortBlock) onesweep_kernel(const uint64_t *__
                     p -= consumed;
                     if (consumed < LOOKBACK) __builtin_amdgcn_s_sleep(1);
                 }
-                __hip_atomic_store(col + (size_t)part * kBins, kFlagIncl | (prefix + total), __ATOMIC_RELAXED,
+                __hip_atomic_store(col + part, kFlagIncl | (prefix + total), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
             }
             s_glob[d] = s_base[d] + prefix;
@@ -472,6 +481,7 @@ __global__ void __launch_bounds__(kSortBlock) onesweep_kernel(const uint64_t *__
             __syncthreads();
         }
         if (tid < kBins) s_local[tid] = s_scan[tid] - total;
+        if (tid == 0) s_next = atomicAdd(ticket, 1u);  // the next partition, taken ahead of the scatter
         __syncthreads();
         // stage into LDS in block-local sorted order
 #pragma unroll
@@ -495,7 +505,41 @@ __global__ void __launch_bounds__(kSortBlock) onesweep_kernel(const uint64_t *__
             vals_out[dst] = s_vals[q];
         }
         __syncthreads();  // LDS is reused by the next partition
+        part = s_next;
+        for (int k = tid; k < kSortWaves * kBins; k += kSortBlock) (&s_wh[0][0])[k] = 0u;
+        __syncthreads();
     }
+}
+
+// inclusive scan over the 256 threads of a workgroup (four waves)
+__device__ __forceinline__ uint32_t block256_inclusive_scan(uint32_t v, uint32_t *s_w) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(v, off, 64);
+        if (lane >= off) v += y;
+    }
+    if (lane == 63) s_w[wave] = v;
+    __syncthreads();
+    for (int k = 0; k < wave; ++k) v += s_w[k];
+    __syncthreads();
+    return v;
+}
+
+// Global start of every digit of every pass: digit counts are the prefix
+// sums of the difference arrays (the sum of the partial rows), and the start
+// of digit d is the exclusive prefix of the counts.  One workgroup per pass.
+__global__ void __launch_bounds__(kBins) digit_base_kernel(const uint32_t *hist_part /*[kHistRows][stride]*/,
+                                                           int stride, uint32_t *base /*[passes][256]*/) {
+    __shared__ uint32_t s_w[kBins / 64];
+    const int d = threadIdx.x;
+    const uint32_t *h = hist_part + blockIdx.x * kHistStride;
+    uint32_t v = 0u;
+#pragma unroll
+    for (int r = 0; r < kHistRows; ++r) v += h[(size_t)r * stride + d];
+    const uint32_t count = block256_inclusive_scan(v, s_w);
+    const uint32_t running = block256_inclusive_scan(count, s_w);
+    base[blockIdx.x * kBins + d] = running - count;
 }
 
 // ---------------------------------------------------------------------------
@@ -545,6 +589,8 @@ SortPlan make_sort_plan(int64_t n, int64_t capacity, int64_t n_tiles_total) {
     o = align256(o + sizeof(uint32_t) * (size_t)(capacity > 0 ? capacity : 1));
     p.off_rows = o;
     o = align256(o + sizeof(uint32_t) * (size_t)kEmitGrid * p.passes * kHistStride);
+    p.off_dbase = o;
+    o = align256(o + sizeof(uint32_t) * (size_t)kMaxPasses * kBins);
     // histogram partials, status and tickets are contiguous so one fill clears them
     p.off_hist = o;
     o = o + sizeof(uint32_t) * (size_t)kHistRows * kMaxPasses * kHistStride;
@@ -565,6 +611,7 @@ hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec
     uint32_t *vals2 = reinterpret_cast<uint32_t *>(ws + P.off_vals2);
     uint32_t *hist = reinterpret_cast<uint32_t *>(ws + P.off_hist);
     uint32_t *rows = reinterpret_cast<uint32_t *>(ws + P.off_rows);
+    uint32_t *dbase = reinterpret_cast<uint32_t *>(ws + P.off_dbase);
     uint32_t *ticket = reinterpret_cast<uint32_t *>(ws + P.off_ticket);
     uint32_t *status = reinterpret_cast<uint32_t *>(ws + P.off_status);
     const size_t clear_words = (P.off_status - P.off_hist) / 4 + (size_t)P.passes * P.sort_parts * kBins;
@@ -590,18 +637,21 @@ hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec
     if (P.n > 0) {
         int64_t eg = P.scan_blocks;
         if (eg > kEmitGrid) eg = kEmitGrid;
-        if ((e = launch_kernel(emit_kernel, dim3((unsigned)eg), dim3(kScanBlock), s, tt, part, rec, P.n,
+        if ((e = launch_kernel(emit_kernel, dim3((unsigned)eg), dim3(kEmitBlock), s, tt, part, rec, P.n,
                                P.scan_blocks, TX, TY, P.capacity, k_a, v_a, P.passes, rows, eg)) != hipSuccess)
             return e;
         const int cols = P.passes * kHistStride;
         if ((e = launch_kernel(hist_reduce_kernel, dim3((unsigned)((cols + 63) / 64), kHistRows), dim3(256), s, rows,
                                (int)eg, cols, hist)) != hipSuccess)
             return e;
+        if ((e = launch_kernel(digit_base_kernel, dim3((unsigned)P.passes), dim3(kBins), s, hist, cols, dbase)) !=
+            hipSuccess)
+            return e;
     }
     // 3. onesweep passes over the significant bits (digit counts come from the emission)
     // persistent grid: one workgroup per CU (60 or 110 KB of LDS)
     using SweepFn = void (*)(const uint64_t *, const uint32_t *, uint64_t *, uint32_t *, const int64_t *, int64_t,
-                             int, const uint32_t *, int, uint32_t *, uint32_t *, const int32_t *);
+                             int, const uint32_t *, uint32_t *, int64_t, uint32_t *, const int32_t *);
     SweepFn sweep;
     const int part_keys = (P.part_keys == 2 * kMinSortPart) ? 2 * kMinSortPart : kMinSortPart;
     if (part_keys == kMinSortPart)
@@ -616,8 +666,8 @@ hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec
     if (sg < 1) sg = 1;
     for (int p = 0; p < P.passes; ++p) {
         if ((e = launch_kernel(sweep, dim3((unsigned)sg), dim3(kSortBlock), s, k_a, v_a, k_b, v_b, d_num,
-                               P.capacity, p * kRadixBits, hist + p * kHistStride, P.passes * kHistStride,
-                               status + (size_t)p * P.sort_parts * kBins, ticket + p * 64, d_overflow)) != hipSuccess)
+                               P.capacity, p * kRadixBits, dbase + p * kBins,
+                               status + (size_t)p * P.sort_parts * kBins, P.sort_parts, ticket + p * 64, d_overflow)) != hipSuccess)
             return e;
         uint64_t *tk = k_a;
         k_a = k_b;
