@@ -346,8 +346,7 @@ __global__ void __launch_bounds__(kSortBlock) onesweep_kernel(const uint64_t *__
                                                               uint32_t *__restrict__ vals_out, const int64_t *d_num,
                                                               int64_t capacity, int shift,
                                                               const uint32_t *digit_base /*[256]*/,
-                                                              uint32_t *status /*[256][parts_stride]*/,
-                                                              int64_t parts_stride, uint32_t *ticket,
+                                                              uint32_t *status /*[parts][256]*/, uint32_t *ticket,
                                                               const int32_t *d_overflow) {
     __shared__ uint32_t s_part, s_next;
     __shared__ uint32_t s_wh[kSortWaves][kBins];  // per-wave digit counts -> prefix across waves
@@ -427,20 +426,22 @@ __global__ void __launch_bounds__(kSortBlock) onesweep_kernel(const uint64_t *__
             }
             total = run;
             // decoupled look-back: publish the aggregate, then walk back over
-            // the predecessors LOOKBACK at a time until an inclusive prefix;
-            // digit d's statuses of consecutive partitions are contiguous
-            uint32_t *col = status + (size_t)d * parts_stride;
+            // the predecessors LOOKBACK at a time until an inclusive prefix.
+            // Statuses are partition-major (one 1-KB row per partition), so a
+            // workgroup publishes into lines no other workgroup writes.
+            uint32_t *col = status + d;
             uint32_t prefix = 0u;
             if (part == 0) {
                 __hip_atomic_store(col, kFlagIncl | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             } else {
-                __hip_atomic_store(col + part, kFlagAgg | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(col + (size_t)part * kBins, kFlagAgg | total, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
                 int64_t p = (int64_t)part - 1;
                 while (true) {
                     uint32_t w[LOOKBACK];
 #pragma unroll
                     for (int i = 0; i < LOOKBACK; ++i)
-                        w[i] = (p - i >= 0) ? __hip_atomic_load(col + (p - i), __ATOMIC_RELAXED,
+                        w[i] = (p - i >= 0) ? __hip_atomic_load(col + (size_t)(p - i) * kBins, __ATOMIC_RELAXED,
                                                                 __HIP_MEMORY_SCOPE_AGENT)
                                             : kFlagIncl;  // never reached: partition 0 is inclusive
                     bool stop = false, incl = false;
@@ -465,7 +466,7 @@ __global__ void __launch_bounds__(kSortBlock) onesweep_kernel(const uint64_t *__
                     p -= consumed;
                     if (consumed < LOOKBACK) __builtin_amdgcn_s_sleep(1);
                 }
-                __hip_atomic_store(col + part, kFlagIncl | (prefix + total), __ATOMIC_RELAXED,
+                __hip_atomic_store(col + (size_t)part * kBins, kFlagIncl | (prefix + total), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
             }
             s_glob[d] = s_base[d] + prefix;
@@ -651,7 +652,7 @@ hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec
     // 3. onesweep passes over the significant bits (digit counts come from the emission)
     // persistent grid: one workgroup per CU (60 or 110 KB of LDS)
     using SweepFn = void (*)(const uint64_t *, const uint32_t *, uint64_t *, uint32_t *, const int64_t *, int64_t,
-                             int, const uint32_t *, uint32_t *, int64_t, uint32_t *, const int32_t *);
+                             int, const uint32_t *, uint32_t *, uint32_t *, const int32_t *);
     SweepFn sweep;
     const int part_keys = (P.part_keys == 2 * kMinSortPart) ? 2 * kMinSortPart : kMinSortPart;
     if (part_keys == kMinSortPart)
@@ -667,7 +668,7 @@ hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec
     for (int p = 0; p < P.passes; ++p) {
         if ((e = launch_kernel(sweep, dim3((unsigned)sg), dim3(kSortBlock), s, k_a, v_a, k_b, v_b, d_num,
                                P.capacity, p * kRadixBits, dbase + p * kBins,
-                               status + (size_t)p * P.sort_parts * kBins, P.sort_parts, ticket + p * 64, d_overflow)) != hipSuccess)
+                               status + (size_t)p * P.sort_parts * kBins, ticket + p * 64, d_overflow)) != hipSuccess)
             return e;
         uint64_t *tk = k_a;
         k_a = k_b;
