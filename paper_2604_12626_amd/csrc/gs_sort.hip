@@ -425,52 +425,71 @@ __global__ void __launch_bounds__(kSortBlock) onesweep_kernel(const uint64_t *__
                 run += c;
             }
             total = run;
-            // decoupled look-back: publish the aggregate, then walk back over
-            // the predecessors LOOKBACK at a time until an inclusive prefix.
-            // Statuses are partition-major (one 1-KB row per partition), so a
-            // workgroup publishes into lines no other workgroup writes.
-            uint32_t *col = status + d;
-            uint32_t prefix = 0u;
+            s_scan[d] = total;
+        }
+        __syncthreads();
+        // Decoupled look-back, two digits per thread: one 64-bit status word
+        // holds digits 2t (low half) and 2t + 1 (high half) of a partition.
+        // Publish the aggregates, then walk back over the predecessors
+        // LOOKBACK at a time until an inclusive prefix.  Statuses are
+        // partition-major (one 1-KB row per partition), so a workgroup
+        // publishes into lines no other workgroup writes.  A digit with no
+        // key in this partition skips the walk (its prefix is never used;
+        // its aggregate, 0, lets successors walk past).
+        if (tid < kBins / 2) {
+            const uint32_t t0 = s_scan[2 * tid], t1 = s_scan[2 * tid + 1];
+            uint64_t *col = reinterpret_cast<uint64_t *>(status) + tid;
+            constexpr uint32_t kRow = kBins / 2;  // 64-bit words per partition row
+            uint32_t pre[2] = {0u, 0u};
             if (part == 0) {
-                __hip_atomic_store(col, kFlagIncl | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            } else {
-                __hip_atomic_store(col + (size_t)part * kBins, kFlagAgg | total, __ATOMIC_RELAXED,
+                __hip_atomic_store(col, ((uint64_t)(kFlagIncl | t1) << 32) | (kFlagIncl | t0), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
-                int64_t p = (int64_t)part - 1;
-                while (true) {
-                    uint32_t w[LOOKBACK];
+            } else {
+                __hip_atomic_store(col + (size_t)part * kRow, ((uint64_t)(kFlagAgg | t1) << 32) | (kFlagAgg | t0),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                bool done[2] = {t0 == 0u, t1 == 0u};
+                int64_t ph[2] = {(int64_t)part - 1, (int64_t)part - 1};  // next predecessor to read, per half
+                while (!(done[0] && done[1])) {
+                    // the window starts at the half that is further behind
+                    const int64_t p = done[0] ? ph[1] : done[1] ? ph[0] : (ph[0] > ph[1] ? ph[0] : ph[1]);
+                    uint64_t w[LOOKBACK];
 #pragma unroll
                     for (int i = 0; i < LOOKBACK; ++i)
-                        w[i] = (p - i >= 0) ? __hip_atomic_load(col + (size_t)(p - i) * kBins, __ATOMIC_RELAXED,
+                        w[i] = (p - i >= 0) ? __hip_atomic_load(col + (size_t)(p - i) * kRow, __ATOMIC_RELAXED,
                                                                 __HIP_MEMORY_SCOPE_AGENT)
-                                            : kFlagIncl;  // never reached: partition 0 is inclusive
-                    bool stop = false, incl = false;
-                    int consumed = 0;
+                                            : 0ull;  // never reached: partition 0 is inclusive
+                    bool stalled = false;
 #pragma unroll
-                    for (int i = 0; i < LOOKBACK; ++i) {
-                        if (!stop) {
-                            const uint32_t flag = w[i] & ~kCountMask;
+                    for (int h = 0; h < 2; ++h) {
+                        if (done[h]) continue;
+                        bool stop = false;
+#pragma unroll
+                        for (int i = 0; i < LOOKBACK; ++i) {
+                            if (stop || p - i > ph[h]) continue;  // entries this half already consumed
+                            const uint32_t x = (uint32_t)(w[i] >> (32 * h));
+                            const uint32_t flag = x & ~kCountMask;
                             if (flag == 0u) {
                                 stop = true;  // not published yet: poll again from here
+                                stalled = true;
                             } else {
-                                prefix += w[i] & kCountMask;
-                                ++consumed;
+                                pre[h] += x & kCountMask;
+                                ph[h] = p - i - 1;
                                 if (flag == kFlagIncl) {
-                                    incl = true;
+                                    done[h] = true;
                                     stop = true;
                                 }
                             }
                         }
                     }
-                    if (incl) break;
-                    p -= consumed;
-                    if (consumed < LOOKBACK) __builtin_amdgcn_s_sleep(1);
+                    if (stalled) __builtin_amdgcn_s_sleep(1);
                 }
-                __hip_atomic_store(col + (size_t)part * kBins, kFlagIncl | (prefix + total), __ATOMIC_RELAXED,
+                const uint32_t s0 = t0 ? (kFlagIncl | (pre[0] + t0)) : kFlagAgg;
+                const uint32_t s1 = t1 ? (kFlagIncl | (pre[1] + t1)) : kFlagAgg;
+                __hip_atomic_store(col + (size_t)part * kRow, ((uint64_t)s1 << 32) | s0, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
             }
-            s_glob[d] = s_base[d] + prefix;
-            s_scan[d] = total;
+            s_glob[2 * tid] = s_base[2 * tid] + pre[0];
+            s_glob[2 * tid + 1] = s_base[2 * tid + 1] + pre[1];
         }
         __syncthreads();
         // block-local exclusive scan of the digit totals
