@@ -34,6 +34,7 @@ constexpr int kBins = 1 << kRadixBits;
 constexpr int kMaxPasses = 8;
 constexpr int kHistStride = kBins + 1;  // per-pass difference array of the digit counts
 constexpr int kHistRows = 16;           // partial histogram rows left by hist_reduce_kernel
+constexpr uint32_t kGroup = 16;  // partitions per look-back group
 constexpr uint32_t kFlagAgg = 1u << 30;
 constexpr uint32_t kFlagIncl = 2u << 30;
 constexpr uint32_t kCountMask = (1u << 30) - 1u;
@@ -346,7 +347,8 @@ __global__ void __launch_bounds__(kSortBlock) onesweep_kernel(const uint64_t *__
                                                               uint32_t *__restrict__ vals_out, const int64_t *d_num,
                                                               int64_t capacity, int shift,
                                                               const uint32_t *digit_base /*[256]*/,
-                                                              uint32_t *status /*[parts][256]*/, uint32_t *ticket,
+                                                              uint32_t *status /*[parts][256]*/,
+                                                              uint32_t *gstatus /*[groups][256]*/, uint32_t *ticket,
                                                               const int32_t *d_overflow) {
     __shared__ uint32_t s_part, s_next;
     __shared__ uint32_t s_wh[kSortWaves][kBins];  // per-wave digit counts -> prefix across waves
@@ -425,71 +427,90 @@ __global__ void __launch_bounds__(kSortBlock) onesweep_kernel(const uint64_t *__
                 run += c;
             }
             total = run;
-            s_scan[d] = total;
-        }
-        __syncthreads();
-        // Decoupled look-back, two digits per thread: one 64-bit status word
-        // holds digits 2t (low half) and 2t + 1 (high half) of a partition.
-        // Publish the aggregates, then walk back over the predecessors
-        // LOOKBACK at a time until an inclusive prefix.  Statuses are
-        // partition-major (one 1-KB row per partition), so a workgroup
-        // publishes into lines no other workgroup writes.  A digit with no
-        // key in this partition skips the walk (its prefix is never used;
-        // its aggregate, 0, lets successors walk past).
-        if (tid < kBins / 2) {
-            const uint32_t t0 = s_scan[2 * tid], t1 = s_scan[2 * tid + 1];
-            uint64_t *col = reinterpret_cast<uint64_t *>(status) + tid;
-            constexpr uint32_t kRow = kBins / 2;  // 64-bit words per partition row
-            uint32_t pre[2] = {0u, 0u};
-            if (part == 0) {
-                __hip_atomic_store(col, ((uint64_t)(kFlagIncl | t1) << 32) | (kFlagIncl | t0), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+            // Two-level decoupled look-back.  Partition p = 16 g + i first
+            // publishes its aggregate, then sums the aggregates of its group
+            // siblings 16 g .. p - 1 (one round trip once they are
+            // published).  The group's last partition publishes the group
+            // aggregate, and every partition walks back over the group
+            // statuses LOOKBACK at a time until an inclusive group prefix,
+            // which the group's last partition then publishes.  All
+            // partitions of a pass run at once here, so a one-level walk
+            // would take a round trip per LOOKBACK predecessors; this takes
+            // a few.  Statuses are partition-major rows (and group-major
+            // rows), so a workgroup publishes into lines no other
+            // workgroup writes.
+            const uint32_t g = part / kGroup, i = part % kGroup;
+            uint32_t *l1 = status + d;
+            uint32_t *l2 = gstatus + d;
+            __hip_atomic_store(l1 + (size_t)part * kBins, kFlagAgg | total, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            uint32_t local = 0u;
+            if (i > 0) {
+                while (true) {
+                    uint32_t sum = 0u;
+                    bool ready = true;
+#pragma unroll
+                    for (uint32_t j = 0; j < kGroup - 1; ++j) {
+                        if (j < i) {
+                            const uint32_t x = __hip_atomic_load(l1 + (size_t)(g * kGroup + j) * kBins,
+                                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            ready = ready && (x & ~kCountMask) != 0u;
+                            sum += x & kCountMask;
+                        }
+                    }
+                    if (ready) {
+                        local = sum;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            }
+            uint32_t gprefix = 0u;
+            const bool last_in_group = (i == kGroup - 1);
+            if (g == 0) {
+                if (last_in_group)
+                    __hip_atomic_store(l2, kFlagIncl | (local + total), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             } else {
-                __hip_atomic_store(col + (size_t)part * kRow, ((uint64_t)(kFlagAgg | t1) << 32) | (kFlagAgg | t0),
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                bool done[2] = {t0 == 0u, t1 == 0u};
-                int64_t ph[2] = {(int64_t)part - 1, (int64_t)part - 1};  // next predecessor to read, per half
-                while (!(done[0] && done[1])) {
-                    // the window starts at the half that is further behind
-                    const int64_t p = done[0] ? ph[1] : done[1] ? ph[0] : (ph[0] > ph[1] ? ph[0] : ph[1]);
-                    uint64_t w[LOOKBACK];
+                if (last_in_group)
+                    __hip_atomic_store(l2 + (size_t)g * kBins, kFlagAgg | (local + total), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                int64_t q = (int64_t)g - 1;
+                while (true) {
+                    uint32_t w[LOOKBACK];
 #pragma unroll
-                    for (int i = 0; i < LOOKBACK; ++i)
-                        w[i] = (p - i >= 0) ? __hip_atomic_load(col + (size_t)(p - i) * kRow, __ATOMIC_RELAXED,
+                    for (int k = 0; k < LOOKBACK; ++k)
+                        w[k] = (q - k >= 0) ? __hip_atomic_load(l2 + (size_t)(q - k) * kBins, __ATOMIC_RELAXED,
                                                                 __HIP_MEMORY_SCOPE_AGENT)
-                                            : 0ull;  // never reached: partition 0 is inclusive
-                    bool stalled = false;
+                                            : kFlagIncl;  // never reached: group 0 is inclusive
+                    bool stop = false, incl = false;
+                    int consumed = 0;
 #pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        if (done[h]) continue;
-                        bool stop = false;
-#pragma unroll
-                        for (int i = 0; i < LOOKBACK; ++i) {
-                            if (stop || p - i > ph[h]) continue;  // entries this half already consumed
-                            const uint32_t x = (uint32_t)(w[i] >> (32 * h));
-                            const uint32_t flag = x & ~kCountMask;
+                    for (int k = 0; k < LOOKBACK; ++k) {
+                        if (!stop) {
+                            const uint32_t flag = w[k] & ~kCountMask;
                             if (flag == 0u) {
                                 stop = true;  // not published yet: poll again from here
-                                stalled = true;
                             } else {
-                                pre[h] += x & kCountMask;
-                                ph[h] = p - i - 1;
+                                gprefix += w[k] & kCountMask;
+                                ++consumed;
                                 if (flag == kFlagIncl) {
-                                    done[h] = true;
+                                    incl = true;
                                     stop = true;
                                 }
                             }
                         }
                     }
-                    if (stalled) __builtin_amdgcn_s_sleep(1);
+                    if (incl) break;
+                    q -= consumed;
+                    if (consumed < LOOKBACK) __builtin_amdgcn_s_sleep(1);
                 }
-                const uint32_t s0 = t0 ? (kFlagIncl | (pre[0] + t0)) : kFlagAgg;
-                const uint32_t s1 = t1 ? (kFlagIncl | (pre[1] + t1)) : kFlagAgg;
-                __hip_atomic_store(col + (size_t)part * kRow, ((uint64_t)s1 << 32) | s0, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+                if (last_in_group)
+                    __hip_atomic_store(l2 + (size_t)g * kBins, kFlagIncl | (gprefix + local + total),
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            s_glob[2 * tid] = s_base[2 * tid] + pre[0];
-            s_glob[2 * tid + 1] = s_base[2 * tid + 1] + pre[1];
+            const uint32_t prefix = gprefix + local;
+            s_glob[d] = s_base[d] + prefix;
+            s_scan[d] = total;
         }
         __syncthreads();
         // block-local exclusive scan of the digit totals
@@ -618,6 +639,8 @@ SortPlan make_sort_plan(int64_t n, int64_t capacity, int64_t n_tiles_total) {
     o = o + sizeof(uint32_t) * (size_t)kMaxPasses * 64;
     p.off_status = o;
     o = o + sizeof(uint32_t) * (size_t)p.passes * (size_t)p.sort_parts * kBins;
+    p.sort_groups = (p.sort_parts + kGroup - 1) / kGroup;
+    o = o + sizeof(uint32_t) * (size_t)p.passes * (size_t)p.sort_groups * kBins;
     p.total = align256(o);
     return p;
 }
@@ -634,7 +657,9 @@ hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec
     uint32_t *dbase = reinterpret_cast<uint32_t *>(ws + P.off_dbase);
     uint32_t *ticket = reinterpret_cast<uint32_t *>(ws + P.off_ticket);
     uint32_t *status = reinterpret_cast<uint32_t *>(ws + P.off_status);
-    const size_t clear_words = (P.off_status - P.off_hist) / 4 + (size_t)P.passes * P.sort_parts * kBins;
+    uint32_t *gstatus = status + (size_t)P.passes * P.sort_parts * kBins;
+    const size_t clear_words = (P.off_status - P.off_hist) / 4 +
+                               (size_t)P.passes * (P.sort_parts + P.sort_groups) * kBins;
 
     if ((e = launch_kernel(clear2_kernel, dim3(1024), dim3(256), s, hist, (int64_t)clear_words, ranges,
                            2 * P.n_tiles_total, (int64_t)1024 * 256)) != hipSuccess)
@@ -671,7 +696,7 @@ hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec
     // 3. onesweep passes over the significant bits (digit counts come from the emission)
     // persistent grid: one workgroup per CU (60 or 110 KB of LDS)
     using SweepFn = void (*)(const uint64_t *, const uint32_t *, uint64_t *, uint32_t *, const int64_t *, int64_t,
-                             int, const uint32_t *, uint32_t *, uint32_t *, const int32_t *);
+                             int, const uint32_t *, uint32_t *, uint32_t *, uint32_t *, const int32_t *);
     SweepFn sweep;
     const int part_keys = (P.part_keys == 2 * kMinSortPart) ? 2 * kMinSortPart : kMinSortPart;
     if (part_keys == kMinSortPart)
@@ -687,7 +712,8 @@ hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec
     for (int p = 0; p < P.passes; ++p) {
         if ((e = launch_kernel(sweep, dim3((unsigned)sg), dim3(kSortBlock), s, k_a, v_a, k_b, v_b, d_num,
                                P.capacity, p * kRadixBits, dbase + p * kBins,
-                               status + (size_t)p * P.sort_parts * kBins, ticket + p * 64, d_overflow)) != hipSuccess)
+                               status + (size_t)p * P.sort_parts * kBins,
+                               gstatus + (size_t)p * P.sort_groups * kBins, ticket + p * 64, d_overflow)) != hipSuccess)
             return e;
         uint64_t *tk = k_a;
         k_a = k_b;
