@@ -362,32 +362,51 @@ __global__ void __launch_bounds__(kSortBlock) onesweep_kernel(const uint64_t *__
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    if (*d_overflow) return;  // keys beyond the capacity were dropped: nothing consistent to sort
+    // Everything the first partition needs is requested at once: the
+    // overflow flag, the key count, the first ticket, the digit bases, and --
+    // speculatively -- the keys of partition blockIdx.x, which is usually the
+    // ticket this workgroup draws (loads stay below the capacity; keys at or
+    // beyond the count are masked in the ranking).
+    const int32_t overflow = *d_overflow;
     const int64_t K = sort_count(d_num, capacity);
-    // the first ticket and the digit bases, in flight together
     if (tid == 0) s_part = atomicAdd(ticket, 1u);
     if (tid < kBins) s_base[tid] = digit_base[tid];
     for (int k = tid; k < kSortWaves * kBins; k += kSortBlock) (&s_wh[0][0])[k] = 0u;
+    uint64_t key[ITEMS];
+    uint32_t val[ITEMS];
+    const uint32_t spec = blockIdx.x;
+    {
+        const int64_t s0 = (int64_t)spec * (kSortBlock * ITEMS) + (int64_t)wave * (ITEMS * 64) + lane;
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const int64_t idx = s0 + j * 64;
+            key[j] = idx < capacity ? keys_in[idx] : ~0ull;
+            val[j] = idx < capacity ? vals_in[idx] : 0u;
+        }
+    }
+    if (overflow) return;  // keys beyond the capacity were dropped: nothing consistent to sort
     __syncthreads();
     uint32_t part = s_part;
+    bool loaded = (part == spec);
     // persistent: take partitions in ticket order until none is left
     while (true) {
         const int64_t start = (int64_t)part * (kSortBlock * ITEMS);
         if (start >= K) return;  // uniform across the workgroup
 
-        uint64_t key[ITEMS];
-        uint32_t val[ITEMS];
         uint32_t rank[ITEMS];
         uint32_t dig[ITEMS];
         // all loads first (independent, in flight together), then the ranking
         // (whose LDS fences would otherwise serialise one load per stripe)
+        if (!loaded) {
 #pragma unroll
-        for (int j = 0; j < ITEMS; ++j) {
-            const int64_t idx = start + (int64_t)wave * (ITEMS * 64) + j * 64 + lane;
-            const bool valid = idx < K;
-            key[j] = valid ? keys_in[idx] : ~0ull;
-            val[j] = valid ? vals_in[idx] : 0u;
+            for (int j = 0; j < ITEMS; ++j) {
+                const int64_t idx = start + (int64_t)wave * (ITEMS * 64) + j * 64 + lane;
+                const bool valid = idx < K;
+                key[j] = valid ? keys_in[idx] : ~0ull;
+                val[j] = valid ? vals_in[idx] : 0u;
+            }
         }
+        loaded = false;
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
             const int64_t idx = start + (int64_t)wave * (ITEMS * 64) + j * 64 + lane;
