@@ -96,7 +96,7 @@ struct SortPlan {
     int64_t n, capacity, n_tiles_total;
     int tile_bits, passes;
     int part_keys, lookback;  // onesweep partition size (4096 / 8192) and look-back window (16 / 32 / 64)
-    int64_t scan_blocks, sort_parts, sort_groups;
+    int64_t scan_blocks, sort_parts;
     // workspace layout (byte offsets)
     size_t off_part, off_keys2, off_vals2, off_rows, off_dbase, off_hist, off_status, off_ticket, total;
 };

@@ -34,7 +34,6 @@ constexpr int kBins = 1 << kRadixBits;
 constexpr int kMaxPasses = 8;
 constexpr int kHistStride = kBins + 1;  // per-pass difference array of the digit counts
 constexpr int kHistRows = 16;           // partial histogram rows left by hist_reduce_kernel
-constexpr uint32_t kGroup = 16;  // partitions per look-back group
 constexpr uint32_t kFlagAgg = 1u << 30;
 constexpr uint32_t kFlagIncl = 2u << 30;
 constexpr uint32_t kCountMask = (1u << 30) - 1u;
@@ -347,8 +346,7 @@ __global__ void __launch_bounds__(kSortBlock) onesweep_kernel(const uint64_t *__
                                                               uint32_t *__restrict__ vals_out, const int64_t *d_num,
                                                               int64_t capacity, int shift,
                                                               const uint32_t *digit_base /*[256]*/,
-                                                              uint32_t *status /*[parts][256]*/,
-                                                              uint32_t *gstatus /*[groups][256]*/, uint32_t *ticket,
+                                                              uint32_t *status /*[parts][256]*/, uint32_t *ticket,
                                                               const int32_t *d_overflow) {
     __shared__ uint32_t s_part, s_next;
     __shared__ uint32_t s_wh[kSortWaves][kBins];  // per-wave digit counts -> prefix across waves
@@ -362,51 +360,32 @@ __global__ void __launch_bounds__(kSortBlock) onesweep_kernel(const uint64_t *__
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    // Everything the first partition needs is requested at once: the
-    // overflow flag, the key count, the first ticket, the digit bases, and --
-    // speculatively -- the keys of partition blockIdx.x, which is usually the
-    // ticket this workgroup draws (loads stay below the capacity; keys at or
-    // beyond the count are masked in the ranking).
-    const int32_t overflow = *d_overflow;
+    if (*d_overflow) return;  // keys beyond the capacity were dropped: nothing consistent to sort
     const int64_t K = sort_count(d_num, capacity);
+    // the first ticket and the digit bases, in flight together
     if (tid == 0) s_part = atomicAdd(ticket, 1u);
     if (tid < kBins) s_base[tid] = digit_base[tid];
     for (int k = tid; k < kSortWaves * kBins; k += kSortBlock) (&s_wh[0][0])[k] = 0u;
-    uint64_t key[ITEMS];
-    uint32_t val[ITEMS];
-    const uint32_t spec = blockIdx.x;
-    {
-        const int64_t s0 = (int64_t)spec * (kSortBlock * ITEMS) + (int64_t)wave * (ITEMS * 64) + lane;
-#pragma unroll
-        for (int j = 0; j < ITEMS; ++j) {
-            const int64_t idx = s0 + j * 64;
-            key[j] = idx < capacity ? keys_in[idx] : ~0ull;
-            val[j] = idx < capacity ? vals_in[idx] : 0u;
-        }
-    }
-    if (overflow) return;  // keys beyond the capacity were dropped: nothing consistent to sort
     __syncthreads();
     uint32_t part = s_part;
-    bool loaded = (part == spec);
     // persistent: take partitions in ticket order until none is left
     while (true) {
         const int64_t start = (int64_t)part * (kSortBlock * ITEMS);
         if (start >= K) return;  // uniform across the workgroup
 
+        uint64_t key[ITEMS];
+        uint32_t val[ITEMS];
         uint32_t rank[ITEMS];
         uint32_t dig[ITEMS];
         // all loads first (independent, in flight together), then the ranking
         // (whose LDS fences would otherwise serialise one load per stripe)
-        if (!loaded) {
 #pragma unroll
-            for (int j = 0; j < ITEMS; ++j) {
-                const int64_t idx = start + (int64_t)wave * (ITEMS * 64) + j * 64 + lane;
-                const bool valid = idx < K;
-                key[j] = valid ? keys_in[idx] : ~0ull;
-                val[j] = valid ? vals_in[idx] : 0u;
-            }
+        for (int j = 0; j < ITEMS; ++j) {
+            const int64_t idx = start + (int64_t)wave * (ITEMS * 64) + j * 64 + lane;
+            const bool valid = idx < K;
+            key[j] = valid ? keys_in[idx] : ~0ull;
+            val[j] = valid ? vals_in[idx] : 0u;
         }
-        loaded = false;
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
             const int64_t idx = start + (int64_t)wave * (ITEMS * 64) + j * 64 + lane;
@@ -446,71 +425,35 @@ __global__ void __launch_bounds__(kSortBlock) onesweep_kernel(const uint64_t *__
                 run += c;
             }
             total = run;
-            // Two-level decoupled look-back.  Partition p = 16 g + i first
-            // publishes its aggregate, then sums the aggregates of its group
-            // siblings 16 g .. p - 1 (one round trip once they are
-            // published).  The group's last partition publishes the group
-            // aggregate, and every partition walks back over the group
-            // statuses LOOKBACK at a time until an inclusive group prefix,
-            // which the group's last partition then publishes.  All
-            // partitions of a pass run at once here, so a one-level walk
-            // would take a round trip per LOOKBACK predecessors; this takes
-            // a few.  Statuses are partition-major rows (and group-major
-            // rows), so a workgroup publishes into lines no other
-            // workgroup writes.
-            const uint32_t g = part / kGroup, i = part % kGroup;
-            uint32_t *l1 = status + d;
-            uint32_t *l2 = gstatus + d;
-            __hip_atomic_store(l1 + (size_t)part * kBins, kFlagAgg | total, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-            uint32_t local = 0u;
-            if (i > 0) {
-                while (true) {
-                    uint32_t sum = 0u;
-                    bool ready = true;
-#pragma unroll
-                    for (uint32_t j = 0; j < kGroup - 1; ++j) {
-                        if (j < i) {
-                            const uint32_t x = __hip_atomic_load(l1 + (size_t)(g * kGroup + j) * kBins,
-                                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            ready = ready && (x & ~kCountMask) != 0u;
-                            sum += x & kCountMask;
-                        }
-                    }
-                    if (ready) {
-                        local = sum;
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                }
-            }
-            uint32_t gprefix = 0u;
-            const bool last_in_group = (i == kGroup - 1);
-            if (g == 0) {
-                if (last_in_group)
-                    __hip_atomic_store(l2, kFlagIncl | (local + total), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // decoupled look-back: publish the aggregate, then walk back over
+            // the predecessors LOOKBACK at a time until an inclusive prefix.
+            // Statuses are partition-major (one 1-KB row per partition), so a
+            // workgroup publishes into lines no other workgroup writes.
+            uint32_t *col = status + d;
+            uint32_t prefix = 0u;
+            if (part == 0) {
+                __hip_atomic_store(col, kFlagIncl | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             } else {
-                if (last_in_group)
-                    __hip_atomic_store(l2 + (size_t)g * kBins, kFlagAgg | (local + total), __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-                int64_t q = (int64_t)g - 1;
+                __hip_atomic_store(col + (size_t)part * kBins, kFlagAgg | total, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                int64_t p = (int64_t)part - 1;
                 while (true) {
                     uint32_t w[LOOKBACK];
 #pragma unroll
-                    for (int k = 0; k < LOOKBACK; ++k)
-                        w[k] = (q - k >= 0) ? __hip_atomic_load(l2 + (size_t)(q - k) * kBins, __ATOMIC_RELAXED,
+                    for (int i = 0; i < LOOKBACK; ++i)
+                        w[i] = (p - i >= 0) ? __hip_atomic_load(col + (size_t)(p - i) * kBins, __ATOMIC_RELAXED,
                                                                 __HIP_MEMORY_SCOPE_AGENT)
-                                            : kFlagIncl;  // never reached: group 0 is inclusive
+                                            : kFlagIncl;  // never reached: partition 0 is inclusive
                     bool stop = false, incl = false;
                     int consumed = 0;
 #pragma unroll
-                    for (int k = 0; k < LOOKBACK; ++k) {
+                    for (int i = 0; i < LOOKBACK; ++i) {
                         if (!stop) {
-                            const uint32_t flag = w[k] & ~kCountMask;
+                            const uint32_t flag = w[i] & ~kCountMask;
                             if (flag == 0u) {
                                 stop = true;  // not published yet: poll again from here
                             } else {
-                                gprefix += w[k] & kCountMask;
+                                prefix += w[i] & kCountMask;
                                 ++consumed;
                                 if (flag == kFlagIncl) {
                                     incl = true;
@@ -520,14 +463,12 @@ __global__ void __launch_bounds__(kSortBlock) onesweep_kernel(const uint64_t *__
                         }
                     }
                     if (incl) break;
-                    q -= consumed;
+                    p -= consumed;
                     if (consumed < LOOKBACK) __builtin_amdgcn_s_sleep(1);
                 }
-                if (last_in_group)
-                    __hip_atomic_store(l2 + (size_t)g * kBins, kFlagIncl | (gprefix + local + total),
-                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(col + (size_t)part * kBins, kFlagIncl | (prefix + total), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
             }
-            const uint32_t prefix = gprefix + local;
             s_glob[d] = s_base[d] + prefix;
             s_scan[d] = total;
         }
@@ -658,8 +599,6 @@ SortPlan make_sort_plan(int64_t n, int64_t capacity, int64_t n_tiles_total) {
     o = o + sizeof(uint32_t) * (size_t)kMaxPasses * 64;
     p.off_status = o;
     o = o + sizeof(uint32_t) * (size_t)p.passes * (size_t)p.sort_parts * kBins;
-    p.sort_groups = (p.sort_parts + kGroup - 1) / kGroup;
-    o = o + sizeof(uint32_t) * (size_t)p.passes * (size_t)p.sort_groups * kBins;
     p.total = align256(o);
     return p;
 }
@@ -676,9 +615,7 @@ hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec
     uint32_t *dbase = reinterpret_cast<uint32_t *>(ws + P.off_dbase);
     uint32_t *ticket = reinterpret_cast<uint32_t *>(ws + P.off_ticket);
     uint32_t *status = reinterpret_cast<uint32_t *>(ws + P.off_status);
-    uint32_t *gstatus = status + (size_t)P.passes * P.sort_parts * kBins;
-    const size_t clear_words = (P.off_status - P.off_hist) / 4 +
-                               (size_t)P.passes * (P.sort_parts + P.sort_groups) * kBins;
+    const size_t clear_words = (P.off_status - P.off_hist) / 4 + (size_t)P.passes * P.sort_parts * kBins;
 
     if ((e = launch_kernel(clear2_kernel, dim3(1024), dim3(256), s, hist, (int64_t)clear_words, ranges,
                            2 * P.n_tiles_total, (int64_t)1024 * 256)) != hipSuccess)
@@ -715,7 +652,7 @@ hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec
     // 3. onesweep passes over the significant bits (digit counts come from the emission)
     // persistent grid: one workgroup per CU (60 or 110 KB of LDS)
     using SweepFn = void (*)(const uint64_t *, const uint32_t *, uint64_t *, uint32_t *, const int64_t *, int64_t,
-                             int, const uint32_t *, uint32_t *, uint32_t *, uint32_t *, const int32_t *);
+                             int, const uint32_t *, uint32_t *, uint32_t *, const int32_t *);
     SweepFn sweep;
     const int part_keys = (P.part_keys == 2 * kMinSortPart) ? 2 * kMinSortPart : kMinSortPart;
     if (part_keys == kMinSortPart)
@@ -731,8 +668,7 @@ hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec
     for (int p = 0; p < P.passes; ++p) {
         if ((e = launch_kernel(sweep, dim3((unsigned)sg), dim3(kSortBlock), s, k_a, v_a, k_b, v_b, d_num,
                                P.capacity, p * kRadixBits, dbase + p * kBins,
-                               status + (size_t)p * P.sort_parts * kBins,
-                               gstatus + (size_t)p * P.sort_groups * kBins, ticket + p * 64, d_overflow)) != hipSuccess)
+                               status + (size_t)p * P.sort_parts * kBins, ticket + p * 64, d_overflow)) != hipSuccess)
             return e;
         uint64_t *tk = k_a;
         k_a = k_b;
