@@ -72,22 +72,37 @@ __global__ void __launch_bounds__(64 * kWavesPerGroup) composite_kernel(const Co
         float T = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f, dd = 0.0f;
         uint32_t last = 0;
         bool done = !inside;
-        for (uint32_t b0 = range.x; b0 < range.y; b0 += 64) {
-            const uint32_t j = b0 + lane;
-            bool hit = false;
-            float4 q0, q1, q2;
-            if (j < range.y) {
-                const uint32_t g = a.vals[j];
+        // software pipeline over the list chunks: while chunk c is culled and
+        // composited, the records of chunk c + 1 and the list values of
+        // chunk c + 2 are already in flight
+        uint32_t g_next = 0u;  // list value of this lane's entry in the next chunk
+        float4 q0, q1, q2;     // this lane's record in the current chunk
+        {
+            const uint32_t j0 = range.x + lane, j1 = range.x + 64 + lane;
+            if (j0 < range.y) {
+                const uint32_t g = a.vals[j0];
                 q0 = a.rec[3 * (size_t)g];
                 q1 = a.rec[3 * (size_t)g + 1];
                 q2 = a.rec[3 * (size_t)g + 2];
-                hit = entry_reaches_box(q0.x, q0.y, q1.x, q1.y, q1.z, q1.w, a.alpha_min, bx0, by0, bx0 + 7.0f,
-                                        by0 + 7.0f);
             }
+            if (j1 < range.y) g_next = a.vals[j1];
+        }
+        for (uint32_t b0 = range.x; b0 < range.y; b0 += 64) {
+            const uint32_t j = b0 + lane;
+            const bool hit = (j < range.y) && entry_reaches_box(q0.x, q0.y, q1.x, q1.y, q1.z, q1.w, a.alpha_min,
+                                                               bx0, by0, bx0 + 7.0f, by0 + 7.0f);
+            const float4 c0 = q0, c1 = q1, c2 = q2;
+            // next chunk's records, and the list values of the one after
+            if (j + 64 < range.y) {
+                q0 = a.rec[3 * (size_t)g_next];
+                q1 = a.rec[3 * (size_t)g_next + 1];
+                q2 = a.rec[3 * (size_t)g_next + 2];
+            }
+            if (j + 128 < range.y) g_next = a.vals[j + 128];
             const uint64_t bal = __ballot(hit);
             if (hit) {
                 const int pos = __popcll(bal & lt_mask);
-                const Entry e = make_entry(q0, q1, q2);
+                const Entry e = make_entry(c0, c1, c2);
                 e0s[pos] = make_float4(e.u, e.v, e.a, e.b);
                 e1s[pos] = make_float4(e.c, e.o, e.z, e.r);
                 e2s[pos] = make_float4(e.g, e.bl, __uint_as_float(b0 - range.x + (uint32_t)lane + 1u), 0.0f);
