@@ -29,6 +29,13 @@ constexpr int kWavesPerGroup = 4;
 constexpr int kQueues = 8;         // one per XCD
 constexpr int kCounterStride = 32;  // words between queue heads (one 128-B line each)
 
+// wave issue priority 0..3 from the list length (512, 1024, 2048 entries)
+__device__ __forceinline__ void set_wave_priority(uint32_t len) {
+    if (len >= 2048u) __builtin_amdgcn_s_setprio(3);
+    else if (len >= 1024u) __builtin_amdgcn_s_setprio(2);
+    else if (len >= 512u) __builtin_amdgcn_s_setprio(1);
+}
+
 __global__ void __launch_bounds__(64 * kWavesPerGroup) composite_kernel(const CompositeArgs a) {
     __shared__ float4 s_e0[kWavesPerGroup][64], s_e1[kWavesPerGroup][64], s_e2[kWavesPerGroup][64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -69,6 +76,10 @@ __global__ void __launch_bounds__(64 * kWavesPerGroup) composite_kernel(const Co
         const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
         const float bx0 = (float)qx0 + 0.5f, by0 = (float)qy0 + 0.5f;
         const uint2 range = a.ranges[titem];
+        // Waves of long lists get a higher issue priority on their SIMD: the
+        // longest lists bound the kernel's duration, and shorter ones fill
+        // the issue slots those leave while they wait on memory.
+        set_wave_priority(range.y - range.x);
         float T = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f, dd = 0.0f;
         uint32_t last = 0;
         bool done = !inside;
@@ -142,6 +153,7 @@ __global__ void __launch_bounds__(64 * kWavesPerGroup) composite_kernel(const Co
             if (a.t_final) a.t_final[pix] = T;
             if (a.n_contrib) a.n_contrib[pix] = last;
         }
+        __builtin_amdgcn_s_setprio(0);
     }
     // every pop of every wave has happened once the last workgroup gets here
     __syncthreads();
