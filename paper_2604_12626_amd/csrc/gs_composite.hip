@@ -84,47 +84,32 @@ __global__ void __launch_bounds__(64 * kWavesPerGroup) composite_kernel(const Co
         uint32_t last = 0;
         bool done = !inside;
         // software pipeline over the list chunks: while chunk c is culled and
-        // composited, the records of chunks c + 1 and c + 2 and the list
-        // values of chunk c + 3 are already in flight
-        float4 q0, q1, q2;  // this lane's record in chunk c
-        float4 r0, r1, r2;  // ... in chunk c + 1
-        float4 s0, s1, s2;  // ... in chunk c + 2
-        uint32_t g_next = 0u;  // list value of this lane's entry in chunk c + 3 (then c + 2 on entry)
+        // composited, the records of chunk c + 1 and the list values of
+        // chunk c + 2 are already in flight
+        uint32_t g_next = 0u;  // list value of this lane's entry in the next chunk
+        float4 q0, q1, q2;     // this lane's record in the current chunk
         {
-            const uint32_t j0 = range.x + lane;
-            uint32_t g0 = 0u, g1 = 0u;
-            if (j0 < range.y) g0 = a.vals[j0];
-            if (j0 + 64 < range.y) g1 = a.vals[j0 + 64];
-            if (j0 + 128 < range.y) g_next = a.vals[j0 + 128];
+            const uint32_t j0 = range.x + lane, j1 = range.x + 64 + lane;
             if (j0 < range.y) {
-                q0 = a.rec[3 * (size_t)g0];
-                q1 = a.rec[3 * (size_t)g0 + 1];
-                q2 = a.rec[3 * (size_t)g0 + 2];
+                const uint32_t g = a.vals[j0];
+                q0 = a.rec[3 * (size_t)g];
+                q1 = a.rec[3 * (size_t)g + 1];
+                q2 = a.rec[3 * (size_t)g + 2];
             }
-            if (j0 + 64 < range.y) {
-                r0 = a.rec[3 * (size_t)g1];
-                r1 = a.rec[3 * (size_t)g1 + 1];
-                r2 = a.rec[3 * (size_t)g1 + 2];
-            }
+            if (j1 < range.y) g_next = a.vals[j1];
         }
         for (uint32_t b0 = range.x; b0 < range.y; b0 += 64) {
             const uint32_t j = b0 + lane;
             const bool hit = (j < range.y) && entry_reaches_box(q0.x, q0.y, q1.x, q1.y, q1.z, q1.w, a.alpha_min,
                                                                bx0, by0, bx0 + 7.0f, by0 + 7.0f);
             const float4 c0 = q0, c1 = q1, c2 = q2;
-            // chunk c + 2's records, and the list values of chunk c + 3
-            if (j + 128 < range.y) {
-                s0 = a.rec[3 * (size_t)g_next];
-                s1 = a.rec[3 * (size_t)g_next + 1];
-                s2 = a.rec[3 * (size_t)g_next + 2];
+            // next chunk's records, and the list values of the one after
+            if (j + 64 < range.y) {
+                q0 = a.rec[3 * (size_t)g_next];
+                q1 = a.rec[3 * (size_t)g_next + 1];
+                q2 = a.rec[3 * (size_t)g_next + 2];
             }
-            if (j + 192 < range.y) g_next = a.vals[j + 192];
-            q0 = r0;
-            q1 = r1;
-            q2 = r2;
-            r0 = s0;
-            r1 = s1;
-            r2 = s2;
+            if (j + 128 < range.y) g_next = a.vals[j + 128];
             const uint64_t bal = __ballot(hit);
             if (hit) {
                 const int pos = __popcll(bal & lt_mask);
