@@ -81,6 +81,7 @@ __global__ void __launch_bounds__(64 * kWavesPerGroup) composite_kernel(const Co
         // the issue slots those leave while they wait on memory.
         set_wave_priority(range.y - range.x);
         float T = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f, dd = 0.0f;
+        const float amax = __builtin_canonicalizef(a.alpha_max);  // keeps the clamp's operand out of the loop
         uint32_t last = 0;
         bool done = !inside;
         // software pipeline over the list chunks: while chunk c is culled and
@@ -120,25 +121,39 @@ __global__ void __launch_bounds__(64 * kWavesPerGroup) composite_kernel(const Co
             }
             __builtin_amdgcn_wave_barrier();
             const int n = __popcll(bal);
-            // uniform trip count; the per-lane skip / stop / done decisions are
-            // predicates (no divergent exits in the loop)
-            for (int q = 0; q < n; ++q) {
-                const float4 e0 = e0s[q], e1 = e1s[q], e2 = e2s[q];
-                const float dx = fx - e0.x, dy = fy - e0.y;
-                const float p2 = entry_power2(e0.z, e0.w, e1.x, dx, dy);
-                const float al = fminf(a.alpha_max, e1.y * fast_exp2(p2));
-                const float Tn = T * (1.0f - al);
-                const bool take = !done && !(al < a.alpha_min);
-                const bool stop = take && (Tn < a.t_min);
-                const bool use = take && !stop;
-                const float w = use ? al * T : 0.0f;
-                cr = fmaf(w, e1.w, cr);
-                cg = fmaf(w, e2.x, cg);
-                cb = fmaf(w, e2.y, cb);
-                dd = fmaf(w, e1.z, dd);
-                T = use ? Tn : T;
-                last = use ? __float_as_uint(e2.z) : last;
-                done = done || stop;
+            // pad the list to a multiple of 4 with entries of zero opacity
+            // (alpha 0: always skipped)
+            if (lane < ((4 - (n & 3)) & 3)) {
+                e0s[n + lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                e1s[n + lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                e2s[n + lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            }
+            __builtin_amdgcn_wave_barrier();
+            // Uniform trip count, four entries per step (their LDS reads are
+            // issued together, ahead of the arithmetic); the per-lane skip /
+            // stop / done decisions are predicates, with no divergent exits.
+            // T (1 - alpha) is formed as T - alpha T, the weight itself.
+            for (int q = 0; q < n; q += 4) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const float4 e0 = e0s[q + u], e1 = e1s[q + u], e2 = e2s[q + u];
+                    const float dx = fx - e0.x, dy = fy - e0.y;
+                    const float p2 = entry_power2(e0.z, e0.w, e1.x, dx, dy);
+                    const float al = fminf(amax, e1.y * fast_exp2(p2));
+                    const float w = al * T;
+                    const float Tn = T - w;
+                    const bool take = !done && !(al < a.alpha_min);
+                    const bool stop = take && (Tn < a.t_min);
+                    const bool use = take && !stop;
+                    const float ws = use ? w : 0.0f;
+                    cr = fmaf(ws, e1.w, cr);
+                    cg = fmaf(ws, e2.x, cg);
+                    cb = fmaf(ws, e2.y, cb);
+                    dd = fmaf(ws, e1.z, dd);
+                    T = use ? Tn : T;
+                    last = use ? __float_as_uint(e2.z) : last;
+                    done = done || stop;
+                }
             }
             __builtin_amdgcn_wave_barrier();
             if (__ballot(!done) == 0ull) break;

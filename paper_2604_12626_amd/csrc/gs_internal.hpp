@@ -372,7 +372,8 @@ __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_ex
 
 // exponent (base 2) at pixel offset (dx, dy); clamped to <= 0
 __device__ __forceinline__ float entry_power2(float a, float b, float c, float dx, float dy) {
-    const float p = a * dx * dx + c * dy * dy + b * dx * dy;
+    // a dx^2 + b dx dy + c dy^2 = dx (a dx + b dy) + (c dy) dy
+    const float p = fmaf(dx, fmaf(a, dx, b * dy), (c * dy) * dy);
     return fminf(p, 0.0f);
 }
 
