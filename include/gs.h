@@ -144,6 +144,11 @@ void gs_default_params(gs_params *p, int32_t width, int32_t height);
  *    8192, default 4096).
  *  sort_lookback: predecessor partitions read per round trip of the onesweep
  *    look-back (16, 32 or 64, default 16).
+ *  sort_algorithm: 0 (default) sorts by tile buckets when the launch has at
+ *    most 65536 tiles over all views (count per tile, scatter into buckets,
+ *    sort each bucket by (depth, instance) in LDS) and with the onesweep
+ *    radix sort otherwise; 1 always uses the onesweep radix sort.  Both give
+ *    the same keys, values and ranges.
  * gs_set_tuning(NULL) restores the defaults; invalid values return
  * GS_ERR_INVALID_ARGUMENT and change nothing.  Meant for an autotuner that
  * times the candidates on the target workload. */
@@ -151,7 +156,8 @@ typedef struct gs_tuning {
     int32_t composite_groups_per_cu;
     int32_t sort_partition_keys;
     int32_t sort_lookback;
-    int32_t reserved[5];
+    int32_t sort_algorithm;
+    int32_t reserved[4];
 } gs_tuning;
 gs_status gs_set_tuning(const gs_tuning *t);
 void gs_get_tuning(gs_tuning *t);

@@ -106,6 +106,7 @@ int64_t seg_offset_in_view(const gs_gaussians *segs, uint32_t mask, int s) {
 std::atomic<int> g_comp_groups{8};
 std::atomic<int> g_sort_part_keys{4096};
 std::atomic<int> g_sort_lookback{16};
+std::atomic<int> g_sort_algorithm{0};
 
 std::mutex g_dev_mu;
 int g_cu_count[64] = {0};
@@ -161,6 +162,7 @@ gs_status gs_set_tuning(const gs_tuning *t) {
         g_comp_groups.store(8);
         g_sort_part_keys.store(4096);
         g_sort_lookback.store(16);
+        g_sort_algorithm.store(0);
         return GS_OK;
     }
     if (t->composite_groups_per_cu < 1 || t->composite_groups_per_cu > 32)
@@ -169,9 +171,12 @@ gs_status gs_set_tuning(const gs_tuning *t) {
         return fail(GS_ERR_INVALID_ARGUMENT, "sort_partition_keys=%d (4096 or 8192)", t->sort_partition_keys);
     if (t->sort_lookback != 16 && t->sort_lookback != 32 && t->sort_lookback != 64)
         return fail(GS_ERR_INVALID_ARGUMENT, "sort_lookback=%d (16, 32 or 64)", t->sort_lookback);
+    if (t->sort_algorithm != 0 && t->sort_algorithm != 1)
+        return fail(GS_ERR_INVALID_ARGUMENT, "sort_algorithm=%d (0 or 1)", t->sort_algorithm);
     g_comp_groups.store(t->composite_groups_per_cu);
     g_sort_part_keys.store(t->sort_partition_keys);
     g_sort_lookback.store(t->sort_lookback);
+    g_sort_algorithm.store(t->sort_algorithm);
     return GS_OK;
 }
 
@@ -181,6 +186,7 @@ void gs_get_tuning(gs_tuning *t) {
     t->composite_groups_per_cu = g_comp_groups.load();
     t->sort_partition_keys = g_sort_part_keys.load();
     t->sort_lookback = g_sort_lookback.load();
+    t->sort_algorithm = g_sort_algorithm.load();
 }
 
 gs_status gs_instance_offsets(const gs_gaussians *segs, int32_t n_segs, int32_t n_views,
@@ -340,6 +346,7 @@ gs_status gs_bin_sort(const gs_projected *proj, int32_t n_views, const gs_params
     gs::SortPlan plan = gs::make_sort_plan(proj->n_instances, capacity, T * n_views);
     plan.part_keys = g_sort_part_keys.load();
     plan.lookback = g_sort_lookback.load();
+    plan.use_bucket = plan.bucket_ok && g_sort_algorithm.load() == 0;
     if (ws_bytes < plan.total)
         return fail(GS_ERR_WORKSPACE_TOO_SMALL, "workspace %zu < %zu bytes", ws_bytes, plan.total);
     hipError_t e = gs::run_bin_sort(plan, proj->tiles_touched, reinterpret_cast<const float4 *>(proj->rec),

@@ -96,9 +96,11 @@ struct SortPlan {
     int64_t n, capacity, n_tiles_total;
     int tile_bits, passes;
     int part_keys, lookback;  // onesweep partition size (4096 / 8192) and look-back window (16 / 32 / 64)
+    bool bucket_ok, use_bucket;  // bucket-by-tile path available / chosen (else onesweep)
+    int64_t bucket_blocks;
     int64_t scan_blocks, sort_parts;
     // workspace layout (byte offsets)
-    size_t off_part, off_keys2, off_vals2, off_rows, off_dbase, off_hist, off_status, off_ticket, total;
+    size_t off_part, off_keys2, off_vals2, off_rows, off_dbase, off_tcnt, off_tcount, off_tstart, off_hist, off_status, off_ticket, total;
 };
 
 // launchers (one per translation unit)

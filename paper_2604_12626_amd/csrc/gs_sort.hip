@@ -29,6 +29,8 @@ constexpr int kSortWaves = kSortBlock / 64;
 constexpr int kMinSortItems = 8;                    // partitions of 4096 or 8192 keys (tunable)
 constexpr int kMinSortPart = kSortBlock * kMinSortItems;
 constexpr int kEmitGrid = 1024;  // emission workgroups at most (grid-stride over scan tiles beyond)
+constexpr int kBucketGrid = 256;  // emission workgroups of the bucket path (rows of the tile counters)
+constexpr int64_t kBucketMaxTiles = 1 << 16;  // the bucket path serves up to this many tiles (all views)
 constexpr int kRadixBits = 8;
 constexpr int kBins = 1 << kRadixBits;
 constexpr int kMaxPasses = 8;
@@ -178,11 +180,29 @@ constexpr int kEmitItems = kScanTile / kEmitBlock;  // 4 instances per thread
 constexpr int kEmitWaves = kEmitBlock / 64;
 constexpr int kWaveInst = 64 * kEmitItems;          // 256 instances per wave
 
-__global__ void __launch_bounds__(kEmitBlock) emit_kernel(const uint32_t *tt, const uint64_t *part,
-                                                          const float4 *rec, int64_t n, int64_t n_tiles_scan,
-                                                          int TX, int TY, int64_t capacity, uint64_t *keys,
-                                                          uint32_t *vals, int passes,
-                                                          uint32_t *rows /*[grid][passes*257]*/, int64_t n_blocks) {
+enum EmitMode { kEmitSortKeys = 0, kEmitCountTiles = 1, kEmitScatterTiles = 2 };
+
+struct EmitArgs {
+    const uint32_t *tt;
+    const uint64_t *part;
+    const float4 *rec;
+    int64_t n, n_tiles_scan, capacity, n_blocks;
+    int TX, TY;
+    // kEmitSortKeys: keys, values and the digit histograms of every pass
+    uint64_t *keys;
+    uint32_t *vals;
+    int passes;
+    uint32_t *rows;  // [grid][passes * 257]
+    // kEmitCountTiles / kEmitScatterTiles: per-workgroup tile counters
+    uint32_t *tile_cnt;          // [grid][n_tiles]: counts, then running offsets within the tile
+    const uint32_t *tile_start;  // [n_tiles]: first key of each tile
+    uint64_t *bucket;            // [capacity]: (depth bits << 32) | instance, grouped by tile
+    int64_t n_tiles;
+    const int32_t *d_overflow;
+};
+
+template <int MODE>
+__global__ void __launch_bounds__(kEmitBlock) emit_kernel(const EmitArgs A) {
     __shared__ uint32_t s_h[kMaxPasses][kHistStride];
     __shared__ uint64_t s_wsum[kEmitWaves];
     // per wave, per list entry: staged record, then the emission layout
@@ -194,9 +214,16 @@ __global__ void __launch_bounds__(kEmitBlock) emit_kernel(const uint32_t *tt, co
     __shared__ uint32_t s_a5[kEmitWaves][kWaveInst];  // instance index
     __shared__ uint32_t s_a6[kEmitWaves][kWaveInst];  // first key, relative to the wave's first
     __shared__ uint32_t s_a7[kEmitWaves][kWaveInst];  // tiles_touched
-    for (int k = threadIdx.x; k < kMaxPasses * kHistStride; k += kEmitBlock) (&s_h[0][0])[k] = 0u;
+    if (MODE == kEmitScatterTiles && *A.d_overflow) return;  // nothing consistent to scatter
+    const uint32_t *tt = A.tt;
+    const float4 *rec = A.rec;
+    const int64_t n = A.n, capacity = A.capacity;
+    const int TX = A.TX, TY = A.TY, passes = A.passes;
+    if (MODE == kEmitSortKeys)
+        for (int k = threadIdx.x; k < kMaxPasses * kHistStride; k += kEmitBlock) (&s_h[0][0])[k] = 0u;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int64_t tile = blockIdx.x; tile < n_tiles_scan; tile += n_blocks) {  // uniform per workgroup
+    uint32_t *my_cnt = A.tile_cnt + (size_t)blockIdx.x * A.n_tiles;
+    for (int64_t tile = blockIdx.x; tile < A.n_tiles_scan; tile += A.n_blocks) {  // uniform per workgroup
         const int64_t base = tile * kScanTile + (int64_t)threadIdx.x * kEmitItems;
         uint32_t v[kEmitItems];
         if (base + kEmitItems <= n) {  // one 16-B load (tt is 16-B aligned: caller-owned allocation)
@@ -223,7 +250,7 @@ __global__ void __launch_bounds__(kEmitBlock) emit_kernel(const uint32_t *tt, co
         __syncthreads();
         uint64_t wave_excl = 0;
         for (int k = 0; k < wave; ++k) wave_excl += s_wsum[k];
-        const int64_t kw = (int64_t)(part[tile] + wave_excl);  // first key of the wave
+        const int64_t kw = (int64_t)(A.part[tile] + wave_excl);  // first key of the wave
         const int64_t room = capacity - kw;
         // live instances of the lane and their place in the wave's list
         uint32_t start[kEmitItems];
@@ -276,10 +303,12 @@ __global__ void __launch_bounds__(kEmitBlock) emit_kernel(const uint32_t *tt, co
             const Rect R = tile_rect(u, vv, (int)s_a3[wave][e], TX, TY);
             const uint64_t tbase = (uint64_t)s_a4[wave][e] * (uint64_t)(TX * TY);
             const uint32_t t = s_a7[wave][e];
+            if (MODE == kEmitSortKeys) {
 #pragma unroll
-            for (int p = 0; p < 4; ++p) hist_add(s_h[p], (depth_bits >> (8 * p)) & 255u, t);
-            for (int ty = R.y0; ty < R.y1; ++ty)
-                hist_add_row(s_h, passes, tbase + (uint64_t)(ty * TX + R.x0), (uint32_t)(R.x1 - R.x0));
+                for (int p = 0; p < 4; ++p) hist_add(s_h[p], (depth_bits >> (8 * p)) & 255u, t);
+                for (int ty = R.y0; ty < R.y1; ++ty)
+                    hist_add_row(s_h, passes, tbase + (uint64_t)(ty * TX + R.x0), (uint32_t)(R.x1 - R.x0));
+            }
             s_a0[wave][e] = (uint32_t)R.x0 | ((uint32_t)R.y0 << 16);
             s_a1[wave][e] = (uint32_t)(R.x1 - R.x0);
             s_a3[wave][e] = (uint32_t)tbase;
@@ -299,16 +328,26 @@ __global__ void __launch_bounds__(kEmitBlock) emit_kernel(const uint32_t *tt, co
                 const uint32_t rel = j - s_a6[wave][lo];
                 const uint32_t w = s_a1[wave][lo], xy = s_a0[wave][lo];
                 const uint32_t ty = (xy >> 16) + rel / w, tx = (xy & 0xFFFFu) + rel % w;
-                const int64_t k = kw + (int64_t)j;
-                keys[k] = ((uint64_t)(s_a3[wave][lo] + ty * (uint32_t)TX + tx) << 32) | (uint64_t)s_a2[wave][lo];
-                vals[k] = s_a5[wave][lo];
+                const uint32_t tg = s_a3[wave][lo] + ty * (uint32_t)TX + tx;  // tile across all views
+                if (MODE == kEmitSortKeys) {
+                    const int64_t k = kw + (int64_t)j;
+                    A.keys[k] = ((uint64_t)tg << 32) | (uint64_t)s_a2[wave][lo];
+                    A.vals[k] = s_a5[wave][lo];
+                } else if (MODE == kEmitCountTiles) {
+                    atomicAdd(my_cnt + tg, 1u);
+                } else {
+                    const uint32_t slot = A.tile_start[tg] + atomicAdd(my_cnt + tg, 1u);
+                    A.bucket[slot] = ((uint64_t)s_a2[wave][lo] << 32) | (uint64_t)s_a5[wave][lo];
+                }
             }
         }
         __syncthreads();  // s_wsum and the lists are reused by the next tile
     }
-    __syncthreads();
-    uint32_t *row = rows + (size_t)blockIdx.x * passes * kHistStride;
-    for (int k = threadIdx.x; k < passes * kHistStride; k += kEmitBlock) row[k] = (&s_h[0][0])[k];
+    if (MODE == kEmitSortKeys) {
+        __syncthreads();
+        uint32_t *row = A.rows + (size_t)blockIdx.x * passes * kHistStride;
+        for (int k = threadIdx.x; k < passes * kHistStride; k += kEmitBlock) row[k] = (&s_h[0][0])[k];
+    }
 }
 
 // Partial sums of the emission rows: part[ry][c] = sum of rows[r][c] over the
@@ -544,6 +583,147 @@ __global__ void __launch_bounds__(kBins) digit_base_kernel(const uint32_t *hist_
 }
 
 // ---------------------------------------------------------------------------
+// bucket sort by tile (the default when the tile count is moderate)
+// ---------------------------------------------------------------------------
+// The sorted order is (tile, depth bits, instance).  Instead of sorting all
+// key bits across the whole array, keys are counted per (emission workgroup,
+// tile), the counts are scanned into per-workgroup slots inside each tile's
+// bucket, the keys are scattered there as (depth bits, instance) pairs, and
+// each tile's bucket is sorted on its own in LDS.  The scatter order inside a
+// bucket is arbitrary, but the pairs are distinct, so the per-tile sort
+// alone fixes the order -- the same order a stable sort of (tile, depth)
+// keys emitted in instance order produces.
+
+// per tile t: exclusive scan of the per-workgroup counts down the column (in
+// place) and the tile's total
+__global__ void __launch_bounds__(256) bucket_colscan_kernel(uint32_t *cnt /*[rows][n_tiles]*/, int n_rows,
+                                                             int64_t n_tiles, uint32_t *tile_count) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= n_tiles) return;
+    uint32_t run = 0u;
+    int r = 0;
+    for (; r + 8 <= n_rows; r += 8) {  // eight loads in flight
+        uint32_t c[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) c[k] = cnt[(size_t)(r + k) * n_tiles + t];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            cnt[(size_t)(r + k) * n_tiles + t] = run;
+            run += c[k];
+        }
+    }
+    for (; r < n_rows; ++r) {
+        const uint32_t c = cnt[(size_t)r * n_tiles + t];
+        cnt[(size_t)r * n_tiles + t] = run;
+        run += c;
+    }
+    tile_count[t] = run;
+}
+
+// exclusive scan of the tile totals (one workgroup): each tile's first key,
+// and the ranges ([first, end) for tiles with keys, [0, 0) otherwise)
+__global__ void __launch_bounds__(1024) bucket_tilescan_kernel(const uint32_t *tile_count, int64_t n_tiles,
+                                                               uint32_t *tile_start, uint32_t *ranges,
+                                                               const int32_t *d_overflow) {
+    __shared__ uint32_t s_w[16];
+    if (*d_overflow) return;  // ranges stay cleared
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t per = (n_tiles + 1023) / 1024;
+    const int64_t t0 = (int64_t)tid * per, t1 = (t0 + per < n_tiles) ? t0 + per : n_tiles;
+    uint32_t sum = 0u;
+    for (int64_t t = t0; t < t1; ++t) sum += tile_count[t];
+    uint32_t incl = sum;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
+    }
+    if (lane == 63) s_w[wave] = incl;
+    __syncthreads();
+    uint32_t run = incl - sum;
+    for (int k = 0; k < wave; ++k) run += s_w[k];
+    for (int64_t t = t0; t < t1; ++t) {
+        const uint32_t c = tile_count[t];
+        tile_start[t] = run;
+        ranges[2 * t] = c ? run : 0u;
+        ranges[2 * t + 1] = c ? run + c : 0u;
+        run += c;
+    }
+}
+
+// Ascending bitonic sort of s[0, n2) (n2 a power of two) by a workgroup of
+// `threads`; each merge starts with the reflected compare (i, block end - 1 -
+// i), so every compare-exchange is ascending and padding at the end stays
+// there.  `lim`: entries at or beyond it are virtual +infinity and are never
+// touched (for in-place sorts of unpadded global segments).
+template <int THREADS, typename Ptr>
+__device__ __forceinline__ void bitonic_sort(Ptr s, uint32_t n2, uint32_t lim) {
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t k = 2; k <= n2; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t t = tid; t < (n2 >> 1); t += THREADS) {
+                const uint32_t blk = t / j, r = t % j;
+                uint32_t i, p;
+                if (j == (k >> 1)) {
+                    i = blk * k + r;
+                    p = blk * k + (k - 1 - r);
+                } else {
+                    i = blk * (2 * j) + r;
+                    p = i + j;
+                }
+                if (p < lim) {
+                    const uint64_t a = s[i], b = s[p];
+                    if (a > b) {
+                        s[i] = b;
+                        s[p] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+constexpr int kTileSortBlock = 512;
+constexpr int kTileSortCap = 8192;  // entries sorted in LDS; longer buckets are sorted in place in HBM
+
+// one workgroup per tile (grid-stride): sort the bucket and write the keys
+// (tile << 32 | depth bits) and values (instance)
+__global__ void __launch_bounds__(kTileSortBlock) tile_sort_kernel(uint64_t *bucket, const uint32_t *ranges,
+                                                                   int64_t n_tiles, int64_t n_blocks,
+                                                                   uint64_t *keys, uint32_t *vals,
+                                                                   const int32_t *d_overflow) {
+    __shared__ uint64_t s[kTileSortCap];
+    if (*d_overflow) return;
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += n_blocks) {  // uniform per workgroup
+        const uint32_t b = ranges[2 * tile], L = ranges[2 * tile + 1] - b;
+        if (L == 0u) continue;
+        uint32_t n2 = 2;
+        while (n2 < L) n2 <<= 1;
+        const uint64_t thi = (uint64_t)tile << 32;
+        if (L <= (uint32_t)kTileSortCap) {
+            for (uint32_t i = threadIdx.x; i < n2; i += kTileSortBlock) s[i] = (i < L) ? bucket[b + i] : ~0ull;
+            __syncthreads();
+            bitonic_sort<kTileSortBlock>(s, n2, n2);
+            for (uint32_t i = threadIdx.x; i < L; i += kTileSortBlock) {
+                const uint64_t c = s[i];
+                keys[b + i] = thi | (c >> 32);
+                vals[b + i] = (uint32_t)c;
+            }
+            __syncthreads();  // s is reused by the next tile
+        } else {
+            bitonic_sort<kTileSortBlock>(bucket + b, n2, L);
+            for (uint32_t i = threadIdx.x; i < L; i += kTileSortBlock) {
+                const uint64_t c = bucket[b + i];
+                keys[b + i] = thi | (c >> 32);
+                vals[b + i] = (uint32_t)c;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // tile ranges
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) ranges_kernel(const uint64_t *keys, const int64_t *d_num, int64_t capacity,
@@ -599,8 +779,61 @@ SortPlan make_sort_plan(int64_t n, int64_t capacity, int64_t n_tiles_total) {
     o = o + sizeof(uint32_t) * (size_t)kMaxPasses * 64;
     p.off_status = o;
     o = o + sizeof(uint32_t) * (size_t)p.passes * (size_t)p.sort_parts * kBins;
+    o = align256(o);
+    // bucket path (moderate tile counts): per-workgroup tile counters, tile totals and starts
+    p.bucket_ok = n_tiles_total <= kBucketMaxTiles;
+    p.bucket_blocks = p.scan_blocks < kBucketGrid ? p.scan_blocks : kBucketGrid;
+    p.off_tcnt = o;
+    if (p.bucket_ok) o = align256(o + sizeof(uint32_t) * (size_t)p.bucket_blocks * (size_t)n_tiles_total);
+    p.off_tcount = o;
+    if (p.bucket_ok) o = align256(o + sizeof(uint32_t) * (size_t)n_tiles_total);
+    p.off_tstart = o;
+    if (p.bucket_ok) o = align256(o + sizeof(uint32_t) * (size_t)n_tiles_total);
+    p.use_bucket = p.bucket_ok;
     p.total = align256(o);
     return p;
+}
+
+// the bucket path after the scan: count per (workgroup, tile), scan the
+// counters, scatter into the buckets, sort each bucket
+static hipError_t run_bucket_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec, int TX, int TY,
+                                  char *ws, uint64_t *keys, uint32_t *vals, uint32_t *ranges,
+                                  const int32_t *d_overflow, int n_cu, hipStream_t s) {
+    hipError_t e;
+    if (P.n <= 0) return hipSuccess;  // no keys: ranges are cleared
+    EmitArgs A = {};
+    A.tt = tt;
+    A.part = reinterpret_cast<const uint64_t *>(ws + P.off_part);
+    A.rec = rec;
+    A.n = P.n;
+    A.n_tiles_scan = P.scan_blocks;
+    A.capacity = P.capacity;
+    A.n_blocks = P.bucket_blocks;
+    A.TX = TX;
+    A.TY = TY;
+    A.tile_cnt = reinterpret_cast<uint32_t *>(ws + P.off_tcnt);
+    A.tile_start = reinterpret_cast<const uint32_t *>(ws + P.off_tstart);
+    A.bucket = reinterpret_cast<uint64_t *>(ws + P.off_keys2);
+    A.n_tiles = P.n_tiles_total;
+    A.d_overflow = d_overflow;
+    uint32_t *tcount = reinterpret_cast<uint32_t *>(ws + P.off_tcount);
+    uint32_t *tstart = reinterpret_cast<uint32_t *>(ws + P.off_tstart);
+    if ((e = launch_kernel(emit_kernel<kEmitCountTiles>, dim3((unsigned)P.bucket_blocks), dim3(kEmitBlock), s, A)) !=
+        hipSuccess)
+        return e;
+    if ((e = launch_kernel(bucket_colscan_kernel, dim3((unsigned)((P.n_tiles_total + 255) / 256)), dim3(256), s,
+                           A.tile_cnt, (int)P.bucket_blocks, P.n_tiles_total, tcount)) != hipSuccess)
+        return e;
+    if ((e = launch_kernel(bucket_tilescan_kernel, dim3(1), dim3(1024), s, tcount, P.n_tiles_total, tstart, ranges,
+                           d_overflow)) != hipSuccess)
+        return e;
+    if ((e = launch_kernel(emit_kernel<kEmitScatterTiles>, dim3((unsigned)P.bucket_blocks), dim3(kEmitBlock), s,
+                           A)) != hipSuccess)
+        return e;
+    int64_t sg = 2 * (int64_t)n_cu;
+    if (sg > P.n_tiles_total) sg = P.n_tiles_total;
+    return launch_kernel(tile_sort_kernel, dim3((unsigned)sg), dim3(kTileSortBlock), s, A.bucket,
+                         (const uint32_t *)ranges, P.n_tiles_total, sg, keys, vals, d_overflow);
 }
 
 hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec, int TX, int TY, char *ws,
@@ -616,9 +849,12 @@ hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec
     uint32_t *ticket = reinterpret_cast<uint32_t *>(ws + P.off_ticket);
     uint32_t *status = reinterpret_cast<uint32_t *>(ws + P.off_status);
     const size_t clear_words = (P.off_status - P.off_hist) / 4 + (size_t)P.passes * P.sort_parts * kBins;
+    uint32_t *tcnt = reinterpret_cast<uint32_t *>(ws + P.off_tcnt);
+    const size_t tcnt_words = P.use_bucket ? (size_t)P.bucket_blocks * (size_t)P.n_tiles_total : 0;
 
-    if ((e = launch_kernel(clear2_kernel, dim3(1024), dim3(256), s, hist, (int64_t)clear_words, ranges,
-                           2 * P.n_tiles_total, (int64_t)1024 * 256)) != hipSuccess)
+    if ((e = launch_kernel(clear2_kernel, dim3(1024), dim3(256), s, P.use_bucket ? tcnt : hist,
+                           (int64_t)(P.use_bucket ? tcnt_words : clear_words), ranges, 2 * P.n_tiles_total,
+                           (int64_t)1024 * 256)) != hipSuccess)
         return e;
     // 1. scan
     if (P.n > 0) {
@@ -629,6 +865,7 @@ hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec
     if ((e = launch_kernel(scan_partials_kernel, dim3(1), dim3(1024), s, part, P.n > 0 ? P.scan_blocks : (int64_t)0,
                            P.capacity, d_num, d_overflow)) != hipSuccess)
         return e;
+    if (P.use_bucket) return run_bucket_sort(P, tt, rec, TX, TY, ws, keys, vals, ranges, d_overflow, n_cu, s);
     // 2. emission (with the scan downsweep) into the buffer that the last pass does not write to
     const bool odd = (P.passes & 1) != 0;
     uint64_t *k_a = odd ? keys2 : keys;
@@ -638,8 +875,22 @@ hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec
     if (P.n > 0) {
         int64_t eg = P.scan_blocks;
         if (eg > kEmitGrid) eg = kEmitGrid;
-        if ((e = launch_kernel(emit_kernel, dim3((unsigned)eg), dim3(kEmitBlock), s, tt, part, rec, P.n,
-                               P.scan_blocks, TX, TY, P.capacity, k_a, v_a, P.passes, rows, eg)) != hipSuccess)
+        EmitArgs A = {};
+        A.tt = tt;
+        A.part = part;
+        A.rec = rec;
+        A.n = P.n;
+        A.n_tiles_scan = P.scan_blocks;
+        A.capacity = P.capacity;
+        A.n_blocks = eg;
+        A.TX = TX;
+        A.TY = TY;
+        A.keys = k_a;
+        A.vals = v_a;
+        A.passes = P.passes;
+        A.rows = rows;
+        A.d_overflow = d_overflow;
+        if ((e = launch_kernel(emit_kernel<kEmitSortKeys>, dim3((unsigned)eg), dim3(kEmitBlock), s, A)) != hipSuccess)
             return e;
         const int cols = P.passes * kHistStride;
         if ((e = launch_kernel(hist_reduce_kernel, dim3((unsigned)((cols + 63) / 64), kHistRows), dim3(256), s, rows,

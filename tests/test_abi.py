@@ -129,14 +129,16 @@ def test_tuning_validation():
     prev = B.get_tuning()
     try:
         for bad in ({"composite_groups_per_cu": 0}, {"composite_groups_per_cu": 33},
-                    {"sort_partition_keys": 2048}, {"sort_lookback": 8}):
+                    {"sort_partition_keys": 2048}, {"sort_lookback": 8}, {"sort_algorithm": 2}):
             before = B.get_tuning()
             with pytest.raises(B.GSError):
                 B.set_tuning(**bad)
             assert B.get_tuning() == before
-        B.set_tuning(5, sort_partition_keys=4096, sort_lookback=64)
-        assert B.get_tuning() == {"composite_groups_per_cu": 5, "sort_partition_keys": 4096, "sort_lookback": 64}
+        B.set_tuning(5, sort_partition_keys=8192, sort_lookback=64, sort_algorithm=1)
+        assert B.get_tuning() == {"composite_groups_per_cu": 5, "sort_partition_keys": 8192, "sort_lookback": 64,
+                                  "sort_algorithm": 1}
         B.set_tuning()
-        assert B.get_tuning() == {"composite_groups_per_cu": 8, "sort_partition_keys": 4096, "sort_lookback": 16}
+        assert B.get_tuning() == {"composite_groups_per_cu": 8, "sort_partition_keys": 4096, "sort_lookback": 16,
+                                  "sort_algorithm": 0}
     finally:
         B.set_tuning(**prev)

@@ -118,10 +118,14 @@ def test_bin_sort_bit_exact(dev, orc, name, counts, W, H):
     tt_o, keys_o, vals_o, ranges_o, K = orc.bin_records(rec, vis, W, H, V)
     say("bin_sort:", name, "instances", len(rec), "K", K)
     prm = B.make_params(W, H)
-    # every onesweep configuration the tuner may pick sorts identically
-    runs = [(K + 1000, 0, {}), (K + 1000, 0, {"sort_partition_keys": 8192, "sort_lookback": 64}),
-            (K + 1000, 0, {"sort_partition_keys": 4096, "sort_lookback": 32}),
-            (max(1, K // 2), 1 if K > max(1, K // 2) else 0, {})]
+    # both sort algorithms, and every onesweep configuration the tuner may
+    # pick, sort identically
+    one = {"sort_algorithm": 1}
+    runs = [(K + 1000, 0, {}), (K + 1000, 0, one),
+            (K + 1000, 0, dict(one, sort_partition_keys=8192, sort_lookback=64)),
+            (K + 1000, 0, dict(one, sort_partition_keys=4096, sort_lookback=32)),
+            (max(1, K // 2), 1 if K > max(1, K // 2) else 0, {}),
+            (max(1, K // 2), 1 if K > max(1, K // 2) else 0, one)]
     prev = B.get_tuning()
     try:
         for cap, expect_ovf, knobs in runs:
