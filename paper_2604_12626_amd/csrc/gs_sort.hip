@@ -179,6 +179,8 @@ constexpr int kEmitBlock = 1024;
 constexpr int kEmitItems = kScanTile / kEmitBlock;  // 4 instances per thread
 constexpr int kEmitWaves = kEmitBlock / 64;
 constexpr int kWaveInst = 64 * kEmitItems;          // 256 instances per wave
+constexpr int kLdsTiles = 4096;                     // tile counters kept in LDS up to this many tiles
+static_assert(kLdsTiles >= kMaxPasses * kHistStride, "the LDS buffer also holds the digit histograms");
 
 enum EmitMode { kEmitSortKeys = 0, kEmitCountTiles = 1, kEmitScatterTiles = 2 };
 
@@ -203,7 +205,10 @@ struct EmitArgs {
 
 template <int MODE>
 __global__ void __launch_bounds__(kEmitBlock) emit_kernel(const EmitArgs A) {
-    __shared__ uint32_t s_h[kMaxPasses][kHistStride];
+    // digit histograms (sort keys) or, for up to kLdsTiles tiles, the
+    // workgroup's tile counters (count / scatter)
+    __shared__ uint32_t s_aux[kLdsTiles];
+    uint32_t(*s_h)[kHistStride] = reinterpret_cast<uint32_t(*)[kHistStride]>(s_aux);
     __shared__ uint64_t s_wsum[kEmitWaves];
     // per wave, per list entry: staged record, then the emission layout
     __shared__ uint32_t s_a0[kEmitWaves][kWaveInst];  // u bits          -> rect origin x0 | y0 << 16
@@ -220,9 +225,14 @@ __global__ void __launch_bounds__(kEmitBlock) emit_kernel(const EmitArgs A) {
     const int64_t n = A.n, capacity = A.capacity;
     const int TX = A.TX, TY = A.TY, passes = A.passes;
     if (MODE == kEmitSortKeys)
-        for (int k = threadIdx.x; k < kMaxPasses * kHistStride; k += kEmitBlock) (&s_h[0][0])[k] = 0u;
+        for (int k = threadIdx.x; k < kMaxPasses * kHistStride; k += kEmitBlock) s_aux[k] = 0u;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     uint32_t *my_cnt = A.tile_cnt + (size_t)blockIdx.x * A.n_tiles;
+    const bool lds_tiles = A.n_tiles <= kLdsTiles;
+    if (MODE == kEmitCountTiles && lds_tiles)
+        for (int k = threadIdx.x; k < A.n_tiles; k += kEmitBlock) s_aux[k] = 0u;
+    if (MODE == kEmitScatterTiles && lds_tiles)  // this workgroup's first slot in every bucket
+        for (int k = threadIdx.x; k < A.n_tiles; k += kEmitBlock) s_aux[k] = A.tile_start[k] + my_cnt[k];
     for (int64_t tile = blockIdx.x; tile < A.n_tiles_scan; tile += A.n_blocks) {  // uniform per workgroup
         const int64_t base = tile * kScanTile + (int64_t)threadIdx.x * kEmitItems;
         uint32_t v[kEmitItems];
@@ -334,9 +344,11 @@ __global__ void __launch_bounds__(kEmitBlock) emit_kernel(const EmitArgs A) {
                     A.keys[k] = ((uint64_t)tg << 32) | (uint64_t)s_a2[wave][lo];
                     A.vals[k] = s_a5[wave][lo];
                 } else if (MODE == kEmitCountTiles) {
-                    atomicAdd(my_cnt + tg, 1u);
+                    if (lds_tiles) atomicAdd(s_aux + tg, 1u);
+                    else atomicAdd(my_cnt + tg, 1u);
                 } else {
-                    const uint32_t slot = A.tile_start[tg] + atomicAdd(my_cnt + tg, 1u);
+                    const uint32_t slot =
+                        lds_tiles ? atomicAdd(s_aux + tg, 1u) : A.tile_start[tg] + atomicAdd(my_cnt + tg, 1u);
                     A.bucket[slot] = ((uint64_t)s_a2[wave][lo] << 32) | (uint64_t)s_a5[wave][lo];
                 }
             }
@@ -346,7 +358,11 @@ __global__ void __launch_bounds__(kEmitBlock) emit_kernel(const EmitArgs A) {
     if (MODE == kEmitSortKeys) {
         __syncthreads();
         uint32_t *row = A.rows + (size_t)blockIdx.x * passes * kHistStride;
-        for (int k = threadIdx.x; k < passes * kHistStride; k += kEmitBlock) row[k] = (&s_h[0][0])[k];
+        for (int k = threadIdx.x; k < passes * kHistStride; k += kEmitBlock) row[k] = s_aux[k];
+    }
+    if (MODE == kEmitCountTiles && lds_tiles) {
+        __syncthreads();
+        for (int k = threadIdx.x; k < A.n_tiles; k += kEmitBlock) my_cnt[k] = s_aux[k];
     }
 }
 
@@ -602,12 +618,12 @@ __global__ void __launch_bounds__(256) bucket_colscan_kernel(uint32_t *cnt /*[ro
     if (t >= n_tiles) return;
     uint32_t run = 0u;
     int r = 0;
-    for (; r + 8 <= n_rows; r += 8) {  // eight loads in flight
-        uint32_t c[8];
+    for (; r + 32 <= n_rows; r += 32) {  // 32 loads in flight
+        uint32_t c[32];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) c[k] = cnt[(size_t)(r + k) * n_tiles + t];
+        for (int k = 0; k < 32; ++k) c[k] = cnt[(size_t)(r + k) * n_tiles + t];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
+        for (int k = 0; k < 32; ++k) {
             cnt[(size_t)(r + k) * n_tiles + t] = run;
             run += c[k];
         }
@@ -656,11 +672,16 @@ __global__ void __launch_bounds__(1024) bucket_tilescan_kernel(const uint32_t *t
 // i), so every compare-exchange is ascending and padding at the end stays
 // there.  `lim`: entries at or beyond it are virtual +infinity and are never
 // touched (for in-place sorts of unpadded global segments).
-template <int THREADS, typename Ptr>
+// In LDS, a step with j <= 64 pairs elements inside the 128-element block
+// that one wave's 64 consecutive pair indices cover, so consecutive such
+// steps need only the wave's own (in-order) LDS accesses; a workgroup
+// barrier separates the others.  In HBM every step ends with a barrier.
+template <int THREADS, bool IN_LDS, typename Ptr>
 __device__ __forceinline__ void bitonic_sort(Ptr s, uint32_t n2, uint32_t lim) {
     const uint32_t tid = threadIdx.x;
     for (uint32_t k = 2; k <= n2; k <<= 1) {
         for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            const uint32_t next_j = (j > 1) ? (j >> 1) : k;  // first step of the next merge is j = k
             for (uint32_t t = tid; t < (n2 >> 1); t += THREADS) {
                 const uint32_t blk = t / j, r = t % j;
                 uint32_t i, p;
@@ -679,7 +700,13 @@ __device__ __forceinline__ void bitonic_sort(Ptr s, uint32_t n2, uint32_t lim) {
                     }
                 }
             }
-            __syncthreads();
+            if (!IN_LDS || j > 64 || next_j > 64 || k == n2) {
+                __syncthreads();
+            } else {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
         }
     }
 }
@@ -704,7 +731,7 @@ __global__ void __launch_bounds__(kTileSortBlock) tile_sort_kernel(uint64_t *buc
         if (L <= (uint32_t)kTileSortCap) {
             for (uint32_t i = threadIdx.x; i < n2; i += kTileSortBlock) s[i] = (i < L) ? bucket[b + i] : ~0ull;
             __syncthreads();
-            bitonic_sort<kTileSortBlock>(s, n2, n2);
+            bitonic_sort<kTileSortBlock, true>(s, n2, n2);
             for (uint32_t i = threadIdx.x; i < L; i += kTileSortBlock) {
                 const uint64_t c = s[i];
                 keys[b + i] = thi | (c >> 32);
@@ -712,7 +739,7 @@ __global__ void __launch_bounds__(kTileSortBlock) tile_sort_kernel(uint64_t *buc
             }
             __syncthreads();  // s is reused by the next tile
         } else {
-            bitonic_sort<kTileSortBlock>(bucket + b, n2, L);
+            bitonic_sort<kTileSortBlock, false>(bucket + b, n2, L);
             for (uint32_t i = threadIdx.x; i < L; i += kTileSortBlock) {
                 const uint64_t c = bucket[b + i];
                 keys[b + i] = thi | (c >> 32);
