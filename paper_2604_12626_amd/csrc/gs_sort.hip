@@ -196,7 +196,7 @@ struct EmitArgs {
     int passes;
     uint32_t *rows;  // [grid][passes * 257]
     // kEmitCountTiles / kEmitScatterTiles: per-workgroup tile counters
-    uint32_t *tile_cnt;          // [grid][n_tiles]: counts, then running offsets within the tile
+    uint32_t *tile_cnt;          // [n_tiles][grid]: counts, then running offsets within the tile
     const uint32_t *tile_start;  // [n_tiles]: first key of each tile
     uint64_t *bucket;            // [capacity]: (depth bits << 32) | instance, grouped by tile
     int64_t n_tiles;
@@ -227,12 +227,14 @@ __global__ void __launch_bounds__(kEmitBlock) emit_kernel(const EmitArgs A) {
     if (MODE == kEmitSortKeys)
         for (int k = threadIdx.x; k < kMaxPasses * kHistStride; k += kEmitBlock) s_aux[k] = 0u;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    uint32_t *my_cnt = A.tile_cnt + (size_t)blockIdx.x * A.n_tiles;
+    // counters are tile-major: tile t's counts of all workgroups are one row
+    uint32_t *my_cnt = A.tile_cnt + blockIdx.x;
+    const int64_t cs = A.n_blocks;  // row stride
     const bool lds_tiles = A.n_tiles <= kLdsTiles;
     if (MODE == kEmitCountTiles && lds_tiles)
         for (int k = threadIdx.x; k < A.n_tiles; k += kEmitBlock) s_aux[k] = 0u;
     if (MODE == kEmitScatterTiles && lds_tiles)  // this workgroup's first slot in every bucket
-        for (int k = threadIdx.x; k < A.n_tiles; k += kEmitBlock) s_aux[k] = A.tile_start[k] + my_cnt[k];
+        for (int k = threadIdx.x; k < A.n_tiles; k += kEmitBlock) s_aux[k] = A.tile_start[k] + my_cnt[k * cs];
     for (int64_t tile = blockIdx.x; tile < A.n_tiles_scan; tile += A.n_blocks) {  // uniform per workgroup
         const int64_t base = tile * kScanTile + (int64_t)threadIdx.x * kEmitItems;
         uint32_t v[kEmitItems];
@@ -345,10 +347,10 @@ __global__ void __launch_bounds__(kEmitBlock) emit_kernel(const EmitArgs A) {
                     A.vals[k] = s_a5[wave][lo];
                 } else if (MODE == kEmitCountTiles) {
                     if (lds_tiles) atomicAdd(s_aux + tg, 1u);
-                    else atomicAdd(my_cnt + tg, 1u);
+                    else atomicAdd(my_cnt + (size_t)tg * cs, 1u);
                 } else {
                     const uint32_t slot =
-                        lds_tiles ? atomicAdd(s_aux + tg, 1u) : A.tile_start[tg] + atomicAdd(my_cnt + tg, 1u);
+                        lds_tiles ? atomicAdd(s_aux + tg, 1u) : A.tile_start[tg] + atomicAdd(my_cnt + (size_t)tg * cs, 1u);
                     A.bucket[slot] = ((uint64_t)s_a2[wave][lo] << 32) | (uint64_t)s_a5[wave][lo];
                 }
             }
@@ -362,7 +364,7 @@ __global__ void __launch_bounds__(kEmitBlock) emit_kernel(const EmitArgs A) {
     }
     if (MODE == kEmitCountTiles && lds_tiles) {
         __syncthreads();
-        for (int k = threadIdx.x; k < A.n_tiles; k += kEmitBlock) my_cnt[k] = s_aux[k];
+        for (int k = threadIdx.x; k < A.n_tiles; k += kEmitBlock) my_cnt[k * cs] = s_aux[k];
     }
 }
 
@@ -610,30 +612,39 @@ __global__ void __launch_bounds__(kBins) digit_base_kernel(const uint32_t *hist_
 // alone fixes the order -- the same order a stable sort of (tile, depth)
 // keys emitted in instance order produces.
 
-// per tile t: exclusive scan of the per-workgroup counts down the column (in
-// place) and the tile's total
-__global__ void __launch_bounds__(256) bucket_colscan_kernel(uint32_t *cnt /*[rows][n_tiles]*/, int n_rows,
+// per tile t (one wave each): exclusive scan of the per-workgroup counts
+// along the tile's row (in place) and the tile's total
+__global__ void __launch_bounds__(256) bucket_colscan_kernel(uint32_t *cnt /*[n_tiles][rows]*/, int n_rows,
                                                              int64_t n_tiles, uint32_t *tile_count) {
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (t >= n_tiles) return;
-    uint32_t run = 0u;
-    int r = 0;
-    for (; r + 32 <= n_rows; r += 32) {  // 32 loads in flight
-        uint32_t c[32];
+    const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (t >= n_tiles) return;  // uniform per wave
+    uint32_t *row = cnt + (size_t)t * n_rows;
+    uint32_t carry = 0u;
+    for (int r0 = 0; r0 < n_rows; r0 += 256) {  // 4 consecutive counts per lane
+        uint32_t c[4], sum = 0u;
 #pragma unroll
-        for (int k = 0; k < 32; ++k) c[k] = cnt[(size_t)(r + k) * n_tiles + t];
+        for (int k = 0; k < 4; ++k) {
+            const int r = r0 + lane * 4 + k;
+            c[k] = r < n_rows ? row[r] : 0u;
+            sum += c[k];
+        }
+        uint32_t incl = sum;
 #pragma unroll
-        for (int k = 0; k < 32; ++k) {
-            cnt[(size_t)(r + k) * n_tiles + t] = run;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += y;
+        }
+        uint32_t run = carry + incl - sum;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int r = r0 + lane * 4 + k;
+            if (r < n_rows) row[r] = run;
             run += c[k];
         }
+        carry += __shfl(incl, 63, 64);
     }
-    for (; r < n_rows; ++r) {
-        const uint32_t c = cnt[(size_t)r * n_tiles + t];
-        cnt[(size_t)r * n_tiles + t] = run;
-        run += c;
-    }
-    tile_count[t] = run;
+    if (lane == 0) tile_count[t] = carry;
 }
 
 // exclusive scan of the tile totals (one workgroup): each tile's first key,
@@ -679,17 +690,19 @@ __global__ void __launch_bounds__(1024) bucket_tilescan_kernel(const uint32_t *t
 template <int THREADS, bool IN_LDS, typename Ptr>
 __device__ __forceinline__ void bitonic_sort(Ptr s, uint32_t n2, uint32_t lim) {
     const uint32_t tid = threadIdx.x;
-    for (uint32_t k = 2; k <= n2; k <<= 1) {
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+    for (uint32_t lk = 1; (1u << lk) <= n2; ++lk) {
+        const uint32_t k = 1u << lk;
+        for (int lj = (int)lk - 1; lj >= 0; --lj) {
+            const uint32_t j = 1u << lj;
             const uint32_t next_j = (j > 1) ? (j >> 1) : k;  // first step of the next merge is j = k
             for (uint32_t t = tid; t < (n2 >> 1); t += THREADS) {
-                const uint32_t blk = t / j, r = t % j;
+                const uint32_t blk = t >> lj, r = t & (j - 1);
                 uint32_t i, p;
                 if (j == (k >> 1)) {
-                    i = blk * k + r;
-                    p = blk * k + (k - 1 - r);
+                    i = (blk << lk) + r;
+                    p = (blk << lk) + (k - 1 - r);
                 } else {
-                    i = blk * (2 * j) + r;
+                    i = (blk << (lj + 1)) + r;
                     p = i + j;
                 }
                 if (p < lim) {
@@ -848,7 +861,7 @@ static hipError_t run_bucket_sort(const SortPlan &P, const uint32_t *tt, const f
     if ((e = launch_kernel(emit_kernel<kEmitCountTiles>, dim3((unsigned)P.bucket_blocks), dim3(kEmitBlock), s, A)) !=
         hipSuccess)
         return e;
-    if ((e = launch_kernel(bucket_colscan_kernel, dim3((unsigned)((P.n_tiles_total + 255) / 256)), dim3(256), s,
+    if ((e = launch_kernel(bucket_colscan_kernel, dim3((unsigned)((P.n_tiles_total + 3) / 4)), dim3(256), s,
                            A.tile_cnt, (int)P.bucket_blocks, P.n_tiles_total, tcount)) != hipSuccess)
         return e;
     if ((e = launch_kernel(bucket_tilescan_kernel, dim3(1), dim3(1024), s, tcount, P.n_tiles_total, tstart, ranges,
