@@ -679,47 +679,56 @@ __global__ void __launch_bounds__(1024) bucket_tilescan_kernel(const uint32_t *t
 }
 
 // Ascending bitonic sort of s[0, n2) (n2 a power of two) by a workgroup of
-// `threads`; each merge starts with the reflected compare (i, block end - 1 -
-// i), so every compare-exchange is ascending and padding at the end stays
-// there.  `lim`: entries at or beyond it are virtual +infinity and are never
-// touched (for in-place sorts of unpadded global segments).
+// THREADS threads; each merge starts with the reflected compare (i, block end
+// - 1 - i), so every compare-exchange is ascending and padding at the end
+// stays there.  In HBM (IN_LDS false) entries at or beyond `lim` are virtual
+// +infinity and are never touched (in-place sort of an unpadded segment).
 // In LDS, a step with j <= 64 pairs elements inside the 128-element block
 // that one wave's 64 consecutive pair indices cover, so consecutive such
 // steps need only the wave's own (in-order) LDS accesses; a workgroup
 // barrier separates the others.  In HBM every step ends with a barrier.
+template <bool IN_LDS, typename Ptr>
+__device__ __forceinline__ void compare_exchange(Ptr s, uint32_t i, uint32_t p, uint32_t lim) {
+    if (!IN_LDS && p >= lim) return;
+    const uint64_t a = s[i], b = s[p];
+    const bool sw = a > b;
+    s[i] = sw ? b : a;
+    s[p] = sw ? a : b;
+}
+
+template <bool IN_LDS>
+__device__ __forceinline__ void bitonic_step_sync(uint32_t j, uint32_t next_j, bool last) {
+    if (!IN_LDS || j > 64 || next_j > 64 || last) {
+        __syncthreads();
+    } else {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
 template <int THREADS, bool IN_LDS, typename Ptr>
 __device__ __forceinline__ void bitonic_sort(Ptr s, uint32_t n2, uint32_t lim) {
-    const uint32_t tid = threadIdx.x;
+    const uint32_t tid = threadIdx.x, half = n2 >> 1;
     for (uint32_t lk = 1; (1u << lk) <= n2; ++lk) {
         const uint32_t k = 1u << lk;
-        for (int lj = (int)lk - 1; lj >= 0; --lj) {
+        // reflected step (j = k / 2)
+        {
+            const uint32_t lj = lk - 1, j = k >> 1;
+            for (uint32_t t = tid; t < half; t += THREADS) {
+                const uint32_t base = (t >> lj) << lk, r = t & (j - 1);
+                compare_exchange<IN_LDS>(s, base + r, base + (k - 1 - r), lim);
+            }
+            bitonic_step_sync<IN_LDS>(j, j > 1 ? (j >> 1) : (k << 1) >> 1, j == 1 && k == n2);
+        }
+        // half-cleaners (j = k / 4 .. 1)
+        for (int lj = (int)lk - 2; lj >= 0; --lj) {
             const uint32_t j = 1u << lj;
-            const uint32_t next_j = (j > 1) ? (j >> 1) : k;  // first step of the next merge is j = k
-            for (uint32_t t = tid; t < (n2 >> 1); t += THREADS) {
-                const uint32_t blk = t >> lj, r = t & (j - 1);
-                uint32_t i, p;
-                if (j == (k >> 1)) {
-                    i = (blk << lk) + r;
-                    p = (blk << lk) + (k - 1 - r);
-                } else {
-                    i = (blk << (lj + 1)) + r;
-                    p = i + j;
-                }
-                if (p < lim) {
-                    const uint64_t a = s[i], b = s[p];
-                    if (a > b) {
-                        s[i] = b;
-                        s[p] = a;
-                    }
-                }
+            for (uint32_t t = tid; t < half; t += THREADS) {
+                const uint32_t i = ((t >> lj) << (lj + 1)) + (t & (j - 1));
+                compare_exchange<IN_LDS>(s, i, i + j, lim);
             }
-            if (!IN_LDS || j > 64 || next_j > 64 || k == n2) {
-                __syncthreads();
-            } else {
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            }
+            bitonic_step_sync<IN_LDS>(j, j > 1 ? (j >> 1) : k, j == 1 && k == n2);
         }
     }
 }
