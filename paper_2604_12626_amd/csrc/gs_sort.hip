@@ -733,95 +733,6 @@ __device__ __forceinline__ void bitonic_sort(Ptr s, uint32_t n2, uint32_t lim) {
     }
 }
 
-// Register bitonic sort of 64 * E entries by one wave: lane l holds entries
-// l * E .. l * E + E - 1 in x[].  Steps with a partner in the same lane
-// compare registers; the others exchange through cross-lane shuffles, the
-// lane holding the lower index keeping the minimum.  No LDS, no barrier.
-template <int E, int J>
-__device__ __forceinline__ void lane_steps(uint64_t (&x)[E], uint32_t k) {
-    if constexpr (J >= 1) {
-        if ((uint32_t)J <= (k >> 1)) {
-            const bool reflect = ((uint32_t)J == (k >> 1));
-#pragma unroll
-            for (int q = 0; q < E; ++q) {
-                if ((q & J) == 0) {
-                    const int p = reflect ? (q ^ (2 * J - 1)) : (q ^ J);
-                    const uint64_t a = x[q], b = x[p];
-                    x[q] = a < b ? a : b;
-                    x[p] = a < b ? b : a;
-                }
-            }
-        }
-        lane_steps<E, J / 2>(x, k);
-    }
-}
-
-template <int E>
-__device__ __forceinline__ void wave_bitonic(uint64_t (&x)[E], uint32_t lane) {
-    for (uint32_t k = 2; k <= 64u * E; k <<= 1) {
-        for (uint32_t j = k >> 1; j >= (uint32_t)E; j >>= 1) {
-            const bool reflect = (j == (k >> 1));
-            const uint32_t m = reflect ? (k / E - 1) : (j / E);  // lane xor mask
-            const uint32_t hb = reflect ? (k / (2 * E)) : (j / E);
-            const bool lower = (lane & hb) == 0u;
-            // entry q pairs with the partner lane's entry E - 1 - q (reflect)
-            // or q: exchange q and E - 1 - q together so that both shuffles
-            // read values from before the step
-#pragma unroll
-            for (int q = 0; q < E / 2; ++q) {
-                const int r = E - 1 - q;
-                const uint64_t yq = __shfl_xor(reflect ? x[r] : x[q], (int)m, 64);
-                const uint64_t yr = __shfl_xor(reflect ? x[q] : x[r], (int)m, 64);
-                const uint64_t a = x[q], c = x[r];
-                x[q] = lower ? (a < yq ? a : yq) : (a < yq ? yq : a);
-                x[r] = lower ? (c < yr ? c : yr) : (c < yr ? yr : c);
-            }
-        }
-        lane_steps<E, E / 2>(x, k);
-    }
-}
-
-constexpr int kWaveSortMax = 2048;  // buckets up to this size are sorted by one wave in registers
-
-template <int E>
-__device__ __forceinline__ void wave_sort_bucket(uint64_t *bucket, uint32_t b, uint32_t L, uint64_t thi,
-                                                 uint64_t *keys, uint32_t *vals, uint32_t lane) {
-    uint64_t x[E];
-#pragma unroll
-    for (int q = 0; q < E; ++q) {
-        const uint32_t e = lane * E + q;
-        x[q] = e < L ? bucket[b + e] : ~0ull;
-    }
-    wave_bitonic<E>(x, lane);
-#pragma unroll
-    for (int q = 0; q < E; ++q) {
-        const uint32_t e = lane * E + q;
-        if (e < L) {
-            keys[b + e] = thi | (x[q] >> 32);
-            vals[b + e] = (uint32_t)x[q];
-        }
-    }
-}
-
-// one wave per tile (four per workgroup, grid-stride) for buckets of at most
-// kWaveSortMax entries; longer ones are left to tile_sort_kernel
-__global__ void __launch_bounds__(256) tile_sort_wave_kernel(uint64_t *bucket, const uint32_t *ranges,
-                                                             int64_t n_tiles, int64_t n_waves, uint64_t *keys,
-                                                             uint32_t *vals, const int32_t *d_overflow) {
-    if (*d_overflow) return;
-    const uint32_t lane = threadIdx.x & 63;
-    for (int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); tile < n_tiles; tile += n_waves) {
-        const uint32_t b = ranges[2 * tile], L = ranges[2 * tile + 1] - b;  // uniform per wave
-        if (L == 0u || L > (uint32_t)kWaveSortMax) continue;
-        const uint64_t thi = (uint64_t)tile << 32;
-        if (L <= 128u) wave_sort_bucket<2>(bucket, b, L, thi, keys, vals, lane);
-        else if (L <= 256u) wave_sort_bucket<4>(bucket, b, L, thi, keys, vals, lane);
-        else if (L <= 512u) wave_sort_bucket<8>(bucket, b, L, thi, keys, vals, lane);
-        else if (L <= 1024u) wave_sort_bucket<16>(bucket, b, L, thi, keys, vals, lane);
-        else wave_sort_bucket<32>(bucket, b, L, thi, keys, vals, lane);
-    }
-}
-
 constexpr int kTileSortBlock = 512;
 constexpr int kTileSortCap = 8192;  // entries sorted in LDS; longer buckets are sorted in place in HBM
 
@@ -835,7 +746,7 @@ __global__ void __launch_bounds__(kTileSortBlock) tile_sort_kernel(uint64_t *buc
     if (*d_overflow) return;
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += n_blocks) {  // uniform per workgroup
         const uint32_t b = ranges[2 * tile], L = ranges[2 * tile + 1] - b;
-        if (L <= (uint32_t)kWaveSortMax) continue;  // sorted by tile_sort_wave_kernel
+        if (L == 0u) continue;
         uint32_t n2 = 2;
         while (n2 < L) n2 <<= 1;
         const uint64_t thi = (uint64_t)tile << 32;
@@ -968,13 +879,7 @@ static hipError_t run_bucket_sort(const SortPlan &P, const uint32_t *tt, const f
     if ((e = launch_kernel(emit_kernel<kEmitScatterTiles>, dim3((unsigned)P.bucket_blocks), dim3(kEmitBlock), s,
                            A)) != hipSuccess)
         return e;
-    // buckets up to kWaveSortMax entries: one wave each; longer ones: a workgroup each
-    int64_t wg = (P.n_tiles_total + 3) / 4;
-    if (wg > 8 * (int64_t)n_cu) wg = 8 * (int64_t)n_cu;
-    if ((e = launch_kernel(tile_sort_wave_kernel, dim3((unsigned)wg), dim3(256), s, A.bucket,
-                           (const uint32_t *)ranges, P.n_tiles_total, 4 * wg, keys, vals, d_overflow)) != hipSuccess)
-        return e;
-    int64_t sg = (int64_t)n_cu;
+    int64_t sg = 2 * (int64_t)n_cu;
     if (sg > P.n_tiles_total) sg = P.n_tiles_total;
     return launch_kernel(tile_sort_kernel, dim3((unsigned)sg), dim3(kTileSortBlock), s, A.bucket,
                          (const uint32_t *)ranges, P.n_tiles_total, sg, keys, vals, d_overflow);
