@@ -733,36 +733,38 @@ __device__ __forceinline__ void bitonic_sort(Ptr s, uint32_t n2, uint32_t lim) {
     }
 }
 
-constexpr int kTileSortBlock = 512;
-constexpr int kTileSortCap = 8192;  // entries sorted in LDS; longer buckets are sorted in place in HBM
+constexpr int kSmallSortBlock = 256, kSmallSortCap = 2048;  // most buckets: many small workgroups per CU
+constexpr int kTileSortBlock = 512, kTileSortCap = 8192;    // longer buckets in LDS; beyond, in place in HBM
 
-// one workgroup per tile (grid-stride): sort the bucket and write the keys
-// (tile << 32 | depth bits) and values (instance)
-__global__ void __launch_bounds__(kTileSortBlock) tile_sort_kernel(uint64_t *bucket, const uint32_t *ranges,
-                                                                   int64_t n_tiles, int64_t n_blocks,
-                                                                   uint64_t *keys, uint32_t *vals,
-                                                                   const int32_t *d_overflow) {
-    __shared__ uint64_t s[kTileSortCap];
+// One workgroup per tile (grid-stride): sort the bucket and write the keys
+// (tile << 32 | depth bits) and values (instance).  Launched twice: small
+// workgroups for buckets of 1..SMALL_MAX entries (many resident per CU),
+// then large ones for the rest.
+template <int THREADS, int CAP, bool SMALL>
+__global__ void __launch_bounds__(THREADS) tile_sort_kernel(uint64_t *bucket, const uint32_t *ranges,
+                                                            int64_t n_tiles, int64_t n_blocks, uint64_t *keys,
+                                                            uint32_t *vals, const int32_t *d_overflow) {
+    __shared__ uint64_t s[CAP];
     if (*d_overflow) return;
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += n_blocks) {  // uniform per workgroup
         const uint32_t b = ranges[2 * tile], L = ranges[2 * tile + 1] - b;
-        if (L == 0u) continue;
+        if (L == 0u || (SMALL ? L > (uint32_t)kSmallSortCap : L <= (uint32_t)kSmallSortCap)) continue;
         uint32_t n2 = 2;
         while (n2 < L) n2 <<= 1;
         const uint64_t thi = (uint64_t)tile << 32;
-        if (L <= (uint32_t)kTileSortCap) {
-            for (uint32_t i = threadIdx.x; i < n2; i += kTileSortBlock) s[i] = (i < L) ? bucket[b + i] : ~0ull;
+        if (L <= (uint32_t)CAP) {
+            for (uint32_t i = threadIdx.x; i < n2; i += THREADS) s[i] = (i < L) ? bucket[b + i] : ~0ull;
             __syncthreads();
-            bitonic_sort<kTileSortBlock, true>(s, n2, n2);
-            for (uint32_t i = threadIdx.x; i < L; i += kTileSortBlock) {
+            bitonic_sort<THREADS, true>(s, n2, n2);
+            for (uint32_t i = threadIdx.x; i < L; i += THREADS) {
                 const uint64_t c = s[i];
                 keys[b + i] = thi | (c >> 32);
                 vals[b + i] = (uint32_t)c;
             }
             __syncthreads();  // s is reused by the next tile
         } else {
-            bitonic_sort<kTileSortBlock, false>(bucket + b, n2, L);
-            for (uint32_t i = threadIdx.x; i < L; i += kTileSortBlock) {
+            bitonic_sort<THREADS, false>(bucket + b, n2, L);
+            for (uint32_t i = threadIdx.x; i < L; i += THREADS) {
                 const uint64_t c = bucket[b + i];
                 keys[b + i] = thi | (c >> 32);
                 vals[b + i] = (uint32_t)c;
@@ -879,10 +881,17 @@ static hipError_t run_bucket_sort(const SortPlan &P, const uint32_t *tt, const f
     if ((e = launch_kernel(emit_kernel<kEmitScatterTiles>, dim3((unsigned)P.bucket_blocks), dim3(kEmitBlock), s,
                            A)) != hipSuccess)
         return e;
-    int64_t sg = 2 * (int64_t)n_cu;
+    int64_t sg = 8 * (int64_t)n_cu;
     if (sg > P.n_tiles_total) sg = P.n_tiles_total;
-    return launch_kernel(tile_sort_kernel, dim3((unsigned)sg), dim3(kTileSortBlock), s, A.bucket,
-                         (const uint32_t *)ranges, P.n_tiles_total, sg, keys, vals, d_overflow);
+    if ((e = launch_kernel(tile_sort_kernel<kSmallSortBlock, kSmallSortCap, true>, dim3((unsigned)sg),
+                           dim3(kSmallSortBlock), s, A.bucket, (const uint32_t *)ranges, P.n_tiles_total, sg, keys,
+                           vals, d_overflow)) != hipSuccess)
+        return e;
+    int64_t lg = (int64_t)n_cu;
+    if (lg > P.n_tiles_total) lg = P.n_tiles_total;
+    return launch_kernel(tile_sort_kernel<kTileSortBlock, kTileSortCap, false>, dim3((unsigned)lg),
+                         dim3(kTileSortBlock), s, A.bucket, (const uint32_t *)ranges, P.n_tiles_total, lg, keys, vals,
+                         d_overflow);
 }
 
 hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec, int TX, int TY, char *ws,
