@@ -8,7 +8,7 @@
 // T_i = T_{i+1} / (1 - alpha_i), and forming the screen-space adjoint of each
 // entry (u, v, conic, opacity, colour, depth).  Entries that cannot reach a
 // wave's quadrant are dropped by the same conservative bound as the forward;
-// per remaining entry the 64 lanes are summed with cross-lane adds and one
+// per remaining entry the 64 lanes are summed with DPP adds and the last
 // lane issues the global float atomics (skipped when no lane contributed).
 //
 // B2 (per Gaussian of a segment, scene-major): chains the screen-space
@@ -21,9 +21,23 @@ namespace gs {
 
 
 
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+// Sum over the wave, complete in lane 63 only, with DPP lane moves fused
+// into the adds (no LDS traffic): pairs, quads, half rows, rows (these leave
+// every lane of a 16-lane row holding the row sum), then row 0 into row 1
+// and row 2 into row 3, then rows 0-1 into row 3.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_add(float v) {
+    // rows outside ROW_MASK add `old` = 0
+    return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
+}
+
+__device__ __forceinline__ float wave_sum_to_last(float v) {
+    v = dpp_add<0xB1, 0xF>(v);   // quad_perm [1, 0, 3, 2]
+    v = dpp_add<0x4E, 0xF>(v);   // quad_perm [2, 3, 0, 1]
+    v = dpp_add<0x141, 0xF>(v);  // row_half_mirror
+    v = dpp_add<0x140, 0xF>(v);  // row_mirror
+    v = dpp_add<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    v = dpp_add<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
     return v;
 }
 
@@ -134,17 +148,17 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
                 }
             }
             if (__ballot(contrib) == 0ull) continue;
-            gu = wave_sum(gu);
-            gv = wave_sum(gv);
-            gA = wave_sum(gA);
-            gB = wave_sum(gB);
-            gC = wave_sum(gC);
-            go = wave_sum(go);
-            gr = wave_sum(gr);
-            gg = wave_sum(gg);
-            gb = wave_sum(gb);
-            gz = wave_sum(gz);
-            if (lane == 0) {
+            gu = wave_sum_to_last(gu);
+            gv = wave_sum_to_last(gv);
+            gA = wave_sum_to_last(gA);
+            gB = wave_sum_to_last(gB);
+            gC = wave_sum_to_last(gC);
+            go = wave_sum_to_last(go);
+            gr = wave_sum_to_last(gr);
+            gg = wave_sum_to_last(gg);
+            gb = wave_sum_to_last(gb);
+            gz = wave_sum_to_last(gz);
+            if (lane == 63) {
                 float *dst = a.g2d + (size_t)__float_as_uint(e2.z) * kG2D;
                 atomicAdd(dst + kGU, gu);
                 atomicAdd(dst + kGV, gv);
