@@ -406,9 +406,20 @@ gs_status gs_composite(const gs_projected *proj, const uint32_t *vals, const uin
 }
 
 // ---------------------------------------------------------------------------
+// workspace: per-instance screen-space accumulators, then the compacted
+// Gaussian list of one projection launch, then its counters (one per launch)
+static size_t bwd_list_offset(int64_t n_instances) {
+    return ((size_t)(n_instances > 0 ? n_instances : 1) * gs::kG2D * sizeof(float) + 255) & ~(size_t)255;
+}
+static size_t bwd_count_offset(int64_t n_instances) {
+    return bwd_list_offset(n_instances) +
+           (((size_t)(n_instances > 0 ? n_instances : 1) * sizeof(uint32_t) + 255) & ~(size_t)255);
+}
+constexpr int kBwdMaxLaunches = GS_MAX_SEGMENTS * ((GS_MAX_VIEWS + gs::kProjViews - 1) / gs::kProjViews);
+
 size_t gs_render_backward_workspace(int64_t n_instances) {
     if (n_instances < 0) return 0;
-    return (size_t)(n_instances > 0 ? n_instances : 1) * gs::kG2D * sizeof(float);
+    return bwd_count_offset(n_instances) + sizeof(uint32_t) * kBwdMaxLaunches;
 }
 
 gs_status gs_render_backward(const gs_gaussians *segs, int32_t n_segs, const gs_camera *cams, int32_t n_views,
@@ -439,8 +450,13 @@ gs_status gs_render_backward(const gs_gaussians *segs, int32_t n_segs, const gs_
     }
     hipStream_t sm = (hipStream_t)stream;
     float *g2d = static_cast<float *>(ws);
-    hipError_t e = gs::launch_fill_u32(reinterpret_cast<uint32_t *>(g2d), 0u, proj->n_instances * gs::kG2D, sm);
+    uint32_t *list = reinterpret_cast<uint32_t *>(static_cast<char *>(ws) + bwd_list_offset(proj->n_instances));
+    uint32_t *counts = reinterpret_cast<uint32_t *>(static_cast<char *>(ws) + bwd_count_offset(proj->n_instances));
+    // one fill clears the accumulators and the list counters (the list between them is rewritten)
+    hipError_t e = gs::launch_fill_u32(reinterpret_cast<uint32_t *>(g2d), 0u,
+                                       (int64_t)(bwd_count_offset(proj->n_instances) / 4) + kBwdMaxLaunches, sm);
     if (e != hipSuccess) return hip_fail(e, "gs_render_backward");
+    int launch_no = 0;
     gs::BackwardTileArgs b = {};
     b.rec = reinterpret_cast<const float4 *>(proj->rec);
     b.vals = vals;
@@ -490,6 +506,8 @@ gs_status gs_render_backward(const gs_gaussians *segs, int32_t n_segs, const gs_
             a.lowpass = p->lowpass;
             a.sigma_cut = p->sigma_cut;
             a.fov_clamp = p->fov_clamp;
+            a.list = list;
+            a.count = counts + launch_no++;
             e = gs::launch_backward_project(a, sm);
             if (e != hipSuccess) return hip_fail(e, "gs_render_backward (projection)");
             c += gs::kProjViews;

@@ -199,8 +199,9 @@ __global__ void __launch_bounds__(256) backward_project_kernel(const BackwardPro
         for (int j = 0; j < 3; ++j) c[16 + j] = -(c[j] * c[9] + c[3 + j] * c[10] + c[6 + j] * c[11]);
     }
     __syncthreads();
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= a.seg.n) return;
+    const int64_t li = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (li >= (int64_t)*a.count) return;
+    const int64_t i = a.list[li];
 
     const float mx = a.seg.means[3 * i + 0], my = a.seg.means[3 * i + 1], mz = a.seg.means[3 * i + 2];
     float S[6];
@@ -383,9 +384,58 @@ __global__ void __launch_bounds__(256) backward_project_kernel(const BackwardPro
     }
 }
 
+// Dense gradients start at zero: every plane of the segment is cleared here
+// (a Gaussian no view draws keeps zeros), and backward_project_kernel then
+// writes the Gaussians of the compacted list only.
+__global__ void __launch_bounds__(256) zero_grads_kernel(gs_gaussians_grad g, int64_t n, int sh_floats,
+                                                         int64_t stride) {
+    float *planes[6] = {g.means, g.log_scales, g.quats, g.cov6, g.opacity, g.sh};
+    const int width[6] = {3, 3, 4, 6, 1, sh_floats};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        float *p = planes[k];
+        if (!p) continue;
+        const int64_t m = n * width[k];
+        for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < m; j += stride) p[j] = 0.0f;
+    }
+}
+
+// Gaussians of the segment with an instance drawn (tiles_touched > 0) in one
+// of the chunk's views, appended to a.list (order of arrival; each Gaussian
+// is handled on its own, so the order does not affect any result)
+__global__ void __launch_bounds__(256) compact_visible_kernel(const BackwardProjectArgs a) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    bool vis = false;
+    if (i < a.seg.n)
+        for (int vi = 0; vi < a.nv && !vis; ++vi) vis = a.tiles_touched[a.base[vi] + i] != 0u;
+    const uint64_t bal = __ballot(vis);
+    const int lane = threadIdx.x & 63;
+    uint32_t base = 0u;
+    if (lane == 0 && bal) base = atomicAdd(a.count, (uint32_t)__popcll(bal));
+    base = (uint32_t)__shfl((int)base, 0, 64);
+    if (vis) {
+        const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+        a.list[base + (uint32_t)__popcll(bal & lt)] = (uint32_t)i;
+    }
+}
+
 hipError_t launch_backward_project(const BackwardProjectArgs &a, hipStream_t s) {
     if (a.seg.n == 0) return hipSuccess;
     const unsigned grid = (unsigned)((a.seg.n + 255) / 256);
+    hipError_t e;
+    if (a.first) {
+        int64_t zb = (a.seg.n * 48 + 255) / 256;
+        if (zb > 4096) zb = 4096;
+        const int K = (a.seg.sh_degree + 1) * (a.seg.sh_degree + 1);
+        gs_gaussians_grad g = a.grad;
+        if (a.seg.cov6) g.log_scales = g.quats = nullptr;  // not written for covariance segments
+        else g.cov6 = nullptr;
+        if ((e = launch_kernel(zero_grads_kernel, dim3((unsigned)zb), dim3(256), s, g, a.seg.n, 3 * K, zb * 256)) !=
+            hipSuccess)
+            return e;
+    }
+    if (a.nv == 0) return hipSuccess;
+    if ((e = launch_kernel(compact_visible_kernel, dim3(grid), dim3(256), s, a)) != hipSuccess) return e;
     switch (a.seg.sh_degree) {
         case 0: return launch_kernel(backward_project_kernel<0>, dim3(grid), dim3(256), s, a);
         case 1: return launch_kernel(backward_project_kernel<1>, dim3(grid), dim3(256), s, a);

@@ -48,6 +48,8 @@ struct BackwardProjectArgs {
     int32_t first;     // 1: overwrite the gradients, 0: accumulate (later chunk of views)
     int32_t W, H;
     float near_plane, lowpass, sigma_cut, fov_clamp;
+    uint32_t *list;    // [seg.n]: Gaussians with an instance drawn in one of the views (compacted)
+    uint32_t *count;   // number of entries of `list` (zero before the compaction)
 };
 
 struct CompositeArgs {
