@@ -401,21 +401,33 @@ __global__ void __launch_bounds__(256) zero_grads_kernel(gs_gaussians_grad g, in
 }
 
 // Gaussians of the segment with an instance drawn (tiles_touched > 0) in one
-// of the chunk's views, appended to a.list (order of arrival; each Gaussian
-// is handled on its own, so the order does not affect any result)
-__global__ void __launch_bounds__(256) compact_visible_kernel(const BackwardProjectArgs a) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+// of the chunk's views, appended to a.list: positions inside a 1024-thread
+// workgroup come from ballots and a prefix over its 16 waves, and one atomic
+// per workgroup reserves its stretch (order of arrival; each Gaussian is
+// handled on its own, so the order does not affect any result)
+__global__ void __launch_bounds__(1024) compact_visible_kernel(const BackwardProjectArgs a) {
+    __shared__ uint32_t s_cnt[16], s_base;
+    const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     bool vis = false;
     if (i < a.seg.n)
         for (int vi = 0; vi < a.nv && !vis; ++vi) vis = a.tiles_touched[a.base[vi] + i] != 0u;
     const uint64_t bal = __ballot(vis);
-    const int lane = threadIdx.x & 63;
-    uint32_t base = 0u;
-    if (lane == 0 && bal) base = atomicAdd(a.count, (uint32_t)__popcll(bal));
-    base = (uint32_t)__shfl((int)base, 0, 64);
+    if (lane == 0) s_cnt[wave] = (uint32_t)__popcll(bal);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t total = 0u;
+        for (int w = 0; w < 16; ++w) {
+            const uint32_t c = s_cnt[w];
+            s_cnt[w] = total;
+            total += c;
+        }
+        s_base = total ? atomicAdd(a.count, total) : 0u;
+    }
+    __syncthreads();
     if (vis) {
         const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-        a.list[base + (uint32_t)__popcll(bal & lt)] = (uint32_t)i;
+        a.list[s_base + s_cnt[wave] + (uint32_t)__popcll(bal & lt)] = (uint32_t)i;
     }
 }
 
@@ -435,7 +447,9 @@ hipError_t launch_backward_project(const BackwardProjectArgs &a, hipStream_t s) 
             return e;
     }
     if (a.nv == 0) return hipSuccess;
-    if ((e = launch_kernel(compact_visible_kernel, dim3(grid), dim3(256), s, a)) != hipSuccess) return e;
+    if ((e = launch_kernel(compact_visible_kernel, dim3((unsigned)((a.seg.n + 1023) / 1024)), dim3(1024), s, a)) !=
+        hipSuccess)
+        return e;
     switch (a.seg.sh_degree) {
         case 0: return launch_kernel(backward_project_kernel<0>, dim3(grid), dim3(256), s, a);
         case 1: return launch_kernel(backward_project_kernel<1>, dim3(grid), dim3(256), s, a);
