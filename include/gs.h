@@ -218,10 +218,7 @@ gs_status gs_project(const gs_gaussians *segs, int32_t n_segs, const gs_camera *
                      const uint32_t *view_seg_mask, const gs_params *p, gs_projected *out, gs_stream_t stream);
 
 /* Workspace bytes gs_bin_sort needs for n_instances projected instances,
- * `capacity` key slots and n_views views of p->width x p->height.  The
- * workspace holds arrival counters: it must be zero-filled before its first
- * use, and every call leaves the counters at zero again (calls sharing a
- * workspace must not overlap). */
+ * `capacity` key slots and n_views views of p->width x p->height. */
 size_t gs_bin_sort_workspace(int64_t n_instances, int64_t capacity, int32_t n_views, const gs_params *p);
 
 /* Tile binning of the projected instances:

@@ -102,7 +102,7 @@ struct SortPlan {
     int64_t bucket_blocks;
     int64_t scan_blocks, sort_parts;
     // workspace layout (byte offsets)
-    size_t off_sync, off_part, off_keys2, off_vals2, off_rows, off_dbase, off_tcnt, off_tcount, off_tstart, off_hist, off_status, off_ticket, total;
+    size_t off_part, off_keys2, off_vals2, off_rows, off_dbase, off_tcnt, off_tcount, off_tstart, off_hist, off_status, off_ticket, total;
 };
 
 // launchers (one per translation unit)

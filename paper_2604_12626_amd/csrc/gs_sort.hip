@@ -75,32 +75,8 @@ __device__ __forceinline__ uint64_t block_reduce_u64(uint64_t v, uint64_t *s_tmp
     return t;  // valid in thread 0
 }
 
-// exclusive scan of v over the 256 threads of a workgroup (64-bit), and the total
-__device__ __forceinline__ uint64_t block256_exclusive_u64(uint64_t v, uint64_t *s_w, uint64_t *total) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    uint64_t incl = v;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint64_t y = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += y;
-    }
-    if (lane == 63) s_w[wave] = incl;
-    __syncthreads();
-    uint64_t before = 0;
-    for (int k = 0; k < wave; ++k) before += s_w[k];
-    *total = s_w[0] + s_w[1] + s_w[2] + s_w[3];
-    __syncthreads();
-    return before + incl - v;
-}
-
-// Sum of tiles_touched per 4096-instance block; the last workgroup to finish
-// (device-scope fence + arrival counter, which it returns to zero) turns the
-// sums into exclusive block prefixes and writes K and the overflow flag.
-__global__ void __launch_bounds__(kScanBlock) scan_reduce_kernel(const uint32_t *tt, int64_t n, uint64_t *part,
-                                                                 int64_t nparts, int64_t capacity, int64_t *d_num,
-                                                                 int32_t *d_overflow, uint32_t *arrive) {
+__global__ void __launch_bounds__(kScanBlock) scan_reduce_kernel(const uint32_t *tt, int64_t n, uint64_t *part) {
     __shared__ uint64_t s_tmp[4];
-    __shared__ bool s_last;
     const int64_t base = (int64_t)blockIdx.x * kScanTile;
     uint64_t acc = 0;
 #pragma unroll
@@ -109,27 +85,33 @@ __global__ void __launch_bounds__(kScanBlock) scan_reduce_kernel(const uint32_t 
         if (i < n) acc += tt[i];
     }
     const uint64_t t = block_reduce_u64(acc, s_tmp);
-    if (threadIdx.x == 0) {
-        part[blockIdx.x] = t;
-        __threadfence();
-        s_last = atomicAdd(arrive, 1u) == (uint32_t)(nparts - 1);
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// one workgroup of 1024 threads: exclusive scan of the block sums in place;
+// writes K and the overflow flag
+__global__ void __launch_bounds__(1024) scan_partials_kernel(uint64_t *part, int64_t nparts, int64_t capacity,
+                                                             int64_t *d_num, int32_t *d_overflow) {
+    __shared__ uint64_t s[1024];
     uint64_t carry = 0;
-    for (int64_t c0 = 0; c0 < nparts; c0 += kScanBlock) {
-        const int64_t i = c0 + threadIdx.x;
-        const uint64_t v = (i < nparts) ? __hip_atomic_load(part + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
-        uint64_t total;
-        const uint64_t ex = block256_exclusive_u64(v, s_tmp, &total);
-        if (i < nparts) part[i] = carry + ex;
-        carry += total;
+    for (int64_t base = 0; base < nparts; base += 1024) {
+        const int64_t i = base + threadIdx.x;
+        const uint64_t v = (i < nparts) ? part[i] : 0;
+        s[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            const uint64_t t = (threadIdx.x >= (unsigned)off) ? s[threadIdx.x - off] : 0;
+            __syncthreads();
+            s[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (i < nparts) part[i] = carry + s[threadIdx.x] - v;
+        carry += s[1023];
+        __syncthreads();
     }
     if (threadIdx.x == 0) {
         *d_num = (int64_t)carry;
         *d_overflow = ((int64_t)carry > capacity) ? 1 : 0;
-        atomicExch(arrive, 0u);
     }
 }
 
@@ -631,84 +613,76 @@ __global__ void __launch_bounds__(kBins) digit_base_kernel(const uint32_t *hist_
 // keys emitted in instance order produces.
 
 // per tile t (one wave each): exclusive scan of the per-workgroup counts
-// along the tile's row (in place) and the tile's total.  The last workgroup
-// to finish (fence + arrival counter, returned to zero) scans the tile
-// totals into each tile's first key and writes the ranges ([first, end) for
-// tiles with keys, [0, 0) otherwise, and all [0, 0) after an overflow).
+// along the tile's row (in place) and the tile's total
 __global__ void __launch_bounds__(256) bucket_colscan_kernel(uint32_t *cnt /*[n_tiles][rows]*/, int n_rows,
-                                                             int64_t n_tiles, uint32_t *tile_count,
-                                                             uint32_t *tile_start, uint32_t *ranges,
-                                                             const int32_t *d_overflow, uint32_t *arrive,
-                                                             uint32_t n_blocks) {
-    __shared__ uint32_t s_w[4];
-    __shared__ bool s_last;
+                                                             int64_t n_tiles, uint32_t *tile_count) {
     const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (t < n_tiles) {  // uniform per wave
-        uint32_t *row = cnt + (size_t)t * n_rows;
-        uint32_t carry = 0u;
-        for (int r0 = 0; r0 < n_rows; r0 += 256) {  // 4 consecutive counts per lane
-            uint32_t c[4], sum = 0u;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int r = r0 + lane * 4 + k;
-                c[k] = r < n_rows ? row[r] : 0u;
-                sum += c[k];
-            }
-            uint32_t incl = sum;
-#pragma unroll
-            for (int off = 1; off < 64; off <<= 1) {
-                const uint32_t y = __shfl_up(incl, off, 64);
-                if (lane >= off) incl += y;
-            }
-            uint32_t run = carry + incl - sum;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int r = r0 + lane * 4 + k;
-                if (r < n_rows) row[r] = run;
-                run += c[k];
-            }
-            carry += __shfl(incl, 63, 64);
-        }
-        if (lane == 0) tile_count[t] = carry;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        s_last = atomicAdd(arrive, 1u) == n_blocks - 1u;
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    const bool ovf = *d_overflow != 0;
-    const int wave = threadIdx.x >> 6;
+    if (t >= n_tiles) return;  // uniform per wave
+    uint32_t *row = cnt + (size_t)t * n_rows;
     uint32_t carry = 0u;
-    for (int64_t c0 = 0; c0 < n_tiles; c0 += 256) {
-        const int64_t tt = c0 + threadIdx.x;
-        const uint32_t c =
-            tt < n_tiles ? __hip_atomic_load(tile_count + tt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
-        uint32_t incl = c;
+    for (int r0 = 0; r0 < n_rows; r0 += 256) {  // 4 consecutive counts per lane
+        uint32_t c[4], sum = 0u;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int r = r0 + lane * 4 + k;
+            c[k] = r < n_rows ? row[r] : 0u;
+            sum += c[k];
+        }
+        uint32_t incl = sum;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
             const uint32_t y = __shfl_up(incl, off, 64);
             if (lane >= off) incl += y;
         }
-        if (lane == 63) s_w[wave] = incl;
-        __syncthreads();
-        uint32_t before = carry;
-        for (int k = 0; k < wave; ++k) before += s_w[k];
-        const uint32_t start = before + incl - c;
-        if (tt < n_tiles) {
-            tile_start[tt] = start;
-            ranges[2 * tt] = (c && !ovf) ? start : 0u;
-            ranges[2 * tt + 1] = (c && !ovf) ? start + c : 0u;
+        uint32_t run = carry + incl - sum;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int r = r0 + lane * 4 + k;
+            if (r < n_rows) row[r] = run;
+            run += c[k];
         }
-        carry += s_w[0] + s_w[1] + s_w[2] + s_w[3];
-        __syncthreads();
+        carry += __shfl(incl, 63, 64);
     }
-    if (threadIdx.x == 0) atomicExch(arrive, 0u);
+    if (lane == 0) tile_count[t] = carry;
 }
 
+// exclusive scan of the tile totals (one workgroup): each tile's first key,
+// and the ranges ([first, end) for tiles with keys, [0, 0) otherwise)
+__global__ void __launch_bounds__(1024) bucket_tilescan_kernel(const uint32_t *tile_count, int64_t n_tiles,
+                                                               uint32_t *tile_start, uint32_t *ranges,
+                                                               const int32_t *d_overflow) {
+    __shared__ uint32_t s_w[16];
+    if (*d_overflow) return;  // ranges stay cleared
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t per = (n_tiles + 1023) / 1024;
+    const int64_t t0 = (int64_t)tid * per, t1 = (t0 + per < n_tiles) ? t0 + per : n_tiles;
+    uint32_t sum = 0u;
+    for (int64_t t = t0; t < t1; ++t) sum += tile_count[t];
+    uint32_t incl = sum;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
+    }
+    if (lane == 63) s_w[wave] = incl;
+    __syncthreads();
+    uint32_t run = incl - sum;
+    for (int k = 0; k < wave; ++k) run += s_w[k];
+    for (int64_t t = t0; t < t1; ++t) {
+        const uint32_t c = tile_count[t];
+        tile_start[t] = run;
+        ranges[2 * t] = c ? run : 0u;
+        ranges[2 * t + 1] = c ? run + c : 0u;
+        run += c;
+    }
+}
+
+// Ascending bitonic sort of s[0, n2) (n2 a power of two) by a workgroup of
+// THREADS threads; each merge starts with the reflected compare (i, block end
+// - 1 - i), so every compare-exchange is ascending and padding at the end
+// stays there.  In HBM (IN_LDS false) entries at or beyond `lim` are virtual
+// +infinity and are never touched (in-place sort of an unpadded segment).
 // In LDS, a step with j <= 64 pairs elements inside the 128-element block
 // that one wave's 64 consecutive pair indices cover, so consecutive such
 // steps need only the wave's own (in-order) LDS accesses; a workgroup
@@ -839,8 +813,6 @@ SortPlan make_sort_plan(int64_t n, int64_t capacity, int64_t n_tiles_total) {
     p.sort_parts = (capacity + kMinSortPart - 1) / kMinSortPart;
     if (p.sort_parts < 1) p.sort_parts = 1;
     size_t o = 0;
-    p.off_sync = o;  // arrival counters (zero between calls)
-    o = align256(o + 256);
     p.off_part = o;
     o = align256(o + sizeof(uint64_t) * (size_t)p.scan_blocks);
     p.off_keys2 = o;
@@ -879,7 +851,7 @@ static hipError_t run_bucket_sort(const SortPlan &P, const uint32_t *tt, const f
                                   char *ws, uint64_t *keys, uint32_t *vals, uint32_t *ranges,
                                   const int32_t *d_overflow, int n_cu, hipStream_t s) {
     hipError_t e;
-    if (P.n <= 0) return launch_fill_u32(ranges, 0u, 2 * P.n_tiles_total, s);  // no keys
+    if (P.n <= 0) return hipSuccess;  // no keys: ranges are cleared
     EmitArgs A = {};
     A.tt = tt;
     A.part = reinterpret_cast<const uint64_t *>(ws + P.off_part);
@@ -900,10 +872,11 @@ static hipError_t run_bucket_sort(const SortPlan &P, const uint32_t *tt, const f
     if ((e = launch_kernel(emit_kernel<kEmitCountTiles>, dim3((unsigned)P.bucket_blocks), dim3(kEmitBlock), s, A)) !=
         hipSuccess)
         return e;
-    const uint32_t cs_blocks = (uint32_t)((P.n_tiles_total + 3) / 4);
-    if ((e = launch_kernel(bucket_colscan_kernel, dim3(cs_blocks), dim3(256), s, A.tile_cnt, (int)P.bucket_blocks,
-                           P.n_tiles_total, tcount, tstart, ranges, d_overflow,
-                           reinterpret_cast<uint32_t *>(ws + P.off_sync) + 32, cs_blocks)) != hipSuccess)
+    if ((e = launch_kernel(bucket_colscan_kernel, dim3((unsigned)((P.n_tiles_total + 3) / 4)), dim3(256), s,
+                           A.tile_cnt, (int)P.bucket_blocks, P.n_tiles_total, tcount)) != hipSuccess)
+        return e;
+    if ((e = launch_kernel(bucket_tilescan_kernel, dim3(1), dim3(1024), s, tcount, P.n_tiles_total, tstart, ranges,
+                           d_overflow)) != hipSuccess)
         return e;
     if ((e = launch_kernel(emit_kernel<kEmitScatterTiles>, dim3((unsigned)P.bucket_blocks), dim3(kEmitBlock), s,
                            A)) != hipSuccess)
@@ -935,22 +908,20 @@ hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec
     uint32_t *status = reinterpret_cast<uint32_t *>(ws + P.off_status);
     const size_t clear_words = (P.off_status - P.off_hist) / 4 + (size_t)P.passes * P.sort_parts * kBins;
     uint32_t *tcnt = reinterpret_cast<uint32_t *>(ws + P.off_tcnt);
-    const size_t tcnt_words = (size_t)P.bucket_blocks * (size_t)P.n_tiles_total;
+    const size_t tcnt_words = P.use_bucket ? (size_t)P.bucket_blocks * (size_t)P.n_tiles_total : 0;
 
-    // clears: the onesweep state and the ranges (onesweep), or the global
-    // tile counters when they do not fit in LDS (bucket); the bucket path
-    // with LDS counters writes every counter and every range itself
-    if (!P.use_bucket) {
-        if ((e = launch_kernel(clear2_kernel, dim3(1024), dim3(256), s, hist, (int64_t)clear_words, ranges,
-                               2 * P.n_tiles_total, (int64_t)1024 * 256)) != hipSuccess)
+    if ((e = launch_kernel(clear2_kernel, dim3(1024), dim3(256), s, P.use_bucket ? tcnt : hist,
+                           (int64_t)(P.use_bucket ? tcnt_words : clear_words), ranges, 2 * P.n_tiles_total,
+                           (int64_t)1024 * 256)) != hipSuccess)
+        return e;
+    // 1. scan
+    if (P.n > 0) {
+        if ((e = launch_kernel(scan_reduce_kernel, dim3((unsigned)P.scan_blocks), dim3(kScanBlock), s, tt, P.n,
+                               part)) != hipSuccess)
             return e;
-    } else if (P.n_tiles_total > kLdsTiles) {
-        if ((e = launch_fill_u32(tcnt, 0u, (int64_t)tcnt_words, s)) != hipSuccess) return e;
     }
-    // 1. scan of tiles_touched: block sums, then (last workgroup) their prefixes, K and the overflow flag
-    if ((e = launch_kernel(scan_reduce_kernel, dim3((unsigned)P.scan_blocks), dim3(kScanBlock), s, tt, P.n, part,
-                           P.scan_blocks, P.capacity, d_num, d_overflow,
-                           reinterpret_cast<uint32_t *>(ws + P.off_sync))) != hipSuccess)
+    if ((e = launch_kernel(scan_partials_kernel, dim3(1), dim3(1024), s, part, P.n > 0 ? P.scan_blocks : (int64_t)0,
+                           P.capacity, d_num, d_overflow)) != hipSuccess)
         return e;
     if (P.use_bucket) return run_bucket_sort(P, tt, rec, TX, TY, ws, keys, vals, ranges, d_overflow, n_cu, s);
     // 2. emission (with the scan downsweep) into the buffer that the last pass does not write to

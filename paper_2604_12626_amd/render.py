@@ -70,8 +70,7 @@ class Renderer:
         f.num = self._buf("num", (1,), torch.int64)
         f.overflow = self._buf("ovf", (1,), torch.int32)
         ws = B.bin_sort_workspace(n_inst, self.capacity, n_views, self.params)
-        # zeroed once; gs_bin_sort leaves its arrival counters at zero
-        f.sort_ws = self._buf("sort_ws", ((ws + 255) // 256 * 256,), torch.uint8, zero=True)
+        f.sort_ws = self._buf("sort_ws", ((ws + 255) // 256 * 256,), torch.uint8)
         # zeroed once; gs_composite leaves its queue counters at zero
         f.comp_ws = self._buf("comp_ws", (B.composite_workspace(n_views, self.params),), torch.uint8, zero=True)
         hw = (n_views, self.H, self.W)

@@ -145,12 +145,10 @@ def _bin_sort_case(dev, B, rec, tt_o, keys_o, vals_o, ranges_o, K, V, W, H, prm,
     ranges = torch.full((V * T, 2), 7, dtype=torch.int32, device=dev)
     num = torch.zeros(1, dtype=torch.int64, device=dev)
     ovf = torch.full((1,), 5, dtype=torch.int32, device=dev)
-    ws = torch.zeros(B.bin_sort_workspace(len(rec), cap, V, prm), dtype=torch.uint8, device=dev)
+    ws = torch.empty(B.bin_sort_workspace(len(rec), cap, V, prm), dtype=torch.uint8, device=dev)
     B.bin_sort(tt, r, V, prm, ws, keys, vals, ranges, num, ovf)
     torch.cuda.synchronize()
     assert int(num.item()) == K and int(ovf.item()) == expect_ovf
-    # the arrival counters at the head of the workspace are back at zero
-    assert int(ws[:256].to(torch.int32).sum().item()) == 0
     if expect_ovf:
         assert np.all(ranges.cpu().numpy() == 0)
         return
@@ -187,7 +185,7 @@ def test_composite_parity(dev, orc, name, counts, W, H, rmed, aniso):
     ranges = torch.zeros((V * T, 2), dtype=torch.int32, device=dev)
     num = torch.zeros(1, dtype=torch.int64, device=dev)
     ovf = torch.zeros(1, dtype=torch.int32, device=dev)
-    ws = torch.zeros(B.bin_sort_workspace(len(rec), K + 16, V, prm), dtype=torch.uint8, device=dev)
+    ws = torch.empty(B.bin_sort_workspace(len(rec), K + 16, V, prm), dtype=torch.uint8, device=dev)
     B.bin_sort(tt, r, V, prm, ws, keys, vals, ranges, num, ovf)
     rgb = torch.zeros(V, H, W, 3, device=dev)
     depth = torch.zeros(V, H, W, device=dev)
