@@ -648,12 +648,13 @@ __global__ void __launch_bounds__(256) bucket_colscan_kernel(uint32_t *cnt /*[n_
 }
 
 // exclusive scan of the tile totals (one workgroup): each tile's first key,
-// and the ranges ([first, end) for tiles with keys, [0, 0) otherwise)
+// and the ranges ([first, end) for tiles with keys, [0, 0) otherwise, and
+// all [0, 0) after an overflow)
 __global__ void __launch_bounds__(1024) bucket_tilescan_kernel(const uint32_t *tile_count, int64_t n_tiles,
                                                                uint32_t *tile_start, uint32_t *ranges,
                                                                const int32_t *d_overflow) {
     __shared__ uint32_t s_w[16];
-    if (*d_overflow) return;  // ranges stay cleared
+    const bool ovf = *d_overflow != 0;  // then every range is [0, 0)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t per = (n_tiles + 1023) / 1024;
     const int64_t t0 = (int64_t)tid * per, t1 = (t0 + per < n_tiles) ? t0 + per : n_tiles;
@@ -672,8 +673,8 @@ __global__ void __launch_bounds__(1024) bucket_tilescan_kernel(const uint32_t *t
     for (int64_t t = t0; t < t1; ++t) {
         const uint32_t c = tile_count[t];
         tile_start[t] = run;
-        ranges[2 * t] = c ? run : 0u;
-        ranges[2 * t + 1] = c ? run + c : 0u;
+        ranges[2 * t] = (c && !ovf) ? run : 0u;
+        ranges[2 * t + 1] = (c && !ovf) ? run + c : 0u;
         run += c;
     }
 }
@@ -851,7 +852,7 @@ static hipError_t run_bucket_sort(const SortPlan &P, const uint32_t *tt, const f
                                   char *ws, uint64_t *keys, uint32_t *vals, uint32_t *ranges,
                                   const int32_t *d_overflow, int n_cu, hipStream_t s) {
     hipError_t e;
-    if (P.n <= 0) return hipSuccess;  // no keys: ranges are cleared
+    if (P.n <= 0) return launch_fill_u32(ranges, 0u, 2 * P.n_tiles_total, s);  // no keys
     EmitArgs A = {};
     A.tt = tt;
     A.part = reinterpret_cast<const uint64_t *>(ws + P.off_part);
@@ -908,12 +909,18 @@ hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec
     uint32_t *status = reinterpret_cast<uint32_t *>(ws + P.off_status);
     const size_t clear_words = (P.off_status - P.off_hist) / 4 + (size_t)P.passes * P.sort_parts * kBins;
     uint32_t *tcnt = reinterpret_cast<uint32_t *>(ws + P.off_tcnt);
-    const size_t tcnt_words = P.use_bucket ? (size_t)P.bucket_blocks * (size_t)P.n_tiles_total : 0;
+    const size_t tcnt_words = (size_t)P.bucket_blocks * (size_t)P.n_tiles_total;
 
-    if ((e = launch_kernel(clear2_kernel, dim3(1024), dim3(256), s, P.use_bucket ? tcnt : hist,
-                           (int64_t)(P.use_bucket ? tcnt_words : clear_words), ranges, 2 * P.n_tiles_total,
-                           (int64_t)1024 * 256)) != hipSuccess)
-        return e;
+    // clears: the onesweep state and the ranges (onesweep), or the global
+    // tile counters when they do not fit in LDS (bucket); the bucket path
+    // with LDS counters writes every counter and every range itself
+    if (!P.use_bucket) {
+        if ((e = launch_kernel(clear2_kernel, dim3(1024), dim3(256), s, hist, (int64_t)clear_words, ranges,
+                               2 * P.n_tiles_total, (int64_t)1024 * 256)) != hipSuccess)
+            return e;
+    } else if (P.n_tiles_total > kLdsTiles) {
+        if ((e = launch_fill_u32(tcnt, 0u, (int64_t)tcnt_words, s)) != hipSuccess) return e;
+    }
     // 1. scan
     if (P.n > 0) {
         if ((e = launch_kernel(scan_reduce_kernel, dim3((unsigned)P.scan_blocks), dim3(kScanBlock), s, tt, P.n,
