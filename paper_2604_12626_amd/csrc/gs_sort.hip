@@ -734,116 +734,13 @@ __device__ __forceinline__ void bitonic_sort(Ptr s, uint32_t n2, uint32_t lim) {
     }
 }
 
-// Register-blocked bitonic sort of up to E * THREADS entries: thread t holds
-// entries t * E .. t * E + E - 1 in x[].  Steps whose partner lies in the same
-// thread compare registers; the others exchange through LDS (laid out
-// q * THREADS + t, so a wave's accesses fall in distinct banks), with only a
-// wave barrier when the partner thread is in the same wave.
-template <int E, int J>
-__device__ __forceinline__ void reg_steps(uint64_t (&x)[E], uint32_t k) {
-    if constexpr (J >= 1) {
-        if ((uint32_t)J <= (k >> 1)) {
-            const bool reflect = ((uint32_t)J == (k >> 1));
-#pragma unroll
-            for (int q = 0; q < E; ++q) {
-                if ((q & J) == 0) {
-                    const int p = reflect ? (q ^ (2 * J - 1)) : (q ^ J);
-                    const uint64_t a = x[q], b = x[p];
-                    x[q] = a < b ? a : b;
-                    x[p] = a < b ? b : a;
-                }
-            }
-        }
-        reg_steps<E, J / 2>(x, k);
-    }
-}
-
-template <int THREADS>
-__device__ __forceinline__ void exchange_sync(bool block_wide) {
-    if (block_wide) {
-        __syncthreads();
-    } else {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
-}
-
-template <int E, int THREADS>
-__device__ __forceinline__ void reg_bitonic(uint64_t (&x)[E], uint64_t *s, uint32_t n2, bool active) {
-    const uint32_t t = threadIdx.x;
-    for (uint32_t k = 2; k <= n2; k <<= 1) {
-        for (uint32_t j = k >> 1; j >= (uint32_t)E; j >>= 1) {
-            const bool reflect = (j == (k >> 1));
-            const uint32_t m = reflect ? (k / E - 1) : (j / E);  // partner thread = t ^ m
-            const uint32_t hb = reflect ? (k / (2 * E)) : (j / E);
-            const bool block_wide = m >= 64u;
-            if (active) {
-#pragma unroll
-                for (int q = 0; q < E; ++q) s[q * THREADS + t] = x[q];
-            }
-            exchange_sync<THREADS>(block_wide);
-            if (active) {
-                const uint32_t pt = t ^ m;
-                const bool lower = (t & hb) == 0u;
-#pragma unroll
-                for (int q = 0; q < E; ++q) {
-                    const uint64_t y = s[(reflect ? (E - 1 - q) : q) * THREADS + pt];
-                    const uint64_t a = x[q];
-                    x[q] = lower ? (a < y ? a : y) : (a < y ? y : a);
-                }
-            }
-            exchange_sync<THREADS>(block_wide);
-        }
-        reg_steps<E, E / 2>(x, k);
-    }
-}
-
-constexpr int kRegSortE = 16, kRegSortThreads = 128;  // buckets up to 2048 entries
-
-// one workgroup of 128 threads per tile (grid-stride) for buckets of
-// 1..2048 entries
-__global__ void __launch_bounds__(kRegSortThreads) tile_sort_reg_kernel(uint64_t *bucket, const uint32_t *ranges,
-                                                                       int64_t n_tiles, int64_t n_blocks,
-                                                                       uint64_t *keys, uint32_t *vals,
-                                                                       const int32_t *d_overflow) {
-    constexpr int E = kRegSortE, THREADS = kRegSortThreads;
-    __shared__ uint64_t s[E * THREADS];
-    if (*d_overflow) return;
-    const uint32_t t = threadIdx.x;
-    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += n_blocks) {  // uniform per workgroup
-        const uint32_t b = ranges[2 * tile], L = ranges[2 * tile + 1] - b;
-        if (L == 0u || L > (uint32_t)(E * THREADS)) continue;
-        uint32_t n2 = E;
-        while (n2 < L) n2 <<= 1;
-        const bool active = t < n2 / E;
-        uint64_t x[E];
-#pragma unroll
-        for (int q = 0; q < E; ++q) {
-            const uint32_t e = t * E + q;
-            x[q] = (active && e < L) ? bucket[b + e] : ~0ull;
-        }
-        reg_bitonic<E, THREADS>(x, s, n2, active);
-        const uint64_t thi = (uint64_t)tile << 32;
-        if (active) {
-#pragma unroll
-            for (int q = 0; q < E; ++q) {
-                const uint32_t e = t * E + q;
-                if (e < L) {
-                    keys[b + e] = thi | (x[q] >> 32);
-                    vals[b + e] = (uint32_t)x[q];
-                }
-            }
-        }
-    }
-}
-
-constexpr int kSmallSortCap = 2048;  // buckets up to this size are sorted by tile_sort_reg_kernel
+constexpr int kSmallSortBlock = 256, kSmallSortCap = 2048;  // most buckets: many small workgroups per CU
 constexpr int kTileSortBlock = 512, kTileSortCap = 8192;    // longer buckets in LDS; beyond, in place in HBM
 
-// One workgroup per tile (grid-stride) for buckets longer than
-// kSmallSortCap: sort the bucket (in LDS up to CAP entries, in place in HBM
-// beyond) and write the keys (tile << 32 | depth bits) and values (instance).
+// One workgroup per tile (grid-stride): sort the bucket and write the keys
+// (tile << 32 | depth bits) and values (instance).  Launched twice: small
+// workgroups for buckets of 1..SMALL_MAX entries (many resident per CU),
+// then large ones for the rest.
 template <int THREADS, int CAP, bool SMALL>
 __global__ void __launch_bounds__(THREADS) tile_sort_kernel(uint64_t *bucket, const uint32_t *ranges,
                                                             int64_t n_tiles, int64_t n_blocks, uint64_t *keys,
@@ -985,10 +882,11 @@ static hipError_t run_bucket_sort(const SortPlan &P, const uint32_t *tt, const f
     if ((e = launch_kernel(emit_kernel<kEmitScatterTiles>, dim3((unsigned)P.bucket_blocks), dim3(kEmitBlock), s,
                            A)) != hipSuccess)
         return e;
-    int64_t sg = 16 * (int64_t)n_cu;
+    int64_t sg = 8 * (int64_t)n_cu;
     if (sg > P.n_tiles_total) sg = P.n_tiles_total;
-    if ((e = launch_kernel(tile_sort_reg_kernel, dim3((unsigned)sg), dim3(kRegSortThreads), s, A.bucket,
-                           (const uint32_t *)ranges, P.n_tiles_total, sg, keys, vals, d_overflow)) != hipSuccess)
+    if ((e = launch_kernel(tile_sort_kernel<kSmallSortBlock, kSmallSortCap, true>, dim3((unsigned)sg),
+                           dim3(kSmallSortBlock), s, A.bucket, (const uint32_t *)ranges, P.n_tiles_total, sg, keys,
+                           vals, d_overflow)) != hipSuccess)
         return e;
     int64_t lg = (int64_t)n_cu;
     if (lg > P.n_tiles_total) lg = P.n_tiles_total;
