@@ -367,7 +367,32 @@ __device__ __forceinline__ bool entry_reaches_box(float u, float v, float A, flo
     const float inv = 2.0f * t2 / detq;
     const float ex = sqrtf(inv * C) * 1.01f + 0.02f;
     const float ey = sqrtf(inv * A) * 1.01f + 0.02f;
-    return u + ex >= bx0 && u - ex <= bx1 && v + ey >= by0 && v - ey <= by1;
+    if (!(u + ex >= bx0 && u - ex <= bx1 && v + ey >= by0 && v - ey <= by1)) return false;
+    // The box meets the ellipse's bounding box; test the ellipse itself: the
+    // minimum over the box of 1/2 d^T Q d (centre inside: 0; else on one of
+    // the four edges, where it is a clamped one-dimensional minimum) against
+    // the same widened threshold t2, on a box widened by the same 0.02 px.
+    const float x0 = bx0 - 0.02f, x1 = bx1 + 0.02f, y0 = by0 - 0.02f, y1 = by1 + 0.02f;
+    if (u >= x0 && u <= x1 && v >= y0 && v <= y1) return true;
+    const float lx0 = x0 - u, lx1 = x1 - u, ly0 = y0 - v, ly1 = y1 - v;
+    float qmin = INFINITY;
+    {  // vertical edges: dx fixed, best dy = -B dx / C
+        const float dx[2] = {lx0, lx1};
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const float dy = fminf(fmaxf(-B * dx[k] / C, ly0), ly1);
+            qmin = fminf(qmin, 0.5f * (A * dx[k] * dx[k] + C * dy * dy) + B * dx[k] * dy);
+        }
+    }
+    {  // horizontal edges: dy fixed, best dx = -B dy / A
+        const float dy[2] = {ly0, ly1};
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const float dx = fminf(fmaxf(-B * dy[k] / A, lx0), lx1);
+            qmin = fminf(qmin, 0.5f * (A * dx * dx + C * dy[k] * dy[k]) + B * dx * dy[k]);
+        }
+    }
+    return !(qmin > t2);
 }
 
 // 2^x with the hardware instruction (v_exp_f32); the forward and the backward
