@@ -145,7 +145,7 @@ void gs_default_params(gs_params *p, int32_t width, int32_t height);
  *  sort_lookback: predecessor partitions read per round trip of the onesweep
  *    look-back (16, 32 or 64, default 16).
  *  sort_algorithm: 0 (default) sorts by tile buckets when the launch has at
- *    most 65536 tiles over all views (count per tile, scatter into buckets,
+ *    most 4096 tiles over all views (count per tile, scatter into buckets,
  *    sort each bucket by (depth, instance) in LDS) and with the onesweep
  *    radix sort otherwise; 1 always uses the onesweep radix sort.  Both give
  *    the same keys, values and ranges.

@@ -30,7 +30,7 @@ constexpr int kMinSortItems = 8;                    // partitions of 4096 or 819
 constexpr int kMinSortPart = kSortBlock * kMinSortItems;
 constexpr int kEmitGrid = 1024;  // emission workgroups at most (grid-stride over scan tiles beyond)
 constexpr int kBucketGrid = 256;  // emission workgroups of the bucket path (rows of the tile counters)
-constexpr int64_t kBucketMaxTiles = 1 << 16;  // the bucket path serves up to this many tiles (all views)
+constexpr int64_t kBucketMaxTiles = 4096;  // the bucket path serves up to this many tiles (all views)
 constexpr int kRadixBits = 8;
 constexpr int kBins = 1 << kRadixBits;
 constexpr int kMaxPasses = 8;
@@ -179,8 +179,9 @@ constexpr int kEmitBlock = 1024;
 constexpr int kEmitItems = kScanTile / kEmitBlock;  // 4 instances per thread
 constexpr int kEmitWaves = kEmitBlock / 64;
 constexpr int kWaveInst = 64 * kEmitItems;          // 256 instances per wave
-constexpr int kLdsTiles = 4096;                     // tile counters kept in LDS up to this many tiles
+constexpr int kLdsTiles = 4096;                     // LDS words for tile counters / digit histograms
 static_assert(kLdsTiles >= kMaxPasses * kHistStride, "the LDS buffer also holds the digit histograms");
+static_assert(kBucketMaxTiles <= kLdsTiles, "bucket tile counters live in LDS");
 
 enum EmitMode { kEmitSortKeys = 0, kEmitCountTiles = 1, kEmitScatterTiles = 2 };
 
@@ -227,13 +228,13 @@ __global__ void __launch_bounds__(kEmitBlock) emit_kernel(const EmitArgs A) {
     if (MODE == kEmitSortKeys)
         for (int k = threadIdx.x; k < kMaxPasses * kHistStride; k += kEmitBlock) s_aux[k] = 0u;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    // counters are tile-major: tile t's counts of all workgroups are one row
+    // tile counters in HBM are tile-major: tile t's counts of all workgroups are one row
     uint32_t *my_cnt = A.tile_cnt + blockIdx.x;
     const int64_t cs = A.n_blocks;  // row stride
-    const bool lds_tiles = A.n_tiles <= kLdsTiles;
-    if (MODE == kEmitCountTiles && lds_tiles)
+    // count / scatter: the tile counters live in LDS (at most kLdsTiles tiles)
+    if (MODE == kEmitCountTiles)
         for (int k = threadIdx.x; k < A.n_tiles; k += kEmitBlock) s_aux[k] = 0u;
-    if (MODE == kEmitScatterTiles && lds_tiles)  // this workgroup's first slot in every bucket
+    if (MODE == kEmitScatterTiles)  // this workgroup's first slot in every bucket
         for (int k = threadIdx.x; k < A.n_tiles; k += kEmitBlock) s_aux[k] = A.tile_start[k] + my_cnt[k * cs];
     for (int64_t tile = blockIdx.x; tile < A.n_tiles_scan; tile += A.n_blocks) {  // uniform per workgroup
         const int64_t base = tile * kScanTile + (int64_t)threadIdx.x * kEmitItems;
@@ -346,11 +347,9 @@ __global__ void __launch_bounds__(kEmitBlock) emit_kernel(const EmitArgs A) {
                     A.keys[k] = ((uint64_t)tg << 32) | (uint64_t)s_a2[wave][lo];
                     A.vals[k] = s_a5[wave][lo];
                 } else if (MODE == kEmitCountTiles) {
-                    if (lds_tiles) atomicAdd(s_aux + tg, 1u);
-                    else atomicAdd(my_cnt + (size_t)tg * cs, 1u);
+                    atomicAdd(s_aux + tg, 1u);
                 } else {
-                    const uint32_t slot =
-                        lds_tiles ? atomicAdd(s_aux + tg, 1u) : A.tile_start[tg] + atomicAdd(my_cnt + (size_t)tg * cs, 1u);
+                    const uint32_t slot = atomicAdd(s_aux + tg, 1u);
                     A.bucket[slot] = ((uint64_t)s_a2[wave][lo] << 32) | (uint64_t)s_a5[wave][lo];
                 }
             }
@@ -362,7 +361,7 @@ __global__ void __launch_bounds__(kEmitBlock) emit_kernel(const EmitArgs A) {
         uint32_t *row = A.rows + (size_t)blockIdx.x * passes * kHistStride;
         for (int k = threadIdx.x; k < passes * kHistStride; k += kEmitBlock) row[k] = s_aux[k];
     }
-    if (MODE == kEmitCountTiles && lds_tiles) {
+    if (MODE == kEmitCountTiles) {
         __syncthreads();
         for (int k = threadIdx.x; k < A.n_tiles; k += kEmitBlock) my_cnt[k * cs] = s_aux[k];
     }
@@ -908,18 +907,13 @@ hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec
     uint32_t *ticket = reinterpret_cast<uint32_t *>(ws + P.off_ticket);
     uint32_t *status = reinterpret_cast<uint32_t *>(ws + P.off_status);
     const size_t clear_words = (P.off_status - P.off_hist) / 4 + (size_t)P.passes * P.sort_parts * kBins;
-    uint32_t *tcnt = reinterpret_cast<uint32_t *>(ws + P.off_tcnt);
-    const size_t tcnt_words = (size_t)P.bucket_blocks * (size_t)P.n_tiles_total;
 
-    // clears: the onesweep state and the ranges (onesweep), or the global
-    // tile counters when they do not fit in LDS (bucket); the bucket path
-    // with LDS counters writes every counter and every range itself
+    // clears the onesweep state and the ranges; the bucket path writes every
+    // counter and every range itself
     if (!P.use_bucket) {
         if ((e = launch_kernel(clear2_kernel, dim3(1024), dim3(256), s, hist, (int64_t)clear_words, ranges,
                                2 * P.n_tiles_total, (int64_t)1024 * 256)) != hipSuccess)
             return e;
-    } else if (P.n_tiles_total > kLdsTiles) {
-        if ((e = launch_fill_u32(tcnt, 0u, (int64_t)tcnt_words, s)) != hipSuccess) return e;
     }
     // 1. scan
     if (P.n > 0) {
