@@ -60,8 +60,7 @@ __global__ void __launch_bounds__(256) project_kernel(const ProjectArgs a) {
         return;
     }
 
-    float sh[3 * K];
-    bool have_sh = false;
+    const float *shp = a.seg.sh + (size_t)(3 * K) * i;
     for (int vi = 0; vi < a.nv; ++vi) {
         const int64_t inst = a.base[vi] + i;
         const float *cam = s_cam + vi * kCamStride;
@@ -71,23 +70,6 @@ __global__ void __launch_bounds__(256) project_kernel(const ProjectArgs a) {
             a.tiles_touched[inst] = 0u;
             continue;
         }
-        if (!have_sh) {
-            const float *src = a.seg.sh + (size_t)(3 * K) * i;
-            if ((3 * K) % 4 == 0) {
-#pragma unroll
-                for (int k = 0; k < 3 * K / 4; ++k) {
-                    const float4 t = reinterpret_cast<const float4 *>(src)[k];
-                    sh[4 * k + 0] = t.x;
-                    sh[4 * k + 1] = t.y;
-                    sh[4 * k + 2] = t.z;
-                    sh[4 * k + 3] = t.w;
-                }
-            } else {
-#pragma unroll
-                for (int k = 0; k < 3 * K; ++k) sh[k] = src[k];
-            }
-            have_sh = true;
-        }
         // view direction in world space, from the camera centre to the mean
         float dx = mx - cam[16], dy = my - cam[17], dz = mz - cam[18];
         const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
@@ -96,14 +78,27 @@ __global__ void __launch_bounds__(256) project_kernel(const ProjectArgs a) {
         dz *= inv;
         float Y[K];
         sh_basis<D>(dx, dy, dz, Y);
-        float col[3];
+        // colour straight from the SH rows (16-B loads when the row allows;
+        // later views of the same Gaussian hit the caches), accumulated per
+        // channel in basis order
+        float col[3] = {0.0f, 0.0f, 0.0f};
+        if ((3 * K) % 4 == 0) {
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-            float acc = 0.0f;
+            for (int k4 = 0; k4 < 3 * K / 4; ++k4) {
+                const float4 t = reinterpret_cast<const float4 *>(shp)[k4];
+                const float v4[4] = {t.x, t.y, t.z, t.w};
 #pragma unroll
-            for (int k = 0; k < K; ++k) acc += Y[k] * sh[3 * k + ch];
-            col[ch] = fmaxf(acc + 0.5f, 0.0f);
+                for (int m = 0; m < 4; ++m) {
+                    const int f = 4 * k4 + m;  // coefficient f = 3 k + ch
+                    col[f % 3] += Y[f / 3] * v4[m];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int f = 0; f < 3 * K; ++f) col[f % 3] += Y[f / 3] * shp[f];
         }
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) col[ch] = fmaxf(col[ch] + 0.5f, 0.0f);
         float4 *r = a.rec + 3 * inst;
         r[0] = make_float4(p.u, p.v, p.tz, __int_as_float(p.radius));
         r[1] = make_float4(p.A, p.B, p.C, opac);
