@@ -4,7 +4,8 @@
 // (the cameras are staged in LDS), so a scene drawn by many views is read from
 // HBM once.  Attribute reads are row-per-Gaussian (means 12 B, scales 12 B,
 // quats 16 B, SH 12 (D+1)^2 B contiguous), so a Gaussian culled in every view
-// never pulls its SH rows.
+// never pulls its SH rows (the 32 B of rotation, scales and opacity are read
+// with the mean, to overlap their latency).
 #include "gs_ewa.hpp"
 
 namespace gs {
@@ -30,8 +31,23 @@ __global__ void __launch_bounds__(256) project_kernel(const ProjectArgs a) {
     if (i >= a.seg.n) return;
 
     const float mx = a.seg.means[3 * i + 0], my = a.seg.means[3 * i + 1], mz = a.seg.means[3 * i + 2];
+    // the small attribute rows (rotation, scales, opacity: 32 B) are requested
+    // together with the mean, so their latency overlaps; the SH rows are read
+    // only once the Gaussian is known to land in a view
+    float4 q4 = make_float4(1.0f, 0.0f, 0.0f, 0.0f);
+    float ls[3] = {0.0f, 0.0f, 0.0f};
+    float S[6];
+    if (a.seg.cov6) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) S[k] = a.seg.cov6[6 * i + k];
+    } else {
+        q4 = reinterpret_cast<const float4 *>(a.seg.quats)[i];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) ls[k] = a.seg.log_scales[3 * i + k];
+    }
+    const float opac = a.seg.opacity[i];
     // near-plane test from the mean alone: a Gaussian behind every camera of
-    // the launch never reads its scale, rotation, opacity or SH rows
+    // the launch never reads its SH rows
     bool any_front = false;
     for (int vi = 0; vi < a.nv; ++vi) {
         const float *c = s_cam + vi * kCamStride;
@@ -42,19 +58,13 @@ __global__ void __launch_bounds__(256) project_kernel(const ProjectArgs a) {
         for (int vi = 0; vi < a.nv; ++vi) a.tiles_touched[a.base[vi] + i] = 0u;
         return;
     }
-    float S[6];
-    if (a.seg.cov6) {
-#pragma unroll
-        for (int k = 0; k < 6; ++k) S[k] = a.seg.cov6[6 * i + k];
-    } else {
-        const float4 q = reinterpret_cast<const float4 *>(a.seg.quats)[i];
-        const Rot rot = quat_rot(q.x, q.y, q.z, q.w);
+    if (!a.seg.cov6) {
+        const Rot rot = quat_rot(q4.x, q4.y, q4.z, q4.w);
         float s[3];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) s[k] = expf(a.seg.log_scales[3 * i + k]);
+        for (int k = 0; k < 3; ++k) s[k] = expf(ls[k]);
         cov_from_rot_scale(rot.R, s, S);
     }
-    const float opac = a.seg.opacity[i];
     if (!isfinite(opac)) {  // non-finite input is culled, never rendered
         for (int vi = 0; vi < a.nv; ++vi) a.tiles_touched[a.base[vi] + i] = 0u;
         return;
