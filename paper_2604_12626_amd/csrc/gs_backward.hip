@@ -107,85 +107,69 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
         }
         __builtin_amdgcn_wave_barrier();
         const int n = __popcll(bal);
-        // pad to a multiple of 4 with entries that never contribute (list
-        // position past every pixel's last composited entry)
-        if (lane < ((4 - (n & 3)) & 3)) {
-            e0s[n + lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            e1s[n + lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            e2s[n + lane] = make_float4(0.0f, 0.0f, 0.0f, __uint_as_float(0xFFFFFFFFu));
-            qs[n + lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        }
-        __builtin_amdgcn_wave_barrier();
-        // back to front, four entries per step: their per-pixel terms first
-        // (independent work interleaves), then the wave sums and atomics
-        for (int q0 = ((n + 3) & ~3) - 1; q0 >= 0; q0 -= 4) {
-            float gsum[4][kG2D];
-            bool any[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int q = q0 - u;
-                const float4 e0 = e0s[q], e1 = e1s[q], e2 = e2s[q];
-                const uint32_t pos = __float_as_uint(e2.w);  // list position (< maxlast <= list length)
-                float gu = 0.f, gv = 0.f, gA = 0.f, gB = 0.f, gC = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gb = 0.f,
-                      gz = 0.f;
-                bool contrib = false;
-                if (pos < last) {
-                    const float dx = fx - e0.x, dy = fy - e0.y;
-                    const float p2 = entry_power2(e0.z, e0.w, e1.x, dx, dy);
-                    const float G = fast_exp2(p2);
-                    const float oG = e1.y * G;
-                    const float al = fminf(a.alpha_max, oG);
-                    if (!(al < a.alpha_min)) {
-                        contrib = true;
-                        const float one_m = 1.0f - al;
-                        T = T / one_m;  // transmittance in front of this entry
-                        const float w = al * T;
-                        gr = dR * w;
-                        gg = dG * w;
-                        gb = dB * w;
-                        gz = dD * w;
-                        const float dal = T * (dR * (e1.w - Sr) + dG * (e2.x - Sg) + dB * (e2.y - Sb) +
-                                               dD * (e1.z - Sd)) +
-                                          dA * Tfin / one_m;
-                        if (!(oG > a.alpha_max)) {
-                            const float4 cq = qs[q];
-                            go = dal * G;
-                            // dL/dP with P the natural-log exponent (dG/dP = G)
-                            const float dP = dal * e1.y * G;
-                            gu = dP * (cq.x * dx + cq.y * dy);
-                            gv = dP * (cq.y * dx + cq.z * dy);
-                            gA = -0.5f * dP * dx * dx;
-                            gB = -dP * dx * dy;
-                            gC = -0.5f * dP * dy * dy;
-                        }
-                        Sr = al * e1.w + one_m * Sr;
-                        Sg = al * e2.x + one_m * Sg;
-                        Sb = al * e2.y + one_m * Sb;
-                        Sd = al * e1.z + one_m * Sd;
+        for (int q = n - 1; q >= 0; --q) {
+            const float4 e0 = e0s[q], e1 = e1s[q], e2 = e2s[q];
+            const uint32_t pos = __float_as_uint(e2.w);  // list position (< maxlast <= list length)
+            float gu = 0.f, gv = 0.f, gA = 0.f, gB = 0.f, gC = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gb = 0.f, gz = 0.f;
+            bool contrib = false;
+            if (pos < last) {
+                const float dx = fx - e0.x, dy = fy - e0.y;
+                const float p2 = entry_power2(e0.z, e0.w, e1.x, dx, dy);
+                const float G = fast_exp2(p2);
+                const float oG = e1.y * G;
+                const float al = fminf(a.alpha_max, oG);
+                if (!(al < a.alpha_min)) {
+                    contrib = true;
+                    const float one_m = 1.0f - al;
+                    T = T / one_m;  // transmittance in front of this entry
+                    const float w = al * T;
+                    gr = dR * w;
+                    gg = dG * w;
+                    gb = dB * w;
+                    gz = dD * w;
+                    const float dal = T * (dR * (e1.w - Sr) + dG * (e2.x - Sg) + dB * (e2.y - Sb) +
+                                           dD * (e1.z - Sd)) +
+                                      dA * Tfin / one_m;
+                    if (!(oG > a.alpha_max)) {
+                        const float4 cq = qs[q];
+                        go = dal * G;
+                        // dL/dP with P the natural-log exponent (dG/dP = G)
+                        const float dP = dal * e1.y * G;
+                        gu = dP * (cq.x * dx + cq.y * dy);
+                        gv = dP * (cq.y * dx + cq.z * dy);
+                        gA = -0.5f * dP * dx * dx;
+                        gB = -dP * dx * dy;
+                        gC = -0.5f * dP * dy * dy;
                     }
+                    Sr = al * e1.w + one_m * Sr;
+                    Sg = al * e2.x + one_m * Sg;
+                    Sb = al * e2.y + one_m * Sb;
+                    Sd = al * e1.z + one_m * Sd;
                 }
-                any[u] = __ballot(contrib) != 0ull;
-                gsum[u][kGU] = gu;
-                gsum[u][kGV] = gv;
-                gsum[u][kGA] = gA;
-                gsum[u][kGB] = gB;
-                gsum[u][kGC] = gC;
-                gsum[u][kGO] = go;
-                gsum[u][kGR] = gr;
-                gsum[u][kGG] = gg;
-                gsum[u][kGBl] = gb;
-                gsum[u][kGZ] = gz;
             }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (!any[u]) continue;
-#pragma unroll
-                for (int k = 0; k < kG2D; ++k) gsum[u][k] = wave_sum_to_last(gsum[u][k]);
-                if (lane == 63) {
-                    float *dst = a.g2d + (size_t)__float_as_uint(e2s[q0 - u].z) * kG2D;
-#pragma unroll
-                    for (int k = 0; k < kG2D; ++k) atomicAdd(dst + k, gsum[u][k]);
-                }
+            if (__ballot(contrib) == 0ull) continue;
+            gu = wave_sum_to_last(gu);
+            gv = wave_sum_to_last(gv);
+            gA = wave_sum_to_last(gA);
+            gB = wave_sum_to_last(gB);
+            gC = wave_sum_to_last(gC);
+            go = wave_sum_to_last(go);
+            gr = wave_sum_to_last(gr);
+            gg = wave_sum_to_last(gg);
+            gb = wave_sum_to_last(gb);
+            gz = wave_sum_to_last(gz);
+            if (lane == 63) {
+                float *dst = a.g2d + (size_t)__float_as_uint(e2.z) * kG2D;
+                atomicAdd(dst + kGU, gu);
+                atomicAdd(dst + kGV, gv);
+                atomicAdd(dst + kGA, gA);
+                atomicAdd(dst + kGB, gB);
+                atomicAdd(dst + kGC, gC);
+                atomicAdd(dst + kGO, go);
+                atomicAdd(dst + kGR, gr);
+                atomicAdd(dst + kGG, gg);
+                atomicAdd(dst + kGBl, gb);
+                atomicAdd(dst + kGZ, gz);
             }
         }
         __builtin_amdgcn_wave_barrier();
