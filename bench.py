@@ -10,7 +10,7 @@ synchronisation and inputs resident in HBM.  Further lines of the metric
 "extras".
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras]
-                       [--no-cpu-baseline] [--profile]
+                       [--no-cpu-baseline] [--profile] [--profile-fwd-bwd]
 Prints one JSON line.
 """
 import argparse
@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile", action="store_true", help="headline workload only, for rocprofv3 runs")
     ap.add_argument("--copy-calib", action="store_true", help="also run a 512 MiB device copy (counter scale)")
+    ap.add_argument("--profile-fwd-bwd", action="store_true",
+                    help="forward + backward of the 256x256 500k-Gaussian view only, for rocprofv3 runs")
     return ap.parse_args()
 
 
@@ -343,6 +345,11 @@ def main():
     from paper_2604_12626_amd import binding
     binding.load()
     dev = torch.device("cuda:0")
+    if args.profile_fwd_bwd:
+        log("fwd+bwd only: 256x256, 500k Gaussians")
+        ms = bench_fwd_bwd(args, dev, args.steps)
+        print(json.dumps({"fwd_bwd_256x256_500k_ms": ms, "steps": args.steps, "warmup": args.warmup}), flush=True)
+        return
     if args.copy_calib:
         log("copy calibration: 512 MiB x 3")
         copy_calibration(dev)
