@@ -678,57 +678,157 @@ __global__ void __launch_bounds__(1024) bucket_tilescan_kernel(const uint32_t *t
     }
 }
 
-// Ascending bitonic sort of s[0, n2) (n2 a power of two) by a workgroup of
-// THREADS threads; each merge starts with the reflected compare (i, block end
-// - 1 - i), so every compare-exchange is ascending and padding at the end
-// stays there.  In HBM (IN_LDS false) entries at or beyond `lim` are virtual
-// +infinity and are never touched (in-place sort of an unpadded segment).
-// In LDS, a step with j <= 64 pairs elements inside the 128-element block
-// that one wave's 64 consecutive pair indices cover, so consecutive such
-// steps need only the wave's own (in-order) LDS accesses; a workgroup
-// barrier separates the others.  In HBM every step ends with a barrier.
-template <bool IN_LDS, typename Ptr>
-__device__ __forceinline__ void compare_exchange(Ptr s, uint32_t i, uint32_t p, uint32_t lim) {
-    if (!IN_LDS && p >= lim) return;
+// Ascending bitonic sort in place in HBM of s[0, n2) (n2 a power of two) by
+// a workgroup of THREADS threads, for buckets too long for LDS.  Each merge
+// starts with the reflected compare (i, block end - 1 - i), so every
+// compare-exchange is ascending and entries at or beyond `lim` act as
+// +infinity without being stored; every step ends with a workgroup barrier.
+__device__ __forceinline__ void compare_exchange_hbm(uint64_t *s, uint32_t i, uint32_t p, uint32_t lim) {
+    if (p >= lim) return;
     const uint64_t a = s[i], b = s[p];
     const bool sw = a > b;
     s[i] = sw ? b : a;
     s[p] = sw ? a : b;
 }
 
-template <bool IN_LDS>
-__device__ __forceinline__ void bitonic_step_sync(uint32_t j, uint32_t next_j, bool last) {
-    if (!IN_LDS || j > 64 || next_j > 64 || last) {
-        __syncthreads();
-    } else {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
-}
-
-template <int THREADS, bool IN_LDS, typename Ptr>
-__device__ __forceinline__ void bitonic_sort(Ptr s, uint32_t n2, uint32_t lim) {
+template <int THREADS>
+__device__ __forceinline__ void bitonic_sort_hbm(uint64_t *s, uint32_t n2, uint32_t lim) {
     const uint32_t tid = threadIdx.x, half = n2 >> 1;
     for (uint32_t lk = 1; (1u << lk) <= n2; ++lk) {
         const uint32_t k = 1u << lk;
-        // reflected step (j = k / 2)
         {
             const uint32_t lj = lk - 1, j = k >> 1;
             for (uint32_t t = tid; t < half; t += THREADS) {
                 const uint32_t base = (t >> lj) << lk, r = t & (j - 1);
-                compare_exchange<IN_LDS>(s, base + r, base + (k - 1 - r), lim);
+                compare_exchange_hbm(s, base + r, base + (k - 1 - r), lim);
             }
-            bitonic_step_sync<IN_LDS>(j, j > 1 ? (j >> 1) : (k << 1) >> 1, j == 1 && k == n2);
+            __syncthreads();
         }
-        // half-cleaners (j = k / 4 .. 1)
         for (int lj = (int)lk - 2; lj >= 0; --lj) {
             const uint32_t j = 1u << lj;
             for (uint32_t t = tid; t < half; t += THREADS) {
                 const uint32_t i = ((t >> lj) << (lj + 1)) + (t & (j - 1));
-                compare_exchange<IN_LDS>(s, i, i + j, lim);
+                compare_exchange_hbm(s, i, i + j, lim);
             }
-            bitonic_step_sync<IN_LDS>(j, j > 1 ? (j >> 1) : k, j == 1 && k == n2);
+            __syncthreads();
+        }
+    }
+}
+
+// Bitonic sort of a bucket in LDS with eight entries per thread and up to
+// three network steps per LDS round trip.  A group is the eight positions
+// base + m * 2^lo (m = 0..7, mask bits lo..lo+2); one pass loads a group into
+// registers, applies the compare-exchanges of the top `b` mask bits (the
+// network's next steps), and stores it back.  Merge k = 2^lk runs its steps
+// bit lk-1 down to bit 3 in passes of up to three bits, then bits 2..0 in one
+// pass over eight consecutive positions.  Directions follow the classic
+// network (descending where bit lk of the position is set, except in the
+// final merge), and they are uniform inside a group because every mask bit
+// lies below lk.  LDS slot i + i/8 keeps the strided passes free of bank
+// conflicts.  A pass whose mask stays below bit 9 only touches the 512
+// positions its wave owns (position bits 9 and up come from the wave index),
+// so two such passes in a row need no workgroup barrier.
+__device__ __forceinline__ uint32_t lds_slot(uint32_t i) { return i + (i >> 3); }
+
+__device__ __forceinline__ void cmp_swap(uint64_t &a, uint64_t &b, bool desc) {
+    const bool sw = (a > b) != desc;
+    const uint64_t lo = sw ? b : a, hi = sw ? a : b;
+    a = lo;
+    b = hi;
+}
+
+// compare-exchanges along mask bits r = 2 .. 3 - B of the register group
+template <int B>
+__device__ __forceinline__ void group_steps(uint64_t (&v)[8], bool desc) {
+#pragma unroll
+    for (int r = 2; r > 2 - B; --r) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+            if (!(m & (1 << r))) cmp_swap(v[m], v[m | (1 << r)], desc);
+    }
+}
+
+__device__ __forceinline__ void lds_wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Sorts the L entries at in[0, L) (n2 = 2^ln >= 8 and >= L; s holds at least
+// lds_slot(n2) entries) and writes key (thi | depth bits) and value
+// (instance) of sorted entry p to keys[p], vals[p].
+template <int THREADS>
+__device__ __forceinline__ void sort_bucket_lds(uint64_t *s, const uint64_t *in, uint32_t L, uint32_t n2, int ln,
+                                                uint64_t thi, uint64_t *keys, uint32_t *vals) {
+    const uint32_t groups = n2 >> 3, tid = threadIdx.x;
+    // merges of 2, 4 and 8 in registers.  Input j = m * groups + g takes
+    // position 8 g + m (any placement is valid; this one reads coalesced).
+    for (uint32_t g = tid; g < groups; g += THREADS) {
+        uint64_t v[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const uint32_t j = (uint32_t)m * groups + g;
+            v[m] = j < L ? in[j] : ~0ull;
+        }
+#pragma unroll
+        for (int lk = 1; lk <= 3; ++lk)
+#pragma unroll
+            for (int lj = lk - 1; lj >= 0; --lj)
+#pragma unroll
+                for (int m = 0; m < 8; ++m)
+                    if (!(m & (1 << lj)))
+                        cmp_swap(v[m], v[m | (1 << lj)], lk < ln && (lk < 3 ? ((m >> lk) & 1) : (g & 1u)));
+        const uint32_t base = g << 3;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            if (ln == 3) {
+                if (base + m < L) {
+                    keys[base + m] = thi | (v[m] >> 32);
+                    vals[base + m] = (uint32_t)v[m];
+                }
+            } else {
+                s[lds_slot(base + m)] = v[m];
+            }
+        }
+    }
+    int top_prev = 2;
+    for (int lk = 4; lk <= ln; ++lk) {
+        const bool fin = lk == ln;
+        for (int hi = lk - 1;;) {
+            // mask bits hi-2 .. hi; compare-exchanges along the top b of them
+            const bool low = hi == 2;
+            const int b = low ? 3 : (hi - 2 < 3 ? hi - 2 : 3), lo = hi - 2;
+            if (hi >= 9 || top_prev >= 9)
+                __syncthreads();
+            else
+                lds_wave_sync();
+            top_prev = hi;
+            for (uint32_t g = tid; g < groups; g += THREADS) {
+                const uint32_t base = ((g >> lo) << (lo + 3)) | (g & ((1u << lo) - 1u));
+                uint64_t v[8];
+#pragma unroll
+                for (int m = 0; m < 8; ++m) v[m] = s[lds_slot(base + ((uint32_t)m << lo))];
+                const bool desc = !fin && ((base >> lk) & 1u);
+                if (b == 1)
+                    group_steps<1>(v, desc);
+                else if (b == 2)
+                    group_steps<2>(v, desc);
+                else
+                    group_steps<3>(v, desc);
+                if (fin && low) {  // eight consecutive sorted entries
+#pragma unroll
+                    for (int m = 0; m < 8; ++m)
+                        if (base + m < L) {
+                            keys[base + m] = thi | (v[m] >> 32);
+                            vals[base + m] = (uint32_t)v[m];
+                        }
+                } else {
+#pragma unroll
+                    for (int m = 0; m < 8; ++m) s[lds_slot(base + ((uint32_t)m << lo))] = v[m];
+                }
+            }
+            if (low) break;
+            hi -= b;
         }
     }
 }
@@ -738,39 +838,32 @@ constexpr int kTileSortBlock = 512, kTileSortCap = 8192;    // longer buckets in
 
 // One workgroup per tile (grid-stride): sort the bucket and write the keys
 // (tile << 32 | depth bits) and values (instance).  Launched twice: small
-// workgroups for buckets of 1..SMALL_MAX entries (many resident per CU),
+// workgroups for buckets of 1..kSmallSortCap entries (many resident per CU),
 // then large ones for the rest.
 template <int THREADS, int CAP, bool SMALL>
 __global__ void __launch_bounds__(THREADS) tile_sort_kernel(uint64_t *bucket, const uint32_t *ranges,
                                                             int64_t n_tiles, int64_t n_blocks, uint64_t *keys,
                                                             uint32_t *vals, const int32_t *d_overflow) {
-    __shared__ uint64_t s[CAP];
+    __shared__ uint64_t s[CAP + CAP / 8];
     if (*d_overflow) return;
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += n_blocks) {  // uniform per workgroup
         const uint32_t b = ranges[2 * tile], L = ranges[2 * tile + 1] - b;
         if (L == 0u || (SMALL ? L > (uint32_t)kSmallSortCap : L <= (uint32_t)kSmallSortCap)) continue;
-        uint32_t n2 = 2;
-        while (n2 < L) n2 <<= 1;
+        uint32_t n2 = 8;
+        int ln = 3;
+        while (n2 < L) n2 <<= 1, ++ln;
         const uint64_t thi = (uint64_t)tile << 32;
         if (L <= (uint32_t)CAP) {
-            for (uint32_t i = threadIdx.x; i < n2; i += THREADS) s[i] = (i < L) ? bucket[b + i] : ~0ull;
-            __syncthreads();
-            bitonic_sort<THREADS, true>(s, n2, n2);
-            for (uint32_t i = threadIdx.x; i < L; i += THREADS) {
-                const uint64_t c = s[i];
-                keys[b + i] = thi | (c >> 32);
-                vals[b + i] = (uint32_t)c;
-            }
-            __syncthreads();  // s is reused by the next tile
+            sort_bucket_lds<THREADS>(s, bucket + b, L, n2, ln, thi, keys + b, vals + b);
         } else {
-            bitonic_sort<THREADS, false>(bucket + b, n2, L);
+            bitonic_sort_hbm<THREADS>(bucket + b, n2, L);
             for (uint32_t i = threadIdx.x; i < L; i += THREADS) {
                 const uint64_t c = bucket[b + i];
                 keys[b + i] = thi | (c >> 32);
                 vals[b + i] = (uint32_t)c;
             }
-            __syncthreads();
         }
+        __syncthreads();  // s and the bucket are reused by the next tile
     }
 }
 
