@@ -259,12 +259,18 @@ __global__ void __launch_bounds__(kEmitBlock) emit_kernel(const EmitArgs A) {
             if (lane >= off) incl += y;
         }
         const uint32_t wave_total = __shfl(incl, 63, 64);
-        if (lane == 0) s_wsum[wave] = wave_total;
-        __syncthreads();
-        uint64_t wave_excl = 0;
-        for (int k = 0; k < wave; ++k) wave_excl += s_wsum[k];
-        const int64_t kw = (int64_t)(A.part[tile] + wave_excl);  // first key of the wave
-        const int64_t room = capacity - kw;
+        // sort keys go to the wave's stretch of the key array (first key kw,
+        // nothing past the capacity); the bucket modes place keys by tile
+        // counters instead and scatter only when the total fits
+        int64_t kw = 0, room = INT64_MAX;
+        if (MODE == kEmitSortKeys) {
+            if (lane == 0) s_wsum[wave] = wave_total;
+            __syncthreads();
+            uint64_t wave_excl = 0;
+            for (int k = 0; k < wave; ++k) wave_excl += s_wsum[k];
+            kw = (int64_t)(A.part[tile] + wave_excl);
+            room = capacity - kw;
+        }
         // live instances of the lane and their place in the wave's list
         uint32_t start[kEmitItems];
         uint32_t live_mask = 0u;
@@ -646,34 +652,43 @@ __global__ void __launch_bounds__(256) bucket_colscan_kernel(uint32_t *cnt /*[n_
     if (lane == 0) tile_count[t] = carry;
 }
 
-// exclusive scan of the tile totals (one workgroup): each tile's first key,
-// and the ranges ([first, end) for tiles with keys, [0, 0) otherwise, and
-// all [0, 0) after an overflow)
+// exclusive scan of the tile totals (one workgroup): the key count and the
+// overflow flag (count above the capacity), each tile's first key, and the
+// ranges ([first, end) for tiles with keys, [0, 0) otherwise, and all [0, 0)
+// after an overflow)
 __global__ void __launch_bounds__(1024) bucket_tilescan_kernel(const uint32_t *tile_count, int64_t n_tiles,
-                                                               uint32_t *tile_start, uint32_t *ranges,
-                                                               const int32_t *d_overflow) {
-    __shared__ uint32_t s_w[16];
-    const bool ovf = *d_overflow != 0;  // then every range is [0, 0)
+                                                               int64_t capacity, uint32_t *tile_start,
+                                                               uint32_t *ranges, int64_t *d_num,
+                                                               int32_t *d_overflow) {
+    __shared__ uint64_t s_w[16];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t per = (n_tiles + 1023) / 1024;
     const int64_t t0 = (int64_t)tid * per, t1 = (t0 + per < n_tiles) ? t0 + per : n_tiles;
-    uint32_t sum = 0u;
+    uint64_t sum = 0u;
     for (int64_t t = t0; t < t1; ++t) sum += tile_count[t];
-    uint32_t incl = sum;
+    uint64_t incl = sum;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t y = __shfl_up(incl, off, 64);
+        const uint64_t y = __shfl_up(incl, off, 64);
         if (lane >= off) incl += y;
     }
     if (lane == 63) s_w[wave] = incl;
     __syncthreads();
-    uint32_t run = incl - sum;
-    for (int k = 0; k < wave; ++k) run += s_w[k];
+    uint64_t run = incl - sum, total = 0u;
+    for (int k = 0; k < 16; ++k) {
+        if (k < wave) run += s_w[k];
+        total += s_w[k];
+    }
+    const bool ovf = total > (uint64_t)capacity;  // then every range is [0, 0)
+    if (tid == 0) {
+        *d_num = (int64_t)total;
+        *d_overflow = ovf ? 1 : 0;
+    }
     for (int64_t t = t0; t < t1; ++t) {
         const uint32_t c = tile_count[t];
-        tile_start[t] = run;
-        ranges[2 * t] = (c && !ovf) ? run : 0u;
-        ranges[2 * t + 1] = (c && !ovf) ? run + c : 0u;
+        tile_start[t] = (uint32_t)run;
+        ranges[2 * t] = (c && !ovf) ? (uint32_t)run : 0u;
+        ranges[2 * t + 1] = (c && !ovf) ? (uint32_t)(run + c) : 0u;
         run += c;
     }
 }
@@ -715,36 +730,43 @@ __device__ __forceinline__ void bitonic_sort_hbm(uint64_t *s, uint32_t n2, uint3
     }
 }
 
-// Bitonic sort of a bucket in LDS with eight entries per thread and up to
-// three network steps per LDS round trip.  A group is the eight positions
-// base + m * 2^lo (m = 0..7, mask bits lo..lo+2); one pass loads a group into
-// registers, applies the compare-exchanges of the top `b` mask bits (the
+// Bitonic sort of a bucket in LDS with E = 2^P entries per thread and up to
+// P network steps per LDS round trip.  A group is the E positions
+// base + m * 2^lo (m < E, mask bits lo .. lo+P-1); one pass loads a group
+// into registers, applies the compare-exchanges of the top `b` mask bits (the
 // network's next steps), and stores it back.  Merge k = 2^lk runs its steps
-// bit lk-1 down to bit 3 in passes of up to three bits, then bits 2..0 in one
-// pass over eight consecutive positions.  Directions follow the classic
-// network (descending where bit lk of the position is set, except in the
-// final merge), and they are uniform inside a group because every mask bit
-// lies below lk.  LDS slot i + i/8 keeps the strided passes free of bank
-// conflicts.  A pass whose mask stays below bit 9 only touches the 512
-// positions its wave owns (position bits 9 and up come from the wave index),
-// so two such passes in a row need no workgroup barrier.
-__device__ __forceinline__ uint32_t lds_slot(uint32_t i) { return i + (i >> 3); }
+// bit lk-1 down to bit P in passes of up to P bits, then bits P-1 .. 0 in one
+// pass over E consecutive positions; merges up to E happen in registers
+// right after the bucket is read.  The network is the classic one (merge lk
+// sorts descending where bit lk of the position is set, except the final
+// merge); instead of a direction per compare-exchange, an entry is held
+// bit-complemented while its merge runs descending, so every compare-exchange
+// is ascending, and entries are complemented or restored only where one
+// merge hands over to the next.  LDS slot i + i / E keeps the strided passes
+// free of bank conflicts.  With several waves on one bucket, a pass whose mask
+// stays below bit 6 + P only touches the 64 E positions its wave owns (higher
+// position bits come from the wave index), so two such passes in a row need
+// no workgroup barrier; a bucket sorted by one wave never needs one.
+template <int P>
+__device__ __forceinline__ uint32_t lds_slot(uint32_t i) {
+    return i + (i >> P);
+}
 
-__device__ __forceinline__ void cmp_swap(uint64_t &a, uint64_t &b, bool desc) {
-    const bool sw = (a > b) != desc;
+__device__ __forceinline__ void cmp_swap_up(uint64_t &a, uint64_t &b) {
+    const bool sw = a > b;
     const uint64_t lo = sw ? b : a, hi = sw ? a : b;
     a = lo;
     b = hi;
 }
 
-// compare-exchanges along mask bits r = 2 .. 3 - B of the register group
-template <int B>
-__device__ __forceinline__ void group_steps(uint64_t (&v)[8], bool desc) {
+// ascending compare-exchanges along mask bits r = P-1 .. P-B of the group
+template <int P, int B>
+__device__ __forceinline__ void group_steps(uint64_t (&v)[1 << P]) {
 #pragma unroll
-    for (int r = 2; r > 2 - B; --r) {
+    for (int r = P - 1; r > P - 1 - B; --r) {
 #pragma unroll
-        for (int m = 0; m < 8; ++m)
-            if (!(m & (1 << r))) cmp_swap(v[m], v[m | (1 << r)], desc);
+        for (int m = 0; m < (1 << P); ++m)
+            if (!(m & (1 << r))) cmp_swap_up(v[m], v[m | (1 << r)]);
     }
 }
 
@@ -754,77 +776,98 @@ __device__ __forceinline__ void lds_wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Sorts the L entries at in[0, L) (n2 = 2^ln >= 8 and >= L; s holds at least
-// lds_slot(n2) entries) and writes key (thi | depth bits) and value
+// all-ones when the entry at a position with bit `j` equal to `bit` is held
+// complemented during merge j of a network of 2^ln entries
+__device__ __forceinline__ uint64_t held_mask(int j, int ln, uint32_t bit) {
+    return (j < ln && bit) ? ~0ull : 0ull;
+}
+
+// Sorts the L entries at in[0, L) (n2 = 2^ln >= max(L, 2^P); s holds at
+// least lds_slot<P>(n2) entries) with NT threads (tid < NT; NT = 64 and
+// ONE_WAVE for a wave on its own) and writes key (thi | depth bits) and value
 // (instance) of sorted entry p to keys[p], vals[p].
-template <int THREADS>
+template <int NT, int P, bool ONE_WAVE>
 __device__ __forceinline__ void sort_bucket_lds(uint64_t *s, const uint64_t *in, uint32_t L, uint32_t n2, int ln,
-                                                uint64_t thi, uint64_t *keys, uint32_t *vals) {
-    const uint32_t groups = n2 >> 3, tid = threadIdx.x;
-    // merges of 2, 4 and 8 in registers.  Input j = m * groups + g takes
-    // position 8 g + m (any placement is valid; this one reads coalesced).
-    for (uint32_t g = tid; g < groups; g += THREADS) {
-        uint64_t v[8];
+                                                uint64_t thi, uint64_t *keys, uint32_t *vals, uint32_t tid) {
+    constexpr int E = 1 << P;
+    const uint32_t groups = n2 >> P;
+    // merges of 2 .. E in registers.  Input j = m * groups + g takes
+    // position E g + m (any placement is valid; this one reads coalesced).
+    for (uint32_t g = tid; g < groups; g += NT) {
+        uint64_t v[E];
 #pragma unroll
-        for (int m = 0; m < 8; ++m) {
+        for (int m = 0; m < E; ++m) {
             const uint32_t j = (uint32_t)m * groups + g;
             v[m] = j < L ? in[j] : ~0ull;
         }
 #pragma unroll
-        for (int lk = 1; lk <= 3; ++lk)
+        for (int lk = 1; lk <= P; ++lk) {
+            // hand over from merge lk-1 to merge lk (bit P of the position is bit 0 of g)
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                const uint32_t cur = lk < P ? ((m >> lk) & 1) : (g & 1u);
+                const uint32_t prev = (m >> (lk - 1)) & 1;
+                v[m] ^= held_mask(lk, ln, cur) ^ (lk > 1 ? held_mask(lk - 1, ln, prev) : 0ull);
+            }
 #pragma unroll
             for (int lj = lk - 1; lj >= 0; --lj)
 #pragma unroll
-                for (int m = 0; m < 8; ++m)
-                    if (!(m & (1 << lj)))
-                        cmp_swap(v[m], v[m | (1 << lj)], lk < ln && (lk < 3 ? ((m >> lk) & 1) : (g & 1u)));
-        const uint32_t base = g << 3;
+                for (int m = 0; m < E; ++m)
+                    if (!(m & (1 << lj))) cmp_swap_up(v[m], v[m | (1 << lj)]);
+        }
+        const uint32_t base = g << P;
+        if (ln == P) {  // merge P was the final one: nothing is held complemented
 #pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            if (ln == 3) {
+            for (int m = 0; m < E; ++m)
                 if (base + m < L) {
                     keys[base + m] = thi | (v[m] >> 32);
                     vals[base + m] = (uint32_t)v[m];
                 }
-            } else {
-                s[lds_slot(base + m)] = v[m];
-            }
+        } else {
+            const uint64_t flip = held_mask(P, ln, g & 1u) ^ held_mask(P + 1, ln, (g >> 1) & 1u);
+#pragma unroll
+            for (int m = 0; m < E; ++m) s[lds_slot<P>(base + m)] = v[m] ^ flip;
         }
     }
-    int top_prev = 2;
-    for (int lk = 4; lk <= ln; ++lk) {
+    int top_prev = P - 1;
+    for (int lk = P + 1; lk <= ln; ++lk) {
         const bool fin = lk == ln;
         for (int hi = lk - 1;;) {
-            // mask bits hi-2 .. hi; compare-exchanges along the top b of them
-            const bool low = hi == 2;
-            const int b = low ? 3 : (hi - 2 < 3 ? hi - 2 : 3), lo = hi - 2;
-            if (hi >= 9 || top_prev >= 9)
+            // mask bits hi-P+1 .. hi; compare-exchanges along the top b of them
+            const bool low = hi == P - 1;
+            const int b = low ? P : (hi - (P - 1) < P ? hi - (P - 1) : P), lo = hi - (P - 1);
+            if (!ONE_WAVE && (hi >= 6 + P || top_prev >= 6 + P))
                 __syncthreads();
             else
                 lds_wave_sync();
             top_prev = hi;
-            for (uint32_t g = tid; g < groups; g += THREADS) {
-                const uint32_t base = ((g >> lo) << (lo + 3)) | (g & ((1u << lo) - 1u));
-                uint64_t v[8];
+            for (uint32_t g = tid; g < groups; g += NT) {
+                const uint32_t base = ((g >> lo) << (lo + P)) | (g & ((1u << lo) - 1u));
+                uint64_t v[E];
 #pragma unroll
-                for (int m = 0; m < 8; ++m) v[m] = s[lds_slot(base + ((uint32_t)m << lo))];
-                const bool desc = !fin && ((base >> lk) & 1u);
-                if (b == 1)
-                    group_steps<1>(v, desc);
+                for (int m = 0; m < E; ++m) v[m] = s[lds_slot<P>(base + ((uint32_t)m << lo))];
+                if (b == P)
+                    group_steps<P, P>(v);
+                else if (b == 1)
+                    group_steps<P, 1>(v);
                 else if (b == 2)
-                    group_steps<2>(v, desc);
+                    group_steps<P, (P > 2 ? 2 : 1)>(v);
                 else
-                    group_steps<3>(v, desc);
-                if (fin && low) {  // eight consecutive sorted entries
+                    group_steps<P, (P > 3 ? 3 : 1)>(v);
+                if (fin && low) {  // E consecutive sorted entries, none held complemented
 #pragma unroll
-                    for (int m = 0; m < 8; ++m)
+                    for (int m = 0; m < E; ++m)
                         if (base + m < L) {
                             keys[base + m] = thi | (v[m] >> 32);
                             vals[base + m] = (uint32_t)v[m];
                         }
                 } else {
+                    // the last pass of a merge hands over to the next merge
+                    const uint64_t flip = low ? held_mask(lk, ln, (base >> lk) & 1u) ^
+                                                    held_mask(lk + 1, ln, (base >> (lk + 1)) & 1u)
+                                              : 0ull;
 #pragma unroll
-                    for (int m = 0; m < 8; ++m) s[lds_slot(base + ((uint32_t)m << lo))] = v[m];
+                    for (int m = 0; m < E; ++m) s[lds_slot<P>(base + ((uint32_t)m << lo))] = v[m] ^ flip;
                 }
             }
             if (low) break;
@@ -833,13 +876,16 @@ __device__ __forceinline__ void sort_bucket_lds(uint64_t *s, const uint64_t *in,
     }
 }
 
-constexpr int kSmallSortBlock = 256, kSmallSortCap = 2048;  // most buckets: many small workgroups per CU
-constexpr int kTileSortBlock = 512, kTileSortCap = 8192;    // longer buckets in LDS; beyond, in place in HBM
+// Buckets of up to kSmallSortCap entries: a 256-thread workgroup each (up
+// to seven resident per CU); longer ones: a 512-thread workgroup each, in LDS
+// up to kTileSortCap, in place in HBM beyond.  Eight entries per thread.
+constexpr int kSmallSortBlock = 256, kSmallSortCap = 2048;
+constexpr int kTileSortBlock = 512, kTileSortCap = 8192;
 
 // One workgroup per tile (grid-stride): sort the bucket and write the keys
 // (tile << 32 | depth bits) and values (instance).  Launched twice: small
-// workgroups for buckets of 1..kSmallSortCap entries (many resident per CU),
-// then large ones for the rest.
+// workgroups for buckets of 1..kSmallSortCap entries, then large ones for the
+// rest.
 template <int THREADS, int CAP, bool SMALL>
 __global__ void __launch_bounds__(THREADS) tile_sort_kernel(uint64_t *bucket, const uint32_t *ranges,
                                                             int64_t n_tiles, int64_t n_blocks, uint64_t *keys,
@@ -854,7 +900,7 @@ __global__ void __launch_bounds__(THREADS) tile_sort_kernel(uint64_t *bucket, co
         while (n2 < L) n2 <<= 1, ++ln;
         const uint64_t thi = (uint64_t)tile << 32;
         if (L <= (uint32_t)CAP) {
-            sort_bucket_lds<THREADS>(s, bucket + b, L, n2, ln, thi, keys + b, vals + b);
+            sort_bucket_lds<THREADS, 3, false>(s, bucket + b, L, n2, ln, thi, keys + b, vals + b, threadIdx.x);
         } else {
             bitonic_sort_hbm<THREADS>(bucket + b, n2, L);
             for (uint32_t i = threadIdx.x; i < L; i += THREADS) {
@@ -941,13 +987,17 @@ SortPlan make_sort_plan(int64_t n, int64_t capacity, int64_t n_tiles_total) {
 // the bucket path after the scan: count per (workgroup, tile), scan the
 // counters, scatter into the buckets, sort each bucket
 static hipError_t run_bucket_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec, int TX, int TY,
-                                  char *ws, uint64_t *keys, uint32_t *vals, uint32_t *ranges,
-                                  const int32_t *d_overflow, int n_cu, hipStream_t s) {
+                                  char *ws, uint64_t *keys, uint32_t *vals, uint32_t *ranges, int64_t *d_num,
+                                  int32_t *d_overflow, int n_cu, hipStream_t s) {
     hipError_t e;
-    if (P.n <= 0) return launch_fill_u32(ranges, 0u, 2 * P.n_tiles_total, s);  // no keys
+    if (P.n <= 0) {  // no keys: count 0, no overflow, every range empty
+        if ((e = launch_kernel(scan_partials_kernel, dim3(1), dim3(1024), s, (uint64_t *)nullptr, (int64_t)0,
+                               P.capacity, d_num, d_overflow)) != hipSuccess)
+            return e;
+        return launch_fill_u32(ranges, 0u, 2 * P.n_tiles_total, s);
+    }
     EmitArgs A = {};
     A.tt = tt;
-    A.part = reinterpret_cast<const uint64_t *>(ws + P.off_part);
     A.rec = rec;
     A.n = P.n;
     A.n_tiles_scan = P.scan_blocks;
@@ -968,8 +1018,8 @@ static hipError_t run_bucket_sort(const SortPlan &P, const uint32_t *tt, const f
     if ((e = launch_kernel(bucket_colscan_kernel, dim3((unsigned)((P.n_tiles_total + 3) / 4)), dim3(256), s,
                            A.tile_cnt, (int)P.bucket_blocks, P.n_tiles_total, tcount)) != hipSuccess)
         return e;
-    if ((e = launch_kernel(bucket_tilescan_kernel, dim3(1), dim3(1024), s, tcount, P.n_tiles_total, tstart, ranges,
-                           d_overflow)) != hipSuccess)
+    if ((e = launch_kernel(bucket_tilescan_kernel, dim3(1), dim3(1024), s, (const uint32_t *)tcount, P.n_tiles_total,
+                           P.capacity, tstart, ranges, d_num, d_overflow)) != hipSuccess)
         return e;
     if ((e = launch_kernel(emit_kernel<kEmitScatterTiles>, dim3((unsigned)P.bucket_blocks), dim3(kEmitBlock), s,
                            A)) != hipSuccess)
@@ -1008,6 +1058,8 @@ hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec
                                2 * P.n_tiles_total, (int64_t)1024 * 256)) != hipSuccess)
             return e;
     }
+    // the bucket path counts keys per tile and needs no scan over instances
+    if (P.use_bucket) return run_bucket_sort(P, tt, rec, TX, TY, ws, keys, vals, ranges, d_num, d_overflow, n_cu, s);
     // 1. scan
     if (P.n > 0) {
         if ((e = launch_kernel(scan_reduce_kernel, dim3((unsigned)P.scan_blocks), dim3(kScanBlock), s, tt, P.n,
@@ -1017,7 +1069,6 @@ hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec
     if ((e = launch_kernel(scan_partials_kernel, dim3(1), dim3(1024), s, part, P.n > 0 ? P.scan_blocks : (int64_t)0,
                            P.capacity, d_num, d_overflow)) != hipSuccess)
         return e;
-    if (P.use_bucket) return run_bucket_sort(P, tt, rec, TX, TY, ws, keys, vals, ranges, d_overflow, n_cu, s);
     // 2. emission (with the scan downsweep) into the buffer that the last pass does not write to
     const bool odd = (P.passes & 1) != 0;
     uint64_t *k_a = odd ? keys2 : keys;
