@@ -138,7 +138,7 @@ void gs_default_params(gs_params *p, int32_t width, int32_t height);
 /* Launch configuration (host-side, process-wide; it changes scheduling only,
  * never a result).
  *  composite_groups_per_cu: persistent 4-wave groups per compute unit in
- *    gs_composite (1..32, default 8); each wave of the grid pops (view, tile,
+ *    gs_composite (1..32, default 4); each wave of the grid pops (view, tile,
  *    quadrant) work items until none is left.
  *  sort_partition_keys: keys per onesweep partition in gs_bin_sort (4096 or
  *    8192, default 4096).
@@ -242,10 +242,13 @@ gs_status gs_bin_sort(const gs_projected *proj, int32_t n_views, const gs_params
                       uint64_t *keys, uint32_t *vals, int64_t capacity, uint32_t *tile_ranges,
                       int64_t *d_num_instances, int32_t *d_overflow, gs_stream_t stream);
 
-/* Workspace bytes gs_composite needs (the persistent tile queues).  The
- * workspace must be zero-filled before its first use; every call leaves it
- * zero-filled again, so one zeroing at allocation serves all later calls
- * (calls sharing a workspace must not overlap). */
+/* Workspace bytes gs_composite needs for n_views views of the image size in
+ * p (0 for a NULL or invalid p or n_views < 1): the persistent tile queues'
+ * counters (the first 2048 bytes) and each queue's item order (4 bytes per
+ * (view, tile), rewritten by every call).  The counters must be zero-filled
+ * before the workspace's first use; every call leaves them zero-filled again,
+ * so one zeroing at allocation serves all later calls (calls sharing a
+ * workspace must not overlap). */
 size_t gs_composite_workspace(int32_t n_views, const gs_params *p);
 
 /* Per-tile front-to-back compositing.  For each pixel p = (x + 1/2, y + 1/2)
@@ -258,7 +261,7 @@ size_t gs_composite_workspace(int32_t n_views, const gs_params *p);
  * backward pass starts from; pass NULL to skip them).
  * The tiles are processed by a persistent grid that pops (view, tile,
  * quadrant) work items from counters in `ws` (zero on entry, zero again when
- * the call completes).
+ * the call completes), longest tile lists first.
  * Errors: GS_ERR_INVALID_ARGUMENT, GS_ERR_WORKSPACE_TOO_SMALL. */
 gs_status gs_composite(const gs_projected *proj, const uint32_t *vals, const uint32_t *tile_ranges,
                        int32_t n_views, const gs_params *p, void *ws, size_t ws_bytes, float *rgb, float *depth,

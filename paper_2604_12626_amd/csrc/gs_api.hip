@@ -103,7 +103,7 @@ int64_t seg_offset_in_view(const gs_gaussians *segs, uint32_t mask, int s) {
     return o;
 }
 
-std::atomic<int> g_comp_groups{8};
+std::atomic<int> g_comp_groups{4};
 std::atomic<int> g_sort_part_keys{4096};
 std::atomic<int> g_sort_lookback{16};
 std::atomic<int> g_sort_algorithm{0};
@@ -159,7 +159,7 @@ void gs_default_params(gs_params *p, int32_t width, int32_t height) {
 gs_status gs_set_tuning(const gs_tuning *t) {
     clear_error();
     if (!t) {
-        g_comp_groups.store(8);
+        g_comp_groups.store(4);
         g_sort_part_keys.store(4096);
         g_sort_lookback.store(16);
         g_sort_algorithm.store(0);
@@ -356,10 +356,14 @@ gs_status gs_bin_sort(const gs_projected *proj, int32_t n_views, const gs_params
 }
 
 // ---------------------------------------------------------------------------
+// nine counters (one 128-B line each), then the per-queue item order
+static constexpr size_t kCompCounterBytes = 2048;
+static int64_t comp_qstride(int64_t n_items) { return (n_items + 7) / 8; }
+
 size_t gs_composite_workspace(int32_t n_views, const gs_params *p) {
-    (void)n_views;
-    (void)p;
-    return 2048;  // nine counters, one 128-B line each
+    if (!p || n_views < 1 || check_params(p) != GS_OK) return 0;
+    const int64_t n_items = (int64_t)tiles_x(p) * tiles_y(p) * n_views;
+    return kCompCounterBytes + (size_t)8 * comp_qstride(n_items) * sizeof(uint32_t);
 }
 
 gs_status gs_composite(const gs_projected *proj, const uint32_t *vals, const uint32_t *tile_ranges,
@@ -380,11 +384,13 @@ gs_status gs_composite(const gs_projected *proj, const uint32_t *vals, const uin
     a.vals = vals;
     a.ranges = reinterpret_cast<const uint2 *>(tile_ranges);
     a.counter = static_cast<uint32_t *>(ws);
+    a.order = reinterpret_cast<uint32_t *>(static_cast<char *>(ws) + kCompCounterBytes);
     a.W = p->width;
     a.H = p->height;
     a.TX = tiles_x(p);
     a.T = tiles_x(p) * tiles_y(p);
     a.n_items = (int64_t)a.T * n_views;
+    a.qstride = comp_qstride(a.n_items);
     a.alpha_max = p->alpha_max;
     a.alpha_min = p->alpha_min;
     a.t_min = p->t_min;

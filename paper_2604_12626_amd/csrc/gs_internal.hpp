@@ -57,6 +57,8 @@ struct CompositeArgs {
     const uint32_t *vals;
     const uint2 *ranges;
     uint32_t *counter;  // 8 queue heads + workgroups finished, 128 B apart; zero on entry and on exit
+    uint32_t *order;    // [8][qstride] items of each queue, longest list first (written per call)
+    int64_t qstride;    // ceil(n_items / 8)
     int64_t n_items;    // n_views * T
     uint32_t n_groups;  // workgroups in the grid (set by the launcher)
     int32_t W, H, TX, T;
