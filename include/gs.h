@@ -221,34 +221,47 @@ gs_status gs_project(const gs_gaussians *segs, int32_t n_segs, const gs_camera *
  * `capacity` key slots and n_views views of p->width x p->height. */
 size_t gs_bin_sort_workspace(int64_t n_instances, int64_t capacity, int32_t n_views, const gs_params *p);
 
-/* Tile binning of the projected instances:
- *   1. exclusive scan of tiles_touched -> per-instance key offsets, K;
- *   2. every visible instance g emits one key per tile of its rect, in
- *      row-major tile order: key = ((view * T + tile) << 32) | bits(fp32 z),
- *      value = g  (T = tiles per view; z > 0 so the bits order like z);
- *   3. stable LSD radix sort of (key, value) over the significant key bits
- *      (a hand-written onesweep pass per 8-bit digit), so ties in depth keep
- *      ascending instance order;
- *   4. tile_ranges[t] = [first, last + 1) of tile t's run, (0, 0) if empty.
+/* Words of a tile work order (see gs_bin_sort) for n_views views of the
+ * image size in p: 8 * ceil(n_views * T / 8) (0 for a NULL or invalid p or
+ * n_views < 1). */
+size_t gs_tile_order_words(int32_t n_views, const gs_params *p);
+
+/* Tile binning of the projected instances.  Every visible instance g emits
+ * one key per tile of its rect: key = ((view * T + tile) << 32) | bits(fp32
+ * z), value = g (T = tiles per view; z > 0 so the bits order like z).  The
+ * result is the (key, value) pairs in the order a stable sort by key of the
+ * keys emitted in ascending instance order gives (ties in depth keep
+ * ascending instance order), computed either by bucketing the keys by tile
+ * and sorting each bucket (launches with up to 4096 tiles over all views,
+ * unless gs_tuning selects the other path) or by a stable LSD radix sort
+ * over the significant key bits (one hand-written onesweep pass per 8-bit
+ * digit); both give identical output.
  *  keys uint64 [capacity], vals uint32 [capacity]: sorted output.
- *  tile_ranges uint32 [n_views * T][2].
- *  d_num_instances (int64, device): K.  d_overflow (int32, device): set to 1
- *  when K > capacity (then only the first `capacity` keys are emitted and the
- *  order and ranges are invalid), else 0.  The caller re-runs with a larger
- *  capacity; nothing here synchronises with the host.
+ *  tile_ranges uint32 [n_views * T][2]: [first, last + 1) of each (view,
+ *  tile) run, (0, 0) if empty.
+ *  tile_order uint32 [gs_tile_order_words()] or NULL: the work order
+ *  gs_composite pops tiles in -- queue q = item mod 8 lists its (view, tile)
+ *  items (item = view * T + tile) from word q * ceil(n_views * T / 8) on, by
+ *  descending list length in chunks of 64 entries.  Always a permutation of
+ *  the items, also after an overflow.
+ *  d_num_instances (int64, device): K, the number of keys.  d_overflow
+ *  (int32, device): set to 1 when K > capacity (then keys, values and the
+ *  ranges' contents are invalid and every range is (0, 0)), else 0.  The
+ *  caller re-runs with a larger capacity; nothing here synchronises with the
+ *  host.
  * Errors: GS_ERR_INVALID_ARGUMENT, GS_ERR_WORKSPACE_TOO_SMALL,
  * GS_ERR_UNSUPPORTED (capacity > GS_MAX_CAPACITY, n_views * T > 2^31). */
 gs_status gs_bin_sort(const gs_projected *proj, int32_t n_views, const gs_params *p, void *ws, size_t ws_bytes,
-                      uint64_t *keys, uint32_t *vals, int64_t capacity, uint32_t *tile_ranges,
+                      uint64_t *keys, uint32_t *vals, int64_t capacity, uint32_t *tile_ranges, uint32_t *tile_order,
                       int64_t *d_num_instances, int32_t *d_overflow, gs_stream_t stream);
 
 /* Workspace bytes gs_composite needs for n_views views of the image size in
  * p (0 for a NULL or invalid p or n_views < 1): the persistent tile queues'
- * counters (the first 2048 bytes) and each queue's item order (4 bytes per
- * (view, tile), rewritten by every call).  The counters must be zero-filled
- * before the workspace's first use; every call leaves them zero-filled again,
- * so one zeroing at allocation serves all later calls (calls sharing a
- * workspace must not overlap). */
+ * counters (the first 2048 bytes), then room for a tile work order (used
+ * when the call gets none).  The counters must be zero-filled before the
+ * workspace's first use; every call leaves them zero-filled again, so one
+ * zeroing at allocation serves all later calls (calls sharing a workspace
+ * must not overlap). */
 size_t gs_composite_workspace(int32_t n_views, const gs_params *p);
 
 /* Per-tile front-to-back compositing.  For each pixel p = (x + 1/2, y + 1/2)
@@ -261,11 +274,14 @@ size_t gs_composite_workspace(int32_t n_views, const gs_params *p);
  * backward pass starts from; pass NULL to skip them).
  * The tiles are processed by a persistent grid that pops (view, tile,
  * quadrant) work items from counters in `ws` (zero on entry, zero again when
- * the call completes), longest tile lists first.
+ * the call completes) in the order of tile_order: the one gs_bin_sort wrote
+ * for the same ranges, or NULL to have it computed here into `ws` (one more
+ * small launch).  The order only affects timing, never a result.
  * Errors: GS_ERR_INVALID_ARGUMENT, GS_ERR_WORKSPACE_TOO_SMALL. */
 gs_status gs_composite(const gs_projected *proj, const uint32_t *vals, const uint32_t *tile_ranges,
-                       int32_t n_views, const gs_params *p, void *ws, size_t ws_bytes, float *rgb, float *depth,
-                       float *alpha, float *t_final, uint32_t *n_contrib, gs_stream_t stream);
+                       const uint32_t *tile_order, int32_t n_views, const gs_params *p, void *ws, size_t ws_bytes,
+                       float *rgb, float *depth, float *alpha, float *t_final, uint32_t *n_contrib,
+                       gs_stream_t stream);
 
 /* Workspace bytes gs_render_backward needs for n_instances instances. */
 size_t gs_render_backward_workspace(int64_t n_instances);

@@ -60,7 +60,7 @@ TUNING_FIELDS = ("composite_groups_per_cu", "sort_partition_keys", "sort_lookbac
 
 EXPORTS = ["gs_status_string", "gs_last_error", "gs_version", "gs_default_params", "gs_set_tuning", "gs_get_tuning",
            "gs_instance_offsets",
-           "gs_deform_lbs", "gs_deform_lbs_backward", "gs_project", "gs_bin_sort_workspace", "gs_bin_sort",
+           "gs_deform_lbs", "gs_deform_lbs_backward", "gs_project", "gs_bin_sort_workspace", "gs_tile_order_words", "gs_bin_sort",
            "gs_composite_workspace", "gs_composite", "gs_render_backward_workspace", "gs_render_backward"]
 
 _lib = None
@@ -94,11 +94,14 @@ def load():
                                ctypes.POINTER(Projected), P]
     lib.gs_bin_sort_workspace.restype = sz
     lib.gs_bin_sort_workspace.argtypes = [i64, i64, i32, ctypes.POINTER(Params)]
-    lib.gs_bin_sort.argtypes = [ctypes.POINTER(Projected), i32, ctypes.POINTER(Params), P, sz, P, P, i64, P, P, P, P]
+    lib.gs_tile_order_words.restype = sz
+    lib.gs_tile_order_words.argtypes = [i32, ctypes.POINTER(Params)]
+    lib.gs_bin_sort.argtypes = [ctypes.POINTER(Projected), i32, ctypes.POINTER(Params), P, sz, P, P, i64, P, P, P, P,
+                                P]
     lib.gs_composite_workspace.restype = sz
     lib.gs_composite_workspace.argtypes = [i32, ctypes.POINTER(Params)]
-    lib.gs_composite.argtypes = [ctypes.POINTER(Projected), P, P, i32, ctypes.POINTER(Params), P, sz, P, P, P, P, P,
-                                 P]
+    lib.gs_composite.argtypes = [ctypes.POINTER(Projected), P, P, P, i32, ctypes.POINTER(Params), P, sz, P, P, P, P,
+                                 P, P]
     lib.gs_render_backward_workspace.restype = sz
     lib.gs_render_backward_workspace.argtypes = [i64]
     lib.gs_render_backward.argtypes = [ctypes.POINTER(Gaussians), i32, P, i32, P, ctypes.POINTER(Params),
@@ -208,23 +211,27 @@ def bin_sort_workspace(n_instances, capacity, n_views, params):
     return int(load().gs_bin_sort_workspace(int(n_instances), int(capacity), int(n_views), ctypes.byref(params)))
 
 
-def bin_sort(tiles_touched, rec, n_views, params, ws, keys, vals, ranges, d_num, d_overflow):
+def tile_order_words(n_views, params):
+    return int(load().gs_tile_order_words(int(n_views), ctypes.byref(params)))
+
+
+def bin_sort(tiles_touched, rec, n_views, params, ws, keys, vals, ranges, d_num, d_overflow, order=None):
     lib = load()
     proj = Projected(int(rec.shape[0]), ptr(tiles_touched), ptr(rec))
     _check(lib.gs_bin_sort(ctypes.byref(proj), int(n_views), ctypes.byref(params), ptr(ws), ws.numel() * ws.element_size(),
-                           ptr(keys), ptr(vals), int(keys.shape[0]), ptr(ranges), ptr(d_num), ptr(d_overflow),
-                           stream_handle()))
+                           ptr(keys), ptr(vals), int(keys.shape[0]), ptr(ranges), ptr(order), ptr(d_num),
+                           ptr(d_overflow), stream_handle()))
 
 
 def composite_workspace(n_views, params):
     return int(load().gs_composite_workspace(int(n_views), ctypes.byref(params)))
 
 
-def composite(rec, vals, ranges, n_views, params, ws, rgb, depth, alpha, t_final=None, n_contrib=None):
+def composite(rec, vals, ranges, n_views, params, ws, rgb, depth, alpha, t_final=None, n_contrib=None, order=None):
     lib = load()
     proj = Projected(int(rec.shape[0]), None, ptr(rec))
-    _check(lib.gs_composite(ctypes.byref(proj), ptr(vals), ptr(ranges), int(n_views), ctypes.byref(params), ptr(ws),
-                            ws.numel() * ws.element_size(), ptr(rgb), ptr(depth), ptr(alpha), ptr(t_final),
+    _check(lib.gs_composite(ctypes.byref(proj), ptr(vals), ptr(ranges), ptr(order), int(n_views), ctypes.byref(params),
+                            ptr(ws), ws.numel() * ws.element_size(), ptr(rgb), ptr(depth), ptr(alpha), ptr(t_final),
                             ptr(n_contrib), stream_handle()))
 
 

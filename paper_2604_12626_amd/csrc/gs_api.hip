@@ -324,8 +324,13 @@ size_t gs_bin_sort_workspace(int64_t n_instances, int64_t capacity, int32_t n_vi
     return gs::make_sort_plan(n_instances, capacity, T * n_views).total;
 }
 
+size_t gs_tile_order_words(int32_t n_views, const gs_params *p) {
+    if (!p || n_views < 1 || check_params(p) != GS_OK) return 0;
+    return (size_t)gs::kOrderQueues * gs::order_stride((int64_t)tiles_x(p) * tiles_y(p) * n_views);
+}
+
 gs_status gs_bin_sort(const gs_projected *proj, int32_t n_views, const gs_params *p, void *ws, size_t ws_bytes,
-                      uint64_t *keys, uint32_t *vals, int64_t capacity, uint32_t *tile_ranges,
+                      uint64_t *keys, uint32_t *vals, int64_t capacity, uint32_t *tile_ranges, uint32_t *tile_order,
                       int64_t *d_num_instances, int32_t *d_overflow, gs_stream_t stream) {
     clear_error();
     gs_status st;
@@ -339,8 +344,9 @@ gs_status gs_bin_sort(const gs_projected *proj, int32_t n_views, const gs_params
         return fail(GS_ERR_INVALID_ARGUMENT, "proj arrays NULL or rec/tiles_touched not 16-byte aligned");
     if (!keys || !vals || !tile_ranges || !d_num_instances || !d_overflow || !ws)
         return fail(GS_ERR_INVALID_ARGUMENT, "NULL output or workspace");
-    if (!aligned(keys, 8) || !aligned(tile_ranges, 8) || !aligned(d_num_instances, 8) || !aligned(ws, 256))
-        return fail(GS_ERR_INVALID_ARGUMENT, "keys/ranges/counter need 8-byte, ws 256-byte alignment");
+    if (!aligned(keys, 8) || !aligned(tile_ranges, 8) || !aligned(d_num_instances, 8) || !aligned(ws, 256) ||
+        !aligned(tile_order, 4))
+        return fail(GS_ERR_INVALID_ARGUMENT, "keys/ranges/counter need 8-byte, order 4-byte, ws 256-byte alignment");
     const int64_t T = (int64_t)tiles_x(p) * tiles_y(p);
     if (T * n_views > (1ll << 31)) return fail(GS_ERR_UNSUPPORTED, "more than 2^31 tiles");
     gs::SortPlan plan = gs::make_sort_plan(proj->n_instances, capacity, T * n_views);
@@ -351,24 +357,23 @@ gs_status gs_bin_sort(const gs_projected *proj, int32_t n_views, const gs_params
         return fail(GS_ERR_WORKSPACE_TOO_SMALL, "workspace %zu < %zu bytes", ws_bytes, plan.total);
     hipError_t e = gs::run_bin_sort(plan, proj->tiles_touched, reinterpret_cast<const float4 *>(proj->rec),
                                     tiles_x(p), tiles_y(p), static_cast<char *>(ws), keys, vals, tile_ranges,
-                                    d_num_instances, d_overflow, cu_count(), (hipStream_t)stream);
+                                    tile_order, d_num_instances, d_overflow, cu_count(), (hipStream_t)stream);
     return e == hipSuccess ? GS_OK : hip_fail(e, "gs_bin_sort");
 }
 
 // ---------------------------------------------------------------------------
-// nine counters (one 128-B line each), then the per-queue item order
+// nine counters (one 128-B line each), then room for a tile work order
 static constexpr size_t kCompCounterBytes = 2048;
-static int64_t comp_qstride(int64_t n_items) { return (n_items + 7) / 8; }
 
 size_t gs_composite_workspace(int32_t n_views, const gs_params *p) {
-    if (!p || n_views < 1 || check_params(p) != GS_OK) return 0;
-    const int64_t n_items = (int64_t)tiles_x(p) * tiles_y(p) * n_views;
-    return kCompCounterBytes + (size_t)8 * comp_qstride(n_items) * sizeof(uint32_t);
+    const size_t words = gs_tile_order_words(n_views, p);
+    return words ? kCompCounterBytes + words * sizeof(uint32_t) : 0;
 }
 
 gs_status gs_composite(const gs_projected *proj, const uint32_t *vals, const uint32_t *tile_ranges,
-                       int32_t n_views, const gs_params *p, void *ws, size_t ws_bytes, float *rgb, float *depth,
-                       float *alpha, float *t_final, uint32_t *n_contrib, gs_stream_t stream) {
+                       const uint32_t *tile_order, int32_t n_views, const gs_params *p, void *ws, size_t ws_bytes,
+                       float *rgb, float *depth, float *alpha, float *t_final, uint32_t *n_contrib,
+                       gs_stream_t stream) {
     clear_error();
     gs_status st;
     if ((st = check_params(p)) != GS_OK) return st;
@@ -377,20 +382,22 @@ gs_status gs_composite(const gs_projected *proj, const uint32_t *vals, const uin
     if (n_views < 1 || n_views > GS_MAX_VIEWS) return fail(GS_ERR_INVALID_ARGUMENT, "n_views=%d", n_views);
     if (proj->n_instances > 0 && (!proj->rec || !aligned(proj->rec, 16)))
         return fail(GS_ERR_INVALID_ARGUMENT, "rec NULL or not 16-byte aligned");
-    if (!aligned(tile_ranges, 8) || !aligned(ws, 4)) return fail(GS_ERR_INVALID_ARGUMENT, "misaligned ranges/ws");
+    if (!aligned(tile_ranges, 8) || !aligned(ws, 4) || !aligned(tile_order, 4))
+        return fail(GS_ERR_INVALID_ARGUMENT, "misaligned ranges/order/ws");
     if (ws_bytes < gs_composite_workspace(n_views, p)) return fail(GS_ERR_WORKSPACE_TOO_SMALL, "workspace too small");
     gs::CompositeArgs a = {};
     a.rec = reinterpret_cast<const float4 *>(proj->rec);
     a.vals = vals;
     a.ranges = reinterpret_cast<const uint2 *>(tile_ranges);
     a.counter = static_cast<uint32_t *>(ws);
-    a.order = reinterpret_cast<uint32_t *>(static_cast<char *>(ws) + kCompCounterBytes);
+    uint32_t *own_order = reinterpret_cast<uint32_t *>(static_cast<char *>(ws) + kCompCounterBytes);
+    a.order = tile_order ? tile_order : own_order;
     a.W = p->width;
     a.H = p->height;
     a.TX = tiles_x(p);
     a.T = tiles_x(p) * tiles_y(p);
     a.n_items = (int64_t)a.T * n_views;
-    a.qstride = comp_qstride(a.n_items);
+    a.qstride = gs::order_stride(a.n_items);
     a.alpha_max = p->alpha_max;
     a.alpha_min = p->alpha_min;
     a.t_min = p->t_min;
@@ -407,6 +414,8 @@ gs_status gs_composite(const gs_projected *proj, const uint32_t *vals, const uin
     // more waves than quadrant work items
     int64_t grid = (int64_t)cu_count() * g_comp_groups.load();
     if (grid > a.n_items) grid = a.n_items;
+    if (!tile_order && (e = gs::launch_tile_order(tile_ranges, a.n_items, own_order, (hipStream_t)stream)) != hipSuccess)
+        return hip_fail(e, "gs_composite");
     e = gs::launch_composite(a, (int)grid, (hipStream_t)stream);
     return e == hipSuccess ? GS_OK : hip_fail(e, "gs_composite");
 }

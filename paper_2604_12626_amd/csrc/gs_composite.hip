@@ -18,8 +18,8 @@
 // XCD still gets an even share of the image.  An exhausted queue sends its
 // waves on to the other queues (work stealing; a queue seen to be empty by a
 // plain load is skipped without an atomic).  Each queue head sits in its own
-// 128-B line.  Within a queue the items are popped longest list first (a
-// counting sort by list chunks, done by a one-workgroup kernel just before),
+// 128-B line.  Within a queue the items are popped longest list first (the
+// tile work order, a counting sort by list chunks that the binning writes),
 // so the waves that bound the kernel's duration start at once and short
 // lists fill the gaps at the end.  Placement and order only affect locality
 // and timing, never results.  The last workgroup to leave returns the
@@ -30,7 +30,7 @@
 namespace gs {
 
 constexpr int kWavesPerGroup = 4;
-constexpr int kQueues = 8;         // one per XCD
+constexpr int kQueues = kOrderQueues;  // one per XCD
 constexpr int kCounterStride = 32;  // words between queue heads (one 128-B line each)
 
 // wave issue priority 0..3 from the list length (512, 1024, 2048 entries)
@@ -61,7 +61,8 @@ __global__ void __launch_bounds__(64 * kWavesPerGroup) composite_kernel(const Co
                 }
                 const uint32_t k = atomicAdd(head, 1u);
                 if (k < size) {
-                    item = (long long)a.order[q * a.qstride + (k >> 2)] * 4 + (k & 3);
+                    const uint32_t t = a.order[q * a.qstride + (k >> 2)];
+                    item = t < (uint64_t)a.n_items ? (long long)t * 4 + (k & 3) : -1;  // -1: not an item
                     break;
                 }
                 ++visited;
@@ -184,47 +185,9 @@ __global__ void __launch_bounds__(64 * kWavesPerGroup) composite_kernel(const Co
     }
 }
 
-// Longest-first order of each queue's items: order[q * qstride + i] is the
-// i-th (view, tile) item of queue q (items t = q mod 8) by descending list
-// length in chunks of 64 entries (lists of 63 chunks and more share the first
-// bin; the order inside a bin is that of the atomics).
-constexpr int kOrderBins = 64;
-__global__ void __launch_bounds__(1024) tile_order_kernel(const uint2 *ranges, int64_t n_items, int64_t qstride,
-                                                          uint32_t *order) {
-    __shared__ uint32_t s_cnt[kQueues][kOrderBins];
-    const int tid = threadIdx.x;
-    for (int i = tid; i < kQueues * kOrderBins; i += 1024) (&s_cnt[0][0])[i] = 0u;
-    __syncthreads();
-    for (int64_t t = tid; t < n_items; t += 1024) {
-        const uint2 r = ranges[t];
-        const uint32_t chunks = (r.y - r.x) >> 6;
-        atomicAdd(&s_cnt[t & (kQueues - 1)][kOrderBins - 1 - (chunks < kOrderBins - 1 ? chunks : kOrderBins - 1)], 1u);
-    }
-    __syncthreads();
-    if (tid < kQueues) {  // bin starts inside each queue's stretch
-        uint32_t run = 0u;
-        for (int b = 0; b < kOrderBins; ++b) {
-            const uint32_t c = s_cnt[tid][b];
-            s_cnt[tid][b] = run;
-            run += c;
-        }
-    }
-    __syncthreads();
-    for (int64_t t = tid; t < n_items; t += 1024) {
-        const uint2 r = ranges[t];
-        const uint32_t chunks = (r.y - r.x) >> 6;
-        const int q = (int)(t & (kQueues - 1));
-        const uint32_t pos =
-            atomicAdd(&s_cnt[q][kOrderBins - 1 - (chunks < kOrderBins - 1 ? chunks : kOrderBins - 1)], 1u);
-        order[q * qstride + pos] = (uint32_t)t;
-    }
-}
-
 hipError_t launch_composite(CompositeArgs a, int grid, hipStream_t s) {
     if (a.n_items == 0 || grid <= 0) return hipSuccess;
     a.n_groups = (uint32_t)grid;
-    hipError_t e = launch_kernel(tile_order_kernel, dim3(1), dim3(1024), s, a.ranges, a.n_items, a.qstride, a.order);
-    if (e != hipSuccess) return e;
     return launch_kernel(composite_kernel, dim3(grid), dim3(64 * kWavesPerGroup), s, a);
 }
 

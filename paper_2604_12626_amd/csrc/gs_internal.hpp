@@ -57,8 +57,8 @@ struct CompositeArgs {
     const uint32_t *vals;
     const uint2 *ranges;
     uint32_t *counter;  // 8 queue heads + workgroups finished, 128 B apart; zero on entry and on exit
-    uint32_t *order;    // [8][qstride] items of each queue, longest list first (written per call)
-    int64_t qstride;    // ceil(n_items / 8)
+    const uint32_t *order;  // [8][qstride] items of each queue, longest list first
+    int64_t qstride;        // order_stride(n_items)
     int64_t n_items;    // n_views * T
     uint32_t n_groups;  // workgroups in the grid (set by the launcher)
     int32_t W, H, TX, T;
@@ -112,8 +112,15 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_project(const ProjectArgs &a, hipStream_t s);
 SortPlan make_sort_plan(int64_t n, int64_t capacity, int64_t n_tiles_total);
 hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec, int TX, int TY, char *ws,
-                        uint64_t *keys, uint32_t *vals, uint32_t *ranges, int64_t *d_num, int32_t *d_overflow,
-                        int n_cu, hipStream_t s);
+                        uint64_t *keys, uint32_t *vals, uint32_t *ranges, uint32_t *order, int64_t *d_num,
+                        int32_t *d_overflow, int n_cu, hipStream_t s);
+// Tile work order for the compositing queues: queue q (items t = q mod
+// kOrderQueues) lists its items from order[q * order_stride(n_items)] on, by
+// descending list length in chunks of 64 entries (kOrderBins bins, the last
+// holding every list of 63 chunks or more).
+constexpr int kOrderQueues = 8, kOrderBins = 64;
+__host__ __device__ inline int64_t order_stride(int64_t n_items) { return (n_items + kOrderQueues - 1) / kOrderQueues; }
+hipError_t launch_tile_order(const uint32_t *ranges, int64_t n_items, uint32_t *order, hipStream_t s);
 hipError_t launch_composite(CompositeArgs a, int grid, hipStream_t s);
 hipError_t launch_backward_tiles(const BackwardTileArgs &a, hipStream_t s);
 hipError_t launch_backward_project(const BackwardProjectArgs &a, hipStream_t s);

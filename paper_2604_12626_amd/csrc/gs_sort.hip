@@ -652,15 +652,68 @@ __global__ void __launch_bounds__(256) bucket_colscan_kernel(uint32_t *cnt /*[n_
     if (lane == 0) tile_count[t] = carry;
 }
 
+// ---------------------------------------------------------------------------
+// tile work order (one workgroup of 1024 threads): a counting sort of each
+// queue's items by descending list chunks
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t order_bin(uint32_t len) {
+    const uint32_t chunks = len >> 6;
+    return (uint32_t)(kOrderBins - 1) - (chunks < (uint32_t)(kOrderBins - 1) ? chunks : (uint32_t)(kOrderBins - 1));
+}
+
+// s_cnt[q][b] holds the item count of bin b of queue q; turns every row into
+// its exclusive prefix (one wave per queue, one bin per lane)
+__device__ __forceinline__ void order_bin_starts(uint32_t (*s_cnt)[kOrderBins]) {
+    static_assert(kOrderBins == 64 && kOrderQueues <= 16, "one wave per queue, one lane per bin");
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (wave < kOrderQueues) {
+        const uint32_t c = s_cnt[wave][lane];
+        uint32_t incl = c;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += y;
+        }
+        s_cnt[wave][lane] = incl - c;
+    }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(1024) tile_order_kernel(const uint2 *ranges, int64_t n_items, uint32_t *order) {
+    __shared__ uint32_t s_cnt[kOrderQueues][kOrderBins];
+    const int tid = threadIdx.x;
+    const int64_t qs = order_stride(n_items);
+    for (int i = tid; i < kOrderQueues * kOrderBins; i += 1024) (&s_cnt[0][0])[i] = 0u;
+    __syncthreads();
+    for (int64_t t = tid; t < n_items; t += 1024) {
+        const uint2 r = ranges[t];
+        atomicAdd(&s_cnt[t % kOrderQueues][order_bin(r.y - r.x)], 1u);
+    }
+    order_bin_starts(s_cnt);
+    for (int64_t t = tid; t < n_items; t += 1024) {
+        const uint2 r = ranges[t];
+        const int q = (int)(t % kOrderQueues);
+        order[q * qs + atomicAdd(&s_cnt[q][order_bin(r.y - r.x)], 1u)] = (uint32_t)t;
+    }
+}
+
+hipError_t launch_tile_order(const uint32_t *ranges, int64_t n_items, uint32_t *order, hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    return launch_kernel(tile_order_kernel, dim3(1), dim3(1024), s, reinterpret_cast<const uint2 *>(ranges), n_items,
+                         order);
+}
+
 // exclusive scan of the tile totals (one workgroup): the key count and the
 // overflow flag (count above the capacity), each tile's first key, and the
 // ranges ([first, end) for tiles with keys, [0, 0) otherwise, and all [0, 0)
 // after an overflow)
 __global__ void __launch_bounds__(1024) bucket_tilescan_kernel(const uint32_t *tile_count, int64_t n_tiles,
                                                                int64_t capacity, uint32_t *tile_start,
-                                                               uint32_t *ranges, int64_t *d_num,
+                                                               uint32_t *ranges, uint32_t *order, int64_t *d_num,
                                                                int32_t *d_overflow) {
     __shared__ uint64_t s_w[16];
+    __shared__ uint32_t s_cnt[kOrderQueues][kOrderBins];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t per = (n_tiles + 1023) / 1024;
     const int64_t t0 = (int64_t)tid * per, t1 = (t0 + per < n_tiles) ? t0 + per : n_tiles;
@@ -690,6 +743,17 @@ __global__ void __launch_bounds__(1024) bucket_tilescan_kernel(const uint32_t *t
         ranges[2 * t] = (c && !ovf) ? (uint32_t)run : 0u;
         ranges[2 * t + 1] = (c && !ovf) ? (uint32_t)(run + c) : 0u;
         run += c;
+    }
+    if (!order) return;  // uniform
+    // the work order of the lists just ranged (empty ones after an overflow)
+    for (int i = tid; i < kOrderQueues * kOrderBins; i += 1024) (&s_cnt[0][0])[i] = 0u;
+    __syncthreads();
+    for (int64_t t = t0; t < t1; ++t) atomicAdd(&s_cnt[t % kOrderQueues][order_bin(ovf ? 0u : tile_count[t])], 1u);
+    order_bin_starts(s_cnt);
+    const int64_t qs = order_stride(n_tiles);
+    for (int64_t t = t0; t < t1; ++t) {
+        const int q = (int)(t % kOrderQueues);
+        order[q * qs + atomicAdd(&s_cnt[q][order_bin(ovf ? 0u : tile_count[t])], 1u)] = (uint32_t)t;
     }
 }
 
@@ -987,14 +1051,15 @@ SortPlan make_sort_plan(int64_t n, int64_t capacity, int64_t n_tiles_total) {
 // the bucket path after the scan: count per (workgroup, tile), scan the
 // counters, scatter into the buckets, sort each bucket
 static hipError_t run_bucket_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec, int TX, int TY,
-                                  char *ws, uint64_t *keys, uint32_t *vals, uint32_t *ranges, int64_t *d_num,
-                                  int32_t *d_overflow, int n_cu, hipStream_t s) {
+                                  char *ws, uint64_t *keys, uint32_t *vals, uint32_t *ranges, uint32_t *order,
+                                  int64_t *d_num, int32_t *d_overflow, int n_cu, hipStream_t s) {
     hipError_t e;
     if (P.n <= 0) {  // no keys: count 0, no overflow, every range empty
         if ((e = launch_kernel(scan_partials_kernel, dim3(1), dim3(1024), s, (uint64_t *)nullptr, (int64_t)0,
                                P.capacity, d_num, d_overflow)) != hipSuccess)
             return e;
-        return launch_fill_u32(ranges, 0u, 2 * P.n_tiles_total, s);
+        if ((e = launch_fill_u32(ranges, 0u, 2 * P.n_tiles_total, s)) != hipSuccess) return e;
+        return order ? launch_tile_order(ranges, P.n_tiles_total, order, s) : hipSuccess;
     }
     EmitArgs A = {};
     A.tt = tt;
@@ -1019,7 +1084,7 @@ static hipError_t run_bucket_sort(const SortPlan &P, const uint32_t *tt, const f
                            A.tile_cnt, (int)P.bucket_blocks, P.n_tiles_total, tcount)) != hipSuccess)
         return e;
     if ((e = launch_kernel(bucket_tilescan_kernel, dim3(1), dim3(1024), s, (const uint32_t *)tcount, P.n_tiles_total,
-                           P.capacity, tstart, ranges, d_num, d_overflow)) != hipSuccess)
+                           P.capacity, tstart, ranges, order, d_num, d_overflow)) != hipSuccess)
         return e;
     if ((e = launch_kernel(emit_kernel<kEmitScatterTiles>, dim3((unsigned)P.bucket_blocks), dim3(kEmitBlock), s,
                            A)) != hipSuccess)
@@ -1038,8 +1103,8 @@ static hipError_t run_bucket_sort(const SortPlan &P, const uint32_t *tt, const f
 }
 
 hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec, int TX, int TY, char *ws,
-                        uint64_t *keys, uint32_t *vals, uint32_t *ranges, int64_t *d_num, int32_t *d_overflow,
-                        int n_cu, hipStream_t s) {
+                        uint64_t *keys, uint32_t *vals, uint32_t *ranges, uint32_t *order, int64_t *d_num,
+                        int32_t *d_overflow, int n_cu, hipStream_t s) {
     hipError_t e;
     uint64_t *part = reinterpret_cast<uint64_t *>(ws + P.off_part);
     uint64_t *keys2 = reinterpret_cast<uint64_t *>(ws + P.off_keys2);
@@ -1059,7 +1124,8 @@ hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec
             return e;
     }
     // the bucket path counts keys per tile and needs no scan over instances
-    if (P.use_bucket) return run_bucket_sort(P, tt, rec, TX, TY, ws, keys, vals, ranges, d_num, d_overflow, n_cu, s);
+    if (P.use_bucket)
+        return run_bucket_sort(P, tt, rec, TX, TY, ws, keys, vals, ranges, order, d_num, d_overflow, n_cu, s);
     // 1. scan
     if (P.n > 0) {
         if ((e = launch_kernel(scan_reduce_kernel, dim3((unsigned)P.scan_blocks), dim3(kScanBlock), s, tt, P.n,
@@ -1136,10 +1202,12 @@ hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec
     {
         int64_t blocks = (P.capacity + 255) / 256;
         if (blocks > (int64_t)n_cu * 4) blocks = (int64_t)n_cu * 4;
-        return launch_kernel(ranges_kernel, dim3((unsigned)blocks), dim3(256), s, k_a, d_num, P.capacity, d_overflow,
-                             ranges, (uint64_t)P.n_tiles_total, blocks * 256);
+        if ((e = launch_kernel(ranges_kernel, dim3((unsigned)blocks), dim3(256), s, k_a, d_num, P.capacity,
+                               d_overflow, ranges, (uint64_t)P.n_tiles_total, blocks * 256)) != hipSuccess)
+            return e;
     }
-    return hipSuccess;
+    // 5. the compositing work order
+    return order ? launch_tile_order(ranges, P.n_tiles_total, order, s) : hipSuccess;
 }
 
 }  // namespace gs

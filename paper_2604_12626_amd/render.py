@@ -67,6 +67,7 @@ class Renderer:
         f.keys = self._buf("keys", (self.capacity,), torch.int64)
         f.vals = self._buf("vals", (self.capacity,), torch.int32)
         f.ranges = self._buf("ranges", (n_views * self.T, 2), torch.int32)
+        f.order = self._buf("order", (B.tile_order_words(n_views, self.params),), torch.int32)
         f.num = self._buf("num", (1,), torch.int64)
         f.overflow = self._buf("ovf", (1,), torch.int32)
         ws = B.bin_sort_workspace(n_inst, self.capacity, n_views, self.params)
@@ -87,11 +88,11 @@ class Renderer:
 
     def bin_sort(self, f, n_views):
         B.bin_sort(f.tiles_touched, f.rec, n_views, self.params, f.sort_ws, f.keys, f.vals, f.ranges, f.num,
-                   f.overflow)
+                   f.overflow, order=f.order)
 
     def composite(self, f, n_views):
         B.composite(f.rec, f.vals, f.ranges, n_views, self.params, f.comp_ws, f.rgb, f.depth, f.alpha, f.t_final,
-                    f.n_contrib)
+                    f.n_contrib, order=f.order)
 
     def enqueue(self, segs, cams, view_segs, f):
         """All forward stages, no host synchronisation."""

@@ -99,11 +99,11 @@ def test_bin_sort_capacity_and_workspace_errors(lib):
     a = ctypes.c_void_p(0x10000)
     ws_need = lib.gs_bin_sort_workspace(100, 1000, 1, ctypes.byref(p))
     assert ws_need > 0
-    st = lib.gs_bin_sort(ctypes.byref(proj), 1, ctypes.byref(p), a, ws_need - 1, a, a, 1000, a, a, a, None)
+    st = lib.gs_bin_sort(ctypes.byref(proj), 1, ctypes.byref(p), a, ws_need - 1, a, a, 1000, a, None, a, a, None)
     assert st == B.GS_ERR_WORKSPACE_TOO_SMALL
-    st = lib.gs_bin_sort(ctypes.byref(proj), 1, ctypes.byref(p), a, ws_need, a, a, 1 << 30, a, a, a, None)
+    st = lib.gs_bin_sort(ctypes.byref(proj), 1, ctypes.byref(p), a, ws_need, a, a, 1 << 30, a, None, a, a, None)
     assert st == B.GS_ERR_UNSUPPORTED
-    st = lib.gs_bin_sort(ctypes.byref(proj), 1, ctypes.byref(p), a, ws_need, a, a, 0, a, a, a, None)
+    st = lib.gs_bin_sort(ctypes.byref(proj), 1, ctypes.byref(p), a, ws_need, a, a, 0, a, None, a, a, None)
     assert st == B.GS_ERR_INVALID_ARGUMENT
     # workspace grows with capacity (ping-pong key/value buffers)
     assert lib.gs_bin_sort_workspace(100, 2000, 1, ctypes.byref(p)) >= ws_need + 1000 * 12
@@ -118,10 +118,28 @@ def test_lbs_and_composite_validation(lib):
     assert lib.gs_deform_lbs(0, None, None, None, None, None, None, None, 1, 24, None, None, None) == B.GS_OK
     p = B.make_params(64, 64)
     proj = B.Projected(10, None, a)
-    st = lib.gs_composite(ctypes.byref(proj), a, a, 1, ctypes.byref(p), a, 8, a, a, a, None, None, None)
+    st = lib.gs_composite(ctypes.byref(proj), a, a, None, 1, ctypes.byref(p), a, 8, a, a, a, None, None, None)
     assert st == B.GS_ERR_WORKSPACE_TOO_SMALL
-    st = lib.gs_composite(ctypes.byref(proj), None, a, 1, ctypes.byref(p), a, 256, a, a, a, None, None, None)
+    st = lib.gs_composite(ctypes.byref(proj), None, a, None, 1, ctypes.byref(p), a, 256, a, a, a, None, None, None)
     assert st == B.GS_ERR_INVALID_ARGUMENT
+    ws = lib.gs_composite_workspace(1, ctypes.byref(p))
+    st = lib.gs_composite(ctypes.byref(proj), a, a, ctypes.c_void_p(0x10002), 1, ctypes.byref(p), a, ws, a, a, a,
+                          None, None, None)
+    assert st == B.GS_ERR_INVALID_ARGUMENT  # misaligned work order
+
+
+def test_tile_order_sizes(lib):
+    # 8 queues of ceil(n_views * T / 8) words; the compositing workspace holds
+    # 2048 bytes of counters and room for one order
+    from paper_2604_12626_amd import binding as B
+    for (w, h, v, T) in ((64, 64, 1, 16), (640, 480, 1, 1200), (100, 70, 3, 35), (256, 256, 64, 256)):
+        p = B.make_params(w, h)
+        words = lib.gs_tile_order_words(v, ctypes.byref(p))
+        assert words == 8 * ((v * T + 7) // 8)
+        assert lib.gs_composite_workspace(v, ctypes.byref(p)) == 2048 + 4 * words
+    p = B.make_params(64, 64)
+    assert lib.gs_tile_order_words(0, ctypes.byref(p)) == 0
+    assert lib.gs_tile_order_words(1, None) == 0
 
 
 def test_tuning_validation():

@@ -146,15 +146,34 @@ def _bin_sort_case(dev, B, rec, tt_o, keys_o, vals_o, ranges_o, K, V, W, H, prm,
     num = torch.zeros(1, dtype=torch.int64, device=dev)
     ovf = torch.full((1,), 5, dtype=torch.int32, device=dev)
     ws = torch.empty(B.bin_sort_workspace(len(rec), cap, V, prm), dtype=torch.uint8, device=dev)
-    B.bin_sort(tt, r, V, prm, ws, keys, vals, ranges, num, ovf)
+    order = torch.full((B.tile_order_words(V, prm),), -1, dtype=torch.int32, device=dev)
+    B.bin_sort(tt, r, V, prm, ws, keys, vals, ranges, num, ovf, order=order)
     torch.cuda.synchronize()
     assert int(num.item()) == K and int(ovf.item()) == expect_ovf
     if expect_ovf:
         assert np.all(ranges.cpu().numpy() == 0)
+        check_tile_order(order.cpu().numpy(), np.zeros(V * T, np.int64))
         return
     assert np.array_equal(keys.cpu().numpy()[:K].view(np.uint64), keys_o)
     assert np.array_equal(vals.cpu().numpy()[:K].view(np.uint32), vals_o)
     assert np.array_equal(ranges.cpu().numpy().view(np.uint32), ranges_o)
+    ro = ranges_o.reshape(-1, 2).astype(np.int64)
+    check_tile_order(order.cpu().numpy(), ro[:, 1] - ro[:, 0])
+
+
+def check_tile_order(order, lens):
+    """The compositing work order: queue q (items t = q mod 8) lists each of
+    its items once from word q * ceil(n / 8) on, in descending list length
+    counted in chunks of 64 entries (63 chunks and more tie)."""
+    n = len(lens)
+    qs = (n + 7) // 8
+    assert len(order) == 8 * qs
+    chunks = np.minimum(lens // 64, 63)
+    for q in range(8):
+        mine = np.arange(q, n, 8)
+        got = order[q * qs: q * qs + len(mine)].astype(np.int64)
+        assert np.array_equal(np.sort(got), mine), "queue %d is not a permutation of its items" % q
+        assert np.all(np.diff(chunks[got]) <= 0), "queue %d not in descending list chunks" % q
 
 
 COMPOSITE_CASES = [
@@ -186,7 +205,8 @@ def test_composite_parity(dev, orc, name, counts, W, H, rmed, aniso):
     num = torch.zeros(1, dtype=torch.int64, device=dev)
     ovf = torch.zeros(1, dtype=torch.int32, device=dev)
     ws = torch.empty(B.bin_sort_workspace(len(rec), K + 16, V, prm), dtype=torch.uint8, device=dev)
-    B.bin_sort(tt, r, V, prm, ws, keys, vals, ranges, num, ovf)
+    order = torch.empty(B.tile_order_words(V, prm), dtype=torch.int32, device=dev)
+    B.bin_sort(tt, r, V, prm, ws, keys, vals, ranges, num, ovf, order=order)
     rgb = torch.zeros(V, H, W, 3, device=dev)
     depth = torch.zeros(V, H, W, device=dev)
     alpha = torch.zeros(V, H, W, device=dev)
@@ -195,12 +215,13 @@ def test_composite_parity(dev, orc, name, counts, W, H, rmed, aniso):
     cws = torch.zeros(B.composite_workspace(V, prm), dtype=torch.uint8, device=dev)
     B.composite(r, vals, ranges, V, prm, cws, rgb, depth, alpha, tfin, ncon)
     torch.cuda.synchronize()
-    # the call leaves its queue counters (the first 2048 bytes) at zero, and a
-    # second call over the same workspace gives the same images
+    # the call (its own work order) leaves its queue counters (the first 2048
+    # bytes) at zero, and a second call over the same workspace, popping tiles
+    # in the order the binning wrote, gives the same images
     assert int(cws[:2048].to(torch.int32).abs().sum().item()) == 0, "composite counters not returned to zero"
     rgb2 = torch.full_like(rgb, -1.0)
     ncon2 = torch.full_like(ncon, -1)
-    B.composite(r, vals, ranges, V, prm, cws, rgb2, depth, alpha, tfin, ncon2)
+    B.composite(r, vals, ranges, V, prm, cws, rgb2, depth, alpha, tfin, ncon2, order=order)
     torch.cuda.synchronize()
     assert torch.equal(rgb, rgb2) and torch.equal(ncon, ncon2)
     gimg = np.concatenate([rgb.cpu().numpy(), depth.cpu().numpy()[..., None], alpha.cpu().numpy()[..., None]],
@@ -290,6 +311,11 @@ def test_composite_schedule_does_not_change_results(dev):
             r.composite(f, len(vs))
             torch.cuda.synchronize()
             assert torch.equal(f.rgb, ref[0]) and torch.equal(f.depth, ref[1]) and torch.equal(f.n_contrib, ref[2])
+        # without the binning's work order (computed inside the call)
+        B.composite(f.rec, f.vals, f.ranges, len(vs), r.params, f.comp_ws, f.rgb, f.depth, f.alpha, f.t_final,
+                    f.n_contrib)
+        torch.cuda.synchronize()
+        assert torch.equal(f.rgb, ref[0]) and torch.equal(f.depth, ref[1]) and torch.equal(f.n_contrib, ref[2])
         best, times = autotune.tune_composite(r, f, len(vs), candidates=(2, 8), reps=2)
         assert best in (2, 8) and B.get_tuning()["composite_groups_per_cu"] == best
     finally:
