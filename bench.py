@@ -148,8 +148,8 @@ def bench_forward(args, dev, timer_steps):
 def bench_fwd_bwd(args, dev, steps):
     """Forward + backward of one 256x256 view of a 500k-Gaussian SH3 room:
     L = sum |rgb - rgb*|^2 + sum (D - D*)^2 against the render of the
-    perturbed parameters; one step = forward, loss adjoint, backward with dense
-    gradients of every parameter."""
+    perturbed parameters; one step = forward (recording segment checkpoints),
+    loss adjoint, backward with dense gradients of every parameter."""
     import torch
     from paper_2604_12626_amd import render, synth
     cfg = synth.config(2)
@@ -158,7 +158,7 @@ def bench_fwd_bwd(args, dev, steps):
     tgt = [to_dev(synth.perturb(g, cfg["perturb_rng"]), dev)]
     cams = torch.from_numpy(cfg["cams"]).to(dev)
     vs = [[0]]
-    r = render.Renderer(cfg["W"], cfg["H"], capacity=1 << 21, device=dev)
+    r = render.Renderer(cfg["W"], cfg["H"], capacity=1 << 21, device=dev, checkpoints=True)
     ft = r.render(tgt, cams, vs)
     rgb_t, depth_t = ft.rgb.clone(), ft.depth.clone()
     r.render(segs, cams, vs)  # sizes the key capacity for the timed parameters
@@ -207,8 +207,9 @@ def bench_batched(args, dev, steps):
 def bench_avatars(args, dev, steps):
     """1M room + 8 avatars x 50k Gaussians, 16 views at 640x480: LBS of the
     avatar Gaussians, then all views of room + posed avatars in one call
-    (forward), and the same with the backward through the renderer and LBS
-    to the canonical avatar parameters (fwd+bwd)."""
+    (forward), and the same with the backward (segment checkpoints recorded
+    by its forward) through the renderer and LBS to the canonical avatar
+    parameters (fwd+bwd)."""
     import torch
     from paper_2604_12626_amd import binding as B, render
     from paper_2604_12626_amd import synth
@@ -238,16 +239,19 @@ def bench_avatars(args, dev, steps):
         lbs()
         r.enqueue([room, posed], cams, vs, f)
 
+    rb = render.Renderer(cfg["W"], cfg["H"], capacity=1 << 24, device=dev, checkpoints=True)
+    fb = rb.render([room, posed], cams, vs)
+
     def frame_bwd():
         lbs()
-        r.enqueue([room, posed], cams, vs, f)
-        gr = r.backward([room, posed], cams, vs, f, 2.0 * (f.rgb - target), None, None)
+        rb.enqueue([room, posed], cams, vs, fb)
+        gr = rb.backward([room, posed], cams, vs, fb, 2.0 * (fb.rgb - target), None, None)
         B.deform_lbs_backward(av["means"], av["log_scales"], av["quats"], av["joint_idx"], av["weights"],
                               av["avatar_of"], skin, gr[1]["means"], gr[1]["cov6"], d_means, d_ls, d_q)
 
     ms = _time_seq(frame, args.warmup, steps)
     ms_b = _time_seq(frame_bwd, max(2, args.warmup // 2), max(3, steps // 2))
-    assert int(f.overflow.item()) == 0
+    assert int(f.overflow.item()) == 0 and int(fb.overflow.item()) == 0
     return ms, ms_b, len(vs)
 
 

@@ -74,6 +74,7 @@ typedef enum gs_status {
 #define GS_MAX_VIEWS 4096
 #define GS_MAX_SH_DEGREE 3
 #define GS_MAX_CAPACITY ((1LL << 30) - 1) /* tile-instance limit of one gs_bin_sort call */
+#define GS_SEGMENT 64         /* list entries per segment of the segmented backward */
 
 /* Pinhole camera, world -> camera with OpenCV axes (x right, y down, z
  * forward): p_cam = R p_world + t, R row-major.  Pixel (x, y) samples the
@@ -277,11 +278,24 @@ size_t gs_composite_workspace(int32_t n_views, const gs_params *p);
  * the call completes) in the order of tile_order: the one gs_bin_sort wrote
  * for the same ranges, or NULL to have it computed here into `ws` (one more
  * small launch).  The order only affects timing, never a result.
+ *  ckpt (optional, ckpt_floats floats; NULL to skip): the state of every
+ *  pixel at each position b = m GS_SEGMENT (m >= 1) inside a tile list that
+ *  its compositing walk crosses, for gs_render_backward: transmittance T_b in
+ *  front of entry b, then the colour (3) and depth still to come from
+ *  entries b.. (background included) divided by T_b.  Layout: slot (list
+ *  start + b) / GS_SEGMENT, 8 x 8 quadrant (0..3, row-major in the tile),
+ *  value (5), pixel of the quadrant (64, row-major).  Size it with
+ *  gs_checkpoint_floats(capacity of the binning); writes past ckpt_floats
+ *  are dropped.
  * Errors: GS_ERR_INVALID_ARGUMENT, GS_ERR_WORKSPACE_TOO_SMALL. */
 gs_status gs_composite(const gs_projected *proj, const uint32_t *vals, const uint32_t *tile_ranges,
                        const uint32_t *tile_order, int32_t n_views, const gs_params *p, void *ws, size_t ws_bytes,
-                       float *rgb, float *depth, float *alpha, float *t_final, uint32_t *n_contrib,
-                       gs_stream_t stream);
+                       float *rgb, float *depth, float *alpha, float *t_final, uint32_t *n_contrib, float *ckpt,
+                       size_t ckpt_floats, gs_stream_t stream);
+
+/* Floats of a compositing checkpoint buffer for `capacity` key slots:
+ * (capacity / GS_SEGMENT + 1) * 4 * 5 * 64 (0 for capacity < 1). */
+size_t gs_checkpoint_floats(int64_t capacity);
 
 /* Workspace bytes gs_render_backward needs for n_instances instances. */
 size_t gs_render_backward_workspace(int64_t n_instances);
@@ -289,21 +303,27 @@ size_t gs_render_backward_workspace(int64_t n_instances);
 /* Gradients of L(rgb, depth, alpha) given dL/drgb [V][H][W][3],
  * dL/ddepth [V][H][W], dL/dalpha [V][H][W] (any may be NULL = zero), for the
  * forward described by the same segs/cams/masks/params and its outputs
- * (proj, vals, tile_ranges, t_final, n_contrib).  The transmittance of each
- * pixel is recovered back to front from t_final (T_i = T_{i+1} / (1 -
- * alpha_i)); the discrete decisions of the forward (cull, rect, skip, stop,
- * clamp) are held fixed, so this is the derivative almost everywhere, and it
- * is zero through the alpha clamp.  Gradients are summed over the views that
- * draw a segment and written densely (zeros for Gaussians no view sees).
+ * (proj, vals, tile_ranges, t_final, n_contrib, and ckpt).  The transmittance
+ * of each pixel is recovered back to front (T_i = T_{i+1} / (1 - alpha_i));
+ * the discrete decisions of the forward (cull, rect, skip, stop, clamp) are
+ * held fixed, so this is the derivative almost everywhere, and it is zero
+ * through the alpha clamp.  Gradients are summed over the views that draw a
+ * segment and written densely (zeros for Gaussians no view sees).
+ *  ckpt: the checkpoints gs_composite wrote for this frame (ckpt_floats
+ *  floats), or NULL.  With them each tile list is walked in segments of
+ *  GS_SEGMENT entries by separate workgroups, each starting from the state
+ *  at its segment's end (the last segment, and every list without them,
+ *  from t_final and the background), so long lists are differentiated in
+ *  parallel; the two give the same gradients up to rounding.
  *  grads: host array of n_segs gradient descriptors (device pointers),
  *  overwritten.  ws: per-instance screen-space accumulators.
  * Errors: as gs_project, plus GS_ERR_WORKSPACE_TOO_SMALL. */
 gs_status gs_render_backward(const gs_gaussians *segs, int32_t n_segs, const gs_camera *cams, int32_t n_views,
                              const uint32_t *view_seg_mask, const gs_params *p, const gs_projected *proj,
                              const uint32_t *vals, const uint32_t *tile_ranges, const float *t_final,
-                             const uint32_t *n_contrib, const float *d_rgb, const float *d_depth,
-                             const float *d_alpha, void *ws, size_t ws_bytes, const gs_gaussians_grad *grads,
-                             gs_stream_t stream);
+                             const uint32_t *n_contrib, const float *ckpt, size_t ckpt_floats, const float *d_rgb,
+                             const float *d_depth, const float *d_alpha, void *ws, size_t ws_bytes,
+                             const gs_gaussians_grad *grads, gs_stream_t stream);
 
 #ifdef __cplusplus
 }

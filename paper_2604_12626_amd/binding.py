@@ -61,7 +61,7 @@ TUNING_FIELDS = ("composite_groups_per_cu", "sort_partition_keys", "sort_lookbac
 EXPORTS = ["gs_status_string", "gs_last_error", "gs_version", "gs_default_params", "gs_set_tuning", "gs_get_tuning",
            "gs_instance_offsets",
            "gs_deform_lbs", "gs_deform_lbs_backward", "gs_project", "gs_bin_sort_workspace", "gs_tile_order_words", "gs_bin_sort",
-           "gs_composite_workspace", "gs_composite", "gs_render_backward_workspace", "gs_render_backward"]
+           "gs_composite_workspace", "gs_composite", "gs_checkpoint_floats", "gs_render_backward_workspace", "gs_render_backward"]
 
 _lib = None
 
@@ -101,11 +101,13 @@ def load():
     lib.gs_composite_workspace.restype = sz
     lib.gs_composite_workspace.argtypes = [i32, ctypes.POINTER(Params)]
     lib.gs_composite.argtypes = [ctypes.POINTER(Projected), P, P, P, i32, ctypes.POINTER(Params), P, sz, P, P, P, P,
-                                 P, P]
+                                 P, P, sz, P]
+    lib.gs_checkpoint_floats.restype = sz
+    lib.gs_checkpoint_floats.argtypes = [i64]
     lib.gs_render_backward_workspace.restype = sz
     lib.gs_render_backward_workspace.argtypes = [i64]
     lib.gs_render_backward.argtypes = [ctypes.POINTER(Gaussians), i32, P, i32, P, ctypes.POINTER(Params),
-                                       ctypes.POINTER(Projected), P, P, P, P, P, P, P, P, sz,
+                                       ctypes.POINTER(Projected), P, P, P, P, P, sz, P, P, P, P, sz,
                                        ctypes.POINTER(GaussiansGrad), P]
     lib.gs_set_tuning.argtypes = [ctypes.POINTER(Tuning)]
     lib.gs_get_tuning.argtypes = [ctypes.POINTER(Tuning)]
@@ -227,12 +229,17 @@ def composite_workspace(n_views, params):
     return int(load().gs_composite_workspace(int(n_views), ctypes.byref(params)))
 
 
-def composite(rec, vals, ranges, n_views, params, ws, rgb, depth, alpha, t_final=None, n_contrib=None, order=None):
+def checkpoint_floats(capacity):
+    return int(load().gs_checkpoint_floats(int(capacity)))
+
+
+def composite(rec, vals, ranges, n_views, params, ws, rgb, depth, alpha, t_final=None, n_contrib=None, order=None,
+              ckpt=None):
     lib = load()
     proj = Projected(int(rec.shape[0]), None, ptr(rec))
     _check(lib.gs_composite(ctypes.byref(proj), ptr(vals), ptr(ranges), ptr(order), int(n_views), ctypes.byref(params),
                             ptr(ws), ws.numel() * ws.element_size(), ptr(rgb), ptr(depth), ptr(alpha), ptr(t_final),
-                            ptr(n_contrib), stream_handle()))
+                            ptr(n_contrib), ptr(ckpt), 0 if ckpt is None else ckpt.numel(), stream_handle()))
 
 
 def render_backward_workspace(n_instances):
@@ -240,7 +247,7 @@ def render_backward_workspace(n_instances):
 
 
 def render_backward(segs, cams, view_segs, params, tiles_touched, rec, vals, ranges, t_final, n_contrib, d_rgb,
-                    d_depth, d_alpha, ws, grads):
+                    d_depth, d_alpha, ws, grads, ckpt=None):
     """grads: list (per segment) of dicts of output tensors (means, log_scales, quats, cov6, opacity, sh)."""
     lib = load()
     arr = seg_array(segs)
@@ -251,9 +258,9 @@ def render_backward(segs, cams, view_segs, params, tiles_touched, rec, vals, ran
                                 ptr(g.get("opacity")), ptr(g.get("sh")))
     proj = Projected(int(rec.shape[0]), ptr(tiles_touched), ptr(rec))
     _check(lib.gs_render_backward(arr, len(segs), ptr(cams), len(view_segs), masks, ctypes.byref(params),
-                                  ctypes.byref(proj), ptr(vals), ptr(ranges), ptr(t_final), ptr(n_contrib), ptr(d_rgb),
-                                  ptr(d_depth), ptr(d_alpha), ptr(ws), ws.numel() * ws.element_size(), garr,
-                                  stream_handle()))
+                                  ctypes.byref(proj), ptr(vals), ptr(ranges), ptr(t_final), ptr(n_contrib), ptr(ckpt),
+                                  0 if ckpt is None else ckpt.numel(), ptr(d_rgb), ptr(d_depth), ptr(d_alpha), ptr(ws),
+                                  ws.numel() * ws.element_size(), garr, stream_handle()))
 
 
 def deform_lbs(means_c, log_scales_c, quats_c, joint_idx, weights, avatar_of, skin_mats, means_out, cov6_out):

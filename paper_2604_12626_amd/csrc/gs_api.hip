@@ -370,10 +370,15 @@ size_t gs_composite_workspace(int32_t n_views, const gs_params *p) {
     return words ? kCompCounterBytes + words * sizeof(uint32_t) : 0;
 }
 
+size_t gs_checkpoint_floats(int64_t capacity) {
+    if (capacity < 1) return 0;
+    return (size_t)(capacity / (int64_t)gs::kSegment + 1) * 4 * gs::kCkptVals * 64;
+}
+
 gs_status gs_composite(const gs_projected *proj, const uint32_t *vals, const uint32_t *tile_ranges,
                        const uint32_t *tile_order, int32_t n_views, const gs_params *p, void *ws, size_t ws_bytes,
-                       float *rgb, float *depth, float *alpha, float *t_final, uint32_t *n_contrib,
-                       gs_stream_t stream) {
+                       float *rgb, float *depth, float *alpha, float *t_final, uint32_t *n_contrib, float *ckpt,
+                       size_t ckpt_floats, gs_stream_t stream) {
     clear_error();
     gs_status st;
     if ((st = check_params(p)) != GS_OK) return st;
@@ -382,8 +387,8 @@ gs_status gs_composite(const gs_projected *proj, const uint32_t *vals, const uin
     if (n_views < 1 || n_views > GS_MAX_VIEWS) return fail(GS_ERR_INVALID_ARGUMENT, "n_views=%d", n_views);
     if (proj->n_instances > 0 && (!proj->rec || !aligned(proj->rec, 16)))
         return fail(GS_ERR_INVALID_ARGUMENT, "rec NULL or not 16-byte aligned");
-    if (!aligned(tile_ranges, 8) || !aligned(ws, 4) || !aligned(tile_order, 4))
-        return fail(GS_ERR_INVALID_ARGUMENT, "misaligned ranges/order/ws");
+    if (!aligned(tile_ranges, 8) || !aligned(ws, 4) || !aligned(tile_order, 4) || !aligned(ckpt, 4))
+        return fail(GS_ERR_INVALID_ARGUMENT, "misaligned ranges/order/ws/ckpt");
     if (ws_bytes < gs_composite_workspace(n_views, p)) return fail(GS_ERR_WORKSPACE_TOO_SMALL, "workspace too small");
     gs::CompositeArgs a = {};
     a.rec = reinterpret_cast<const float4 *>(proj->rec);
@@ -409,6 +414,8 @@ gs_status gs_composite(const gs_projected *proj, const uint32_t *vals, const uin
     a.alpha = alpha;
     a.t_final = t_final;
     a.n_contrib = n_contrib;
+    a.ckpt = ckpt_floats ? ckpt : nullptr;
+    a.ckpt_floats = ckpt_floats;
     hipError_t e;
     // persistent waves: a tunable number of four-wave groups per CU, never
     // more waves than quadrant work items
@@ -440,9 +447,9 @@ size_t gs_render_backward_workspace(int64_t n_instances) {
 gs_status gs_render_backward(const gs_gaussians *segs, int32_t n_segs, const gs_camera *cams, int32_t n_views,
                              const uint32_t *view_seg_mask, const gs_params *p, const gs_projected *proj,
                              const uint32_t *vals, const uint32_t *tile_ranges, const float *t_final,
-                             const uint32_t *n_contrib, const float *d_rgb, const float *d_depth,
-                             const float *d_alpha, void *ws, size_t ws_bytes, const gs_gaussians_grad *grads,
-                             gs_stream_t stream) {
+                             const uint32_t *n_contrib, const float *ckpt, size_t ckpt_floats, const float *d_rgb,
+                             const float *d_depth, const float *d_alpha, void *ws, size_t ws_bytes,
+                             const gs_gaussians_grad *grads, gs_stream_t stream) {
     clear_error();
     gs_status st;
     if ((st = check_params(p)) != GS_OK) return st;
@@ -450,6 +457,7 @@ gs_status gs_render_backward(const gs_gaussians *segs, int32_t n_segs, const gs_
     if ((st = check_views(cams, n_views, view_seg_mask, n_segs)) != GS_OK) return st;
     if (!proj || !vals || !tile_ranges || !t_final || !n_contrib || !ws || !grads)
         return fail(GS_ERR_INVALID_ARGUMENT, "NULL argument");
+    if (!aligned(ckpt, 4)) return fail(GS_ERR_INVALID_ARGUMENT, "ckpt not 4-byte aligned");
     std::vector<int64_t> off(n_views + 1);
     instance_offsets(segs, n_segs, n_views, view_seg_mask, off.data());
     if (proj->n_instances != off[n_views])
@@ -482,6 +490,8 @@ gs_status gs_render_backward(const gs_gaussians *segs, int32_t n_segs, const gs_
     b.d_depth = d_depth;
     b.d_alpha = d_alpha;
     b.g2d = g2d;
+    b.ckpt = ckpt_floats ? ckpt : nullptr;
+    b.ckpt_floats = ckpt_floats;
     b.W = p->width;
     b.H = p->height;
     b.TX = tiles_x(p);

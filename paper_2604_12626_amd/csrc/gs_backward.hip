@@ -10,6 +10,11 @@
 // wave's quadrant are dropped by the same conservative bound as the forward;
 // per remaining entry the 64 lanes are summed with DPP adds and the last
 // lane issues the global float atomics (skipped when no lane contributed).
+// With the forward's segment checkpoints a list is cut into segments of
+// kSegment entries, one workgroup each (grid y), every segment's walk
+// starting from the transmittance and the normalised colour still to come
+// that the forward recorded at its end; the last segment of a list starts
+// from t_final and the background, as the whole list does without them.
 //
 // B2 (per Gaussian of a segment, scene-major): chains the screen-space
 // adjoints of every view that drew the Gaussian through the projection to the
@@ -57,6 +62,35 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
     const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
     const float bx0 = (float)qx0 + 0.5f, by0 = (float)qy0 + 0.5f;
     const uint2 range = a.ranges[item];
+    const uint32_t L = range.y - range.x;
+    if (blockIdx.y * kSegment >= L && blockIdx.y > 0) return;  // segment past the list
+    // this workgroup's segment [seg_lo, seg_hi) of list positions: all of
+    // them without checkpoints, else segment blockIdx.y (the last one takes
+    // the rest of the list)
+    static_assert(kSegment == 64, "a middle segment is one chunk");
+    const uint32_t s = blockIdx.y;
+    const bool last_seg = !a.ckpt || s + 1u == gridDim.y;
+    const uint32_t seg_lo = a.ckpt ? s * kSegment : 0u;
+    // A middle segment is the one chunk from seg_lo: its list values, records
+    // and end checkpoint are requested before the pixel state, so that the
+    // gather overlaps those loads (requests past what the walk needs are
+    // harmless: positions below the list length, slots inside the buffer).
+    const bool pre = !last_seg;
+    uint32_t g_pre = 0;
+    float4 p0 = make_float4(0.f, 0.f, 0.f, 0.f), p1 = p0, p2 = p0;
+    if (pre && seg_lo + lane < L) {
+        g_pre = a.vals[range.x + seg_lo + lane];
+        p0 = a.rec[3 * (size_t)g_pre];
+        p1 = a.rec[3 * (size_t)g_pre + 1];
+        p2 = a.rec[3 * (size_t)g_pre + 2];
+    }
+    const uint64_t slot = (range.x + seg_lo + kSegment) / kSegment;
+    const bool ck_ok = pre && seg_lo + kSegment < L && ckpt_index(slot, wave, kCkptVals - 1, 63) < a.ckpt_floats;
+    float ck[kCkptVals] = {1.0f, a.bg0, a.bg1, a.bg2, 0.0f};
+    if (ck_ok) {
+#pragma unroll
+        for (int v = 0; v < kCkptVals; ++v) ck[v] = a.ckpt[ckpt_index(slot, wave, v, lane)];
+    }
 
     float T = 1.0f, Tfin = 1.0f;
     uint32_t last = 0;
@@ -77,22 +111,40 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
     uint32_t maxlast = last;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) maxlast = max(maxlast, (uint32_t)__shfl_xor((int)maxlast, off, 64));
-    maxlast = min(maxlast, range.y - range.x);
-    // suffix colour / depth behind the current entry (background at the end)
+    maxlast = min(maxlast, L);
+    const uint32_t seg_end = last_seg ? maxlast : seg_lo + kSegment;  // state known here
+    const uint32_t seg_hi = seg_end < maxlast ? seg_end : maxlast;
+    if (seg_lo >= seg_hi) return;  // no barriers below: waves leave on their own
+    // suffix colour / depth behind the current entry over its transmittance:
+    // the background at the end of the walk, else the checkpoint at seg_end
     float Sr = a.bg0, Sg = a.bg1, Sb = a.bg2, Sd = 0.0f;
+    if (seg_end < maxlast && ck_ok) {
+        T = ck[0];
+        Sr = ck[1];
+        Sg = ck[2];
+        Sb = ck[3];
+        Sd = ck[4];
+    }
 
     // chunks [lo, hi) of list positions, from the back
-    for (int64_t hi = (int64_t)maxlast; hi > 0; hi -= 64) {
-        const int64_t lo = hi - 64 > 0 ? hi - 64 : 0;
+    for (int64_t hi = (int64_t)seg_hi; hi > (int64_t)seg_lo; hi -= 64) {
+        const int64_t lo = hi - 64 > (int64_t)seg_lo ? hi - 64 : (int64_t)seg_lo;
         const bool valid = lo + lane < hi;
         bool hit = false;
         float4 q0, q1, q2;
         uint32_t g = 0;
         if (valid) {
-            g = a.vals[range.x + (uint32_t)lo + lane];
-            q0 = a.rec[3 * (size_t)g];
-            q1 = a.rec[3 * (size_t)g + 1];
-            q2 = a.rec[3 * (size_t)g + 2];
+            if (pre) {  // the one chunk of a middle segment, requested up front
+                g = g_pre;
+                q0 = p0;
+                q1 = p1;
+                q2 = p2;
+            } else {
+                g = a.vals[range.x + (uint32_t)lo + lane];
+                q0 = a.rec[3 * (size_t)g];
+                q1 = a.rec[3 * (size_t)g + 1];
+                q2 = a.rec[3 * (size_t)g + 2];
+            }
             hit = entry_reaches_box(q0.x, q0.y, q1.x, q1.y, q1.z, q1.w, a.alpha_min, bx0, by0, bx0 + 7.0f,
                                     by0 + 7.0f);
         }
@@ -121,7 +173,8 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
                 if (!(al < a.alpha_min)) {
                     contrib = true;
                     const float one_m = 1.0f - al;
-                    T = T / one_m;  // transmittance in front of this entry
+                    const float r_one_m = __builtin_amdgcn_rcpf(one_m);  // 1 ulp reciprocal (one_m >= 0.01)
+                    T = T * r_one_m;  // transmittance in front of this entry
                     const float w = al * T;
                     gr = dR * w;
                     gg = dG * w;
@@ -129,7 +182,7 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
                     gz = dD * w;
                     const float dal = T * (dR * (e1.w - Sr) + dG * (e2.x - Sg) + dB * (e2.y - Sb) +
                                            dD * (e1.z - Sd)) +
-                                      dA * Tfin / one_m;
+                                      dA * Tfin * r_one_m;
                     if (!(oG > a.alpha_max)) {
                         const float4 cq = qs[q];
                         go = dal * G;
@@ -178,7 +231,8 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
 
 hipError_t launch_backward_tiles(const BackwardTileArgs &a, hipStream_t s) {
     if (a.n_items == 0) return hipSuccess;
-    return launch_kernel(backward_tile_kernel, dim3((unsigned)a.n_items), dim3(kTilePixels), s, a);
+    return launch_kernel(backward_tile_kernel, dim3((unsigned)a.n_items, a.ckpt ? (unsigned)kMaxSegments : 1u),
+                         dim3(kTilePixels), s, a);
 }
 
 // ---------------------------------------------------------------------------

@@ -88,6 +88,7 @@ __global__ void __launch_bounds__(64 * kWavesPerGroup) composite_kernel(const Co
         float T = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f, dd = 0.0f;
         const float amax = __builtin_canonicalizef(a.alpha_max);  // keeps the clamp's operand out of the loop
         uint32_t last = 0;
+        uint32_t done_end = 0;  // list position after the last chunk walked
         bool done = !inside;
         // software pipeline over the list chunks: while chunk c is culled and
         // composited, the records of chunk c + 1 and the list values of
@@ -161,7 +162,36 @@ __global__ void __launch_bounds__(64 * kWavesPerGroup) composite_kernel(const Co
                 }
             }
             __builtin_amdgcn_wave_barrier();
+            // segment checkpoint at the end of this chunk (a multiple of the
+            // segment length inside the list): T and the colour so far
+            done_end = b0 - range.x + 64u;
+            if (a.ckpt && done_end % kSegment == 0u && done_end < range.y - range.x) {
+                const uint64_t slot = (range.x + done_end) / kSegment;
+                if (ckpt_index(slot, quad, kCkptVals - 1, 63) < a.ckpt_floats) {
+                    a.ckpt[ckpt_index(slot, quad, 0, lane)] = T;
+                    a.ckpt[ckpt_index(slot, quad, 1, lane)] = cr;
+                    a.ckpt[ckpt_index(slot, quad, 2, lane)] = cg;
+                    a.ckpt[ckpt_index(slot, quad, 3, lane)] = cb;
+                    a.ckpt[ckpt_index(slot, quad, 4, lane)] = dd;
+                }
+            }
             if (__ballot(!done) == 0ull) break;
+        }
+        // the checkpoints crossed become (T_b, what is still to come behind b
+        // -- the final colour, background included, minus the colour so far --
+        // divided by T_b)
+        if (a.ckpt) {
+            for (uint32_t b = kSegment; b < done_end && b < range.y - range.x; b += kSegment) {
+                const uint64_t slot = (range.x + b) / kSegment;
+                if (ckpt_index(slot, quad, kCkptVals - 1, 63) >= a.ckpt_floats) break;
+                float *c = a.ckpt;
+                const float tb = c[ckpt_index(slot, quad, 0, lane)];
+                const float inv = 1.0f / tb;
+                c[ckpt_index(slot, quad, 1, lane)] = (cr - c[ckpt_index(slot, quad, 1, lane)] + T * a.bg0) * inv;
+                c[ckpt_index(slot, quad, 2, lane)] = (cg - c[ckpt_index(slot, quad, 2, lane)] + T * a.bg1) * inv;
+                c[ckpt_index(slot, quad, 3, lane)] = (cb - c[ckpt_index(slot, quad, 3, lane)] + T * a.bg2) * inv;
+                c[ckpt_index(slot, quad, 4, lane)] = (dd - c[ckpt_index(slot, quad, 4, lane)]) * inv;
+            }
         }
         if (inside) {
             const size_t pix = ((size_t)view * a.H + py) * a.W + px;

@@ -66,7 +66,17 @@ struct CompositeArgs {
     float bg0, bg1, bg2;
     float *rgb, *depth, *alpha, *t_final;
     uint32_t *n_contrib;
+    float *ckpt;          // segment checkpoints (optional)
+    uint64_t ckpt_floats;
 };
+
+// segmented backward: checkpoint layout [slot][quadrant][kCkptVals][64]
+constexpr uint32_t kSegment = GS_SEGMENT;
+constexpr int kCkptVals = 5;      // T, then colour r g b and depth behind, over T
+constexpr int kMaxSegments = 64;  // backward workgroups per list at most (the last takes the rest)
+__host__ __device__ inline uint64_t ckpt_index(uint64_t slot, int quad, int val, int lane) {
+    return ((slot * 4 + (uint64_t)quad) * kCkptVals + (uint64_t)val) * 64 + (uint64_t)lane;
+}
 
 struct BackwardTileArgs {
     const float4 *rec;
@@ -76,6 +86,8 @@ struct BackwardTileArgs {
     const uint32_t *n_contrib;
     const float *d_rgb, *d_depth, *d_alpha;
     float *g2d;  // [instances][kG2D]
+    const float *ckpt;  // segment checkpoints, or null (one segment per list)
+    uint64_t ckpt_floats;
     int64_t n_items;
     int32_t W, H, TX, T;
     float alpha_max, alpha_min;

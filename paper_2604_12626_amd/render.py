@@ -27,7 +27,7 @@ class Frame:
     def __init__(self):
         self.rgb = self.depth = self.alpha = self.t_final = self.n_contrib = None
         self.tiles_touched = self.rec = self.keys = self.vals = self.ranges = None
-        self.num = self.overflow = None
+        self.num = self.overflow = self.order = self.ckpt = None
 
 
 class Renderer:
@@ -38,8 +38,12 @@ class Renderer:
     cov6 [n,6] instead of log_scales/quats); cams: [V,16] float32 device
     tensor; view_segs: per-view lists of segment indices."""
 
-    def __init__(self, width, height, bg=(0.0, 0.0, 0.0), capacity=1 << 20, device="cuda", **overrides):
+    def __init__(self, width, height, bg=(0.0, 0.0, 0.0), capacity=1 << 20, device="cuda", checkpoints=False,
+                 **overrides):
+        """checkpoints: the forward records segment checkpoints so that the
+        backward differentiates long tile lists in parallel segments."""
         B.load()
+        self.checkpoints = bool(checkpoints)
         self.W, self.H = int(width), int(height)
         self.params = B.make_params(self.W, self.H, bg=bg, **overrides)
         self.TX = (self.W + B.TILE - 1) // B.TILE
@@ -60,7 +64,7 @@ class Renderer:
             self._bufs[name] = t
         return t[:n].view(*shape) if len(shape) else t[:1]
 
-    def alloc_frame(self, n_inst, n_views):
+    def alloc_frame(self, n_inst, n_views, ckpt=False):
         f = Frame()
         f.tiles_touched = self._buf("tt", (n_inst,), torch.int32)
         f.rec = self._buf("rec", (n_inst, B.REC_FLOATS), torch.float32)
@@ -68,6 +72,7 @@ class Renderer:
         f.vals = self._buf("vals", (self.capacity,), torch.int32)
         f.ranges = self._buf("ranges", (n_views * self.T, 2), torch.int32)
         f.order = self._buf("order", (B.tile_order_words(n_views, self.params),), torch.int32)
+        f.ckpt = self._buf("ckpt", (B.checkpoint_floats(self.capacity),), torch.float32) if ckpt else None
         f.num = self._buf("num", (1,), torch.int64)
         f.overflow = self._buf("ovf", (1,), torch.int32)
         ws = B.bin_sort_workspace(n_inst, self.capacity, n_views, self.params)
@@ -92,7 +97,7 @@ class Renderer:
 
     def composite(self, f, n_views):
         B.composite(f.rec, f.vals, f.ranges, n_views, self.params, f.comp_ws, f.rgb, f.depth, f.alpha, f.t_final,
-                    f.n_contrib, order=f.order)
+                    f.n_contrib, order=f.order, ckpt=f.ckpt)
 
     def enqueue(self, segs, cams, view_segs, f):
         """All forward stages, no host synchronisation."""
@@ -101,19 +106,22 @@ class Renderer:
         self.bin_sort(f, n_views)
         self.composite(f, n_views)
 
-    def render(self, segs, cams, view_segs=None, sync_check=True):
+    def render(self, segs, cams, view_segs=None, sync_check=True, checkpoints=None):
         """Eager forward.  Returns a Frame whose tensors are views of the
-        renderer's buffers (valid until the next call)."""
+        renderer's buffers (valid until the next call).  checkpoints (default:
+        the renderer's setting) records segment checkpoints for a faster
+        backward."""
         if view_segs is None:
             view_segs = [list(range(len(segs)))] * int(cams.shape[0])
+        ckpt = self.checkpoints if checkpoints is None else bool(checkpoints)
         n_views = len(view_segs)
         n_inst = B.instance_offsets(segs, view_segs)[-1]
-        f = self.alloc_frame(n_inst, n_views)
+        f = self.alloc_frame(n_inst, n_views, ckpt)
         self.project(segs, cams, view_segs, f)
         self.bin_sort(f, n_views)
         if sync_check and int(f.overflow.item()):
             self.capacity = min(_grow(int(f.num.item())), B.MAX_CAPACITY)
-            f = self.alloc_frame(n_inst, n_views)
+            f = self.alloc_frame(n_inst, n_views, ckpt)
             self.project(segs, cams, view_segs, f)
             self.bin_sort(f, n_views)
             if int(f.overflow.item()):
@@ -139,7 +147,7 @@ class Renderer:
             grads.append(d)
         ws = self._buf("bwd_ws", ((B.render_backward_workspace(f.n_inst) + 3) // 4,), torch.float32)
         B.render_backward(segs, cams, view_segs, self.params, f.tiles_touched, f.rec, f.vals, f.ranges, f.t_final,
-                          f.n_contrib, d_rgb, d_depth, d_alpha, ws, grads)
+                          f.n_contrib, d_rgb, d_depth, d_alpha, ws, grads, ckpt=f.ckpt)
         return grads
 
 
@@ -155,7 +163,7 @@ class _RasterizeFn(torch.autograd.Function):
         seg = {"means": means.contiguous(), "log_scales": log_scales.contiguous(), "quats": quats.contiguous(),
                "opacity": opacity.contiguous(), "sh": sh.contiguous(), "sh_degree": sh_degree}
         view_segs = [[0]] * int(cams.shape[0])
-        f = renderer.render([seg], cams, view_segs)
+        f = renderer.render([seg], cams, view_segs, checkpoints=True)
         ctx.renderer, ctx.seg, ctx.view_segs, ctx.frame = renderer, seg, view_segs, f
         ctx.save_for_backward(cams)
         return f.rgb.clone(), f.depth.clone(), f.alpha.clone()

@@ -118,14 +118,19 @@ def test_lbs_and_composite_validation(lib):
     assert lib.gs_deform_lbs(0, None, None, None, None, None, None, None, 1, 24, None, None, None) == B.GS_OK
     p = B.make_params(64, 64)
     proj = B.Projected(10, None, a)
-    st = lib.gs_composite(ctypes.byref(proj), a, a, None, 1, ctypes.byref(p), a, 8, a, a, a, None, None, None)
+    st = lib.gs_composite(ctypes.byref(proj), a, a, None, 1, ctypes.byref(p), a, 8, a, a, a, None, None, None, 0,
+                          None)
     assert st == B.GS_ERR_WORKSPACE_TOO_SMALL
-    st = lib.gs_composite(ctypes.byref(proj), None, a, None, 1, ctypes.byref(p), a, 256, a, a, a, None, None, None)
+    st = lib.gs_composite(ctypes.byref(proj), None, a, None, 1, ctypes.byref(p), a, 256, a, a, a, None, None, None,
+                          0, None)
     assert st == B.GS_ERR_INVALID_ARGUMENT
     ws = lib.gs_composite_workspace(1, ctypes.byref(p))
     st = lib.gs_composite(ctypes.byref(proj), a, a, ctypes.c_void_p(0x10002), 1, ctypes.byref(p), a, ws, a, a, a,
-                          None, None, None)
+                          None, None, None, 0, None)
     assert st == B.GS_ERR_INVALID_ARGUMENT  # misaligned work order
+    st = lib.gs_composite(ctypes.byref(proj), a, a, None, 1, ctypes.byref(p), a, ws, a, a, a, None, None,
+                          ctypes.c_void_p(0x10002), 100, None)
+    assert st == B.GS_ERR_INVALID_ARGUMENT  # misaligned checkpoints
 
 
 def test_tile_order_sizes(lib):
@@ -140,6 +145,10 @@ def test_tile_order_sizes(lib):
     p = B.make_params(64, 64)
     assert lib.gs_tile_order_words(0, ctypes.byref(p)) == 0
     assert lib.gs_tile_order_words(1, None) == 0
+    # segment checkpoints: one slot per GS_SEGMENT key slots (+1), 4 quadrants x 5 values x 64 pixels
+    for cap in (1, 63, 64, 1 << 20):
+        assert lib.gs_checkpoint_floats(cap) == (cap // 64 + 1) * 4 * 5 * 64
+    assert lib.gs_checkpoint_floats(0) == 0
 
 
 def test_tuning_validation():

@@ -374,19 +374,21 @@ def _max_rel_block(gpu, ref):
     return np.abs(gpu - ref).max() / max(np.abs(ref).max(), 1e-30)
 
 
-def test_backward_parity_sh3(dev, orc):
+@pytest.mark.parametrize("checkpoints", [False, True], ids=["whole_lists", "segmented"])
+def test_backward_parity_sh3(dev, orc, checkpoints):
     """Gradients of <G, render> for random output adjoints G (rgb, depth,
-    alpha) against the oracle's FP64 adjoint, on every Gaussian."""
+    alpha) against the oracle's FP64 adjoint, on every Gaussian; lists walked
+    whole, or in segments from the forward's checkpoints."""
     import torch
     from paper_2604_12626_amd import render
     cfg = synth.config(2, scale=0.04)  # 20k Gaussians, 256x256, SH3
     W, H = cfg["W"], cfg["H"]
     g = cfg["segments"][0]
-    say("backward parity: room20k 256x256 sh3")
+    say("backward parity: room20k 256x256 sh3, checkpoints", checkpoints)
     rng = np.random.default_rng(5)
     G = [rng.standard_normal((1, H, W, 3)).astype(F32), rng.standard_normal((1, H, W)).astype(F32),
          rng.standard_normal((1, H, W)).astype(F32)]
-    r = render.Renderer(W, H, capacity=1 << 18, device=dev)
+    r = render.Renderer(W, H, capacity=1 << 18, device=dev, checkpoints=checkpoints)
     tg = to_dev(g, dev)
     cams = torch.from_numpy(cfg["cams"]).to(dev)
     f = r.render([tg], cams, [[0]])
@@ -413,6 +415,41 @@ def test_backward_parity_sh3(dev, orc):
     for k in worst:
         assert worst[k] <= 1e-4, (k, worst[k])
         assert loose[k] <= 5e-2, (k, loose[k])
+
+
+def test_segmented_backward_matches_whole_lists(dev):
+    """With lists of thousands of entries (many segments each, and some longer
+    than the segment grid holds: 1M room Gaussians at five times their
+    scale, 256x256), the segmented backward equals the whole-list walk up to
+    rounding, on every parameter block, and the forward images do not depend
+    on whether checkpoints are recorded."""
+    import torch
+    from paper_2604_12626_amd import render
+    cfg = synth.config(2, scale=2.0)
+    W, H = cfg["W"], cfg["H"]
+    g0 = dict(cfg["segments"][0])
+    g0["log_scales"] = (g0["log_scales"] + np.log(5.0)).astype(F32)
+    g = to_dev(g0, dev)
+    cams = torch.from_numpy(cfg["cams"]).to(dev)
+    rng = np.random.default_rng(9)
+    G = [torch.from_numpy(rng.standard_normal(sh).astype(F32)).to(dev) for sh in ((1, H, W, 3), (1, H, W), (1, H, W))]
+    out = {}
+    for ck in (False, True):
+        r = render.Renderer(W, H, capacity=1 << 22, device=dev, checkpoints=ck)
+        f = r.render([g], cams, [[0]])
+        img = (f.rgb.clone(), f.depth.clone(), f.alpha.clone())
+        d = r.backward([g], cams, [[0]], f, *G)[0]
+        torch.cuda.synchronize()
+        out[ck] = (img, {k: v.cpu().numpy().astype(np.float64) for k, v in d.items()})
+        lens = (f.ranges[:, 1] - f.ranges[:, 0]).cpu().numpy()
+    say("  list length max %d, lists over 8 segments: %d" % (lens.max(), int((lens > 8 * 64).sum())))
+    assert lens.max() > 64 * 64, "the case must exceed the segment grid"
+    for a, b in zip(out[False][0], out[True][0]):
+        assert torch.equal(a, b)
+    for k, ref in out[False][1].items():
+        err = np.abs(out[True][1][k] - ref).max() / max(np.abs(ref).max(), 1e-30)
+        say("  %s: max |seg - whole| / max |whole| = %.2e" % (k, err))
+        assert err <= 1e-4, (k, err)
 
 
 def test_lbs_parity(dev, orc):
