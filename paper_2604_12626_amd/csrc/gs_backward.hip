@@ -69,7 +69,7 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
     // the rest of the list)
     static_assert(kSegment == 64, "a middle segment is one chunk");
     const uint32_t s = blockIdx.y;
-    const bool last_seg = !a.ckpt || s + 1u == gridDim.y;
+    const bool last_seg = !a.ckpt || s + 1u == a.n_seg;
     const uint32_t seg_lo = a.ckpt ? s * kSegment : 0u;
     // A middle segment is the one chunk from seg_lo: its list values, records
     // and end checkpoint are requested before the pixel state, so that the
@@ -229,10 +229,10 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
     }
 }
 
-hipError_t launch_backward_tiles(const BackwardTileArgs &a, hipStream_t s) {
+hipError_t launch_backward_tiles(BackwardTileArgs a, hipStream_t s) {
     if (a.n_items == 0) return hipSuccess;
-    return launch_kernel(backward_tile_kernel, dim3((unsigned)a.n_items, a.ckpt ? (unsigned)kMaxSegments : 1u),
-                         dim3(kTilePixels), s, a);
+    a.n_seg = a.ckpt ? (uint32_t)kMaxSegments : 1u;
+    return launch_kernel(backward_tile_kernel, dim3((unsigned)a.n_items, a.n_seg), dim3(kTilePixels), s, a);
 }
 
 // ---------------------------------------------------------------------------

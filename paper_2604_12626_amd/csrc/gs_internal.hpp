@@ -88,6 +88,7 @@ struct BackwardTileArgs {
     float *g2d;  // [instances][kG2D]
     const float *ckpt;  // segment checkpoints, or null (one segment per list)
     uint64_t ckpt_floats;
+    uint32_t n_seg;     // workgroups per list (grid y), set by the launcher
     int64_t n_items;
     int32_t W, H, TX, T;
     float alpha_max, alpha_min;
@@ -134,7 +135,7 @@ constexpr int kOrderQueues = 8, kOrderBins = 64;
 __host__ __device__ inline int64_t order_stride(int64_t n_items) { return (n_items + kOrderQueues - 1) / kOrderQueues; }
 hipError_t launch_tile_order(const uint32_t *ranges, int64_t n_items, uint32_t *order, hipStream_t s);
 hipError_t launch_composite(CompositeArgs a, int grid, hipStream_t s);
-hipError_t launch_backward_tiles(const BackwardTileArgs &a, hipStream_t s);
+hipError_t launch_backward_tiles(BackwardTileArgs a, hipStream_t s);
 hipError_t launch_backward_project(const BackwardProjectArgs &a, hipStream_t s);
 hipError_t launch_lbs(const LbsArgs &a, bool backward, hipStream_t s);
 
