@@ -158,7 +158,7 @@ def bench_fwd_bwd(args, dev, steps):
     tgt = [to_dev(synth.perturb(g, cfg["perturb_rng"]), dev)]
     cams = torch.from_numpy(cfg["cams"]).to(dev)
     vs = [[0]]
-    r = render.Renderer(cfg["W"], cfg["H"], capacity=1 << 21, device=dev, checkpoints=True)
+    r = render.Renderer(cfg["W"], cfg["H"], capacity=1 << 21, device=dev, checkpoints="auto")
     ft = r.render(tgt, cams, vs)
     rgb_t, depth_t = ft.rgb.clone(), ft.depth.clone()
     r.render(segs, cams, vs)  # sizes the key capacity for the timed parameters
@@ -207,9 +207,9 @@ def bench_batched(args, dev, steps):
 def bench_avatars(args, dev, steps):
     """1M room + 8 avatars x 50k Gaussians, 16 views at 640x480: LBS of the
     avatar Gaussians, then all views of room + posed avatars in one call
-    (forward), and the same with the backward (segment checkpoints recorded
-    by its forward) through the renderer and LBS to the canonical avatar
-    parameters (fwd+bwd)."""
+    (forward), and the same with the backward through the renderer and LBS
+    to the canonical avatar parameters (fwd+bwd; checkpoints "auto", which
+    leaves them off for 19200 tile lists)."""
     import torch
     from paper_2604_12626_amd import binding as B, render
     from paper_2604_12626_amd import synth
@@ -239,7 +239,7 @@ def bench_avatars(args, dev, steps):
         lbs()
         r.enqueue([room, posed], cams, vs, f)
 
-    rb = render.Renderer(cfg["W"], cfg["H"], capacity=1 << 24, device=dev, checkpoints=True)
+    rb = render.Renderer(cfg["W"], cfg["H"], capacity=1 << 24, device=dev, checkpoints="auto")
     fb = rb.render([room, posed], cams, vs)
 
     def frame_bwd():

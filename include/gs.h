@@ -294,7 +294,10 @@ gs_status gs_composite(const gs_projected *proj, const uint32_t *vals, const uin
                        size_t ckpt_floats, gs_stream_t stream);
 
 /* Floats of a compositing checkpoint buffer for `capacity` key slots:
- * (capacity / GS_SEGMENT + 1) * 4 * 5 * 64 (0 for capacity < 1). */
+ * (capacity / GS_SEGMENT + 1) * (4 * 5 * 64 + GS_SEGMENT + 2) + 1 (0 for
+ * capacity < 1): the checkpoint slots, then room for gs_render_backward's
+ * list of segments to walk (it rewrites that part; gs_composite never
+ * touches it). */
 size_t gs_checkpoint_floats(int64_t capacity);
 
 /* Workspace bytes gs_render_backward needs for n_instances instances. */
@@ -311,10 +314,12 @@ size_t gs_render_backward_workspace(int64_t n_instances);
  * segment and written densely (zeros for Gaussians no view sees).
  *  ckpt: the checkpoints gs_composite wrote for this frame (ckpt_floats
  *  floats), or NULL.  With them each tile list is walked in segments of
- *  GS_SEGMENT entries by separate workgroups, each starting from the state
- *  at its segment's end (the last segment, and every list without them,
- *  from t_final and the background), so long lists are differentiated in
- *  parallel; the two give the same gradients up to rounding.
+ *  GS_SEGMENT entries (at most 64 per list, the last taking the rest) by a
+ *  persistent grid that pops them from a list built here in the buffer's
+ *  tail, each segment starting from the state at its end (the last segment,
+ *  and every list without checkpoints, from t_final and the background), so
+ *  long lists are differentiated in parallel; the two give the same
+ *  gradients up to rounding.
  *  grads: host array of n_segs gradient descriptors (device pointers),
  *  overwritten.  ws: per-instance screen-space accumulators.
  * Errors: as gs_project, plus GS_ERR_WORKSPACE_TOO_SMALL. */

@@ -372,7 +372,7 @@ size_t gs_composite_workspace(int32_t n_views, const gs_params *p) {
 
 size_t gs_checkpoint_floats(int64_t capacity) {
     if (capacity < 1) return 0;
-    return (size_t)(capacity / (int64_t)gs::kSegment + 1) * 4 * gs::kCkptVals * 64;
+    return (size_t)(capacity / (int64_t)gs::kSegment + 1) * (gs::kCkptSlotFloats + gs::kListPerSlot) + 1;
 }
 
 gs_status gs_composite(const gs_projected *proj, const uint32_t *vals, const uint32_t *tile_ranges,
@@ -414,8 +414,8 @@ gs_status gs_composite(const gs_projected *proj, const uint32_t *vals, const uin
     a.alpha = alpha;
     a.t_final = t_final;
     a.n_contrib = n_contrib;
-    a.ckpt = ckpt_floats ? ckpt : nullptr;
-    a.ckpt_floats = ckpt_floats;
+    a.ckpt_slots = gs::ckpt_slots(ckpt_floats);
+    a.ckpt = a.ckpt_slots ? ckpt : nullptr;
     hipError_t e;
     // persistent waves: a tunable number of four-wave groups per CU, never
     // more waves than quadrant work items
@@ -490,8 +490,11 @@ gs_status gs_render_backward(const gs_gaussians *segs, int32_t n_segs, const gs_
     b.d_depth = d_depth;
     b.d_alpha = d_alpha;
     b.g2d = g2d;
-    b.ckpt = ckpt_floats ? ckpt : nullptr;
-    b.ckpt_floats = ckpt_floats;
+    b.ckpt_slots = gs::ckpt_slots(ckpt_floats);
+    b.ckpt = b.ckpt_slots ? ckpt : nullptr;
+    // the work list lives behind the checkpoints (the backward's own part of the buffer)
+    b.seg_list = b.ckpt ? reinterpret_cast<uint32_t *>(const_cast<float *>(ckpt) + b.ckpt_slots * gs::kCkptSlotFloats)
+                        : nullptr;
     b.W = p->width;
     b.H = p->height;
     b.TX = tiles_x(p);
@@ -503,7 +506,7 @@ gs_status gs_render_backward(const gs_gaussians *segs, int32_t n_segs, const gs_
     b.bg1 = p->bg[1];
     b.bg2 = p->bg[2];
     if (proj->n_instances > 0) {
-        e = gs::launch_backward_tiles(b, sm);
+        e = gs::launch_backward_tiles(b, cu_count(), sm);
         if (e != hipSuccess) return hip_fail(e, "gs_render_backward (tiles)");
     }
     for (int s = 0; s < n_segs; ++s) {

@@ -51,8 +51,14 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     float4 *e0s = s_e0[wave], *e1s = s_e1[wave], *e2s = s_e2[wave], *qs = s_q[wave];
-    // one workgroup per (view, tile); wave w owns the 8 x 8 quadrant w, one pixel per lane
-    const int64_t item = blockIdx.x;
+    // work: a (view, tile) list, or with checkpoints one segment of one (the
+    // listed pairs, popped by a persistent grid); wave w owns the 8 x 8
+    // quadrant w, one pixel per lane
+    const uint32_t n_work = a.seg_list ? a.seg_list[0] : (uint32_t)a.n_items;
+    for (uint32_t wk = blockIdx.x; wk < n_work; wk += a.n_groups) {
+    const uint32_t entry = a.seg_list ? a.seg_list[1 + wk] : 0u;
+    const int64_t item = a.seg_list ? (int64_t)(entry >> 6) : (int64_t)wk;
+    const uint32_t s = a.seg_list ? (entry & 63u) : 0u;
     const int view = (int)(item / a.T);
     const int tile = (int)(item - (int64_t)view * a.T);
     const int qx0 = (tile % a.TX) * kTile + ((wave & 1) << 3);
@@ -63,14 +69,12 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
     const float bx0 = (float)qx0 + 0.5f, by0 = (float)qy0 + 0.5f;
     const uint2 range = a.ranges[item];
     const uint32_t L = range.y - range.x;
-    if (blockIdx.y * kSegment >= L && blockIdx.y > 0) return;  // segment past the list
-    // this workgroup's segment [seg_lo, seg_hi) of list positions: all of
-    // them without checkpoints, else segment blockIdx.y (the last one takes
-    // the rest of the list)
-    static_assert(kSegment == 64, "a middle segment is one chunk");
-    const uint32_t s = blockIdx.y;
-    const bool last_seg = !a.ckpt || s + 1u == a.n_seg;
-    const uint32_t seg_lo = a.ckpt ? s * kSegment : 0u;
+    // this segment [seg_lo, seg_hi) of list positions: all of them without
+    // checkpoints, else segment s (the last one of the grid takes the rest of
+    // the list)
+    static_assert(kSegment == 64 && kMaxSegments <= 64, "a middle segment is one chunk; six bits name it");
+    const bool last_seg = !a.seg_list || s + 1u == (uint32_t)kMaxSegments;
+    const uint32_t seg_lo = a.seg_list ? s * kSegment : 0u;
     // A middle segment is the one chunk from seg_lo: its list values, records
     // and end checkpoint are requested before the pixel state, so that the
     // gather overlaps those loads (requests past what the walk needs are
@@ -85,7 +89,7 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
         p2 = a.rec[3 * (size_t)g_pre + 2];
     }
     const uint64_t slot = (range.x + seg_lo + kSegment) / kSegment;
-    const bool ck_ok = pre && seg_lo + kSegment < L && ckpt_index(slot, wave, kCkptVals - 1, 63) < a.ckpt_floats;
+    const bool ck_ok = pre && seg_lo + kSegment < L && slot < a.ckpt_slots;
     float ck[kCkptVals] = {1.0f, a.bg0, a.bg1, a.bg2, 0.0f};
     if (ck_ok) {
 #pragma unroll
@@ -114,7 +118,7 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
     maxlast = min(maxlast, L);
     const uint32_t seg_end = last_seg ? maxlast : seg_lo + kSegment;  // state known here
     const uint32_t seg_hi = seg_end < maxlast ? seg_end : maxlast;
-    if (seg_lo >= seg_hi) return;  // no barriers below: waves leave on their own
+    if (seg_lo >= seg_hi) continue;  // no barriers in the loop: waves move on on their own
     // suffix colour / depth behind the current entry over its transmittance:
     // the background at the end of the walk, else the checkpoint at seg_end
     float Sr = a.bg0, Sg = a.bg1, Sb = a.bg2, Sd = 0.0f;
@@ -227,12 +231,57 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
         }
         __builtin_amdgcn_wave_barrier();
     }
+    }  // work loop
 }
 
-hipError_t launch_backward_tiles(BackwardTileArgs a, hipStream_t s) {
+// The backward's work list (one workgroup): for every (view, tile) list of
+// L > 0 entries its min(ceil(L / 64), kMaxSegments) segments, as
+// (item << 6 | segment) in item order, after their count; at most `cap`.
+__global__ void __launch_bounds__(1024) segment_list_kernel(const uint2 *ranges, int64_t n_items, uint32_t *list,
+                                                            uint64_t cap) {
+    __shared__ uint32_t s_w[16];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t per = (n_items + 1023) / 1024;
+    const int64_t t0 = (int64_t)tid * per, t1 = (t0 + per < n_items) ? t0 + per : n_items;
+    auto n_seg = [](uint2 r) -> uint32_t {
+        const uint32_t c = (r.y - r.x + kSegment - 1u) / kSegment;
+        return c < (uint32_t)kMaxSegments ? c : (uint32_t)kMaxSegments;
+    };
+    uint32_t cnt = 0u;
+    for (int64_t t = t0; t < t1; ++t) cnt += n_seg(ranges[t]);
+    uint32_t incl = cnt;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
+    }
+    if (lane == 63) s_w[wave] = incl;
+    __syncthreads();
+    uint64_t pos = incl - cnt, total = 0u;
+    for (int k = 0; k < 16; ++k) {
+        if (k < wave) pos += s_w[k];
+        total += s_w[k];
+    }
+    for (int64_t t = t0; t < t1; ++t) {
+        const uint32_t c = n_seg(ranges[t]);
+        for (uint32_t q = 0; q < c; ++q, ++pos)
+            if (pos < cap) list[1 + pos] = ((uint32_t)t << 6) | q;
+    }
+    if (tid == 0) list[0] = (uint32_t)(total < cap ? total : cap);
+}
+
+hipError_t launch_backward_tiles(BackwardTileArgs a, int n_cu, hipStream_t s) {
     if (a.n_items == 0) return hipSuccess;
-    a.n_seg = a.ckpt ? (uint32_t)kMaxSegments : 1u;
-    return launch_kernel(backward_tile_kernel, dim3((unsigned)a.n_items, a.n_seg), dim3(kTilePixels), s, a);
+    if (a.seg_list && a.n_items >= (int64_t)1 << 26) a.seg_list = nullptr;  // item ids need 26 bits
+    if (!a.seg_list) {  // one workgroup per list
+        a.n_groups = (uint32_t)a.n_items;
+        return launch_kernel(backward_tile_kernel, dim3((unsigned)a.n_items), dim3(kTilePixels), s, a);
+    }
+    hipError_t e = launch_kernel(segment_list_kernel, dim3(1), dim3(1024), s, a.ranges, a.n_items, a.seg_list,
+                                 (uint64_t)(a.ckpt_slots * kListPerSlot));
+    if (e != hipSuccess) return e;
+    a.n_groups = (uint32_t)(6 * n_cu);  // persistent: about what the CUs hold at once
+    return launch_kernel(backward_tile_kernel, dim3(a.n_groups), dim3(kTilePixels), s, a);
 }
 
 // ---------------------------------------------------------------------------

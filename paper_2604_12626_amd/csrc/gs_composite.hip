@@ -167,7 +167,7 @@ __global__ void __launch_bounds__(64 * kWavesPerGroup) composite_kernel(const Co
             done_end = b0 - range.x + 64u;
             if (a.ckpt && done_end % kSegment == 0u && done_end < range.y - range.x) {
                 const uint64_t slot = (range.x + done_end) / kSegment;
-                if (ckpt_index(slot, quad, kCkptVals - 1, 63) < a.ckpt_floats) {
+                if (slot < a.ckpt_slots) {
                     a.ckpt[ckpt_index(slot, quad, 0, lane)] = T;
                     a.ckpt[ckpt_index(slot, quad, 1, lane)] = cr;
                     a.ckpt[ckpt_index(slot, quad, 2, lane)] = cg;
@@ -183,7 +183,7 @@ __global__ void __launch_bounds__(64 * kWavesPerGroup) composite_kernel(const Co
         if (a.ckpt) {
             for (uint32_t b = kSegment; b < done_end && b < range.y - range.x; b += kSegment) {
                 const uint64_t slot = (range.x + b) / kSegment;
-                if (ckpt_index(slot, quad, kCkptVals - 1, 63) >= a.ckpt_floats) break;
+                if (slot >= a.ckpt_slots) break;
                 float *c = a.ckpt;
                 const float tb = c[ckpt_index(slot, quad, 0, lane)];
                 const float inv = 1.0f / tb;

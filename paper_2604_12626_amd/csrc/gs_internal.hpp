@@ -67,13 +67,21 @@ struct CompositeArgs {
     float *rgb, *depth, *alpha, *t_final;
     uint32_t *n_contrib;
     float *ckpt;          // segment checkpoints (optional)
-    uint64_t ckpt_floats;
+    uint64_t ckpt_slots;  // checkpoint slots the buffer holds
 };
 
-// segmented backward: checkpoint layout [slot][quadrant][kCkptVals][64]
+// Segmented backward.  Checkpoint buffer: S slots of [quadrant][kCkptVals][64]
+// floats, then the backward's work list (a count, then up to kListPerSlot
+// entries per slot: a list has at most ceil(L / kSegment) segments, and the L
+// sum to at most 64 S keys), S taken from the buffer's size.
 constexpr uint32_t kSegment = GS_SEGMENT;
 constexpr int kCkptVals = 5;      // T, then colour r g b and depth behind, over T
-constexpr int kMaxSegments = 64;  // backward workgroups per list at most (the last takes the rest)
+constexpr int kMaxSegments = 64;  // segments per list at most (the last takes the rest)
+constexpr uint64_t kCkptSlotFloats = 4 * kCkptVals * 64;
+constexpr uint64_t kListPerSlot = kSegment + 2;
+__host__ __device__ inline uint64_t ckpt_slots(uint64_t floats) {
+    return floats > 0 ? (floats - 1) / (kCkptSlotFloats + kListPerSlot) : 0;
+}
 __host__ __device__ inline uint64_t ckpt_index(uint64_t slot, int quad, int val, int lane) {
     return ((slot * 4 + (uint64_t)quad) * kCkptVals + (uint64_t)val) * 64 + (uint64_t)lane;
 }
@@ -86,9 +94,10 @@ struct BackwardTileArgs {
     const uint32_t *n_contrib;
     const float *d_rgb, *d_depth, *d_alpha;
     float *g2d;  // [instances][kG2D]
-    const float *ckpt;  // segment checkpoints, or null (one segment per list)
-    uint64_t ckpt_floats;
-    uint32_t n_seg;     // workgroups per list (grid y), set by the launcher
+    const float *ckpt;   // segment checkpoints, or null (one walk per list)
+    uint64_t ckpt_slots;
+    uint32_t *seg_list;  // (item << 6 | segment) of every segment to walk, after a count
+    uint32_t n_groups;   // workgroups of the persistent grid (set by the launcher)
     int64_t n_items;
     int32_t W, H, TX, T;
     float alpha_max, alpha_min;
@@ -135,7 +144,7 @@ constexpr int kOrderQueues = 8, kOrderBins = 64;
 __host__ __device__ inline int64_t order_stride(int64_t n_items) { return (n_items + kOrderQueues - 1) / kOrderQueues; }
 hipError_t launch_tile_order(const uint32_t *ranges, int64_t n_items, uint32_t *order, hipStream_t s);
 hipError_t launch_composite(CompositeArgs a, int grid, hipStream_t s);
-hipError_t launch_backward_tiles(BackwardTileArgs a, hipStream_t s);
+hipError_t launch_backward_tiles(BackwardTileArgs a, int n_cu, hipStream_t s);
 hipError_t launch_backward_project(const BackwardProjectArgs &a, hipStream_t s);
 hipError_t launch_lbs(const LbsArgs &a, bool backward, hipStream_t s);
 

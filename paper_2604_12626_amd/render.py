@@ -38,12 +38,20 @@ class Renderer:
     cov6 [n,6] instead of log_scales/quats); cams: [V,16] float32 device
     tensor; view_segs: per-view lists of segment indices."""
 
+    # Segment checkpoints pay off while the (view, tile) lists alone leave
+    # the GPU short of waves (four per list): up to this many lists.
+    AUTO_CHECKPOINT_ITEMS = 2048
+
     def __init__(self, width, height, bg=(0.0, 0.0, 0.0), capacity=1 << 20, device="cuda", checkpoints=False,
                  **overrides):
-        """checkpoints: the forward records segment checkpoints so that the
-        backward differentiates long tile lists in parallel segments."""
+        """checkpoints: True / False / "auto" -- the forward records segment
+        checkpoints so that the backward differentiates long tile lists in
+        parallel segments ("auto": when there are at most
+        AUTO_CHECKPOINT_ITEMS (view, tile) lists)."""
         B.load()
-        self.checkpoints = bool(checkpoints)
+        if checkpoints not in (True, False, "auto"):
+            raise ValueError("checkpoints must be True, False or 'auto'")
+        self.checkpoints = checkpoints
         self.W, self.H = int(width), int(height)
         self.params = B.make_params(self.W, self.H, bg=bg, **overrides)
         self.TX = (self.W + B.TILE - 1) // B.TILE
@@ -109,12 +117,13 @@ class Renderer:
     def render(self, segs, cams, view_segs=None, sync_check=True, checkpoints=None):
         """Eager forward.  Returns a Frame whose tensors are views of the
         renderer's buffers (valid until the next call).  checkpoints (default:
-        the renderer's setting) records segment checkpoints for a faster
-        backward."""
+        the renderer's setting; True, False or "auto") records segment
+        checkpoints for a faster backward."""
         if view_segs is None:
             view_segs = [list(range(len(segs)))] * int(cams.shape[0])
-        ckpt = self.checkpoints if checkpoints is None else bool(checkpoints)
+        mode = self.checkpoints if checkpoints is None else checkpoints
         n_views = len(view_segs)
+        ckpt = (n_views * self.T <= self.AUTO_CHECKPOINT_ITEMS) if mode == "auto" else bool(mode)
         n_inst = B.instance_offsets(segs, view_segs)[-1]
         f = self.alloc_frame(n_inst, n_views, ckpt)
         self.project(segs, cams, view_segs, f)
@@ -163,7 +172,7 @@ class _RasterizeFn(torch.autograd.Function):
         seg = {"means": means.contiguous(), "log_scales": log_scales.contiguous(), "quats": quats.contiguous(),
                "opacity": opacity.contiguous(), "sh": sh.contiguous(), "sh_degree": sh_degree}
         view_segs = [[0]] * int(cams.shape[0])
-        f = renderer.render([seg], cams, view_segs, checkpoints=True)
+        f = renderer.render([seg], cams, view_segs, checkpoints="auto")
         ctx.renderer, ctx.seg, ctx.view_segs, ctx.frame = renderer, seg, view_segs, f
         ctx.save_for_backward(cams)
         return f.rgb.clone(), f.depth.clone(), f.alpha.clone()

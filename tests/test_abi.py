@@ -145,9 +145,10 @@ def test_tile_order_sizes(lib):
     p = B.make_params(64, 64)
     assert lib.gs_tile_order_words(0, ctypes.byref(p)) == 0
     assert lib.gs_tile_order_words(1, None) == 0
-    # segment checkpoints: one slot per GS_SEGMENT key slots (+1), 4 quadrants x 5 values x 64 pixels
+    # segment checkpoints: one slot per GS_SEGMENT key slots (+1), 4 quadrants x 5 values x 64
+    # pixels, and GS_SEGMENT + 2 words of the backward's work list per slot, plus its count
     for cap in (1, 63, 64, 1 << 20):
-        assert lib.gs_checkpoint_floats(cap) == (cap // 64 + 1) * 4 * 5 * 64
+        assert lib.gs_checkpoint_floats(cap) == (cap // 64 + 1) * (4 * 5 * 64 + 66) + 1
     assert lib.gs_checkpoint_floats(0) == 0
 
 

@@ -430,15 +430,18 @@ def test_segmented_backward_matches_whole_lists(dev):
     g0 = dict(cfg["segments"][0])
     g0["log_scales"] = (g0["log_scales"] + np.log(5.0)).astype(F32)
     g = to_dev(g0, dev)
-    cams = torch.from_numpy(cfg["cams"]).to(dev)
+    # two views: the work list spans several views' tiles
+    cam2 = synth.camera_room(np.random.default_rng(21), W, H, fx=128.0)[None]
+    cams = torch.from_numpy(np.concatenate([cfg["cams"], cam2]).astype(F32)).to(dev)
+    V = 2
     rng = np.random.default_rng(9)
-    G = [torch.from_numpy(rng.standard_normal(sh).astype(F32)).to(dev) for sh in ((1, H, W, 3), (1, H, W), (1, H, W))]
+    G = [torch.from_numpy(rng.standard_normal(sh).astype(F32)).to(dev) for sh in ((V, H, W, 3), (V, H, W), (V, H, W))]
     out = {}
     for ck in (False, True):
         r = render.Renderer(W, H, capacity=1 << 22, device=dev, checkpoints=ck)
-        f = r.render([g], cams, [[0]])
+        f = r.render([g], cams, [[0]] * V)
         img = (f.rgb.clone(), f.depth.clone(), f.alpha.clone())
-        d = r.backward([g], cams, [[0]], f, *G)[0]
+        d = r.backward([g], cams, [[0]] * V, f, *G)[0]
         torch.cuda.synchronize()
         out[ck] = (img, {k: v.cpu().numpy().astype(np.float64) for k, v in d.items()})
         lens = (f.ranges[:, 1] - f.ranges[:, 0]).cpu().numpy()
