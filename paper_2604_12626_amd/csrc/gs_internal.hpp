@@ -385,19 +385,22 @@ __device__ __forceinline__ Entry make_entry(const float4 q0, const float4 q1, co
 // d^T Q d <= 2 tau with tau = ln(o / alpha_min); the test uses the bounding
 // box of that ellipse with tau widened by 1% + 0.1 + 1e-5 cond(Q), which
 // exceeds the FP32 rounding of the exponent the compositing loop evaluates,
-// so culling never changes a result.
+// so culling never changes a result.  The bound is evaluated with the
+// hardware reciprocal, logarithm and square root (errors of a few ulp, far
+// inside the widening), since it runs for every list entry of every quadrant.
 __device__ __forceinline__ bool entry_reaches_box(float u, float v, float A, float B, float C, float o,
                                                   float alpha_min, float bx0, float by0, float bx1, float by1) {
     if (!(o >= alpha_min)) return false;
     const float detq = A * C - B * B;
     if (!(detq > 0.0f)) return true;
-    const float tau = logf(o / alpha_min);
+    const float rdet = __builtin_amdgcn_rcpf(detq);
+    constexpr float kLn2 = 0.693147180559945f;
+    const float tau = (__builtin_amdgcn_logf(o) - __builtin_amdgcn_logf(alpha_min)) * kLn2;
     const float tr = A + C;
-    const float cond = tr * tr / detq;
-    const float t2 = 1.01f * tau + 0.1f + 1e-5f * cond;
-    const float inv = 2.0f * t2 / detq;
-    const float ex = sqrtf(inv * C) * 1.01f + 0.02f;
-    const float ey = sqrtf(inv * A) * 1.01f + 0.02f;
+    const float t2 = fmaf(1.01f, tau, 0.1f) + 1e-5f * (tr * tr * rdet);
+    const float inv = 2.0f * t2 * rdet;
+    const float ex = fmaf(__builtin_amdgcn_sqrtf(inv * C), 1.01f, 0.02f);
+    const float ey = fmaf(__builtin_amdgcn_sqrtf(inv * A), 1.01f, 0.02f);
     if (!(u + ex >= bx0 && u - ex <= bx1 && v + ey >= by0 && v - ey <= by1)) return false;
     // The box meets the ellipse's bounding box; test the ellipse itself: the
     // minimum over the box of 1/2 d^T Q d (centre inside: 0; else on one of
@@ -406,12 +409,14 @@ __device__ __forceinline__ bool entry_reaches_box(float u, float v, float A, flo
     const float x0 = bx0 - 0.02f, x1 = bx1 + 0.02f, y0 = by0 - 0.02f, y1 = by1 + 0.02f;
     if (u >= x0 && u <= x1 && v >= y0 && v <= y1) return true;
     const float lx0 = x0 - u, lx1 = x1 - u, ly0 = y0 - v, ly1 = y1 - v;
+    // A, C > 0 here (A C > B^2 >= 0); the slopes of the best point on an edge
+    const float sy = -B * __builtin_amdgcn_rcpf(C), sx = -B * __builtin_amdgcn_rcpf(A);
     float qmin = INFINITY;
     {  // vertical edges: dx fixed, best dy = -B dx / C
         const float dx[2] = {lx0, lx1};
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
-            const float dy = fminf(fmaxf(-B * dx[k] / C, ly0), ly1);
+            const float dy = fminf(fmaxf(sy * dx[k], ly0), ly1);
             qmin = fminf(qmin, 0.5f * (A * dx[k] * dx[k] + C * dy * dy) + B * dx[k] * dy);
         }
     }
@@ -419,7 +424,7 @@ __device__ __forceinline__ bool entry_reaches_box(float u, float v, float A, flo
         const float dy[2] = {ly0, ly1};
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
-            const float dx = fminf(fmaxf(-B * dy[k] / A, lx0), lx1);
+            const float dx = fminf(fmaxf(sx * dy[k], lx0), lx1);
             qmin = fminf(qmin, 0.5f * (A * dx * dx + C * dy[k] * dy[k]) + B * dx * dy[k]);
         }
     }
