@@ -1181,7 +1181,9 @@ hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec
     else
         sweep = P.lookback >= 64 ? onesweep_kernel<16, 64> : P.lookback >= 32 ? onesweep_kernel<16, 32>
                                                                                : onesweep_kernel<16, 16>;
-    int64_t sg = (int64_t)n_cu;
+    // two persistent workgroups per CU (the LDS of each allows two): while
+    // one waits on its look-back or loads, the other ranks or scatters
+    int64_t sg = 2 * (int64_t)n_cu;
     const int64_t parts_used = (P.capacity + part_keys - 1) / part_keys;
     if (sg > parts_used) sg = parts_used;
     if (sg < 1) sg = 1;
