@@ -170,3 +170,13 @@ def test_tuning_validation():
                                   "sort_algorithm": 0}
     finally:
         B.set_tuning(**prev)
+
+
+def test_renderer_checkpoint_modes():
+    # True / False / "auto" only; "auto" records checkpoints up to the item limit
+    from paper_2604_12626_amd import render
+    import pytest as _pt
+    with _pt.raises(ValueError):
+        render.Renderer(64, 64, device="cpu", checkpoints="sometimes")
+    r = render.Renderer(64, 64, device="cpu", checkpoints="auto")
+    assert r.checkpoints == "auto" and r.T * 1 <= render.Renderer.AUTO_CHECKPOINT_ITEMS
