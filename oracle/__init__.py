@@ -328,3 +328,45 @@ def lbs_backward(means, log_scales, quats, w_dense, avatar_of, skin, n_joints, d
                         _p(np.ascontiguousarray(avatar_of, dtype=np.int32)), _p(_f32(skin)), n_joints,
                         _p(_f32(d_means_out)), _p(_f32(d_cov6_out)), _p(dm), _p(ds), _p(dq))
     return dm, ds, dq
+
+
+def sensor_compose(rgb, depth, alpha, mesh_rgba=None, mesh_depth=None):
+    """Sensor hand-off: the observation the RGB and depth sensors deliver.
+
+    Sec. 3.4 asks for RGB and depth in the mesh renderer's format (8-bit RGBA
+    and metric depth); Sec. 3.2 resolves occlusion against a mesh pass by
+    keeping, per pixel, the nearer of the 3DGS fragment (C_g, D_g) and the
+    mesh fragment (C_m, D_m), the mesh winning ties.  Because this turns
+    floats into byte codes and a comparison, it is written in FP32 (the
+    precision the decision is taken in), pixel-wise:
+      3DGS fragment where alpha > 0, D_g = depth / alpha;
+      bytes rint(clip(c, 0, 1) * 255) (nearest even; NaN -> 0), fourth byte 255;
+      mesh fragment where mesh_depth > 0 (NaN: none), bytes copied;
+      neither: the 3DGS colour and depth 0.
+    Shapes: rgb [..., 3], depth and alpha [...], mesh_rgba uint8 [..., 4],
+    mesh_depth [...].  Returns (rgba uint8 [..., 4], depth float32 [...]).
+    """
+    rgb = np.asarray(rgb, np.float32)
+    depth = np.asarray(depth, np.float32)
+    alpha = np.asarray(alpha, np.float32)
+    one, zero = np.float32(1.0), np.float32(0.0)
+    clipped = np.where(rgb > zero, np.minimum(rgb, one), zero)
+    codes = np.rint(clipped * np.float32(255.0)).astype(np.uint8)
+    out_rgba = np.empty(depth.shape + (4,), np.uint8)
+    out_rgba[..., :3] = codes
+    out_rgba[..., 3] = 255
+    gs_frag = alpha > zero
+    d_g = np.zeros_like(depth)
+    np.divide(depth, alpha, out=d_g, where=gs_frag)
+    out_depth = np.where(gs_frag, d_g, zero).astype(np.float32)
+    if mesh_rgba is not None:
+        mesh_rgba = np.asarray(mesh_rgba, np.uint8)
+        mesh_depth = np.asarray(mesh_depth, np.float32)
+        with np.errstate(invalid="ignore"):
+            mesh_frag = mesh_depth > zero
+            nearer = d_g < mesh_depth
+        keep_gs = gs_frag & (~mesh_frag | nearer)
+        take_mesh = mesh_frag & ~keep_gs
+        out_rgba[take_mesh] = mesh_rgba[take_mesh]
+        out_depth[take_mesh] = mesh_depth[take_mesh]
+    return out_rgba, out_depth

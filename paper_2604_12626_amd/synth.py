@@ -288,6 +288,41 @@ def synthetic_records(rng, counts, W, H, tie_frac=0.05, vis_frac=0.9, r_median=8
 # --------------------------------------------------------------------------
 # the five workloads
 # --------------------------------------------------------------------------
+def sensor_inputs(seed, n_views, H, W, mesh=True):
+    """Compositing-output and mesh-pass stand-ins for the sensor hand-off:
+    rgb in [-0.1, 1.1] with a few special values (NaN, +-inf, exact k/255
+    steps), alpha 0 on 20% of the pixels and 1 on 10%, accumulated depth
+    alpha * U[0.3, 10], mesh depth U[0.3, 10] with 15% zeros, 3% negatives
+    and 2% NaN, and on 5% of the pixels (those with alpha 1) a mesh depth equal
+    to the accumulated depth (exact ties).  Returns a dict of float32 / uint8
+    arrays [V, H, W(, C)]."""
+    rng = np.random.default_rng(seed)
+    shp = (n_views, H, W)
+    rgb = rng.uniform(-0.1, 1.1, shp + (3,))
+    u = rng.random(shp + (3,))
+    rgb[u < 0.02] = np.round(rgb[u < 0.02] * 255.0) / 255.0
+    rgb = rgb.astype(np.float32)
+    flat = rgb.reshape(-1)
+    sp = rng.integers(0, flat.size, max(4, flat.size // 500))
+    flat[sp] = np.array([np.nan, np.inf, -np.inf, 0.5], np.float32)[np.arange(sp.size) % 4]
+    a = rng.random(shp)
+    alpha = np.where(a < 0.2, 0.0, np.where(a < 0.3, 1.0, rng.uniform(1e-4, 1.0, shp))).astype(np.float32)
+    depth = (alpha.astype(np.float64) * rng.uniform(0.3, 10.0, shp)).astype(np.float32)
+    out = {"rgb": rgb, "depth": depth, "alpha": alpha}
+    if mesh:
+        m = rng.random(shp)
+        md = rng.uniform(0.3, 10.0, shp)
+        md[m < 0.15] = 0.0
+        md[(m >= 0.15) & (m < 0.18)] = -1.0
+        md[(m >= 0.18) & (m < 0.20)] = np.nan
+        md = md.astype(np.float32)
+        tie = (alpha == 1.0) & (rng.random(shp) < 0.5)
+        md[tie] = depth[tie]
+        out["mesh_depth"] = md
+        out["mesh_rgba"] = rng.integers(0, 256, shp + (4,), dtype=np.uint8)
+    return out
+
+
 def config(idx, scale=1.0):
     """Inputs of workload `idx` (0..4).  `scale` < 1 shrinks Gaussian counts
     (for the oracle-sized parity cases); resolutions and structure are kept.

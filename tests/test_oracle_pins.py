@@ -446,3 +446,98 @@ def test_candidate_enumeration_covers_near_threshold_skip(orc):
     assert ncand[8, 8] == 2
     vals = sorted(cands[8, 8, :2, 4])
     assert vals[0] == 0.0 and abs(vals[1] - orc.ALPHA_MIN) < 1e-8
+
+
+# --------------------------------------------------------------------------
+# Sensor hand-off: 8-bit colour codes, metric depth and the nearer-fragment
+# rule (Sec. 3.2, Sec. 3.4)
+# --------------------------------------------------------------------------
+def test_sensor_codes_closed_forms(orc):
+    # c = k / 255 gives exactly byte k; out-of-range values saturate; NaN -> 0
+    k = np.arange(256)
+    c = (k / 255.0).astype(F32)
+    rgb = np.stack([c, c[::-1], np.zeros_like(c)], -1)[None]
+    rgba, _ = orc.sensor_compose(rgb, np.ones((1, 256), F32), np.ones((1, 256), F32))
+    assert np.array_equal(rgba[0, :, 0], k) and np.array_equal(rgba[0, :, 1], k[::-1])
+    assert np.all(rgba[..., 2] == 0) and np.all(rgba[..., 3] == 255)
+    sp = np.array([-1.0, -0.0, 0.5, 0.25, 0.75, 1.0, 2.0, np.inf, -np.inf, np.nan, 1e-30, 3e38], F32)
+    want = [0, 0, 128, 64, 191, 255, 255, 255, 0, 0, 0, 255]  # 127.5 -> 128, 63.75 -> 64, 191.25 -> 191
+    rgba, _ = orc.sensor_compose(np.repeat(sp[:, None], 3, 1), np.ones(len(sp), F32), np.ones(len(sp), F32))
+    assert rgba[:, 0].tolist() == want
+
+
+def test_sensor_codes_error_bound_and_monotone(orc):
+    # |code - 255 c| <= 1/2 (plus the FP32 product's rounding) and codes never
+    # decrease as c grows, over a dense sweep of [0, 1]
+    c = np.sort(np.random.default_rng(5).random(200000).astype(F32))
+    c = np.concatenate([c, np.linspace(0, 1, 100001, dtype=F32)])
+    c.sort()
+    rgba, _ = orc.sensor_compose(np.repeat(c[:, None], 3, 1), np.ones(len(c), F32), np.ones(len(c), F32))
+    code = rgba[:, 0].astype(np.float64)
+    assert np.all(np.abs(code - 255.0 * c.astype(np.float64)) <= 0.5 + 1e-4)
+    assert np.all(np.diff(code) >= 0)
+
+
+def test_sensor_metric_depth_of_one_depth_layer(orc):
+    # every fragment of a pixel at one depth z: accumulated depth / alpha = z
+    r1 = _rec(7.5, 8.5, 2.5, 20, 0.05, 0.01, 0.08, 0.6, [0.2, 0.5, 0.9])
+    r2 = _rec(6.0, 9.0, 2.5, 20, 0.02, -0.005, 0.03, 0.8, [0.9, 0.1, 0.4])
+    img, _, _ = _composite_records(orc, [r1, r2])
+    _, d = orc.sensor_compose(img[None, :, :, :3], img[None, :, :, 3], img[None, :, :, 4])
+    covered = img[:, :, 4] > 0
+    assert covered.sum() > 100
+    assert np.allclose(d[0][covered], 2.5, rtol=1e-6) and np.all(d[0][~covered] == 0)
+    # two layers: the metric depth is an alpha-weighted mean, inside [z1, z2]
+    r3 = _rec(8.0, 8.0, 4.0, 20, 0.01, 0.0, 0.01, 0.9, [0.0, 1.0, 0.0])
+    img, _, _ = _composite_records(orc, [r1, r3])
+    _, d = orc.sensor_compose(img[None, :, :, :3], img[None, :, :, 3], img[None, :, :, 4])
+    cov = img[:, :, 4] > 0
+    assert np.all(d[0][cov] >= 2.5 * (1 - 1e-6)) and np.all(d[0][cov] <= 4.0 * (1 + 1e-6))
+
+
+def test_sensor_nearer_fragment_rule(orc):
+    # (alpha, accumulated depth, mesh depth) -> which fragment the pixel keeps
+    cases = [
+        (0.5, 1.0, 3.0, "gs"),      # D_g = 2 < 3
+        (0.5, 2.0, 3.0, "mesh"),    # D_g = 4 > 3
+        (0.5, 1.5, 3.0, "mesh"),    # tie: the mesh wins
+        (0.0, 0.0, 3.0, "mesh"),    # no 3DGS fragment
+        (0.5, 1.0, 0.0, "gs"),      # no mesh fragment
+        (0.5, 1.0, -1.0, "gs"),
+        (0.5, 1.0, np.nan, "gs"),
+        (0.0, 0.0, 0.0, "none"),    # neither: background colour, depth 0
+        (0.5, 1.0, np.inf, "gs"),
+        (0.0, 0.0, np.inf, "mesh"),
+    ]
+    n = len(cases)
+    al = np.array([c[0] for c in cases], F32)
+    dd = np.array([c[1] for c in cases], F32)
+    md = np.array([c[2] for c in cases], F32)
+    rgb = np.tile(np.array([0.25, 0.5, 1.0], F32), (n, 1))
+    mesh = np.tile(np.array([9, 8, 7, 6], np.uint8), (n, 1))
+    rgba, d = orc.sensor_compose(rgb, dd, al, mesh, md)
+    for i, (a, acc, m, who) in enumerate(cases):
+        if who == "gs":
+            assert rgba[i].tolist() == [64, 128, 255, 255] and d[i] == F32(acc) / F32(a)
+        elif who == "mesh":
+            assert rgba[i].tolist() == [9, 8, 7, 6] and d[i] == F32(m)
+        else:
+            assert rgba[i].tolist() == [64, 128, 255, 255] and d[i] == 0
+
+
+def test_sensor_mesh_invariants(orc):
+    rng = np.random.default_rng(11)
+    V, H, W = 2, 9, 13
+    rgb = rng.random((V, H, W, 3)).astype(F32)
+    al = np.where(rng.random((V, H, W)) < 0.2, 0, rng.random((V, H, W))).astype(F32)
+    dd = (al * rng.uniform(0.5, 6.0, (V, H, W))).astype(F32)
+    mesh = rng.integers(0, 256, (V, H, W, 4), dtype=np.uint8)
+    plain = orc.sensor_compose(rgb, dd, al)
+    # a mesh pass that covers nothing changes nothing
+    empty = orc.sensor_compose(rgb, dd, al, mesh, np.zeros((V, H, W), F32))
+    assert np.array_equal(plain[0], empty[0]) and np.array_equal(plain[1], empty[1])
+    # a mesh wall at depth m: the observed depth is min(D_g, m) where both exist
+    m = F32(3.0)
+    rgba, d = orc.sensor_compose(rgb, dd, al, mesh, np.full((V, H, W), m, F32))
+    has = al > 0
+    assert np.array_equal(d[has], np.minimum(plain[1][has], m)) and np.all(d[~has] == m)
