@@ -255,6 +255,29 @@ def bench_avatars(args, dev, steps):
     return ms, ms_b, len(vs)
 
 
+def bench_sensor(args, dev, steps):
+    """Sensor hand-off of 16 views at 640x480 against a mesh pass: HBM-bound,
+    28 B read + 8 B written per pixel.  Returns (ms per call, fraction of the
+    HBM peak)."""
+    import torch
+    from paper_2604_12626_amd import render, synth
+    d = synth.sensor_inputs(7, 16, 480, 640, mesh=True)
+    t = {k: torch.from_numpy(v).to(dev) for k, v in d.items()}
+    out = render.observation(t["rgb"], t["depth"], t["alpha"], t["mesh_rgba"], t["mesh_depth"])
+    reps = 20 * steps
+    for _ in range(args.warmup):
+        render.observation(t["rgb"], t["depth"], t["alpha"], t["mesh_rgba"], t["mesh_depth"], out=out)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        render.observation(t["rgb"], t["depth"], t["alpha"], t["mesh_rgba"], t["mesh_depth"], out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    n_px = 16 * 480 * 640
+    return ms, n_px * 36 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS
+
+
 def _time_seq(fn, warmup, steps):
     import torch
     for _ in range(warmup):
@@ -378,6 +401,10 @@ def main():
         ms_a, ms_ab, nva = bench_avatars(args, dev, steps2)
         extras["avatars_16x640x480_fwd_fps"] = nva * 1e3 / ms_a
         extras["avatars_16x640x480_fwd_bwd_fps"] = nva * 1e3 / ms_ab
+        log("sensor hand-off: 16 views x 640x480 with a mesh pass")
+        ms_s, frac_s = bench_sensor(args, dev, steps2)
+        extras["sensor_16x640x480_mesh_ms"] = ms_s
+        extras["sensor_16x640x480_mesh_hbm_frac"] = frac_s
     cpu, pairs = None, None
     if not args.profile and not args.no_cpu_baseline:
         log("cpu baseline (oracle)")

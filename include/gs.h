@@ -330,6 +330,38 @@ gs_status gs_render_backward(const gs_gaussians *segs, int32_t n_segs, const gs_
                              const float *d_depth, const float *d_alpha, void *ws, size_t ws_bytes,
                              const gs_gaussians_grad *grads, gs_stream_t stream);
 
+/* ---------------------------------------------------------------------- */
+/* sensor hand-off (Sec. 3.2 occlusion rule, Sec. 3.4 sensor format)       */
+/* ---------------------------------------------------------------------- */
+/* Turns the compositing outputs of n_views views of height x width pixels
+ * into what the simulator's RGB and depth sensors deliver, and optionally
+ * resolves occlusion against a mesh pass by the nearer-fragment rule of
+ * Sec. 3.2: per pixel, the colour and depth of whichever pass is nearer.
+ *  in:  rgb [V][H][W][3], depth [V][H][W] (accumulated z-depth) and alpha
+ *       [V][H][W], as gs_composite writes them;
+ *       mesh_rgba uint8 [V][H][W][4] and mesh_depth [V][H][W] (metric
+ *       depth) of a mesh pass, or both NULL when there is none.
+ *  out: out_rgba uint8 [V][H][W][4], out_depth [V][H][W] (metric depth).
+ * Per pixel, all in FP32:
+ *  - the 3DGS fragment exists where alpha > 0; its depth is
+ *    D_g = depth / alpha (correctly rounded division) and its colour bytes
+ *    are rint(min(max(c, 0), 1) * 255) per channel (round to nearest even;
+ *    NaN gives 0), with 255 in the fourth byte;
+ *  - the mesh fragment exists where mesh_depth > 0 (0, negative values and
+ *    NaN mark pixels the mesh pass did not cover); its bytes are copied;
+ *  - the 3DGS fragment is kept where it exists and either there is no mesh
+ *    fragment or D_g < D_m (the mesh wins ties); otherwise the mesh
+ *    fragment where it exists; a pixel with neither gets the 3DGS colour
+ *    (the background) and depth 0.
+ * Outputs must not overlap the inputs.  Float arrays need 4-byte alignment
+ * and the byte arrays 4-byte alignment; with every array 16-byte aligned
+ * each thread moves four pixels with 16-byte accesses.  n_views == 0 is a
+ * no-op.  Errors: GS_ERR_INVALID_ARGUMENT for negative or oversized sizes,
+ * NULL arrays, only one of mesh_rgba / mesh_depth, or misalignment. */
+gs_status gs_sensor_compose(int32_t n_views, int32_t height, int32_t width, const float *rgb, const float *depth,
+                            const float *alpha, const uint8_t *mesh_rgba, const float *mesh_depth,
+                            uint8_t *out_rgba, float *out_depth, gs_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -61,7 +61,8 @@ TUNING_FIELDS = ("composite_groups_per_cu", "sort_partition_keys", "sort_lookbac
 EXPORTS = ["gs_status_string", "gs_last_error", "gs_version", "gs_default_params", "gs_set_tuning", "gs_get_tuning",
            "gs_instance_offsets",
            "gs_deform_lbs", "gs_deform_lbs_backward", "gs_project", "gs_bin_sort_workspace", "gs_tile_order_words", "gs_bin_sort",
-           "gs_composite_workspace", "gs_composite", "gs_checkpoint_floats", "gs_render_backward_workspace", "gs_render_backward"]
+           "gs_composite_workspace", "gs_composite", "gs_checkpoint_floats", "gs_render_backward_workspace", "gs_render_backward",
+           "gs_sensor_compose"]
 
 _lib = None
 
@@ -109,11 +110,12 @@ def load():
     lib.gs_render_backward.argtypes = [ctypes.POINTER(Gaussians), i32, P, i32, P, ctypes.POINTER(Params),
                                        ctypes.POINTER(Projected), P, P, P, P, P, sz, P, P, P, P, sz,
                                        ctypes.POINTER(GaussiansGrad), P]
+    lib.gs_sensor_compose.argtypes = [i32, i32, i32, P, P, P, P, P, P, P, P]
     lib.gs_set_tuning.argtypes = [ctypes.POINTER(Tuning)]
     lib.gs_get_tuning.argtypes = [ctypes.POINTER(Tuning)]
     lib.gs_get_tuning.restype = None
     for f in ("gs_deform_lbs", "gs_deform_lbs_backward", "gs_project", "gs_bin_sort", "gs_composite",
-              "gs_render_backward", "gs_instance_offsets", "gs_set_tuning"):
+              "gs_render_backward", "gs_instance_offsets", "gs_set_tuning", "gs_sensor_compose"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -279,6 +281,16 @@ def deform_lbs_backward(means_c, log_scales_c, quats_c, joint_idx, weights, avat
                                       ptr(joint_idx), ptr(weights), ptr(avatar_of), ptr(skin_mats), A, J,
                                       ptr(d_means_out), ptr(d_cov6_out), ptr(d_means), ptr(d_log_scales),
                                       ptr(d_quats), stream_handle()))
+
+
+def sensor_compose(rgb, depth, alpha, out_rgba, out_depth, mesh_rgba=None, mesh_depth=None):
+    """gs_sensor_compose on [V, H, W] views: rgb [V, H, W, 3], depth / alpha
+    [V, H, W], optional mesh_rgba uint8 [V, H, W, 4] and mesh_depth; writes
+    out_rgba uint8 [V, H, W, 4] and out_depth [V, H, W]."""
+    lib = load()
+    V, H, W = (int(x) for x in depth.shape)
+    _check(lib.gs_sensor_compose(V, H, W, ptr(rgb), ptr(depth), ptr(alpha), ptr(mesh_rgba), ptr(mesh_depth),
+                                 ptr(out_rgba), ptr(out_depth), stream_handle()))
 
 
 def set_tuning(composite_groups_per_cu=None, **kw):

@@ -544,4 +544,34 @@ gs_status gs_render_backward(const gs_gaussians *segs, int32_t n_segs, const gs_
     return GS_OK;
 }
 
+gs_status gs_sensor_compose(int32_t n_views, int32_t height, int32_t width, const float *rgb, const float *depth,
+                            const float *alpha, const uint8_t *mesh_rgba, const float *mesh_depth,
+                            uint8_t *out_rgba, float *out_depth, gs_stream_t stream) {
+    clear_error();
+    if (n_views < 0 || height < 1 || width < 1 || height > (1 << 16) || width > (1 << 16))
+        return fail(GS_ERR_INVALID_ARGUMENT, "n_views=%d height=%d width=%d invalid", n_views, height, width);
+    if (n_views == 0) return GS_OK;
+    if (!rgb || !depth || !alpha || !out_rgba || !out_depth)
+        return fail(GS_ERR_INVALID_ARGUMENT, "NULL array");
+    if ((mesh_rgba == nullptr) != (mesh_depth == nullptr))
+        return fail(GS_ERR_INVALID_ARGUMENT, "mesh_rgba and mesh_depth must both be given or both be NULL");
+    const void *arrays[7] = {rgb, depth, alpha, mesh_rgba, mesh_depth, out_rgba, out_depth};
+    bool vec4 = true;
+    for (const void *q : arrays) {
+        if (q && !aligned(q, 4)) return fail(GS_ERR_INVALID_ARGUMENT, "arrays need 4-byte alignment");
+        if (q && !aligned(q, 16)) vec4 = false;
+    }
+    gs::SensorArgs a = {};
+    a.n_px = (int64_t)n_views * height * width;
+    a.rgb = rgb;
+    a.depth = depth;
+    a.alpha = alpha;
+    a.mesh_rgba = reinterpret_cast<const uint32_t *>(mesh_rgba);
+    a.mesh_depth = mesh_depth;
+    a.out_rgba = reinterpret_cast<uint32_t *>(out_rgba);
+    a.out_depth = out_depth;
+    hipError_t e = gs::launch_sensor(a, vec4, (hipStream_t)stream);
+    return e == hipSuccess ? GS_OK : hip_fail(e, "gs_sensor_compose");
+}
+
 }  // extern "C"

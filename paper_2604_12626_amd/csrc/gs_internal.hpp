@@ -118,6 +118,17 @@ struct LbsArgs {
     float *d_means, *d_log_scales, *d_quats;
 };
 
+// sensor hand-off: n_px pixels of compositing outputs (and an optional mesh
+// pass) in, packed RGBA bytes and metric depth out
+struct SensorArgs {
+    int64_t n_px;
+    const float *rgb, *depth, *alpha;
+    const uint32_t *mesh_rgba;  // NULL: no mesh pass (mesh_depth NULL too)
+    const float *mesh_depth;
+    uint32_t *out_rgba;
+    float *out_depth;
+};
+
 struct SortPlan {
     int64_t n, capacity, n_tiles_total;
     int tile_bits, passes;
@@ -147,6 +158,7 @@ hipError_t launch_composite(CompositeArgs a, int grid, hipStream_t s);
 hipError_t launch_backward_tiles(BackwardTileArgs a, int n_cu, hipStream_t s);
 hipError_t launch_backward_project(const BackwardProjectArgs &a, hipStream_t s);
 hipError_t launch_lbs(const LbsArgs &a, bool backward, hipStream_t s);
+hipError_t launch_sensor(const SensorArgs &a, bool vec4, hipStream_t s);
 
 // Launch a kernel through hipLaunchKernel so that the call returns the status
 // of this launch itself (never a stale error of an earlier runtime call).  The

@@ -192,3 +192,16 @@ def rasterize(means, log_scales, quats, opacity, sh, cams, renderer, sh_degree=N
     if sh_degree is None:
         sh_degree = int(round(math.sqrt(sh.shape[1]))) - 1
     return _RasterizeFn.apply(means, log_scales, quats, opacity, sh, cams, renderer, sh_degree)
+
+
+def observation(rgb, depth, alpha, mesh_rgba=None, mesh_depth=None, out=None):
+    """The sensor observation of rendered views: (rgba uint8 [V, H, W, 4],
+    metric depth [V, H, W]), optionally resolved against a mesh pass by the
+    nearer-fragment rule (gs_sensor_compose).  `out` reuses a previous
+    (rgba, depth) pair of the same shape."""
+    V, H, W = (int(x) for x in depth.shape)
+    if out is None:
+        out = (torch.empty((V, H, W, 4), dtype=torch.uint8, device=depth.device),
+               torch.empty((V, H, W), dtype=torch.float32, device=depth.device))
+    B.sensor_compose(_c(rgb), _c(depth), _c(alpha), out[0], out[1], _c(mesh_rgba), _c(mesh_depth))
+    return out

@@ -133,6 +133,24 @@ def test_lbs_and_composite_validation(lib):
     assert st == B.GS_ERR_INVALID_ARGUMENT  # misaligned checkpoints
 
 
+def test_sensor_compose_validation(lib):
+    from paper_2604_12626_amd import binding as B
+    a = ctypes.c_void_p(0x10000)
+    bad = ctypes.c_void_p(0x10002)
+    f = lib.gs_sensor_compose
+    assert f(0, 4, 4, None, None, None, None, None, None, None, None) == B.GS_OK  # no views: no-op
+    assert f(-1, 4, 4, a, a, a, None, None, a, a, None) == B.GS_ERR_INVALID_ARGUMENT
+    assert f(1, 0, 4, a, a, a, None, None, a, a, None) == B.GS_ERR_INVALID_ARGUMENT
+    assert f(1, 4, (1 << 16) + 1, a, a, a, None, None, a, a, None) == B.GS_ERR_INVALID_ARGUMENT
+    assert f(1, 4, 4, None, a, a, None, None, a, a, None) == B.GS_ERR_INVALID_ARGUMENT
+    assert f(1, 4, 4, a, a, a, None, None, a, None, None) == B.GS_ERR_INVALID_ARGUMENT
+    assert f(1, 4, 4, a, a, a, a, None, a, a, None) == B.GS_ERR_INVALID_ARGUMENT  # mesh colour without depth
+    assert "both" in _err(lib)
+    assert f(1, 4, 4, a, a, a, None, a, a, a, None) == B.GS_ERR_INVALID_ARGUMENT
+    assert f(1, 4, 4, a, a, bad, None, None, a, a, None) == B.GS_ERR_INVALID_ARGUMENT  # misaligned
+    assert f(1, 4, 4, a, a, a, bad, a, a, a, None) == B.GS_ERR_INVALID_ARGUMENT
+
+
 def test_tile_order_sizes(lib):
     # 8 queues of ceil(n_views * T / 8) words; the compositing workspace holds
     # 2048 bytes of counters and room for one order

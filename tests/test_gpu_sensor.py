@@ -1,0 +1,116 @@
+"""GPU parity of the sensor hand-off (gs_sensor_compose, through the C ABI)
+against the oracle.  The kernel turns floats into byte codes and a depth
+comparison, and both sides take those decisions in FP32, so the bar is
+bit-exact: every byte and every depth bit pattern."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2604_12626_amd import synth
+
+from parity import to_dev
+
+pytestmark = pytest.mark.gpu
+
+F32 = np.float32
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2604_12626_amd import binding
+    binding.load()
+    return torch.device("cuda:0")
+
+
+def _upload(a, dev, offset):
+    """A device copy of a; with offset 1 it starts 4 bytes into a larger
+    allocation (4-byte but not 16-byte aligned)."""
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if offset == 0:
+        return t.to(dev)
+    flat = torch.zeros(t.numel() + 4, dtype=t.dtype, device=dev)
+    step = 4 if t.dtype == torch.uint8 else 1  # bytes of uint8 arrays move in whole pixels
+    view = flat[step:step + t.numel()].view(t.shape)
+    view.copy_(t.to(dev))
+    return view
+
+
+def _compose_gpu(d, dev, mesh, offset=0):
+    import torch
+    from paper_2604_12626_amd import render
+    V, H, W = d["depth"].shape
+    args = [_upload(d[k], dev, offset if k == "rgb" else 0) for k in ("rgb", "depth", "alpha")]
+    m_rgba = _upload(d["mesh_rgba"], dev, 0) if mesh else None
+    m_depth = _upload(d["mesh_depth"], dev, 0) if mesh else None
+    rgba, depth = render.observation(*args, mesh_rgba=m_rgba, mesh_depth=m_depth)
+    torch.cuda.synchronize()
+    return rgba.cpu().numpy(), depth.cpu().numpy()
+
+
+def _check(orc, d, mesh, got):
+    ref = orc.sensor_compose(d["rgb"], d["depth"], d["alpha"], d.get("mesh_rgba") if mesh else None,
+                             d.get("mesh_depth") if mesh else None)
+    assert np.array_equal(got[0], ref[0]), "bytes differ at %d pixels" % int((got[0] != ref[0]).any(-1).sum())
+    diff = got[1].view(np.uint32) != ref[1].view(np.uint32)
+    assert not diff.any(), "depth differs at %d pixels" % int(diff.sum())
+
+
+SIZES = [("1x1x1", 1, 1, 1), ("1x5x7_tail", 1, 5, 7), ("3x37x53_ragged", 3, 37, 53), ("2x256x256", 2, 256, 256)]
+
+
+@pytest.mark.parametrize("mesh", [True, False], ids=["mesh", "nomesh"])
+@pytest.mark.parametrize("offset", [0, 1], ids=["vec4", "scalar"])
+@pytest.mark.parametrize("name,V,H,W", SIZES, ids=[s[0] for s in SIZES])
+def test_sensor_parity(dev, orc, name, V, H, W, mesh, offset):
+    say("sensor_compose", name, "mesh" if mesh else "nomesh", "offset", offset)
+    d = synth.sensor_inputs(100 + V * H * W, V, H, W, mesh=mesh)
+    _check(orc, d, mesh, _compose_gpu(d, dev, mesh, offset))
+
+
+def test_sensor_parity_full_size(dev, orc):
+    # 16 views at 640 x 480 with a mesh pass, the launch the benchmark times
+    say("sensor_compose 16x480x640 mesh")
+    d = synth.sensor_inputs(7, 16, 480, 640, mesh=True)
+    _check(orc, d, True, _compose_gpu(d, dev, True))
+
+
+def test_sensor_of_a_rendered_frame(dev, orc):
+    # rendered views through the hand-off, against a mesh pass that covers
+    # only the left half, sloping from depth 2.5 to 3.5 across it (the cube's
+    # Gaussians lie at depths 2 to 4)
+    import torch
+    from paper_2604_12626_amd import render
+    say("sensor_compose of a rendered cube10k frame")
+    cfg = synth.config(0)
+    W, H = cfg["W"], cfg["H"]
+    g = cfg["segments"][0]
+    r = render.Renderer(W, H, capacity=1 << 18, device=dev)
+    cams = torch.from_numpy(cfg["cams"][:1]).to(dev)
+    f = r.render([to_dev(g, dev)], cams, [[0]])
+    torch.cuda.synchronize()
+    d = {"rgb": f.rgb.cpu().numpy(), "depth": f.depth.cpu().numpy(), "alpha": f.alpha.cpu().numpy()}
+    rng = np.random.default_rng(3)
+    d["mesh_rgba"] = rng.integers(0, 256, (1, H, W, 4), dtype=np.uint8)
+    md = np.zeros((1, H, W), F32)
+    md[:, :, :W // 2] = np.linspace(2.5, 3.5, W // 2, dtype=F32)[None, None, :]
+    d["mesh_depth"] = md
+    got = _compose_gpu(d, dev, True)
+    _check(orc, d, True, got)
+    has = d["alpha"] > 0
+    assert has.sum() > 1000
+    # the case exercises both outcomes where both passes have a fragment
+    d_g = np.divide(d["depth"], d["alpha"], out=np.zeros_like(md), where=has)
+    both = has & (md > 0)
+    assert (both & (d_g < md)).any() and (both & ~(d_g < md)).any()
+    # without a mesh pass: the frame's own observation
+    d.pop("mesh_rgba"), d.pop("mesh_depth")
+    _check(orc, d, False, _compose_gpu(d, dev, False))
