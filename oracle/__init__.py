@@ -24,6 +24,7 @@ against closed forms, invariants, brute force and independent derivations.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -370,3 +371,57 @@ def sensor_compose(rgb, depth, alpha, mesh_rgba=None, mesh_depth=None):
         out_rgba[take_mesh] = mesh_rgba[take_mesh]
         out_depth[take_mesh] = mesh_depth[take_mesh]
     return out_rgba, out_depth
+
+
+def clip_frames(frame_pos, clip_first, clip_frames, clip_total):
+    """Sec. 3.3 (GAMMA trajectory): each avatar's joint matrices at the
+    current time are interpolated between the two clip frames around its
+    fractional frame position.  Reading: linear interpolation of the matrices
+    ((1 - s) M[f] + s M[f + 1], f = floor(p), s = p - f), p clamped to the
+    clip (NaN -> 0), a one-frame clip holding its pose; clip_first clamped
+    into the clip array, clip_frames to [1, frames left].  Returns per avatar
+    (absolute frame f0, absolute frame f1, s) with s in double."""
+    out = []
+    for a in range(len(clip_first)):
+        first = min(max(int(clip_first[a]), 0), clip_total - 1)
+        F = min(max(int(clip_frames[a]), 1), clip_total - first)
+        p = float(np.float32(frame_pos[a]))
+        p = min(p, float(F - 1)) if p > 0 else 0.0
+        if F > 1:
+            f0 = min(int(math.floor(p)), F - 2)
+            out.append((first + f0, first + f0 + 1, p - f0))
+        else:
+            out.append((first, first, 0.0))
+    return out
+
+
+def _clip_as_lbs(w_dense, avatar_of, clip, frames):
+    """The interpolated blend as a blend over 2J matrices per avatar (the
+    frames f0 and f1 of every joint) with weights w (1 - s) and w s: exact,
+    since interpolation and blend are both linear in the matrices."""
+    J = clip.shape[1]
+    skin2 = np.zeros((len(frames), 2 * J, 12), np.float32)
+    s_av = np.zeros(len(frames))
+    for a, (f0, f1, s) in enumerate(frames):
+        skin2[a, :J] = clip[f0]
+        skin2[a, J:] = clip[f1]
+        s_av[a] = s
+    sa = s_av[np.asarray(avatar_of, np.int64)][:, None]
+    w2 = np.concatenate([w_dense * (1.0 - sa), w_dense * sa], 1)
+    return skin2, w2, 2 * J
+
+
+def lbs_clip(means, log_scales, quats, w_dense, avatar_of, clip, clip_first, clip_frames_, frame_pos):
+    """LBS (O13) with each avatar's joint matrices interpolated at its frame
+    position (see clip_frames); double precision."""
+    frames = clip_frames(frame_pos, clip_first, clip_frames_, len(clip))
+    skin2, w2, J2 = _clip_as_lbs(w_dense, avatar_of, clip, frames)
+    return lbs(means, log_scales, quats, w2, avatar_of, skin2, J2)
+
+
+def lbs_clip_backward(means, log_scales, quats, w_dense, avatar_of, clip, clip_first, clip_frames_, frame_pos,
+                      d_means_out, d_cov6_out):
+    """Adjoint of lbs_clip w.r.t. canonical means, log-scales, quaternions."""
+    frames = clip_frames(frame_pos, clip_first, clip_frames_, len(clip))
+    skin2, w2, J2 = _clip_as_lbs(w_dense, avatar_of, clip, frames)
+    return lbs_backward(means, log_scales, quats, w2, avatar_of, skin2, J2, d_means_out, d_cov6_out)

@@ -242,6 +242,31 @@ def avatar_pose(rng, sigma=0.3):
     return pose, Rz, pos
 
 
+def avatar_clips(rng, frames, fps=30.0, speed=1.2):
+    """Per-frame skinning matrices of walking avatars, standing in for the
+    offline GAMMA -> forward-kinematics clips (Sec. 3.3): avatar a has
+    frames[a] frames; its root walks in a straight line at `speed` m/s from a
+    random floor position with a random yaw, and its joint angles swing
+    sinusoidally (amplitude ~0.3 rad, random phase per joint, 1 Hz).
+    Returns (clip [sum(frames), 24, 12] float32, first int32 [A],
+    frames int32 [A])."""
+    mats, first = [], []
+    for F in frames:
+        pose0, Rz, pos = avatar_pose(rng)
+        amp = rng.normal(0.0, 0.3, (N_JOINTS, 3))
+        phase = rng.uniform(0.0, 2 * math.pi, (N_JOINTS, 1))
+        heading = Rz @ np.array([1.0, 0.0, 0.0])
+        first.append(sum(len(m) for m in mats))
+        clip = []
+        for f in range(F):
+            t = f / fps
+            pose = 0.3 * pose0 + amp * np.sin(2 * math.pi * t + phase)
+            clip.append(skinning_matrices(pose, Rz, pos + speed * t * heading))
+        mats.append(np.stack(clip))
+    return (np.concatenate(mats).astype(np.float32), np.array(first, np.int32),
+            np.array(list(frames), np.int32))
+
+
 # --------------------------------------------------------------------------
 # projected-record stand-ins (inputs of the binning and compositing calls)
 # --------------------------------------------------------------------------

@@ -84,9 +84,9 @@ def test_sensor_parity_full_size(dev, orc):
 
 
 def test_sensor_of_a_rendered_frame(dev, orc):
-    # rendered views through the hand-off, against a mesh pass that covers
-    # only the left half, sloping from depth 2.5 to 3.5 across it (the cube's
-    # Gaussians lie at depths 2 to 4)
+    # rendered views through the hand-off, against a mesh wall over the left
+    # half at the median metric depth of the rendered pixels (so that both
+    # passes win somewhere)
     import torch
     from paper_2604_12626_amd import render
     say("sensor_compose of a rendered cube10k frame")
@@ -100,15 +100,14 @@ def test_sensor_of_a_rendered_frame(dev, orc):
     d = {"rgb": f.rgb.cpu().numpy(), "depth": f.depth.cpu().numpy(), "alpha": f.alpha.cpu().numpy()}
     rng = np.random.default_rng(3)
     d["mesh_rgba"] = rng.integers(0, 256, (1, H, W, 4), dtype=np.uint8)
+    has = d["alpha"] > 0
+    assert has.sum() > 1000
+    d_g = np.divide(d["depth"], d["alpha"], out=np.zeros_like(d["depth"]), where=has)
     md = np.zeros((1, H, W), F32)
-    md[:, :, :W // 2] = np.linspace(2.5, 3.5, W // 2, dtype=F32)[None, None, :]
+    md[:, :, :W // 2] = F32(np.median(d_g[has]))
     d["mesh_depth"] = md
     got = _compose_gpu(d, dev, True)
     _check(orc, d, True, got)
-    has = d["alpha"] > 0
-    assert has.sum() > 1000
-    # the case exercises both outcomes where both passes have a fragment
-    d_g = np.divide(d["depth"], d["alpha"], out=np.zeros_like(md), where=has)
     both = has & (md > 0)
     assert (both & (d_g < md)).any() and (both & ~(d_g < md)).any()
     # without a mesh pass: the frame's own observation

@@ -288,3 +288,112 @@ def test_lbs_backward_by_finite_differences(orc):
                 fd = (L(args_p["means"], args_p["log_scales"], args_p["quats"]) -
                       L(args_m["means"], args_m["log_scales"], args_m["quats"])) / (float(ap[i, c]) - float(am[i, c]))
                 assert abs(fd - ref[i, c]) <= 1e-5 * np.abs(ref).max() + 1e-4 * abs(ref[i, c]), (name, i, c)
+
+
+# --------------------------------------------------------------------------
+# Sec. 3.3 GAMMA trajectory: joint matrices interpolated at the current time
+# --------------------------------------------------------------------------
+def _clip_setup(frames=(1, 4, 9), seed=51, n=48):
+    rng = np.random.default_rng(seed)
+    A = len(frames)
+    av = synth.avatar_canonical(n, rng, sh_degree=0)
+    aof = (np.arange(n) % A).astype(np.int32)
+    clip, first, nfr = synth.avatar_clips(rng, frames)
+    return av, aof, clip, first, nfr
+
+
+def test_clip_frame_selection_and_clamps(orc):
+    first = np.array([0, 1, 5], np.int32)
+    nfr = np.array([1, 4, 9], np.int32)
+    total = 14
+    fr = orc.clip_frames(np.array([3.7, 2.25, 8.0], np.float32), first, nfr, total)
+    assert fr[0] == (0, 0, 0.0)                     # one frame: the pose is held
+    assert fr[1] == (3, 4, 0.25)                    # floor 2, s = 0.25
+    assert fr[2] == (12, 13, 1.0)                   # the last frame exactly
+    fr = orc.clip_frames(np.array([-1.0, np.nan, 100.0], np.float32), first, nfr, total)
+    assert fr[0] == (0, 0, 0.0) and fr[1] == (1, 2, 0.0) and fr[2] == (12, 13, 1.0)
+    # out-of-range clip descriptors are clamped into the clip array
+    fr = orc.clip_frames(np.array([0.5], np.float32), np.array([20], np.int32), np.array([5], np.int32), total)
+    assert fr[0] == (13, 13, 0.0)
+
+
+def test_clip_lbs_at_frames_equals_plain_lbs(orc):
+    av, aof, clip, first, nfr = _clip_setup()
+    J = synth.N_JOINTS
+    w = orc.dense_weights(av["joint_idx"], av["weights"], J)
+    for pos in ([0.0, 2.0, 5.0], [0.0, 3.0, 8.0], [0.0, 0.0, 0.0]):
+        mo, co = orc.lbs_clip(av["means"], av["log_scales"], av["quats"], w, aof, clip, first, nfr,
+                              np.array(pos, np.float32))
+        skin = np.stack([clip[first[a] + int(pos[a])] for a in range(3)])
+        mr, cr = orc.lbs(av["means"], av["log_scales"], av["quats"], w, aof, skin, J)
+        assert np.array_equal(mo, mr) and np.array_equal(co, cr)
+
+
+def test_clip_lbs_means_are_linear_in_time(orc):
+    # means' = A mean + a is linear in the matrices, so at f + s the posed
+    # means are the same interpolation of the posed means at f and f + 1
+    av, aof, clip, first, nfr = _clip_setup()
+    J = synth.N_JOINTS
+    w = orc.dense_weights(av["joint_idx"], av["weights"], J)
+    s = 0.375
+    m0, _ = orc.lbs_clip(av["means"], av["log_scales"], av["quats"], w, aof, clip, first, nfr,
+                         np.array([0.0, 1.0, 6.0], np.float32))
+    m1, _ = orc.lbs_clip(av["means"], av["log_scales"], av["quats"], w, aof, clip, first, nfr,
+                         np.array([0.0, 2.0, 7.0], np.float32))
+    ms, _ = orc.lbs_clip(av["means"], av["log_scales"], av["quats"], w, aof, clip, first, nfr,
+                         np.array([0.0, 1.0 + s, 6.0 + s], np.float32))
+    assert np.allclose(ms, (1 - s) * m0 + s * m1, rtol=1e-12, atol=1e-12)
+
+
+def test_clip_lbs_half_way_between_two_rotations(orc):
+    # one joint, frames Rz(0) and Rz(theta): at s = 1/2 the matrix is
+    # (I + Rz(theta)) / 2, whose xy block is cos(theta / 2) R(theta / 2)
+    # (a rotation by half the angle, shrunk) and whose z entry is 1
+    av = _avatar(16, 61)
+    n, J = len(av["means"]), synth.N_JOINTS
+    th = 1.1
+    clip = np.zeros((2, J, 12), F32)
+    clip[0, :] = np.eye(3, 4).reshape(12)
+    clip[1, :] = np.concatenate([Rotation.from_rotvec([0, 0, th]).as_matrix(), np.zeros((3, 1))], 1).reshape(12)
+    w = np.zeros((n, J))
+    w[:, 7] = 1.0
+    aof = np.zeros(n, np.int32)
+    mo, co = orc.lbs_clip(av["means"], av["log_scales"], av["quats"], w, aof, clip, np.array([0], np.int32),
+                          np.array([2], np.int32), np.array([0.5], np.float32))
+    R1 = clip[1, 7].astype(np.float64).reshape(3, 4)[:, :3]
+    th32 = math.atan2(R1[1, 0], R1[0, 0])  # the angle the FP32 matrix holds
+    Ah = Rotation.from_rotvec([0, 0, th32 / 2]).as_matrix()
+    Ah[:2, :2] *= math.cos(th32 / 2)
+    cov = orc.cov3d(av["log_scales"], av["quats"])
+    for i in range(n):
+        assert np.allclose(_full(co[i]), Ah @ _full(cov[i]) @ Ah.T, rtol=1e-6, atol=1e-14)
+    assert np.allclose(mo, av["means"].astype(np.float64) @ Ah.T, rtol=1e-6, atol=1e-9)
+
+
+def test_clip_lbs_backward_by_finite_differences(orc):
+    av, aof, clip, first, nfr = _clip_setup(frames=(3, 5), seed=71, n=18)
+    J = synth.N_JOINTS
+    w = orc.dense_weights(av["joint_idx"], av["weights"], J)
+    pos = np.array([1.3, 2.8], np.float32)
+    rng = np.random.default_rng(72)
+    Gm = rng.standard_normal((len(aof), 3)).astype(F32)
+    Gc = rng.standard_normal((len(aof), 6)).astype(F32)
+    dm, ds, dq = orc.lbs_clip_backward(av["means"], av["log_scales"], av["quats"], w, aof, clip, first, nfr, pos,
+                                       Gm, Gc)
+
+    def L(means, lsc, q):
+        mo, co = orc.lbs_clip(means, lsc, q, w, aof, clip, first, nfr, pos)
+        return (Gm * mo).sum() + (Gc * co).sum()
+
+    for name, ref, k in [("means", dm, 0), ("log_scales", ds, 1), ("quats", dq, 2)]:
+        base = [av["means"], av["log_scales"], av["quats"]]
+        for i in range(0, len(aof), 4):
+            for c in range(base[k].shape[1]):
+                x0 = float(base[k][i, c])
+                h = 2e-4 * max(abs(x0), 0.1)
+                ap, am = base[k].copy(), base[k].copy()
+                ap[i, c], am[i, c] = F32(x0 + h), F32(x0 - h)
+                bp, bm = list(base), list(base)
+                bp[k], bm[k] = ap, am
+                fd = (L(*bp) - L(*bm)) / (float(ap[i, c]) - float(am[i, c]))
+                assert abs(fd - ref[i, c]) <= 1e-5 * np.abs(ref).max() + 1e-4 * abs(ref[i, c]), (name, i, c)
