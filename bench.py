@@ -252,7 +252,33 @@ def bench_avatars(args, dev, steps):
     ms = _time_seq(frame, args.warmup, steps)
     ms_b = _time_seq(frame_bwd, max(2, args.warmup // 2), max(3, steps // 2))
     assert int(f.overflow.item()) == 0 and int(fb.overflow.item()) == 0
-    return ms, ms_b, len(vs)
+    # skinning alone, with fixed joint matrices and with each avatar's matrices
+    # interpolated in a 90-frame walking clip at its current time
+    clip, first, nfr = synth.avatar_clips(np.random.default_rng(5), [90] * int(skin.shape[0]))
+    tclip = [torch.from_numpy(x).to(dev) for x in (clip, first, nfr)]
+    fpos = torch.linspace(0.3, 80.7, int(skin.shape[0]), device=dev)
+
+    def lbs_clip():
+        B.deform_lbs_clip(av["means"], av["log_scales"], av["quats"], av["joint_idx"], av["weights"],
+                          av["avatar_of"], *tclip, fpos, posed["means"], posed["cov6"])
+
+    lbs_ms = {k: _event_ms(fn, 20 * steps) for k, fn in (("fixed", lbs), ("clip", lbs_clip))}
+    return ms, ms_b, len(vs), lbs_ms, n_av
+
+
+def _event_ms(fn, reps):
+    """Mean device time per call of a short launch sequence (HIP events on
+    the current stream around reps back-to-back calls)."""
+    import torch
+    for _ in range(3):
+        fn()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
 
 
 def bench_sensor(args, dev, steps):
@@ -398,9 +424,12 @@ def main():
         extras["batched_tile_instances"] = kb
         extras["batched_composite_groups_per_cu"] = best
         log("avatars: 1M room + 8 x 50k avatars, 16 views x 640x480")
-        ms_a, ms_ab, nva = bench_avatars(args, dev, steps2)
+        ms_a, ms_ab, nva, lbs_ms, n_av = bench_avatars(args, dev, steps2)
         extras["avatars_16x640x480_fwd_fps"] = nva * 1e3 / ms_a
         extras["avatars_16x640x480_fwd_bwd_fps"] = nva * 1e3 / ms_ab
+        extras["lbs_400k_fixed_ms"] = lbs_ms["fixed"]
+        extras["lbs_400k_clip_ms"] = lbs_ms["clip"]
+        extras["lbs_400k_clip_hbm_frac"] = n_av * 96 / (lbs_ms["clip"] * 1e-3) / 1e9 / HBM_PEAK_GBS
         log("sensor hand-off: 16 views x 640x480 with a mesh pass")
         ms_s, frac_s = bench_sensor(args, dev, steps2)
         extras["sensor_16x640x480_mesh_ms"] = ms_s

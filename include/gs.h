@@ -197,6 +197,38 @@ gs_status gs_deform_lbs_backward(int64_t n, const float *means_c, const float *l
                                  int32_t n_joints, const float *d_means_out, const float *d_cov6_out,
                                  float *d_means_c, float *d_log_scales_c, float *d_quats_c, gs_stream_t stream);
 
+/* The same deformation with each avatar's joint matrices taken at its
+ * current time (Sec. 3.3, GAMMA trajectory: per-frame joint matrices
+ * prepared offline by forward kinematics are interpolated at the current
+ * simulation time before skinning).  The interpolation is linear in the
+ * matrices, fused into the blend: with p = frame_pos[a] clamped to
+ * [0, clip_frames[a] - 1] (NaN -> 0), f = floor(p) (at most
+ * clip_frames[a] - 2) and s = p - f, joint j of avatar a uses
+ * (1 - s) M_j[clip_first[a] + f] + s M_j[clip_first[a] + f + 1]; a clip of
+ * one frame holds that pose.
+ *  clip_mats [clip_total_frames][n_joints][12] (row-major 3x4, 16-byte
+ *  aligned): the frames of all avatars' clips; clip_first, clip_frames
+ *  int32 [n_avatars] and frame_pos [n_avatars] are device arrays (read at
+ *  run time, so a captured graph replays with new times); clip_first is
+ *  clamped to [0, clip_total_frames - 1] and clip_frames to [1, the frames
+ *  left from there].  Other arguments and errors as gs_deform_lbs. */
+gs_status gs_deform_lbs_clip(int64_t n, const float *means_c, const float *log_scales_c, const float *quats_c,
+                             const uint8_t *joint_idx, const float *weights, const int32_t *avatar_of,
+                             const float *clip_mats, int32_t clip_total_frames, const int32_t *clip_first,
+                             const int32_t *clip_frames, const float *frame_pos, int32_t n_avatars,
+                             int32_t n_joints, float *means_out, float *cov6_out, gs_stream_t stream);
+
+/* Adjoint of gs_deform_lbs_clip w.r.t. the canonical means, log-scales and
+ * quaternions (clip and times held fixed); arguments as
+ * gs_deform_lbs_backward with the clip arguments of gs_deform_lbs_clip. */
+gs_status gs_deform_lbs_clip_backward(int64_t n, const float *means_c, const float *log_scales_c,
+                                      const float *quats_c, const uint8_t *joint_idx, const float *weights,
+                                      const int32_t *avatar_of, const float *clip_mats, int32_t clip_total_frames,
+                                      const int32_t *clip_first, const int32_t *clip_frames,
+                                      const float *frame_pos, int32_t n_avatars, int32_t n_joints,
+                                      const float *d_means_out, const float *d_cov6_out, float *d_means_c,
+                                      float *d_log_scales_c, float *d_quats_c, gs_stream_t stream);
+
 /* ---------------------------------------------------------------------- */
 /* rasterizer (Sec. 2.2, Sec. 3.2)                                         */
 /* ---------------------------------------------------------------------- */

@@ -60,7 +60,7 @@ TUNING_FIELDS = ("composite_groups_per_cu", "sort_partition_keys", "sort_lookbac
 
 EXPORTS = ["gs_status_string", "gs_last_error", "gs_version", "gs_default_params", "gs_set_tuning", "gs_get_tuning",
            "gs_instance_offsets",
-           "gs_deform_lbs", "gs_deform_lbs_backward", "gs_project", "gs_bin_sort_workspace", "gs_tile_order_words", "gs_bin_sort",
+           "gs_deform_lbs", "gs_deform_lbs_backward", "gs_deform_lbs_clip", "gs_deform_lbs_clip_backward", "gs_project", "gs_bin_sort_workspace", "gs_tile_order_words", "gs_bin_sort",
            "gs_composite_workspace", "gs_composite", "gs_checkpoint_floats", "gs_render_backward_workspace", "gs_render_backward",
            "gs_sensor_compose"]
 
@@ -91,6 +91,8 @@ def load():
     lib.gs_instance_offsets.argtypes = [ctypes.POINTER(Gaussians), i32, i32, P, P]
     lib.gs_deform_lbs.argtypes = [i64, P, P, P, P, P, P, P, i32, i32, P, P, P]
     lib.gs_deform_lbs_backward.argtypes = [i64, P, P, P, P, P, P, P, i32, i32, P, P, P, P, P, P]
+    lib.gs_deform_lbs_clip.argtypes = [i64, P, P, P, P, P, P, P, i32, P, P, P, i32, i32, P, P, P]
+    lib.gs_deform_lbs_clip_backward.argtypes = [i64, P, P, P, P, P, P, P, i32, P, P, P, i32, i32, P, P, P, P, P, P]
     lib.gs_project.argtypes = [ctypes.POINTER(Gaussians), i32, P, i32, P, ctypes.POINTER(Params),
                                ctypes.POINTER(Projected), P]
     lib.gs_bin_sort_workspace.restype = sz
@@ -114,7 +116,8 @@ def load():
     lib.gs_set_tuning.argtypes = [ctypes.POINTER(Tuning)]
     lib.gs_get_tuning.argtypes = [ctypes.POINTER(Tuning)]
     lib.gs_get_tuning.restype = None
-    for f in ("gs_deform_lbs", "gs_deform_lbs_backward", "gs_project", "gs_bin_sort", "gs_composite",
+    for f in ("gs_deform_lbs", "gs_deform_lbs_backward", "gs_deform_lbs_clip", "gs_deform_lbs_clip_backward",
+              "gs_project", "gs_bin_sort", "gs_composite",
               "gs_render_backward", "gs_instance_offsets", "gs_set_tuning", "gs_sensor_compose"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
@@ -291,6 +294,28 @@ def sensor_compose(rgb, depth, alpha, out_rgba, out_depth, mesh_rgba=None, mesh_
     V, H, W = (int(x) for x in depth.shape)
     _check(lib.gs_sensor_compose(V, H, W, ptr(rgb), ptr(depth), ptr(alpha), ptr(mesh_rgba), ptr(mesh_depth),
                                  ptr(out_rgba), ptr(out_depth), stream_handle()))
+
+
+def deform_lbs_clip(means_c, log_scales_c, quats_c, joint_idx, weights, avatar_of, clip, clip_first, clip_frames,
+                    frame_pos, means_out, cov6_out):
+    """gs_deform_lbs_clip: clip [frames, J, 12]; clip_first, clip_frames int32
+    [A] and frame_pos float32 [A] on the device."""
+    lib = load()
+    _check(lib.gs_deform_lbs_clip(int(means_c.shape[0]), ptr(means_c), ptr(log_scales_c), ptr(quats_c),
+                                  ptr(joint_idx), ptr(weights), ptr(avatar_of), ptr(clip), int(clip.shape[0]),
+                                  ptr(clip_first), ptr(clip_frames), ptr(frame_pos), int(clip_first.shape[0]),
+                                  int(clip.shape[1]), ptr(means_out), ptr(cov6_out), stream_handle()))
+
+
+def deform_lbs_clip_backward(means_c, log_scales_c, quats_c, joint_idx, weights, avatar_of, clip, clip_first,
+                             clip_frames, frame_pos, d_means_out, d_cov6_out, d_means, d_log_scales, d_quats):
+    lib = load()
+    _check(lib.gs_deform_lbs_clip_backward(int(means_c.shape[0]), ptr(means_c), ptr(log_scales_c), ptr(quats_c),
+                                           ptr(joint_idx), ptr(weights), ptr(avatar_of), ptr(clip),
+                                           int(clip.shape[0]), ptr(clip_first), ptr(clip_frames), ptr(frame_pos),
+                                           int(clip_first.shape[0]), int(clip.shape[1]), ptr(d_means_out),
+                                           ptr(d_cov6_out), ptr(d_means), ptr(d_log_scales), ptr(d_quats),
+                                           stream_handle()))
 
 
 def set_tuning(composite_groups_per_cu=None, **kw):

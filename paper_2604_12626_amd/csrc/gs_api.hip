@@ -544,6 +544,91 @@ gs_status gs_render_backward(const gs_gaussians *segs, int32_t n_segs, const gs_
     return GS_OK;
 }
 
+// the clip-mode arguments shared by gs_deform_lbs_clip and its backward
+static gs_status clip_args(gs::LbsArgs &a, const float *clip_mats, int32_t clip_total_frames,
+                           const int32_t *clip_first, const int32_t *clip_frames, const float *frame_pos) {
+    if (clip_total_frames < 1) return fail(GS_ERR_INVALID_ARGUMENT, "clip_total_frames=%d", clip_total_frames);
+    if (!clip_mats || !clip_first || !clip_frames || !frame_pos) return fail(GS_ERR_INVALID_ARGUMENT, "NULL clip array");
+    if (!aligned(clip_mats, 16)) return fail(GS_ERR_INVALID_ARGUMENT, "clip_mats needs 16-byte alignment");
+    a.skin = nullptr;
+    a.clip = clip_mats;
+    a.clip_total = clip_total_frames;
+    a.clip_first = clip_first;
+    a.clip_frames = clip_frames;
+    a.frame_pos = frame_pos;
+    return GS_OK;
+}
+
+gs_status gs_deform_lbs_clip(int64_t n, const float *means_c, const float *log_scales_c, const float *quats_c,
+                             const uint8_t *joint_idx, const float *weights, const int32_t *avatar_of,
+                             const float *clip_mats, int32_t clip_total_frames, const int32_t *clip_first,
+                             const int32_t *clip_frames, const float *frame_pos, int32_t n_avatars,
+                             int32_t n_joints, float *means_out, float *cov6_out, gs_stream_t stream) {
+    clear_error();
+    if (n < 0) return fail(GS_ERR_INVALID_ARGUMENT, "n < 0");
+    if (n_avatars < 1 || n_joints < 1 || n_joints > 256)
+        return fail(GS_ERR_INVALID_ARGUMENT, "n_avatars=%d / n_joints=%d invalid", n_avatars, n_joints);
+    if (n == 0) return GS_OK;
+    if (!means_c || !log_scales_c || !quats_c || !joint_idx || !weights || !avatar_of || !means_out || !cov6_out)
+        return fail(GS_ERR_INVALID_ARGUMENT, "NULL array");
+    if (!aligned(quats_c, 16) || !aligned(weights, 16) || !aligned(joint_idx, 4))
+        return fail(GS_ERR_INVALID_ARGUMENT, "quats/weights need 16-byte, joint_idx 4-byte alignment");
+    gs::LbsArgs a = {};
+    gs_status st = clip_args(a, clip_mats, clip_total_frames, clip_first, clip_frames, frame_pos);
+    if (st != GS_OK) return st;
+    a.n = n;
+    a.means = means_c;
+    a.log_scales = log_scales_c;
+    a.quats = quats_c;
+    a.joint_idx = joint_idx;
+    a.weights = weights;
+    a.avatar_of = avatar_of;
+    a.n_avatars = n_avatars;
+    a.n_joints = n_joints;
+    a.means_out = means_out;
+    a.cov6_out = cov6_out;
+    hipError_t e = gs::launch_lbs(a, false, (hipStream_t)stream);
+    return e == hipSuccess ? GS_OK : hip_fail(e, "gs_deform_lbs_clip");
+}
+
+gs_status gs_deform_lbs_clip_backward(int64_t n, const float *means_c, const float *log_scales_c,
+                                      const float *quats_c, const uint8_t *joint_idx, const float *weights,
+                                      const int32_t *avatar_of, const float *clip_mats, int32_t clip_total_frames,
+                                      const int32_t *clip_first, const int32_t *clip_frames,
+                                      const float *frame_pos, int32_t n_avatars, int32_t n_joints,
+                                      const float *d_means_out, const float *d_cov6_out, float *d_means_c,
+                                      float *d_log_scales_c, float *d_quats_c, gs_stream_t stream) {
+    clear_error();
+    if (n < 0) return fail(GS_ERR_INVALID_ARGUMENT, "n < 0");
+    if (n_avatars < 1 || n_joints < 1 || n_joints > 256)
+        return fail(GS_ERR_INVALID_ARGUMENT, "n_avatars=%d / n_joints=%d invalid", n_avatars, n_joints);
+    if (n == 0) return GS_OK;
+    if (!means_c || !log_scales_c || !quats_c || !joint_idx || !weights || !avatar_of || !d_means_out ||
+        !d_cov6_out || !d_means_c || !d_log_scales_c || !d_quats_c)
+        return fail(GS_ERR_INVALID_ARGUMENT, "NULL array");
+    if (!aligned(quats_c, 16) || !aligned(weights, 16) || !aligned(joint_idx, 4) || !aligned(d_quats_c, 16))
+        return fail(GS_ERR_INVALID_ARGUMENT, "quats/weights/d_quats need 16-byte alignment");
+    gs::LbsArgs a = {};
+    gs_status st = clip_args(a, clip_mats, clip_total_frames, clip_first, clip_frames, frame_pos);
+    if (st != GS_OK) return st;
+    a.n = n;
+    a.means = means_c;
+    a.log_scales = log_scales_c;
+    a.quats = quats_c;
+    a.joint_idx = joint_idx;
+    a.weights = weights;
+    a.avatar_of = avatar_of;
+    a.n_avatars = n_avatars;
+    a.n_joints = n_joints;
+    a.d_means_out = d_means_out;
+    a.d_cov6_out = d_cov6_out;
+    a.d_means = d_means_c;
+    a.d_log_scales = d_log_scales_c;
+    a.d_quats = d_quats_c;
+    hipError_t e = gs::launch_lbs(a, true, (hipStream_t)stream);
+    return e == hipSuccess ? GS_OK : hip_fail(e, "gs_deform_lbs_clip_backward");
+}
+
 gs_status gs_sensor_compose(int32_t n_views, int32_t height, int32_t width, const float *rgb, const float *depth,
                             const float *alpha, const uint8_t *mesh_rgba, const float *mesh_depth,
                             uint8_t *out_rgba, float *out_depth, gs_stream_t stream) {

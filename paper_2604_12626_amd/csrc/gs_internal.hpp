@@ -116,6 +116,13 @@ struct LbsArgs {
     // backward
     const float *d_means_out, *d_cov6_out;
     float *d_means, *d_log_scales, *d_quats;
+    // clip mode (skin == NULL): per-frame joint matrices of all avatars'
+    // clips [clip_total][n_joints][12], avatar a's clip is frames
+    // clip_first[a] .. + clip_frames[a] - 1, sampled at frame_pos[a]
+    const float *clip;
+    const int32_t *clip_first, *clip_frames;
+    const float *frame_pos;
+    int32_t clip_total;
 };
 
 // sensor hand-off: n_px pixels of compositing outputs (and an optional mesh

@@ -133,6 +133,22 @@ def test_lbs_and_composite_validation(lib):
     assert st == B.GS_ERR_INVALID_ARGUMENT  # misaligned checkpoints
 
 
+def test_lbs_clip_validation(lib):
+    from paper_2604_12626_amd import binding as B
+    a = ctypes.c_void_p(0x10000)
+    f = lib.gs_deform_lbs_clip
+    assert f(0, None, None, None, None, None, None, None, 0, None, None, None, 1, 24, None, None, None) == B.GS_OK
+    assert f(10, a, a, a, a, a, a, a, 0, a, a, a, 1, 24, a, a, None) == B.GS_ERR_INVALID_ARGUMENT  # no frames
+    assert f(10, a, a, a, a, a, a, None, 5, a, a, a, 1, 24, a, a, None) == B.GS_ERR_INVALID_ARGUMENT
+    assert f(10, a, a, a, a, a, a, a, 5, a, None, a, 1, 24, a, a, None) == B.GS_ERR_INVALID_ARGUMENT
+    assert f(10, a, a, a, a, a, a, ctypes.c_void_p(0x10004), 5, a, a, a, 1, 24, a, a, None) == \
+        B.GS_ERR_INVALID_ARGUMENT  # misaligned clip
+    assert f(10, a, a, a, a, a, a, a, 5, a, a, a, 0, 24, a, a, None) == B.GS_ERR_INVALID_ARGUMENT
+    g = lib.gs_deform_lbs_clip_backward
+    assert g(10, a, a, a, a, a, a, a, 5, a, a, None, 1, 24, a, a, a, a, a, None) == B.GS_ERR_INVALID_ARGUMENT
+    assert g(10, a, a, a, a, a, a, a, 5, a, a, a, 1, 24, a, a, a, a, None, None) == B.GS_ERR_INVALID_ARGUMENT
+
+
 def test_sensor_compose_validation(lib):
     from paper_2604_12626_amd import binding as B
     a = ctypes.c_void_p(0x10000)

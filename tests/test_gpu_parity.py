@@ -484,3 +484,57 @@ def test_lbs_parity(dev, orc):
     for a, b in ((dm, rm), (ds, rs), (dq, rq)):
         a = a.cpu().numpy().astype(np.float64)
         assert np.all(np.abs(a - b) <= 1e-4 * np.abs(b).max(1, keepdims=True) + 1e-9), np.abs(a - b).max()
+
+
+
+CLIP_POSITIONS = [
+    ("fractions", [0.0, 0.4, 2.5, 7.75, 13.2, 28.9, 1.0, 5.5]),
+    ("integers_and_ends", [0.0, 1.0, 3.0, 8.0, 0.0, 29.0, 2.0, 11.0]),
+    ("clamped", [-3.0, 100.0, float("nan"), -0.5, 1e9, 29.0001, float("inf"), -float("inf")]),
+]
+
+
+@pytest.mark.parametrize("name,pos", CLIP_POSITIONS, ids=[c[0] for c in CLIP_POSITIONS])
+def test_lbs_clip_parity(dev, orc, name, pos):
+    # 8 avatars x 1000 Gaussians, walking clips of 1 to 30 frames sampled at
+    # fractional, integer and out-of-range times
+    import torch
+    from paper_2604_12626_amd import binding as B
+    cfg = synth.config(4, scale=0.02)
+    av = cfg["avatars"]
+    n, J = len(av["means"]), synth.N_JOINTS
+    clip, first, nfr = synth.avatar_clips(np.random.default_rng(17), [1, 2, 4, 9, 3, 30, 6, 12])
+    fpos = np.array(pos, np.float32)
+    say("lbs clip parity:", name, n, "avatar gaussians,", len(clip), "clip frames")
+    t = to_dev(av, dev)
+    tc = [torch.from_numpy(x).to(dev) for x in (clip, first, nfr, fpos)]
+    mo = torch.empty(n, 3, device=dev)
+    co = torch.empty(n, 6, device=dev)
+    B.deform_lbs_clip(t["means"], t["log_scales"], t["quats"], t["joint_idx"], t["weights"], t["avatar_of"], *tc,
+                      mo, co)
+    w = orc.dense_weights(av["joint_idx"], av["weights"], J)
+    mo_o, co_o = orc.lbs_clip(av["means"], av["log_scales"], av["quats"], w, av["avatar_of"], clip, first, nfr, fpos)
+    torch.cuda.synchronize()
+    assert np.abs(mo.cpu().numpy() - mo_o).max() <= 1e-5 * max(1.0, np.abs(mo_o).max())
+    cs = np.abs(co_o).max(1, keepdims=True)
+    assert np.all(np.abs(co.cpu().numpy() - co_o) <= 1e-5 * cs + 1e-12)
+    rng = np.random.default_rng(4)
+    gm = rng.standard_normal((n, 3)).astype(F32)
+    gc = (rng.standard_normal((n, 6)) * 1e3).astype(F32)
+    dm, ds, dq = (torch.empty(n, k, device=dev) for k in (3, 3, 4))
+    B.deform_lbs_clip_backward(t["means"], t["log_scales"], t["quats"], t["joint_idx"], t["weights"], t["avatar_of"],
+                               *tc, torch.from_numpy(gm).to(dev), torch.from_numpy(gc).to(dev), dm, ds, dq)
+    rm, rs, rq = orc.lbs_clip_backward(av["means"], av["log_scales"], av["quats"], w, av["avatar_of"], clip, first,
+                                       nfr, fpos, gm, gc)
+    torch.cuda.synchronize()
+    for a, b in ((dm, rm), (ds, rs), (dq, rq)):
+        a = a.cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(a - b) <= 1e-4 * np.abs(b).max(1, keepdims=True) + 1e-9), np.abs(a - b).max()
+    # at integer times the clip path equals the plain path on that frame's matrices, bit for bit
+    if name == "integers_and_ends":
+        skin = np.stack([clip[first[a] + int(pos[a])] for a in range(len(first))])
+        mp, cp = torch.empty_like(mo), torch.empty_like(co)
+        B.deform_lbs(t["means"], t["log_scales"], t["quats"], t["joint_idx"], t["weights"], t["avatar_of"],
+                     torch.from_numpy(skin).to(dev), mp, cp)
+        torch.cuda.synchronize()
+        assert torch.equal(mp, mo) and torch.equal(cp, co)
