@@ -425,3 +425,106 @@ def lbs_clip_backward(means, log_scales, quats, w_dense, avatar_of, clip, clip_f
     frames = clip_frames(frame_pos, clip_first, clip_frames_, len(clip))
     skin2, w2, J2 = _clip_as_lbs(w_dense, avatar_of, clip, frames)
     return lbs_backward(means, log_scales, quats, w2, avatar_of, skin2, J2, d_means_out, d_cov6_out)
+
+
+# --------------------------------------------------------------------------
+# Avatar capsule queries (Sec. 3.3 dynamic NavMesh blocking, Sec. 3.4 query
+# APIs): clearance to the nearest avatar capsule and whether a step is
+# blocked.  Plain double-precision geometry, one agent at a time.
+# --------------------------------------------------------------------------
+def point_segment_distance(x, a, b):
+    """min over t in [0, 1] of |x - (a + t (b - a))| (the minimiser of a
+    one-dimensional convex quadratic, clamped to the interval)."""
+    x, a, b = (np.asarray(v, np.float64) for v in (x, a, b))
+    d = b - a
+    dd = float(d @ d)
+    t = 0.0 if dd == 0.0 else min(max(float((x - a) @ d) / dd, 0.0), 1.0)
+    return float(np.linalg.norm(x - (a + t * d)))
+
+
+def segment_segment_distance(p0, p1, q0, q1):
+    """min over (s, t) in [0, 1]^2 of |p(s) - q(t)|: a convex quadratic over a
+    square, so the minimum is its stationary point when that lies inside,
+    else on one of the four sides (each a point-segment distance)."""
+    p0, p1, q0, q1 = (np.asarray(v, np.float64) for v in (p0, p1, q0, q1))
+    u, v, w = p1 - p0, q1 - q0, p0 - q0
+    a, b, c, d, e = u @ u, u @ v, v @ v, u @ w, v @ w
+    best = min(point_segment_distance(p0, q0, q1), point_segment_distance(p1, q0, q1),
+               point_segment_distance(q0, p0, p1), point_segment_distance(q1, p0, p1))
+    den = a * c - b * b
+    if den > 1e-12 * a * c:
+        s = (b * e - c * d) / den
+        t = (a * e - b * d) / den
+        if 0.0 <= s <= 1.0 and 0.0 <= t <= 1.0:
+            best = min(best, float(np.linalg.norm(w + s * u - t * v)))
+    return best
+
+
+def segment_parallelogram_distance(s0, s1, o, U, V):
+    """Distance between the segment [s0, s1] and the parallelogram
+    {o + a U + b V : a, b in [0, 1]}: zero where the segment crosses it,
+    else attained at a segment end point (against the parallelogram) or on
+    one of its four edges (against the segment)."""
+    s0, s1, o, U, V = (np.asarray(x, np.float64) for x in (s0, s1, o, U, V))
+    edges = [(o, o + U), (o + V, o + U + V), (o, o + V), (o + U, o + U + V)]
+    best = min(segment_segment_distance(s0, s1, e0, e1) for e0, e1 in edges)
+    g11, g12, g22 = U @ U, U @ V, V @ V
+    gd = g11 * g22 - g12 * g12
+    if gd > 1e-12 * g11 * g22:  # a proper parallelogram: end points over its interior
+        n = np.cross(U, V)
+        for x in (s0, s1):
+            r = x - o
+            a = (g22 * (r @ U) - g12 * (r @ V)) / gd
+            b = (g11 * (r @ V) - g12 * (r @ U)) / gd
+            if 0.0 <= a <= 1.0 and 0.0 <= b <= 1.0:
+                best = min(best, abs(float(r @ n)) / float(np.linalg.norm(n)))
+        # the segment crossing the interior: s0 + l (s1 - s0) = o + a U + b V
+        M = np.stack([s1 - s0, -U, -V], 1)
+        det = float(np.linalg.det(M))
+        scale = float(np.linalg.norm(s1 - s0) * np.linalg.norm(U) * np.linalg.norm(V))
+        if abs(det) > 1e-6 * scale:
+            lab = np.linalg.solve(M, o - s0)
+            if np.all(lab >= 0.0) and np.all(lab <= 1.0):
+                best = 0.0
+    return best
+
+
+def capsule_queries(agent_pos, agent_next, agent_avatars, radius, height, caps, clip_first, clip_frames_,
+                    frame_pos, n_caps):
+    """Per agent e (a vertical capsule: axis from agent_pos[e] up `height`,
+    radius `radius`), against the capsules of avatars agent_avatars[e] =
+    (first, count):
+      clearance[e] = min over capsules of dist(agent axis, capsule axis)
+                     - radius - r_c (negative: overlap), +inf with no capsule;
+      nearest[e]   = the capsule attaining it (avatar * n_caps + c), -1 if none;
+      step_gap[e]  = the same minimum for the step from agent_pos[e] to
+                     agent_next[e]: the agent axis swept along the step is the
+                     parallelogram {p0 + a (p1 - p0) + b height z}.
+    Capsule endpoints (and radius) are interpolated linearly in each avatar's
+    clip at its frame position, with the clip rules of clip_frames.
+    caps: [frames][n_caps][8] = (a.xyz, r, b.xyz, unused)."""
+    caps = np.asarray(caps, np.float64)
+    frames = clip_frames(frame_pos, clip_first, clip_frames_, len(caps))
+    A = len(frames)
+    cur = np.zeros((A, n_caps, 7))
+    for a, (f0, f1, s) in enumerate(frames):
+        cur[a] = (1.0 - s) * caps[f0, :, :7] + s * caps[f1, :, :7]
+    E = len(agent_pos)
+    clearance = np.full(E, np.inf)
+    nearest = np.full(E, -1, np.int64)
+    step_gap = np.full(E, np.inf)
+    zup = np.array([0.0, 0.0, float(height)])
+    for e in range(E):
+        first, count = int(agent_avatars[e][0]), int(agent_avatars[e][1])
+        p0 = np.asarray(agent_pos[e], np.float64)
+        for av in range(max(first, 0), min(first + count, A)):
+            for c in range(n_caps):
+                ca, r, cb = cur[av, c, 0:3], cur[av, c, 3], cur[av, c, 4:7]
+                g = segment_segment_distance(p0, p0 + zup, ca, cb) - radius - r
+                if g < clearance[e]:
+                    clearance[e], nearest[e] = g, av * n_caps + c
+                if agent_next is not None:
+                    p1 = np.asarray(agent_next[e], np.float64)
+                    gs = segment_parallelogram_distance(ca, cb, p0, p1 - p0, zup) - radius - r
+                    step_gap[e] = min(step_gap[e], gs)
+    return clearance, nearest, step_gap

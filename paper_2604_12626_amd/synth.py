@@ -267,6 +267,47 @@ def avatar_clips(rng, frames, fps=30.0, speed=1.2):
             np.array(list(frames), np.int32))
 
 
+def capsule_clips(clip):
+    """Per-frame proxy capsules of the bones of the synthetic skeleton
+    (Sec. 3.3: capsules derived from the skeletal bones, world positions
+    pre-computed per frame), from the skinning matrices of avatar_clips:
+    one capsule per non-root joint k, from the posed parent joint to the posed
+    joint k, radius 0.05 m + 0.1 x its rest length.  The posed position of
+    joint k is skin_k [rest_k, 1].  Returns [frames, 23, 8] float32 rows
+    (a.xyz, r, b.xyz, 0)."""
+    clip = np.asarray(clip, np.float64).reshape(len(clip), N_JOINTS, 3, 4)
+    joints = np.einsum("fkij,kj->fki", clip[..., :3], REST) + clip[..., 3]
+    kids = [k for k in range(N_JOINTS) if PARENTS[k] >= 0]
+    out = np.zeros((len(clip), len(kids), 8))
+    for c, k in enumerate(kids):
+        p = PARENTS[k]
+        out[:, c, 0:3] = joints[:, p]
+        out[:, c, 3] = 0.05 + 0.1 * np.linalg.norm(REST[k] - REST[p])
+        out[:, c, 4:7] = joints[:, k]
+    return out.astype(np.float32)
+
+
+def agents_near_avatars(rng, caps_now, n_agents, height=1.5, step=0.25):
+    """Agents standing on the floor around the avatars (positions within
+    1.5 m of a random avatar's pelvis capsule), each with a candidate forward
+    step of `step` m in a random heading; a quarter of them placed right
+    against a capsule.  caps_now: [A, n_caps, 8] capsules at the current time.
+    Returns (pos [E, 3], next [E, 3]) float32."""
+    A = len(caps_now)
+    pos = np.zeros((n_agents, 3))
+    for e in range(n_agents):
+        a = rng.integers(0, A)
+        base = caps_now[a, 0, 0:3].astype(np.float64)
+        if rng.random() < 0.25:
+            c = caps_now[a, rng.integers(0, caps_now.shape[1])].astype(np.float64)
+            pos[e, :2] = (c[0:2] + c[4:6]) / 2 + rng.normal(0.0, 0.1, 2)
+        else:
+            pos[e, :2] = base[:2] + rng.uniform(-1.5, 1.5, 2)
+    heading = rng.uniform(0.0, 2 * math.pi, n_agents)
+    nxt = pos + step * np.stack([np.cos(heading), np.sin(heading), np.zeros(n_agents)], 1)
+    return pos.astype(np.float32), nxt.astype(np.float32)
+
+
 # --------------------------------------------------------------------------
 # projected-record stand-ins (inputs of the binning and compositing calls)
 # --------------------------------------------------------------------------
