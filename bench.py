@@ -304,6 +304,31 @@ def bench_sensor(args, dev, steps):
     return ms, n_px * 36 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS
 
 
+def bench_capsules(args, dev, steps):
+    """Capsule queries of 4096 agents against 8 walking avatars (184
+    capsules, 90-frame clips): clearance, nearest capsule and a swept 0.25 m
+    step per agent.  Returns ms per call."""
+    import torch
+    from paper_2604_12626_amd import binding as B, synth
+    rng = np.random.default_rng(41)
+    clip, first, nfr = synth.avatar_clips(rng, [90] * 8)
+    caps = synth.capsule_clips(clip)
+    now = np.stack([caps[first[a]] for a in range(8)])
+    pos, nxt = synth.agents_near_avatars(rng, now, 4096)
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    tp, tn, ta = t(pos), t(nxt), t(np.tile(np.array([0, 8], np.int32), (4096, 1)))
+    tc, tf, tnf, tfp = t(caps), t(first), t(nfr), t(np.linspace(0.3, 80.7, 8).astype(np.float32))
+    cl = torch.empty(4096, device=dev)
+    nn = torch.empty(4096, dtype=torch.int32, device=dev)
+    sg = torch.empty(4096, device=dev)
+    bl = torch.empty(4096, dtype=torch.uint8, device=dev)
+
+    def q():
+        B.capsule_queries(tp, tn, ta, 0.1, 1.5, tc, tf, tnf, tfp, cl, nn, sg, bl)
+
+    return _event_ms(q, 20 * steps)
+
+
 def _time_seq(fn, warmup, steps):
     import torch
     for _ in range(warmup):
@@ -434,6 +459,8 @@ def main():
         ms_s, frac_s = bench_sensor(args, dev, steps2)
         extras["sensor_16x640x480_mesh_ms"] = ms_s
         extras["sensor_16x640x480_mesh_hbm_frac"] = frac_s
+        log("capsule queries: 4096 agents x 8 avatars")
+        extras["capsule_queries_4096x184_ms"] = bench_capsules(args, dev, steps2)
     cpu, pairs = None, None
     if not args.profile and not args.no_cpu_baseline:
         log("cpu baseline (oracle)")

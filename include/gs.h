@@ -17,6 +17,15 @@
  *   gs_composite        per-tile front-to-back alpha compositing -> RGB, depth, alpha
  *   gs_render_backward  gradients of an image loss w.r.t. the Gaussian parameters
  *
+ * Around it, the pieces the paper puts directly before and after the path:
+ *
+ *   gs_deform_lbs_clip  the same skinning with each avatar's joint matrices
+ *                       interpolated in its clip at the current time (Sec. 3.3)
+ *   gs_sensor_compose   8-bit RGBA + metric depth observation, nearer-fragment
+ *                       select against a mesh pass (Sec. 3.2, Sec. 3.4)
+ *   gs_capsule_queries  clearance to the nearest avatar capsule and blocked
+ *                       steps for a batch of agents (Sec. 3.3, Sec. 3.4)
+ *
  * Conventions shared by every call
  * --------------------------------
  *  - Memory.  Every array argument is a DEVICE pointer owned by the caller,
@@ -361,6 +370,38 @@ gs_status gs_render_backward(const gs_gaussians *segs, int32_t n_segs, const gs_
                              const uint32_t *n_contrib, const float *ckpt, size_t ckpt_floats, const float *d_rgb,
                              const float *d_depth, const float *d_alpha, void *ws, size_t ws_bytes,
                              const gs_gaussians_grad *grads, gs_stream_t stream);
+
+/* ---------------------------------------------------------------------- */
+/* avatar capsule queries (Sec. 3.3 dynamic NavMesh blocking, Sec. 3.4)    */
+/* ---------------------------------------------------------------------- */
+/* The two avatar queries of the Habitat-Lab API for a batch of agents: the
+ * clearance to the nearest avatar proxy capsule and whether a candidate
+ * step is blocked.  An agent is a vertical capsule: axis from its base point
+ * agent_pos[e] up agent_height, radius agent_radius.  It is checked against
+ * the capsules of avatars agent_avatars[e] = (first, count) (clipped to
+ * [0, n_avatars)).  Capsule endpoints and radius are interpolated linearly
+ * in each avatar's clip at frame_pos, with the clip rules of
+ * gs_deform_lbs_clip.
+ *  caps [caps_total_frames][n_caps][8] (16-byte aligned): per frame and
+ *  capsule (a.x, a.y, a.z, r, b.x, b.y, b.z, unused), the capsules of avatar
+ *  a being frames clip_first[a] .. + clip_frames[a] - 1.
+ *  out: clearance [n_agents] = min over capsules of dist(agent axis,
+ *       capsule axis) - agent_radius - r (negative: overlap; +inf with no
+ *       capsule); nearest int32 [n_agents] (or NULL) = the capsule attaining
+ *       it, avatar * n_caps + capsule (smallest on ties; -1 if none);
+ *       with agent_next [n_agents][3] (or NULL): step_gap [n_agents] = the
+ *       same minimum for the agent's axis swept along the step, the
+ *       parallelogram {p0 + a (p1 - p0) + b h z : a, b in [0, 1]}, and
+ *       blocked uint8 [n_agents] = step_gap < 0.
+ * One wave per agent.  Errors: GS_ERR_INVALID_ARGUMENT for negative
+ * counts, non-finite or negative agent sizes, NULL arrays, agent_next /
+ * step_gap / blocked not all given or all NULL, misaligned caps. */
+gs_status gs_capsule_queries(int32_t n_agents, const float *agent_pos, const float *agent_next,
+                             const int32_t *agent_avatars, float agent_radius, float agent_height,
+                             const float *caps, int32_t caps_total_frames, int32_t n_caps,
+                             const int32_t *clip_first, const int32_t *clip_frames, const float *frame_pos,
+                             int32_t n_avatars, float *clearance, int32_t *nearest, float *step_gap,
+                             uint8_t *blocked, gs_stream_t stream);
 
 /* ---------------------------------------------------------------------- */
 /* sensor hand-off (Sec. 3.2 occlusion rule, Sec. 3.4 sensor format)       */

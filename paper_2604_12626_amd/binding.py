@@ -62,7 +62,7 @@ EXPORTS = ["gs_status_string", "gs_last_error", "gs_version", "gs_default_params
            "gs_instance_offsets",
            "gs_deform_lbs", "gs_deform_lbs_backward", "gs_deform_lbs_clip", "gs_deform_lbs_clip_backward", "gs_project", "gs_bin_sort_workspace", "gs_tile_order_words", "gs_bin_sort",
            "gs_composite_workspace", "gs_composite", "gs_checkpoint_floats", "gs_render_backward_workspace", "gs_render_backward",
-           "gs_sensor_compose"]
+           "gs_sensor_compose", "gs_capsule_queries"]
 
 _lib = None
 
@@ -113,12 +113,15 @@ def load():
                                        ctypes.POINTER(Projected), P, P, P, P, P, sz, P, P, P, P, sz,
                                        ctypes.POINTER(GaussiansGrad), P]
     lib.gs_sensor_compose.argtypes = [i32, i32, i32, P, P, P, P, P, P, P, P]
+    f32 = ctypes.c_float
+    lib.gs_capsule_queries.argtypes = [i32, P, P, P, f32, f32, P, i32, i32, P, P, P, i32, P, P, P, P, P]
     lib.gs_set_tuning.argtypes = [ctypes.POINTER(Tuning)]
     lib.gs_get_tuning.argtypes = [ctypes.POINTER(Tuning)]
     lib.gs_get_tuning.restype = None
     for f in ("gs_deform_lbs", "gs_deform_lbs_backward", "gs_deform_lbs_clip", "gs_deform_lbs_clip_backward",
               "gs_project", "gs_bin_sort", "gs_composite",
-              "gs_render_backward", "gs_instance_offsets", "gs_set_tuning", "gs_sensor_compose"):
+              "gs_render_backward", "gs_instance_offsets", "gs_set_tuning", "gs_sensor_compose",
+              "gs_capsule_queries"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -316,6 +319,19 @@ def deform_lbs_clip_backward(means_c, log_scales_c, quats_c, joint_idx, weights,
                                            int(clip_first.shape[0]), int(clip.shape[1]), ptr(d_means_out),
                                            ptr(d_cov6_out), ptr(d_means), ptr(d_log_scales), ptr(d_quats),
                                            stream_handle()))
+
+
+def capsule_queries(agent_pos, agent_next, agent_avatars, radius, height, caps, clip_first, clip_frames, frame_pos,
+                    clearance, nearest=None, step_gap=None, blocked=None):
+    """gs_capsule_queries: agent_pos / agent_next [E, 3], agent_avatars int32
+    [E, 2], caps [frames, n_caps, 8], clip_first / clip_frames int32 [A],
+    frame_pos [A]; writes clearance [E] (and nearest int32 [E], step_gap [E],
+    blocked uint8 [E])."""
+    lib = load()
+    _check(lib.gs_capsule_queries(int(agent_pos.shape[0]), ptr(agent_pos), ptr(agent_next), ptr(agent_avatars),
+                                  float(radius), float(height), ptr(caps), int(caps.shape[0]), int(caps.shape[1]),
+                                  ptr(clip_first), ptr(clip_frames), ptr(frame_pos), int(clip_first.shape[0]),
+                                  ptr(clearance), ptr(nearest), ptr(step_gap), ptr(blocked), stream_handle()))
 
 
 def set_tuning(composite_groups_per_cu=None, **kw):

@@ -10,6 +10,8 @@
 #include <string>
 #include <vector>
 
+#include <cmath>
+
 #include "gs_internal.hpp"
 
 namespace {
@@ -627,6 +629,48 @@ gs_status gs_deform_lbs_clip_backward(int64_t n, const float *means_c, const flo
     a.d_quats = d_quats_c;
     hipError_t e = gs::launch_lbs(a, true, (hipStream_t)stream);
     return e == hipSuccess ? GS_OK : hip_fail(e, "gs_deform_lbs_clip_backward");
+}
+
+gs_status gs_capsule_queries(int32_t n_agents, const float *agent_pos, const float *agent_next,
+                             const int32_t *agent_avatars, float agent_radius, float agent_height,
+                             const float *caps, int32_t caps_total_frames, int32_t n_caps,
+                             const int32_t *clip_first, const int32_t *clip_frames, const float *frame_pos,
+                             int32_t n_avatars, float *clearance, int32_t *nearest, float *step_gap,
+                             uint8_t *blocked, gs_stream_t stream) {
+    clear_error();
+    if (n_agents < 0) return fail(GS_ERR_INVALID_ARGUMENT, "n_agents < 0");
+    if (n_agents == 0) return GS_OK;
+    if (n_avatars < 1 || n_caps < 1 || caps_total_frames < 1)
+        return fail(GS_ERR_INVALID_ARGUMENT, "n_avatars=%d n_caps=%d caps_total_frames=%d invalid", n_avatars,
+                    n_caps, caps_total_frames);
+    if (!(agent_radius >= 0.0f) || !(agent_height >= 0.0f) || !std::isfinite(agent_radius) ||
+        !std::isfinite(agent_height))
+        return fail(GS_ERR_INVALID_ARGUMENT, "agent radius / height must be finite and >= 0");
+    if (!agent_pos || !agent_avatars || !caps || !clip_first || !clip_frames || !frame_pos || !clearance)
+        return fail(GS_ERR_INVALID_ARGUMENT, "NULL array");
+    if ((agent_next == nullptr) != (step_gap == nullptr) || (agent_next == nullptr) != (blocked == nullptr))
+        return fail(GS_ERR_INVALID_ARGUMENT, "agent_next, step_gap and blocked must all be given or all be NULL");
+    if (!aligned(caps, 16)) return fail(GS_ERR_INVALID_ARGUMENT, "caps needs 16-byte alignment");
+    gs::CapsuleArgs a = {};
+    a.n_agents = n_agents;
+    a.agent_pos = agent_pos;
+    a.agent_next = agent_next;
+    a.agent_avatars = agent_avatars;
+    a.radius = agent_radius;
+    a.height = agent_height;
+    a.caps = caps;
+    a.clip_total = caps_total_frames;
+    a.n_caps = n_caps;
+    a.n_avatars = n_avatars;
+    a.clip_first = clip_first;
+    a.clip_frames = clip_frames;
+    a.frame_pos = frame_pos;
+    a.clearance = clearance;
+    a.nearest = nearest;
+    a.step_gap = step_gap;
+    a.blocked = blocked;
+    hipError_t e = gs::launch_capsule_queries(a, (hipStream_t)stream);
+    return e == hipSuccess ? GS_OK : hip_fail(e, "gs_capsule_queries");
 }
 
 gs_status gs_sensor_compose(int32_t n_views, int32_t height, int32_t width, const float *rgb, const float *depth,

@@ -136,6 +136,22 @@ struct SensorArgs {
     float *out_depth;
 };
 
+// avatar capsule queries: agents [n_agents] against the capsules of their
+// avatars, interpolated in per-avatar clips
+struct CapsuleArgs {
+    int64_t n_agents;
+    const float *agent_pos, *agent_next;  // [n][3]; agent_next NULL: no step query
+    const int32_t *agent_avatars;         // [n][2] (first, count)
+    float radius, height;
+    const float *caps;  // [clip_total][n_caps][8] (a.xyz, r, b.xyz, -)
+    int32_t clip_total, n_caps, n_avatars;
+    const int32_t *clip_first, *clip_frames;
+    const float *frame_pos;
+    float *clearance, *step_gap;
+    int32_t *nearest;
+    uint8_t *blocked;
+};
+
 struct SortPlan {
     int64_t n, capacity, n_tiles_total;
     int tile_bits, passes;
@@ -166,6 +182,7 @@ hipError_t launch_backward_tiles(BackwardTileArgs a, int n_cu, hipStream_t s);
 hipError_t launch_backward_project(const BackwardProjectArgs &a, hipStream_t s);
 hipError_t launch_lbs(const LbsArgs &a, bool backward, hipStream_t s);
 hipError_t launch_sensor(const SensorArgs &a, bool vec4, hipStream_t s);
+hipError_t launch_capsule_queries(const CapsuleArgs &a, hipStream_t s);
 
 // Launch a kernel through hipLaunchKernel so that the call returns the status
 // of this launch itself (never a stale error of an earlier runtime call).  The

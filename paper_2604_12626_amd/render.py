@@ -205,3 +205,14 @@ def observation(rgb, depth, alpha, mesh_rgba=None, mesh_depth=None, out=None):
                torch.empty((V, H, W), dtype=torch.float32, device=depth.device))
     B.sensor_compose(_c(rgb), _c(depth), _c(alpha), out[0], out[1], _c(mesh_rgba), _c(mesh_depth))
     return out
+
+
+def observation_two_pass(scene, avatars, out=None):
+    """The paper's own way of adding avatars (Sec. 3.2): scene and avatars
+    rasterized in separate passes, then each pixel keeps the nearer of the
+    two fragments (the avatar pass wins ties), with the same 8-bit / metric
+    depth hand-off.  `scene` and `avatars` are rendered frames of the same
+    views (any objects with rgb, depth and alpha).  The union rendering --
+    avatars as a second segment of one pass -- blends the two instead."""
+    av = observation(avatars.rgb, avatars.depth, avatars.alpha)
+    return observation(scene.rgb, scene.depth, scene.alpha, mesh_rgba=av[0], mesh_depth=av[1], out=out)

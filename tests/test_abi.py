@@ -149,6 +149,29 @@ def test_lbs_clip_validation(lib):
     assert g(10, a, a, a, a, a, a, a, 5, a, a, a, 1, 24, a, a, a, a, None, None) == B.GS_ERR_INVALID_ARGUMENT
 
 
+def test_capsule_queries_validation(lib):
+    from paper_2604_12626_amd import binding as B
+    a = ctypes.c_void_p(0x10000)
+    f = lib.gs_capsule_queries
+    ok = [a, a, a, 0.1, 1.5, a, 4, 23, a, a, a, 2, a, a, a, a, None]
+    assert f(0, *([None] * 3), 0.1, 1.5, None, 0, 0, None, None, None, 0, None, None, None, None, None) == B.GS_OK
+    assert f(-1, *ok) == B.GS_ERR_INVALID_ARGUMENT
+    for k, bad in ((3, -0.1), (3, float("nan")), (4, float("inf")), (6, 0), (7, 0), (11, 0)):
+        args = list(ok)
+        args[k] = bad
+        assert f(5, *args) == B.GS_ERR_INVALID_ARGUMENT, k
+    for k in (0, 2, 5, 8, 9, 10, 12):  # required arrays
+        args = list(ok)
+        args[k] = None
+        assert f(5, *args) == B.GS_ERR_INVALID_ARGUMENT, k
+    args = list(ok)
+    args[1] = None  # no step but step outputs given
+    assert f(5, *args) == B.GS_ERR_INVALID_ARGUMENT and "all" in _err(lib)
+    args = list(ok)
+    args[5] = ctypes.c_void_p(0x10004)  # misaligned capsules
+    assert f(5, *args) == B.GS_ERR_INVALID_ARGUMENT
+
+
 def test_sensor_compose_validation(lib):
     from paper_2604_12626_amd import binding as B
     a = ctypes.c_void_p(0x10000)

@@ -2,6 +2,7 @@
 against the oracle.  The kernel turns floats into byte codes and a depth
 comparison, and both sides take those decisions in FP32, so the bar is
 bit-exact: every byte and every depth bit pattern."""
+import math
 import sys
 
 import numpy as np
@@ -113,3 +114,59 @@ def test_sensor_of_a_rendered_frame(dev, orc):
     # without a mesh pass: the frame's own observation
     d.pop("mesh_rgba"), d.pop("mesh_depth")
     _check(orc, d, False, _compose_gpu(d, dev, False))
+
+
+def test_two_pass_avatars_against_union(dev, orc):
+    # room + 8 posed avatars, 2 views: the two-pass composition matches the
+    # oracle's select of the two passes bit for bit, and the union rendering
+    # equals the scene-only rendering wherever no avatar Gaussian is drawn
+    import torch
+    from paper_2604_12626_amd import binding as B, render
+    say("two-pass avatars vs union, room 50k + 8 x 2.5k avatars, 2 x 320x240")
+    cfg = synth.config(4, scale=0.05)
+    W, H = 320, 240
+    room = to_dev(cfg["segments"][0], dev)
+    av = to_dev(cfg["avatars"], dev)
+    n_av = av["means"].shape[0]
+    posed = {"means": torch.empty(n_av, 3, device=dev), "cov6": torch.empty(n_av, 6, device=dev),
+             "opacity": av["opacity"], "sh": av["sh"], "sh_degree": 3}
+    B.deform_lbs(av["means"], av["log_scales"], av["quats"], av["joint_idx"], av["weights"], av["avatar_of"],
+                 torch.from_numpy(cfg["skin"]).to(dev), posed["means"], posed["cov6"])
+    # two cameras 2.5 m from avatars 0 and 3 (at 1.2 m height), looking at them
+    pm = posed["means"].cpu().numpy()
+    aof = cfg["avatars"]["avatar_of"]
+    cams = []
+    for a, yaw in ((0, 0.3), (3, 2.0)):
+        c = pm[aof == a].mean(0)
+        pos = c - 2.5 * np.array([math.cos(yaw), math.sin(yaw), 0.0])
+        pos[2] = 1.2
+        cams.append(synth.look_camera(pos, yaw, math.atan2(c[2] - 1.2, 2.5), W / 2.0, W / 2.0, W / 2.0, H / 2.0))
+    tc = torch.from_numpy(np.stack(cams)).to(dev)
+    frames = {}
+    for name, segs, vs in (("scene", [room], [[0], [0]]), ("avatars", [posed], [[0], [0]]),
+                           ("union", [room, posed], [[0, 1], [0, 1]])):
+        r = render.Renderer(W, H, capacity=1 << 21, device=dev)
+        f = r.render(segs, tc, vs)
+        frames[name] = {k: getattr(f, k).clone() for k in ("rgb", "depth", "alpha")}
+        del r
+    torch.cuda.synchronize()
+
+    class F:
+        def __init__(self, d):
+            self.__dict__.update(d)
+
+    got = render.observation_two_pass(F(frames["scene"]), F(frames["avatars"]))
+    torch.cuda.synchronize()
+    h = {n: {k: v.cpu().numpy() for k, v in d.items()} for n, d in frames.items()}
+    av_obs = orc.sensor_compose(h["avatars"]["rgb"], h["avatars"]["depth"], h["avatars"]["alpha"])
+    ref = orc.sensor_compose(h["scene"]["rgb"], h["scene"]["depth"], h["scene"]["alpha"], av_obs[0], av_obs[1])
+    assert np.array_equal(got[0].cpu().numpy(), ref[0])
+    assert np.array_equal(got[1].cpu().numpy().view(np.uint32), ref[1].view(np.uint32))
+    no_av = h["avatars"]["alpha"] == 0
+    some = ~no_av
+    assert some.sum() > 200 and no_av.sum() > 1000
+    for k in ("rgb", "depth", "alpha"):
+        assert np.array_equal(h["union"][k][no_av], h["scene"][k][no_av]), k
+    # where avatars are drawn the two modes may differ (blend vs select)
+    diff = np.abs(h["union"]["rgb"] - ref[0][..., :3] / 255.0).max(-1)
+    say("pixels with avatars: %d, mean |union - two-pass| colour %.4f" % (some.sum(), diff[some].mean()))
