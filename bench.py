@@ -211,7 +211,7 @@ def bench_avatars(args, dev, steps):
     to the canonical avatar parameters (fwd+bwd; checkpoints "auto", which
     leaves them off for 19200 tile lists)."""
     import torch
-    from paper_2604_12626_amd import binding as B, render
+    from paper_2604_12626_amd import autotune, binding as B, render
     from paper_2604_12626_amd import synth
     cfg = synth.config(4)
     room = to_dev(cfg["segments"][0], dev)
@@ -233,6 +233,7 @@ def bench_avatars(args, dev, steps):
 
     lbs()
     f = r.render([room, posed], cams, vs)
+    autotune.tune_composite(r, f, len(vs))  # the compositing schedule for this workload
     target = torch.rand_like(f.rgb)
 
     def frame():

@@ -148,7 +148,7 @@ void gs_default_params(gs_params *p, int32_t width, int32_t height);
 /* Launch configuration (host-side, process-wide; it changes scheduling only,
  * never a result).
  *  composite_groups_per_cu: persistent 4-wave groups per compute unit in
- *    gs_composite (1..32, default 4); each wave of the grid pops (view, tile,
+ *    gs_composite (1..32, default 3); each wave of the grid pops (view, tile,
  *    quadrant) work items until none is left.
  *  sort_partition_keys: keys per onesweep partition in gs_bin_sort (4096 or
  *    8192, default 4096).

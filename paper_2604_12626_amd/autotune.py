@@ -20,7 +20,7 @@ import torch
 
 from . import binding as B
 
-CANDIDATES = (1, 2, 4, 8, 16)
+CANDIDATES = (2, 3, 4, 5, 6, 8)
 _cache: dict = {}
 
 

@@ -105,7 +105,7 @@ int64_t seg_offset_in_view(const gs_gaussians *segs, uint32_t mask, int s) {
     return o;
 }
 
-std::atomic<int> g_comp_groups{4};
+std::atomic<int> g_comp_groups{3};
 std::atomic<int> g_sort_part_keys{4096};
 std::atomic<int> g_sort_lookback{16};
 std::atomic<int> g_sort_algorithm{0};
@@ -161,7 +161,7 @@ void gs_default_params(gs_params *p, int32_t width, int32_t height) {
 gs_status gs_set_tuning(const gs_tuning *t) {
     clear_error();
     if (!t) {
-        g_comp_groups.store(4);
+        g_comp_groups.store(3);
         g_sort_part_keys.store(4096);
         g_sort_lookback.store(16);
         g_sort_algorithm.store(0);

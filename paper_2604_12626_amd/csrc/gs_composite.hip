@@ -90,41 +90,51 @@ __global__ void __launch_bounds__(64 * kWavesPerGroup) composite_kernel(const Co
         uint32_t last = 0;
         uint32_t done_end = 0;  // list position after the last chunk walked
         bool done = !inside;
-        // software pipeline over the list chunks: while chunk c is culled and
-        // composited, the records of chunk c + 1 and the list values of
-        // chunk c + 2 are already in flight
-        uint32_t g_next = 0u;  // list value of this lane's entry in the next chunk
-        float4 q0, q1, q2;     // this lane's record in the current chunk
-        {
-            const uint32_t j0 = range.x + lane, j1 = range.x + 64 + lane;
-            if (j0 < range.y) {
-                const uint32_t g = a.vals[j0];
-                q0 = a.rec[3 * (size_t)g];
-                q1 = a.rec[3 * (size_t)g + 1];
-                q2 = a.rec[3 * (size_t)g + 2];
-            }
-            if (j1 < range.y) g_next = a.vals[j1];
+        // software pipeline over the list chunks, two deep: the records of
+        // chunks c and c + 1 sit in two register sets and the list values of
+        // c + 2 and c + 3 are in flight; once chunk c's records have been
+        // culled and staged, its set is refilled in place with chunk c + 2
+        float4 qa0, qa1, qa2, qb0, qb1, qb2;  // records of this lane's entry in chunks c, c + 1
+        uint32_t ga = 0u, gb = 0u;            // list values of its entries in chunks c + 2, c + 3
+        // every load is unconditional: a lane past the list's end reads the
+        // list's last entry again (a cache hit), so a refill overwrites its
+        // whole register set and needs no merge with the old contents
+        const uint32_t jl = range.y > range.x ? range.y - 1u : range.x;
+        if (range.y > range.x) {
+            const uint32_t j0 = range.x + lane;
+            const uint32_t g0 = a.vals[min(j0, jl)], g1 = a.vals[min(j0 + 64u, jl)];
+            // issued in the order the loop refills them
+            qa0 = a.rec[3 * (size_t)g0];
+            qa1 = a.rec[3 * (size_t)g0 + 1];
+            qa2 = a.rec[3 * (size_t)g0 + 2];
+            ga = a.vals[min(j0 + 128u, jl)];
+            qb0 = a.rec[3 * (size_t)g1];
+            qb1 = a.rec[3 * (size_t)g1 + 1];
+            qb2 = a.rec[3 * (size_t)g1 + 2];
+            gb = a.vals[min(j0 + 192u, jl)];
         }
-        for (uint32_t b0 = range.x; b0 < range.y; b0 += 64) {
+        // one chunk of 64 list entries starting at b0 whose records are in
+        // (q0, q1, q2); returns true once every pixel of the quadrant stopped
+        auto chunk = [&](uint32_t b0, float4 &q0, float4 &q1, float4 &q2, uint32_t &gn) -> bool {
             const uint32_t j = b0 + lane;
             const bool hit = (j < range.y) && entry_reaches_box(q0.x, q0.y, q1.x, q1.y, q1.z, q1.w, a.alpha_min,
                                                                bx0, by0, bx0 + 7.0f, by0 + 7.0f);
-            const float4 c0 = q0, c1 = q1, c2 = q2;
-            // next chunk's records, and the list values of the one after
-            if (j + 64 < range.y) {
-                q0 = a.rec[3 * (size_t)g_next];
-                q1 = a.rec[3 * (size_t)g_next + 1];
-                q2 = a.rec[3 * (size_t)g_next + 2];
-            }
-            if (j + 128 < range.y) g_next = a.vals[j + 128];
+            // the whole record set has arrived here on every path, so the
+            // in-place refill below never waits on its old loads
+            asm volatile("" ::"v"(q0.z), "v"(q0.w), "v"(q2.x), "v"(q2.y), "v"(q2.z));
             const uint64_t bal = __ballot(hit);
             if (hit) {
                 const int pos = __popcll(bal & lt_mask);
-                const Entry e = make_entry(c0, c1, c2);
+                const Entry e = make_entry(q0, q1, q2);
                 e0s[pos] = make_float4(e.u, e.v, e.a, e.b);
                 e1s[pos] = make_float4(e.c, e.o, e.z, e.r);
                 e2s[pos] = make_float4(e.g, e.bl, __uint_as_float(b0 - range.x + (uint32_t)lane + 1u), 0.0f);
             }
+            // refill: the records of chunk c + 2, the list values of c + 4
+            q0 = a.rec[3 * (size_t)gn];
+            q1 = a.rec[3 * (size_t)gn + 1];
+            q2 = a.rec[3 * (size_t)gn + 2];
+            gn = a.vals[min(j + 256u, jl)];
             __builtin_amdgcn_wave_barrier();
             const int n = __popcll(bal);
             // pad the list to a multiple of 4 with entries of zero opacity
@@ -175,7 +185,12 @@ __global__ void __launch_bounds__(64 * kWavesPerGroup) composite_kernel(const Co
                     a.ckpt[ckpt_index(slot, quad, 4, lane)] = dd;
                 }
             }
-            if (__ballot(!done) == 0ull) break;
+            return __ballot(!done) == 0ull;
+        };
+        for (uint32_t b0 = range.x; b0 < range.y; b0 += 128) {
+            if (chunk(b0, qa0, qa1, qa2, ga)) break;
+            if (b0 + 64 >= range.y) break;
+            if (chunk(b0 + 64, qb0, qb1, qb2, gb)) break;
         }
         // the checkpoints crossed become (T_b, what is still to come behind b
         // -- the final colour, background included, minus the colour so far --

@@ -223,7 +223,7 @@ def test_tuning_validation():
         assert B.get_tuning() == {"composite_groups_per_cu": 5, "sort_partition_keys": 8192, "sort_lookback": 64,
                                   "sort_algorithm": 1}
         B.set_tuning()
-        assert B.get_tuning() == {"composite_groups_per_cu": 4, "sort_partition_keys": 4096, "sort_lookback": 16,
+        assert B.get_tuning() == {"composite_groups_per_cu": 3, "sort_partition_keys": 4096, "sort_lookback": 16,
                                   "sort_algorithm": 0}
     finally:
         B.set_tuning(**prev)
