@@ -528,3 +528,32 @@ def capsule_queries(agent_pos, agent_next, agent_avatars, radius, height, caps, 
                     gs = segment_parallelogram_distance(ca, cb, p0, p1 - p0, zup) - radius - r
                     step_gap[e] = min(step_gap[e], gs)
     return clearance, nearest, step_gap
+
+
+def lbs_backward_joints(means, log_scales, quats, w_dense, avatar_of, skin, n_joints, d_means_out, d_cov6_out):
+    """Adjoint of lbs (O13) w.r.t. the joint matrices: d_skin [A][J][12] in
+    double.  Per Gaussian, with A = sum_j w_j M_j (3x4) and G the symmetric
+    adjoint of the posed covariance (off-diagonal cov6 adjoints halved):
+    dL/dA[:, :3] = g mean^T + 2 G A3 Sigma, dL/dA[:, 3] = g; then
+    dL/dM_j += w_j dL/dA for the Gaussian's avatar."""
+    means = np.asarray(means, np.float64)
+    Sig = cov3d(log_scales, quats)  # [n, 6] (xx, xy, xz, yy, yz, zz)
+    n = len(means)
+    A_av = int(np.asarray(skin).shape[0])
+    sk = np.asarray(skin, np.float64).reshape(A_av, n_joints, 3, 4)
+    aof = np.asarray(avatar_of, np.int64)
+    w = np.asarray(w_dense, np.float64)
+    gm = np.asarray(d_means_out, np.float64)
+    gc = np.asarray(d_cov6_out, np.float64)
+    out = np.zeros((A_av, n_joints, 3, 4))
+    for i in range(n):
+        A = np.einsum("j,jrc->rc", w[i], sk[aof[i]])
+        S = np.array([[Sig[i, 0], Sig[i, 1], Sig[i, 2]], [Sig[i, 1], Sig[i, 3], Sig[i, 4]],
+                      [Sig[i, 2], Sig[i, 4], Sig[i, 5]]])
+        G = np.array([[gc[i, 0], gc[i, 1] / 2, gc[i, 2] / 2], [gc[i, 1] / 2, gc[i, 3], gc[i, 4] / 2],
+                      [gc[i, 2] / 2, gc[i, 4] / 2, gc[i, 5]]])
+        dA = np.zeros((3, 4))
+        dA[:, :3] = np.outer(gm[i], means[i]) + 2.0 * G @ A[:, :3] @ S
+        dA[:, 3] = gm[i]
+        out[aof[i]] += w[i][:, None, None] * dA[None]
+    return out.reshape(A_av, n_joints, 12)

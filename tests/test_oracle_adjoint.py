@@ -397,3 +397,36 @@ def test_clip_lbs_backward_by_finite_differences(orc):
                 bp[k], bm[k] = ap, am
                 fd = (L(*bp) - L(*bm)) / (float(ap[i, c]) - float(am[i, c]))
                 assert abs(fd - ref[i, c]) <= 1e-5 * np.abs(ref).max() + 1e-4 * abs(ref[i, c]), (name, i, c)
+
+
+def test_lbs_joint_matrix_adjoint_by_finite_differences(orc):
+    # adjoint w.r.t. the joint matrices (two avatars), against central
+    # differences of the forward oracle on every entry of a few joints
+    av = _avatar(30, 81)
+    n, J = len(av["means"]), synth.N_JOINTS
+    rng = np.random.default_rng(82)
+    skin = np.stack([synth.skinning_matrices(*synth.avatar_pose(rng)) for _ in range(2)]).astype(F32)
+    w = orc.dense_weights(av["joint_idx"], av["weights"], J)
+    aof = (np.arange(n) % 2).astype(np.int32)
+    Gm = rng.standard_normal((n, 3)).astype(F32)
+    Gc = rng.standard_normal((n, 6)).astype(F32)
+    dM = orc.lbs_backward_joints(av["means"], av["log_scales"], av["quats"], w, aof, skin, J, Gm, Gc)
+
+    def L(sk):
+        mo, co = orc.lbs(av["means"], av["log_scales"], av["quats"], w, aof, sk, J)
+        return (Gm * mo).sum() + (Gc * co).sum()
+
+    used = np.unique(np.concatenate([av["joint_idx"][aof == a].ravel() * 0 + a * J + av["joint_idx"][aof == a].ravel()
+                                     for a in range(2)]))
+    for aj in used[::4]:
+        a, j = divmod(int(aj), J)
+        for e in range(12):
+            x0 = float(skin[a, j, e])
+            h = 1e-3 * max(abs(x0), 0.1)
+            sp, sm = skin.copy(), skin.copy()
+            sp[a, j, e], sm[a, j, e] = F32(x0 + h), F32(x0 - h)
+            fd = (L(sp) - L(sm)) / (float(sp[a, j, e]) - float(sm[a, j, e]))
+            assert abs(fd - dM[a, j, e]) <= 1e-6 * np.abs(dM).max() + 1e-5 * abs(dM[a, j, e]), (a, j, e)
+    # joints no Gaussian uses get no gradient
+    unused = np.setdiff1d(np.arange(2 * J), used)
+    assert np.all(dM.reshape(2 * J, 12)[unused] == 0)
