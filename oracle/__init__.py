@@ -557,3 +557,41 @@ def lbs_backward_joints(means, log_scales, quats, w_dense, avatar_of, skin, n_jo
         dA[:, 3] = gm[i]
         out[aof[i]] += w[i][:, None, None] * dA[None]
     return out.reshape(A_av, n_joints, 12)
+
+
+def axis_angle_matrix(w):
+    """Rotation by |w| about w / |w| (Rodrigues' formula), double."""
+    w = np.asarray(w, np.float64)
+    th = float(np.linalg.norm(w))
+    if th == 0.0:
+        return np.eye(3)
+    k = w / th
+    K = np.array([[0.0, -k[2], k[1]], [k[2], 0.0, -k[0]], [-k[1], k[0], 0.0]])
+    return np.eye(3) + math.sin(th) * K + (1.0 - math.cos(th)) * (K @ K)
+
+
+def forward_kinematics(parents, rest, pose, root):
+    """Skinning matrices of posed skeletons (the forward-kinematics step that
+    turns joint rotations into the per-frame joint matrices of Sec. 3.3):
+    joint k's world transform is its parent's (the root transform for the
+    root) times [R(pose_k) | rest_k - rest_parent] (rest_k for the root), and
+    its skinning matrix is that transform times [I | -rest_k], i.e. relative
+    to the rest pose.  pose [A][J][3] axis-angle, root [A][12] (3x4),
+    rest [J][3].  Returns [A][J][12] double."""
+    rest = np.asarray(rest, np.float64)
+    A, J = len(pose), len(parents)
+    out = np.zeros((A, J, 12))
+    for a in range(A):
+        Rt = np.eye(4)
+        Rt[:3, :] = np.asarray(root[a], np.float64).reshape(3, 4)
+        G = [None] * J
+        for k in range(J):
+            L = np.eye(4)
+            L[:3, :3] = axis_angle_matrix(pose[a][k])
+            p = int(parents[k])
+            L[:3, 3] = rest[k] - (rest[p] if p >= 0 else 0.0)
+            G[k] = (Rt if p < 0 else G[p]) @ L
+            to_rest = np.eye(4)
+            to_rest[:3, 3] = -rest[k]
+            out[a, k] = (G[k] @ to_rest)[:3, :].reshape(12)
+    return out

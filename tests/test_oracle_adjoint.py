@@ -430,3 +430,55 @@ def test_lbs_joint_matrix_adjoint_by_finite_differences(orc):
     # joints no Gaussian uses get no gradient
     unused = np.setdiff1d(np.arange(2 * J), used)
     assert np.all(dM.reshape(2 * J, 12)[unused] == 0)
+
+
+def test_forward_kinematics_pins(orc):
+    J = synth.N_JOINTS
+    par, rest = synth.PARENTS, synth.REST
+    # rest pose with the identity root: every skinning matrix is the identity
+    M = orc.forward_kinematics(par, rest, np.zeros((1, J, 3)), [np.eye(3, 4).reshape(12)])
+    assert np.allclose(M[0], np.tile(np.eye(3, 4).reshape(12), (J, 1)), atol=1e-15)
+    # rest pose under a rigid root transform: every joint carries the root transform
+    Rr = Rotation.from_rotvec([0.2, -0.4, 1.1]).as_matrix()
+    root = np.concatenate([Rr, [[0.5], [-1.0], [2.0]]], 1).reshape(12)
+    M = orc.forward_kinematics(par, rest, np.zeros((1, J, 3)), [root])
+    assert np.allclose(M[0], np.tile(root, (J, 1)), atol=1e-14)
+    # random poses: rotation parts orthonormal, posed bones keep their rest
+    # lengths, Rodrigues against scipy
+    rng = np.random.default_rng(17)
+    pose = rng.normal(0.0, 0.5, (3, J, 3))
+    roots = [np.concatenate([Rotation.from_rotvec(rng.normal(0, 1, 3)).as_matrix(), rng.normal(0, 1, (3, 1))], 1).reshape(12)
+             for _ in range(3)]
+    M = orc.forward_kinematics(par, rest, pose, roots).reshape(3, J, 3, 4)
+    for a in range(3):
+        posed = np.einsum("kij,kj->ki", M[a, :, :, :3], rest) + M[a, :, :, 3]
+        for k in range(J):
+            assert np.allclose(M[a, k, :, :3] @ M[a, k, :, :3].T, np.eye(3), atol=1e-12)
+            if par[k] >= 0:
+                assert abs(np.linalg.norm(posed[k] - posed[par[k]]) - np.linalg.norm(rest[k] - rest[par[k]])) < 1e-12
+    for w in rng.normal(0.0, 1.0, (5, 3)):
+        assert np.allclose(orc.axis_angle_matrix(w), Rotation.from_rotvec(w).as_matrix(), atol=1e-14)
+    # a single bent joint: its children rotate about it, the rest do not move
+    pose1 = np.zeros((1, J, 3))
+    k0 = [k for k in range(J) if par[k] >= 0 and any(par[c] == k for c in range(J))][0]
+    pose1[0, k0] = [0.0, 0.0, 0.7]
+    M = orc.forward_kinematics(par, rest, pose1, [np.eye(3, 4).reshape(12)]).reshape(J, 3, 4)
+    anc = set()
+    k = k0
+    while k >= 0:
+        anc.add(k)
+        k = par[k]
+    for k in range(J):
+        if k in anc - {k0} or not _descends(par, k, k0):
+            assert np.allclose(M[k], np.eye(3, 4), atol=1e-15)
+        else:
+            assert np.allclose(M[k, :, :3], Rotation.from_rotvec([0, 0, 0.7]).as_matrix(), atol=1e-14)
+            assert np.allclose(M[k, :, :3] @ rest[k0] + M[k, :, 3], rest[k0], atol=1e-14)  # pivot fixed
+
+
+def _descends(par, k, anc):
+    while k >= 0:
+        if k == anc:
+            return True
+        k = par[k]
+    return False
