@@ -21,6 +21,9 @@
  *
  *   gs_deform_lbs_clip  the same skinning with each avatar's joint matrices
  *                       interpolated in its clip at the current time (Sec. 3.3)
+ *   gs_deform_lbs_backward_joints
+ *                       gradients w.r.t. the joint matrices (pose fitting)
+ *   gs_forward_kinematics  joint rotations -> joint (skinning) matrices
  *   gs_sensor_compose   8-bit RGBA + metric depth observation, nearer-fragment
  *                       select against a mesh pass (Sec. 3.2, Sec. 3.4)
  *   gs_capsule_queries  clearance to the nearest avatar capsule and blocked
@@ -205,6 +208,38 @@ gs_status gs_deform_lbs_backward(int64_t n, const float *means_c, const float *l
                                  const int32_t *avatar_of, const float *skin_mats, int32_t n_avatars,
                                  int32_t n_joints, const float *d_means_out, const float *d_cov6_out,
                                  float *d_means_c, float *d_log_scales_c, float *d_quats_c, gs_stream_t stream);
+
+/* Adjoint of gs_deform_lbs w.r.t. the joint matrices: d_skin_mats
+ * [n_avatars][n_joints][12] (overwritten) = sum over the Gaussians of each
+ * avatar of w_k dL/dA for the joints they blend, with dL/dA[:, :3] =
+ * g mean^T + 2 G A3 Sigma and dL/dA[:, 3] = g (g = d_means_out, G the
+ * symmetric adjoint of the posed covariance from d_cov6_out).  For fitting
+ * poses through the renderer; the paper prepares the matrices offline.
+ * Summed with float atomics (per-workgroup partial sums first when all
+ * matrices fit in 16 KB), so the order of the additions, and the last bits,
+ * vary from run to run.  Arguments and errors as gs_deform_lbs_backward;
+ * n == 0 clears d_skin_mats. */
+gs_status gs_deform_lbs_backward_joints(int64_t n, const float *means_c, const float *log_scales_c,
+                                        const float *quats_c, const uint8_t *joint_idx, const float *weights,
+                                        const int32_t *avatar_of, const float *skin_mats, int32_t n_avatars,
+                                        int32_t n_joints, const float *d_means_out, const float *d_cov6_out,
+                                        float *d_skin_mats, gs_stream_t stream);
+
+/* Skinning matrices of posed skeletons: the forward-kinematics step that
+ * turns per-joint rotations into the joint matrices gs_deform_lbs consumes
+ * (the paper runs it offline on the GAMMA poses, Sec. 3.3; here it can run
+ * per frame on the device).  Joint k's world transform is its parent's (the
+ * root transform for a root) times [R(pose_k) | rest_k - rest_parent]
+ * (rest_k for a root); its skinning matrix is that times [I | -rest_k].
+ *  parents  HOST int32 [n_joints]: -1 for a root, else a joint < k
+ *  rest     [n_joints][3] rest-pose joint positions
+ *  pose     [n_avatars][n_joints][3] axis-angle rotations
+ *  root     [n_avatars][12] root transforms (row-major 3x4)
+ *  skin_out [n_avatars][n_joints][12], overwritten.
+ * One thread per avatar.  Errors: GS_ERR_INVALID_ARGUMENT for n_joints
+ * outside 1..256, parents not before their children, NULL arrays. */
+gs_status gs_forward_kinematics(int32_t n_avatars, int32_t n_joints, const int32_t *parents, const float *rest,
+                                const float *pose, const float *root, float *skin_out, gs_stream_t stream);
 
 /* The same deformation with each avatar's joint matrices taken at its
  * current time (Sec. 3.3, GAMMA trajectory: per-frame joint matrices

@@ -60,7 +60,7 @@ TUNING_FIELDS = ("composite_groups_per_cu", "sort_partition_keys", "sort_lookbac
 
 EXPORTS = ["gs_status_string", "gs_last_error", "gs_version", "gs_default_params", "gs_set_tuning", "gs_get_tuning",
            "gs_instance_offsets",
-           "gs_deform_lbs", "gs_deform_lbs_backward", "gs_deform_lbs_clip", "gs_deform_lbs_clip_backward", "gs_project", "gs_bin_sort_workspace", "gs_tile_order_words", "gs_bin_sort",
+           "gs_deform_lbs", "gs_deform_lbs_backward", "gs_deform_lbs_backward_joints", "gs_forward_kinematics", "gs_deform_lbs_clip", "gs_deform_lbs_clip_backward", "gs_project", "gs_bin_sort_workspace", "gs_tile_order_words", "gs_bin_sort",
            "gs_composite_workspace", "gs_composite", "gs_checkpoint_floats", "gs_render_backward_workspace", "gs_render_backward",
            "gs_sensor_compose", "gs_capsule_queries"]
 
@@ -91,6 +91,8 @@ def load():
     lib.gs_instance_offsets.argtypes = [ctypes.POINTER(Gaussians), i32, i32, P, P]
     lib.gs_deform_lbs.argtypes = [i64, P, P, P, P, P, P, P, i32, i32, P, P, P]
     lib.gs_deform_lbs_backward.argtypes = [i64, P, P, P, P, P, P, P, i32, i32, P, P, P, P, P, P]
+    lib.gs_deform_lbs_backward_joints.argtypes = [i64, P, P, P, P, P, P, P, i32, i32, P, P, P, P]
+    lib.gs_forward_kinematics.argtypes = [i32, i32, P, P, P, P, P, P]
     lib.gs_deform_lbs_clip.argtypes = [i64, P, P, P, P, P, P, P, i32, P, P, P, i32, i32, P, P, P]
     lib.gs_deform_lbs_clip_backward.argtypes = [i64, P, P, P, P, P, P, P, i32, P, P, P, i32, i32, P, P, P, P, P, P]
     lib.gs_project.argtypes = [ctypes.POINTER(Gaussians), i32, P, i32, P, ctypes.POINTER(Params),
@@ -118,7 +120,7 @@ def load():
     lib.gs_set_tuning.argtypes = [ctypes.POINTER(Tuning)]
     lib.gs_get_tuning.argtypes = [ctypes.POINTER(Tuning)]
     lib.gs_get_tuning.restype = None
-    for f in ("gs_deform_lbs", "gs_deform_lbs_backward", "gs_deform_lbs_clip", "gs_deform_lbs_clip_backward",
+    for f in ("gs_deform_lbs", "gs_deform_lbs_backward", "gs_deform_lbs_backward_joints", "gs_forward_kinematics", "gs_deform_lbs_clip", "gs_deform_lbs_clip_backward",
               "gs_project", "gs_bin_sort", "gs_composite",
               "gs_render_backward", "gs_instance_offsets", "gs_set_tuning", "gs_sensor_compose",
               "gs_capsule_queries"):
@@ -297,6 +299,24 @@ def sensor_compose(rgb, depth, alpha, out_rgba, out_depth, mesh_rgba=None, mesh_
     V, H, W = (int(x) for x in depth.shape)
     _check(lib.gs_sensor_compose(V, H, W, ptr(rgb), ptr(depth), ptr(alpha), ptr(mesh_rgba), ptr(mesh_depth),
                                  ptr(out_rgba), ptr(out_depth), stream_handle()))
+
+
+def deform_lbs_backward_joints(means_c, log_scales_c, quats_c, joint_idx, weights, avatar_of, skin_mats, d_means_out,
+                               d_cov6_out, d_skin_mats):
+    lib = load()
+    A, J = int(skin_mats.shape[0]), int(skin_mats.shape[1])
+    _check(lib.gs_deform_lbs_backward_joints(int(means_c.shape[0]), ptr(means_c), ptr(log_scales_c), ptr(quats_c),
+                                             ptr(joint_idx), ptr(weights), ptr(avatar_of), ptr(skin_mats), A, J,
+                                             ptr(d_means_out), ptr(d_cov6_out), ptr(d_skin_mats), stream_handle()))
+
+
+def forward_kinematics(parents, rest, pose, root, skin_out):
+    """gs_forward_kinematics: parents is a host sequence of ints; rest [J, 3],
+    pose [A, J, 3], root [A, 12] and skin_out [A, J, 12] on the device."""
+    lib = load()
+    par = (ctypes.c_int32 * len(parents))(*[int(p) for p in parents])
+    _check(lib.gs_forward_kinematics(int(pose.shape[0]), len(parents), par, ptr(rest), ptr(pose), ptr(root),
+                                     ptr(skin_out), stream_handle()))
 
 
 def deform_lbs_clip(means_c, log_scales_c, quats_c, joint_idx, weights, avatar_of, clip, clip_first, clip_frames,

@@ -546,6 +546,63 @@ gs_status gs_render_backward(const gs_gaussians *segs, int32_t n_segs, const gs_
     return GS_OK;
 }
 
+gs_status gs_deform_lbs_backward_joints(int64_t n, const float *means_c, const float *log_scales_c,
+                                        const float *quats_c, const uint8_t *joint_idx, const float *weights,
+                                        const int32_t *avatar_of, const float *skin_mats, int32_t n_avatars,
+                                        int32_t n_joints, const float *d_means_out, const float *d_cov6_out,
+                                        float *d_skin_mats, gs_stream_t stream) {
+    clear_error();
+    if (n < 0) return fail(GS_ERR_INVALID_ARGUMENT, "n < 0");
+    if (n_avatars < 1 || n_joints < 1 || n_joints > 256)
+        return fail(GS_ERR_INVALID_ARGUMENT, "n_avatars=%d / n_joints=%d invalid", n_avatars, n_joints);
+    if (!d_skin_mats) return fail(GS_ERR_INVALID_ARGUMENT, "NULL d_skin_mats");
+    if (n > 0 && (!means_c || !log_scales_c || !quats_c || !joint_idx || !weights || !avatar_of || !skin_mats ||
+                  !d_means_out || !d_cov6_out))
+        return fail(GS_ERR_INVALID_ARGUMENT, "NULL array");
+    if (!aligned(quats_c, 16) || !aligned(weights, 16) || !aligned(skin_mats, 16) || !aligned(joint_idx, 4))
+        return fail(GS_ERR_INVALID_ARGUMENT, "quats/weights/skin_mats need 16-byte, joint_idx 4-byte alignment");
+    gs::LbsArgs a = {};
+    a.n = n;
+    a.means = means_c;
+    a.log_scales = log_scales_c;
+    a.quats = quats_c;
+    a.joint_idx = joint_idx;
+    a.weights = weights;
+    a.avatar_of = avatar_of;
+    a.skin = skin_mats;
+    a.n_avatars = n_avatars;
+    a.n_joints = n_joints;
+    a.d_means_out = d_means_out;
+    a.d_cov6_out = d_cov6_out;
+    hipError_t e = gs::launch_lbs_joint_grad(a, d_skin_mats, cu_count(), (hipStream_t)stream);
+    return e == hipSuccess ? GS_OK : hip_fail(e, "gs_deform_lbs_backward_joints");
+}
+
+gs_status gs_forward_kinematics(int32_t n_avatars, int32_t n_joints, const int32_t *parents, const float *rest,
+                                const float *pose, const float *root, float *skin_out, gs_stream_t stream) {
+    clear_error();
+    if (n_avatars < 0 || n_joints < 1 || n_joints > gs::kFkMaxJoints)
+        return fail(GS_ERR_INVALID_ARGUMENT, "n_avatars=%d / n_joints=%d invalid", n_avatars, n_joints);
+    if (!parents) return fail(GS_ERR_INVALID_ARGUMENT, "NULL parents (host array)");
+    gs::FkArgs f = {};
+    for (int k = 0; k < n_joints; ++k) {
+        if (parents[k] < -1 || parents[k] >= k)
+            return fail(GS_ERR_INVALID_ARGUMENT, "parents[%d]=%d: parents must come before their children", k,
+                        parents[k]);
+        f.parents[k] = (int16_t)parents[k];
+    }
+    if (n_avatars == 0) return GS_OK;
+    if (!rest || !pose || !root || !skin_out) return fail(GS_ERR_INVALID_ARGUMENT, "NULL array");
+    f.n_avatars = n_avatars;
+    f.n_joints = n_joints;
+    f.rest = rest;
+    f.pose = pose;
+    f.root = root;
+    f.out = skin_out;
+    hipError_t e = gs::launch_fk(f, (hipStream_t)stream);
+    return e == hipSuccess ? GS_OK : hip_fail(e, "gs_forward_kinematics");
+}
+
 // the clip-mode arguments shared by gs_deform_lbs_clip and its backward
 static gs_status clip_args(gs::LbsArgs &a, const float *clip_mats, int32_t clip_total_frames,
                            const int32_t *clip_first, const int32_t *clip_frames, const float *frame_pos) {

@@ -125,6 +125,17 @@ struct LbsArgs {
     int32_t clip_total;
 };
 
+// forward kinematics: one thread per avatar, joints in parent-first order
+constexpr int kFkMaxJoints = 256;
+struct FkArgs {
+    int32_t n_avatars, n_joints;
+    int16_t parents[kFkMaxJoints];
+    const float *rest;  // [J][3]
+    const float *pose;  // [A][J][3] axis-angle
+    const float *root;  // [A][12]
+    float *out;         // [A][J][12]
+};
+
 // sensor hand-off: n_px pixels of compositing outputs (and an optional mesh
 // pass) in, packed RGBA bytes and metric depth out
 struct SensorArgs {
@@ -181,6 +192,8 @@ hipError_t launch_composite(CompositeArgs a, int grid, hipStream_t s);
 hipError_t launch_backward_tiles(BackwardTileArgs a, int n_cu, hipStream_t s);
 hipError_t launch_backward_project(const BackwardProjectArgs &a, hipStream_t s);
 hipError_t launch_lbs(const LbsArgs &a, bool backward, hipStream_t s);
+hipError_t launch_lbs_joint_grad(const LbsArgs &a, float *d_skin, int n_cu, hipStream_t s);
+hipError_t launch_fk(const FkArgs &a, hipStream_t s);
 hipError_t launch_sensor(const SensorArgs &a, bool vec4, hipStream_t s);
 hipError_t launch_capsule_queries(const CapsuleArgs &a, hipStream_t s);
 

@@ -133,6 +133,32 @@ def test_lbs_and_composite_validation(lib):
     assert st == B.GS_ERR_INVALID_ARGUMENT  # misaligned checkpoints
 
 
+def test_lbs_joint_gradient_validation(lib):
+    from paper_2604_12626_amd import binding as B
+    a = ctypes.c_void_p(0x10000)
+    f = lib.gs_deform_lbs_backward_joints
+    assert f(-1, a, a, a, a, a, a, a, 1, 24, a, a, a, None) == B.GS_ERR_INVALID_ARGUMENT
+    assert f(10, a, a, a, a, a, a, a, 1, 24, a, a, None, None) == B.GS_ERR_INVALID_ARGUMENT
+    assert f(10, a, a, a, a, a, a, None, 1, 24, a, a, a, None) == B.GS_ERR_INVALID_ARGUMENT
+    assert f(10, a, a, a, a, a, a, a, 1, 300, a, a, a, None) == B.GS_ERR_INVALID_ARGUMENT
+    assert f(10, a, a, a, a, a, a, ctypes.c_void_p(0x10008), 1, 24, a, a, a, None) == B.GS_ERR_INVALID_ARGUMENT
+
+
+def test_forward_kinematics_validation(lib):
+    from paper_2604_12626_amd import binding as B
+    a = ctypes.c_void_p(0x10000)
+    f = lib.gs_forward_kinematics
+    par = lambda *p: (ctypes.c_int32 * len(p))(*p)
+    assert f(0, 3, par(-1, 0, 1), None, None, None, None, None) == B.GS_OK
+    assert f(2, 0, par(-1), a, a, a, a, None) == B.GS_ERR_INVALID_ARGUMENT
+    assert f(2, 257, None, a, a, a, a, None) == B.GS_ERR_INVALID_ARGUMENT
+    assert f(2, 3, None, a, a, a, a, None) == B.GS_ERR_INVALID_ARGUMENT
+    assert f(2, 3, par(-1, 2, 0), a, a, a, a, None) == B.GS_ERR_INVALID_ARGUMENT  # child before parent
+    assert "before" in _err(lib)
+    assert f(2, 3, par(-1, 0, -2), a, a, a, a, None) == B.GS_ERR_INVALID_ARGUMENT
+    assert f(2, 3, par(-1, 0, 1), a, None, a, a, None) == B.GS_ERR_INVALID_ARGUMENT
+
+
 def test_lbs_clip_validation(lib):
     from paper_2604_12626_amd import binding as B
     a = ctypes.c_void_p(0x10000)

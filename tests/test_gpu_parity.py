@@ -487,6 +487,65 @@ def test_lbs_parity(dev, orc):
 
 
 
+@pytest.mark.parametrize("n_avatars", [8, 16], ids=["lds_sums", "global_sums"])
+def test_lbs_joint_matrix_gradient_parity(dev, orc, n_avatars):
+    # adjoint w.r.t. the joint matrices; 16 avatars x 24 joints exceed the
+    # 16-KB workgroup copy, so the kernel sums into the output directly
+    import torch
+    from paper_2604_12626_amd import binding as B
+    cfg = synth.config(4, scale=0.02)
+    av = cfg["avatars"]
+    n, J = len(av["means"]), synth.N_JOINTS
+    rng = np.random.default_rng(91)
+    skin = np.stack([synth.skinning_matrices(*synth.avatar_pose(rng)) for _ in range(n_avatars)]).astype(F32)
+    aof = (np.arange(n) % n_avatars).astype(np.int32)
+    say("lbs joint-matrix gradient:", n, "gaussians,", n_avatars, "avatars")
+    t = to_dev(av, dev)
+    gm = rng.standard_normal((n, 3)).astype(F32)
+    gc = (rng.standard_normal((n, 6)) * 1e3).astype(F32)
+    d_skin = torch.full((n_avatars, J, 12), 7.0, device=dev)
+    B.deform_lbs_backward_joints(t["means"], t["log_scales"], t["quats"], t["joint_idx"], t["weights"],
+                                 torch.from_numpy(aof).to(dev), torch.from_numpy(skin).to(dev),
+                                 torch.from_numpy(gm).to(dev), torch.from_numpy(gc).to(dev), d_skin)
+    w = orc.dense_weights(av["joint_idx"], av["weights"], J)
+    ref = orc.lbs_backward_joints(av["means"], av["log_scales"], av["quats"], w, aof, skin, J, gm, gc)
+    torch.cuda.synchronize()
+    got = d_skin.cpu().numpy().astype(np.float64)
+    assert np.abs(got - ref).max() <= 2e-4 * np.abs(ref).max(), np.abs(got - ref).max() / np.abs(ref).max()
+    assert np.all(got[ref == 0] == 0)  # joints no Gaussian blends stay exactly zero
+
+
+@pytest.mark.parametrize("n_avatars", [8, 131], ids=["8", "131_ragged"])
+def test_forward_kinematics_parity(dev, orc, n_avatars):
+    import torch
+    from paper_2604_12626_amd import binding as B
+    J = synth.N_JOINTS
+    rng = np.random.default_rng(101)
+    pose = rng.normal(0.0, 0.6, (n_avatars, J, 3)).astype(F32)
+    pose[0] = 0.0                                   # rest pose
+    pose[1, :, :] = rng.normal(0.0, 1e-4, (J, 3))   # tiny angles (series branch of sin t / t)
+    pose[2, 5] = [0.0, 3.1, 0.0]                    # near pi
+    roots = np.stack([np.concatenate([synth.rodrigues(rng.normal(0, 1, 3)), rng.uniform(-4, 4, (3, 1))], 1)
+                      .reshape(12) for _ in range(n_avatars)]).astype(F32)
+    say("forward kinematics:", n_avatars, "avatars")
+    out = torch.full((n_avatars, J, 12), 7.0, device=dev)
+    B.forward_kinematics(synth.PARENTS, torch.from_numpy(synth.REST.astype(F32)).to(dev),
+                         torch.from_numpy(pose).to(dev), torch.from_numpy(roots).to(dev), out)
+    ref = orc.forward_kinematics(synth.PARENTS, synth.REST.astype(F32).astype(np.float64), pose, roots)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(got - ref) <= 2e-5 * np.maximum(1.0, np.abs(ref))), np.abs(got - ref).max()
+    # the matrices drive the skinning kernel like any others
+    cfg = synth.config(4, scale=0.02)
+    av = to_dev(cfg["avatars"], dev)
+    n = av["means"].shape[0]
+    mo, co = torch.empty(n, 3, device=dev), torch.empty(n, 6, device=dev)
+    B.deform_lbs(av["means"], av["log_scales"], av["quats"], av["joint_idx"], av["weights"], av["avatar_of"],
+                 out[:8].contiguous(), mo, co)
+    torch.cuda.synchronize()
+    assert torch.isfinite(mo).all() and torch.isfinite(co).all()
+
+
 CLIP_POSITIONS = [
     ("fractions", [0.0, 0.4, 2.5, 7.75, 13.2, 28.9, 1.0, 5.5]),
     ("integers_and_ends", [0.0, 1.0, 3.0, 8.0, 0.0, 29.0, 2.0, 11.0]),
