@@ -464,7 +464,8 @@ gs_status gs_capsule_queries(int32_t n_agents, const float *agent_pos, const flo
  * Outputs must not overlap the inputs.  Float arrays need 4-byte alignment
  * and the byte arrays 4-byte alignment; with every array 16-byte aligned
  * each thread moves four pixels with 16-byte accesses.  n_views == 0 is a
- * no-op.  Errors: GS_ERR_INVALID_ARGUMENT for negative or oversized sizes,
+ * no-op.  Errors: GS_ERR_INVALID_ARGUMENT for negative or oversized sizes
+ * (height or width above 65536, more than 2^38 pixels in all),
  * NULL arrays, only one of mesh_rgba / mesh_depth, or misalignment. */
 gs_status gs_sensor_compose(int32_t n_views, int32_t height, int32_t width, const float *rgb, const float *depth,
                             const float *alpha, const uint8_t *mesh_rgba, const float *mesh_depth,

@@ -749,6 +749,8 @@ gs_status gs_sensor_compose(int32_t n_views, int32_t height, int32_t width, cons
     }
     gs::SensorArgs a = {};
     a.n_px = (int64_t)n_views * height * width;
+    if (a.n_px > ((int64_t)1 << 38))  // keeps the one-pixel-per-thread grid within 2^30 workgroups
+        return fail(GS_ERR_INVALID_ARGUMENT, "%lld pixels: too many for one call", (long long)a.n_px);
     a.rgb = rgb;
     a.depth = depth;
     a.alpha = alpha;

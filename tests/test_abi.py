@@ -207,6 +207,7 @@ def test_sensor_compose_validation(lib):
     assert f(-1, 4, 4, a, a, a, None, None, a, a, None) == B.GS_ERR_INVALID_ARGUMENT
     assert f(1, 0, 4, a, a, a, None, None, a, a, None) == B.GS_ERR_INVALID_ARGUMENT
     assert f(1, 4, (1 << 16) + 1, a, a, a, None, None, a, a, None) == B.GS_ERR_INVALID_ARGUMENT
+    assert f(100000, 1 << 16, 1 << 16, a, a, a, None, None, a, a, None) == B.GS_ERR_INVALID_ARGUMENT  # > 2^38 px
     assert f(1, 4, 4, None, a, a, None, None, a, a, None) == B.GS_ERR_INVALID_ARGUMENT
     assert f(1, 4, 4, a, a, a, None, None, a, None, None) == B.GS_ERR_INVALID_ARGUMENT
     assert f(1, 4, 4, a, a, a, a, None, a, a, None) == B.GS_ERR_INVALID_ARGUMENT  # mesh colour without depth
