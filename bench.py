@@ -416,7 +416,7 @@ def copy_calibration(dev):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU only (this build renders on a single MI355X); "
+        print("bench.py measures one GPU only (the renderer runs on a single MI355X); "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch

@@ -75,7 +75,7 @@ typedef void *gs_stream_t;
 typedef enum gs_status {
     GS_OK = 0,
     GS_ERR_INVALID_ARGUMENT = 1,   /* a pointer, size or parameter is invalid */
-    GS_ERR_UNSUPPORTED = 2,        /* valid but outside this build's limits */
+    GS_ERR_UNSUPPORTED = 2,        /* valid but outside this library's limits */
     GS_ERR_WORKSPACE_TOO_SMALL = 3,
     GS_ERR_HIP = 4                 /* a HIP runtime call or launch failed */
 } gs_status;
