@@ -145,6 +145,8 @@ typedef struct gs_projected {
 /* ---------------------------------------------------------------------- */
 const char *gs_status_string(gs_status s);
 const char *gs_last_error(void); /* thread-local; "" if none */
+/* ABI version: 2 adds the sensor hand-off, the capsule queries, the clip,
+ * joint-gradient and forward-kinematics skinning calls. */
 int32_t gs_version(void);
 void gs_default_params(gs_params *p, int32_t width, int32_t height);
 

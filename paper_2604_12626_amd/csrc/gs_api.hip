@@ -142,7 +142,7 @@ const char *gs_status_string(gs_status s) {
 
 const char *gs_last_error(void) { return g_last_error.c_str(); }
 
-int32_t gs_version(void) { return 1; }
+int32_t gs_version(void) { return 2; }
 
 void gs_default_params(gs_params *p, int32_t width, int32_t height) {
     if (!p) return;

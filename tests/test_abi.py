@@ -41,6 +41,7 @@ def test_struct_layouts_match_header(lib):
 
 def test_status_strings_and_defaults(lib):
     from paper_2604_12626_amd import binding as B
+    assert lib.gs_version() == 2
     assert lib.gs_status_string(0) == b"GS_OK"
     assert lib.gs_status_string(3) == b"GS_ERR_WORKSPACE_TOO_SMALL"
     p = B.make_params(640, 480)
