@@ -265,3 +265,12 @@ def test_renderer_checkpoint_modes():
         render.Renderer(64, 64, device="cpu", checkpoints="sometimes")
     r = render.Renderer(64, 64, device="cpu", checkpoints="auto")
     assert r.checkpoints == "auto" and r.T * 1 <= render.Renderer.AUTO_CHECKPOINT_ITEMS
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # the benchmark measures one GPU; --gpus N > 1 exits with a message before touching a device
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2", "--steps", "1"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
