@@ -46,8 +46,16 @@ __device__ __forceinline__ float wave_sum_to_last(float v) {
     return v;
 }
 
+// SEG: the work is the listed (tile, segment) pairs (checkpoint mode); else
+// one whole list per workgroup.
+template <bool SEG>
 __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const BackwardTileArgs a) {
     __shared__ float4 s_e0[4][64], s_e1[4][64], s_e2[4][64], s_q[4][64];
+    // a segment of at most 64 list entries: the four quadrant waves add their
+    // per-entry sums here, and the workgroup then issues one set of global
+    // atomics per entry (instead of one per quadrant)
+    __shared__ float s_acc[SEG ? kSegment * kG2D : 1];
+    __shared__ uint32_t s_gid[SEG ? kSegment : 1];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     float4 *e0s = s_e0[wave], *e1s = s_e1[wave], *e2s = s_e2[wave], *qs = s_q[wave];
@@ -55,6 +63,10 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
     // listed pairs, popped by a persistent grid); wave w owns the 8 x 8
     // quadrant w, one pixel per lane
     const uint32_t n_work = a.seg_list ? a.seg_list[0] : (uint32_t)a.n_items;
+    if (SEG) {
+        for (int i = threadIdx.x; i < kSegment * kG2D; i += kTilePixels) s_acc[i] = 0.0f;
+        __syncthreads();
+    }
     for (uint32_t wk = blockIdx.x; wk < n_work; wk += a.n_groups) {
     const uint32_t entry = a.seg_list ? a.seg_list[1 + wk] : 0u;
     const int64_t item = a.seg_list ? (int64_t)(entry >> 6) : (int64_t)wk;
@@ -118,7 +130,12 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
     maxlast = min(maxlast, L);
     const uint32_t seg_end = last_seg ? maxlast : seg_lo + kSegment;  // state known here
     const uint32_t seg_hi = seg_end < maxlast ? seg_end : maxlast;
-    if (seg_lo >= seg_hi) continue;  // no barriers in the loop: waves move on on their own
+    // segments of at most 64 entries (every middle one, and a last one that
+    // short) sum per entry in LDS; the others add to HBM directly, wave by
+    // wave, with no barrier.  Uniform per workgroup: it depends on the item only.
+    const bool lds_sum = SEG && (pre || L <= seg_lo + (uint32_t)kSegment);
+    if (!lds_sum && seg_lo >= seg_hi) continue;
+    if (seg_lo < seg_hi) {
     // suffix colour / depth behind the current entry over its transmittance:
     // the background at the end of the walk, else the checkpoint at seg_end
     float Sr = a.bg0, Sg = a.bg1, Sb = a.bg2, Sd = 0.0f;
@@ -215,7 +232,22 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
             gg = wave_sum_to_last(gg);
             gb = wave_sum_to_last(gb);
             gz = wave_sum_to_last(gz);
-            if (lane == 63) {
+            if (lds_sum) {
+                if (lane == 63) {
+                    float *acc = s_acc + (pos - seg_lo) * kG2D;
+                    s_gid[pos - seg_lo] = __float_as_uint(e2.z);
+                    atomicAdd(acc + kGU, gu);
+                    atomicAdd(acc + kGV, gv);
+                    atomicAdd(acc + kGA, gA);
+                    atomicAdd(acc + kGB, gB);
+                    atomicAdd(acc + kGC, gC);
+                    atomicAdd(acc + kGO, go);
+                    atomicAdd(acc + kGR, gr);
+                    atomicAdd(acc + kGG, gg);
+                    atomicAdd(acc + kGBl, gb);
+                    atomicAdd(acc + kGZ, gz);
+                }
+            } else if (lane == 63) {
                 float *dst = a.g2d + (size_t)__float_as_uint(e2.z) * kG2D;
                 atomicAdd(dst + kGU, gu);
                 atomicAdd(dst + kGV, gv);
@@ -230,6 +262,20 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
             }
         }
         __builtin_amdgcn_wave_barrier();
+    }
+    }  // this wave's walk of the segment
+    if (lds_sum) {
+        // every quadrant has added its sums: one global atomic per nonzero
+        // (entry, value), and the accumulator is cleared for the next item
+        __syncthreads();
+        for (int i = threadIdx.x; i < kSegment * kG2D; i += kTilePixels) {
+            const float v = s_acc[i];
+            if (v != 0.0f) {
+                atomicAdd(a.g2d + (size_t)s_gid[i / kG2D] * kG2D + (i % kG2D), v);
+                s_acc[i] = 0.0f;
+            }
+        }
+        __syncthreads();
     }
     }  // work loop
 }
@@ -275,13 +321,13 @@ hipError_t launch_backward_tiles(BackwardTileArgs a, int n_cu, hipStream_t s) {
     if (a.seg_list && a.n_items >= (int64_t)1 << 26) a.seg_list = nullptr;  // item ids need 26 bits
     if (!a.seg_list) {  // one workgroup per list
         a.n_groups = (uint32_t)a.n_items;
-        return launch_kernel(backward_tile_kernel, dim3((unsigned)a.n_items), dim3(kTilePixels), s, a);
+        return launch_kernel(backward_tile_kernel<false>, dim3((unsigned)a.n_items), dim3(kTilePixels), s, a);
     }
     hipError_t e = launch_kernel(segment_list_kernel, dim3(1), dim3(1024), s, a.ranges, a.n_items, a.seg_list,
                                  (uint64_t)(a.ckpt_slots * kListPerSlot));
     if (e != hipSuccess) return e;
     a.n_groups = (uint32_t)(6 * n_cu);  // persistent: about what the CUs hold at once
-    return launch_kernel(backward_tile_kernel, dim3(a.n_groups), dim3(kTilePixels), s, a);
+    return launch_kernel(backward_tile_kernel<true>, dim3(a.n_groups), dim3(kTilePixels), s, a);
 }
 
 // ---------------------------------------------------------------------------
