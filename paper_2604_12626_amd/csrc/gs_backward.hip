@@ -47,15 +47,18 @@ __device__ __forceinline__ float wave_sum_to_last(float v) {
 }
 
 // SEG: the work is the listed (tile, segment) pairs (checkpoint mode); else
-// one whole list per workgroup.
-template <bool SEG>
+// one whole list per workgroup, its quadrant sums through LDS (WLDS) or
+// added to HBM by each wave.
+template <bool SEG, bool WLDS>
 __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const BackwardTileArgs a) {
+    constexpr bool kLds = SEG || WLDS;
     __shared__ float4 s_e0[4][64], s_e1[4][64], s_e2[4][64], s_q[4][64];
-    // a segment of at most 64 list entries: the four quadrant waves add their
-    // per-entry sums here, and the workgroup then issues one set of global
-    // atomics per entry (instead of one per quadrant)
-    __shared__ float s_acc[SEG ? kSegment * kG2D : 1];
-    __shared__ uint32_t s_gid[SEG ? kSegment : 1];
+    // 64 list positions: the four quadrant waves add their per-entry sums
+    // here, and the workgroup then issues one set of global atomics per entry
+    // (instead of one per quadrant)
+    __shared__ float s_acc[kLds ? kSegment * kG2D : 1];
+    __shared__ uint32_t s_gid[kLds ? kSegment : 1];
+    __shared__ uint32_t s_top;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     float4 *e0s = s_e0[wave], *e1s = s_e1[wave], *e2s = s_e2[wave], *qs = s_q[wave];
@@ -63,7 +66,7 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
     // listed pairs, popped by a persistent grid); wave w owns the 8 x 8
     // quadrant w, one pixel per lane
     const uint32_t n_work = a.seg_list ? a.seg_list[0] : (uint32_t)a.n_items;
-    if (SEG) {
+    if (kLds) {
         for (int i = threadIdx.x; i < kSegment * kG2D; i += kTilePixels) s_acc[i] = 0.0f;
         __syncthreads();
     }
@@ -130,12 +133,29 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
     maxlast = min(maxlast, L);
     const uint32_t seg_end = last_seg ? maxlast : seg_lo + kSegment;  // state known here
     const uint32_t seg_hi = seg_end < maxlast ? seg_end : maxlast;
-    // segments of at most 64 entries (every middle one, and a last one that
-    // short) sum per entry in LDS; the others add to HBM directly, wave by
-    // wave, with no barrier.  Uniform per workgroup: it depends on the item only.
-    const bool lds_sum = SEG && (pre || L <= seg_lo + (uint32_t)kSegment);
+    // Per-entry sums over the four quadrant waves go through LDS, 64 list
+    // positions at a time, for segments of at most 64 entries (every middle
+    // one, and a last one that short) and, when the launch has many lists,
+    // for whole lists: all waves walk the same chunks, from `top` down, and
+    // after each chunk the workgroup issues one global atomic per nonzero
+    // (entry, value).  Otherwise (a longer last segment, or a few long whole
+    // lists, where waves walking in step would wait for each other) each
+    // wave adds to HBM directly, with no barrier.  Uniform per workgroup.
+    const bool lds_sum = SEG ? (pre || L <= seg_lo + (uint32_t)kSegment) : WLDS;
     if (!lds_sum && seg_lo >= seg_hi) continue;
-    if (seg_lo < seg_hi) {
+    uint32_t top = seg_hi;
+    if (lds_sum) {
+        if (SEG) {
+            top = min(seg_lo + (uint32_t)kSegment, L);
+        } else {  // the longest walk of the four quadrants
+            if (threadIdx.x == 0) s_top = 0u;
+            __syncthreads();
+            if (lane == 0) atomicMax(&s_top, seg_hi);
+            __syncthreads();
+            top = s_top;
+        }
+    }
+    {
     // suffix colour / depth behind the current entry over its transmittance:
     // the background at the end of the walk, else the checkpoint at seg_end
     float Sr = a.bg0, Sg = a.bg1, Sb = a.bg2, Sd = 0.0f;
@@ -147,10 +167,11 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
         Sd = ck[4];
     }
 
-    // chunks [lo, hi) of list positions, from the back
-    for (int64_t hi = (int64_t)seg_hi; hi > (int64_t)seg_lo; hi -= 64) {
+    // chunks [lo, hi) of list positions, from the back (this wave's entries
+    // end at seg_hi)
+    for (int64_t hi = (int64_t)top; hi > (int64_t)seg_lo; hi -= 64) {
         const int64_t lo = hi - 64 > (int64_t)seg_lo ? hi - 64 : (int64_t)seg_lo;
-        const bool valid = lo + lane < hi;
+        const bool valid = lo + lane < min(hi, (int64_t)seg_hi);
         bool hit = false;
         float4 q0, q1, q2;
         uint32_t g = 0;
@@ -232,10 +253,10 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
             gg = wave_sum_to_last(gg);
             gb = wave_sum_to_last(gb);
             gz = wave_sum_to_last(gz);
-            if (lds_sum) {
+            if (kLds && lds_sum) {
                 if (lane == 63) {
-                    float *acc = s_acc + (pos - seg_lo) * kG2D;
-                    s_gid[pos - seg_lo] = __float_as_uint(e2.z);
+                    float *acc = s_acc + (pos - (uint32_t)lo) * kG2D;
+                    s_gid[pos - (uint32_t)lo] = __float_as_uint(e2.z);
                     atomicAdd(acc + kGU, gu);
                     atomicAdd(acc + kGV, gv);
                     atomicAdd(acc + kGA, gA);
@@ -262,21 +283,21 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
             }
         }
         __builtin_amdgcn_wave_barrier();
-    }
-    }  // this wave's walk of the segment
-    if (lds_sum) {
-        // every quadrant has added its sums: one global atomic per nonzero
-        // (entry, value), and the accumulator is cleared for the next item
-        __syncthreads();
-        for (int i = threadIdx.x; i < kSegment * kG2D; i += kTilePixels) {
-            const float v = s_acc[i];
-            if (v != 0.0f) {
-                atomicAdd(a.g2d + (size_t)s_gid[i / kG2D] * kG2D + (i % kG2D), v);
-                s_acc[i] = 0.0f;
+        if (kLds && lds_sum) {
+            // every quadrant has added its sums for this chunk: one global
+            // atomic per nonzero (entry, value), and the accumulator is cleared
+            __syncthreads();
+            for (int i = threadIdx.x; i < kSegment * kG2D; i += kTilePixels) {
+                const float v = s_acc[i];
+                if (v != 0.0f) {
+                    atomicAdd(a.g2d + (size_t)s_gid[i / kG2D] * kG2D + (i % kG2D), v);
+                    s_acc[i] = 0.0f;
+                }
             }
+            __syncthreads();
         }
-        __syncthreads();
     }
+    }  // this wave's walk
     }  // work loop
 }
 
@@ -321,13 +342,18 @@ hipError_t launch_backward_tiles(BackwardTileArgs a, int n_cu, hipStream_t s) {
     if (a.seg_list && a.n_items >= (int64_t)1 << 26) a.seg_list = nullptr;  // item ids need 26 bits
     if (!a.seg_list) {  // one workgroup per list
         a.n_groups = (uint32_t)a.n_items;
-        return launch_kernel(backward_tile_kernel<false>, dim3((unsigned)a.n_items), dim3(kTilePixels), s, a);
+        // many lists (more than the GPU holds at once): fewer global atomics
+        // pay for the waves of a tile walking in step; few long lists: not
+        if (a.n_items >= 2048)
+            return launch_kernel(backward_tile_kernel<false, true>, dim3((unsigned)a.n_items), dim3(kTilePixels), s,
+                                 a);
+        return launch_kernel(backward_tile_kernel<false, false>, dim3((unsigned)a.n_items), dim3(kTilePixels), s, a);
     }
     hipError_t e = launch_kernel(segment_list_kernel, dim3(1), dim3(1024), s, a.ranges, a.n_items, a.seg_list,
                                  (uint64_t)(a.ckpt_slots * kListPerSlot));
     if (e != hipSuccess) return e;
     a.n_groups = (uint32_t)(6 * n_cu);  // persistent: about what the CUs hold at once
-    return launch_kernel(backward_tile_kernel<true>, dim3(a.n_groups), dim3(kTilePixels), s, a);
+    return launch_kernel(backward_tile_kernel<true, true>, dim3(a.n_groups), dim3(kTilePixels), s, a);
 }
 
 // ---------------------------------------------------------------------------
