@@ -68,8 +68,9 @@ def _load():
     lib.or_bin.restype = i64
     lib.or_composite.argtypes = [i32, P, P, P, P, P, P, P]
     lib.or_render_view.argtypes = [i64, P, P, P, P, P, P, P]
-    lib.or_backward_2d.argtypes = [i64, P, P, P, P, P, P, P]
+    lib.or_backward_2d.argtypes = [i64, P, P, P, P, P, P, P, P, i64, P, P, P]
     lib.or_backward_3d.argtypes = [i64, i32, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P]
+    lib.or_fd_loss.argtypes = [i64, i32, P, P, P, P, P, P, P, P, P, P, P, P, P, i64, P, P, P, P, P]
     lib.or_lbs.argtypes = [i64, P, P, P, P, P, P, i32, P, P]
     lib.or_lbs_backward.argtypes = [i64, P, P, P, P, P, P, i32, P, P, P, P, P]
     lib.or_version.restype = i32
@@ -88,14 +89,21 @@ def _f32(a):
 
 
 def params(width, height, near=0.2, lowpass=0.3, sigma_cut=3.0, fov_clamp=1.3, bg=(0.0, 0.0, 0.0), tile=16,
-           d_skip=1e-4, d_stop=1e-4, d_near=1e-5, d_int=1e-5, d_tie=1e-6, max_flips=3):
+           d_skip=1e-4, d_stop=1e-4, d_near=1e-5, d_int=1e-5, d_tie=1e-6, max_flips=3, img_tol=1e-4):
     """Rendering constants plus the oracle's decision margins (all double).
 
     The constants near/lowpass/sigma_cut/fov_clamp are FP32 values on the GPU
-    side; they are promoted from FP32 here too so both sides use one value."""
+    side; they are promoted from FP32 here too so both sides use one value.
+    d_skip / d_stop: relative windows around the alpha and transmittance
+    thresholds inside which an FP32 implementation may take the other branch
+    (its projected means and conics carry FP32 error that moves the exponent
+    by ~1e-5..1e-4 relative, see the design notes); d_near / d_int: windows of
+    the near-plane test and of the integer radius / floor; d_tie: relative
+    depth gap under which two entries' order may swap; img_tol: the image
+    tolerance a branch must meet to be taken as an implementation's."""
     f = lambda x: float(np.float32(x))
     return np.array([width, height, f(near), f(lowpass), f(sigma_cut), f(fov_clamp), ALPHA_MAX, ALPHA_MIN, T_MIN,
-                     f(bg[0]), f(bg[1]), f(bg[2]), tile, d_skip, d_stop, d_near, d_int, d_tie, max_flips],
+                     f(bg[0]), f(bg[1]), f(bg[2]), tile, d_skip, d_stop, d_near, d_int, d_tie, max_flips, img_tol],
                     dtype=np.float64)
 
 
@@ -246,28 +254,40 @@ def render(g, cam, prm, want_cands=True):
     return (proj,) + render_view(proj, prm, want_cands)
 
 
-def backward(g, cams, prm, d_rgb, d_depth, d_alpha):
+def _flat_gaussians(g):
+    n = len(g["means"])
+    use = g.get("use_cov6")
+    return (n, int(g["sh_degree"]), _f32(g["means"]), _f32(g.get("log_scales")), _f32(g.get("quats")),
+            _f32(g.get("cov6")), None if use is None else np.ascontiguousarray(use, dtype=np.uint8),
+            _f32(g["opacity"]), _f32(g["sh"]))
+
+
+def backward(g, cams, prm, d_rgb, d_depth, d_alpha, decisions=None):
     """O12 adjoint summed over the views in `cams` (all of the same gaussian set).
 
     d_rgb [V,H,W,3], d_depth [V,H,W], d_alpha [V,H,W].  Returns a dict of
     double gradients with the input layouts (means, log_scales, quats, opacity,
-    sh, cov6 when present) plus "ambiguous" [n] (uint8): Gaussians whose
-    gradient depends on a near-threshold decision (see or_backward_2d)."""
+    sh, cov6 when present).
+
+    decisions (optional): an implementation's discrete decisions per view, a
+    list of dicts with "vals" and "ranges" (its per-tile lists for that view:
+    ranges [T, 2] into vals), "base" (the instance id of the view's first
+    Gaussian), "n_contrib" [H,W] and "img" [H,W,5] (r, g, b, depth, alpha).
+    The adjoint then differentiates the branch that implementation took (see
+    or_backward_2d) and the result also holds "pixel_status" [V,H,W]:
+    0 same decisions as FP64, 1 decisions differing only inside their
+    windows with the image reproduced, 2 otherwise."""
     lib = _load()
     if isinstance(g, (list, tuple)):
         g = concat_segments(g)
-    n = len(g["means"])
-    D = int(g["sh_degree"])
+    n, D, means, lsc, quats, cov6, use, opac, sh = _flat_gaussians(g)
     K = (D + 1) ** 2
-    means, lsc, quats = _f32(g["means"]), _f32(g.get("log_scales")), _f32(g.get("quats"))
-    cov6 = _f32(g.get("cov6"))
-    use = g.get("use_cov6")
-    use = None if use is None else np.ascontiguousarray(use, dtype=np.uint8)
-    opac, sh = _f32(g["opacity"]), _f32(g["sh"])
     out = {"means": np.zeros((n, 3)), "log_scales": np.zeros((n, 3)), "quats": np.zeros((n, 4)),
-           "opacity": np.zeros(n), "sh": np.zeros((n, K, 3)), "cov6": np.zeros((n, 6)),
-           "ambiguous": np.zeros(n, np.uint8)}
+           "opacity": np.zeros(n), "sh": np.zeros((n, K, 3)), "cov6": np.zeros((n, 6))}
     cams = np.asarray(cams, dtype=np.float32).reshape(-1, 16)
+    W, H = int(prm[0]), int(prm[1])
+    if decisions is not None:
+        out["pixel_status"] = np.zeros((len(cams), H, W), np.uint8)
     for v in range(len(cams)):
         cam = cam_array(cams[v])
         proj = np.zeros((n, PROJ_STRIDE))
@@ -277,9 +297,20 @@ def backward(g, cams, prm, d_rgb, d_depth, d_alpha):
         dr = _f32(d_rgb[v])
         dd = _f32(d_depth[v])
         da = _f32(d_alpha[v])
-        amb = np.zeros(n, np.uint8)
-        lib.or_backward_2d(n, _p(proj), _p(prm), _p(dr), _p(dd), _p(da), _p(g2d), _p(amb))
-        out["ambiguous"] |= amb
+        if decisions is None:
+            lib.or_backward_2d(n, _p(proj), _p(prm), _p(dr), _p(dd), _p(da), _p(g2d), None, None, 0, None, None, None)
+        else:
+            dv = decisions[v]
+            vals = np.ascontiguousarray(dv["vals"], dtype=np.uint32)
+            ranges = np.ascontiguousarray(dv["ranges"], dtype=np.uint32).reshape(-1, 2)
+            assert len(ranges) == ((W + 15) // 16) * ((H + 15) // 16)
+            nc = np.ascontiguousarray(dv["n_contrib"], dtype=np.int32).reshape(H, W)
+            img = _f32(dv["img"]).reshape(H, W, 5)
+            st = np.zeros((H, W), np.uint8)
+            lib.or_backward_2d(n, _p(proj), _p(prm), _p(dr), _p(dd), _p(da), _p(g2d),
+                               _p(vals if len(vals) else np.zeros(1, np.uint32)), _p(ranges), int(dv["base"]),
+                               _p(nc), _p(img), _p(st))
+            out["pixel_status"][v] = st
         lib.or_backward_3d(n, D, _p(means), _p(lsc), _p(quats), _p(cov6), _p(use), _p(opac), _p(sh), _p(cam), _p(prm),
                            _p(g2d), _p(out["means"]), _p(out["log_scales"]), _p(out["quats"]), _p(out["opacity"]),
                            _p(out["sh"]), _p(out["cov6"]))
@@ -292,8 +323,48 @@ def backward_2d(proj, prm, d_rgb, d_depth, d_alpha):
     n = len(proj)
     g2d = np.zeros((n, 10))
     lib.or_backward_2d(n, _p(np.ascontiguousarray(proj)), _p(prm), _p(_f32(d_rgb)), _p(_f32(d_depth)),
-                       _p(_f32(d_alpha)), _p(g2d), None)
+                       _p(_f32(d_alpha)), _p(g2d), None, None, 0, None, None, None)
     return g2d
+
+
+def param_index(field, comp, sh_degree):
+    """Index of one parameter in the flat per-Gaussian vector of fd_loss:
+    means 0..2, log_scales 3..5, quats 6..9, opacity 10, sh 11.. (coefficient
+    k, channel c at 11 + 3 k + c), cov6 after the SH."""
+    K = (sh_degree + 1) ** 2
+    base = {"means": 0, "log_scales": 3, "quats": 6, "opacity": 10, "sh": 11, "cov6": 11 + 3 * K}[field]
+    return base + int(comp)
+
+
+def fd_loss(g, cam, prm, samples, h, lin=None, quad=None, tgt=None):
+    """Central finite differences (double precision) of the image loss
+    L = sum_pix sum_k lin[..., k] y_k + quad[k] (y_k - tgt[..., k])^2 over
+    y = (r, g, b, depth, alpha) of the oracle's render of one view, w.r.t.
+    the parameters `samples` = [(gaussian, param_index), ...] with steps h.
+    Only the tiles the perturbed Gaussian covers are re-rendered.  Returns
+    (fd [S], flag [S]); flag 1 marks a sample whose discrete decisions change
+    within +-h (no derivative there)."""
+    lib = _load()
+    if isinstance(g, (list, tuple)):
+        g = concat_segments(g)
+    n, D, means, lsc, quats, cov6, use, opac, sh = _flat_gaussians(g)
+    W, H = int(prm[0]), int(prm[1])
+    camd = cam_array(cam)
+    proj = np.zeros((n, PROJ_STRIDE))
+    lib.or_project(n, D, _p(means), _p(lsc), _p(quats), _p(cov6), _p(use), _p(opac), _p(sh), _p(camd), _p(prm),
+                   _p(proj))
+    lin = np.zeros((H, W, 5)) if lin is None else np.ascontiguousarray(lin, dtype=np.float64).reshape(H, W, 5)
+    quad = np.zeros(5) if quad is None else np.ascontiguousarray(quad, dtype=np.float64).reshape(5)
+    tgt = np.zeros((H, W, 5)) if tgt is None else np.ascontiguousarray(tgt, dtype=np.float64).reshape(H, W, 5)
+    samples = np.asarray(samples, dtype=np.int64).reshape(-1, 2)
+    gi = np.ascontiguousarray(samples[:, 0])
+    pi = np.ascontiguousarray(samples[:, 1].astype(np.int32))
+    hh = np.ascontiguousarray(np.broadcast_to(np.asarray(h, np.float64), (len(samples),)))
+    fd = np.zeros(len(samples))
+    flag = np.zeros(len(samples), np.int32)
+    lib.or_fd_loss(n, D, _p(means), _p(lsc), _p(quats), _p(cov6), _p(use), _p(opac), _p(sh), _p(camd), _p(prm),
+                   _p(proj), _p(lin), _p(quad), _p(tgt), len(samples), _p(gi), _p(pi), _p(hh), _p(fd), _p(flag))
+    return fd, flag
 
 
 def dense_weights(joint_idx, weights, n_joints):

@@ -60,11 +60,12 @@ typedef struct {
     double d_near, d_int;  /* margins of the near-plane test and integer decisions */
     double d_tie;          /* relative depth margin for order ties */
     int max_flips;
+    double img_tol;        /* image tolerance a branch must meet to be taken as an implementation's */
 } oprm;
 
 /* prm layout: 0 W, 1 H, 2 near, 3 lowpass, 4 sigma_cut, 5 fov_clamp,
  * 6 alpha_max, 7 alpha_min, 8 t_min, 9..11 bg, 12 tile, 13 d_skip, 14 d_stop,
- * 15 d_near, 16 d_int, 17 d_tie, 18 max_flips */
+ * 15 d_near, 16 d_int, 17 d_tie, 18 max_flips, 19 img_tol */
 static oprm unpack_prm(const double *p)
 {
     oprm o;
@@ -87,6 +88,7 @@ static oprm unpack_prm(const double *p)
     o.d_int = p[16];
     o.d_tie = p[17];
     o.max_flips = (int)p[18];
+    o.img_tol = p[19];
     return o;
 }
 
@@ -307,15 +309,41 @@ static int64_t radius_of(double x)
     return (int64_t)c;
 }
 
-static void project_one(const oprm *p, const ocam *cam, int D, const float *mean, const float *lsc,
-                        const float *quat, const float *cov6, float opac, const float *sh, oproj *o)
+/* One Gaussian's parameters in double precision (FP32 inputs are promoted
+ * exactly; the finite-difference checks perturb them below FP32 resolution). */
+typedef struct {
+    int D, use_cov6;
+    double mean[3], lsc[3], q[4], cov6[6], opac;
+    double sh[3 * OR_MAXK];
+} oin;
+
+static void load_in(int D, const float *mean, const float *lsc, const float *quat, const float *cov6, float opac,
+                    const float *sh, oin *g)
 {
+    memset(g, 0, sizeof(*g));
+    g->D = D;
+    for (int k = 0; k < 3; ++k) g->mean[k] = mean[k];
+    if (cov6) {
+        g->use_cov6 = 1;
+        for (int k = 0; k < 6; ++k) g->cov6[k] = cov6[k];
+    } else {
+        for (int k = 0; k < 3; ++k) g->lsc[k] = lsc[k];
+        for (int k = 0; k < 4; ++k) g->q[k] = quat[k];
+    }
+    g->opac = opac;
+    for (int k = 0; k < 3 * (D + 1) * (D + 1); ++k) g->sh[k] = sh[k];
+}
+
+static void project_one(const oprm *p, const ocam *cam, const oin *g, oproj *o)
+{
+    const int D = g->D;
     memset(o, 0, sizeof(*o));
-    o->opacity = (double)opac;
-    const double mu[3] = {mean[0], mean[1], mean[2]};
+    o->opacity = g->opac;
+    const double mu[3] = {g->mean[0], g->mean[1], g->mean[2]};
     if (!isfinite(o->opacity)) return; /* non-finite input is culled (vis = 0) */
     /* O1/O2: covariance */
-    if (cov6) {
+    if (g->use_cov6) {
+        const double *cov6 = g->cov6;
         o->use_cov6 = 1;
         o->Sig[0] = cov6[0];
         o->Sig[1] = o->Sig[3] = cov6[1];
@@ -324,7 +352,7 @@ static void project_one(const oprm *p, const ocam *cam, int D, const float *mean
         o->Sig[5] = o->Sig[7] = cov6[4];
         o->Sig[8] = cov6[5];
     } else {
-        double q[4] = {quat[0], quat[1], quat[2], quat[3]};
+        double q[4] = {g->q[0], g->q[1], g->q[2], g->q[3]};
         double n2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
         if (!(n2 >= 1e-24)) {
             o->qn = 0.0;
@@ -335,7 +363,7 @@ static void project_one(const oprm *p, const ocam *cam, int D, const float *mean
             for (int i = 0; i < 4; ++i) o->q[i] = q[i] / o->qn;
         }
         quat_to_rot(o->q, o->R);
-        for (int i = 0; i < 3; ++i) o->s[i] = exp((double)lsc[i]);
+        for (int i = 0; i < 3; ++i) o->s[i] = exp(g->lsc[i]);
         double M[9];
         for (int i = 0; i < 3; ++i)
             for (int j = 0; j < 3; ++j) M[3 * i + j] = o->R[3 * i + j] * o->s[j];
@@ -483,7 +511,7 @@ static void project_one(const oprm *p, const ocam *cam, int D, const float *mean
     const int K = (D + 1) * (D + 1);
     for (int ch = 0; ch < 3; ++ch) {
         double s = 0.0;
-        for (int k = 0; k < K; ++k) s += Y[k] * (double)sh[3 * k + ch];
+        for (int k = 0; k < K; ++k) s += Y[k] * g->sh[3 * k + ch];
         o->raw[ch] = s + 0.5;
         o->rgb[ch] = o->raw[ch] > 0.0 ? o->raw[ch] : 0.0;
     }
@@ -501,7 +529,9 @@ void or_cov3d(int64_t n, const float *lsc, const float *quats, double *cov6)
         memset(&c, 0, sizeof(c));
         const float zero3[3] = {0, 0, 0}, sh0[3] = {0, 0, 0};
         p.near_plane = 1e300; /* cull right after the covariance step */
-        project_one(&p, &c, 0, zero3, lsc + 3 * i, quats + 4 * i, NULL, 0.5f, sh0, &o);
+        oin g;
+        load_in(0, zero3, lsc + 3 * i, quats + 4 * i, NULL, 0.5f, sh0, &g);
+        project_one(&p, &c, &g, &o);
         cov6[6 * i + 0] = o.Sig[0];
         cov6[6 * i + 1] = o.Sig[1];
         cov6[6 * i + 2] = o.Sig[2];
@@ -528,8 +558,10 @@ void or_project(int64_t n, int D, const float *means, const float *lsc, const fl
     for (int64_t i = 0; i < n; ++i) {
         oproj o;
         const float *c6 = (cov6 && (!use_cov6 || use_cov6[i])) ? cov6 + 6 * i : NULL;
-        project_one(&p, &cam, D, means + 3 * i, lsc ? lsc + 3 * i : NULL, quats ? quats + 4 * i : NULL, c6,
-                    opacity[i], sh + (size_t)3 * K * i, &o);
+        oin g;
+        load_in(D, means + 3 * i, lsc ? lsc + 3 * i : NULL, quats ? quats + 4 * i : NULL, c6, opacity[i],
+                sh + (size_t)3 * K * i, &g);
+        project_one(&p, &cam, &g, &o);
         double *r = out + OR_PROJ_STRIDE * i;
         memset(r, 0, sizeof(double) * OR_PROJ_STRIDE);
         r[0] = o.vis;
@@ -1060,115 +1092,263 @@ static void atomic_add(double *p, double v)
     *p += v;
 }
 
-/* Backward of one view from the oracle's own forward (primary decisions held
- * fixed).  g2d: [n][10] accumulated (u, v, A, B, C, opacity, r, g, b, z).
- * amb_g (nullable, [n]): set to 1 for every Gaussian that reaches the skip
- * threshold at a pixel whose compositing holds a decision inside its margin,
- * a depth near-tie or a rect ambiguity -- its gradient depends on which side
- * an FP32 implementation takes. */
+/* The per-pixel adjoint of O12 along one fixed branch: the composited
+ * entries cj[0..nc) (positions in the list `ent`, front to back) with their
+ * alpha, transmittance before them, Gaussian value and pixel offset; T_end
+ * is the final transmittance.  Accumulates into g2d. */
+typedef struct {
+    int j, clamped;
+    double a, T, G, dx, dy;
+} ocomp;
+
+static void adjoint_pixel(const oprm *p, const double *proj, const int64_t *ent, const ocomp *cc, int nc,
+                          double T_end, const double dC[3], double dD, double dA, double *g2d)
+{
+    double S[3] = {p->bg[0], p->bg[1], p->bg[2]}, SD = 0.0;
+    for (int k = nc - 1; k >= 0; --k) {
+        const int64_t gi = ent[cc[k].j];
+        const double *r = proj + OR_PROJ_STRIDE * gi;
+        const double a = cc[k].a, Ti = cc[k].T;
+        double dalpha = 0.0;
+        for (int ch = 0; ch < 3; ++ch) dalpha += dC[ch] * (r[8 + ch] - S[ch]);
+        dalpha += dD * (r[3] - SD);
+        dalpha *= Ti;
+        dalpha += dA * T_end / (1.0 - a);
+        double *g = g2d + G_N * gi;
+        for (int ch = 0; ch < 3; ++ch) atomic_add(&g[G_R + ch], dC[ch] * a * Ti);
+        atomic_add(&g[G_Z], dD * a * Ti);
+        if (!cc[k].clamped) {
+            const double dG = dalpha * r[7];
+            atomic_add(&g[G_O], dalpha * cc[k].G);
+            const double dP = dG * cc[k].G;
+            const double dx = cc[k].dx, dy = cc[k].dy;
+            atomic_add(&g[G_U], dP * (r[4] * dx + r[5] * dy));
+            atomic_add(&g[G_V], dP * (r[5] * dx + r[6] * dy));
+            atomic_add(&g[G_A], dP * (-0.5 * dx * dx));
+            atomic_add(&g[G_B], dP * (-dx * dy));
+            atomic_add(&g[G_C], dP * (-0.5 * dy * dy));
+        }
+        for (int ch = 0; ch < 3; ++ch) S[ch] = a * r[8 + ch] + (1.0 - a) * S[ch];
+        SD = a * r[3] + (1.0 - a) * SD;
+    }
+}
+
+/* alpha of list entry gi at pixel centre (cx, cy) from the FP64 projection
+ * (0 for a Gaussian the FP64 projection culls) */
+static void pixel_alpha(const oprm *p, const double *proj, int64_t gi, double cx, double cy, ocomp *e)
+{
+    const double *r = proj + OR_PROJ_STRIDE * gi;
+    e->a = e->G = e->dx = e->dy = 0.0;
+    e->clamped = 0;
+    if (r[0] == 0.0) return;
+    e->dx = cx - r[1];
+    e->dy = cy - r[2];
+    double P = -0.5 * (r[4] * e->dx * e->dx + r[6] * e->dy * e->dy) - r[5] * e->dx * e->dy;
+    if (P > 0.0) P = 0.0;
+    e->G = exp(P);
+    e->a = r[7] * e->G;
+    if (e->a > p->alpha_max) {
+        e->a = p->alpha_max;
+        e->clamped = 1;
+    }
+}
+
+#define OR_MAX_ENUM 4 /* skip decisions enumerated per pixel in the implementation's-branch mode */
+
+/* Implementation's-branch mode, one pixel: entries ent[0..len) in the
+ * implementation's list order, nc its n_contrib, img its (r, g, b, depth,
+ * alpha).  Picks the skip decisions (see or_backward_2d), writes the
+ * composited entries into cc and returns their count; *T_end the final
+ * transmittance; *stat the pixel status. */
+static int branch_from_image(const oprm *p, const double *proj, const int64_t *ent, int len, int nc, double cx,
+                             double cy, const float *img, ocomp *all, ocomp *cc, double *T_end, int *stat)
+{
+    const double amin = p->alpha_min, tmin = p->t_min;
+    int st = 0;
+    if (nc > len) {
+        st = 2;
+        nc = len;
+    }
+    /* FP64 alphas of the entries up to the implementation's last composited one */
+    int amb[OR_MAX_ENUM], namb = 0;
+    for (int j = 0; j < nc; ++j) {
+        pixel_alpha(p, proj, ent[j], cx, cy, &all[j]);
+        all[j].j = j;
+    }
+    /* skip decisions inside the window, nearest the threshold first */
+    for (int j = 0; j + 1 < nc; ++j) {
+        const double m = fabs(all[j].a - amin) / amin;
+        if (m > p->d_skip) continue;
+        if (namb < OR_MAX_ENUM) {
+            amb[namb++] = j;
+        } else {
+            int far = 0;
+            for (int k = 1; k < namb; ++k)
+                if (fabs(all[amb[k]].a - amin) > fabs(all[amb[far]].a - amin)) far = k;
+            if (m < fabs(all[amb[far]].a - amin) / amin) amb[far] = j;
+        }
+    }
+    if (nc > 0 && all[nc - 1].a < amin) /* the implementation composited it: its FP64 alpha must be in the window */
+        if (fabs(all[nc - 1].a - amin) > p->d_skip * amin) st = 2;
+    /* every combination of the ambiguous decisions; the FP64 one first */
+    double best = INFINITY;
+    int best_combo = 0;
+    const int ncombo = 1 << namb;
+    int primary = 0;
+    for (int k = 0; k < namb; ++k)
+        if (!(all[amb[k]].a < amin)) primary |= 1 << k;
+    for (int t = 0; t < ncombo; ++t) {
+        const int combo = t == 0 ? primary : (t == primary ? 0 : t);
+        double T = 1.0, C[3] = {0, 0, 0}, D = 0.0;
+        for (int j = 0; j < nc; ++j) {
+            int take = !(all[j].a < amin) || j == nc - 1;
+            for (int k = 0; k < namb; ++k)
+                if (amb[k] == j) take = (combo >> k) & 1;
+            if (!take) continue;
+            const double *r = proj + OR_PROJ_STRIDE * ent[j];
+            for (int ch = 0; ch < 3; ++ch) C[ch] += r[8 + ch] * all[j].a * T;
+            D += r[3] * all[j].a * T;
+            T *= 1.0 - all[j].a;
+        }
+        double d = 0.0;
+        for (int ch = 0; ch < 3; ++ch) d = fmax(d, fabs(C[ch] + T * p->bg[ch] - img[ch]) / p->img_tol);
+        d = fmax(d, fabs(D - img[3]) / (p->img_tol * fmax(1.0, fabs(D))));
+        d = fmax(d, fabs(1.0 - T - img[4]) / p->img_tol);
+        if (d < best) {
+            best = d;
+            best_combo = combo;
+        }
+    }
+    if (best > 1.0) st = 2;
+    if (best_combo != primary && st == 0) st = 1;
+    if (nc > 0 && all[nc - 1].a < amin && st == 0) st = 1;
+    /* the chosen branch, with its stop decisions checked against the FP64 values */
+    double T = 1.0;
+    int n = 0;
+    for (int j = 0; j < nc; ++j) {
+        int take = !(all[j].a < amin) || j == nc - 1;
+        for (int k = 0; k < namb; ++k)
+            if (amb[k] == j) take = (best_combo >> k) & 1;
+        if (!take) continue;
+        all[j].T = T;
+        cc[n++] = all[j];
+        const double Tn = T * (1.0 - all[j].a);
+        if (Tn < tmin) { /* the FP64 path stops here, the implementation composited it */
+            if (fabs(Tn - tmin) > p->d_stop * tmin) st = 2;
+            else if (st == 0) st = 1;
+        }
+        T = Tn;
+    }
+    /* after the last composited entry the implementation stops, or its list ends: the first entry it may take
+     * (FP64 alpha not clearly below the threshold) must stop it */
+    int resolved = 0;
+    for (int j = nc; j < len && !resolved; ++j) {
+        ocomp e;
+        pixel_alpha(p, proj, ent[j], cx, cy, &e);
+        if (e.a < amin * (1.0 - p->d_skip)) continue; /* skipped on both sides */
+        const double Tn = T * (1.0 - e.a);
+        if (Tn < tmin) {
+            if (e.a < amin && st == 0) st = 1; /* taken (and stopping) only inside the skip window */
+            resolved = 1;
+        } else if (fabs(Tn - tmin) <= p->d_stop * tmin) {
+            if (st == 0) st = 1;
+            resolved = 1;
+        } else if (e.a < amin * (1.0 + p->d_skip)) {
+            if (st == 0) st = 1; /* the implementation skipped it inside the window; go on */
+        } else {
+            st = 2; /* the FP64 path would composite it */
+            resolved = 1;
+        }
+    }
+    *T_end = T;
+    *stat = st;
+    return n;
+}
+
+/* Backward of one view (O12): per-Gaussian screen-space adjoints g2d [n][10]
+ * (u, v, A, B, C, opacity, r, g, b, z), accumulated, with the discrete
+ * decisions (list membership and order, skips, the stop) held fixed.
+ * proj: the oracle's own FP64 projection of the view.
+ *
+ * lvals == NULL: the decisions are the oracle's own FP64 ones on its own
+ * lists.
+ *
+ * Otherwise an implementation's decisions are given and the adjoint
+ * differentiates the branch it took, evaluated at the FP64 values:
+ * membership and order from its per-tile lists (lvals / lranges as produced
+ * by the binning; a value minus val_base indexes proj), the stop from its
+ * n_contrib (the list position after the last composited entry), and each
+ * skip decision from the FP64 alpha, except those within d_skip of the
+ * threshold (relative), which are set to the combination whose forward
+ * result is nearest the implementation's image gimg [H][W][5] (r, g, b,
+ * depth, alpha).  pstat [H][W] (nullable): 0 the given decisions are the
+ * FP64 ones and the image is reproduced within img_tol (depth: img_tol
+ * max(1, |D|)); 1 they differ only in decisions inside their windows (d_skip,
+ * d_stop) and the image is reproduced; 2 otherwise. */
 void or_backward_2d(int64_t n, const double *proj, const double *prm, const float *d_rgb, const float *d_depth,
-                    const float *d_alpha, double *g2d, uint8_t *amb_g)
+                    const float *d_alpha, double *g2d, const uint32_t *lvals, const uint32_t *lranges,
+                    int64_t val_base, const int32_t *ncontrib, const float *gimg, uint8_t *pstat)
 {
     const oprm p = unpack_prm(prm);
     const int TX = (p.W + p.tile - 1) / p.tile, TY = (p.H + p.tile - 1) / p.tile, T = TX * TY;
-    int64_t *lp, *li;
-    build_lists(&p, n, proj, &lp, &li);
-    uint8_t *pflags = calloc((size_t)p.H * p.W, 1);
-    rect_flags(&p, n, proj, pflags);
+    int64_t *lp = NULL, *li = NULL;
+    if (!lvals) build_lists(&p, n, proj, &lp, &li);
 #pragma omp parallel for schedule(dynamic, 1)
     for (int t = 0; t < T; ++t) {
-        const int len = (int)(lp[t + 1] - lp[t]);
         const int tx = t % TX, ty = t / TX;
-        int *cj = malloc(sizeof(int) * (len + 1));
-        double *ca = malloc(sizeof(double) * (len + 1) * 6);
-        double *cT = ca + (len + 1), *cG = cT + (len + 1), *cdx = cG + (len + 1), *cdy = cdx + (len + 1),
-               *ccl = cdy + (len + 1);
-        for (int py = ty * p.tile; py < (ty + 1) * p.tile && py < p.H; ++py)
-            for (int px = tx * p.tile; px < (tx + 1) * p.tile && px < p.W; ++px) {
-                /* forward, recording composited entries; a decision inside its
-                 * margin, a depth near-tie or a rect ambiguity at this pixel
-                 * makes every entry that reaches the skip threshold here
-                 * ambiguous (its gradient depends on the branch taken) */
-                double Tcur = 1.0, zlast = -1.0;
-                int nc = 0, amb = pflags[(size_t)py * p.W + px] != 0, jend = len;
-                for (int j = 0; j < len; ++j) {
-                    const double *r = proj + OR_PROJ_STRIDE * li[lp[t] + j];
-                    const double ddx = px + 0.5 - r[1], ddy = py + 0.5 - r[2];
-                    double P = -0.5 * (r[4] * ddx * ddx + r[6] * ddy * ddy) - r[5] * ddx * ddy;
-                    if (P > 0.0) P = 0.0;
-                    const double g = exp(P);
-                    double a = r[7] * g;
-                    int cl = 0;
-                    if (a > p.alpha_max) {
-                        a = p.alpha_max;
-                        cl = 1;
-                    }
-                    if (fabs(a - p.alpha_min) <= p.d_skip * p.alpha_min) amb = 1;
-                    if (a >= p.alpha_min * (1.0 - p.d_skip)) {
-                        if (zlast > 0.0 && fabs(r[3] - zlast) <= p.d_tie * (r[3] > zlast ? r[3] : zlast)) amb = 1;
-                        zlast = r[3];
-                    }
-                    if (a < p.alpha_min) continue;
-                    const double Tn = Tcur * (1.0 - a);
-                    if (fabs(Tn - p.t_min) <= p.d_stop * p.t_min) amb = 1;
-                    if (Tn < p.t_min) {
-                        jend = j + 1;
-                        break;
-                    }
-                    cj[nc] = j;
-                    ca[nc] = a;
-                    cT[nc] = Tcur;
-                    cG[nc] = g;
-                    cdx[nc] = ddx;
-                    cdy[nc] = ddy;
-                    ccl[nc] = cl;
-                    ++nc;
-                    Tcur = Tn;
-                }
-                if (amb && amb_g) {
-                    for (int j = 0; j < jend; ++j) {
-                        const double *r = proj + OR_PROJ_STRIDE * li[lp[t] + j];
-                        const double ddx = px + 0.5 - r[1], ddy = py + 0.5 - r[2];
-                        double P = -0.5 * (r[4] * ddx * ddx + r[6] * ddy * ddy) - r[5] * ddx * ddy;
-                        if (P > 0.0) P = 0.0;
-                        if (r[7] * exp(P) >= p.alpha_min * (1.0 - p.d_skip)) amb_g[li[lp[t] + j]] = 1;
-                    }
-                }
-                const size_t pix = (size_t)py * p.W + px;
-                const double dC[3] = {d_rgb[3 * pix], d_rgb[3 * pix + 1], d_rgb[3 * pix + 2]};
-                const double dD = d_depth[pix], dA = d_alpha[pix];
-                double S[3] = {p.bg[0], p.bg[1], p.bg[2]}, SD = 0.0;
-                for (int k = nc - 1; k >= 0; --k) {
-                    const int64_t gi = li[lp[t] + cj[k]];
-                    const double *r = proj + OR_PROJ_STRIDE * gi;
-                    const double a = ca[k], Ti = cT[k];
-                    double dalpha = 0.0;
-                    for (int ch = 0; ch < 3; ++ch) dalpha += dC[ch] * (r[8 + ch] - S[ch]);
-                    dalpha += dD * (r[3] - SD);
-                    dalpha *= Ti;
-                    dalpha += dA * Tcur / (1.0 - a);
-                    double *g = g2d + G_N * gi;
-                    for (int ch = 0; ch < 3; ++ch) atomic_add(&g[G_R + ch], dC[ch] * a * Ti);
-                    atomic_add(&g[G_Z], dD * a * Ti);
-                    if (!ccl[k]) {
-                        const double dG = dalpha * r[7];
-                        atomic_add(&g[G_O], dalpha * cG[k]);
-                        const double dP = dG * cG[k];
-                        const double dx = cdx[k], dy = cdy[k];
-                        atomic_add(&g[G_U], dP * (r[4] * dx + r[5] * dy));
-                        atomic_add(&g[G_V], dP * (r[5] * dx + r[6] * dy));
-                        atomic_add(&g[G_A], dP * (-0.5 * dx * dx));
-                        atomic_add(&g[G_B], dP * (-dx * dy));
-                        atomic_add(&g[G_C], dP * (-0.5 * dy * dy));
-                    }
-                    for (int ch = 0; ch < 3; ++ch) S[ch] = a * r[8 + ch] + (1.0 - a) * S[ch];
-                    SD = a * r[3] + (1.0 - a) * SD;
+        int len;
+        int64_t *ent;
+        int bad_val = 0;
+        if (lvals) {
+            const uint32_t b = lranges[2 * t], e = lranges[2 * t + 1];
+            len = e > b ? (int)(e - b) : 0;
+            ent = malloc(sizeof(int64_t) * (len + 1));
+            for (int j = 0; j < len; ++j) {
+                ent[j] = (int64_t)lvals[b + j] - val_base;
+                if (ent[j] < 0 || ent[j] >= n) {
+                    bad_val = 1;
+                    ent[j] = 0;
                 }
             }
-        free(cj);
-        free(ca);
+        } else {
+            len = (int)(lp[t + 1] - lp[t]);
+            ent = malloc(sizeof(int64_t) * (len + 1));
+            for (int j = 0; j < len; ++j) ent[j] = li[lp[t] + j];
+        }
+        ocomp *all = malloc(sizeof(ocomp) * (len + 1));
+        ocomp *cc = malloc(sizeof(ocomp) * (len + 1));
+        for (int py = ty * p.tile; py < (ty + 1) * p.tile && py < p.H; ++py)
+            for (int px = tx * p.tile; px < (tx + 1) * p.tile && px < p.W; ++px) {
+                const size_t pix = (size_t)py * p.W + px;
+                const double cx = px + 0.5, cy = py + 0.5;
+                int nc = 0, st = 0;
+                double Tcur = 1.0;
+                if (lvals) {
+                    nc = branch_from_image(&p, proj, ent, len, ncontrib[pix] < 0 ? 0 : ncontrib[pix], cx, cy,
+                                           gimg + 5 * pix, all, cc, &Tcur, &st);
+                    if (bad_val) st = 2;
+                } else {
+                    /* O11 on the oracle's own list with its FP64 decisions */
+                    for (int j = 0; j < len; ++j) {
+                        ocomp e;
+                        pixel_alpha(&p, proj, ent[j], cx, cy, &e);
+                        e.j = j;
+                        if (e.a < p.alpha_min) continue;
+                        const double Tn = Tcur * (1.0 - e.a);
+                        if (Tn < p.t_min) break;
+                        e.T = Tcur;
+                        cc[nc++] = e;
+                        Tcur = Tn;
+                    }
+                }
+                if (pstat) pstat[pix] = (uint8_t)st;
+                const double dC[3] = {d_rgb[3 * pix], d_rgb[3 * pix + 1], d_rgb[3 * pix + 2]};
+                adjoint_pixel(&p, proj, ent, cc, nc, Tcur, dC, d_depth[pix], d_alpha[pix], g2d);
+            }
+        free(ent);
+        free(all);
+        free(cc);
     }
-    free(pflags);
     free(lp);
     free(li);
 }
@@ -1192,8 +1372,10 @@ void or_backward_3d(int64_t n, int D, const float *means, const float *lsc, cons
         if (!nz) continue;
         oproj o;
         const int c6 = cov6 && (!use_cov6 || use_cov6[i]);
-        project_one(&p, &cam, D, means + 3 * i, lsc ? lsc + 3 * i : NULL, quats ? quats + 4 * i : NULL,
-                    c6 ? cov6 + 6 * i : NULL, opacity[i], sh + (size_t)3 * K * i, &o);
+        oin gi;
+        load_in(D, means + 3 * i, lsc ? lsc + 3 * i : NULL, quats ? quats + 4 * i : NULL, c6 ? cov6 + 6 * i : NULL,
+                opacity[i], sh + (size_t)3 * K * i, &gi);
+        project_one(&p, &cam, &gi, &o);
         if (!o.vis) continue;
         const double *W = cam.R;
         double dmu[3] = {0, 0, 0};
@@ -1287,6 +1469,178 @@ void or_backward_3d(int64_t n, int D, const float *means, const float *lsc, cons
             }
         }
     }
+}
+
+/* ------------------------------------------------------------------------ */
+/* central finite differences of an image loss (pins of the adjoint)          */
+/* ------------------------------------------------------------------------ */
+/* Per-pixel loss l = sum_k lin[k] y_k + quad[k] (y_k - tgt[k])^2 over
+ * y = (r, g, b, depth, alpha); the loss is summed over the view's pixels. */
+typedef struct {
+    double T, C[3], D;
+    uint64_t sig; /* hash of the composited Gaussians in order */
+    int stopped;
+} opix;
+
+static void pix_entry(const oprm *p, double cx, double cy, int64_t gi, double u, double v, double A, double B,
+                      double Cc, double o, double z, const double *rgb, opix *s)
+{
+    if (s->stopped) return;
+    const double dx = cx - u, dy = cy - v;
+    double P = -0.5 * (A * dx * dx + Cc * dy * dy) - B * dx * dy;
+    if (P > 0.0) P = 0.0;
+    double a = o * exp(P);
+    if (a > p->alpha_max) a = p->alpha_max;
+    if (a < p->alpha_min) return;
+    const double Tn = s->T * (1.0 - a);
+    if (Tn < p->t_min) {
+        s->stopped = 1;
+        return;
+    }
+    for (int ch = 0; ch < 3; ++ch) s->C[ch] += rgb[ch] * a * s->T;
+    s->D += z * a * s->T;
+    s->T = Tn;
+    s->sig = s->sig * 1000003u + (uint64_t)gi + 1u;
+}
+
+static void pix_entry_proj(const oprm *p, const double *proj, int64_t gi, double cx, double cy, opix *s)
+{
+    const double *r = proj + OR_PROJ_STRIDE * gi;
+    pix_entry(p, cx, cy, gi, r[1], r[2], r[4], r[5], r[6], r[7], r[3], r + 8, s);
+}
+
+/* param index k of the flat per-Gaussian vector: 0..2 mean, 3..5 log-scale,
+ * 6..9 quaternion, 10 opacity, 11..11+3K-1 SH (k, channel), then 6 cov6 */
+static double *param_ptr(oin *g, int k)
+{
+    const int K = (g->D + 1) * (g->D + 1);
+    if (k < 3) return &g->mean[k];
+    if (k < 6) return &g->lsc[k - 3];
+    if (k < 10) return &g->q[k - 6];
+    if (k == 10) return &g->opac;
+    if (k < 11 + 3 * K) return &g->sh[k - 11];
+    if (k < 17 + 3 * K) return &g->cov6[k - 11 - 3 * K];
+    return NULL;
+}
+
+/* FD gradient of the loss w.r.t. parameter param[s] of Gaussian gauss[s],
+ * step h[s] (double, central).  The view is re-rendered only where Gaussian
+ * gauss[s] can change it (the tiles of its rects at theta and theta +- h),
+ * with the other Gaussians' FP64 projection and the oracle's lists at theta.
+ * flag[s] = 1 when a discrete decision (composited set, list order or
+ * membership) differs between theta - h, theta and theta + h: the sample is
+ * then not a derivative and fd[s] is left 0. */
+void or_fd_loss(int64_t n, int D, const float *means, const float *lsc, const float *quats, const float *cov6,
+                const uint8_t *use_cov6, const float *opacity, const float *sh, const double *camp, const double *prm,
+                const double *proj, const double *lin, const double *quad, const double *tgt, int64_t n_samples,
+                const int64_t *gauss, const int32_t *param, const double *h, double *fd, int32_t *flag)
+{
+    const oprm p = unpack_prm(prm);
+    const ocam cam = unpack_cam(camp);
+    const int K = (D + 1) * (D + 1);
+    const int TX = (p.W + p.tile - 1) / p.tile, TY = (p.H + p.tile - 1) / p.tile;
+    int64_t *lp, *li;
+    build_lists(&p, n, proj, &lp, &li);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t s = 0; s < n_samples; ++s) {
+        const int64_t i = gauss[s];
+        fd[s] = 0.0;
+        flag[s] = 0;
+        const int c6 = cov6 && (!use_cov6 || use_cov6[i]);
+        oin g0;
+        load_in(D, means + 3 * i, lsc ? lsc + 3 * i : NULL, quats ? quats + 4 * i : NULL, c6 ? cov6 + 6 * i : NULL,
+                opacity[i], sh + (size_t)3 * K * i, &g0);
+        oin gv[3] = {g0, g0, g0}; /* theta - h, theta, theta + h */
+        double *pm = param_ptr(&gv[0], param[s]), *pp = param_ptr(&gv[2], param[s]);
+        if (!pm || !pp) {
+            flag[s] = 2;
+            continue;
+        }
+        *pm -= h[s];
+        *pp += h[s];
+        oproj o[3];
+        for (int k = 0; k < 3; ++k) project_one(&p, &cam, &gv[k], &o[k]);
+        /* tiles any variant covers */
+        int x0 = TX, x1 = 0, y0 = TY, y1 = 0;
+        for (int k = 0; k < 3; ++k) {
+            if (!o[k].vis) continue;
+            if (o[k].rect[0] < x0) x0 = o[k].rect[0];
+            if (o[k].rect[1] > x1) x1 = o[k].rect[1];
+            if (o[k].rect[2] < y0) y0 = o[k].rect[2];
+            if (o[k].rect[3] > y1) y1 = o[k].rect[3];
+        }
+        double dL = 0.0;
+        for (int ty = y0; ty < y1 && !flag[s]; ++ty)
+            for (int tx = x0; tx < x1 && !flag[s]; ++tx) {
+                const int t = ty * TX + tx;
+                const int64_t b = lp[t], e = lp[t + 1];
+                /* the position of i among the other entries of the list, per variant (sorted by depth, then index) */
+                int64_t pos[3];
+                int mem[3];
+                for (int k = 0; k < 3; ++k) {
+                    mem[k] = o[k].vis && tx >= o[k].rect[0] && tx < o[k].rect[1] && ty >= o[k].rect[2] &&
+                             ty < o[k].rect[3];
+                    int64_t c = 0;
+                    for (int64_t j = b; j < e; ++j) {
+                        const int64_t gj = li[j];
+                        if (gj == i) continue;
+                        const double zj = proj[OR_PROJ_STRIDE * gj + 3];
+                        if (zj < o[k].tc[2] || (zj == o[k].tc[2] && gj < i)) ++c;
+                    }
+                    pos[k] = c;
+                }
+                int64_t pos0 = -1;
+                for (int k = 0; k < 3; ++k) {
+                    if (!mem[k]) continue;
+                    if (pos0 >= 0 && pos[k] != pos0) flag[s] = 1; /* the list order changes */
+                    pos0 = pos[k];
+                }
+                if (flag[s]) break;
+                if (pos0 < 0) continue; /* no variant covers this tile */
+                for (int py = ty * p.tile; py < (ty + 1) * p.tile && py < p.H; ++py)
+                    for (int px = tx * p.tile; px < (tx + 1) * p.tile && px < p.W; ++px) {
+                        const double cx = px + 0.5, cy = py + 0.5;
+                        opix pre = {1.0, {0, 0, 0}, 0.0, 0u, 0};
+                        int64_t j = b, c = 0;
+                        for (; j < e && c < pos0; ++j) {
+                            if (li[j] == i) continue;
+                            pix_entry_proj(&p, proj, li[j], cx, cy, &pre);
+                            ++c;
+                        }
+                        if (pre.stopped) continue;
+                        opix st[3];
+                        for (int k = 0; k < 3; ++k) {
+                            st[k] = pre;
+                            if (mem[k])
+                                pix_entry(&p, cx, cy, i, o[k].u, o[k].v, o[k].conic[0], o[k].conic[1], o[k].conic[2],
+                                          o[k].opacity, o[k].tc[2], o[k].rgb, &st[k]);
+                            for (int64_t jj = j; jj < e && !st[k].stopped; ++jj)
+                                if (li[jj] != i) pix_entry_proj(&p, proj, li[jj], cx, cy, &st[k]);
+                        }
+                        if (st[0].sig != st[1].sig || st[2].sig != st[1].sig) {
+                            flag[s] = 1;
+                            break;
+                        }
+                        const size_t pix = (size_t)py * p.W + px;
+                        double yp[5], ym[5];
+                        for (int ch = 0; ch < 3; ++ch) {
+                            yp[ch] = st[2].C[ch] + st[2].T * p.bg[ch];
+                            ym[ch] = st[0].C[ch] + st[0].T * p.bg[ch];
+                        }
+                        yp[3] = st[2].D;
+                        ym[3] = st[0].D;
+                        yp[4] = 1.0 - st[2].T;
+                        ym[4] = 1.0 - st[0].T;
+                        for (int k = 0; k < 5; ++k) {
+                            const double dy = yp[k] - ym[k];
+                            dL += lin[5 * pix + k] * dy + quad[k] * dy * (yp[k] + ym[k] - 2.0 * tgt[5 * pix + k]);
+                        }
+                    }
+            }
+        if (!flag[s]) fd[s] = dL / (2.0 * h[s]);
+    }
+    free(lp);
+    free(li);
 }
 
 /* ------------------------------------------------------------------------ */

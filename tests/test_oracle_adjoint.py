@@ -88,13 +88,18 @@ def _torch_render(p, cam, W, H, prm):
     fx, fy, cx, cy = (float(x) for x in cam[12:16])
     near, lp, sc, fc, amax, amin, tmin = (float(prm[k]) for k in (2, 3, 4, 5, 6, 7, 8))
     bg = torch.tensor(prm[9:12], dtype=dt)
-    q = p["quats"] / p["quats"].norm(dim=1, keepdim=True)
-    w, x, y, z = q.unbind(1)
-    Rq = torch.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
-                      2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
-                      2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], 1).reshape(-1, 3, 3)
-    M = Rq * torch.exp(p["log_scales"])[:, None, :]
-    Sig = M @ M.transpose(1, 2)
+    if "cov6" in p:  # a covariance given directly: the symmetric matrix of its six entries
+        c = p["cov6"]
+        Sig = torch.stack([c[:, 0], c[:, 1], c[:, 2], c[:, 1], c[:, 3], c[:, 4], c[:, 2], c[:, 4], c[:, 5]],
+                          1).reshape(-1, 3, 3)
+    else:
+        q = p["quats"] / p["quats"].norm(dim=1, keepdim=True)
+        w, x, y, z = q.unbind(1)
+        Rq = torch.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                          2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                          2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], 1).reshape(-1, 3, 3)
+        M = Rq * torch.exp(p["log_scales"])[:, None, :]
+        Sig = M @ M.transpose(1, 2)
     tc = p["means"] @ R.T + t
     tx, ty, tz = tc.unbind(1)
     u = fx * tx / tz + cx
@@ -171,6 +176,116 @@ def test_adjoint_matches_torch_autograd_of_dense_renderer(orc):
         ref = p[k].grad.numpy().reshape(ours[k].shape)
         assert np.abs(ref).max() > 0, k
         assert np.allclose(ours[k], ref, rtol=1e-9, atol=1e-11 * np.abs(ref).max()), k
+
+
+def _scene_clamped(seed, n, D, cov6=False):
+    """The small scene plus two Gaussians whose centres lie beyond the
+    Jacobian's tangent clamp (x/z = 0.6 > 1.3 W / (2 fx) = 0.52, and
+    y/z = -0.55 < -0.473) but whose footprints reach into the 32 x 32 image.
+    With cov6=True every Gaussian is given by its covariance (an asymmetric
+    one: distinct scales, random rotations) instead of scales and rotations."""
+    g, cam = _scene(seed, n, D)
+    R = cam[:9].astype(np.float64).reshape(3, 3)
+    t = cam[9:12].astype(np.float64)
+    z = 3.0
+    tc = np.array([[0.6 * z, 0.05 * z, z], [-0.1 * z, -0.55 * z, z]])
+    extra = {"means": ((tc - t) @ R).astype(F32),
+             "log_scales": np.array([[-1.1, -1.3, -1.6], [-1.4, -1.0, -1.5]], F32),
+             "quats": np.array([[0.9, 0.2, -0.3, 0.1], [0.7, -0.1, 0.4, 0.5]], F32),
+             "opacity": np.array([0.8, 0.7], F32),
+             "sh": np.random.default_rng(seed + 1).normal(0, 0.3, (2, (D + 1) ** 2, 3)).astype(F32)}
+    for k in extra:
+        g[k] = np.concatenate([g[k], extra[k]])
+    if cov6:
+        import oracle
+        g["cov6"] = oracle.cov3d(g["log_scales"], g["quats"]).astype(F32)
+        del g["log_scales"], g["quats"]
+    return g, cam
+
+
+def _clamp_state(orc, g, cam, prm):
+    pr = orc.project(g, cam, prm)
+    W, H = int(prm[0]), int(prm[1])
+    fx, fy, cx, cy = (float(v) for v in cam[12:16])
+    xr, yr = (pr[:, 1] - cx) / fx, (pr[:, 2] - cy) / fy
+    clx = np.abs(xr) > 1.3 * 0.5 * W / fx
+    cly = np.abs(yr) > 1.3 * 0.5 * H / fy
+    return pr, clx, cly
+
+
+@pytest.mark.parametrize("cov6", [False, True], ids=["scale_rotation", "cov6"])
+def test_adjoint_through_cov6_and_the_clamp_matches_torch_autograd(orc, cov6):
+    """The torch renderer computes the clamp limit and the covariance's
+    symmetric entries on its own: a wrong limit, a dropped factor on an
+    off-diagonal covariance adjoint or a wrong clamp derivative fails here."""
+    g, cam = _scene_clamped(23, 12, 1, cov6=cov6)
+    W, H = 32, 32
+    prm = orc.params(W, H, bg=(0.3, 0.0, 0.1))
+    pr, clx, cly = _clamp_state(orc, g, cam, prm)
+    n = len(g["means"])
+    assert clx[n - 2] and cly[n - 1] and pr[n - 2, 0] > 0 and pr[n - 1, 0] > 0
+    rng = np.random.default_rng(24)
+    G = tuple(x.astype(F32).astype(np.float64) for x in
+              (rng.standard_normal((H, W, 3)), rng.standard_normal((H, W)), rng.standard_normal((H, W))))
+    keys = ("means", "cov6", "opacity", "sh") if cov6 else ("means", "log_scales", "quats", "opacity", "sh")
+    p = {k: torch.tensor(g[k].astype(np.float64), requires_grad=True) for k in keys}
+    col, dep, al = _torch_render(p, cam, W, H, prm)
+    _, img, _, _, _, _ = orc.render(g, cam, prm, want_cands=False)
+    # the clamped Gaussians are drawn inside the image
+    assert (img[..., 4] > 0).any()
+    assert np.abs(col.detach().numpy() - img[..., :3]).max() < 1e-12
+    assert np.abs(dep.detach().numpy() - img[..., 3]).max() < 1e-12
+    L = (torch.tensor(G[0]) * col).sum() + (torch.tensor(G[1]) * dep).sum() + (torch.tensor(G[2]) * al).sum()
+    L.backward()
+    ours = orc.backward(g, cam[None], prm, G[0][None], G[1][None], G[2][None])
+    for k in keys:
+        ref = p[k].grad.numpy().reshape(ours[k].shape)
+        assert np.abs(ref[n - 2:]).max() > 0, k  # the clamped Gaussians have gradients
+        assert np.allclose(ours[k], ref, rtol=1e-9, atol=1e-11 * np.abs(ref).max()), k
+
+
+@pytest.mark.parametrize("cov6", [False, True], ids=["scale_rotation", "cov6"])
+def test_adjoint_through_cov6_and_the_clamp_by_finite_differences(orc, cov6):
+    """Central differences in double precision (the oracle's own forward,
+    perturbations below FP32 resolution) of every mean and covariance (or
+    scale / rotation) entry, the clamped Gaussians included."""
+    g, cam = _scene_clamped(25, 10, 2, cov6=cov6)
+    W, H = 32, 32
+    prm = orc.params(W, H, bg=(0.2, 0.1, 0.4))
+    rng = np.random.default_rng(26)
+    G = (rng.standard_normal((H, W, 3)), rng.standard_normal((H, W)), rng.standard_normal((H, W)))
+    grads = orc.backward(g, cam[None], prm, G[0][None], G[1][None], G[2][None])
+    lin = np.concatenate([G[0], G[1][..., None], G[2][..., None]], -1)
+    n = len(g["means"])
+    fields = [("means", 3), ("cov6", 6)] if cov6 else [("means", 3), ("log_scales", 3), ("quats", 4)]
+    fields.append(("opacity", 1))
+    samples, hs, ref = [], [], []
+    for i in range(n):
+        for f, m in fields:
+            for c in range(m):
+                samples.append((i, orc.param_index(f, c, 2)))
+                x0 = float(g[f].reshape(n, -1)[i, c])
+                if f == "cov6":  # relative to the entry's scale sqrt(S_aa S_bb)
+                    a, b = [(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)][c]
+                    d = g["cov6"][i, [0, 3, 5]].astype(np.float64)
+                    hs.append(1e-6 * math.sqrt(d[a] * d[b]))
+                else:
+                    hs.append(1e-6 * max(abs(x0), 1.0))
+                ref.append(grads[f].reshape(n, -1)[i, c])
+    fd, flag = orc.fd_loss(g, cam, prm, samples, np.array(hs), lin=lin)
+    ref = np.array(ref)
+    ok = flag == 0
+    assert ok.sum() >= 0.9 * len(ok)
+    scale = {f: np.abs(grads[f]).max() for f, _ in fields}
+    k = 0
+    for i in range(n):
+        for f, m in fields:
+            for c in range(m):
+                if ok[k]:
+                    assert abs(fd[k] - ref[k]) <= 1e-6 * scale[f] + 1e-5 * abs(ref[k]), (f, i, c, fd[k], ref[k])
+                k += 1
+    # the clamped Gaussians were checked
+    assert ok[-2 * sum(m for _, m in fields):].sum() >= sum(m for _, m in fields)
 
 
 def test_single_gaussian_closed_form_derivatives(orc):
