@@ -700,6 +700,7 @@ typedef struct {
 
 typedef struct {
     double c[3], d, T;
+    double eT; /* bound on the relative error of an FP32 evaluation of T */
     int n;
     int ncomp;    /* number of composited entries */
     uint32_t sig; /* signature of the composited index set */
@@ -715,15 +716,39 @@ typedef struct {
 
 enum { OUT_SKIP = 0, OUT_STOP = 1, OUT_COMP = 2 };
 
-static void entry_alpha(const octx *cx, int j, double *alpha, double *G, int *clamped, double *dx, double *dy)
+/* Bound on the relative error of alpha as an FP32 implementation evaluates
+ * it from the same record at the same pixel.  The exponent is a sum of terms
+ * of total magnitude S = |A| dx^2 / 2 + |C| dy^2 / 2 + |B dx dy|; the pixel
+ * offsets, the products and the sum each round to 2^-24 of a partial sum
+ * (plus a rescaling of the conic for a base-2 exponential), so its absolute
+ * error is a few units of 2^-24 S, which is alpha's relative error; the
+ * exponential, the opacity product and the clamp add a few units of 2^-24.
+ * For a needle-shaped Gaussian far along its axis S exceeds |P| by orders of
+ * magnitude, and so does this bound the fixed window d_skip. */
+#define OR_FP32_ROUNDINGS 16.0
+static double fp32_alpha_err(double S) { return OR_FP32_ROUNDINGS * 0x1p-24 * (S + 1.0); }
+
+static double exponent_terms(double A, double B, double C, double dx, double dy)
+{
+    return 0.5 * fabs(A) * dx * dx + 0.5 * fabs(C) * dy * dy + fabs(B * dx * dy);
+}
+
+/* relative error bound of T (1 - alpha) given those of T and of alpha */
+static double next_eT(double eT, double a, double ea) { return eT + a / (1.0 - a) * (ea + 0x1p-24) + 0x1p-24; }
+
+static void entry_alpha(const octx *cx, int j, double *alpha, double *err, double *G, int *clamped, double *dx,
+                        double *dy)
 {
     const double ddx = cx->px - cx->u[j], ddy = cx->py - cx->v[j];
     double P = -0.5 * (cx->A[j] * ddx * ddx + cx->C[j] * ddy * ddy) - cx->B[j] * ddx * ddy;
+    if (err) *err = fp32_alpha_err(exponent_terms(cx->A[j], cx->B[j], cx->C[j], ddx, ddy));
     if (P > 0.0) P = 0.0;
     const double g = exp(P);
     double a = cx->o[j] * g;
     int cl = 0;
     if (a > cx->p->alpha_max) {
+        /* clamped on both sides: the FP32 value is the clamp constant itself */
+        if (err && a >= cx->p->alpha_max * (1.0 + *err)) *err = 0.0;
         a = cx->p->alpha_max;
         cl = 1;
     }
@@ -751,30 +776,33 @@ static void push_cand(ocands *cb, const ostate *s, const oprm *p, int flips_used
     r[9] = s->sig;
 }
 
-static void apply_comp(const octx *cx, int j, double a, ostate *s)
+static void apply_comp(const octx *cx, int j, double a, double ea, ostate *s)
 {
     for (int ch = 0; ch < 3; ++ch) s->c[ch] += cx->rgb[3 * j + ch] * a * s->T;
     s->d += cx->z[j] * a * s->T;
     s->T = s->T * (1.0 - a);
+    s->eT = next_eT(s->eT, a, ea);
     s->n = j + 1;
     s->ncomp += 1;
     s->sig = s->sig * 1000003u + (uint32_t)(j + 1);
 }
 
-/* O11: front-to-back over the entry list; every near-threshold decision is
- * explored both ways while flips remain. */
+/* O11: front-to-back over the entry list; every decision within its window
+ * (the fixed d_skip / d_stop plus the FP32 rounding bound of that entry's
+ * alpha and of the transmittance so far) is explored both ways while flips
+ * remain. */
 static void comp_rec(const octx *cx, int j, ostate s, int flips, int used, ocands *cb)
 {
     const oprm *p = cx->p;
     for (; j < cx->len; ++j) {
-        double a;
-        entry_alpha(cx, j, &a, NULL, NULL, NULL, NULL);
+        double a, ea;
+        entry_alpha(cx, j, &a, &ea, NULL, NULL, NULL, NULL);
         const double Tn = s.T * (1.0 - a);
         const int skip = a < p->alpha_min;
         const int stop = Tn < p->t_min;
         const int primary = skip ? OUT_SKIP : (stop ? OUT_STOP : OUT_COMP);
-        const int amb_skip = fabs(a - p->alpha_min) <= p->d_skip * p->alpha_min;
-        const int amb_stop = fabs(Tn - p->t_min) <= p->d_stop * p->t_min;
+        const int amb_skip = fabs(a - p->alpha_min) <= (p->d_skip + ea) * p->alpha_min;
+        const int amb_stop = fabs(Tn - p->t_min) <= (p->d_stop + next_eT(s.eT, a, ea)) * p->t_min;
         if (amb_skip || (amb_stop && !skip)) cb->saw_amb = 1;
         if (flips > 0) {
             int alts[3] = {0, 0, 0};
@@ -794,7 +822,7 @@ static void comp_rec(const octx *cx, int j, ostate s, int flips, int used, ocand
                 } else if (alt == OUT_SKIP) {
                     comp_rec(cx, j + 1, s2, flips - 1, used + 1, cb);
                 } else {
-                    apply_comp(cx, j, a, &s2);
+                    apply_comp(cx, j, a, ea, &s2);
                     comp_rec(cx, j + 1, s2, flips - 1, used + 1, cb);
                 }
             }
@@ -804,7 +832,7 @@ static void comp_rec(const octx *cx, int j, ostate s, int flips, int used, ocand
             push_cand(cb, &s, p, used);
             return;
         }
-        apply_comp(cx, j, a, &s);
+        apply_comp(cx, j, a, ea, &s);
     }
     push_cand(cb, &s, p, used);
 }
@@ -999,7 +1027,8 @@ static void rect_flags(const oprm *pp, int64_t n, const double *proj, uint8_t *f
                         const double ddx = px + 0.5 - r[1], ddy = py + 0.5 - r[2];
                         double P = -0.5 * (r[4] * ddx * ddx + r[6] * ddy * ddy) - r[5] * ddx * ddy;
                         if (P > 0.0) P = 0.0;
-                        if (r[7] * exp(P) >= p.alpha_min * (1.0 - p.d_skip)) flags[(size_t)py * p.W + px] |= 1;
+                        const double win = p.d_skip + fp32_alpha_err(exponent_terms(r[4], r[5], r[6], ddx, ddy));
+                        if (r[7] * exp(P) >= p.alpha_min * (1.0 - win)) flags[(size_t)py * p.W + px] |= 1;
                     }
             }
     }
@@ -1058,7 +1087,9 @@ void or_render_view(int64_t n, const double *proj, const double *prm, double *im
                     if (P > 0.0) P = 0.0;
                     double a = ents[j].o * exp(P);
                     if (a > p.alpha_max) a = p.alpha_max;
-                    if (a < p.alpha_min * (1.0 - p.d_skip)) continue;
+                    const double win =
+                        p.d_skip + fp32_alpha_err(exponent_terms(ents[j].A, ents[j].B, ents[j].C, ddx, ddy));
+                    if (a < p.alpha_min * (1.0 - win)) continue;
                     if (zlast > 0.0 && fabs(ents[j].z - zlast) <= p.d_tie * (ents[j].z > zlast ? ents[j].z : zlast))
                         tie = 1;
                     zlast = ents[j].z;
@@ -1099,6 +1130,7 @@ static void atomic_add(double *p, double v)
 typedef struct {
     int j, clamped;
     double a, T, G, dx, dy;
+    double err; /* relative window of this alpha's skip decision: d_skip + its FP32 rounding bound */
 } ocomp;
 
 static void adjoint_pixel(const oprm *p, const double *proj, const int64_t *ent, const ocomp *cc, int nc,
@@ -1140,14 +1172,17 @@ static void pixel_alpha(const oprm *p, const double *proj, int64_t gi, double cx
     const double *r = proj + OR_PROJ_STRIDE * gi;
     e->a = e->G = e->dx = e->dy = 0.0;
     e->clamped = 0;
+    e->err = p->d_skip;
     if (r[0] == 0.0) return;
     e->dx = cx - r[1];
     e->dy = cy - r[2];
+    e->err = p->d_skip + fp32_alpha_err(exponent_terms(r[4], r[5], r[6], e->dx, e->dy));
     double P = -0.5 * (r[4] * e->dx * e->dx + r[6] * e->dy * e->dy) - r[5] * e->dx * e->dy;
     if (P > 0.0) P = 0.0;
     e->G = exp(P);
     e->a = r[7] * e->G;
     if (e->a > p->alpha_max) {
+        if (e->a >= p->alpha_max * (1.0 + e->err)) e->err = p->d_skip; /* the clamp constant on both sides */
         e->a = p->alpha_max;
         e->clamped = 1;
     }
@@ -1178,7 +1213,7 @@ static int branch_from_image(const oprm *p, const double *proj, const int64_t *e
     /* skip decisions inside the window, nearest the threshold first */
     for (int j = 0; j + 1 < nc; ++j) {
         const double m = fabs(all[j].a - amin) / amin;
-        if (m > p->d_skip) continue;
+        if (m > all[j].err) continue;
         if (namb < OR_MAX_ENUM) {
             amb[namb++] = j;
         } else {
@@ -1189,7 +1224,7 @@ static int branch_from_image(const oprm *p, const double *proj, const int64_t *e
         }
     }
     if (nc > 0 && all[nc - 1].a < amin) /* the implementation composited it: its FP64 alpha must be in the window */
-        if (fabs(all[nc - 1].a - amin) > p->d_skip * amin) st = 2;
+        if (fabs(all[nc - 1].a - amin) > all[nc - 1].err * amin) st = 2;
     /* every combination of the ambiguous decisions; the FP64 one first */
     double best = INFINITY;
     int best_combo = 0;
@@ -1223,7 +1258,7 @@ static int branch_from_image(const oprm *p, const double *proj, const int64_t *e
     if (best_combo != primary && st == 0) st = 1;
     if (nc > 0 && all[nc - 1].a < amin && st == 0) st = 1;
     /* the chosen branch, with its stop decisions checked against the FP64 values */
-    double T = 1.0;
+    double T = 1.0, eT = 0.0;
     int n = 0;
     for (int j = 0; j < nc; ++j) {
         int take = !(all[j].a < amin) || j == nc - 1;
@@ -1233,8 +1268,9 @@ static int branch_from_image(const oprm *p, const double *proj, const int64_t *e
         all[j].T = T;
         cc[n++] = all[j];
         const double Tn = T * (1.0 - all[j].a);
+        eT = next_eT(eT, all[j].a, all[j].err - p->d_skip);
         if (Tn < tmin) { /* the FP64 path stops here, the implementation composited it */
-            if (fabs(Tn - tmin) > p->d_stop * tmin) st = 2;
+            if (fabs(Tn - tmin) > (p->d_stop + eT) * tmin) st = 2;
             else if (st == 0) st = 1;
         }
         T = Tn;
@@ -1245,15 +1281,15 @@ static int branch_from_image(const oprm *p, const double *proj, const int64_t *e
     for (int j = nc; j < len && !resolved; ++j) {
         ocomp e;
         pixel_alpha(p, proj, ent[j], cx, cy, &e);
-        if (e.a < amin * (1.0 - p->d_skip)) continue; /* skipped on both sides */
+        if (e.a < amin * (1.0 - e.err)) continue; /* skipped on both sides */
         const double Tn = T * (1.0 - e.a);
         if (Tn < tmin) {
             if (e.a < amin && st == 0) st = 1; /* taken (and stopping) only inside the skip window */
             resolved = 1;
-        } else if (fabs(Tn - tmin) <= p->d_stop * tmin) {
+        } else if (fabs(Tn - tmin) <= (p->d_stop + next_eT(eT, e.a, e.err - p->d_skip)) * tmin) {
             if (st == 0) st = 1;
             resolved = 1;
-        } else if (e.a < amin * (1.0 + p->d_skip)) {
+        } else if (e.a < amin * (1.0 + e.err)) {
             if (st == 0) st = 1; /* the implementation skipped it inside the window; go on */
         } else {
             st = 2; /* the FP64 path would composite it */

@@ -6,7 +6,8 @@ and reused, each call enqueues the five hot-path entry points on torch's
 current stream.  Key-buffer overflow (more tile instances than capacity) is
 detected on the device; `Renderer.render` checks the flag once per call
 (eager mode) and re-runs the binning with a larger capacity, while graph
-replays (`CapturedRender`) never synchronise and check the flag afterwards.
+replays (`CapturedRender`) never synchronise and check the flag afterwards
+(`CapturedRender.overflowed`).
 """
 from __future__ import annotations
 
@@ -216,3 +217,64 @@ def observation_two_pass(scene, avatars, out=None):
     avatars as a second segment of one pass -- blends the two instead."""
     av = observation(avatars.rgb, avatars.depth, avatars.alpha)
     return observation(scene.rgb, scene.depth, scene.alpha, mesh_rgba=av[0], mesh_depth=av[1], out=out)
+
+
+class CapturedRender:
+    """A forward frame (optionally preceded by other launches, e.g. the
+    skinning of avatar Gaussians) captured once into a HIP graph and
+    replayed with no host work per frame.
+
+    The captured kernels hold raw device pointers: to the renderer's
+    buffers, to the frame's outputs and to the inputs (segments, cameras,
+    and whatever `before` writes).  A graph does not keep those tensors
+    alive, and `torch.cuda.graph` returns every unused cached block to the
+    device when it starts a capture, so a buffer whose Python owner is
+    dropped while its graph can still be replayed is unmapped memory the next
+    replay writes to.  This object therefore holds references to everything
+    the graph touches for as long as it lives; the renderer passed in is
+    reserved for it (a later call that grows one of its buffers would leave
+    the graph on the old one).
+
+    The key capacity is sized by an eager render first (growing on
+    overflow).  A replay cannot grow it: after replays, `overflowed()`
+    synchronises and reports whether any frame needed more keys than the
+    capacity (its image is then incomplete; capture again)."""
+
+    def __init__(self, renderer, segs, cams, view_segs=None, checkpoints=False, before=None):
+        if view_segs is None:
+            view_segs = [list(range(len(segs)))] * int(cams.shape[0])
+        self.renderer = renderer
+        self.segs = list(segs)
+        self.cams = cams
+        self.view_segs = [list(v) for v in view_segs]
+        self.before = before
+        if before is not None:
+            before()
+        self.frame = renderer.render(self.segs, cams, self.view_segs, checkpoints=checkpoints)
+        self.n_views = len(self.view_segs)
+        # warm-up launches on a side stream (the capture stream's allocator
+        # state and the library's lazily loaded kernels), then the capture
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            self._enqueue()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self._enqueue()
+        torch.cuda.synchronize()
+
+    def _enqueue(self):
+        if self.before is not None:
+            self.before()
+        self.renderer.enqueue(self.segs, self.cams, self.view_segs, self.frame)
+
+    def replay(self):
+        """Enqueue one frame on torch's current stream; outputs in self.frame."""
+        self.graph.replay()
+        return self.frame
+
+    def overflowed(self):
+        torch.cuda.synchronize()
+        return bool(int(self.frame.overflow.item()))

@@ -44,3 +44,35 @@ def frame_to_numpy(f, view):
     img = np.concatenate([rgb, depth[..., None], alpha[..., None]], -1)
     nc = f.n_contrib[view].cpu().numpy().astype(np.int64)
     return img, nc
+
+
+def gpu_decisions(f, views, bases, W, H):
+    """The GPU frame's discrete decisions per view, in the form the oracle's
+    branch-following adjoint takes: its per-tile lists (vals, ranges of the
+    view), the instance id of the view's first Gaussian, n_contrib and its
+    image (r, g, b, depth, alpha)."""
+    T = ((W + 15) // 16) * ((H + 15) // 16)
+    K = int(f.num.item())
+    vals = f.vals[:K].cpu().numpy().view(np.uint32)
+    ranges = f.ranges.cpu().numpy().view(np.uint32)
+    out = []
+    for v, base in zip(views, bases):
+        img, nc = frame_to_numpy(f, v)
+        out.append({"vals": vals, "ranges": ranges[v * T:(v + 1) * T], "base": int(base), "n_contrib": nc,
+                    "img": img})
+    return out
+
+
+def grad_check(say, got, ref, fields, tol=1e-4, label=""):
+    """max |g_gpu - g_ref| <= tol * max |g_ref| per parameter block, on every
+    Gaussian.  got: dict of numpy arrays, ref: the oracle's dict."""
+    worst = {}
+    for k in fields:
+        g = np.asarray(got[k], np.float64).reshape(ref[k].shape)
+        scale = np.abs(ref[k]).max()
+        assert scale > 0, (label, k)
+        worst[k] = np.abs(g - ref[k]).max() / scale
+    say("  %s max |g_gpu - g_ref| / max |g_ref|:" % label, {k: "%.2e" % v for k, v in worst.items()})
+    for k, v in worst.items():
+        assert v <= tol, (label, k, v)
+    return worst

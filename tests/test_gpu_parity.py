@@ -370,53 +370,6 @@ def test_full_size_room_keys_are_a_valid_binning(dev):
     say("  K = %d, visible = %d" % (K, int((tt > 0).sum())))
 
 
-def _max_rel_block(gpu, ref):
-    return np.abs(gpu - ref).max() / max(np.abs(ref).max(), 1e-30)
-
-
-@pytest.mark.parametrize("checkpoints", [False, True], ids=["whole_lists", "segmented"])
-def test_backward_parity_sh3(dev, orc, checkpoints):
-    """Gradients of <G, render> for random output adjoints G (rgb, depth,
-    alpha) against the oracle's FP64 adjoint, on every Gaussian; lists walked
-    whole, or in segments from the forward's checkpoints."""
-    import torch
-    from paper_2604_12626_amd import render
-    cfg = synth.config(2, scale=0.04)  # 20k Gaussians, 256x256, SH3
-    W, H = cfg["W"], cfg["H"]
-    g = cfg["segments"][0]
-    say("backward parity: room20k 256x256 sh3, checkpoints", checkpoints)
-    rng = np.random.default_rng(5)
-    G = [rng.standard_normal((1, H, W, 3)).astype(F32), rng.standard_normal((1, H, W)).astype(F32),
-         rng.standard_normal((1, H, W)).astype(F32)]
-    r = render.Renderer(W, H, capacity=1 << 18, device=dev, checkpoints=checkpoints)
-    tg = to_dev(g, dev)
-    cams = torch.from_numpy(cfg["cams"]).to(dev)
-    f = r.render([tg], cams, [[0]])
-    d = r.backward([tg], cams, [[0]], f, *[torch.from_numpy(x).to(dev) for x in G])[0]
-    torch.cuda.synchronize()
-    prm = orc.params(W, H)
-    ref = orc.backward(g, cfg["cams"], prm, *G)
-    # Gaussians at a pixel whose compositing holds a decision inside its FP32
-    # margin (the oracle enumerates them) have a branch-dependent gradient:
-    # they are counted and held to a loose bound; all others to 1e-4
-    amb = ref["ambiguous"] > 0
-    visible = np.abs(ref["sh"]).reshape(len(amb), -1).max(1) > 0  # composited at some pixel
-    worst, loose = {}, {}
-    for k in ("means", "log_scales", "quats", "opacity", "sh"):
-        gg = d[k].cpu().numpy().astype(np.float64).reshape(ref[k].shape)
-        err = np.abs(gg - ref[k]).reshape(len(gg), -1).max(1)
-        scale = max(np.abs(ref[k]).max(), 1e-30)
-        worst[k] = err[~amb].max() / scale
-        loose[k] = err[amb].max() / scale if amb.any() else 0.0
-    say("  ambiguous gaussians: %d of %d composited" % (int(amb.sum()), int(visible.sum())))
-    say("  max |g_gpu - g_ref| / max |g_ref| per block:", {k: "%.2e" % v for k, v in worst.items()})
-    say("  same over the ambiguous ones:", {k: "%.2e" % v for k, v in loose.items()})
-    assert amb.sum() <= 0.05 * visible.sum()
-    for k in worst:
-        assert worst[k] <= 1e-4, (k, worst[k])
-        assert loose[k] <= 5e-2, (k, loose[k])
-
-
 def test_segmented_backward_matches_whole_lists(dev):
     """With lists of thousands of entries (many segments each, and some longer
     than the segment grid holds: 1M room Gaussians at five times their

@@ -88,6 +88,33 @@ def test_skip_enumeration_window_edges(orc):
         assert ncand[8, 8] == want, (k, ncand[8, 8])
 
 
+def test_skip_window_widens_with_the_exponents_rounding_bound(orc):
+    """A needle-shaped Gaussian (sigma 5 px along the diagonal, 0.55 px
+    across) far along its axis: its exponent (-5) is a sum of terms of
+    magnitude ~400, so an FP32 evaluation of its alpha carries a relative
+    error of a few 1e-4.  At 3e-4 from the threshold its skip decision is
+    enumerated; a round Gaussian at the same distance is not; the needle at
+    3e-3 is not either."""
+    d = 11.18  # offset in x and in y: 15.8 px along the long axis
+    sl, ss = 5.0, 0.55
+    A = C = 0.5 * (1 / sl ** 2 + 1 / ss ** 2)
+    B = 0.5 * (1 / sl ** 2 - 1 / ss ** 2)
+    cases = [((A, B, C), 3e-4, 2), ((A, B, C), -3e-4, 2), ((A, B, C), 3e-3, 1),
+             ((0.25, 0.0, 0.25), 3e-4, 1), ((0.25, 0.0, 0.25), -3e-4, 1)]
+    for (a, b, c), rel, want in cases:
+        a, b, c = (float(F32(x)) for x in (a, b, c))
+        u = v = float(F32(8.5 - d))
+        dx, dy = 8.5 - u, 8.5 - v
+        P = -0.5 * (a * dx * dx + c * dy * dy) - b * dx * dy
+        S = 0.5 * abs(a) * dx * dx + 0.5 * abs(c) * dy * dy + abs(b * dx * dy)
+        o = F32(orc.ALPHA_MIN * (1.0 + rel) / np.exp(P))
+        r = _rec(u, v, 1.0, 40, a, b, c, o, [1.0, 1.0, 1.0])
+        img, ncand, cands = _composite_records(orc, [r])
+        assert ncand[8, 8] == want, (a, b, c, rel, S, ncand[8, 8])
+        if want == 2:
+            assert S > 300 and abs(P) < 10
+
+
 # --------------------------------------------------------------------------
 # O8 + flags bit 0: a rect that depends on a floor inside its window
 # --------------------------------------------------------------------------
