@@ -3,14 +3,17 @@
 
 Headline (`value`): forward frames/s of one 640x480 view of a 1M-Gaussian SH3
 room scene (synthetic stand-in for an indoor 3DGS capture), the whole
-per-frame path -- projection + SH, scan/emit, onesweep sort, ranges,
-compositing -- enqueued back to back on one stream with no host
-synchronisation and inputs resident in HBM.  Further lines of the metric
-(fwd+bwd, batched multi-view vs plain per-view, avatars) are reported under
-"extras".
+per-frame path -- projection + SH, binning (tile counts, bucket sort by
+tile and depth, ranges, work order), compositing -- replayed from one HIP
+graph with inputs resident in HBM (the eager launch sequence is reported
+beside it).  Further lines of the metric (fwd+bwd, batched multi-view vs
+plain per-view, avatars) are reported under "extras", each with its stage
+roofline (algorithmic bytes, flops and exponentials of every stage from the
+run's own counts, against the HBM, FP32 and transcendental peaks).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras]
                        [--no-cpu-baseline] [--profile] [--profile-fwd-bwd]
+                       [--profile-batched] [--profile-avatars] [--copy-calib]
 Prints one JSON line.
 """
 import argparse
@@ -25,15 +28,21 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# 256 CU x 64 FP32 lanes x 2 flop (FMA) x 2.4 GHz.  The chip's 157.3 TFLOP/s
-# needs packed FP32 instructions, which this library is built without.
+# MI355X vector FP32 peak: the roofline fraction is taken against it.
+FP32_PEAK_TFLOPS = 157.3
+# 256 CU x 64 FP32 lanes x 2 flop (FMA) x 2.4 GHz without packed FP32
+# instructions (this library is built without them): informational.
 FP32_NONPACKED_TFLOPS = 78.6
-FP32_PACKED_TFLOPS = 157.3
+# transcendentals (v_exp_f32) issue at a quarter of the lane rate
+EXP_PEAK_TPS = 256 * 64 * 2.4e9 / 4 / 1e12
 # Algorithmic work of one evaluated (pixel, list entry) pair of front-to-back
 # compositing: offset (2), quadratic form (9), o * exp (1), clamp (1), skip
 # test (1), T (1 - alpha) (2), stop test (1), alpha T (1), colour and depth
 # accumulation (4 FMA = 8); the exponential itself is counted apart.
 FLOPS_PER_PAIR = 26
+# per pair of the backward walk: T recovery, the alpha and colour adjoints,
+# the exponent's gradient and the ten wave sums (one exp, one reciprocal)
+BWD_FLOPS_PER_PAIR = 70
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "composite_room1M_640x480_counters.txt")
 COMPOSITE_SOURCES = [os.path.join(ROOT, "paper_2604_12626_amd", "csrc", n)
                      for n in ("gs_composite.hip", "gs_internal.hpp")]
@@ -50,6 +59,10 @@ def parse():
     ap.add_argument("--copy-calib", action="store_true", help="also run a 512 MiB device copy (counter scale)")
     ap.add_argument("--profile-fwd-bwd", action="store_true",
                     help="forward + backward of the 256x256 500k-Gaussian view only, for rocprofv3 runs")
+    ap.add_argument("--profile-batched", action="store_true",
+                    help="the 64-view batched frame only (graph replays), for rocprofv3 runs")
+    ap.add_argument("--profile-avatars", action="store_true",
+                    help="the 16-view avatar frame only (forward and forward + backward), for rocprofv3 runs")
     return ap.parse_args()
 
 
@@ -88,22 +101,88 @@ def sh_bytes(D):
     return 12 * (D + 1) ** 2
 
 
-def algorithmic_bytes(N, n_vis, K, passes, V, HW, T, D):
-    """Bytes each stage must move at minimum (reads + writes), per call."""
-    return {
-        # means of every Gaussian (near-plane cull) + scale/rotation/opacity and SH of the
-        # visible ones + tiles_touched of all + the 48-B record of the visible ones
-        "project": N * 12 + n_vis * (32 + sh_bytes(D)) + N * 4 + n_vis * 48,
-        # scan (tiles_touched read twice, offsets written), emission (counts, offsets,
-        # the 16-B head + view of visible records, 12 B per key), histogram (8 B per key),
-        # P passes of 24 B per key, ranges (8 B per key + 8 B per tile)
-        "bin_sort": N * 16 + n_vis * 20 + K * 12 + K * 8 + passes * K * 24 + K * 8 + V * T * 8,
-        # values + gathered 48-B records + 28 B of outputs per pixel
-        "composite": K * 52 + V * HW * 28,
+def sort_passes(n_tiles_total):
+    """8-bit LSD passes over the significant key bits (tile bits + 32 depth bits)."""
+    return (32 + max(1, int(np.ceil(np.log2(max(2, n_tiles_total))))) + 7) // 8
+
+
+def stage_roofline(c):
+    """Algorithmic bytes, flops and exponentials of each stage of one step and
+    the roofline time: sum over stages of max(bytes / HBM, flops / FP32 peak,
+    exps / transcendental rate).  c: measured counts -- N (Gaussians read,
+    each scene once), I (instances: Gaussians x the views drawing them),
+    n_vis (visible instances), K (tile instances), V, HW (pixels per view),
+    T (tiles per view), D (SH degree), pairs (evaluated (pixel, entry) pairs
+    of compositing); for a backward also pairs_b (pairs walked back),
+    n_drawn and N_grad (dense gradient rows); n_av (skinned Gaussians)."""
+    D = c["D"]
+    sh = sh_bytes(D)
+    P = sort_passes(c["V"] * c["T"])
+    st = {
+        "project": (c["N"] * 12 + c["I"] * 4 + c["n_vis"] * (32 + sh + 48), 250 * c["n_vis"], 0),
+        "bin_sort": (c["I"] * 4 + c["n_vis"] * 20 + c["K"] * (12 + 8 + P * 24 + 8) + c["V"] * c["T"] * 8, 0, 0),
+        "composite": (c["K"] * 52 + c["V"] * c["HW"] * 28, FLOPS_PER_PAIR * c["pairs"], c["pairs"]),
     }
+    if c.get("pairs_b") is not None:
+        st["bwd_composite"] = (c["V"] * c["HW"] * 28 + c["K"] * 52 + c["n_vis"] * 80,
+                               BWD_FLOPS_PER_PAIR * c["pairs_b"], 2 * c["pairs_b"])
+        st["bwd_project"] = (c["n_drawn"] * (32 + sh + 40 + 48) + c["N_grad"] * 4 * (11 + 3 * (D + 1) ** 2),
+                             600 * c["n_drawn"], 0)
+    if c.get("n_av"):
+        st["lbs"] = (c["n_av"] * 96, 90 * c["n_av"], 0)
+        if c.get("pairs_b") is not None:
+            st["lbs_backward"] = (c["n_av"] * 140, 200 * c["n_av"], 0)
+    out = {}
+    total = 0.0
+    for k, (by, fl, ex) in st.items():
+        t = max(by / (HBM_PEAK_GBS * 1e9), fl / (FP32_PEAK_TFLOPS * 1e12), ex / (EXP_PEAK_TPS * 1e12)) * 1e3
+        out[k] = {"bytes": int(by), "flops": int(fl), "exps": int(ex), "ms": t}
+        total += t
+    return total, out
 
 
-def bench_forward(args, dev, timer_steps):
+def roofline_block(counts, measured_ms, pairs_source):
+    rt, stages = stage_roofline(counts)
+    return {"roofline_ms": rt, "measured_ms": measured_ms, "frac": rt / measured_ms, "pairs_source": pairs_source,
+            "counts": {k: (int(v) if isinstance(v, (int, np.integer)) else v) for k, v in counts.items()},
+            "stages": stages}
+
+
+def oracle_pairs(views):
+    """Evaluated (pixel, entry) pairs of the oracle's render: views is a list
+    of (gaussian dict of numpy arrays, camera, W, H)."""
+    import oracle
+    total = 0
+    for g, cam, W, H in views:
+        prm = oracle.params(W, H, max_flips=0)
+        proj = oracle.project(g, cam, prm)
+        total += oracle.render_view(proj, prm, want_cands=False)[4]
+    return total
+
+
+def _time_seq(fn, warmup, steps):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def _frame_counts(f, n_views, T, HW, D, N, I):
+    import torch
+    return {"N": int(N), "I": int(I), "n_vis": int((f.tiles_touched > 0).sum().item()), "K": int(f.num.item()),
+            "V": int(n_views), "HW": int(HW), "T": int(T), "D": int(D)}
+
+
+def bench_forward(args, dev):
+    """The headline frame: 1M-Gaussian SH3 room, one 640x480 view.  Timed as
+    replays of the captured frame (one HIP graph: projection, binning and
+    compositing, inputs resident) and as the eager launch sequence, whose
+    compositing launches are bracketed by HIP events on their stream."""
     import torch
     from paper_2604_12626_amd import render, synth
     cfg = synth.config(1)
@@ -116,36 +195,40 @@ def bench_forward(args, dev, timer_steps):
     r = render.Renderer(W, H, capacity=1 << 22, device=dev)
     f = r.render(segs, cams, vs)  # sizes the key capacity (grows on overflow)
     torch.cuda.synchronize()
-    K = int(f.num.item())
-    n_vis = int((f.tiles_touched > 0).sum().item())
-    # the whole forward frame as a launch sequence on one stream, no host sync
     for _ in range(args.warmup):
         r.enqueue(segs, cams, vs, f)
     torch.cuda.synchronize()
+    comp_ev = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        r.enqueue(segs, cams, vs, f)
+        r.project(segs, cams, vs, f)
+        r.bin_sort(f, 1)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        r.composite(f, 1)
+        b.record()
+        comp_ev.append((a, b))
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    ms_eager = (time.perf_counter() - t0) * 1e3 / args.steps
+    composite_ms = float(np.mean([a.elapsed_time(b) for a, b in comp_ev]))
     assert int(f.overflow.item()) == 0, "key capacity overflow during the timed region"
-    ms = (t1 - t0) * 1e3 / args.steps
-    # per-stage durations (eager launches bracketed by events on the same stream)
+    cap = render.CapturedRender(render.Renderer(W, H, capacity=r.capacity, device=dev), segs, cams, vs)
+    ms_graph = _time_seq(cap.replay, args.warmup, args.steps)
+    assert not cap.overflowed()
+    assert torch.equal(cap.frame.rgb, f.rgb) and torch.equal(cap.frame.depth, f.depth)
     tm = Timer()
-    for _ in range(timer_steps):
+    for _ in range(max(5, args.steps // 2)):
         tm.run("project", lambda: r.project(segs, cams, vs, f))
         tm.run("bin_sort", lambda: r.bin_sort(f, 1))
-        tm.run("composite", lambda: r.composite(f, 1))
     stages = tm.means_ms()
-    T = r.T
-    tile_bits = max(1, int(np.ceil(np.log2(T))))
-    passes = (32 + tile_bits + 7) // 8
-    nbytes = algorithmic_bytes(N, n_vis, K, passes, 1, W * H, T, D)
-    info = {"N": N, "n_vis": n_vis, "K": K, "sort_passes": passes, "stage_ms": stages, "alg_bytes": nbytes,
-            "capacity": r.capacity, "n_contrib_sum": int(f.n_contrib.to(torch.int64).sum().item())}
-    return ms, info, (r, f, segs, cams, vs)
+    stages["composite"] = composite_ms
+    counts = _frame_counts(f, 1, r.T, W * H, D, N, N)
+    info = {"stage_ms": stages, "counts": counts, "ms_eager": ms_eager,
+            "n_contrib_sum": int(f.n_contrib.to(torch.int64).sum().item())}
+    return ms_graph, info
 
 
-def bench_fwd_bwd(args, dev, steps):
+def bench_fwd_bwd(args, dev, steps, want_pairs=True):
     """Forward + backward of one 256x256 view of a 500k-Gaussian SH3 room:
     L = sum |rgb - rgb*|^2 + sum (D - D*)^2 against the render of the
     perturbed parameters; one step = forward (recording segment checkpoints),
@@ -154,11 +237,12 @@ def bench_fwd_bwd(args, dev, steps):
     from paper_2604_12626_amd import render, synth
     cfg = synth.config(2)
     g = cfg["segments"][0]
+    W, H = cfg["W"], cfg["H"]
     segs = [to_dev(g, dev)]
     tgt = [to_dev(synth.perturb(g, cfg["perturb_rng"]), dev)]
     cams = torch.from_numpy(cfg["cams"]).to(dev)
     vs = [[0]]
-    r = render.Renderer(cfg["W"], cfg["H"], capacity=1 << 21, device=dev, checkpoints="auto")
+    r = render.Renderer(W, H, capacity=1 << 21, device=dev, checkpoints="auto")
     ft = r.render(tgt, cams, vs)
     rgb_t, depth_t = ft.rgb.clone(), ft.depth.clone()
     r.render(segs, cams, vs)  # sizes the key capacity for the timed parameters
@@ -169,14 +253,23 @@ def bench_fwd_bwd(args, dev, steps):
 
     ms = _time_seq(step, max(2, args.warmup // 2), steps)
     assert int(r._bufs["ovf"][0].item()) == 0
-    return ms
+    f = r.render(segs, cams, vs)
+    torch.cuda.synchronize()
+    c = _frame_counts(f, 1, r.T, W * H, g["sh_degree"], len(g["means"]), len(g["means"]))
+    c["pairs_b"] = int(f.n_contrib.to(torch.int64).sum().item())
+    c["n_drawn"] = c["n_vis"]
+    c["N_grad"] = len(g["means"])
+    c["pairs"] = oracle_pairs([(g, cfg["cams"][0], W, H)]) if want_pairs else c["pairs_b"]
+    src = "oracle count (forward); backward: sum of n_contrib" if want_pairs else "lower bound: sum of n_contrib"
+    return ms, roofline_block(c, ms, src)
 
 
-def bench_batched(args, dev, steps):
+def bench_batched(args, dev, steps, want_pairs=True):
     """64 views at 256x256 of 8 room scenes (view v shows scene v mod 8,
-    scenes of 1e5..2e6 Gaussians): one batched call (scene-major projection,
-    one sort and one persistent compositing launch for all views) vs the same
-    views rendered one call at a time (plain)."""
+    scenes of 1e5..2e6 Gaussians): one batched frame (scene-major projection,
+    one sort and one persistent compositing launch for all views) captured
+    into one HIP graph, vs the same views rendered one call at a time (plain,
+    each view its own captured graph); eager launch sequences for reference."""
     import torch
     from paper_2604_12626_amd import autotune, render, synth
     cfg = synth.config(3)
@@ -187,29 +280,45 @@ def bench_batched(args, dev, steps):
     rb = render.Renderer(W, H, capacity=1 << 24, device=dev)
     fb = rb.render(segs, cams, vs)
     best, _ = autotune.tune_composite(rb, fb, len(vs))
-    ms_b = _time_seq(lambda: rb.enqueue(segs, cams, vs, fb), args.warmup, steps)
+    ms_b_eager = _time_seq(lambda: rb.enqueue(segs, cams, vs, fb), args.warmup, steps)
+    cap = render.CapturedRender(render.Renderer(W, H, capacity=rb.capacity, device=dev), segs, cams, vs)
+    ms_b = _time_seq(cap.replay, args.warmup, steps)
+    assert not cap.overflowed()
+    assert torch.equal(cap.frame.rgb, fb.rgb)
     plain = []
     for v in range(len(vs)):
-        rp = render.Renderer(W, H, capacity=1 << 20, device=dev)
         sv = [segs[vs[v][0]]]
-        fp = rp.render(sv, cams[v:v + 1], [[0]])
-        plain.append((rp, fp, sv, v))
+        plain.append(render.CapturedRender(render.Renderer(W, H, capacity=1 << 20, device=dev), sv,
+                                           cams[v:v + 1].contiguous(), [[0]]))
 
     def all_plain():
-        for rp, fp, sv, v in plain:
-            rp.enqueue(sv, cams[v:v + 1], [[0]], fp)
+        for c in plain:
+            c.replay()
 
     ms_p = _time_seq(all_plain, args.warmup, steps)
-    assert int(fb.overflow.item()) == 0 and all(int(fp.overflow.item()) == 0 for _, fp, _, _ in plain)
-    return ms_b, ms_p, len(vs), int(fb.num.item()), best
+    assert not any(c.overflowed() for c in plain)
+    ms_p_eager = _time_seq(lambda: [c.renderer.enqueue(c.segs, c.cams, c.view_segs, c.frame) for c in plain],
+                           args.warmup, steps)
+    Ns = [len(g["means"]) for g in cfg["segments"]]
+    counts = _frame_counts(fb, len(vs), rb.T, W * H, 3, sum(Ns), sum(Ns[v[0]] for v in vs))
+    if want_pairs:
+        counts["pairs"] = oracle_pairs([(cfg["segments"][vs[v][0]], cfg["cams"][v], W, H) for v in range(len(vs))])
+        src = "oracle count"
+    else:
+        counts["pairs"] = int(fb.n_contrib.to(torch.int64).sum().item())
+        src = "lower bound: sum of n_contrib"
+    res = {"ms_batched": ms_b, "ms_plain": ms_p, "ms_batched_eager": ms_b_eager, "ms_plain_eager": ms_p_eager,
+           "n_views": len(vs), "groups_per_cu": best, "roofline": roofline_block(counts, ms_b, src)}
+    return res
 
 
-def bench_avatars(args, dev, steps):
+def bench_avatars(args, dev, steps, want_pairs=True):
     """1M room + 8 avatars x 50k Gaussians, 16 views at 640x480: LBS of the
     avatar Gaussians, then all views of room + posed avatars in one call
-    (forward), and the same with the backward through the renderer and LBS
-    to the canonical avatar parameters (fwd+bwd; checkpoints "auto", which
-    leaves them off for 19200 tile lists)."""
+    (forward, captured with the skinning into one HIP graph), and the same
+    with the backward through the renderer and LBS to the canonical avatar
+    parameters (fwd+bwd; checkpoints "auto", which leaves them off for 19200
+    tile lists)."""
     import torch
     from paper_2604_12626_amd import autotune, binding as B, render
     from paper_2604_12626_amd import synth
@@ -222,7 +331,8 @@ def bench_avatars(args, dev, steps):
              "opacity": av["opacity"], "sh": av["sh"], "sh_degree": 3}
     cams = torch.from_numpy(cfg["cams"]).to(dev)
     vs = cfg["view_segs"]
-    r = render.Renderer(cfg["W"], cfg["H"], capacity=1 << 24, device=dev)
+    W, H = cfg["W"], cfg["H"]
+    r = render.Renderer(W, H, capacity=1 << 24, device=dev)
     d_means = torch.empty(n_av, 3, device=dev)
     d_ls = torch.empty(n_av, 3, device=dev)
     d_q = torch.empty(n_av, 4, device=dev)
@@ -240,7 +350,12 @@ def bench_avatars(args, dev, steps):
         lbs()
         r.enqueue([room, posed], cams, vs, f)
 
-    rb = render.Renderer(cfg["W"], cfg["H"], capacity=1 << 24, device=dev, checkpoints="auto")
+    ms_eager = _time_seq(frame, args.warmup, steps)
+    cap = render.CapturedRender(render.Renderer(W, H, capacity=r.capacity, device=dev), [room, posed], cams, vs,
+                                before=lbs)
+    ms = _time_seq(cap.replay, args.warmup, steps)
+    assert not cap.overflowed()
+    rb = render.Renderer(W, H, capacity=1 << 24, device=dev, checkpoints="auto")
     fb = rb.render([room, posed], cams, vs)
 
     def frame_bwd():
@@ -250,9 +365,27 @@ def bench_avatars(args, dev, steps):
         B.deform_lbs_backward(av["means"], av["log_scales"], av["quats"], av["joint_idx"], av["weights"],
                               av["avatar_of"], skin, gr[1]["means"], gr[1]["cov6"], d_means, d_ls, d_q)
 
-    ms = _time_seq(frame, args.warmup, steps)
     ms_b = _time_seq(frame_bwd, max(2, args.warmup // 2), max(3, steps // 2))
     assert int(f.overflow.item()) == 0 and int(fb.overflow.item()) == 0
+    N_room = int(room["means"].shape[0])
+    counts = _frame_counts(f, len(vs), r.T, W * H, 3, N_room + n_av, len(vs) * (N_room + n_av))
+    counts["n_av"] = int(n_av)
+    if want_pairs:
+        posed_np = {"means": posed["means"].cpu().numpy(), "cov6": posed["cov6"].cpu().numpy(),
+                    "opacity": cfg["avatars"]["opacity"], "sh": cfg["avatars"]["sh"], "sh_degree": 3}
+        import oracle
+        both = oracle.concat_segments([cfg["segments"][0], posed_np])
+        counts["pairs"] = oracle_pairs([(both, cfg["cams"][v], W, H) for v in range(len(vs))])
+        src = "oracle count"
+    else:
+        counts["pairs"] = int(f.n_contrib.to(torch.int64).sum().item())
+        src = "lower bound: sum of n_contrib"
+    roof_f = roofline_block(dict(counts), ms, src)
+    cb = dict(counts)
+    cb["pairs_b"] = int(fb.n_contrib.to(torch.int64).sum().item())
+    cb["n_drawn"] = min(counts["n_vis"], N_room + n_av)
+    cb["N_grad"] = N_room + n_av
+    roof_b = roofline_block(cb, ms_b, src + "; backward: sum of n_contrib")
     # skinning alone, with fixed joint matrices and with each avatar's matrices
     # interpolated in a 90-frame walking clip at its current time
     clip, first, nfr = synth.avatar_clips(np.random.default_rng(5), [90] * int(skin.shape[0]))
@@ -264,7 +397,8 @@ def bench_avatars(args, dev, steps):
                           av["avatar_of"], *tclip, fpos, posed["means"], posed["cov6"])
 
     lbs_ms = {k: _event_ms(fn, 20 * steps) for k, fn in (("fixed", lbs), ("clip", lbs_clip))}
-    return ms, ms_b, len(vs), lbs_ms, n_av
+    return {"ms": ms, "ms_eager": ms_eager, "ms_bwd": ms_b, "n_views": len(vs), "lbs_ms": lbs_ms, "n_av": n_av,
+            "roofline_fwd": roof_f, "roofline_fwd_bwd": roof_b}
 
 
 def _event_ms(fn, reps):
@@ -330,18 +464,6 @@ def bench_capsules(args, dev, steps):
     return _event_ms(q, 20 * steps)
 
 
-def _time_seq(fn, warmup, steps):
-    import torch
-    for _ in range(warmup):
-        fn()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        fn()
-    torch.cuda.synchronize()
-    return (time.perf_counter() - t0) * 1e3 / steps
-
-
 def source_digest(paths):
     import hashlib
     h = hashlib.sha256()
@@ -374,31 +496,82 @@ def counter_traffic():
     return (fetch + write) * 1024.0, "FETCH_SIZE x %s + WRITE_SIZE x %s" % (kv["fetch_scale"], kv["write_scale"])
 
 
-def cpu_baseline(min_seconds=10.0):
-    """The FP64 oracle (as it stands, no candidate enumeration) rendering the
-    headline frame -- projection of all 1M Gaussians and compositing of all
-    640x480 pixels -- repeated until at least `min_seconds` of CPU work."""
-    import oracle
-    from paper_2604_12626_amd import synth
-    cfg = synth.config(1)
-    g = cfg["segments"][0]
-    W, H = cfg["W"], cfg["H"]
-    prm = oracle.params(W, H, max_flips=0)
-    frames = 0
-    pairs = None
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def _time_cpu(fn, min_seconds):
+    n = 0
     t0 = time.perf_counter()
     while True:
-        proj = oracle.project(g, cfg["cams"][0], prm)
-        _, _, _, _, npairs = oracle.render_view(proj, prm, want_cands=False)
-        pairs = npairs if pairs is None else pairs
-        frames += 1
+        fn()
+        n += 1
         el = time.perf_counter() - t0
         if el >= min_seconds:
-            break
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": frames / el, "unit": "frames/s", "cores": cores, "kind": "oracle",
-            "sample": "FP64 oracle, full headline frame (projection of 1M Gaussians + all 640x480 pixels) "
-                      "x %d frames in %.1f s, OpenMP over Gaussians and tiles" % (frames, el)}, pairs
+            return n, el
+
+
+def cpu_baseline(leg_seconds=5.0):
+    """The FP64 oracle as it stands (no candidate enumeration) on the host's
+    cores, on all of its OpenMP threads and on one: the headline frame
+    (projection of all 1M Gaussians and compositing of all 640x480 pixels),
+    the fwd+bwd step of the 500k view (forward, L2 adjoint, backward to every
+    parameter) and a sample of the batched workload (views 0-7: one per
+    scene, 256x256 each).  Each leg repeats for at least `leg_seconds`."""
+    import oracle
+    from paper_2604_12626_amd import synth
+    n_all = oracle.set_threads(1)
+    oracle.set_threads(n_all)
+    c1 = synth.config(1)
+    g1, W1, H1 = c1["segments"][0], c1["W"], c1["H"]
+    p1 = oracle.params(W1, H1, max_flips=0)
+
+    def fwd():
+        oracle.render_view(oracle.project(g1, c1["cams"][0], p1), p1, want_cands=False)
+
+    c2 = synth.config(2)
+    g2, W2, H2 = c2["segments"][0], c2["W"], c2["H"]
+    p2 = oracle.params(W2, H2, max_flips=0)
+    _, timg, *_ = oracle.render(synth.perturb(g2, c2["perturb_rng"]), c2["cams"][0], p2, want_cands=False)
+
+    def fwd_bwd():
+        _, img, *_ = oracle.render(g2, c2["cams"][0], p2, want_cands=False)
+        G = [2.0 * (img[None, ..., :3] - timg[None, ..., :3]), 2.0 * (img[None, ..., 3] - timg[None, ..., 3]),
+             np.zeros((1, H2, W2))]
+        oracle.backward(g2, c2["cams"], p2, *G)
+
+    c3 = synth.config(3)
+    p3 = oracle.params(c3["W"], c3["H"], max_flips=0)
+    sample = list(range(8))
+
+    def batched():
+        for v in sample:
+            oracle.render_view(oracle.project(c3["segments"][c3["view_segs"][v][0]], c3["cams"][v], p3), p3,
+                               want_cands=False)
+
+    legs = {}
+    for name, fn, per in (("fwd_frames_per_s", fwd, 1), ("fwd_bwd_steps_per_s", fwd_bwd, 1),
+                          ("batched_views_per_s", batched, len(sample))):
+        legs[name] = {}
+        for label, nt in (("all_threads", n_all), ("one_thread", 1)):
+            oracle.set_threads(nt)
+            n, el = _time_cpu(fn, leg_seconds)
+            legs[name][label] = per * n / el
+    oracle.set_threads(n_all)
+    return {"value": legs["fwd_frames_per_s"]["all_threads"], "unit": "frames/s", "cores": n_all, "kind": "oracle",
+            "cpu_model": cpu_model(), "legs": legs,
+            "sample": "FP64 oracle, OpenMP over Gaussians and tiles; value: the full headline frame (projection of "
+                      "1M Gaussians + all 640x480 pixels) on %d threads; legs on %d threads and on 1: that frame, "
+                      "the 500k / 256x256 forward + L2 adjoint + backward step, and views 0-7 of the 64-view "
+                      "batch (one per scene); each leg >= %.0f s" % (n_all, n_all, leg_seconds)}
 
 
 def copy_calibration(dev):
@@ -426,68 +599,96 @@ def main():
     dev = torch.device("cuda:0")
     if args.profile_fwd_bwd:
         log("fwd+bwd only: 256x256, 500k Gaussians")
-        ms = bench_fwd_bwd(args, dev, args.steps)
+        ms, _ = bench_fwd_bwd(args, dev, args.steps, want_pairs=False)
         print(json.dumps({"fwd_bwd_256x256_500k_ms": ms, "steps": args.steps, "warmup": args.warmup}), flush=True)
+        return
+    if args.profile_batched:
+        log("batched only: 64 views x 256x256, 8 scenes")
+        res = bench_batched(args, dev, args.steps, want_pairs=False)
+        print(json.dumps({k: v for k, v in res.items() if k != "roofline"}), flush=True)
+        return
+    if args.profile_avatars:
+        log("avatars only: 1M room + 8 x 50k avatars, 16 views x 640x480")
+        res = bench_avatars(args, dev, args.steps, want_pairs=False)
+        print(json.dumps({k: v for k, v in res.items() if not k.startswith("roofline")}), flush=True)
         return
     if args.copy_calib:
         log("copy calibration: 512 MiB x 3")
         copy_calibration(dev)
     log("forward: 640x480, 1M Gaussians, SH3")
-    ms, info, _ = bench_forward(args, dev, timer_steps=max(5, args.steps // 2))
+    ms, info = bench_forward(args, dev)
     fps = 1e3 / ms
     st = info["stage_ms"]
-    extras = {"stage_ms": st, "N": info["N"], "visible": info["n_vis"], "tile_instances": info["K"],
-              "sort_passes": info["sort_passes"],
-              "stage_hbm_frac": {k: info["alg_bytes"][k] / (st[k] * 1e-3) / 1e9 / HBM_PEAK_GBS for k in st}}
+    counts = info["counts"]
+    want_pairs = not args.profile
+    if want_pairs:
+        from paper_2604_12626_amd import synth
+        c1 = synth.config(1)
+        counts["pairs"] = oracle_pairs([(c1["segments"][0], c1["cams"][0], c1["W"], c1["H"])])
+        pair_src = "oracle count of evaluated pairs, same frame"
+    else:
+        counts["pairs"] = int(info["n_contrib_sum"])
+        pair_src = "lower bound: sum of n_contrib over pixels"
+    _, stages_alg = stage_roofline(counts)
+    extras = {"stage_ms": st, "eager_fps": 1e3 / info["ms_eager"], "N": counts["N"], "visible": counts["n_vis"],
+              "tile_instances": counts["K"],
+              "stage_hbm_frac": {k: stages_alg[k]["bytes"] / (st[k] * 1e-3) / 1e9 / HBM_PEAK_GBS for k in st},
+              "frame_roofline": roofline_block(counts, ms, pair_src)}
     if not args.profile and not args.no_extras:
         steps2 = max(5, args.steps // 5)
         log("fwd+bwd: 256x256, 500k Gaussians")
-        extras["fwd_bwd_256x256_500k_fps"] = 1e3 / bench_fwd_bwd(args, dev, steps2)
+        ms_fb, roof_fb = bench_fwd_bwd(args, dev, steps2)
+        extras["fwd_bwd_256x256_500k_fps"] = 1e3 / ms_fb
+        extras["fwd_bwd_roofline"] = roof_fb
         log("batched vs plain: 64 views x 256x256, 8 scenes")
-        ms_b, ms_p, nv, kb, best = bench_batched(args, dev, steps2)
-        extras["batched_64x256x256_8scenes_fps"] = nv * 1e3 / ms_b
-        extras["plain_64x256x256_8scenes_fps"] = nv * 1e3 / ms_p
-        extras["batched_tile_instances"] = kb
-        extras["batched_composite_groups_per_cu"] = best
+        rb = bench_batched(args, dev, steps2)
+        nv = rb["n_views"]
+        extras["batched_64x256x256_8scenes_fps"] = nv * 1e3 / rb["ms_batched"]
+        extras["plain_64x256x256_8scenes_fps"] = nv * 1e3 / rb["ms_plain"]
+        extras["batched_eager_fps"] = nv * 1e3 / rb["ms_batched_eager"]
+        extras["plain_eager_fps"] = nv * 1e3 / rb["ms_plain_eager"]
+        extras["batched_composite_groups_per_cu"] = rb["groups_per_cu"]
+        extras["batched_roofline"] = rb["roofline"]
         log("avatars: 1M room + 8 x 50k avatars, 16 views x 640x480")
-        ms_a, ms_ab, nva, lbs_ms, n_av = bench_avatars(args, dev, steps2)
-        extras["avatars_16x640x480_fwd_fps"] = nva * 1e3 / ms_a
-        extras["avatars_16x640x480_fwd_bwd_fps"] = nva * 1e3 / ms_ab
-        extras["lbs_400k_fixed_ms"] = lbs_ms["fixed"]
-        extras["lbs_400k_clip_ms"] = lbs_ms["clip"]
-        extras["lbs_400k_clip_hbm_frac"] = n_av * 96 / (lbs_ms["clip"] * 1e-3) / 1e9 / HBM_PEAK_GBS
+        ra = bench_avatars(args, dev, steps2)
+        nva = ra["n_views"]
+        extras["avatars_16x640x480_fwd_fps"] = nva * 1e3 / ra["ms"]
+        extras["avatars_16x640x480_fwd_eager_fps"] = nva * 1e3 / ra["ms_eager"]
+        extras["avatars_16x640x480_fwd_bwd_fps"] = nva * 1e3 / ra["ms_bwd"]
+        extras["avatars_fwd_roofline"] = ra["roofline_fwd"]
+        extras["avatars_fwd_bwd_roofline"] = ra["roofline_fwd_bwd"]
+        extras["lbs_400k_fixed_ms"] = ra["lbs_ms"]["fixed"]
+        extras["lbs_400k_clip_ms"] = ra["lbs_ms"]["clip"]
+        extras["lbs_400k_clip_hbm_frac"] = ra["n_av"] * 96 / (ra["lbs_ms"]["clip"] * 1e-3) / 1e9 / HBM_PEAK_GBS
         log("sensor hand-off: 16 views x 640x480 with a mesh pass")
         ms_s, frac_s = bench_sensor(args, dev, steps2)
         extras["sensor_16x640x480_mesh_ms"] = ms_s
         extras["sensor_16x640x480_mesh_hbm_frac"] = frac_s
         log("capsule queries: 4096 agents x 8 avatars")
         extras["capsule_queries_4096x184_ms"] = bench_capsules(args, dev, steps2)
-    cpu, pairs = None, None
+    cpu = None
     if not args.profile and not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        cpu, pairs = cpu_baseline()
-    # roofline of the dominant kernel (compositing: plain FP32 VALU work per
-    # evaluated pair, the pair count taken from the oracle's render of the same
-    # frame; without it, the composited entries n_contrib summed over pixels,
-    # a lower bound)
-    pair_src = "oracle count of evaluated pairs, same frame"
-    if pairs is None:
-        pairs = int(info["n_contrib_sum"])
-        pair_src = "lower bound: sum of n_contrib over pixels"
+        cpu = cpu_baseline()
+    # roofline of the dominant kernel: compositing, plain FP32 VALU work per
+    # evaluated pair (the pair count from the oracle's render of the same
+    # frame), its duration from the events around its launches in the timed loop
+    pairs = counts["pairs"]
     t_comp = st["composite"] * 1e-3
     achieved = pairs * FLOPS_PER_PAIR / t_comp / 1e12
     traffic, traffic_src = counter_traffic()
-    roof = {"bound": "alu", "kernel": "composite_kernel", "achieved": achieved, "peak": FP32_NONPACKED_TFLOPS,
-            "unit": "TFLOP/s", "frac": achieved / FP32_NONPACKED_TFLOPS, "traffic": traffic,
+    roof = {"bound": "alu", "kernel": "composite_kernel", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic,
             "traffic_source": traffic_src, "pairs": pairs, "pairs_source": pair_src,
             "flops_per_pair": FLOPS_PER_PAIR, "exp_per_pair": 1, "avg_launch_ms": st["composite"],
-            "alg_bytes_per_launch": info["alg_bytes"]["composite"],
-            "frac_of_packed_peak": achieved / FP32_PACKED_TFLOPS}
+            "alg_bytes_per_launch": stages_alg["composite"]["bytes"],
+            "frac_of_nonpacked_peak": achieved / FP32_NONPACKED_TFLOPS}
     out = {"metric": "frames/s 640x480 1M-Gaussian SH3: fwd, fwd+bwd, batched vs plain", "value": fps,
            "unit": "frames/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
            "data": "synthetic (seeded room-shaped 3DGS scene; no dataset)",
-           "config": {"workload": "room1M_640x480_sh3: 1 view, 1M Gaussians, SH degree 3, forward",
+           "config": {"workload": "room1M_640x480_sh3: 1 view, 1M Gaussians, SH degree 3, forward frame "
+                                  "(projection, binning, compositing) replayed from one HIP graph",
                       "global_batch": 1, "parallelism": "none (1 GPU)"},
            "roofline": roof, "extras": extras}
     if cpu is not None:

@@ -74,6 +74,8 @@ def _load():
     lib.or_lbs.argtypes = [i64, P, P, P, P, P, P, i32, P, P]
     lib.or_lbs_backward.argtypes = [i64, P, P, P, P, P, P, i32, P, P, P, P, P]
     lib.or_version.restype = i32
+    lib.or_set_threads.argtypes = [i32]
+    lib.or_get_threads.restype = i32
     lib.or_cov3d.argtypes = [i64, P, P, P]
     _ = f64
     _lib = lib
@@ -215,6 +217,14 @@ def render_view(proj, prm, want_cands=True):
     pairs = np.zeros(1, np.int64)
     lib.or_render_view(len(proj), _p(proj), _p(prm), _p(img), _p(ncand), _p(flags), _p(cands), _p(pairs))
     return img, ncand, flags, cands, int(pairs[0])
+
+
+def set_threads(n):
+    """Number of OpenMP threads of the oracle's loops; returns the previous one."""
+    lib = _load()
+    prev = int(lib.or_get_threads())
+    lib.or_set_threads(int(n))
+    return prev
 
 
 def concat_segments(segs):

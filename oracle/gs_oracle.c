@@ -716,17 +716,22 @@ typedef struct {
 
 enum { OUT_SKIP = 0, OUT_STOP = 1, OUT_COMP = 2 };
 
-/* Bound on the relative error of alpha as an FP32 implementation evaluates
- * it from the same record at the same pixel.  The exponent is a sum of terms
- * of total magnitude S = |A| dx^2 / 2 + |C| dy^2 / 2 + |B dx dy|; the pixel
+/* Bound on the error of log(alpha) as an FP32 implementation evaluates it
+ * from the same record at the same pixel.  The exponent is a sum of terms of
+ * total magnitude S = |A| dx^2 / 2 + |C| dy^2 / 2 + |B dx dy|; the pixel
  * offsets, the products and the sum each round to 2^-24 of a partial sum
  * (plus a rescaling of the conic for a base-2 exponential), so its absolute
- * error is a few units of 2^-24 S, which is alpha's relative error; the
- * exponential, the opacity product and the clamp add a few units of 2^-24.
- * For a needle-shaped Gaussian far along its axis S exceeds |P| by orders of
- * magnitude, and so does this bound the fixed window d_skip. */
+ * error is a few units of 2^-24 S; the exponential, the opacity product and
+ * the clamp add a few units of 2^-24.  For a needle-shaped Gaussian far along
+ * its axis S exceeds |P| by orders of magnitude, and so does this bound the
+ * fixed window d_skip.  Windows are therefore taken on log(alpha):
+ * |log(alpha / alpha_min)| <= log(1 + d_skip) + this bound. */
 #define OR_FP32_ROUNDINGS 16.0
 static double fp32_alpha_err(double S) { return OR_FP32_ROUNDINGS * 0x1p-24 * (S + 1.0); }
+
+/* the skip window of an entry on log(alpha), and whether alpha lies in it */
+static double skip_window(const oprm *p, double err) { return log1p(p->d_skip) + err; }
+static int in_skip_window(double a, double amin, double w) { return a > 0.0 && fabs(log(a / amin)) <= w; }
 
 static double exponent_terms(double A, double B, double C, double dx, double dy)
 {
@@ -748,7 +753,7 @@ static void entry_alpha(const octx *cx, int j, double *alpha, double *err, doubl
     int cl = 0;
     if (a > cx->p->alpha_max) {
         /* clamped on both sides: the FP32 value is the clamp constant itself */
-        if (err && a >= cx->p->alpha_max * (1.0 + *err)) *err = 0.0;
+        if (err && a >= cx->p->alpha_max * exp(*err)) *err = 0.0;
         a = cx->p->alpha_max;
         cl = 1;
     }
@@ -801,7 +806,7 @@ static void comp_rec(const octx *cx, int j, ostate s, int flips, int used, ocand
         const int skip = a < p->alpha_min;
         const int stop = Tn < p->t_min;
         const int primary = skip ? OUT_SKIP : (stop ? OUT_STOP : OUT_COMP);
-        const int amb_skip = fabs(a - p->alpha_min) <= (p->d_skip + ea) * p->alpha_min;
+        const int amb_skip = in_skip_window(a, p->alpha_min, skip_window(p, ea));
         const int amb_stop = fabs(Tn - p->t_min) <= (p->d_stop + next_eT(s.eT, a, ea)) * p->t_min;
         if (amb_skip || (amb_stop && !skip)) cb->saw_amb = 1;
         if (flips > 0) {
@@ -1027,8 +1032,8 @@ static void rect_flags(const oprm *pp, int64_t n, const double *proj, uint8_t *f
                         const double ddx = px + 0.5 - r[1], ddy = py + 0.5 - r[2];
                         double P = -0.5 * (r[4] * ddx * ddx + r[6] * ddy * ddy) - r[5] * ddx * ddy;
                         if (P > 0.0) P = 0.0;
-                        const double win = p.d_skip + fp32_alpha_err(exponent_terms(r[4], r[5], r[6], ddx, ddy));
-                        if (r[7] * exp(P) >= p.alpha_min * (1.0 - win)) flags[(size_t)py * p.W + px] |= 1;
+                        const double win = skip_window(&p, fp32_alpha_err(exponent_terms(r[4], r[5], r[6], ddx, ddy)));
+                        if (r[7] * exp(P) >= p.alpha_min * exp(-win)) flags[(size_t)py * p.W + px] |= 1;
                     }
             }
     }
@@ -1079,7 +1084,8 @@ void or_render_view(int64_t n, const double *proj, const double *prm, double *im
          * stops (their order decides the result) */
         for (int py = ty * p.tile; py < (ty + 1) * p.tile && py < p.H; ++py)
             for (int px = tx * p.tile; px < (tx + 1) * p.tile && px < p.W; ++px) {
-                double T_ = 1.0, zlast = -1.0;
+                double T_ = 1.0, zlast = -1.0, alast = 0.0, Tlast = 1.0;
+                const double *clast = NULL;
                 int j = 0, tie = 0;
                 for (; j < len; ++j) {
                     const double ddx = px + 0.5 - ents[j].u, ddy = py + 0.5 - ents[j].v;
@@ -1088,11 +1094,24 @@ void or_render_view(int64_t n, const double *proj, const double *prm, double *im
                     double a = ents[j].o * exp(P);
                     if (a > p.alpha_max) a = p.alpha_max;
                     const double win =
-                        p.d_skip + fp32_alpha_err(exponent_terms(ents[j].A, ents[j].B, ents[j].C, ddx, ddy));
-                    if (a < p.alpha_min * (1.0 - win)) continue;
-                    if (zlast > 0.0 && fabs(ents[j].z - zlast) <= p.d_tie * (ents[j].z > zlast ? ents[j].z : zlast))
-                        tie = 1;
+                        skip_window(&p, fp32_alpha_err(exponent_terms(ents[j].A, ents[j].B, ents[j].C, ddx, ddy)));
+                    if (a < p.alpha_min * exp(-win)) continue;
+                    if (zlast > 0.0 && fabs(ents[j].z - zlast) <= p.d_tie * (ents[j].z > zlast ? ents[j].z : zlast)) {
+                        /* swapping two adjacent entries changes the colour by exactly
+                         * T a1 a2 (c1 - c2) (the depth likewise), and leaves the
+                         * transmittance after both unchanged; it matters when that
+                         * can reach a tenth of the tolerance, or when the first of
+                         * the two may stop the pixel */
+                        double dc = fabs(ents[j].z - zlast);
+                        for (int ch = 0; ch < 3; ++ch) dc = fmax(dc, fabs(ents[j].rgb[ch] - clast[ch]));
+                        const double effect = Tlast * alast * a * dc;
+                        const int near_stop = Tlast * (1.0 - fmax(a, alast)) < p.t_min * 1.01;
+                        if (effect > 0.1 * p.img_tol || near_stop) tie = 1;
+                    }
                     zlast = ents[j].z;
+                    alast = a;
+                    clast = ents[j].rgb;
+                    Tlast = T_;
                     if (a < p.alpha_min) continue;
                     const double Tn = T_ * (1.0 - a);
                     if (Tn < p.t_min) {
@@ -1130,7 +1149,8 @@ static void atomic_add(double *p, double v)
 typedef struct {
     int j, clamped;
     double a, T, G, dx, dy;
-    double err; /* relative window of this alpha's skip decision: d_skip + its FP32 rounding bound */
+    double err; /* bound on the FP32 rounding error of log(alpha) */
+    double win; /* window of its skip decision on log(alpha) */
 } ocomp;
 
 static void adjoint_pixel(const oprm *p, const double *proj, const int64_t *ent, const ocomp *cc, int nc,
@@ -1172,17 +1192,22 @@ static void pixel_alpha(const oprm *p, const double *proj, int64_t gi, double cx
     const double *r = proj + OR_PROJ_STRIDE * gi;
     e->a = e->G = e->dx = e->dy = 0.0;
     e->clamped = 0;
-    e->err = p->d_skip;
+    e->err = 0.0;
+    e->win = skip_window(p, 0.0);
     if (r[0] == 0.0) return;
     e->dx = cx - r[1];
     e->dy = cy - r[2];
-    e->err = p->d_skip + fp32_alpha_err(exponent_terms(r[4], r[5], r[6], e->dx, e->dy));
+    e->err = fp32_alpha_err(exponent_terms(r[4], r[5], r[6], e->dx, e->dy));
+    e->win = skip_window(p, e->err);
     double P = -0.5 * (r[4] * e->dx * e->dx + r[6] * e->dy * e->dy) - r[5] * e->dx * e->dy;
     if (P > 0.0) P = 0.0;
     e->G = exp(P);
     e->a = r[7] * e->G;
     if (e->a > p->alpha_max) {
-        if (e->a >= p->alpha_max * (1.0 + e->err)) e->err = p->d_skip; /* the clamp constant on both sides */
+        if (e->a >= p->alpha_max * exp(e->err)) { /* the clamp constant on both sides */
+            e->err = 0.0;
+            e->win = skip_window(p, 0.0);
+        }
         e->a = p->alpha_max;
         e->clamped = 1;
     }
@@ -1212,19 +1237,19 @@ static int branch_from_image(const oprm *p, const double *proj, const int64_t *e
     }
     /* skip decisions inside the window, nearest the threshold first */
     for (int j = 0; j + 1 < nc; ++j) {
-        const double m = fabs(all[j].a - amin) / amin;
-        if (m > all[j].err) continue;
+        if (!in_skip_window(all[j].a, amin, all[j].win)) continue;
+        const double m = fabs(log(all[j].a / amin));
         if (namb < OR_MAX_ENUM) {
             amb[namb++] = j;
         } else {
             int far = 0;
             for (int k = 1; k < namb; ++k)
-                if (fabs(all[amb[k]].a - amin) > fabs(all[amb[far]].a - amin)) far = k;
-            if (m < fabs(all[amb[far]].a - amin) / amin) amb[far] = j;
+                if (fabs(log(all[amb[k]].a / amin)) > fabs(log(all[amb[far]].a / amin))) far = k;
+            if (m < fabs(log(all[amb[far]].a / amin))) amb[far] = j;
         }
     }
     if (nc > 0 && all[nc - 1].a < amin) /* the implementation composited it: its FP64 alpha must be in the window */
-        if (fabs(all[nc - 1].a - amin) > all[nc - 1].err * amin) st = 2;
+        if (!in_skip_window(all[nc - 1].a, amin, all[nc - 1].win)) st = 2;
     /* every combination of the ambiguous decisions; the FP64 one first */
     double best = INFINITY;
     int best_combo = 0;
@@ -1268,7 +1293,7 @@ static int branch_from_image(const oprm *p, const double *proj, const int64_t *e
         all[j].T = T;
         cc[n++] = all[j];
         const double Tn = T * (1.0 - all[j].a);
-        eT = next_eT(eT, all[j].a, all[j].err - p->d_skip);
+        eT = next_eT(eT, all[j].a, all[j].err);
         if (Tn < tmin) { /* the FP64 path stops here, the implementation composited it */
             if (fabs(Tn - tmin) > (p->d_stop + eT) * tmin) st = 2;
             else if (st == 0) st = 1;
@@ -1281,15 +1306,15 @@ static int branch_from_image(const oprm *p, const double *proj, const int64_t *e
     for (int j = nc; j < len && !resolved; ++j) {
         ocomp e;
         pixel_alpha(p, proj, ent[j], cx, cy, &e);
-        if (e.a < amin * (1.0 - e.err)) continue; /* skipped on both sides */
+        if (e.a < amin * exp(-e.win)) continue; /* skipped on both sides */
         const double Tn = T * (1.0 - e.a);
         if (Tn < tmin) {
             if (e.a < amin && st == 0) st = 1; /* taken (and stopping) only inside the skip window */
             resolved = 1;
-        } else if (fabs(Tn - tmin) <= (p->d_stop + next_eT(eT, e.a, e.err - p->d_skip)) * tmin) {
+        } else if (fabs(Tn - tmin) <= (p->d_stop + next_eT(eT, e.a, e.err)) * tmin) {
             if (st == 0) st = 1;
             resolved = 1;
-        } else if (e.a < amin * (1.0 + e.err)) {
+        } else if (e.a < amin * exp(e.win)) {
             if (st == 0) st = 1; /* the implementation skipped it inside the window; go on */
         } else {
             st = 2; /* the FP64 path would composite it */
@@ -1797,3 +1822,9 @@ void or_lbs_backward(int64_t n, const float *means, const float *lsc, const floa
 }
 
 int or_version(void) { return 1; }
+
+/* Thread count of the oracle's OpenMP loops (the benchmark's CPU baseline
+ * times it on one thread and on all of them). */
+#include <omp.h>
+void or_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int or_get_threads(void) { return omp_get_max_threads(); }

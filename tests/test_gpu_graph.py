@@ -54,3 +54,79 @@ def test_captured_headline_frame_replays_bit_exact():
         say("  replay %d equals the eager frame" % k)
     assert not cap.overflowed()
     assert np.isfinite(cap.frame.rgb.cpu().numpy()).all()
+
+
+def _replays_equal_eager(cap, ref, n=3, between=None):
+    import torch
+    for k in range(n):
+        for t in (cap.frame.rgb, cap.frame.depth, cap.frame.alpha):
+            t.fill_(-1.0)
+        out = cap.replay()
+        torch.cuda.synchronize()
+        for a, b in zip((out.rgb, out.depth, out.alpha, out.n_contrib), ref):
+            assert torch.equal(a, b), k
+        if between is not None:
+            between()
+            torch.cuda.synchronize()
+    assert not cap.overflowed()
+
+
+def test_captured_batched_frame_replays_bit_exact():
+    """The batched frame (64 views at 256x256 of 8 scenes at 1/20 of their
+    size: scene-major projection, onesweep binning past 4096 tiles, one
+    persistent compositing launch) captured into one graph."""
+    import torch
+    from paper_2604_12626_amd import binding, render
+    binding.load()
+    dev = torch.device("cuda:0")
+    cfg = synth.config(3, scale=0.05)
+    W, H = cfg["W"], cfg["H"]
+    say("graph capture: batched 64 views, 8 scenes")
+    segs = [to_dev(g, dev) for g in cfg["segments"]]
+    cams = torch.from_numpy(cfg["cams"]).to(dev)
+    vs = cfg["view_segs"]
+    eager = render.Renderer(W, H, capacity=1 << 22, device=dev)
+    f = eager.render(segs, cams, vs)
+    ref = [t.clone() for t in (f.rgb, f.depth, f.alpha, f.n_contrib)]
+    cap = render.CapturedRender(render.Renderer(W, H, capacity=1 << 22, device=dev),
+                                [to_dev(g, dev) for g in cfg["segments"]], torch.from_numpy(cfg["cams"]).to(dev), vs)
+    gc.collect()
+    torch.cuda.empty_cache()
+    _replays_equal_eager(cap, ref, between=lambda: eager.render(segs, cams, vs))
+    say("  3 replays equal the eager frame")
+
+
+def test_captured_avatar_frame_with_skinning_replays_bit_exact():
+    """Skinning of the avatar Gaussians and the union frame (room + posed
+    avatars, 4 views) captured together: the graph re-poses the avatars from
+    the current joint matrices on every replay."""
+    import torch
+    from paper_2604_12626_amd import binding as B, render
+    B.load()
+    dev = torch.device("cuda:0")
+    cfg = synth.config(4, scale=0.05)
+    W, H = cfg["W"], cfg["H"]
+    say("graph capture: skinning + room/avatar frame, 4 views")
+    room = to_dev(cfg["segments"][0], dev)
+    av = to_dev(cfg["avatars"], dev)
+    skin = torch.from_numpy(cfg["skin"]).to(dev)
+    n = av["means"].shape[0]
+    posed = {"means": torch.empty(n, 3, device=dev), "cov6": torch.empty(n, 6, device=dev),
+             "opacity": av["opacity"], "sh": av["sh"], "sh_degree": 3}
+    cams = torch.from_numpy(cfg["cams"][:4]).to(dev)
+    vs = cfg["view_segs"][:4]
+
+    def lbs():
+        B.deform_lbs(av["means"], av["log_scales"], av["quats"], av["joint_idx"], av["weights"], av["avatar_of"],
+                     skin, posed["means"], posed["cov6"])
+
+    cap = render.CapturedRender(render.Renderer(W, H, capacity=1 << 22, device=dev), [room, posed], cams, vs,
+                                before=lbs)
+    eager = render.Renderer(W, H, capacity=1 << 22, device=dev)
+    # a new pose: the replay must pick up the new joint matrices
+    skin.copy_(torch.from_numpy(np.ascontiguousarray(cfg["skin"][::-1])).to(dev))
+    lbs()
+    f = eager.render([room, posed], cams, vs)
+    ref = [t.clone() for t in (f.rgb, f.depth, f.alpha, f.n_contrib)]
+    _replays_equal_eager(cap, ref, between=lambda: eager.render([room, posed], cams, vs))
+    say("  3 replays after a pose change equal the eager frame")

@@ -165,12 +165,18 @@ def test_depth_tie_flag_fires_only_for_near_ties_that_both_reach(orc):
     cam = synth.identity_camera(64.0, 64.0, 16.0, 16.0)
     prm = orc.params(32, 32)
     d_tie = float(prm[17])
-    for rel, o2, want in [(0.3 * d_tie, 0.5, True), (20 * d_tie, 0.5, False), (0.3 * d_tie, 0.001, False)]:
+    red, green = [1.0, 0.0, 0.5], [0.0, 1.0, 0.5]
+    # (relative depth gap, second opacity, colours, flagged): the order of a
+    # near tie matters when both reach the threshold and their colours differ
+    # (a swap moves the pixel by T a1 a2 (c1 - c2)); equal colours cannot
+    for rel, o2, cols, want in [(0.3 * d_tie, 0.5, (red, green), True), (20 * d_tie, 0.5, (red, green), False),
+                                (0.3 * d_tie, 0.001, (red, green), False), (0.3 * d_tie, 0.5, (red, red), False)]:
         z1 = 2.0
         z2 = float(F32(z1 * (1.0 + rel)))
+        sh = np.array([[(np.asarray(c) - 0.5) / Y0] for c in cols], F32)
         g = {"means": np.array([[0.01, 0.0, z1], [-0.01, 0.0, z2]], F32),
              "log_scales": np.full((2, 3), math.log(0.1), F32), "quats": np.tile(F32([1, 0, 0, 0]), (2, 1)),
-             "opacity": np.array([0.5, o2], F32), "sh": np.zeros((2, 1, 3), F32), "sh_degree": 0}
+             "opacity": np.array([0.5, o2], F32), "sh": sh, "sh_degree": 0}
         pr, img, ncand, flags, _, _ = orc.render(g, cam, prm, want_cands=False)
         f1 = (flags & 2) != 0
         assert z2 != z1 and (z2 - z1) / z1 == pytest_approx(rel, rel=0.5)
