@@ -87,6 +87,11 @@ typedef enum gs_status {
 #define GS_MAX_SH_DEGREE 3
 #define GS_MAX_CAPACITY ((1LL << 30) - 1) /* tile-instance limit of one gs_bin_sort call */
 #define GS_SEGMENT 64         /* list entries per segment of the segmented backward */
+/* gs_composite_noalloc: most (view, tile) items per call, and the bytes of
+ * its library-owned scratch on each GPU (2048 B of queue counters + a work
+ * order of 8 x GS_NOALLOC_MAX_ITEMS / 8 words) */
+#define GS_NOALLOC_MAX_ITEMS 65536
+#define GS_NOALLOC_SCRATCH_BYTES (2048 + 4 * GS_NOALLOC_MAX_ITEMS)
 
 /* Pinhole camera, world -> camera with OpenCV axes (x right, y down, z
  * forward): p_cam = R p_world + t, R row-major.  Pixel (x, y) samples the
@@ -370,6 +375,25 @@ gs_status gs_composite(const gs_projected *proj, const uint32_t *vals, const uin
                        const uint32_t *tile_order, int32_t n_views, const gs_params *p, void *ws, size_t ws_bytes,
                        float *rgb, float *depth, float *alpha, float *t_final, uint32_t *n_contrib, float *ckpt,
                        size_t ckpt_floats, gs_stream_t stream);
+
+/* gs_composite for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation.
+ * Same arguments, results and errors as gs_composite, without the workspace:
+ * the queue counters and (when tile_order is NULL) the work order live in a
+ * library-owned device array of GS_NOALLOC_SCRATCH_BYTES on each GPU, held
+ * until the process ends.  The call allocates nothing: it clears the
+ * counters with a fill kernel on `stream`, then launches as gs_composite.
+ * Call it with the stream's device current (the array's address is looked
+ * up on the current device, once).
+ * Limit: n_views x tiles per view <= GS_NOALLOC_MAX_ITEMS, else
+ * GS_ERR_UNSUPPORTED before anything is enqueued.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (other streams, other host threads) race and give wrong images;
+ * serialise them. */
+gs_status gs_composite_noalloc(const gs_projected *proj, const uint32_t *vals, const uint32_t *tile_ranges,
+                               const uint32_t *tile_order, int32_t n_views, const gs_params *p, float *rgb,
+                               float *depth, float *alpha, float *t_final, uint32_t *n_contrib, float *ckpt,
+                               size_t ckpt_floats, gs_stream_t stream);
 
 /* Floats of a compositing checkpoint buffer for `capacity` key slots:
  * (capacity / GS_SEGMENT + 1) * (4 * 5 * 64 + GS_SEGMENT + 2) + 1 (0 for

@@ -61,7 +61,7 @@ TUNING_FIELDS = ("composite_groups_per_cu", "sort_partition_keys", "sort_lookbac
 EXPORTS = ["gs_status_string", "gs_last_error", "gs_version", "gs_default_params", "gs_set_tuning", "gs_get_tuning",
            "gs_instance_offsets",
            "gs_deform_lbs", "gs_deform_lbs_backward", "gs_deform_lbs_backward_joints", "gs_forward_kinematics", "gs_deform_lbs_clip", "gs_deform_lbs_clip_backward", "gs_project", "gs_bin_sort_workspace", "gs_tile_order_words", "gs_bin_sort",
-           "gs_composite_workspace", "gs_composite", "gs_checkpoint_floats", "gs_render_backward_workspace", "gs_render_backward",
+           "gs_composite_workspace", "gs_composite", "gs_composite_noalloc", "gs_checkpoint_floats", "gs_render_backward_workspace", "gs_render_backward",
            "gs_sensor_compose", "gs_capsule_queries"]
 
 _lib = None
@@ -107,6 +107,8 @@ def load():
     lib.gs_composite_workspace.argtypes = [i32, ctypes.POINTER(Params)]
     lib.gs_composite.argtypes = [ctypes.POINTER(Projected), P, P, P, i32, ctypes.POINTER(Params), P, sz, P, P, P, P,
                                  P, P, sz, P]
+    lib.gs_composite_noalloc.argtypes = [ctypes.POINTER(Projected), P, P, P, i32, ctypes.POINTER(Params), P, P, P, P,
+                                         P, P, sz, P]
     lib.gs_checkpoint_floats.restype = sz
     lib.gs_checkpoint_floats.argtypes = [i64]
     lib.gs_render_backward_workspace.restype = sz
@@ -121,7 +123,7 @@ def load():
     lib.gs_get_tuning.argtypes = [ctypes.POINTER(Tuning)]
     lib.gs_get_tuning.restype = None
     for f in ("gs_deform_lbs", "gs_deform_lbs_backward", "gs_deform_lbs_backward_joints", "gs_forward_kinematics", "gs_deform_lbs_clip", "gs_deform_lbs_clip_backward",
-              "gs_project", "gs_bin_sort", "gs_composite",
+              "gs_project", "gs_bin_sort", "gs_composite", "gs_composite_noalloc",
               "gs_render_backward", "gs_instance_offsets", "gs_set_tuning", "gs_sensor_compose",
               "gs_capsule_queries"):
         getattr(lib, f).restype = ctypes.c_int
@@ -250,6 +252,17 @@ def composite(rec, vals, ranges, n_views, params, ws, rgb, depth, alpha, t_final
     _check(lib.gs_composite(ctypes.byref(proj), ptr(vals), ptr(ranges), ptr(order), int(n_views), ctypes.byref(params),
                             ptr(ws), ws.numel() * ws.element_size(), ptr(rgb), ptr(depth), ptr(alpha), ptr(t_final),
                             ptr(n_contrib), ptr(ckpt), 0 if ckpt is None else ckpt.numel(), stream_handle()))
+
+
+def composite_noalloc(rec, vals, ranges, n_views, params, rgb, depth, alpha, t_final=None, n_contrib=None, order=None,
+                      ckpt=None):
+    """gs_composite_noalloc: gs_composite with its workspace in the library's
+    own per-GPU scratch (nothing allocated by the call)."""
+    lib = load()
+    proj = Projected(int(rec.shape[0]), None, ptr(rec))
+    _check(lib.gs_composite_noalloc(ctypes.byref(proj), ptr(vals), ptr(ranges), ptr(order), int(n_views),
+                                    ctypes.byref(params), ptr(rgb), ptr(depth), ptr(alpha), ptr(t_final),
+                                    ptr(n_contrib), ptr(ckpt), 0 if ckpt is None else ckpt.numel(), stream_handle()))
 
 
 def render_backward_workspace(n_instances):

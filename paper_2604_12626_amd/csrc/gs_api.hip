@@ -125,6 +125,37 @@ int cu_count() {
     return g_cu_count[dev];
 }
 
+// Library-owned workspace of gs_composite_noalloc: the queue counters, then
+// room for a work order of up to GS_NOALLOC_MAX_ITEMS items.  One copy per GPU
+// (a file-scope device array, zero-initialised when the code object loads),
+// held until the process ends; its device address is looked up once per
+// device, with that device current, and used for every launch argument.
+constexpr size_t kCompCounterBytes = 2048;
+constexpr size_t kNoallocScratchBytes =
+    kCompCounterBytes + (size_t)gs::kOrderQueues * gs::order_stride(GS_NOALLOC_MAX_ITEMS) * sizeof(uint32_t);
+static_assert(kNoallocScratchBytes == GS_NOALLOC_SCRATCH_BYTES, "gs.h states the scratch size");
+static __device__ __align__(256) uint8_t scratch[kNoallocScratchBytes];
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[64] = {nullptr};
+
+hipError_t scratch_address(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -365,8 +396,6 @@ gs_status gs_bin_sort(const gs_projected *proj, int32_t n_views, const gs_params
 
 // ---------------------------------------------------------------------------
 // nine counters (one 128-B line each), then room for a tile work order
-static constexpr size_t kCompCounterBytes = 2048;
-
 size_t gs_composite_workspace(int32_t n_views, const gs_params *p) {
     const size_t words = gs_tile_order_words(n_views, p);
     return words ? kCompCounterBytes + words * sizeof(uint32_t) : 0;
@@ -377,27 +406,37 @@ size_t gs_checkpoint_floats(int64_t capacity) {
     return (size_t)(capacity / (int64_t)gs::kSegment + 1) * (gs::kCkptSlotFloats + gs::kListPerSlot) + 1;
 }
 
-gs_status gs_composite(const gs_projected *proj, const uint32_t *vals, const uint32_t *tile_ranges,
-                       const uint32_t *tile_order, int32_t n_views, const gs_params *p, void *ws, size_t ws_bytes,
-                       float *rgb, float *depth, float *alpha, float *t_final, uint32_t *n_contrib, float *ckpt,
-                       size_t ckpt_floats, gs_stream_t stream) {
-    clear_error();
+}  // extern "C"
+
+namespace {
+
+// gs_composite and gs_composite_noalloc: validation, then the launches with
+// the queue counters and work-order room at `counter` / `own_order`.
+gs_status composite_checks(const gs_projected *proj, const uint32_t *vals, const uint32_t *tile_ranges,
+                           const uint32_t *tile_order, int32_t n_views, const gs_params *p, float *rgb, float *depth,
+                           float *alpha, const float *ckpt) {
     gs_status st;
     if ((st = check_params(p)) != GS_OK) return st;
-    if (!proj || !vals || !tile_ranges || !rgb || !depth || !alpha || !ws)
+    if (!proj || !vals || !tile_ranges || !rgb || !depth || !alpha)
         return fail(GS_ERR_INVALID_ARGUMENT, "NULL argument");
     if (n_views < 1 || n_views > GS_MAX_VIEWS) return fail(GS_ERR_INVALID_ARGUMENT, "n_views=%d", n_views);
     if (proj->n_instances > 0 && (!proj->rec || !aligned(proj->rec, 16)))
         return fail(GS_ERR_INVALID_ARGUMENT, "rec NULL or not 16-byte aligned");
-    if (!aligned(tile_ranges, 8) || !aligned(ws, 4) || !aligned(tile_order, 4) || !aligned(ckpt, 4))
-        return fail(GS_ERR_INVALID_ARGUMENT, "misaligned ranges/order/ws/ckpt");
-    if (ws_bytes < gs_composite_workspace(n_views, p)) return fail(GS_ERR_WORKSPACE_TOO_SMALL, "workspace too small");
+    if (!aligned(tile_ranges, 8) || !aligned(tile_order, 4) || !aligned(ckpt, 4))
+        return fail(GS_ERR_INVALID_ARGUMENT, "misaligned ranges/order/ckpt");
+    return GS_OK;
+}
+
+gs_status composite_launch(const char *who, const gs_projected *proj, const uint32_t *vals,
+                           const uint32_t *tile_ranges, const uint32_t *tile_order, int32_t n_views,
+                           const gs_params *p, uint32_t *counter, uint32_t *own_order, bool clear_counters,
+                           float *rgb, float *depth, float *alpha, float *t_final, uint32_t *n_contrib, float *ckpt,
+                           size_t ckpt_floats, hipStream_t stream) {
     gs::CompositeArgs a = {};
     a.rec = reinterpret_cast<const float4 *>(proj->rec);
     a.vals = vals;
     a.ranges = reinterpret_cast<const uint2 *>(tile_ranges);
-    a.counter = static_cast<uint32_t *>(ws);
-    uint32_t *own_order = reinterpret_cast<uint32_t *>(static_cast<char *>(ws) + kCompCounterBytes);
+    a.counter = counter;
     a.order = tile_order ? tile_order : own_order;
     a.W = p->width;
     a.H = p->height;
@@ -423,10 +462,54 @@ gs_status gs_composite(const gs_projected *proj, const uint32_t *vals, const uin
     // more waves than quadrant work items
     int64_t grid = (int64_t)cu_count() * g_comp_groups.load();
     if (grid > a.n_items) grid = a.n_items;
-    if (!tile_order && (e = gs::launch_tile_order(tile_ranges, a.n_items, own_order, (hipStream_t)stream)) != hipSuccess)
-        return hip_fail(e, "gs_composite");
-    e = gs::launch_composite(a, (int)grid, (hipStream_t)stream);
-    return e == hipSuccess ? GS_OK : hip_fail(e, "gs_composite");
+    if (clear_counters &&
+        (e = gs::launch_fill_u32(counter, 0u, (int64_t)(kCompCounterBytes / sizeof(uint32_t)), stream)) != hipSuccess)
+        return hip_fail(e, who);
+    if (!tile_order && (e = gs::launch_tile_order(tile_ranges, a.n_items, own_order, stream)) != hipSuccess)
+        return hip_fail(e, who);
+    e = gs::launch_composite(a, (int)grid, stream);
+    return e == hipSuccess ? GS_OK : hip_fail(e, who);
+}
+
+}  // namespace
+
+extern "C" {
+
+gs_status gs_composite(const gs_projected *proj, const uint32_t *vals, const uint32_t *tile_ranges,
+                       const uint32_t *tile_order, int32_t n_views, const gs_params *p, void *ws, size_t ws_bytes,
+                       float *rgb, float *depth, float *alpha, float *t_final, uint32_t *n_contrib, float *ckpt,
+                       size_t ckpt_floats, gs_stream_t stream) {
+    clear_error();
+    gs_status st = composite_checks(proj, vals, tile_ranges, tile_order, n_views, p, rgb, depth, alpha, ckpt);
+    if (st != GS_OK) return st;
+    if (!ws) return fail(GS_ERR_INVALID_ARGUMENT, "NULL workspace");
+    if (!aligned(ws, 4)) return fail(GS_ERR_INVALID_ARGUMENT, "misaligned workspace");
+    if (ws_bytes < gs_composite_workspace(n_views, p)) return fail(GS_ERR_WORKSPACE_TOO_SMALL, "workspace too small");
+    uint32_t *own_order = reinterpret_cast<uint32_t *>(static_cast<char *>(ws) + kCompCounterBytes);
+    return composite_launch("gs_composite", proj, vals, tile_ranges, tile_order, n_views, p,
+                            static_cast<uint32_t *>(ws), own_order, false, rgb, depth, alpha, t_final, n_contrib,
+                            ckpt, ckpt_floats, (hipStream_t)stream);
+}
+
+gs_status gs_composite_noalloc(const gs_projected *proj, const uint32_t *vals, const uint32_t *tile_ranges,
+                               const uint32_t *tile_order, int32_t n_views, const gs_params *p, float *rgb,
+                               float *depth, float *alpha, float *t_final, uint32_t *n_contrib, float *ckpt,
+                               size_t ckpt_floats, gs_stream_t stream) {
+    clear_error();
+    gs_status st = composite_checks(proj, vals, tile_ranges, tile_order, n_views, p, rgb, depth, alpha, ckpt);
+    if (st != GS_OK) return st;
+    const int64_t n_items = (int64_t)tiles_x(p) * tiles_y(p) * n_views;
+    if (n_items > GS_NOALLOC_MAX_ITEMS)
+        return fail(GS_ERR_UNSUPPORTED, "gs_composite_noalloc: %lld (view, tile) items exceed its scratch (%d)",
+                    (long long)n_items, GS_NOALLOC_MAX_ITEMS);
+    void *base = nullptr;
+    hipError_t e = scratch_address(&base);
+    if (e != hipSuccess) return hip_fail(e, "gs_composite_noalloc: scratch address");
+    uint32_t *counter = static_cast<uint32_t *>(base);
+    uint32_t *own_order = reinterpret_cast<uint32_t *>(static_cast<char *>(base) + kCompCounterBytes);
+    return composite_launch("gs_composite_noalloc", proj, vals, tile_ranges, tile_order, n_views, p, counter,
+                            own_order, true, rgb, depth, alpha, t_final, n_contrib, ckpt, ckpt_floats,
+                            (hipStream_t)stream);
 }
 
 // ---------------------------------------------------------------------------

@@ -186,7 +186,7 @@ hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec
 // descending list length in chunks of 64 entries (kOrderBins bins, the last
 // holding every list of 63 chunks or more).
 constexpr int kOrderQueues = 8, kOrderBins = 64;
-__host__ __device__ inline int64_t order_stride(int64_t n_items) { return (n_items + kOrderQueues - 1) / kOrderQueues; }
+__host__ __device__ constexpr int64_t order_stride(int64_t n_items) { return (n_items + kOrderQueues - 1) / kOrderQueues; }
 hipError_t launch_tile_order(const uint32_t *ranges, int64_t n_items, uint32_t *order, hipStream_t s);
 hipError_t launch_composite(CompositeArgs a, int grid, hipStream_t s);
 hipError_t launch_backward_tiles(BackwardTileArgs a, int n_cu, hipStream_t s);

@@ -274,3 +274,24 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2", "--steps", "1"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_composite_noalloc_rejects_launches_beyond_its_scratch(lib):
+    """gs_composite_noalloc holds its queue counters and work order in a
+    library-owned per-GPU array sized for GS_NOALLOC_MAX_ITEMS (view, tile)
+    items: a larger launch is refused before anything touches a device."""
+    import ctypes as C
+    from paper_2604_12626_amd import binding as B
+    hdr = open(os.path.join(ROOT, "include", "gs.h")).read()
+    max_items = int(re.search(r"#define GS_NOALLOC_MAX_ITEMS (\d+)", hdr).group(1))
+    assert max_items == 65536
+    p = B.make_params(256, 256)  # 256 tiles per view
+    proj = B.Projected(0, None, None)
+    dummy = C.c_void_p(256)  # never dereferenced: validation fails first
+    n_views = max_items // 256 + 1
+    st = lib.gs_composite_noalloc(C.byref(proj), dummy, dummy, None, n_views, C.byref(p), dummy, dummy, dummy,
+                                  None, None, None, 0, None)
+    assert st == 2 and "scratch" in _err(lib)  # GS_ERR_UNSUPPORTED
+    st = lib.gs_composite_noalloc(C.byref(proj), None, dummy, None, 1, C.byref(p), dummy, dummy, dummy,
+                                  None, None, None, 0, None)
+    assert st == 1  # GS_ERR_INVALID_ARGUMENT: NULL list values
