@@ -597,6 +597,9 @@ def main():
     from paper_2604_12626_amd import binding
     binding.load()
     dev = torch.device("cuda:0")
+    if args.copy_calib:
+        log("copy calibration: 512 MiB x 3")
+        copy_calibration(dev)
     if args.profile_fwd_bwd:
         log("fwd+bwd only: 256x256, 500k Gaussians")
         ms, _ = bench_fwd_bwd(args, dev, args.steps, want_pairs=False)
@@ -612,9 +615,6 @@ def main():
         res = bench_avatars(args, dev, args.steps, want_pairs=False)
         print(json.dumps({k: v for k, v in res.items() if not k.startswith("roofline")}), flush=True)
         return
-    if args.copy_calib:
-        log("copy calibration: 512 MiB x 3")
-        copy_calibration(dev)
     log("forward: 640x480, 1M Gaussians, SH3")
     ms, info = bench_forward(args, dev)
     fps = 1e3 / ms

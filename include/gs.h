@@ -418,17 +418,23 @@ size_t gs_render_backward_workspace(int64_t n_instances);
  *  floats), or NULL.  With them each tile list is walked in segments of
  *  GS_SEGMENT entries (at most 64 per list, the last taking the rest) by a
  *  persistent grid that pops them from a list built here in the buffer's
- *  tail, each segment starting from the state at its end (the last segment,
- *  and every list without checkpoints, from t_final and the background), so
- *  long lists are differentiated in parallel; the two give the same
- *  gradients up to rounding.
+ *  tail (so the buffer is written as well as read), each segment starting
+ *  from the state at its end (the last segment, and every list without
+ *  checkpoints, from t_final and the background), so long lists are
+ *  differentiated in parallel; the two give the same gradients up to
+ *  rounding.  A segment whose checkpoint lies past ckpt_floats (a buffer
+ *  sized for a smaller capacity than the binning's) walks from the end of
+ *  its list instead, adding only its own entries: the same gradients,
+ *  slower.
  *  grads: host array of n_segs gradient descriptors (device pointers),
- *  overwritten.  ws: per-instance screen-space accumulators.
+ *  overwritten.  ws: per-instance screen-space accumulators (FP64, 8-byte
+ *  aligned: a large Gaussian sums thousands of largely cancelling per-pixel
+ *  contributions).
  * Errors: as gs_project, plus GS_ERR_WORKSPACE_TOO_SMALL. */
 gs_status gs_render_backward(const gs_gaussians *segs, int32_t n_segs, const gs_camera *cams, int32_t n_views,
                              const uint32_t *view_seg_mask, const gs_params *p, const gs_projected *proj,
                              const uint32_t *vals, const uint32_t *tile_ranges, const float *t_final,
-                             const uint32_t *n_contrib, const float *ckpt, size_t ckpt_floats, const float *d_rgb,
+                             const uint32_t *n_contrib, float *ckpt, size_t ckpt_floats, const float *d_rgb,
                              const float *d_depth, const float *d_alpha, void *ws, size_t ws_bytes,
                              const gs_gaussians_grad *grads, gs_stream_t stream);
 

@@ -516,7 +516,7 @@ gs_status gs_composite_noalloc(const gs_projected *proj, const uint32_t *vals, c
 // workspace: per-instance screen-space accumulators, then the compacted
 // Gaussian list of one projection launch, then its counters (one per launch)
 static size_t bwd_list_offset(int64_t n_instances) {
-    return ((size_t)(n_instances > 0 ? n_instances : 1) * gs::kG2D * sizeof(float) + 255) & ~(size_t)255;
+    return ((size_t)(n_instances > 0 ? n_instances : 1) * gs::kG2D * sizeof(double) + 255) & ~(size_t)255;
 }
 static size_t bwd_count_offset(int64_t n_instances) {
     return bwd_list_offset(n_instances) +
@@ -532,7 +532,7 @@ size_t gs_render_backward_workspace(int64_t n_instances) {
 gs_status gs_render_backward(const gs_gaussians *segs, int32_t n_segs, const gs_camera *cams, int32_t n_views,
                              const uint32_t *view_seg_mask, const gs_params *p, const gs_projected *proj,
                              const uint32_t *vals, const uint32_t *tile_ranges, const float *t_final,
-                             const uint32_t *n_contrib, const float *ckpt, size_t ckpt_floats, const float *d_rgb,
+                             const uint32_t *n_contrib, float *ckpt, size_t ckpt_floats, const float *d_rgb,
                              const float *d_depth, const float *d_alpha, void *ws, size_t ws_bytes,
                              const gs_gaussians_grad *grads, gs_stream_t stream) {
     clear_error();
@@ -542,7 +542,7 @@ gs_status gs_render_backward(const gs_gaussians *segs, int32_t n_segs, const gs_
     if ((st = check_views(cams, n_views, view_seg_mask, n_segs)) != GS_OK) return st;
     if (!proj || !vals || !tile_ranges || !t_final || !n_contrib || !ws || !grads)
         return fail(GS_ERR_INVALID_ARGUMENT, "NULL argument");
-    if (!aligned(ckpt, 4)) return fail(GS_ERR_INVALID_ARGUMENT, "ckpt not 4-byte aligned");
+    if (!aligned(ckpt, 4) || !aligned(ws, 8)) return fail(GS_ERR_INVALID_ARGUMENT, "ckpt or ws misaligned");
     std::vector<int64_t> off(n_views + 1);
     instance_offsets(segs, n_segs, n_views, view_seg_mask, off.data());
     if (proj->n_instances != off[n_views])
@@ -557,7 +557,9 @@ gs_status gs_render_backward(const gs_gaussians *segs, int32_t n_segs, const gs_
             return fail(GS_ERR_INVALID_ARGUMENT, "segment %d: quats gradient must be 16-byte aligned", s);
     }
     hipStream_t sm = (hipStream_t)stream;
-    float *g2d = static_cast<float *>(ws);
+    // screen-space adjoints accumulate in FP64: a large Gaussian sums thousands
+    // of per-pixel contributions that largely cancel
+    double *g2d = static_cast<double *>(ws);
     uint32_t *list = reinterpret_cast<uint32_t *>(static_cast<char *>(ws) + bwd_list_offset(proj->n_instances));
     uint32_t *counts = reinterpret_cast<uint32_t *>(static_cast<char *>(ws) + bwd_count_offset(proj->n_instances));
     // one fill clears the accumulators and the list counters (the list between them is rewritten)
@@ -578,7 +580,7 @@ gs_status gs_render_backward(const gs_gaussians *segs, int32_t n_segs, const gs_
     b.ckpt_slots = gs::ckpt_slots(ckpt_floats);
     b.ckpt = b.ckpt_slots ? ckpt : nullptr;
     // the work list lives behind the checkpoints (the backward's own part of the buffer)
-    b.seg_list = b.ckpt ? reinterpret_cast<uint32_t *>(const_cast<float *>(ckpt) + b.ckpt_slots * gs::kCkptSlotFloats)
+    b.seg_list = b.ckpt ? reinterpret_cast<uint32_t *>(ckpt + b.ckpt_slots * gs::kCkptSlotFloats)
                         : nullptr;
     b.W = p->width;
     b.H = p->height;

@@ -11,10 +11,11 @@
 // per remaining entry the 64 lanes are summed with DPP adds and the last
 // lane issues the global float atomics (skipped when no lane contributed).
 // With the forward's segment checkpoints a list is cut into segments of
-// kSegment entries, one workgroup each (grid y), every segment's walk
-// starting from the transmittance and the normalised colour still to come
-// that the forward recorded at its end; the last segment of a list starts
-// from t_final and the background, as the whole list does without them.
+// kSegment entries (a multiple of that for lists longer than kMaxSegments
+// segments), popped by a persistent grid, every segment's walk starting from
+// the transmittance and the normalised colour still to come that the forward
+// recorded at its end; the last segment of a list starts from t_final and
+// the background, as the whole list does without them.
 //
 // B2 (per Gaussian of a segment, scene-major): chains the screen-space
 // adjoints of every view that drew the Gaussian through the projection to the
@@ -84,17 +85,26 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
     const float bx0 = (float)qx0 + 0.5f, by0 = (float)qy0 + 0.5f;
     const uint2 range = a.ranges[item];
     const uint32_t L = range.y - range.x;
-    // this segment [seg_lo, seg_hi) of list positions: all of them without
-    // checkpoints, else segment s (the last one of the grid takes the rest of
-    // the list)
-    static_assert(kSegment == 64 && kMaxSegments <= 64, "a middle segment is one chunk; six bits name it");
-    const bool last_seg = !a.seg_list || s + 1u == (uint32_t)kMaxSegments;
-    const uint32_t seg_lo = a.seg_list ? s * kSegment : 0u;
-    // A middle segment is the one chunk from seg_lo: its list values, records
-    // and end checkpoint are requested before the pixel state, so that the
-    // gather overlaps those loads (requests past what the walk needs are
-    // harmless: positions below the list length, slots inside the buffer).
-    const bool pre = !last_seg;
+    // this segment [seg_lo, seg_lo + seg_len) of list positions: all of them
+    // without checkpoints, else segment s of the list's segments (kSegment
+    // entries each, or a multiple of that for lists of more than
+    // kMaxSegments * kSegment entries)
+    static_assert(kSegment == 64 && kMaxSegments <= 64, "six bits name a segment; a chunk is 64 entries");
+    const uint32_t seg_len = a.seg_list ? seg_len_of(L) : L;
+    const uint32_t seg_lo = a.seg_list ? s * seg_len : 0u;
+    const bool last_seg = !a.seg_list || seg_lo + seg_len >= L;
+    // A one-chunk middle segment's list values, records and end checkpoint
+    // are requested before the pixel state, so that the gather overlaps those
+    // loads (requests past what the walk needs are harmless: positions below
+    // the list length, slots inside the buffer).
+    // A middle segment whose end checkpoint lies past the buffer (sized for a
+    // smaller capacity than the binning's) walks from the end of the list,
+    // where t_final and the background give the state, and adds only its own
+    // entries: the same gradients, slower.
+    const uint64_t slot = (range.x + seg_lo + seg_len) / kSegment;
+    const bool from_end = !last_seg && slot >= a.ckpt_slots;
+    const bool middle = !last_seg && !from_end;
+    const bool pre = middle && seg_len == kSegment;
     uint32_t g_pre = 0;
     float4 p0 = make_float4(0.f, 0.f, 0.f, 0.f), p1 = p0, p2 = p0;
     if (pre && seg_lo + lane < L) {
@@ -103,8 +113,7 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
         p1 = a.rec[3 * (size_t)g_pre + 1];
         p2 = a.rec[3 * (size_t)g_pre + 2];
     }
-    const uint64_t slot = (range.x + seg_lo + kSegment) / kSegment;
-    const bool ck_ok = pre && seg_lo + kSegment < L && slot < a.ckpt_slots;
+    const bool ck_ok = middle;
     float ck[kCkptVals] = {1.0f, a.bg0, a.bg1, a.bg2, 0.0f};
     if (ck_ok) {
 #pragma unroll
@@ -131,7 +140,8 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) maxlast = max(maxlast, (uint32_t)__shfl_xor((int)maxlast, off, 64));
     maxlast = min(maxlast, L);
-    const uint32_t seg_end = last_seg ? maxlast : seg_lo + kSegment;  // state known here
+    const uint32_t seg_end = (last_seg || from_end) ? maxlast : seg_lo + seg_len;  // state known here
+    const uint32_t own_hi = from_end ? seg_lo + seg_len : seg_end;  // entries this walk adds
     const uint32_t seg_hi = seg_end < maxlast ? seg_end : maxlast;
     // Per-entry sums over the four quadrant waves go through LDS, 64 list
     // positions at a time, for segments of at most 64 entries (every middle
@@ -141,12 +151,12 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
     // (entry, value).  Otherwise (a longer last segment, or a few long whole
     // lists, where waves walking in step would wait for each other) each
     // wave adds to HBM directly, with no barrier.  Uniform per workgroup.
-    const bool lds_sum = SEG ? (pre || L <= seg_lo + (uint32_t)kSegment) : WLDS;
+    const bool lds_sum = SEG ? (middle || L <= seg_lo + (uint32_t)kSegment) : WLDS;
     if (!lds_sum && seg_lo >= seg_hi) continue;
     uint32_t top = seg_hi;
     if (lds_sum) {
         if (SEG) {
-            top = min(seg_lo + (uint32_t)kSegment, L);
+            top = min(seg_lo + seg_len, L);
         } else {  // the longest walk of the four quadrants
             if (threadIdx.x == 0) s_top = 0u;
             __syncthreads();
@@ -242,6 +252,7 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
                     Sd = al * e1.z + one_m * Sd;
                 }
             }
+            contrib = contrib && pos < own_hi;  // uniform: a walk from the end passes others' entries
             if (__ballot(contrib) == 0ull) continue;
             gu = wave_sum_to_last(gu);
             gv = wave_sum_to_last(gv);
@@ -269,17 +280,17 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
                     atomicAdd(acc + kGZ, gz);
                 }
             } else if (lane == 63) {
-                float *dst = a.g2d + (size_t)__float_as_uint(e2.z) * kG2D;
-                atomicAdd(dst + kGU, gu);
-                atomicAdd(dst + kGV, gv);
-                atomicAdd(dst + kGA, gA);
-                atomicAdd(dst + kGB, gB);
-                atomicAdd(dst + kGC, gC);
-                atomicAdd(dst + kGO, go);
-                atomicAdd(dst + kGR, gr);
-                atomicAdd(dst + kGG, gg);
-                atomicAdd(dst + kGBl, gb);
-                atomicAdd(dst + kGZ, gz);
+                double *dst = a.g2d + (size_t)__float_as_uint(e2.z) * kG2D;
+                atomicAdd(dst + kGU, (double)gu);
+                atomicAdd(dst + kGV, (double)gv);
+                atomicAdd(dst + kGA, (double)gA);
+                atomicAdd(dst + kGB, (double)gB);
+                atomicAdd(dst + kGC, (double)gC);
+                atomicAdd(dst + kGO, (double)go);
+                atomicAdd(dst + kGR, (double)gr);
+                atomicAdd(dst + kGG, (double)gg);
+                atomicAdd(dst + kGBl, (double)gb);
+                atomicAdd(dst + kGZ, (double)gz);
             }
         }
         __builtin_amdgcn_wave_barrier();
@@ -290,7 +301,7 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
             for (int i = threadIdx.x; i < kSegment * kG2D; i += kTilePixels) {
                 const float v = s_acc[i];
                 if (v != 0.0f) {
-                    atomicAdd(a.g2d + (size_t)s_gid[i / kG2D] * kG2D + (i % kG2D), v);
+                    atomicAdd(a.g2d + (size_t)s_gid[i / kG2D] * kG2D + (i % kG2D), (double)v);
                     s_acc[i] = 0.0f;
                 }
             }
@@ -302,7 +313,7 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
 }
 
 // The backward's work list (one workgroup): for every (view, tile) list of
-// L > 0 entries its min(ceil(L / 64), kMaxSegments) segments, as
+// L > 0 entries its ceil(L / seg_len_of(L)) <= kMaxSegments segments, as
 // (item << 6 | segment) in item order, after their count; at most `cap`.
 __global__ void __launch_bounds__(1024) segment_list_kernel(const uint2 *ranges, int64_t n_items, uint32_t *list,
                                                             uint64_t cap) {
@@ -311,8 +322,8 @@ __global__ void __launch_bounds__(1024) segment_list_kernel(const uint2 *ranges,
     const int64_t per = (n_items + 1023) / 1024;
     const int64_t t0 = (int64_t)tid * per, t1 = (t0 + per < n_items) ? t0 + per : n_items;
     auto n_seg = [](uint2 r) -> uint32_t {
-        const uint32_t c = (r.y - r.x + kSegment - 1u) / kSegment;
-        return c < (uint32_t)kMaxSegments ? c : (uint32_t)kMaxSegments;
+        const uint32_t L = r.y - r.x;
+        return (L + seg_len_of(L) - 1u) / seg_len_of(L);
     };
     uint32_t cnt = 0u;
     for (int64_t t = t0; t < t1; ++t) cnt += n_seg(ranges[t]);
@@ -406,10 +417,10 @@ __global__ void __launch_bounds__(256) backward_project_kernel(const BackwardPro
     for (int vi = 0; vi < a.nv; ++vi) {
         const int64_t inst = a.base[vi] + i;
         if (a.tiles_touched[inst] == 0u) continue;
-        const float *g = a.g2d + (size_t)inst * kG2D;
+        const double *g = a.g2d + (size_t)inst * kG2D;
         float gl[kG2D];
 #pragma unroll
-        for (int k = 0; k < kG2D; ++k) gl[k] = g[k];
+        for (int k = 0; k < kG2D; ++k) gl[k] = (float)g[k];
         const float *cam = s_cam + vi * kCamStride;
         ViewProj p;
         // the same FP32 projection as the forward; the instance is known to be

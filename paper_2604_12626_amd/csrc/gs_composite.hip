@@ -148,7 +148,11 @@ __global__ void __launch_bounds__(64 * kWavesPerGroup) composite_kernel(const Co
             // Uniform trip count, four entries per step (their LDS reads are
             // issued together, ahead of the arithmetic); the per-lane skip /
             // stop / done decisions are predicates, with no divergent exits.
-            // T (1 - alpha) is formed as T - alpha T, the weight itself.
+            // T (1 - alpha) is one fused multiply-add, fma(-alpha, T, T): a
+            // single rounding of the exact product, where T - (alpha T) would
+            // round alpha T first and lose up to alpha / (1 - alpha) ulps
+            // (99 at the alpha clamp) -- error the backward's recovery
+            // T_i = T_{i+1} / (1 - alpha_i) would carry over whole lists.
             for (int q = 0; q < n; q += 4) {
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
@@ -157,7 +161,7 @@ __global__ void __launch_bounds__(64 * kWavesPerGroup) composite_kernel(const Co
                     const float p2 = entry_power2(e0.z, e0.w, e1.x, dx, dy);
                     const float al = fminf(amax, e1.y * fast_exp2(p2));
                     const float w = al * T;
-                    const float Tn = T - w;
+                    const float Tn = fmaf(-al, T, T);
                     const bool take = !done && !(al < a.alpha_min);
                     const bool stop = take && (Tn < a.t_min);
                     const bool use = take && !stop;

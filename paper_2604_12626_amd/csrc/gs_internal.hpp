@@ -41,7 +41,7 @@ struct BackwardProjectArgs {
     gs_gaussians_grad grad;
     const gs_camera *cams;
     const uint32_t *tiles_touched;
-    const float *g2d;  // [instances][kG2D]
+    const double *g2d;  // [instances][kG2D]
     int64_t base[kProjViews];
     int32_t view[kProjViews];
     int32_t nv;
@@ -76,11 +76,19 @@ struct CompositeArgs {
 // sum to at most 64 S keys), S taken from the buffer's size.
 constexpr uint32_t kSegment = GS_SEGMENT;
 constexpr int kCkptVals = 5;      // T, then colour r g b and depth behind, over T
-constexpr int kMaxSegments = 64;  // segments per list at most (the last takes the rest)
+constexpr int kMaxSegments = 64;  // segments per list at most
 constexpr uint64_t kCkptSlotFloats = 4 * kCkptVals * 64;
 constexpr uint64_t kListPerSlot = kSegment + 2;
 __host__ __device__ inline uint64_t ckpt_slots(uint64_t floats) {
     return floats > 0 ? (floats - 1) / (kCkptSlotFloats + kListPerSlot) : 0;
+}
+// Segment length of a list of L entries: kSegment, or the multiple of it
+// that keeps the list to kMaxSegments segments (each segment then starts from
+// the checkpoint at its end, which sits on a multiple of kSegment).
+__host__ __device__ inline uint32_t seg_len_of(uint32_t L) {
+    const uint32_t chunks = (L + kSegment - 1) / kSegment;
+    const uint32_t per = (chunks + (uint32_t)kMaxSegments - 1) / (uint32_t)kMaxSegments;
+    return (per > 0 ? per : 1u) * kSegment;
 }
 __host__ __device__ inline uint64_t ckpt_index(uint64_t slot, int quad, int val, int lane) {
     return ((slot * 4 + (uint64_t)quad) * kCkptVals + (uint64_t)val) * 64 + (uint64_t)lane;
@@ -93,7 +101,7 @@ struct BackwardTileArgs {
     const float *t_final;
     const uint32_t *n_contrib;
     const float *d_rgb, *d_depth, *d_alpha;
-    float *g2d;  // [instances][kG2D]
+    double *g2d;  // [instances][kG2D], FP64 accumulators
     const float *ckpt;   // segment checkpoints, or null (one walk per list)
     uint64_t ckpt_slots;
     uint32_t *seg_list;  // (item << 6 | segment) of every segment to walk, after a count

@@ -298,3 +298,52 @@ def test_rasterize_autograd_function(dev, orc):
                        decisions=gpu_decisions(f2, [0], [0], W, H))
     _status_check(ref, W * H)
     grad_check(say, _np(d), ref, SQ_FIELDS)
+
+
+def test_segmented_backward_with_a_short_checkpoint_buffer(dev, orc):
+    """A checkpoint buffer sized for about a third of the frame's keys: the
+    segments whose checkpoints lie past it walk from the end of their list
+    and add only their own entries, so the gradients still equal the
+    whole-list walk's up to rounding, and the oracle's."""
+    import torch
+    from paper_2604_12626_amd import binding as B, render
+    cfg = synth.config(2, scale=0.2)
+    W, H = cfg["W"], cfg["H"]
+    g = dict(cfg["segments"][0])
+    g["log_scales"] = (g["log_scales"] + F32(0.5)).astype(F32)
+    tg = to_dev(g, dev)
+    cams = torch.from_numpy(cfg["cams"]).to(dev)
+    G = [torch.from_numpy(x).to(dev) for x in _random_adjoints(np.random.default_rng(15), 1, H, W)]
+    r = render.Renderer(W, H, capacity=1 << 18, device=dev, checkpoints=True)
+    f = r.render([tg], cams, [[0]])
+    K = int(f.num.item())
+    f.ckpt = f.ckpt[:B.checkpoint_floats(K // 3)]
+    say("short checkpoint buffer: %d keys, checkpoints for %d" % (K, K // 3))
+    full = f.ckpt
+    d_full = {k: v.clone() for k, v in r.backward([tg], cams, [[0]], f, *G)[0].items()}
+    f.ckpt = full[:B.checkpoint_floats(K // 3)]
+    say("short checkpoint buffer: %d keys, checkpoints for %d" % (K, K // 3))
+    d_short = {k: v.clone() for k, v in r.backward([tg], cams, [[0]], f, *G)[0].items()}
+    rw = render.Renderer(W, H, capacity=1 << 18, device=dev, checkpoints=False)
+    fw = rw.render([tg], cams, [[0]])
+    d_whole = rw.backward([tg], cams, [[0]], fw, *G)[0]
+    torch.cuda.synchronize()
+    ref = orc.backward(g, cfg["cams"], orc.params(W, H), *[x.cpu().numpy() for x in G],
+                       decisions=gpu_decisions(f, [0], [0], W, H))
+    _status_check(ref, W * H)
+    res = [grad_check(say, _np(d), ref, SQ_FIELDS, label=lb, check=False)
+           for d, lb in ((d_whole, "whole lists"), (d_full, "all checkpoints"), (d_short, "short buffer"))]
+    # the worst Gaussians' conditioning (kappa of the 2D covariance) and screen size
+    pr = orc.project(g, cfg["cams"][0], orc.params(W, H))
+    for (_, where), lb in zip(res, ("whole", "full", "short")):
+        for k, (i, rel) in where.items():
+            a, b_, c = pr[i, 26], pr[i, 27], pr[i, 28]
+            say("    %s %s: Gaussian %d kappa %.3g radius %d opacity %.3f" % (
+                lb, k, i, (a * c + b_ * b_) / (a * c - b_ * b_), pr[i, 11], pr[i, 7]))
+    for w, _ in res:
+        for k, v in w.items():
+            assert v <= 1e-4, (k, v)
+    # GPU against GPU: the summation order of the float atomics differs
+    for k in SQ_FIELDS:
+        err = float((d_short[k] - d_whole[k]).abs().max() / d_whole[k].abs().max())
+        assert err <= 1e-4, (k, err)
