@@ -15,6 +15,7 @@
  *   gs_bin_sort         tile binning: scan, (tile, depth) key emission, onesweep
  *                       LSD radix sort, per-tile ranges
  *   gs_composite        per-tile front-to-back alpha compositing -> RGB, depth, alpha
+ *                       (gs_composite_noalloc: the same with library-owned scratch)
  *   gs_render_backward  gradients of an image loss w.r.t. the Gaussian parameters
  *
  * Around it, the pieces the paper puts directly before and after the path:
@@ -33,9 +34,11 @@
  * --------------------------------
  *  - Memory.  Every array argument is a DEVICE pointer owned by the caller,
  *    unless the comment says "host".  The library never allocates or frees
- *    device memory and keeps no device state between calls; scratch space is
- *    a caller-provided workspace whose size the *_workspace_bytes() helpers
- *    report.
+ *    device memory; scratch space is a caller-provided workspace whose size
+ *    the *_workspace_bytes() helpers report.  The one exception is
+ *    gs_composite_noalloc, whose workspace is a static device array of
+ *    GS_NOALLOC_SCRATCH_BYTES per GPU (loaded with the code object, held until
+ *    the process ends) for callers that cannot allocate.
  *  - Asynchrony.  Each call validates its arguments on the host, then only
  *    enqueues kernels on `stream` (a hipStream_t; NULL is the default
  *    stream) and returns.  Results are ready when the stream reaches them.
@@ -171,7 +174,13 @@ void gs_default_params(gs_params *p, int32_t width, int32_t height);
  *    the same keys, values and ranges.
  * gs_set_tuning(NULL) restores the defaults; invalid values return
  * GS_ERR_INVALID_ARGUMENT and change nothing.  Meant for an autotuner that
- * times the candidates on the target workload. */
+ * times the candidates on the target workload.
+ * The settings are process-wide: one set shared by every caller, stream and
+ * device of the process (atomic, so reading and writing never tear).  A call
+ * reads them when it enqueues its launches, so a change affects only later
+ * calls, and a captured HIP graph keeps the launch shapes of its capture.
+ * Renderers that want different settings must take turns (set, enqueue,
+ * restore); results never depend on them. */
 typedef struct gs_tuning {
     int32_t composite_groups_per_cu;
     int32_t sort_partition_keys;
