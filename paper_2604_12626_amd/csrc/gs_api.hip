@@ -354,7 +354,7 @@ gs_status gs_project(const gs_gaussians *segs, int32_t n_segs, const gs_camera *
 size_t gs_bin_sort_workspace(int64_t n_instances, int64_t capacity, int32_t n_views, const gs_params *p) {
     if (!p || n_views < 1 || capacity < 1 || n_instances < 0) return 0;
     const int64_t T = (int64_t)tiles_x(p) * tiles_y(p);
-    return gs::make_sort_plan(n_instances, capacity, T * n_views).total;
+    return gs::make_sort_plan(n_instances, capacity, T, n_views).total;
 }
 
 size_t gs_tile_order_words(int32_t n_views, const gs_params *p) {
@@ -382,7 +382,7 @@ gs_status gs_bin_sort(const gs_projected *proj, int32_t n_views, const gs_params
         return fail(GS_ERR_INVALID_ARGUMENT, "keys/ranges/counter need 8-byte, order 4-byte, ws 256-byte alignment");
     const int64_t T = (int64_t)tiles_x(p) * tiles_y(p);
     if (T * n_views > (1ll << 31)) return fail(GS_ERR_UNSUPPORTED, "more than 2^31 tiles");
-    gs::SortPlan plan = gs::make_sort_plan(proj->n_instances, capacity, T * n_views);
+    gs::SortPlan plan = gs::make_sort_plan(proj->n_instances, capacity, T, n_views);
     plan.part_keys = g_sort_part_keys.load();
     plan.lookback = g_sort_lookback.load();
     plan.use_bucket = plan.bucket_ok && g_sort_algorithm.load() == 0;

@@ -176,16 +176,20 @@ struct SortPlan {
     int tile_bits, passes;
     int part_keys, lookback;  // onesweep partition size (4096 / 8192) and look-back window (16 / 32 / 64)
     bool bucket_ok, use_bucket;  // bucket-by-tile path available / chosen (else onesweep)
+    bool windowed;               // bucket path with its tile counters in a window of whole views
+    int64_t T;                   // tiles per view
+    int win_views;               // views per window
     int64_t bucket_blocks;
     int64_t scan_blocks, sort_parts;
     // workspace layout (byte offsets)
-    size_t off_part, off_keys2, off_vals2, off_rows, off_dbase, off_tcnt, off_tcount, off_tstart, off_hist, off_status, off_ticket, total;
+    size_t off_part, off_keys2, off_vals2, off_rows, off_dbase, off_tcnt, off_tcount, off_tover, off_tstart, off_comp,
+        off_compn, off_slist, off_sctl, off_rlist, off_hist, off_status, off_ticket, total;
 };
 
 // launchers (one per translation unit)
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_project(const ProjectArgs &a, hipStream_t s);
-SortPlan make_sort_plan(int64_t n, int64_t capacity, int64_t n_tiles_total);
+SortPlan make_sort_plan(int64_t n, int64_t capacity, int64_t tiles_per_view, int64_t n_views);
 hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec, int TX, int TY, char *ws,
                         uint64_t *keys, uint32_t *vals, uint32_t *ranges, uint32_t *order, int64_t *d_num,
                         int32_t *d_overflow, int n_cu, hipStream_t s);

@@ -30,7 +30,9 @@ constexpr int kMinSortItems = 8;                    // partitions of 4096 or 819
 constexpr int kMinSortPart = kSortBlock * kMinSortItems;
 constexpr int kEmitGrid = 1024;  // emission workgroups at most (grid-stride over scan tiles beyond)
 constexpr int kBucketGrid = 256;  // emission workgroups of the bucket path (rows of the tile counters)
-constexpr int64_t kBucketMaxTiles = 4096;  // the bucket path serves up to this many tiles (all views)
+constexpr int kWinGrid = 1024;    // the same with windowed counters (each a contiguous run of scan tiles)
+constexpr int64_t kBucketMaxTiles = 4096;  // tile counters in LDS up to this many tiles (all views)
+constexpr int64_t kWindowMaxTiles = 1 << 18;  // beyond: windowed counters, up to this many (a 256 MB table)
 constexpr int kRadixBits = 8;
 constexpr int kBins = 1 << kRadixBits;
 constexpr int kMaxPasses = 8;
@@ -183,7 +185,7 @@ constexpr int kLdsTiles = 4096;                     // LDS words for tile counte
 static_assert(kLdsTiles >= kMaxPasses * kHistStride, "the LDS buffer also holds the digit histograms");
 static_assert(kBucketMaxTiles <= kLdsTiles, "bucket tile counters live in LDS");
 
-enum EmitMode { kEmitSortKeys = 0, kEmitCountTiles = 1, kEmitScatterTiles = 2 };
+enum EmitMode { kEmitSortKeys = 0, kEmitCountTiles = 1, kEmitScatterTiles = 2, kEmitCountWin = 3, kEmitScatterWin = 4 };
 
 struct EmitArgs {
     const uint32_t *tt;
@@ -202,6 +204,24 @@ struct EmitArgs {
     uint64_t *bucket;            // [capacity]: (depth bits << 32) | instance, grouped by tile
     int64_t n_tiles;
     const int32_t *d_overflow;
+    // kEmitCountWin / kEmitScatterWin (more tiles than LDS holds): each
+    // workgroup takes a contiguous run of scan tiles and counts in an LDS
+    // window of win_views whole views (T tiles each), a ring that moves
+    // forward with the views; a tile's count leaves the window once, with
+    // its view, by one atomic on tile_count that returns the workgroup's
+    // offset inside the tile's windowed keys (kept in tile_cnt, here
+    // [grid][n_tiles]); keys of views beyond the window (a block drawing
+    // more views than it holds) count on tile_over
+    uint32_t *tile_count;  // [n_tiles]: windowed keys per tile
+    uint32_t *tile_over;   // [n_tiles]: keys counted outside a window (count up, scatter down to 0)
+    int64_t T;             // tiles per view
+    int win_views;         // views per window (kLdsTiles / T)
+    // count modes write, scatter modes read, the live instances of every
+    // (scan tile, wave): comp[(tile * kEmitWaves + wave) * kWaveInst + e] =
+    // {first tile, rect width | height << 16, depth bits, instance}, and
+    // their number in comp_n[tile * kEmitWaves + wave]
+    uint4 *comp;
+    uint32_t *comp_n;
 };
 
 template <int MODE>
@@ -212,15 +232,18 @@ __global__ void __launch_bounds__(kEmitBlock) emit_kernel(const EmitArgs A) {
     uint32_t(*s_h)[kHistStride] = reinterpret_cast<uint32_t(*)[kHistStride]>(s_aux);
     __shared__ uint64_t s_wsum[kEmitWaves];
     // per wave, per list entry: staged record, then the emission layout
-    __shared__ uint32_t s_a0[kEmitWaves][kWaveInst];  // u bits          -> rect origin x0 | y0 << 16
+    __shared__ uint32_t s_a0[kEmitWaves][kWaveInst];  // u bits          -> first tile of the rect
     __shared__ uint32_t s_a1[kEmitWaves][kWaveInst];  // v bits          -> rect width
     __shared__ uint32_t s_a2[kEmitWaves][kWaveInst];  // depth bits
-    __shared__ uint32_t s_a3[kEmitWaves][kWaveInst];  // radius          -> first tile of the view
+    __shared__ uint32_t s_a3[kEmitWaves][kWaveInst];  // radius
     __shared__ uint32_t s_a4[kEmitWaves][kWaveInst];  // view
     __shared__ uint32_t s_a5[kEmitWaves][kWaveInst];  // instance index
     __shared__ uint32_t s_a6[kEmitWaves][kWaveInst];  // first key, relative to the wave's first
     __shared__ uint32_t s_a7[kEmitWaves][kWaveInst];  // tiles_touched
-    if (MODE == kEmitScatterTiles && *A.d_overflow) return;  // nothing consistent to scatter
+    // per wave: the lanes of a 64-key window where a list entry starts (tagged
+    // with the window's number, so no clearing between windows)
+    __shared__ uint32_t s_flag[kEmitWaves][64];
+    if ((MODE == kEmitScatterTiles || MODE == kEmitScatterWin) && *A.d_overflow) return;  // nothing consistent to scatter
     const uint32_t *tt = A.tt;
     const float4 *rec = A.rec;
     const int64_t n = A.n, capacity = A.capacity;
@@ -228,6 +251,8 @@ __global__ void __launch_bounds__(kEmitBlock) emit_kernel(const EmitArgs A) {
     if (MODE == kEmitSortKeys)
         for (int k = threadIdx.x; k < kMaxPasses * kHistStride; k += kEmitBlock) s_aux[k] = 0u;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    s_flag[wave][lane] = 0u;
+    uint32_t tag = 0u;  // windows this wave has walked
     // tile counters in HBM are tile-major: tile t's counts of all workgroups are one row
     uint32_t *my_cnt = A.tile_cnt + blockIdx.x;
     const int64_t cs = A.n_blocks;  // row stride
@@ -236,131 +261,311 @@ __global__ void __launch_bounds__(kEmitBlock) emit_kernel(const EmitArgs A) {
         for (int k = threadIdx.x; k < A.n_tiles; k += kEmitBlock) s_aux[k] = 0u;
     if (MODE == kEmitScatterTiles)  // this workgroup's first slot in every bucket
         for (int k = threadIdx.x; k < A.n_tiles; k += kEmitBlock) s_aux[k] = A.tile_start[k] + my_cnt[k * cs];
-    for (int64_t tile = blockIdx.x; tile < A.n_tiles_scan; tile += A.n_blocks) {  // uniform per workgroup
-        const int64_t base = tile * kScanTile + (int64_t)threadIdx.x * kEmitItems;
-        uint32_t v[kEmitItems];
-        if (base + kEmitItems <= n) {  // one 16-B load (tt is 16-B aligned: caller-owned allocation)
-            const uint4 q = *reinterpret_cast<const uint4 *>(tt + base);
-            v[0] = q.x;
-            v[1] = q.y;
-            v[2] = q.z;
-            v[3] = q.w;
+    if (MODE == kEmitCountTiles || MODE == kEmitScatterTiles) __syncthreads();  // the counters are set
+    constexpr bool WIN = MODE == kEmitCountWin || MODE == kEmitScatterWin;
+    // per wave, the views of its block (two blocks' worth: a wave may be one
+    // block ahead of the others, up to the next window barrier)
+    __shared__ uint32_t s_vmin[2][kEmitWaves], s_vmax[2][kEmitWaves];
+    // window [win_base, win_base + win_tiles) of global tiles (uniform)
+    const uint32_t win_tiles = WIN ? (uint32_t)(A.win_views * A.T) : 0u;
+    // the windowed offsets are workgroup-major: a window's are contiguous
+    uint32_t *my_row = A.tile_cnt + (WIN ? (size_t)blockIdx.x * (size_t)A.n_tiles : 0u);
+    int64_t win_lo = -1;  // first view of the window, -1 before the first
+    uint32_t win_base = 0u, ring_off = 0u;  // first tile of the window, its place in the ring
+    if (MODE == kEmitCountWin)
+        for (int k = threadIdx.x; k < kLdsTiles; k += kEmitBlock) s_aux[k] = 0u;
+    // windowed modes: a contiguous run of scan tiles per workgroup, so its
+    // instances -- and their views -- come in increasing order
+    const int64_t t_first = WIN ? (int64_t)blockIdx.x * A.n_tiles_scan / A.n_blocks : (int64_t)blockIdx.x;
+    const int64_t t_last = WIN ? ((int64_t)blockIdx.x + 1) * A.n_tiles_scan / A.n_blocks : A.n_tiles_scan;
+    const int64_t t_step = WIN ? 1 : A.n_blocks;
+    // the ring slots of views [v0, v1) (v1 - v0 <= win_views): count mode
+    // hands their counts to the tiles (one atomic per nonzero tile returns
+    // this workgroup's offset in the tile) and clears them; scatter mode
+    // loads the workgroup's first slot in each of their tiles
+    auto window_views = [&](int64_t v0, int64_t v1) {
+        const uint32_t Tn = (uint32_t)A.T, m = (uint32_t)(v1 - v0) * Tn;
+        for (uint32_t k = threadIdx.x; k < m; k += kEmitBlock) {
+            const int64_t u = v0 + k / Tn;
+            const uint32_t loc = k % Tn, slot = (uint32_t)(u % A.win_views) * Tn + loc;
+            const uint64_t t = (uint64_t)u * Tn + loc;
+            if (MODE == kEmitCountWin) {
+                const uint32_t c = s_aux[slot];
+                if (c && t < (uint64_t)A.n_tiles) my_row[t] = atomicAdd(A.tile_count + t, c);
+                s_aux[slot] = 0u;
+            } else {
+                s_aux[slot] = t < (uint64_t)A.n_tiles ? A.tile_start[t] + my_row[t] : 0u;
+            }
+        }
+    };
+    static_assert(kEmitItems == 4, "one 16-B tiles_touched load per thread");
+    // the thread's four tiles_touched of a scan tile: one 16-B load (tt is
+    // 16-B aligned: caller-owned allocation), element-wise at the end
+    auto load_tt = [&](int64_t tile) {
+        const int64_t b = tile * kScanTile + (int64_t)threadIdx.x * kEmitItems;
+        if (b + kEmitItems <= n) return *reinterpret_cast<const uint4 *>(tt + b);
+        return make_uint4(b < n ? tt[b] : 0u, b + 1 < n ? tt[b + 1] : 0u, b + 2 < n ? tt[b + 2] : 0u,
+                          b + 3 < n ? tt[b + 3] : 0u);
+    };
+    constexpr bool SCATTER = MODE == kEmitScatterTiles || MODE == kEmitScatterWin;
+    constexpr bool COUNT = MODE == kEmitCountTiles || MODE == kEmitCountWin;
+    // scatter modes read what the count pass kept instead of tiles_touched
+    // and the records; the next block's counts are in flight meanwhile
+    // The other modes keep two blocks in flight: at the start of a block the
+    // records of the next one and the counts of the one after are requested.
+    // The first 16 B of a record (u, v, depth, radius) are requested for
+    // every instance of the lane, a culled one's replaced by the first record
+    // (any record in bounds; never used), so that no request depends on a
+    // branch.  Views increase with the instance, so the views of the wave's
+    // first and last drawn instances bound them all: when they are equal,
+    // no other view is read.
+    auto load_rec = [&](const uint4 &qq, int64_t tile, float4 (&o)[kEmitItems], uint32_t &vf, uint32_t &vl) {
+        const int64_t b = tile * kScanTile + (int64_t)threadIdx.x * kEmitItems;
+        const uint32_t c[kEmitItems] = {qq.x, qq.y, qq.z, qq.w};
+#pragma unroll
+        for (int k = 0; k < kEmitItems; ++k) o[k] = rec[3 * (c[k] ? b + k : 0)];
+        const uint64_t m = __ballot((c[0] | c[1] | c[2] | c[3]) != 0u);
+        vf = vl = 0u;
+        if (m) {  // uniform
+            const int lf = __ffsll((unsigned long long)m) - 1, ll = 63 - __clzll((long long)m);
+            const uint32_t kf = c[0] ? 0u : c[1] ? 1u : c[2] ? 2u : 3u, kl = c[3] ? 3u : c[2] ? 2u : c[1] ? 1u : 0u;
+            const int64_t wb = tile * kScanTile + (int64_t)wave * kWaveInst;
+            const int64_t i_f = wb + lf * kEmitItems + (int64_t)__builtin_amdgcn_readlane(kf, lf);
+            const int64_t i_l = wb + ll * kEmitItems + (int64_t)__builtin_amdgcn_readlane(kl, ll);
+            vf = (uint32_t)__float_as_int(rec[3 * i_f + 2].w);
+            vl = (uint32_t)__float_as_int(rec[3 * i_l + 2].w);
+        }
+    };
+    uint4 q_next = make_uint4(0u, 0u, 0u, 0u), q_next2 = make_uint4(0u, 0u, 0u, 0u);
+    float4 qn[kEmitItems];
+    uint32_t vfn = 0u, vln = 0u;
+    uint32_t cn_next = 0u;
+    if (t_first < t_last) {
+        if (SCATTER) {
+            cn_next = A.comp_n[t_first * kEmitWaves + wave];
         } else {
-#pragma unroll
-            for (int k = 0; k < kEmitItems; ++k) v[k] = (base + k < n) ? tt[base + k] : 0u;
+            q_next = load_tt(t_first);
+            if (t_first + t_step < t_last) q_next2 = load_tt(t_first + t_step);
+            load_rec(q_next, t_first, qn, vfn, vln);
         }
-        // wave-level inclusive scan of the per-thread sums (fits 32 bits:
-        // 256 instances of at most 2^22 tiles), then across the waves in 64 bits
-        uint32_t incl = v[0] + v[1] + v[2] + v[3];
-        const uint32_t own = incl;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t y = __shfl_up(incl, off, 64);
-            if (lane >= off) incl += y;
-        }
-        const uint32_t wave_total = __shfl(incl, 63, 64);
-        // sort keys go to the wave's stretch of the key array (first key kw,
-        // nothing past the capacity); the bucket modes place keys by tile
-        // counters instead and scatter only when the total fits
+    }
+    int par = 0;  // block parity
+    for (int64_t tile = t_first; tile < t_last; tile += t_step, par ^= 1) {  // uniform per workgroup
+        const int64_t cbase = (tile * kEmitWaves + wave) * kWaveInst;
+        uint32_t wave_total = 0u, n_live = 0u;
         int64_t kw = 0, room = INT64_MAX;
-        if (MODE == kEmitSortKeys) {
-            if (lane == 0) s_wsum[wave] = wave_total;
-            __syncthreads();
-            uint64_t wave_excl = 0;
-            for (int k = 0; k < wave; ++k) wave_excl += s_wsum[k];
-            kw = (int64_t)(A.part[tile] + wave_excl);
-            room = capacity - kw;
-        }
-        // live instances of the lane and their place in the wave's list
-        uint32_t start[kEmitItems];
-        uint32_t live_mask = 0u;
-        {
-            uint32_t run = incl - own;
+        if (SCATTER) {
+            n_live = cn_next;
+            if (tile + t_step < t_last) cn_next = A.comp_n[(tile + t_step) * kEmitWaves + wave];
+            uint4 r[kWaveInst / 64];
 #pragma unroll
-            for (int k = 0; k < kEmitItems; ++k) {
-                start[k] = run;
-                if (v[k] && (int64_t)run < room) live_mask |= 1u << k;
-                run += v[k];
+            for (int k = 0; k < kWaveInst / 64; ++k) {
+                const uint32_t e = (uint32_t)(k * 64 + lane);
+                r[k] = e < n_live ? A.comp[cbase + e] : make_uint4(0u, 0u, 0u, 0u);
             }
-        }
-        const uint32_t cnt = __popc(live_mask);
-        uint32_t pos = cnt;
+            // list starts: the exclusive scan of the rect sizes
 #pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t y = __shfl_up(pos, off, 64);
-            if (lane >= off) pos += y;
-        }
-        const uint32_t n_live = __shfl(pos, 63, 64);
-        pos -= cnt;
-        // stage the live instances' records (all loads in flight together)
-        float4 q0[kEmitItems];
-        uint32_t view[kEmitItems];
+            for (int k = 0; k < kWaveInst / 64; ++k) {
+                const uint32_t e = (uint32_t)(k * 64 + lane);
+                const uint32_t w = r[k].y & 0xFFFFu, c = w * (r[k].y >> 16);
+                uint32_t incl = c;
 #pragma unroll
-        for (int k = 0; k < kEmitItems; ++k)
-            if (live_mask & (1u << k)) {
-                q0[k] = rec[3 * (base + k)];
-                view[k] = (uint32_t)__float_as_int(rec[3 * (base + k) + 2].w);
+                for (int off = 1; off < 64; off <<= 1) {
+                    const uint32_t y = __shfl_up(incl, off, 64);
+                    if (lane >= off) incl += y;
+                }
+                if (e < n_live) {
+                    s_a0[wave][e] = r[k].x;
+                    s_a1[wave][e] = w;
+                    s_a2[wave][e] = r[k].z;
+                    s_a5[wave][e] = r[k].w;
+                    s_a6[wave][e] = wave_total + incl - c;
+                }
+                wave_total += __shfl(incl, 63, 64);
             }
+            __builtin_amdgcn_wave_barrier();
+        } else {
+            const int64_t base = tile * kScanTile + (int64_t)threadIdx.x * kEmitItems;
+            // this block's counts and records; the next blocks' in flight meanwhile
+            const uint4 q = q_next;
+            float4 q0[kEmitItems];
 #pragma unroll
-        for (int k = 0; k < kEmitItems; ++k)
-            if (live_mask & (1u << k)) {
-                s_a0[wave][pos] = __float_as_uint(q0[k].x);
-                s_a1[wave][pos] = __float_as_uint(q0[k].y);
-                s_a2[wave][pos] = __float_as_uint(q0[k].z);
-                s_a3[wave][pos] = __float_as_uint(q0[k].w);
-                s_a4[wave][pos] = view[k];
-                s_a5[wave][pos] = (uint32_t)(base + k);
-                s_a6[wave][pos] = start[k];
-                s_a7[wave][pos] = v[k];
-                ++pos;
+            for (int k = 0; k < kEmitItems; ++k) q0[k] = qn[k];
+            const uint32_t vf = vfn, vl = vln;
+            q_next = q_next2;
+            if (tile + 2 * t_step < t_last) q_next2 = load_tt(tile + 2 * t_step);
+            if (tile + t_step < t_last) load_rec(q_next, tile + t_step, qn, vfn, vln);
+            uint32_t v[kEmitItems] = {q.x, q.y, q.z, q.w};
+            // wave-level inclusive scan of the per-thread sums (fits 32 bits:
+            // 256 instances of at most 2^22 tiles), then across the waves in 64 bits
+            uint32_t incl = v[0] + v[1] + v[2] + v[3];
+            const uint32_t own = incl;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t y = __shfl_up(incl, off, 64);
+                if (lane >= off) incl += y;
             }
-        __builtin_amdgcn_wave_barrier();
-        // the list, lanes together: rect, histograms, emission layout
-        for (uint32_t e = lane; e < n_live; e += 64) {
-            const float u = __uint_as_float(s_a0[wave][e]), vv = __uint_as_float(s_a1[wave][e]);
-            const uint32_t depth_bits = s_a2[wave][e];
-            const Rect R = tile_rect(u, vv, (int)s_a3[wave][e], TX, TY);
-            const uint64_t tbase = (uint64_t)s_a4[wave][e] * (uint64_t)(TX * TY);
-            const uint32_t t = s_a7[wave][e];
+            wave_total = __shfl(incl, 63, 64);
+            // sort keys go to the wave's stretch of the key array (first key kw,
+            // nothing past the capacity); the bucket modes place keys by tile
+            // counters instead and scatter only when the total fits
             if (MODE == kEmitSortKeys) {
-#pragma unroll
-                for (int p = 0; p < 4; ++p) hist_add(s_h[p], (depth_bits >> (8 * p)) & 255u, t);
-                for (int ty = R.y0; ty < R.y1; ++ty)
-                    hist_add_row(s_h, passes, tbase + (uint64_t)(ty * TX + R.x0), (uint32_t)(R.x1 - R.x0));
+                if (lane == 0) s_wsum[wave] = wave_total;
+                __syncthreads();
+                uint64_t wave_excl = 0;
+                for (int k = 0; k < wave; ++k) wave_excl += s_wsum[k];
+                kw = (int64_t)(A.part[tile] + wave_excl);
+                room = capacity - kw;
             }
-            s_a0[wave][e] = (uint32_t)R.x0 | ((uint32_t)R.y0 << 16);
-            s_a1[wave][e] = (uint32_t)(R.x1 - R.x0);
-            s_a3[wave][e] = (uint32_t)tbase;
+            // live instances of the lane and their place in the wave's list
+            uint32_t start[kEmitItems];
+            uint32_t live_mask = 0u;
+            {
+                uint32_t run = incl - own;
+#pragma unroll
+                for (int k = 0; k < kEmitItems; ++k) {
+                    start[k] = run;
+                    if (v[k] && (int64_t)run < room) live_mask |= 1u << k;
+                    run += v[k];
+                }
+            }
+            const uint32_t cnt = __popc(live_mask);
+            uint32_t pos = cnt;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t y = __shfl_up(pos, off, 64);
+                if (lane >= off) pos += y;
+            }
+            n_live = __shfl(pos, 63, 64);
+            pos -= cnt;
+            // the views: one for the whole wave, or (at a view boundary) read
+            uint32_t view[kEmitItems];
+#pragma unroll
+            for (int k = 0; k < kEmitItems; ++k) view[k] = vf;
+            if (vf != vl) {  // uniform
+#pragma unroll
+                for (int k = 0; k < kEmitItems; ++k)
+                    if (live_mask & (1u << k)) view[k] = (uint32_t)__float_as_int(rec[3 * (base + k) + 2].w);
+            }
+            // stage the live instances' records
+#pragma unroll
+            for (int k = 0; k < kEmitItems; ++k)
+                if (live_mask & (1u << k)) {
+                    s_a0[wave][pos] = __float_as_uint(q0[k].x);
+                    s_a1[wave][pos] = __float_as_uint(q0[k].y);
+                    s_a2[wave][pos] = __float_as_uint(q0[k].z);
+                    s_a3[wave][pos] = __float_as_uint(q0[k].w);
+                    s_a4[wave][pos] = view[k];
+                    s_a5[wave][pos] = (uint32_t)(base + k);
+                    s_a6[wave][pos] = start[k];
+                    s_a7[wave][pos] = v[k];
+                    ++pos;
+                }
+            __builtin_amdgcn_wave_barrier();
+            // the list, lanes together: rect, histograms, emission layout
+            for (uint32_t e = lane; e < n_live; e += 64) {
+                const float u = __uint_as_float(s_a0[wave][e]), vv = __uint_as_float(s_a1[wave][e]);
+                const uint32_t depth_bits = s_a2[wave][e];
+                const Rect R = tile_rect(u, vv, (int)s_a3[wave][e], TX, TY);
+                const uint64_t tbase = (uint64_t)s_a4[wave][e] * (uint64_t)(TX * TY);
+                const uint32_t t = s_a7[wave][e];
+                if (MODE == kEmitSortKeys) {
+#pragma unroll
+                    for (int p = 0; p < 4; ++p) hist_add(s_h[p], (depth_bits >> (8 * p)) & 255u, t);
+                    for (int ty = R.y0; ty < R.y1; ++ty)
+                        hist_add_row(s_h, passes, tbase + (uint64_t)(ty * TX + R.x0), (uint32_t)(R.x1 - R.x0));
+                }
+                const uint32_t t0 = (uint32_t)(tbase + (uint64_t)(R.y0 * TX + R.x0));
+                const uint32_t w = (uint32_t)(R.x1 - R.x0), h = (uint32_t)(R.y1 - R.y0);
+                s_a0[wave][e] = t0;
+                s_a1[wave][e] = w;
+                if (COUNT) A.comp[cbase + e] = make_uint4(t0, w | (h << 16), depth_bits, s_a5[wave][e]);
+            }
+            if (COUNT && lane == 0) A.comp_n[tile * kEmitWaves + wave] = n_live;
+            __builtin_amdgcn_wave_barrier();
         }
-        __builtin_amdgcn_wave_barrier();
-        // the wave's keys: list starts increase strictly, so the owner of key
-        // j is the last entry whose start is <= j
+        if (WIN) {
+            // the views this block draws: from the first live entry of its
+            // first non-empty wave to the last of its last (views increase
+            // with the instance index)
+            if (lane == 0) {
+                const uint32_t T32 = (uint32_t)A.T;
+                s_vmin[par][wave] = n_live ? (SCATTER ? s_a0[wave][0] / T32 : s_a4[wave][0]) : 0xFFFFFFFFu;
+                s_vmax[par][wave] = n_live ? (SCATTER ? s_a0[wave][n_live - 1] / T32 : s_a4[wave][n_live - 1]) : 0u;
+            }
+            __syncthreads();  // also: every wave is done with the previous block's keys
+            uint32_t vmin = 0xFFFFFFFFu, vmax = 0u;
+            for (int k = 0; k < kEmitWaves; ++k) {
+                vmin = min(vmin, s_vmin[par][k]);
+                vmax = max(vmax, s_vmax[par][k]);
+            }
+            if (vmin != 0xFFFFFFFFu && (win_lo < 0 || (int64_t)vmax >= win_lo + A.win_views)) {
+                // move the window to start at the block's first view (views
+                // never go back): the views that leave are handed over, the
+                // views that enter are set up, the ones in both keep their slots
+                const int64_t old_hi = win_lo < 0 ? (int64_t)vmin : win_lo + A.win_views;
+                const int64_t lo = vmin, hi = lo + A.win_views;
+                if (MODE == kEmitCountWin && win_lo >= 0) window_views(win_lo, old_hi < lo ? old_hi : lo);
+                if (MODE == kEmitScatterWin) window_views(old_hi > lo ? old_hi : lo, hi);
+                win_lo = lo;
+                win_base = (uint32_t)(lo * A.T);
+                ring_off = (uint32_t)(lo % A.win_views) * (uint32_t)A.T;
+                __syncthreads();
+            }
+        }
+        // the wave's keys, 64 at a time: list starts increase strictly, so the
+        // owner of key j is the last entry whose start is <= j.  The entries
+        // that start inside a window [j0, j0 + 64) are the (at most 64) ones
+        // after the owner of key j0 - 1; each marks its first key's lane, and
+        // a lane's owner is that owner plus the marks at or below it.
         if (n_live) {
             const uint32_t lim = (int64_t)wave_total < room ? wave_total : (uint32_t)room;
-            for (uint32_t j = lane; j < lim; j += 64) {
-                int lo = 0, hi = (int)n_live - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (s_a6[wave][mid] <= j) lo = mid;
-                    else hi = mid - 1;
+            int32_t cur = -1;  // owner of key j0 - 1 (uniform)
+            for (uint32_t j0 = 0; j0 < lim; j0 += 64) {
+                ++tag;
+                const uint32_t e = (uint32_t)(cur + 1) + (uint32_t)lane;
+                if (e < n_live) {
+                    const uint32_t st = s_a6[wave][e];
+                    if (st < j0 + 64u) s_flag[wave][st - j0] = tag;
                 }
-                const uint32_t rel = j - s_a6[wave][lo];
-                const uint32_t w = s_a1[wave][lo], xy = s_a0[wave][lo];
-                const uint32_t ty = (xy >> 16) + rel / w, tx = (xy & 0xFFFFu) + rel % w;
-                const uint32_t tg = s_a3[wave][lo] + ty * (uint32_t)TX + tx;  // tile across all views
+                __builtin_amdgcn_wave_barrier();
+                const uint64_t marks = __ballot(s_flag[wave][lane] == tag);
+                const int lo = cur + (int)__popcll(marks & ((2ull << lane) - 1ull));
+                cur += (int)__popcll(marks);
+                const uint32_t j = j0 + (uint32_t)lane;
+                if (j >= lim) continue;
+                const uint32_t rel = j - s_a6[wave][lo], w = s_a1[wave][lo];
+                const uint32_t tg = s_a0[wave][lo] + (rel / w) * (uint32_t)TX + rel % w;  // tile across all views
                 if (MODE == kEmitSortKeys) {
                     const int64_t k = kw + (int64_t)j;
                     A.keys[k] = ((uint64_t)tg << 32) | (uint64_t)s_a2[wave][lo];
                     A.vals[k] = s_a5[wave][lo];
                 } else if (MODE == kEmitCountTiles) {
                     atomicAdd(s_aux + tg, 1u);
-                } else {
+                } else if (MODE == kEmitScatterTiles) {
                     const uint32_t slot = atomicAdd(s_aux + tg, 1u);
                     A.bucket[slot] = ((uint64_t)s_a2[wave][lo] << 32) | (uint64_t)s_a5[wave][lo];
+                } else {
+                    const uint32_t rel = tg - win_base;  // in the window when below win_tiles
+                    uint32_t ring = rel + ring_off;
+                    if (ring >= win_tiles) ring -= win_tiles;
+                    if (MODE == kEmitCountWin) {
+                        if (rel < win_tiles) atomicAdd(s_aux + ring, 1u);
+                        else atomicAdd(A.tile_over + tg, 1u);
+                    } else {
+                        // keys outside the window take the tile's last slots,
+                        // handed out counting the overflow back down to zero
+                        const uint32_t slot = rel < win_tiles
+                                                  ? atomicAdd(s_aux + ring, 1u)
+                                                  : A.tile_start[tg] + A.tile_count[tg] + atomicSub(A.tile_over + tg, 1u) - 1u;
+                        A.bucket[slot] = ((uint64_t)s_a2[wave][lo] << 32) | (uint64_t)s_a5[wave][lo];
+                    }
                 }
             }
         }
-        __syncthreads();  // s_wsum and the lists are reused by the next tile
+        // sort keys: s_wsum is reused by the next tile (the other modes keep
+        // only per-wave state between tiles)
+        if (MODE == kEmitSortKeys) __syncthreads();
     }
     if (MODE == kEmitSortKeys) {
         __syncthreads();
@@ -370,6 +575,10 @@ __global__ void __launch_bounds__(kEmitBlock) emit_kernel(const EmitArgs A) {
     if (MODE == kEmitCountTiles) {
         __syncthreads();
         for (int k = threadIdx.x; k < A.n_tiles; k += kEmitBlock) my_cnt[k * cs] = s_aux[k];
+    }
+    if (MODE == kEmitCountWin && win_lo >= 0) {
+        __syncthreads();
+        window_views(win_lo, win_lo + A.win_views);
     }
 }
 
@@ -704,134 +913,229 @@ hipError_t launch_tile_order(const uint32_t *ranges, int64_t n_items, uint32_t *
                          order);
 }
 
-// exclusive scan of the tile totals (one workgroup): the key count and the
-// overflow flag (count above the capacity), each tile's first key, and the
+// Tile sorts by bucket length (class: list part and kernel): up to
+// kTinySortCap entries one wave (class 4, eight entries per thread), up to
+// kSmallSortCap a 256-thread workgroup (class 3, eight each), up to
+// kMidSortCap a 256-thread workgroup (class 2, sixteen each, four resident
+// per CU), up to kLargeSortCap a 512-thread workgroup (class 1, sixteen
+// each, two per CU), longer ones a 1024-thread workgroup (class 0, sixteen
+// each: kTileSortCap in LDS, beyond that runs and merges).
+constexpr int kTinySortCap = 512;
+constexpr int kSmallSortBlock = 256, kSmallSortCap = 2048, kMidSortCap = 4096;
+constexpr int kLargeSortBlock = 512, kLargeSortCap = 8192;
+constexpr int kTileSortBlock = 1024, kTileSortCap = 16384;
+constexpr int kSortClasses = 5;
+
+// Exclusive scan of the tile totals (one workgroup): the key count and the
+// overflow flag (count above the capacity), each tile's first key, the
 // ranges ([first, end) for tiles with keys, [0, 0) otherwise, and all [0, 0)
-// after an overflow)
-__global__ void __launch_bounds__(1024) bucket_tilescan_kernel(const uint32_t *tile_count, int64_t n_tiles,
-                                                               int64_t capacity, uint32_t *tile_start,
-                                                               uint32_t *ranges, uint32_t *order, int64_t *d_num,
+// after an overflow), the compositing work order, and the lists the tile
+// sorts take their tiles from: sort_list holds the tiles of more than
+// kLargeSortCap keys by descending length (in bins of 1024 keys), then those
+// of the four shorter classes, longest class first; sort_ctl holds the five
+// counts, the number of tiles of more than kTileSortCap keys and of their runs
+// of up to kTileSortCap keys, which run_list holds as {tile, run}.  Counts are read coalesced, a chunk of
+// kScanChunk tiles at a time, into LDS.
+constexpr int kScanChunk = 16384;
+constexpr int kSortBins = 64;
+constexpr int kHugeBins = kSortBins - kTileSortCap / 1024;  // the bins of the tiles longer than kTileSortCap
+// sort_ctl: the five class counts, then the number of tiles longer than
+// kTileSortCap (the first ones of the list) and of their runs
+constexpr int kSortCtlWords = kSortClasses + 2;
+
+// the list bin of a tile: 0 = longest .. kSortBins - 1, then kSortBins +
+// 0 .. 3 for the four shorter classes
+__device__ __forceinline__ uint32_t sort_bin(uint32_t len) {
+    if (len <= (uint32_t)kTinySortCap) return kSortBins + 3;
+    if (len <= (uint32_t)kSmallSortCap) return kSortBins + 2;
+    if (len <= (uint32_t)kMidSortCap) return kSortBins + 1;
+    if (len <= (uint32_t)kLargeSortCap) return kSortBins;
+    const uint32_t k = (len - 1u) >> 10;  // a tile of more than kTileSortCap keys lands below kHugeBins
+    return (uint32_t)(kSortBins - 1) - (k < (uint32_t)(kSortBins - 1) ? k : (uint32_t)(kSortBins - 1));
+}
+
+// One slot per active lane from *counter (lanes in order): one LDS atomic
+// for the wave.
+__device__ __forceinline__ uint32_t wave_append(uint32_t *counter, bool active) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t m = __ballot(active);
+    if (!m) return 0u;  // uniform
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    uint32_t b = 0u;
+    if (lane == leader) b = atomicAdd(counter, (uint32_t)__popcll(m));
+    b = __builtin_amdgcn_readlane(b, leader);
+    return b + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+}
+
+__global__ void __launch_bounds__(1024) bucket_tilescan_kernel(const uint32_t *tile_count, const uint32_t *tile_over,
+                                                               int64_t n_tiles, int64_t capacity, uint32_t *tile_start,
+                                                               uint32_t *ranges, uint32_t *order, uint32_t *sort_list,
+                                                               uint32_t *sort_ctl, uint2 *run_list, int64_t *d_num,
                                                                int32_t *d_overflow) {
+    constexpr int PER = kScanChunk / 1024;
+    __shared__ uint32_t s_runs;
+    __shared__ uint32_t s_c[kScanChunk];
+    __shared__ uint32_t s_st[kScanChunk];  // first keys of the chunk's tiles
     __shared__ uint64_t s_w[16];
     __shared__ uint32_t s_cnt[kOrderQueues][kOrderBins];
+    __shared__ uint32_t s_big[kSortBins + kSortClasses - 1];  // long tiles by bin, then the shorter classes
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t per = (n_tiles + 1023) / 1024;
-    const int64_t t0 = (int64_t)tid * per, t1 = (t0 + per < n_tiles) ? t0 + per : n_tiles;
-    uint64_t sum = 0u;
-    for (int64_t t = t0; t < t1; ++t) sum += tile_count[t];
-    uint64_t incl = sum;
+    const int64_t n_chunks = (n_tiles + kScanChunk - 1) / kScanChunk;
+    // keys per tile: the counted ones, plus those counted outside a window;
+    // s_c[k] = count of tile cb + k (0 past the end), loads in flight together
+    int64_t loaded = -1;
+    auto load_chunk = [&](int64_t cb) {
+        if (loaded == cb) return;  // uniform
+        __syncthreads();
+        uint32_t c[PER];
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint64_t y = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += y;
+        for (int k = 0; k < PER; ++k) {
+            const int64_t t = cb + k * 1024 + tid;
+            c[k] = t < n_tiles ? tile_count[t] + (tile_over ? tile_over[t] : 0u) : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < PER; ++k) s_c[k * 1024 + tid] = c[k];
+        loaded = cb;
+        __syncthreads();
+    };
+    for (int i = tid; i < kOrderQueues * kOrderBins; i += 1024) (&s_cnt[0][0])[i] = 0u;
+    if (tid < kSortBins + kSortClasses - 1) s_big[tid] = 0u;
+    if (tid == 0) s_runs = 0u;
+    // 1. the total, so that the overflow is known before anything is written
+    uint64_t total = 0u;
+    for (int64_t ch = 0; ch < n_chunks; ++ch) {
+        load_chunk(ch * kScanChunk);
+        uint64_t sum = 0u;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) sum += s_c[k * 1024 + tid];
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) sum += __shfl_xor(sum, off, 64);
+        __syncthreads();
+        if (lane == 0) s_w[wave] = sum;
+        __syncthreads();
+        for (int k = 0; k < 16; ++k) total += s_w[k];
     }
-    if (lane == 63) s_w[wave] = incl;
-    __syncthreads();
-    uint64_t run = incl - sum, total = 0u;
-    for (int k = 0; k < 16; ++k) {
-        if (k < wave) run += s_w[k];
-        total += s_w[k];
-    }
-    const bool ovf = total > (uint64_t)capacity;  // then every range is [0, 0)
+    const bool ovf = total > (uint64_t)capacity;  // then every range is [0, 0) and nothing is listed
     if (tid == 0) {
         *d_num = (int64_t)total;
         *d_overflow = ovf ? 1 : 0;
     }
-    for (int64_t t = t0; t < t1; ++t) {
-        const uint32_t c = tile_count[t];
-        tile_start[t] = (uint32_t)run;
-        ranges[2 * t] = (c && !ovf) ? (uint32_t)run : 0u;
-        ranges[2 * t + 1] = (c && !ovf) ? (uint32_t)(run + c) : 0u;
-        run += c;
+    // 2. starts and ranges (each thread PER consecutive tiles), then the bin
+    // counts (consecutive tiles on consecutive lanes: the order's queues and
+    // bins spread over the lanes)
+    uint64_t carry = 0u;
+    for (int64_t ch = 0; ch < n_chunks; ++ch) {
+        const int64_t cb = ch * kScanChunk;
+        load_chunk(cb);
+        uint32_t c[PER];
+        uint64_t sum = 0u;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            c[k] = s_c[tid * PER + k];
+            sum += c[k];
+        }
+        uint64_t incl = sum;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint64_t y = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += y;
+        }
+        __syncthreads();  // s_w of the previous chunk is read
+        if (lane == 63) s_w[wave] = incl;
+        __syncthreads();
+        uint64_t run = carry + incl - sum, chunk_total = 0u;
+        for (int k = 0; k < 16; ++k) {
+            if (k < wave) run += s_w[k];
+            chunk_total += s_w[k];
+        }
+        carry += chunk_total;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            s_st[tid * PER + k] = (uint32_t)run;
+            run += c[k];
+        }
+        __syncthreads();
+        // consecutive tiles on consecutive lanes: coalesced stores
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int64_t t = cb + k * 1024 + tid;
+            if (t < n_tiles) {
+                const uint32_t c1 = s_c[k * 1024 + tid], st = s_st[k * 1024 + tid];
+                const bool has = c1 && !ovf;
+                tile_start[t] = st;
+                reinterpret_cast<uint2 *>(ranges)[t] = has ? make_uint2(st, st + c1) : make_uint2(0u, 0u);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int64_t t = cb + k * 1024 + tid;
+            const uint32_t c1 = ovf ? 0u : s_c[k * 1024 + tid];
+            if (order && t < n_tiles) atomicAdd(&s_cnt[t % kOrderQueues][order_bin(c1)], 1u);
+            const uint32_t bin = sort_bin(c1);
+            if (c1 && bin < (uint32_t)kSortBins) atomicAdd(&s_big[bin], 1u);
+#pragma unroll
+            for (int cl = 0; cl < kSortClasses - 1; ++cl) {
+                const uint64_t m = __ballot(c1 && bin == (uint32_t)(kSortBins + cl));
+                if (lane == 0 && m) atomicAdd(&s_big[kSortBins + cl], (uint32_t)__popcll(m));
+            }
+        }
     }
-    if (!order) return;  // uniform
-    // the work order of the lists just ranged (empty ones after an overflow)
-    for (int i = tid; i < kOrderQueues * kOrderBins; i += 1024) (&s_cnt[0][0])[i] = 0u;
+    // 3. bin starts, then the order and the sort lists
+    if (order) order_bin_starts(s_cnt);
     __syncthreads();
-    for (int64_t t = t0; t < t1; ++t) atomicAdd(&s_cnt[t % kOrderQueues][order_bin(ovf ? 0u : tile_count[t])], 1u);
-    order_bin_starts(s_cnt);
+    if (wave == 0) {
+        const uint32_t b = s_big[lane];
+        uint32_t incl = b;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += y;
+        }
+        s_big[lane] = incl - b;
+        const uint32_t n_huge = __shfl(incl - b, kHugeBins, 64);
+        if (lane == 0) sort_ctl[kSortClasses] = n_huge;
+        if (lane == 63) {
+            // the shorter classes follow the long tiles, in order
+            uint32_t at = incl;
+            sort_ctl[0] = incl;
+            for (int cl = 0; cl < kSortClasses - 1; ++cl) {
+                const uint32_t cnt = s_big[kSortBins + cl];
+                sort_ctl[1 + cl] = cnt;
+                s_big[kSortBins + cl] = at;
+                at += cnt;
+            }
+        }
+    }
+    __syncthreads();
     const int64_t qs = order_stride(n_tiles);
-    for (int64_t t = t0; t < t1; ++t) {
-        const int q = (int)(t % kOrderQueues);
-        order[q * qs + atomicAdd(&s_cnt[q][order_bin(ovf ? 0u : tile_count[t])], 1u)] = (uint32_t)t;
-    }
-}
-
-// Ascending bitonic sort in place in HBM of s[0, n2) (n2 a power of two) by
-// a workgroup of THREADS threads, for buckets too long for LDS.  Each merge
-// starts with the reflected compare (i, block end - 1 - i), so every
-// compare-exchange is ascending and entries at or beyond `lim` act as
-// +infinity without being stored; every step ends with a workgroup barrier.
-__device__ __forceinline__ void compare_exchange_hbm(uint64_t *s, uint32_t i, uint32_t p, uint32_t lim) {
-    if (p >= lim) return;
-    const uint64_t a = s[i], b = s[p];
-    const bool sw = a > b;
-    s[i] = sw ? b : a;
-    s[p] = sw ? a : b;
-}
-
-template <int THREADS>
-__device__ __forceinline__ void bitonic_sort_hbm(uint64_t *s, uint32_t n2, uint32_t lim) {
-    const uint32_t tid = threadIdx.x, half = n2 >> 1;
-    for (uint32_t lk = 1; (1u << lk) <= n2; ++lk) {
-        const uint32_t k = 1u << lk;
-        {
-            const uint32_t lj = lk - 1, j = k >> 1;
-            for (uint32_t t = tid; t < half; t += THREADS) {
-                const uint32_t base = (t >> lj) << lk, r = t & (j - 1);
-                compare_exchange_hbm(s, base + r, base + (k - 1 - r), lim);
+    for (int64_t ch = 0; ch < n_chunks; ++ch) {
+        const int64_t cb = ch * kScanChunk;
+        load_chunk(cb);
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int64_t t = cb + k * 1024 + tid;
+            const bool in = t < n_tiles;
+            const uint32_t c = (ovf || !in) ? 0u : s_c[k * 1024 + tid];
+            if (order && in) {
+                const int q = (int)(t % kOrderQueues);
+                order[q * qs + atomicAdd(&s_cnt[q][order_bin(c)], 1u)] = (uint32_t)t;
             }
-            __syncthreads();
-        }
-        for (int lj = (int)lk - 2; lj >= 0; --lj) {
-            const uint32_t j = 1u << lj;
-            for (uint32_t t = tid; t < half; t += THREADS) {
-                const uint32_t i = ((t >> lj) << (lj + 1)) + (t & (j - 1));
-                compare_exchange_hbm(s, i, i + j, lim);
+            const uint32_t bin = sort_bin(c);
+            uint32_t slot = 0u;
+#pragma unroll
+            for (int cl = 0; cl < kSortClasses - 1; ++cl) {
+                const uint32_t y = wave_append(&s_big[kSortBins + cl], c && bin == (uint32_t)(kSortBins + cl));
+                if (bin == (uint32_t)(kSortBins + cl)) slot = y;
             }
-            __syncthreads();
+            if (c) sort_list[bin < (uint32_t)kSortBins ? atomicAdd(&s_big[bin], 1u) : slot] = (uint32_t)t;
+            if (c > (uint32_t)kTileSortCap) {
+                const uint32_t R = (c + kTileSortCap - 1) / kTileSortCap, r0 = atomicAdd(&s_runs, R);
+                for (uint32_t r = 0; r < R; ++r) run_list[r0 + r] = make_uint2((uint32_t)t, r);
+            }
         }
     }
-}
-
-// Bitonic sort of a bucket in LDS with E = 2^P entries per thread and up to
-// P network steps per LDS round trip.  A group is the E positions
-// base + m * 2^lo (m < E, mask bits lo .. lo+P-1); one pass loads a group
-// into registers, applies the compare-exchanges of the top `b` mask bits (the
-// network's next steps), and stores it back.  Merge k = 2^lk runs its steps
-// bit lk-1 down to bit P in passes of up to P bits, then bits P-1 .. 0 in one
-// pass over E consecutive positions; merges up to E happen in registers
-// right after the bucket is read.  The network is the classic one (merge lk
-// sorts descending where bit lk of the position is set, except the final
-// merge); instead of a direction per compare-exchange, an entry is held
-// bit-complemented while its merge runs descending, so every compare-exchange
-// is ascending, and entries are complemented or restored only where one
-// merge hands over to the next.  LDS slot i + i / E keeps the strided passes
-// free of bank conflicts.  With several waves on one bucket, a pass whose mask
-// stays below bit 6 + P only touches the 64 E positions its wave owns (higher
-// position bits come from the wave index), so two such passes in a row need
-// no workgroup barrier; a bucket sorted by one wave never needs one.
-template <int P>
-__device__ __forceinline__ uint32_t lds_slot(uint32_t i) {
-    return i + (i >> P);
-}
-
-__device__ __forceinline__ void cmp_swap_up(uint64_t &a, uint64_t &b) {
-    const bool sw = a > b;
-    const uint64_t lo = sw ? b : a, hi = sw ? a : b;
-    a = lo;
-    b = hi;
-}
-
-// ascending compare-exchanges along mask bits r = P-1 .. P-B of the group
-template <int P, int B>
-__device__ __forceinline__ void group_steps(uint64_t (&v)[1 << P]) {
-#pragma unroll
-    for (int r = P - 1; r > P - 1 - B; --r) {
-#pragma unroll
-        for (int m = 0; m < (1 << P); ++m)
-            if (!(m & (1 << r))) cmp_swap_up(v[m], v[m | (1 << r)]);
-    }
+    __syncthreads();
+    if (tid == 0) sort_ctl[kSortClasses + 1] = s_runs;
 }
 
 __device__ __forceinline__ void lds_wave_sync() {
@@ -840,140 +1144,292 @@ __device__ __forceinline__ void lds_wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// all-ones when the entry at a position with bit `j` equal to `bit` is held
-// complemented during merge j of a network of 2^ln entries
-__device__ __forceinline__ uint64_t held_mask(int j, int ln, uint32_t bit) {
-    return (j < ln && bit) ? ~0ull : 0ull;
-}
-
-// Sorts the L entries at in[0, L) (n2 = 2^ln >= max(L, 2^P); s holds at
-// least lds_slot<P>(n2) entries) with NT threads (tid < NT; NT = 64 and
-// ONE_WAVE for a wave on its own) and writes key (thi | depth bits) and value
-// (instance) of sorted entry p to keys[p], vals[p].
-template <int NT, int P, bool ONE_WAVE>
-__device__ __forceinline__ void sort_bucket_lds(uint64_t *s, const uint64_t *in, uint32_t L, uint32_t n2, int ln,
-                                                uint64_t thi, uint64_t *keys, uint32_t *vals, uint32_t tid) {
-    constexpr int E = 1 << P;
-    const uint32_t groups = n2 >> P;
-    // merges of 2 .. E in registers.  Input j = m * groups + g takes
-    // position E g + m (any placement is valid; this one reads coalesced).
-    for (uint32_t g = tid; g < groups; g += NT) {
-        uint64_t v[E];
+// Ascending sorting network (bitonic) over N registers, all indices fixed at
+// compile time.
+template <int N>
+__device__ __forceinline__ void sort_regs(uint64_t (&v)[N]) {
 #pragma unroll
-        for (int m = 0; m < E; ++m) {
-            const uint32_t j = (uint32_t)m * groups + g;
-            v[m] = j < L ? in[j] : ~0ull;
-        }
+    for (int k = 2; k <= N; k <<= 1)
 #pragma unroll
-        for (int lk = 1; lk <= P; ++lk) {
-            // hand over from merge lk-1 to merge lk (bit P of the position is bit 0 of g)
+        for (int j = k >> 1; j > 0; j >>= 1)
 #pragma unroll
-            for (int m = 0; m < E; ++m) {
-                const uint32_t cur = lk < P ? ((m >> lk) & 1) : (g & 1u);
-                const uint32_t prev = (m >> (lk - 1)) & 1;
-                v[m] ^= held_mask(lk, ln, cur) ^ (lk > 1 ? held_mask(lk - 1, ln, prev) : 0ull);
-            }
-#pragma unroll
-            for (int lj = lk - 1; lj >= 0; --lj)
-#pragma unroll
-                for (int m = 0; m < E; ++m)
-                    if (!(m & (1 << lj))) cmp_swap_up(v[m], v[m | (1 << lj)]);
-        }
-        const uint32_t base = g << P;
-        if (ln == P) {  // merge P was the final one: nothing is held complemented
-#pragma unroll
-            for (int m = 0; m < E; ++m)
-                if (base + m < L) {
-                    keys[base + m] = thi | (v[m] >> 32);
-                    vals[base + m] = (uint32_t)v[m];
-                }
-        } else {
-            const uint64_t flip = held_mask(P, ln, g & 1u) ^ held_mask(P + 1, ln, (g >> 1) & 1u);
-#pragma unroll
-            for (int m = 0; m < E; ++m) s[lds_slot<P>(base + m)] = v[m] ^ flip;
-        }
-    }
-    int top_prev = P - 1;
-    for (int lk = P + 1; lk <= ln; ++lk) {
-        const bool fin = lk == ln;
-        for (int hi = lk - 1;;) {
-            // mask bits hi-P+1 .. hi; compare-exchanges along the top b of them
-            const bool low = hi == P - 1;
-            const int b = low ? P : (hi - (P - 1) < P ? hi - (P - 1) : P), lo = hi - (P - 1);
-            if (!ONE_WAVE && (hi >= 6 + P || top_prev >= 6 + P))
-                __syncthreads();
-            else
-                lds_wave_sync();
-            top_prev = hi;
-            for (uint32_t g = tid; g < groups; g += NT) {
-                const uint32_t base = ((g >> lo) << (lo + P)) | (g & ((1u << lo) - 1u));
-                uint64_t v[E];
-#pragma unroll
-                for (int m = 0; m < E; ++m) v[m] = s[lds_slot<P>(base + ((uint32_t)m << lo))];
-                if (b == P)
-                    group_steps<P, P>(v);
-                else if (b == 1)
-                    group_steps<P, 1>(v);
-                else if (b == 2)
-                    group_steps<P, (P > 2 ? 2 : 1)>(v);
-                else
-                    group_steps<P, (P > 3 ? 3 : 1)>(v);
-                if (fin && low) {  // E consecutive sorted entries, none held complemented
-#pragma unroll
-                    for (int m = 0; m < E; ++m)
-                        if (base + m < L) {
-                            keys[base + m] = thi | (v[m] >> 32);
-                            vals[base + m] = (uint32_t)v[m];
-                        }
-                } else {
-                    // the last pass of a merge hands over to the next merge
-                    const uint64_t flip = low ? held_mask(lk, ln, (base >> lk) & 1u) ^
-                                                    held_mask(lk + 1, ln, (base >> (lk + 1)) & 1u)
-                                              : 0ull;
-#pragma unroll
-                    for (int m = 0; m < E; ++m) s[lds_slot<P>(base + ((uint32_t)m << lo))] = v[m] ^ flip;
+            for (int i = 0; i < N; ++i) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const uint64_t x = v[i], y = v[l];
+                    const bool sw = ((i & k) == 0) ? (x > y) : (x < y);
+                    v[i] = sw ? y : x;
+                    v[l] = sw ? x : y;
                 }
             }
-            if (low) break;
-            hi -= b;
+}
+
+// Block merge sort of the L entries at in[0, L) (L <= NT * ITEMS; entries
+// distinct and below ~0, which pads) with NT threads (tid < NT; NT = 64 and
+// ONE_WAVE for a wave on its own).  The smallest power-of-two number of
+// threads that holds L takes ITEMS consecutive entries each and sorts them
+// in registers; then sorted runs are merged pairwise, each thread finding
+// where its ITEMS outputs start on the merge path of its pair by a binary
+// search in LDS and merging them into registers, until one run is left.  s
+// holds n + n / ITEMS entries (n = NT * ITEMS; slot i + i / ITEMS keeps the
+// per-thread rows free of bank conflicts).  Writes key (thi | depth bits) and
+// value (instance) of sorted entry p to keys[p], vals[p], or the entry itself
+// to raw[p] when raw is non-NULL; reads and writes are coalesced through LDS.
+template <int NT, int ITEMS, bool ONE_WAVE>
+__device__ __forceinline__ void merge_sort_lds(uint64_t *s, const uint64_t *in, uint32_t L, uint64_t thi,
+                                               uint64_t *keys, uint32_t *vals, uint64_t *raw, uint32_t tid) {
+    auto slot = [](uint32_t i) { return i + i / ITEMS; };
+    auto sync = [] {
+        if (ONE_WAVE) lds_wave_sync();
+        else __syncthreads();
+    };
+    uint32_t nt = 1;
+    while (nt * ITEMS < L) nt <<= 1;
+    const uint32_t n = nt * ITEMS;
+    const bool act = tid < nt;
+    {
+        // every load issued before any is used (clamped in bounds: L >= 1)
+        uint64_t x[ITEMS];
+#pragma unroll
+        for (int m = 0; m < ITEMS; ++m) x[m] = in[min((uint32_t)m * NT + tid, L - 1u)];
+#pragma unroll
+        for (int m = 0; m < ITEMS; ++m) {
+            const uint32_t i = (uint32_t)m * NT + tid;
+            if (i < n) s[slot(i)] = i < L ? x[m] : ~0ull;
+        }
+    }
+    sync();
+    uint64_t v[ITEMS];
+    if (act) {
+#pragma unroll
+        for (int m = 0; m < ITEMS; ++m) v[m] = s[slot(tid * ITEMS + m)];
+        sort_regs<ITEMS>(v);
+    }
+    for (uint32_t R = ITEMS; R < n; R <<= 1) {  // uniform
+        sync();  // the previous level's reads are done
+        if (act) {
+#pragma unroll
+            for (int m = 0; m < ITEMS; ++m) s[slot(tid * ITEMS + m)] = v[m];
+        }
+        sync();
+        if (act) {
+            // runs A = [a0, a0 + R) and B = [a0 + R, a0 + 2R); this thread
+            // writes outputs d .. d + ITEMS - 1 of their merge (ties: A first)
+            const uint32_t p0 = tid * ITEMS, a0 = p0 & ~(2 * R - 1), b0 = a0 + R, d = p0 - a0;
+            uint32_t lo = d > R ? d - R : 0u, hi = d < R ? d : R;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (s[slot(a0 + mid)] <= s[slot(b0 + d - 1 - mid)]) lo = mid + 1;
+                else hi = mid;
+            }
+            uint32_t i = lo, j = d - lo;
+            uint64_t a = s[slot(a0 + min(i, R - 1))], b = s[slot(b0 + min(j, R - 1))];
+#pragma unroll
+            for (int m = 0; m < ITEMS; ++m) {
+                const bool ta = j >= R || (i < R && a <= b);
+                v[m] = ta ? a : b;
+                i += ta ? 1u : 0u;
+                j += ta ? 0u : 1u;
+                if (m + 1 < ITEMS) {
+                    const uint64_t x = s[slot(ta ? a0 + min(i, R - 1) : b0 + min(j, R - 1))];
+                    a = ta ? x : a;
+                    b = ta ? b : x;
+                }
+            }
+        }
+    }
+    sync();
+    if (act) {
+#pragma unroll
+        for (int m = 0; m < ITEMS; ++m) s[slot(tid * ITEMS + m)] = v[m];
+    }
+    sync();
+    uint64_t x[ITEMS];
+#pragma unroll
+    for (int m = 0; m < ITEMS; ++m) x[m] = s[slot(min((uint32_t)m * NT + tid, n - 1u))];
+#pragma unroll
+    for (int m = 0; m < ITEMS; ++m) {
+        const uint32_t i = (uint32_t)m * NT + tid;
+        if (i < L) {
+            if (raw) {
+                raw[i] = x[m];
+            } else {
+                keys[i] = thi | (x[m] >> 32);
+                vals[i] = (uint32_t)x[m];
+            }
         }
     }
 }
 
-// Buckets of up to kSmallSortCap entries: a 256-thread workgroup each (up
-// to seven resident per CU); longer ones: a 512-thread workgroup each, in LDS
-// up to kTileSortCap, in place in HBM beyond.  Eight entries per thread.
-constexpr int kSmallSortBlock = 256, kSmallSortCap = 2048;
-constexpr int kTileSortBlock = 512, kTileSortCap = 8192;
+// dst[i] = f(src[i]) for i < cnt by NT threads, eight loads in flight per
+// thread (clamped in bounds) before their stores
+template <int NT, typename F>
+__device__ __forceinline__ void copy_block(const uint64_t *src, uint32_t cnt, uint32_t tid, F &&store) {
+    for (uint32_t b0 = 0; b0 < cnt; b0 += 8u * NT) {
+        uint64_t x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = src[min(b0 + (uint32_t)u * NT + tid, cnt - 1u)];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint32_t i = b0 + (uint32_t)u * NT + tid;
+            if (i < cnt) store(i, x[u]);
+        }
+    }
+}
 
-// One workgroup per tile (grid-stride): sort the bucket and write the keys
-// (tile << 32 | depth bits) and values (instance).  Launched twice: small
-// workgroups for buckets of 1..kSmallSortCap entries, then large ones for the
-// rest.
-template <int THREADS, int CAP, bool SMALL>
+// Merges the ascending runs A[0, la) and B[0, lb) (no two entries equal)
+// into dst[0, la + lb) with NT threads, CHUNK outputs at a time: the next
+// CHUNK entries of each run are staged in LDS (s holds 2 CHUNK), every
+// thread finds where its stretch of the chunk starts on the merge path by a
+// binary search in LDS and merges it, and thread 0 finds how far the chunk
+// got into A.
+template <int NT, int CHUNK>
+__device__ __forceinline__ void merge_runs(const uint64_t *A, uint32_t la, const uint64_t *Bv, uint32_t lb,
+                                           uint64_t *dst, uint64_t *s, uint32_t *s_take, uint32_t tid) {
+    constexpr uint32_t PER = CHUNK / NT;
+    uint64_t *sA = s, *sB = s + CHUNK;
+    // i = how many of the first d merged entries come from sA[0, na): the
+    // least i with sA[i] > sB[d - 1 - i], else min(d, na)
+    auto split = [&](uint32_t d, uint32_t na, uint32_t nb) {
+        uint32_t lo = d > nb ? d - nb : 0u, hi = d < na ? d : na;
+        while (lo < hi) {
+            const uint32_t i = (lo + hi) >> 1;
+            if (sA[i] < sB[d - 1 - i]) lo = i + 1;
+            else hi = i;
+        }
+        return lo;
+    };
+    uint32_t i0 = 0, j0 = 0;
+    while (i0 + j0 < la + lb) {  // uniform
+        const uint32_t na = min((uint32_t)CHUNK, la - i0), nb = min((uint32_t)CHUNK, lb - j0);
+        const uint32_t m = min((uint32_t)CHUNK, na + nb);
+        if (na) copy_block<NT>(A + i0, na, tid, [&](uint32_t k, uint64_t x) { sA[k] = x; });
+        if (nb) copy_block<NT>(Bv + j0, nb, tid, [&](uint32_t k, uint64_t x) { sB[k] = x; });
+        __syncthreads();
+        const uint32_t d0 = min(m, tid * PER), d1 = min(m, d0 + PER);
+        if (d0 < d1) {
+            uint32_t i = split(d0, na, nb), j = d0 - i;
+            for (uint32_t d = d0; d < d1; ++d) {
+                const bool take_a = j >= nb || (i < na && sA[i] < sB[j]);
+                dst[i0 + j0 + d] = take_a ? sA[i++] : sB[j++];
+            }
+        }
+        if (tid == 0) *s_take = split(m, na, nb);
+        __syncthreads();
+        const uint32_t ta = *s_take;
+        i0 += ta;
+        j0 += m - ta;
+        __syncthreads();  // sA, sB and s_take are reused by the next chunk
+    }
+}
+
+// One workgroup per item, items taken in rounds from the part of the list
+// the tile scan made for CLASS (class 0 longest first): a bucket of up to CAP
+// entries sorted in LDS, its keys (tile << 32 | depth bits) and values
+// (instance) written to the tile's range.
+template <int THREADS, int CAP, int CLASS>
 __global__ void __launch_bounds__(THREADS) tile_sort_kernel(uint64_t *bucket, const uint32_t *ranges,
-                                                            int64_t n_tiles, int64_t n_blocks, uint64_t *keys,
-                                                            uint32_t *vals, const int32_t *d_overflow) {
+                                                            const uint32_t *sort_list, const uint32_t *sort_ctl,
+                                                            const uint2 *run_list, uint64_t *keys, uint32_t *vals,
+                                                            const int32_t *d_overflow) {
     __shared__ uint64_t s[CAP + CAP / 8];
     if (*d_overflow) return;
-    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += n_blocks) {  // uniform per workgroup
-        const uint32_t b = ranges[2 * tile], L = ranges[2 * tile + 1] - b;
-        if (L == 0u || (SMALL ? L > (uint32_t)kSmallSortCap : L <= (uint32_t)kSmallSortCap)) continue;
-        uint32_t n2 = 8;
-        int ln = 3;
-        while (n2 < L) n2 <<= 1, ++ln;
-        const uint64_t thi = (uint64_t)tile << 32;
-        if (L <= (uint32_t)CAP) {
-            sort_bucket_lds<THREADS, 3, false>(s, bucket + b, L, n2, ln, thi, keys + b, vals + b, threadIdx.x);
+    constexpr bool SMALL = CLASS != 0;
+    uint32_t first = 0u;
+    for (int c = 0; c < CLASS; ++c) first += sort_ctl[c];
+    // class 0: first the runs of the tiles longer than CAP (sorted here, raw,
+    // into the key array; the merge kernel finishes those tiles), then the
+    // other tiles of the class
+    const uint32_t n_huge = SMALL ? 0u : sort_ctl[kSortClasses], n_runs = SMALL ? 0u : sort_ctl[kSortClasses + 1];
+    const uint32_t n_items = n_runs + sort_ctl[CLASS] - n_huge;
+    const uint32_t G = gridDim.x;
+    for (uint32_t r0 = 0; r0 < n_items; r0 += G) {  // uniform
+        // rounds of G items; class 0 comes longest first, so its rounds
+        // alternate direction to even out the workgroups' totals
+        const uint32_t idx = r0 + (SMALL || ((r0 / G) & 1u) == 0u ? blockIdx.x : G - 1u - blockIdx.x);
+        if (idx >= n_items) continue;
+        if (!SMALL && idx < n_runs) {
+            const uint2 tr = run_list[idx];
+            const uint32_t b = ranges[2 * tr.x], L = ranges[2 * tr.x + 1] - b, off = tr.y * (uint32_t)CAP;
+            merge_sort_lds<THREADS, CAP / THREADS, false>(s, bucket + b + off, min((uint32_t)CAP, L - off), 0ull,
+                                                          nullptr, nullptr, keys + b + off, threadIdx.x);
         } else {
-            bitonic_sort_hbm<THREADS>(bucket + b, n2, L);
-            for (uint32_t i = threadIdx.x; i < L; i += THREADS) {
-                const uint64_t c = bucket[b + i];
-                keys[b + i] = thi | (c >> 32);
-                vals[b + i] = (uint32_t)c;
-            }
+            const uint32_t tile = sort_list[first + n_huge + (idx - n_runs)];
+            const uint32_t b = ranges[2 * tile], L = ranges[2 * tile + 1] - b;
+            merge_sort_lds<THREADS, CAP / THREADS, false>(s, bucket + b, L, (uint64_t)tile << 32, keys + b, vals + b,
+                                                          nullptr, threadIdx.x);
         }
-        __syncthreads();  // s and the bucket are reused by the next tile
+        __syncthreads();  // s is reused by the next item
+    }
+}
+
+// The tiles longer than CAP, one workgroup each: their sorted runs (raw in
+// the key array) merged pairwise, ping-ponging between the key array and the
+// bucket, then written as keys (tile << 32 | depth bits) and values.
+template <int THREADS, int CAP>
+__global__ void __launch_bounds__(THREADS) tile_merge_kernel(uint64_t *bucket, const uint32_t *ranges,
+                                                             const uint32_t *sort_list, const uint32_t *sort_ctl,
+                                                             uint64_t *keys, uint32_t *vals,
+                                                             const int32_t *d_overflow) {
+    __shared__ uint64_t s[CAP];
+    __shared__ uint32_t s_take;
+    if (*d_overflow) return;
+    const uint32_t n_huge = sort_ctl[kSortClasses];
+    for (uint32_t h = blockIdx.x; h < n_huge; h += gridDim.x) {  // uniform
+        const uint32_t tile = sort_list[h];
+        const uint32_t b = ranges[2 * tile], L = ranges[2 * tile + 1] - b;
+        const uint64_t thi = (uint64_t)tile << 32;
+        {
+            uint64_t *buf0 = keys + b, *buf1 = bucket + b;
+            uint64_t *src = buf0, *dst = buf1;
+            for (uint32_t w = (uint32_t)CAP; w < L; w <<= 1) {
+                for (uint32_t a0 = 0; a0 < L; a0 += 2 * w) {
+                    const uint32_t la = min(w, L - a0), lb = min(w, L - a0 - la);
+                    if (lb == 0u) {
+                        uint64_t *d = dst + a0;
+                        copy_block<THREADS>(src + a0, la, threadIdx.x, [&](uint32_t i, uint64_t x) { d[i] = x; });
+                    } else {
+                        merge_runs<THREADS, CAP / 2>(src + a0, la, src + a0 + la, lb, dst + a0, s, &s_take,
+                                                     threadIdx.x);
+                    }
+                }
+                __syncthreads();
+                uint64_t *t = src;
+                src = dst;
+                dst = t;
+            }
+            // keys and values of the merged bucket (in place when it ended in the
+            // key array: each entry is read before the same thread rewrites it)
+            uint64_t *kk = keys + b;
+            uint32_t *vv = vals + b;
+            copy_block<THREADS>(src, L, threadIdx.x, [&](uint32_t i, uint64_t c) {
+                kk[i] = thi | (c >> 32);
+                vv[i] = (uint32_t)c;
+            });
+        }
+        __syncthreads();  // s is reused by the next tile
+    }
+}
+
+// The tiles of 1..kTinySortCap keys: one wave each, four waves per
+// workgroup, waves striding over the list (no workgroup barriers).
+__global__ void __launch_bounds__(256) tile_sort_wave_kernel(uint64_t *bucket, const uint32_t *ranges,
+                                                             const uint32_t *sort_list, const uint32_t *sort_ctl,
+                                                             uint64_t *keys, uint32_t *vals,
+                                                             const int32_t *d_overflow) {
+    constexpr int SLOTS = kTinySortCap + kTinySortCap / 8;
+    __shared__ uint64_t s[4][SLOTS];
+    if (*d_overflow) return;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    uint32_t first = 0u;
+    for (int c = 0; c < kSortClasses - 1; ++c) first += sort_ctl[c];
+    const uint32_t n_mine = sort_ctl[kSortClasses - 1];
+    for (uint32_t idx = blockIdx.x * 4u + (uint32_t)wave; idx < n_mine; idx += gridDim.x * 4u) {  // uniform per wave
+        const uint32_t tile = sort_list[first + idx];
+        const uint32_t b = ranges[2 * tile], L = ranges[2 * tile + 1] - b;
+        merge_sort_lds<64, kTinySortCap / 64, true>(s[wave], bucket + b, L, (uint64_t)tile << 32, keys + b, vals + b,
+                                                    nullptr, (uint32_t)lane);
+        lds_wave_sync();  // s is reused by the next tile
     }
 }
 
@@ -1000,8 +1456,9 @@ __global__ void __launch_bounds__(256) ranges_kernel(const uint64_t *keys, const
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-SortPlan make_sort_plan(int64_t n, int64_t capacity, int64_t n_tiles_total) {
+SortPlan make_sort_plan(int64_t n, int64_t capacity, int64_t tiles_per_view, int64_t n_views) {
     SortPlan p;
+    const int64_t n_tiles_total = tiles_per_view * n_views;
     p.part_keys = kMinSortPart;
     p.lookback = 16;
     p.n = n;
@@ -1034,15 +1491,37 @@ SortPlan make_sort_plan(int64_t n, int64_t capacity, int64_t n_tiles_total) {
     p.off_status = o;
     o = o + sizeof(uint32_t) * (size_t)p.passes * (size_t)p.sort_parts * kBins;
     o = align256(o);
-    // bucket path (moderate tile counts): per-workgroup tile counters, tile totals and starts
-    p.bucket_ok = n_tiles_total <= kBucketMaxTiles;
-    p.bucket_blocks = p.scan_blocks < kBucketGrid ? p.scan_blocks : kBucketGrid;
+    // bucket path: per-workgroup tile counters, tile totals (and, windowed,
+    // the keys counted outside a window right after them) and starts; the
+    // counters of up to kBucketMaxTiles tiles fit in LDS, beyond that a
+    // window of whole views does when a view has at most kLdsTiles tiles
+    p.T = tiles_per_view;
+    p.windowed = n_tiles_total > kBucketMaxTiles;
+    p.win_views = (int)(kLdsTiles / (tiles_per_view > 0 ? tiles_per_view : 1));
+    p.bucket_ok = !p.windowed || (tiles_per_view <= kLdsTiles && tiles_per_view > 0 && n_tiles_total <= kWindowMaxTiles);
+    const int64_t grid = p.windowed ? kWinGrid : kBucketGrid;
+    p.bucket_blocks = p.scan_blocks < grid ? p.scan_blocks : grid;
     p.off_tcnt = o;
     if (p.bucket_ok) o = align256(o + sizeof(uint32_t) * (size_t)p.bucket_blocks * (size_t)n_tiles_total);
     p.off_tcount = o;
-    if (p.bucket_ok) o = align256(o + sizeof(uint32_t) * (size_t)n_tiles_total);
+    p.off_tover = o + sizeof(uint32_t) * (size_t)n_tiles_total;
+    if (p.bucket_ok) o = align256(o + sizeof(uint32_t) * (size_t)n_tiles_total * (p.windowed ? 2 : 1));
     p.off_tstart = o;
     if (p.bucket_ok) o = align256(o + sizeof(uint32_t) * (size_t)n_tiles_total);
+    // the count pass's compact records of the live instances
+    p.off_comp = o;
+    if (p.bucket_ok) o = align256(o + sizeof(uint32_t) * 4 * (size_t)kScanTile * (size_t)p.scan_blocks);
+    p.off_compn = o;
+    if (p.bucket_ok) o = align256(o + sizeof(uint32_t) * (size_t)kEmitWaves * (size_t)p.scan_blocks);
+    // the tile sorts' list of tiles and their counters
+    p.off_slist = o;
+    if (p.bucket_ok) o = align256(o + sizeof(uint32_t) * (size_t)n_tiles_total);
+    p.off_sctl = o;
+    if (p.bucket_ok) o = align256(o + sizeof(uint32_t) * kSortCtlWords);
+    // the runs of the tiles longer than kTileSortCap (at most one per tile and one per kTileSortCap keys)
+    p.off_rlist = o;
+    if (p.bucket_ok)
+        o = align256(o + sizeof(uint2) * (size_t)(n_tiles_total + (capacity > 0 ? capacity : 1) / kTileSortCap + 1));
     p.use_bucket = p.bucket_ok;
     p.total = align256(o);
     return p;
@@ -1075,31 +1554,81 @@ static hipError_t run_bucket_sort(const SortPlan &P, const uint32_t *tt, const f
     A.bucket = reinterpret_cast<uint64_t *>(ws + P.off_keys2);
     A.n_tiles = P.n_tiles_total;
     A.d_overflow = d_overflow;
+    A.comp = reinterpret_cast<uint4 *>(ws + P.off_comp);
+    A.comp_n = reinterpret_cast<uint32_t *>(ws + P.off_compn);
     uint32_t *tcount = reinterpret_cast<uint32_t *>(ws + P.off_tcount);
     uint32_t *tstart = reinterpret_cast<uint32_t *>(ws + P.off_tstart);
-    if ((e = launch_kernel(emit_kernel<kEmitCountTiles>, dim3((unsigned)P.bucket_blocks), dim3(kEmitBlock), s, A)) !=
-        hipSuccess)
-        return e;
-    if ((e = launch_kernel(bucket_colscan_kernel, dim3((unsigned)((P.n_tiles_total + 3) / 4)), dim3(256), s,
-                           A.tile_cnt, (int)P.bucket_blocks, P.n_tiles_total, tcount)) != hipSuccess)
-        return e;
-    if ((e = launch_kernel(bucket_tilescan_kernel, dim3(1), dim3(1024), s, (const uint32_t *)tcount, P.n_tiles_total,
-                           P.capacity, tstart, ranges, order, d_num, d_overflow)) != hipSuccess)
-        return e;
-    if ((e = launch_kernel(emit_kernel<kEmitScatterTiles>, dim3((unsigned)P.bucket_blocks), dim3(kEmitBlock), s,
-                           A)) != hipSuccess)
-        return e;
+    uint32_t *slist = reinterpret_cast<uint32_t *>(ws + P.off_slist);
+    uint32_t *sctl = reinterpret_cast<uint32_t *>(ws + P.off_sctl);
+    uint2 *rlist = reinterpret_cast<uint2 *>(ws + P.off_rlist);
+    if (P.windowed) {
+        // window totals and the keys outside windows start at zero (one fill:
+        // the two arrays are adjacent); the counters hold offsets after the count
+        A.tile_count = tcount;
+        A.tile_over = reinterpret_cast<uint32_t *>(ws + P.off_tover);
+        A.T = P.T;
+        A.win_views = P.win_views;
+        if ((e = launch_fill_u32(tcount, 0u, 2 * P.n_tiles_total, s)) != hipSuccess) return e;
+        if ((e = launch_kernel(emit_kernel<kEmitCountWin>, dim3((unsigned)P.bucket_blocks), dim3(kEmitBlock), s,
+                               A)) != hipSuccess)
+            return e;
+        if ((e = launch_kernel(bucket_tilescan_kernel, dim3(1), dim3(1024), s, (const uint32_t *)tcount,
+                               (const uint32_t *)A.tile_over, P.n_tiles_total, P.capacity, tstart, ranges, order,
+                               slist, sctl, rlist, d_num, d_overflow)) != hipSuccess)
+            return e;
+        if ((e = launch_kernel(emit_kernel<kEmitScatterWin>, dim3((unsigned)P.bucket_blocks), dim3(kEmitBlock), s,
+                               A)) != hipSuccess)
+            return e;
+    } else {
+        if ((e = launch_kernel(emit_kernel<kEmitCountTiles>, dim3((unsigned)P.bucket_blocks), dim3(kEmitBlock), s,
+                               A)) != hipSuccess)
+            return e;
+        if ((e = launch_kernel(bucket_colscan_kernel, dim3((unsigned)((P.n_tiles_total + 3) / 4)), dim3(256), s,
+                               A.tile_cnt, (int)P.bucket_blocks, P.n_tiles_total, tcount)) != hipSuccess)
+            return e;
+        if ((e = launch_kernel(bucket_tilescan_kernel, dim3(1), dim3(1024), s, (const uint32_t *)tcount,
+                               (const uint32_t *)nullptr, P.n_tiles_total, P.capacity, tstart, ranges, order, slist,
+                               sctl, rlist, d_num, d_overflow)) != hipSuccess)
+            return e;
+        if ((e = launch_kernel(emit_kernel<kEmitScatterTiles>, dim3((unsigned)P.bucket_blocks), dim3(kEmitBlock), s,
+                               A)) != hipSuccess)
+            return e;
+    }
+    // the tile sorts take their tiles from the list in rounds of one per workgroup (wave)
     int64_t sg = 8 * (int64_t)n_cu;
     if (sg > P.n_tiles_total) sg = P.n_tiles_total;
-    if ((e = launch_kernel(tile_sort_kernel<kSmallSortBlock, kSmallSortCap, true>, dim3((unsigned)sg),
-                           dim3(kSmallSortBlock), s, A.bucket, (const uint32_t *)ranges, P.n_tiles_total, sg, keys,
-                           vals, d_overflow)) != hipSuccess)
+    int64_t wg = 8 * (int64_t)n_cu;
+    if (wg > (P.n_tiles_total + 3) / 4) wg = (P.n_tiles_total + 3) / 4;
+    if ((e = launch_kernel(tile_sort_wave_kernel, dim3((unsigned)wg), dim3(256), s, A.bucket, (const uint32_t *)ranges,
+                           (const uint32_t *)slist, (const uint32_t *)sctl, keys, vals, (const int32_t *)d_overflow)) !=
+        hipSuccess)
+        return e;
+    const uint32_t *cl = slist, *cc = sctl;
+    const uint2 *rl = rlist;
+    const int32_t *ov = d_overflow;
+    if ((e = launch_kernel(tile_sort_kernel<kSmallSortBlock, kSmallSortCap, 3>, dim3((unsigned)sg),
+                           dim3(kSmallSortBlock), s, A.bucket, (const uint32_t *)ranges, cl, cc, rl, keys, vals, ov)) !=
+        hipSuccess)
+        return e;
+    int64_t mg = 4 * (int64_t)n_cu;
+    if (mg > P.n_tiles_total) mg = P.n_tiles_total;
+    if ((e = launch_kernel(tile_sort_kernel<kSmallSortBlock, kMidSortCap, 2>, dim3((unsigned)mg),
+                           dim3(kSmallSortBlock), s, A.bucket, (const uint32_t *)ranges, cl, cc, rl, keys, vals, ov)) !=
+        hipSuccess)
+        return e;
+    int64_t xg = 2 * (int64_t)n_cu;
+    if (xg > P.n_tiles_total) xg = P.n_tiles_total;
+    if ((e = launch_kernel(tile_sort_kernel<kLargeSortBlock, kLargeSortCap, 1>, dim3((unsigned)xg),
+                           dim3(kLargeSortBlock), s, A.bucket, (const uint32_t *)ranges, cl, cc, rl, keys, vals, ov)) !=
+        hipSuccess)
         return e;
     int64_t lg = (int64_t)n_cu;
-    if (lg > P.n_tiles_total) lg = P.n_tiles_total;
-    return launch_kernel(tile_sort_kernel<kTileSortBlock, kTileSortCap, false>, dim3((unsigned)lg),
-                         dim3(kTileSortBlock), s, A.bucket, (const uint32_t *)ranges, P.n_tiles_total, lg, keys, vals,
-                         d_overflow);
+    if ((e = launch_kernel(tile_sort_kernel<kTileSortBlock, kTileSortCap, 0>, dim3((unsigned)lg),
+                           dim3(kTileSortBlock), s, A.bucket, (const uint32_t *)ranges, cl, cc, rl, keys, vals, ov)) !=
+        hipSuccess)
+        return e;
+    return launch_kernel(tile_merge_kernel<kTileSortBlock, kTileSortCap>, dim3((unsigned)lg), dim3(kTileSortBlock), s,
+                         A.bucket, (const uint32_t *)ranges, cl, cc, keys, vals, ov);
 }
 
 hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec, int TX, int TY, char *ws,

@@ -104,8 +104,8 @@ def test_full_size_headline_frame(dev, orc):
 
 def test_batched_beyond_4096_tiles_default_path(dev, orc):
     """20 views at 256x256 over 3 scenes of uneven size: 5120 (view, tile)
-    lists, past the bucket sort's 4096, so the default binning is the
-    onesweep radix sort."""
+    lists, past the 4096 tile counters that LDS holds, so the default
+    binning counts in windows of whole views."""
     import torch
     from paper_2604_12626_amd import binding as B, render
     assert B.get_tuning()["sort_algorithm"] == 0  # default selection

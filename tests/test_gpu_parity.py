@@ -113,6 +113,14 @@ BIN_CASES = [
     ("empty", [0], 32, 32),
     ("1view_640x480_200k", [200000], 640, 480),
     ("16views_256x256_60k", [4000] * 15 + [100], 256, 256),
+    # past 4096 tiles: tile counters in a window of whole views (16 of 256
+    # tiles here) that moves with the views
+    ("64views_256x256_windowed", [3000] * 63 + [500], 256, 256),
+    # one emission block draws 40 views: the keys past its window take the
+    # tiles' last slots
+    ("40views_256x256_block_past_window", [90] * 40, 256, 256),
+    # 475 tiles a view: a window of 8 views, the ring wraps at 3800 tiles
+    ("10views_400x300_ring", [6000] * 10, 400, 300),
 ]
 
 
@@ -139,6 +147,38 @@ def test_bin_sort_bit_exact(dev, orc, name, counts, W, H):
         for cap, expect_ovf, knobs in runs:
             B.set_tuning(**dict(prev, **knobs))
             _bin_sort_case(dev, B, rec, tt_o, keys_o, vals_o, ranges_o, K, V, W, H, prm, cap, expect_ovf)
+    finally:
+        B.set_tuning(**prev)
+
+
+def test_bin_sort_long_buckets_bit_exact(dev, orc):
+    """Buckets longer than one LDS sort (16384 entries): sorted as runs and
+    merged, one with two runs, one with four and a ragged fifth; 20 views of
+    256x256 (5120 tiles, the windowed counters)."""
+    from paper_2604_12626_amd import binding as B
+    rng = np.random.default_rng(77)
+    W = H = 256
+    counts = [80000, 30000] + [2000] * 18
+    rec, vis = synth.synthetic_records(rng, counts, W, H)
+    # view 0: every instance in tile 0; view 1: every instance in tile 5
+    for v, (tx, ty) in ((0, (0, 0)), (1, (5, 0))):
+        sel = rec[:, 11].view(np.int32) == v
+        k = int(sel.sum())
+        rec[sel, 0] = 16 * tx + rng.uniform(4.0, 12.0, k)
+        rec[sel, 1] = 16 * ty + rng.uniform(4.0, 12.0, k)
+        rec[sel, 3] = np.ones(k, np.int32).view(np.float32)
+    V = len(counts)
+    tt_o, keys_o, vals_o, ranges_o, K = orc.bin_records(rec, vis, W, H, V)
+    lens = ranges_o.reshape(-1, 2).astype(np.int64)
+    lens = lens[:, 1] - lens[:, 0]
+    say("long buckets: K %d, longest lists %s" % (K, np.sort(lens)[-3:]))
+    assert lens[0] > 4 * 16384 and 16384 < lens[256 + 5] <= 2 * 16384
+    prm = B.make_params(W, H)
+    prev = B.get_tuning()
+    try:
+        for knobs in ({}, {"sort_algorithm": 1}):
+            B.set_tuning(**dict(prev, **knobs))
+            _bin_sort_case(dev, B, rec, tt_o, keys_o, vals_o, ranges_o, K, V, W, H, prm, K + 1000, 0)
     finally:
         B.set_tuning(**prev)
 
