@@ -987,14 +987,17 @@ __global__ void __launch_bounds__(1024) bucket_tilescan_kernel(const uint32_t *t
     auto load_chunk = [&](int64_t cb) {
         if (loaded == cb) return;  // uniform
         __syncthreads();
-        uint32_t c[PER];
+        // every load issued before any is used: addresses clamped in bounds,
+        // counts past the end zeroed afterwards
+        uint32_t c[PER], o[PER];
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
-            const int64_t t = cb + k * 1024 + tid;
-            c[k] = t < n_tiles ? tile_count[t] + (tile_over ? tile_over[t] : 0u) : 0u;
+            const int64_t t = min(cb + k * 1024 + tid, n_tiles - 1);
+            c[k] = tile_count[t];
+            o[k] = tile_over ? tile_over[t] : 0u;
         }
 #pragma unroll
-        for (int k = 0; k < PER; ++k) s_c[k * 1024 + tid] = c[k];
+        for (int k = 0; k < PER; ++k) s_c[k * 1024 + tid] = cb + k * 1024 + tid < n_tiles ? c[k] + o[k] : 0u;
         loaded = cb;
         __syncthreads();
     };
@@ -1002,8 +1005,9 @@ __global__ void __launch_bounds__(1024) bucket_tilescan_kernel(const uint32_t *t
     if (tid < kSortBins + kSortClasses - 1) s_big[tid] = 0u;
     if (tid == 0) s_runs = 0u;
     // 1. the total, so that the overflow is known before anything is written
+    // (one chunk: the scan below finds it before its first store)
     uint64_t total = 0u;
-    for (int64_t ch = 0; ch < n_chunks; ++ch) {
+    for (int64_t ch = 0; n_chunks > 1 && ch < n_chunks; ++ch) {
         load_chunk(ch * kScanChunk);
         uint64_t sum = 0u;
 #pragma unroll
@@ -1015,11 +1019,7 @@ __global__ void __launch_bounds__(1024) bucket_tilescan_kernel(const uint32_t *t
         __syncthreads();
         for (int k = 0; k < 16; ++k) total += s_w[k];
     }
-    const bool ovf = total > (uint64_t)capacity;  // then every range is [0, 0) and nothing is listed
-    if (tid == 0) {
-        *d_num = (int64_t)total;
-        *d_overflow = ovf ? 1 : 0;
-    }
+    bool ovf = total > (uint64_t)capacity;  // then every range is [0, 0) and nothing is listed
     // 2. starts and ranges (each thread PER consecutive tiles), then the bin
     // counts (consecutive tiles on consecutive lanes: the order's queues and
     // bins spread over the lanes)
@@ -1049,6 +1049,7 @@ __global__ void __launch_bounds__(1024) bucket_tilescan_kernel(const uint32_t *t
             chunk_total += s_w[k];
         }
         carry += chunk_total;
+        if (n_chunks == 1) ovf = carry > (uint64_t)capacity;
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             s_st[tid * PER + k] = (uint32_t)run;
@@ -1058,6 +1059,7 @@ __global__ void __launch_bounds__(1024) bucket_tilescan_kernel(const uint32_t *t
         // consecutive tiles on consecutive lanes: coalesced stores
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
+            if (cb + k * 1024 >= n_tiles) break;  // uniform: nothing left in the chunk
             const int64_t t = cb + k * 1024 + tid;
             if (t < n_tiles) {
                 const uint32_t c1 = s_c[k * 1024 + tid], st = s_st[k * 1024 + tid];
@@ -1068,6 +1070,7 @@ __global__ void __launch_bounds__(1024) bucket_tilescan_kernel(const uint32_t *t
         }
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
+            if (cb + k * 1024 >= n_tiles) break;  // uniform
             const int64_t t = cb + k * 1024 + tid;
             const uint32_t c1 = ovf ? 0u : s_c[k * 1024 + tid];
             if (order && t < n_tiles) atomicAdd(&s_cnt[t % kOrderQueues][order_bin(c1)], 1u);
@@ -1079,6 +1082,10 @@ __global__ void __launch_bounds__(1024) bucket_tilescan_kernel(const uint32_t *t
                 if (lane == 0 && m) atomicAdd(&s_big[kSortBins + cl], (uint32_t)__popcll(m));
             }
         }
+    }
+    if (tid == 0) {
+        *d_num = (int64_t)carry;
+        *d_overflow = ovf ? 1 : 0;
     }
     // 3. bin starts, then the order and the sort lists
     if (order) order_bin_starts(s_cnt);
@@ -1113,6 +1120,7 @@ __global__ void __launch_bounds__(1024) bucket_tilescan_kernel(const uint32_t *t
         load_chunk(cb);
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
+            if (cb + k * 1024 >= n_tiles) break;  // uniform
             const int64_t t = cb + k * 1024 + tid;
             const bool in = t < n_tiles;
             const uint32_t c = (ovf || !in) ? 0u : s_c[k * 1024 + tid];
@@ -1323,25 +1331,71 @@ __device__ __forceinline__ void merge_runs(const uint64_t *A, uint32_t la, const
     }
 }
 
+// A tile of L > CAP entries whose runs of CAP entries are sorted, raw, at
+// keys[b ..]: runs merged pairwise by the workgroup, ping-ponging between the
+// key array and the bucket, then written as keys (tile << 32 | depth bits)
+// and values (s: CAP entries of LDS).
+template <int THREADS, int CAP>
+__device__ __forceinline__ void merge_tile_runs(uint64_t *bucket, uint64_t *keys, uint32_t *vals, uint32_t tile,
+                                                uint32_t b, uint32_t L, uint64_t *s, uint32_t *s_take) {
+    const uint64_t thi = (uint64_t)tile << 32;
+    uint64_t *src = keys + b, *dst = bucket + b;
+    for (uint32_t w = (uint32_t)CAP; w < L; w <<= 1) {
+        for (uint32_t a0 = 0; a0 < L; a0 += 2 * w) {
+            const uint32_t la = min(w, L - a0), lb = min(w, L - a0 - la);
+            if (lb == 0u) {
+                uint64_t *d = dst + a0;
+                copy_block<THREADS>(src + a0, la, threadIdx.x, [&](uint32_t i, uint64_t x) { d[i] = x; });
+            } else {
+                merge_runs<THREADS, CAP / 2>(src + a0, la, src + a0 + la, lb, dst + a0, s, s_take, threadIdx.x);
+            }
+        }
+        __syncthreads();
+        uint64_t *t = src;
+        src = dst;
+        dst = t;
+    }
+    // in place when it ended in the key array: each entry is read before the
+    // same thread rewrites it
+    uint64_t *kk = keys + b;
+    uint32_t *vv = vals + b;
+    copy_block<THREADS>(src, L, threadIdx.x, [&](uint32_t i, uint64_t c) {
+        kk[i] = thi | (c >> 32);
+        vv[i] = (uint32_t)c;
+    });
+}
+
 // One workgroup per item, items taken in rounds from the part of the list
 // the tile scan made for CLASS (class 0 longest first): a bucket of up to CAP
 // entries sorted in LDS, its keys (tile << 32 | depth bits) and values
-// (instance) written to the tile's range.
+// (instance) written to the tile's range.  Besides the five classes, two
+// groupings for launches of few tiles, where one launch for several classes
+// keeps every tile in flight at once: kSortShort (classes 2..4, 256 threads)
+// and kSortLong (classes 0 and 1, 1024 threads, a tile longer than CAP sorted
+// as runs and merged by its own workgroup).  With sixteen
+// entries per thread, a bucket that fits eight per thread takes eight (more
+// threads at work).
+constexpr int kSortShort = 5, kSortLong = 6;
+
 template <int THREADS, int CAP, int CLASS>
 __global__ void __launch_bounds__(THREADS) tile_sort_kernel(uint64_t *bucket, const uint32_t *ranges,
                                                             const uint32_t *sort_list, const uint32_t *sort_ctl,
                                                             const uint2 *run_list, uint64_t *keys, uint32_t *vals,
                                                             const int32_t *d_overflow) {
     __shared__ uint64_t s[CAP + CAP / 8];
+    __shared__ uint32_t s_take;
     if (*d_overflow) return;
-    constexpr bool SMALL = CLASS != 0;
-    uint32_t first = 0u;
-    for (int c = 0; c < CLASS; ++c) first += sort_ctl[c];
     // class 0: first the runs of the tiles longer than CAP (sorted here, raw,
     // into the key array; the merge kernel finishes those tiles), then the
-    // other tiles of the class
+    // other tiles
+    constexpr bool SMALL = CLASS != 0;
+    constexpr int C0 = CLASS == kSortShort ? 2 : CLASS == kSortLong ? 0 : CLASS;
+    constexpr int C1 = CLASS == kSortShort ? 4 : CLASS == kSortLong ? 1 : CLASS;
+    uint32_t first = 0u, n_tiles = 0u;
+    for (int c = 0; c < C0; ++c) first += sort_ctl[c];
+    for (int c = C0; c <= C1; ++c) n_tiles += sort_ctl[c];
     const uint32_t n_huge = SMALL ? 0u : sort_ctl[kSortClasses], n_runs = SMALL ? 0u : sort_ctl[kSortClasses + 1];
-    const uint32_t n_items = n_runs + sort_ctl[CLASS] - n_huge;
+    const uint32_t n_items = n_runs + n_tiles - n_huge;
     const uint32_t G = gridDim.x;
     for (uint32_t r0 = 0; r0 < n_items; r0 += G) {  // uniform
         // rounds of G items; class 0 comes longest first, so its rounds
@@ -1356,8 +1410,20 @@ __global__ void __launch_bounds__(THREADS) tile_sort_kernel(uint64_t *bucket, co
         } else {
             const uint32_t tile = sort_list[first + n_huge + (idx - n_runs)];
             const uint32_t b = ranges[2 * tile], L = ranges[2 * tile + 1] - b;
-            merge_sort_lds<THREADS, CAP / THREADS, false>(s, bucket + b, L, (uint64_t)tile << 32, keys + b, vals + b,
-                                                          nullptr, threadIdx.x);
+            constexpr int IT = CAP / THREADS;
+            if (CLASS == kSortLong && L > (uint32_t)CAP) {
+                for (uint32_t off = 0; off < L; off += (uint32_t)CAP) {
+                    merge_sort_lds<THREADS, IT, false>(s, bucket + b + off, min((uint32_t)CAP, L - off), 0ull, nullptr,
+                                                       nullptr, keys + b + off, threadIdx.x);
+                    __syncthreads();  // s is reused by the next run
+                }
+                merge_tile_runs<THREADS, CAP>(bucket, keys, vals, tile, b, L, s, &s_take);
+            } else if (IT == 16 && L <= (uint32_t)(THREADS * 8))
+                merge_sort_lds<THREADS, (IT == 16 ? 8 : IT), false>(s, bucket + b, L, (uint64_t)tile << 32, keys + b,
+                                                                    vals + b, nullptr, threadIdx.x);
+            else
+                merge_sort_lds<THREADS, IT, false>(s, bucket + b, L, (uint64_t)tile << 32, keys + b, vals + b, nullptr,
+                                                   threadIdx.x);
         }
         __syncthreads();  // s is reused by the next item
     }
@@ -1378,35 +1444,7 @@ __global__ void __launch_bounds__(THREADS) tile_merge_kernel(uint64_t *bucket, c
     for (uint32_t h = blockIdx.x; h < n_huge; h += gridDim.x) {  // uniform
         const uint32_t tile = sort_list[h];
         const uint32_t b = ranges[2 * tile], L = ranges[2 * tile + 1] - b;
-        const uint64_t thi = (uint64_t)tile << 32;
-        {
-            uint64_t *buf0 = keys + b, *buf1 = bucket + b;
-            uint64_t *src = buf0, *dst = buf1;
-            for (uint32_t w = (uint32_t)CAP; w < L; w <<= 1) {
-                for (uint32_t a0 = 0; a0 < L; a0 += 2 * w) {
-                    const uint32_t la = min(w, L - a0), lb = min(w, L - a0 - la);
-                    if (lb == 0u) {
-                        uint64_t *d = dst + a0;
-                        copy_block<THREADS>(src + a0, la, threadIdx.x, [&](uint32_t i, uint64_t x) { d[i] = x; });
-                    } else {
-                        merge_runs<THREADS, CAP / 2>(src + a0, la, src + a0 + la, lb, dst + a0, s, &s_take,
-                                                     threadIdx.x);
-                    }
-                }
-                __syncthreads();
-                uint64_t *t = src;
-                src = dst;
-                dst = t;
-            }
-            // keys and values of the merged bucket (in place when it ended in the
-            // key array: each entry is read before the same thread rewrites it)
-            uint64_t *kk = keys + b;
-            uint32_t *vv = vals + b;
-            copy_block<THREADS>(src, L, threadIdx.x, [&](uint32_t i, uint64_t c) {
-                kk[i] = thi | (c >> 32);
-                vv[i] = (uint32_t)c;
-            });
-        }
+        merge_tile_runs<THREADS, CAP>(bucket, keys, vals, tile, b, L, s, &s_take);
         __syncthreads();  // s is reused by the next tile
     }
 }
@@ -1594,41 +1632,45 @@ static hipError_t run_bucket_sort(const SortPlan &P, const uint32_t *tt, const f
                                A)) != hipSuccess)
             return e;
     }
-    // the tile sorts take their tiles from the list in rounds of one per workgroup (wave)
-    int64_t sg = 8 * (int64_t)n_cu;
-    if (sg > P.n_tiles_total) sg = P.n_tiles_total;
-    int64_t wg = 8 * (int64_t)n_cu;
-    if (wg > (P.n_tiles_total + 3) / 4) wg = (P.n_tiles_total + 3) / 4;
-    if ((e = launch_kernel(tile_sort_wave_kernel, dim3((unsigned)wg), dim3(256), s, A.bucket, (const uint32_t *)ranges,
-                           (const uint32_t *)slist, (const uint32_t *)sctl, keys, vals, (const int32_t *)d_overflow)) !=
-        hipSuccess)
-        return e;
+    // the tile sorts take their tiles from the list in rounds of one per
+    // workgroup (wave); few tiles: two launches cover every class, so all
+    // tiles sort at once; many: one launch per class, each sized to fill the
+    // chip with its own workgroups
     const uint32_t *cl = slist, *cc = sctl;
     const uint2 *rl = rlist;
     const int32_t *ov = d_overflow;
-    if ((e = launch_kernel(tile_sort_kernel<kSmallSortBlock, kSmallSortCap, 3>, dim3((unsigned)sg),
-                           dim3(kSmallSortBlock), s, A.bucket, (const uint32_t *)ranges, cl, cc, rl, keys, vals, ov)) !=
-        hipSuccess)
-        return e;
-    int64_t mg = 4 * (int64_t)n_cu;
-    if (mg > P.n_tiles_total) mg = P.n_tiles_total;
-    if ((e = launch_kernel(tile_sort_kernel<kSmallSortBlock, kMidSortCap, 2>, dim3((unsigned)mg),
-                           dim3(kSmallSortBlock), s, A.bucket, (const uint32_t *)ranges, cl, cc, rl, keys, vals, ov)) !=
-        hipSuccess)
-        return e;
-    int64_t xg = 2 * (int64_t)n_cu;
-    if (xg > P.n_tiles_total) xg = P.n_tiles_total;
-    if ((e = launch_kernel(tile_sort_kernel<kLargeSortBlock, kLargeSortCap, 1>, dim3((unsigned)xg),
-                           dim3(kLargeSortBlock), s, A.bucket, (const uint32_t *)ranges, cl, cc, rl, keys, vals, ov)) !=
-        hipSuccess)
-        return e;
-    int64_t lg = (int64_t)n_cu;
-    if ((e = launch_kernel(tile_sort_kernel<kTileSortBlock, kTileSortCap, 0>, dim3((unsigned)lg),
-                           dim3(kTileSortBlock), s, A.bucket, (const uint32_t *)ranges, cl, cc, rl, keys, vals, ov)) !=
-        hipSuccess)
-        return e;
-    return launch_kernel(tile_merge_kernel<kTileSortBlock, kTileSortCap>, dim3((unsigned)lg), dim3(kTileSortBlock), s,
-                         A.bucket, (const uint32_t *)ranges, cl, cc, keys, vals, ov);
+    const uint32_t *rg = ranges;
+    auto grid = [&](int64_t per_cu, int64_t cap) {
+        int64_t g = per_cu * (int64_t)n_cu;
+        return (unsigned)(g < cap ? g : (cap > 0 ? cap : 1));
+    };
+    const int64_t nt = P.n_tiles_total;
+    if (!P.windowed) {
+        if ((e = launch_kernel(tile_sort_kernel<kSmallSortBlock, kMidSortCap, kSortShort>, dim3(grid(8, nt)),
+                               dim3(kSmallSortBlock), s, A.bucket, rg, cl, cc, rl, keys, vals, ov)) != hipSuccess)
+            return e;
+        return launch_kernel(tile_sort_kernel<kTileSortBlock, kTileSortCap, kSortLong>, dim3(grid(1, nt)),
+                             dim3(kTileSortBlock), s, A.bucket, rg, cl, cc, rl, keys, vals, ov);
+    }
+    {
+        if ((e = launch_kernel(tile_sort_wave_kernel, dim3(grid(8, (nt + 3) / 4)), dim3(256), s, A.bucket, rg, cl, cc,
+                               keys, vals, ov)) != hipSuccess)
+            return e;
+        if ((e = launch_kernel(tile_sort_kernel<kSmallSortBlock, kSmallSortCap, 3>, dim3(grid(8, nt)),
+                               dim3(kSmallSortBlock), s, A.bucket, rg, cl, cc, rl, keys, vals, ov)) != hipSuccess)
+            return e;
+        if ((e = launch_kernel(tile_sort_kernel<kSmallSortBlock, kMidSortCap, 2>, dim3(grid(4, nt)),
+                               dim3(kSmallSortBlock), s, A.bucket, rg, cl, cc, rl, keys, vals, ov)) != hipSuccess)
+            return e;
+        if ((e = launch_kernel(tile_sort_kernel<kLargeSortBlock, kLargeSortCap, 1>, dim3(grid(2, nt)),
+                               dim3(kLargeSortBlock), s, A.bucket, rg, cl, cc, rl, keys, vals, ov)) != hipSuccess)
+            return e;
+        if ((e = launch_kernel(tile_sort_kernel<kTileSortBlock, kTileSortCap, 0>, dim3(grid(1, 1ll << 40)),
+                               dim3(kTileSortBlock), s, A.bucket, rg, cl, cc, rl, keys, vals, ov)) != hipSuccess)
+            return e;
+    }
+    return launch_kernel(tile_merge_kernel<kTileSortBlock, kTileSortCap>, dim3(grid(1, 1ll << 40)),
+                         dim3(kTileSortBlock), s, A.bucket, rg, cl, cc, keys, vals, ov);
 }
 
 hipError_t run_bin_sort(const SortPlan &P, const uint32_t *tt, const float4 *rec, int TX, int TY, char *ws,
