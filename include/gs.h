@@ -436,9 +436,10 @@ size_t gs_render_backward_workspace(int64_t n_instances);
  *  its list instead, adding only its own entries: the same gradients,
  *  slower.
  *  grads: host array of n_segs gradient descriptors (device pointers),
- *  overwritten.  ws: per-instance screen-space accumulators (FP64, 8-byte
- *  aligned: a large Gaussian sums thousands of largely cancelling per-pixel
- *  contributions).
+ *  overwritten (zeros for a Gaussian no view draws).  ws: per-instance
+ *  screen-space accumulators (FP64, 16-byte aligned: a large Gaussian sums
+ *  thousands of largely cancelling per-pixel contributions); only the drawn
+ *  instances' are cleared and used.
  * Errors: as gs_project, plus GS_ERR_WORKSPACE_TOO_SMALL. */
 gs_status gs_render_backward(const gs_gaussians *segs, int32_t n_segs, const gs_camera *cams, int32_t n_views,
                              const uint32_t *view_seg_mask, const gs_params *p, const gs_projected *proj,

@@ -542,7 +542,7 @@ gs_status gs_render_backward(const gs_gaussians *segs, int32_t n_segs, const gs_
     if ((st = check_views(cams, n_views, view_seg_mask, n_segs)) != GS_OK) return st;
     if (!proj || !vals || !tile_ranges || !t_final || !n_contrib || !ws || !grads)
         return fail(GS_ERR_INVALID_ARGUMENT, "NULL argument");
-    if (!aligned(ckpt, 4) || !aligned(ws, 8)) return fail(GS_ERR_INVALID_ARGUMENT, "ckpt or ws misaligned");
+    if (!aligned(ckpt, 4) || !aligned(ws, 16)) return fail(GS_ERR_INVALID_ARGUMENT, "ckpt or ws misaligned");
     std::vector<int64_t> off(n_views + 1);
     instance_offsets(segs, n_segs, n_views, view_seg_mask, off.data());
     if (proj->n_instances != off[n_views])
@@ -562,9 +562,9 @@ gs_status gs_render_backward(const gs_gaussians *segs, int32_t n_segs, const gs_
     double *g2d = static_cast<double *>(ws);
     uint32_t *list = reinterpret_cast<uint32_t *>(static_cast<char *>(ws) + bwd_list_offset(proj->n_instances));
     uint32_t *counts = reinterpret_cast<uint32_t *>(static_cast<char *>(ws) + bwd_count_offset(proj->n_instances));
-    // one fill clears the accumulators and the list counters (the list between them is rewritten)
-    hipError_t e = gs::launch_fill_u32(reinterpret_cast<uint32_t *>(g2d), 0u,
-                                       (int64_t)(bwd_count_offset(proj->n_instances) / 4) + kBwdMaxLaunches, sm);
+    // only the drawn instances' accumulators are used, so only those are
+    // cleared, together with the list counters
+    hipError_t e = gs::launch_clear_g2d(proj->tiles_touched, proj->n_instances, g2d, counts, kBwdMaxLaunches, sm);
     if (e != hipSuccess) return hip_fail(e, "gs_render_backward");
     int launch_no = 0;
     gs::BackwardTileArgs b = {};

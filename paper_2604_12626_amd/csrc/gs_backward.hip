@@ -19,7 +19,10 @@
 //
 // B2 (per Gaussian of a segment, scene-major): chains the screen-space
 // adjoints of every view that drew the Gaussian through the projection to the
-// 3D parameters and writes the dense gradients once (no atomics).
+// 3D parameters and writes the dense gradients once (no atomics).  A first
+// pass over the segment (B2a) writes zeros plane by plane and lists the
+// Gaussians a view of the launch draws; the chain (B2b) then runs over that
+// list only.
 #include "gs_ewa.hpp"
 
 namespace gs {
@@ -54,10 +57,11 @@ template <bool SEG, bool WLDS>
 __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const BackwardTileArgs a) {
     constexpr bool kLds = SEG || WLDS;
     __shared__ float4 s_e0[4][64], s_e1[4][64], s_e2[4][64], s_q[4][64];
-    // 64 list positions: the four quadrant waves add their per-entry sums
-    // here, and the workgroup then issues one set of global atomics per entry
-    // (instead of one per quadrant)
-    __shared__ float s_acc[kLds ? kSegment * kG2D : 1];
+    // 64 list positions: each quadrant wave stores its per-entry sums in its
+    // own row, and the workgroup then adds the four rows in FP64 in a fixed
+    // order and issues one set of global atomics per entry (instead of one
+    // per quadrant)
+    __shared__ float s_acc[4][kLds ? kSegment * kG2D : 1];
     __shared__ uint32_t s_gid[kLds ? kSegment : 1];
     __shared__ uint32_t s_top;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -68,7 +72,7 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
     // quadrant w, one pixel per lane
     const uint32_t n_work = a.seg_list ? a.seg_list[0] : (uint32_t)a.n_items;
     if (kLds) {
-        for (int i = threadIdx.x; i < kSegment * kG2D; i += kTilePixels) s_acc[i] = 0.0f;
+        for (int i = threadIdx.x; i < 4 * kSegment * kG2D; i += kTilePixels) (&s_acc[0][0])[i] = 0.0f;
         __syncthreads();
     }
     for (uint32_t wk = blockIdx.x; wk < n_work; wk += a.n_groups) {
@@ -266,18 +270,18 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
             gz = wave_sum_to_last(gz);
             if (kLds && lds_sum) {
                 if (lane == 63) {
-                    float *acc = s_acc + (pos - (uint32_t)lo) * kG2D;
+                    float *acc = s_acc[wave] + (pos - (uint32_t)lo) * kG2D;
                     s_gid[pos - (uint32_t)lo] = __float_as_uint(e2.z);
-                    atomicAdd(acc + kGU, gu);
-                    atomicAdd(acc + kGV, gv);
-                    atomicAdd(acc + kGA, gA);
-                    atomicAdd(acc + kGB, gB);
-                    atomicAdd(acc + kGC, gC);
-                    atomicAdd(acc + kGO, go);
-                    atomicAdd(acc + kGR, gr);
-                    atomicAdd(acc + kGG, gg);
-                    atomicAdd(acc + kGBl, gb);
-                    atomicAdd(acc + kGZ, gz);
+                    acc[kGU] = gu;
+                    acc[kGV] = gv;
+                    acc[kGA] = gA;
+                    acc[kGB] = gB;
+                    acc[kGC] = gC;
+                    acc[kGO] = go;
+                    acc[kGR] = gr;
+                    acc[kGG] = gg;
+                    acc[kGBl] = gb;
+                    acc[kGZ] = gz;
                 }
             } else if (lane == 63) {
                 double *dst = a.g2d + (size_t)__float_as_uint(e2.z) * kG2D;
@@ -299,11 +303,10 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
             // atomic per nonzero (entry, value), and the accumulator is cleared
             __syncthreads();
             for (int i = threadIdx.x; i < kSegment * kG2D; i += kTilePixels) {
-                const float v = s_acc[i];
-                if (v != 0.0f) {
-                    atomicAdd(a.g2d + (size_t)s_gid[i / kG2D] * kG2D + (i % kG2D), (double)v);
-                    s_acc[i] = 0.0f;
-                }
+                const double v = (((double)s_acc[0][i] + (double)s_acc[1][i]) + (double)s_acc[2][i]) + (double)s_acc[3][i];
+                if (v != 0.0) atomicAdd(a.g2d + (size_t)s_gid[i / kG2D] * kG2D + (i % kG2D), v);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) s_acc[q][i] = 0.0f;
             }
             __syncthreads();
         }
@@ -370,6 +373,69 @@ hipError_t launch_backward_tiles(BackwardTileArgs a, int n_cu, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // B2: screen-space adjoints -> 3D parameters
 // ---------------------------------------------------------------------------
+// zeros for floats [w * i0, w * i1) of a plane of w floats per Gaussian,
+// by the workgroup: 16-byte stores on the 16-byte aligned stretch, single
+// floats at the ends
+__device__ __forceinline__ void zero_plane(float *p, int w, int64_t i0, int64_t i1) {
+    if (!p) return;
+    const int64_t f0 = (int64_t)w * i0, f1 = (int64_t)w * i1;
+    const uint64_t base = (uint64_t)(uintptr_t)p;  // 4-byte aligned (floats)
+    int64_t v0 = f0, v1 = f1;
+    while (((base + 4u * (uint64_t)v0) & 15u) && v0 < f1) ++v0;
+    while (((base + 4u * (uint64_t)v1) & 15u) && v1 > v0) --v1;
+    if (v0 >= v1) {
+        for (int64_t f = f0 + threadIdx.x; f < f1; f += blockDim.x) p[f] = 0.0f;
+        return;
+    }
+    for (int64_t f = f0 + threadIdx.x; f < v0; f += blockDim.x) p[f] = 0.0f;
+    for (int64_t f = v1 + threadIdx.x; f < f1; f += blockDim.x) p[f] = 0.0f;
+    float4 *q = reinterpret_cast<float4 *>(p + v0);
+    for (int64_t k = threadIdx.x; k < (v1 - v0) / 4; k += blockDim.x) q[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+
+// B2a: with the first chunk of views, zeros for every gradient the chain
+// writes, each workgroup's stretch of every plane written with 16-byte stores
+// (the drawn Gaussians are overwritten by B2b; later chunks add to what the
+// first wrote); the drawn Gaussians appended to a.list, positions inside the
+// workgroup from ballots and one atomic per workgroup (order of arrival: each
+// Gaussian is handled on its own)
+__global__ void __launch_bounds__(1024) zero_and_list_kernel(const BackwardProjectArgs a, int sh_floats) {
+    __shared__ uint32_t s_cnt[16], s_base;
+    const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    bool vis = false;
+    if (i < a.seg.n)
+        for (int vi = 0; vi < a.nv && !vis; ++vi) vis = a.tiles_touched[a.base[vi] + i] != 0u;
+    if (a.first) {
+        const int64_t g0 = (int64_t)blockIdx.x * 1024, g1 = g0 + 1024 < a.seg.n ? g0 + 1024 : a.seg.n;
+        const gs_gaussians_grad &G = a.grad;
+        zero_plane(G.means, 3, g0, g1);
+        zero_plane(G.opacity, 1, g0, g1);
+        zero_plane(G.sh, sh_floats, g0, g1);
+        if (a.seg.cov6) {
+            zero_plane(G.cov6, 6, g0, g1);
+        } else {
+            zero_plane(G.log_scales, 3, g0, g1);
+            zero_plane(G.quats, 4, g0, g1);
+        }
+    }
+    const uint64_t bal = __ballot(vis);
+    if (lane == 0) s_cnt[wave] = (uint32_t)__popcll(bal);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t total = 0u;
+        for (int w = 0; w < 16; ++w) {
+            const uint32_t c = s_cnt[w];
+            s_cnt[w] = total;
+            total += c;
+        }
+        s_base = total ? atomicAdd(a.count, total) : 0u;
+    }
+    __syncthreads();
+    if (vis) a.list[s_base + s_cnt[wave] + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull))] = (uint32_t)i;
+}
+
+// B2b: one thread per listed Gaussian
 template <int D>
 __global__ void __launch_bounds__(256) backward_project_kernel(const BackwardProjectArgs a) {
     constexpr int K = (D + 1) * (D + 1);
@@ -388,53 +454,66 @@ __global__ void __launch_bounds__(256) backward_project_kernel(const BackwardPro
     const int64_t li = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (li >= (int64_t)*a.count) return;
     const int64_t i = a.list[li];
+    const bool use_cov6 = a.seg.cov6 != nullptr;
 
+    // FP32 as in the forward where its decisions are repeated (projection,
+    // clamps, colour clamp, SH); FP64 along the chain from the conic back to
+    // the covariance and the mean, where an elongated Gaussian's adjoints
+    // cancel strongly
     const float mx = a.seg.means[3 * i + 0], my = a.seg.means[3 * i + 1], mz = a.seg.means[3 * i + 2];
     float S[6];
-    Rot rot;
-    float sc[3];
-    const bool use_cov6 = a.seg.cov6 != nullptr;
+    double Sd[6], scd[3] = {0.0, 0.0, 0.0};
+    RotT<double> rotd;
     if (use_cov6) {
 #pragma unroll
-        for (int k = 0; k < 6; ++k) S[k] = a.seg.cov6[6 * i + k];
+        for (int k = 0; k < 6; ++k) {
+            S[k] = a.seg.cov6[6 * i + k];
+            Sd[k] = (double)S[k];
+        }
     } else {
         const float4 q = reinterpret_cast<const float4 *>(a.seg.quats)[i];
-        rot = quat_rot(q.x, q.y, q.z, q.w);
+        const Rot rot = quat_rot(q.x, q.y, q.z, q.w);
+        float sc[3];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) sc[k] = expf(a.seg.log_scales[3 * i + k]);
+        for (int k = 0; k < 3; ++k) {
+            const float ls = a.seg.log_scales[3 * i + k];
+            sc[k] = expf(ls);
+            scd[k] = exp((double)ls);
+        }
         cov_from_rot_scale(rot.R, sc, S);
+        rotd = quat_rot_t<double>((double)q.x, (double)q.y, (double)q.z, (double)q.w);
+        cov_from_rot_scale(rotd.R, scd, Sd);
     }
 
-    float dmu[3] = {0.f, 0.f, 0.f};
-    float dS[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // symmetric adjoint of Sigma (xx, xy, xz, yy, yz, zz)
+    double dmu[3] = {0.0, 0.0, 0.0};
+    double dS[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // symmetric adjoint of Sigma (xx, xy, xz, yy, yz, zz)
     float dsh[3 * K];
 #pragma unroll
     for (int k = 0; k < 3 * K; ++k) dsh[k] = 0.f;
     float dop = 0.f;
+    // every listed Gaussian is drawn: its SH rows are requested with the rest
     float sh[3 * K];
-    bool have_sh = false;
+    {
+        const float *src = a.seg.sh + (size_t)(3 * K) * i;
+#pragma unroll
+        for (int k = 0; k < 3 * K; ++k) sh[k] = src[k];
+    }
 
     for (int vi = 0; vi < a.nv; ++vi) {
         const int64_t inst = a.base[vi] + i;
         if (a.tiles_touched[inst] == 0u) continue;
         const double *g = a.g2d + (size_t)inst * kG2D;
-        float gl[kG2D];
+        double gl[kG2D];
 #pragma unroll
-        for (int k = 0; k < kG2D; ++k) gl[k] = (float)g[k];
+        for (int k = 0; k < kG2D; ++k) gl[k] = g[k];
         const float *cam = s_cam + vi * kCamStride;
         ViewProj p;
         // the same FP32 projection as the forward; the instance is known to be
         // visible (tiles_touched > 0), so every field used below is computed
         const int TX = (a.W + kTile - 1) / kTile, TY = (a.H + kTile - 1) / kTile;
         (void)ewa_project(cam, mx, my, mz, S, a.W, a.H, TX, TY, a.near_plane, a.lowpass, a.sigma_cut, a.fov_clamp, p);
-        dop += gl[kGO];
+        dop += (float)gl[kGO];
         // ---- colour -> SH coefficients and view direction
-        if (!have_sh) {
-            const float *src = a.seg.sh + (size_t)(3 * K) * i;
-#pragma unroll
-            for (int k = 0; k < 3 * K; ++k) sh[k] = src[k];
-            have_sh = true;
-        }
         float dx0 = mx - cam[16], dy0 = my - cam[17], dz0 = mz - cam[18];
         const float inv_dist = 1.0f / sqrtf(dx0 * dx0 + dy0 * dy0 + dz0 * dz0);
         const float x = dx0 * inv_dist, y = dy0 * inv_dist, z = dz0 * inv_dist;
@@ -442,7 +521,7 @@ __global__ void __launch_bounds__(256) backward_project_kernel(const BackwardPro
         float3 dY[K];
         sh_basis<D>(x, y, z, Y);
         sh_basis_grad<D>(x, y, z, dY);
-        float dc[3] = {gl[kGR], gl[kGG], gl[kGBl]};
+        float dc[3] = {(float)gl[kGR], (float)gl[kGG], (float)gl[kGBl]};
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
             float acc = 0.0f;  // same accumulation order as the forward
@@ -461,22 +540,51 @@ __global__ void __launch_bounds__(256) backward_project_kernel(const BackwardPro
             for (int ch = 0; ch < 3; ++ch) dsh[3 * k + ch] += dc[ch] * Y[k];
         }
         const float dd = x * ddx + y * ddy + z * ddz;
-        dmu[0] += (ddx - x * dd) * inv_dist;
-        dmu[1] += (ddy - y * dd) * inv_dist;
-        dmu[2] += (ddz - z * dd) * inv_dist;
+        dmu[0] += (double)((ddx - x * dd) * inv_dist);
+        dmu[1] += (double)((ddy - y * dd) * inv_dist);
+        dmu[2] += (double)((ddz - z * dd) * inv_dist);
+        // ---- the projection in FP64, with the forward's clamp decisions
+        double R[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) R[k] = (double)cam[k];
+        const double fxc = (double)cam[12], fyc = (double)cam[13];
+        const double tx = R[0] * mx + R[1] * my + R[2] * mz + (double)cam[9];
+        const double ty = R[3] * mx + R[4] * my + R[5] * mz + (double)cam[10];
+        const double tz = R[6] * mx + R[7] * my + R[8] * mz + (double)cam[11];
+        const double iz = 1.0 / tz, iz2 = iz * iz;
+        const double limx = (double)a.fov_clamp * (0.5 * (double)a.W / fxc);
+        const double limy = (double)a.fov_clamp * (0.5 * (double)a.H / fyc);
+        const double xr = p.clx ? (tx * iz < 0.0 ? -limx : limx) : tx * iz;
+        const double yr = p.cly ? (ty * iz < 0.0 ? -limy : limy) : ty * iz;
+        const double j00 = fxc * iz, j02 = -fxc * xr * iz, j11 = fyc * iz, j12 = -fyc * yr * iz;
+        double T0[3], T1[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            T0[k] = j00 * R[k] + j02 * R[6 + k];
+            T1[k] = j11 * R[3 + k] + j12 * R[6 + k];
+        }
+        double TS0[3], TS1[3];  // T Sigma
+        TS0[0] = T0[0] * Sd[0] + T0[1] * Sd[1] + T0[2] * Sd[2];
+        TS0[1] = T0[0] * Sd[1] + T0[1] * Sd[3] + T0[2] * Sd[4];
+        TS0[2] = T0[0] * Sd[2] + T0[1] * Sd[4] + T0[2] * Sd[5];
+        TS1[0] = T1[0] * Sd[0] + T1[1] * Sd[1] + T1[2] * Sd[2];
+        TS1[1] = T1[0] * Sd[1] + T1[1] * Sd[3] + T1[2] * Sd[4];
+        TS1[2] = T1[0] * Sd[2] + T1[1] * Sd[4] + T1[2] * Sd[5];
+        const double lp = (double)a.lowpass;
+        const double ca = TS0[0] * T0[0] + TS0[1] * T0[1] + TS0[2] * T0[2] + lp;
+        const double cb = TS0[0] * T1[0] + TS0[1] * T1[1] + TS0[2] * T1[2];
+        const double cc = TS1[0] * T1[0] + TS1[1] * T1[1] + TS1[2] * T1[2] + lp;
+        const double idet = 1.0 / (ca * cc - cb * cb);
+        const double qa = cc * idet, qb = -cb * idet, qc = ca * idet;
         // ---- conic -> 2D covariance: dS2 = -Q Gm Q, Gm = [[gA, gB/2], [gB/2, gC]]
-        const float qa = p.A, qb = p.B, qc = p.C;
-        const float ga = gl[kGA], gbh = 0.5f * gl[kGB], gc = gl[kGC];
-        // Q Gm
-        const float m00 = qa * ga + qb * gbh, m01 = qa * gbh + qb * gc;
-        const float m10 = qb * ga + qc * gbh, m11 = qb * gbh + qc * gc;
-        const float s00 = -(m00 * qa + m01 * qb);
-        const float s01 = -(m00 * qb + m01 * qc);
-        const float s11 = -(m10 * qb + m11 * qc);
-        // ---- 2D covariance -> Sigma and T:  S2 = T Sigma T^T + lp I
-        const float *T0 = p.T0, *T1 = p.T1;
-        // dSigma += T^T dS2 T
-        float U[3][2];
+        const double ga = gl[kGA], gbh = 0.5 * gl[kGB], gc = gl[kGC];
+        const double m00 = qa * ga + qb * gbh, m01 = qa * gbh + qb * gc;
+        const double m10 = qb * ga + qc * gbh, m11 = qb * gbh + qc * gc;
+        const double s00 = -(m00 * qa + m01 * qb);
+        const double s01 = -(m00 * qb + m01 * qc);
+        const double s11 = -(m10 * qb + m11 * qc);
+        // ---- 2D covariance -> Sigma and T:  S2 = T Sigma T^T + lp I; dSigma += T^T dS2 T
+        double U[3][2];
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
             U[r][0] = T0[r] * s00 + T1[r] * s01;
@@ -489,42 +597,32 @@ __global__ void __launch_bounds__(256) backward_project_kernel(const BackwardPro
         dS[4] += U[1][0] * T0[2] + U[1][1] * T1[2];
         dS[5] += U[2][0] * T0[2] + U[2][1] * T1[2];
         // dT = 2 dS2 T Sigma
-        float TS0[3], TS1[3];
-        TS0[0] = T0[0] * S[0] + T0[1] * S[1] + T0[2] * S[2];
-        TS0[1] = T0[0] * S[1] + T0[1] * S[3] + T0[2] * S[4];
-        TS0[2] = T0[0] * S[2] + T0[1] * S[4] + T0[2] * S[5];
-        TS1[0] = T1[0] * S[0] + T1[1] * S[1] + T1[2] * S[2];
-        TS1[1] = T1[0] * S[1] + T1[1] * S[3] + T1[2] * S[4];
-        TS1[2] = T1[0] * S[2] + T1[1] * S[4] + T1[2] * S[5];
-        float dT0[3], dT1[3];
+        double dT0[3], dT1[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            dT0[c] = 2.f * (s00 * TS0[c] + s01 * TS1[c]);
-            dT1[c] = 2.f * (s01 * TS0[c] + s11 * TS1[c]);
+            dT0[c] = 2.0 * (s00 * TS0[c] + s01 * TS1[c]);
+            dT1[c] = 2.0 * (s01 * TS0[c] + s11 * TS1[c]);
         }
         // T = J W: dJ = dT W^T;  J00 = fx/z, J02 = -fx xr/z, J11 = fy/z, J12 = -fy yr/z
-        const float *R = cam;
-        const float dJ00 = dT0[0] * R[0] + dT0[1] * R[1] + dT0[2] * R[2];
-        const float dJ02 = dT0[0] * R[6] + dT0[1] * R[7] + dT0[2] * R[8];
-        const float dJ11 = dT1[0] * R[3] + dT1[1] * R[4] + dT1[2] * R[5];
-        const float dJ12 = dT1[0] * R[6] + dT1[1] * R[7] + dT1[2] * R[8];
-        const float fxc = cam[12], fyc = cam[13];
-        const float tz = p.tz, iz = 1.0f / tz, iz2 = iz * iz;
-        float dtx = 0.f, dty = 0.f, dtz = 0.f;
+        const double dJ00 = dT0[0] * R[0] + dT0[1] * R[1] + dT0[2] * R[2];
+        const double dJ02 = dT0[0] * R[6] + dT0[1] * R[7] + dT0[2] * R[8];
+        const double dJ11 = dT1[0] * R[3] + dT1[1] * R[4] + dT1[2] * R[5];
+        const double dJ12 = dT1[0] * R[6] + dT1[1] * R[7] + dT1[2] * R[8];
+        double dtx = 0.0, dty = 0.0, dtz = 0.0;
         dtz += -fxc * iz2 * dJ00 - fyc * iz2 * dJ11;
-        dtz += dJ02 * fxc * p.xr * iz2 + dJ12 * fyc * p.yr * iz2;
+        dtz += dJ02 * fxc * xr * iz2 + dJ12 * fyc * yr * iz2;
         if (!p.clx) {
             dtx += dJ02 * (-fxc * iz) * iz;
-            dtz += dJ02 * (-fxc * iz) * (-p.tx * iz2);
+            dtz += dJ02 * (-fxc * iz) * (-tx * iz2);
         }
         if (!p.cly) {
             dty += dJ12 * (-fyc * iz) * iz;
-            dtz += dJ12 * (-fyc * iz) * (-p.ty * iz2);
+            dtz += dJ12 * (-fyc * iz) * (-ty * iz2);
         }
         // ---- projected mean and depth
         dtx += gl[kGU] * fxc * iz;
         dty += gl[kGV] * fyc * iz;
-        dtz += -gl[kGU] * fxc * p.tx * iz2 - gl[kGV] * fyc * p.ty * iz2 + gl[kGZ];
+        dtz += -gl[kGU] * fxc * tx * iz2 - gl[kGV] * fyc * ty * iz2 + gl[kGZ];
         dmu[0] += R[0] * dtx + R[3] * dty + R[6] * dtz;
         dmu[1] += R[1] * dtx + R[4] * dty + R[7] * dtz;
         dmu[2] += R[2] * dtx + R[5] * dty + R[8] * dtz;
@@ -537,7 +635,7 @@ __global__ void __launch_bounds__(256) backward_project_kernel(const BackwardPro
         else *dst += v;
     };
 #pragma unroll
-    for (int k = 0; k < 3; ++k) put(&G.means[3 * i + k], dmu[k]);
+    for (int k = 0; k < 3; ++k) put(&G.means[3 * i + k], (float)dmu[k]);
     put(&G.opacity[i], dop);
     {
         float *dst = G.sh + (size_t)(3 * K) * i;
@@ -547,95 +645,62 @@ __global__ void __launch_bounds__(256) backward_project_kernel(const BackwardPro
     if (use_cov6) {
         if (G.cov6) {
             // an off-diagonal cov6 entry stands for both symmetric entries
-            put(&G.cov6[6 * i + 0], dS[0]);
-            put(&G.cov6[6 * i + 1], 2.0f * dS[1]);
-            put(&G.cov6[6 * i + 2], 2.0f * dS[2]);
-            put(&G.cov6[6 * i + 3], dS[3]);
-            put(&G.cov6[6 * i + 4], 2.0f * dS[4]);
-            put(&G.cov6[6 * i + 5], dS[5]);
+            put(&G.cov6[6 * i + 0], (float)dS[0]);
+            put(&G.cov6[6 * i + 1], (float)(2.0 * dS[1]));
+            put(&G.cov6[6 * i + 2], (float)(2.0 * dS[2]));
+            put(&G.cov6[6 * i + 3], (float)dS[3]);
+            put(&G.cov6[6 * i + 4], (float)(2.0 * dS[4]));
+            put(&G.cov6[6 * i + 5], (float)dS[5]);
         }
     } else {
         // adjoint of every entry of the full symmetric Sigma
-        const float full[9] = {dS[0], dS[1], dS[2], dS[1], dS[3], dS[4], dS[2], dS[4], dS[5]};
-        float dls[3], dq[4];
-        cov_backward(rot, sc, full, dls, dq);
+        const double full[9] = {dS[0], dS[1], dS[2], dS[1], dS[3], dS[4], dS[2], dS[4], dS[5]};
+        double dls[3], dq[4];
+        cov_backward(rotd, scd, full, dls, dq);
         if (G.log_scales) {
 #pragma unroll
-            for (int k = 0; k < 3; ++k) put(&G.log_scales[3 * i + k], dls[k]);
+            for (int k = 0; k < 3; ++k) put(&G.log_scales[3 * i + k], (float)dls[k]);
         }
         if (G.quats) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) put(&G.quats[4 * i + k], dq[k]);
+            for (int k = 0; k < 4; ++k) put(&G.quats[4 * i + k], (float)dq[k]);
         }
     }
 }
 
-// Dense gradients start at zero: every plane of the segment is cleared here
-// (a Gaussian no view draws keeps zeros), and backward_project_kernel then
-// writes the Gaussians of the compacted list only.
-__global__ void __launch_bounds__(256) zero_grads_kernel(gs_gaussians_grad g, int64_t n, int sh_floats,
-                                                         int64_t stride) {
-    float *planes[6] = {g.means, g.log_scales, g.quats, g.cov6, g.opacity, g.sh};
-    const int width[6] = {3, 3, 4, 6, 1, sh_floats};
+// The screen-space accumulators of the drawn instances start at zero; B1
+// adds only to those and B2 reads only those.
+__global__ void __launch_bounds__(256) clear_g2d_kernel(const uint32_t *tt, int64_t n, double *g2d,
+                                                        uint32_t *counts, int n_counts) {
+    static_assert(kG2D % 2 == 0, "two accumulators per 16-B store");
+    if (blockIdx.x == 0)
+        for (int k = threadIdx.x; k < n_counts; k += 256) counts[k] = 0u;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        if (tt[i]) {
+            double2 *g = reinterpret_cast<double2 *>(g2d + (size_t)i * kG2D);
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        float *p = planes[k];
-        if (!p) continue;
-        const int64_t m = n * width[k];
-        for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < m; j += stride) p[j] = 0.0f;
-    }
+            for (int k = 0; k < kG2D / 2; ++k) g[k] = make_double2(0.0, 0.0);
+        }
 }
 
-// Gaussians of the segment with an instance drawn (tiles_touched > 0) in one
-// of the chunk's views, appended to a.list: positions inside a 1024-thread
-// workgroup come from ballots and a prefix over its 16 waves, and one atomic
-// per workgroup reserves its stretch (order of arrival; each Gaussian is
-// handled on its own, so the order does not affect any result)
-__global__ void __launch_bounds__(1024) compact_visible_kernel(const BackwardProjectArgs a) {
-    __shared__ uint32_t s_cnt[16], s_base;
-    const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    bool vis = false;
-    if (i < a.seg.n)
-        for (int vi = 0; vi < a.nv && !vis; ++vi) vis = a.tiles_touched[a.base[vi] + i] != 0u;
-    const uint64_t bal = __ballot(vis);
-    if (lane == 0) s_cnt[wave] = (uint32_t)__popcll(bal);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t total = 0u;
-        for (int w = 0; w < 16; ++w) {
-            const uint32_t c = s_cnt[w];
-            s_cnt[w] = total;
-            total += c;
-        }
-        s_base = total ? atomicAdd(a.count, total) : 0u;
-    }
-    __syncthreads();
-    if (vis) {
-        const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-        a.list[s_base + s_cnt[wave] + (uint32_t)__popcll(bal & lt)] = (uint32_t)i;
-    }
+hipError_t launch_clear_g2d(const uint32_t *tiles_touched, int64_t n_instances, double *g2d, uint32_t *counts,
+                            int n_counts, hipStream_t s) {
+    int64_t grid = (n_instances + 255) / 256;
+    if (grid > 8192) grid = 8192;
+    if (grid < 1) grid = 1;
+    return launch_kernel(clear_g2d_kernel, dim3((unsigned)grid), dim3(256), s, tiles_touched, n_instances, g2d,
+                         counts, n_counts);
 }
 
 hipError_t launch_backward_project(const BackwardProjectArgs &a, hipStream_t s) {
     if (a.seg.n == 0) return hipSuccess;
-    const unsigned grid = (unsigned)((a.seg.n + 255) / 256);
+    const int K = (a.seg.sh_degree + 1) * (a.seg.sh_degree + 1);
     hipError_t e;
-    if (a.first) {
-        int64_t zb = (a.seg.n * 48 + 255) / 256;
-        if (zb > 4096) zb = 4096;
-        const int K = (a.seg.sh_degree + 1) * (a.seg.sh_degree + 1);
-        gs_gaussians_grad g = a.grad;
-        if (a.seg.cov6) g.log_scales = g.quats = nullptr;  // not written for covariance segments
-        else g.cov6 = nullptr;
-        if ((e = launch_kernel(zero_grads_kernel, dim3((unsigned)zb), dim3(256), s, g, a.seg.n, 3 * K, zb * 256)) !=
-            hipSuccess)
-            return e;
-    }
-    if (a.nv == 0) return hipSuccess;
-    if ((e = launch_kernel(compact_visible_kernel, dim3((unsigned)((a.seg.n + 1023) / 1024)), dim3(1024), s, a)) !=
+    if ((e = launch_kernel(zero_and_list_kernel, dim3((unsigned)((a.seg.n + 1023) / 1024)), dim3(1024), s, a, 3 * K)) !=
         hipSuccess)
         return e;
+    if (a.nv == 0) return hipSuccess;
+    const unsigned grid = (unsigned)((a.seg.n + 255) / 256);
     switch (a.seg.sh_degree) {
         case 0: return launch_kernel(backward_project_kernel<0>, dim3(grid), dim3(256), s, a);
         case 1: return launch_kernel(backward_project_kernel<1>, dim3(grid), dim3(256), s, a);

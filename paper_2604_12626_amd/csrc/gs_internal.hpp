@@ -48,8 +48,8 @@ struct BackwardProjectArgs {
     int32_t first;     // 1: overwrite the gradients, 0: accumulate (later chunk of views)
     int32_t W, H;
     float near_plane, lowpass, sigma_cut, fov_clamp;
-    uint32_t *list;    // [seg.n]: Gaussians with an instance drawn in one of the views (compacted)
-    uint32_t *count;   // number of entries of `list` (zero before the compaction)
+    uint32_t *list;   // [seg.n]: Gaussians with an instance drawn in one of the views (compacted)
+    uint32_t *count;  // number of entries of `list` (zero before the compaction)
 };
 
 struct CompositeArgs {
@@ -203,6 +203,10 @@ hipError_t launch_tile_order(const uint32_t *ranges, int64_t n_items, uint32_t *
 hipError_t launch_composite(CompositeArgs a, int grid, hipStream_t s);
 hipError_t launch_backward_tiles(BackwardTileArgs a, int n_cu, hipStream_t s);
 hipError_t launch_backward_project(const BackwardProjectArgs &a, hipStream_t s);
+// zeroes the screen-space accumulators of the drawn instances (tiles_touched
+// > 0) and the n_counts list counters
+hipError_t launch_clear_g2d(const uint32_t *tiles_touched, int64_t n_instances, double *g2d, uint32_t *counts,
+                            int n_counts, hipStream_t s);
 hipError_t launch_lbs(const LbsArgs &a, bool backward, hipStream_t s);
 hipError_t launch_lbs_joint_grad(const LbsArgs &a, float *d_skin, int n_cu, hipStream_t s);
 hipError_t launch_fk(const FkArgs &a, hipStream_t s);
@@ -322,22 +326,27 @@ __device__ __forceinline__ void sh_basis_grad(float x, float y, float z, float3 
 }
 
 // Unit quaternion (w, x, y, z) -> rotation matrix (row-major).  A quaternion
-// with |q|^2 < 1e-24 stands for the identity.
-struct Rot {
-    float R[9];
-    float q[4];   // normalised
-    float inv_n;  // 1/|q|, 0 for the identity fallback
+// with |q|^2 < 1e-24 stands for the identity.  Templated on the arithmetic
+// type: FP32 where the forward's decisions are made, FP64 in the backward's
+// chain through the projection.
+template <typename F>
+struct RotT {
+    F R[9];
+    F q[4];   // normalised
+    F inv_n;  // 1/|q|, 0 for the identity fallback
 };
+using Rot = RotT<float>;
 
-__device__ __forceinline__ Rot quat_rot(float w, float x, float y, float z) {
-    Rot o;
-    const float n2 = w * w + x * x + y * y + z * z;
-    if (!(n2 >= 1e-24f)) {
-        w = 1.f;
-        x = y = z = 0.f;
-        o.inv_n = 0.f;
+template <typename F>
+__device__ __forceinline__ RotT<F> quat_rot_t(F w, F x, F y, F z) {
+    RotT<F> o;
+    const F n2 = w * w + x * x + y * y + z * z;
+    if (!(n2 >= (F)1e-24f)) {
+        w = (F)1;
+        x = y = z = (F)0;
+        o.inv_n = (F)0;
     } else {
-        const float inv = 1.0f / sqrtf(n2);
+        const F inv = (F)1 / sqrt(n2);
         w *= inv;
         x *= inv;
         y *= inv;
@@ -348,21 +357,23 @@ __device__ __forceinline__ Rot quat_rot(float w, float x, float y, float z) {
     o.q[1] = x;
     o.q[2] = y;
     o.q[3] = z;
-    o.R[0] = 1.f - 2.f * (y * y + z * z);
-    o.R[1] = 2.f * (x * y - w * z);
-    o.R[2] = 2.f * (x * z + w * y);
-    o.R[3] = 2.f * (x * y + w * z);
-    o.R[4] = 1.f - 2.f * (x * x + z * z);
-    o.R[5] = 2.f * (y * z - w * x);
-    o.R[6] = 2.f * (x * z - w * y);
-    o.R[7] = 2.f * (y * z + w * x);
-    o.R[8] = 1.f - 2.f * (x * x + y * y);
+    o.R[0] = (F)1 - (F)2 * (y * y + z * z);
+    o.R[1] = (F)2 * (x * y - w * z);
+    o.R[2] = (F)2 * (x * z + w * y);
+    o.R[3] = (F)2 * (x * y + w * z);
+    o.R[4] = (F)1 - (F)2 * (x * x + z * z);
+    o.R[5] = (F)2 * (y * z - w * x);
+    o.R[6] = (F)2 * (x * z - w * y);
+    o.R[7] = (F)2 * (y * z + w * x);
+    o.R[8] = (F)1 - (F)2 * (x * x + y * y);
     return o;
 }
+__device__ __forceinline__ Rot quat_rot(float w, float x, float y, float z) { return quat_rot_t<float>(w, x, y, z); }
 
 // Sigma = R diag(s^2) R^T as (xx, xy, xz, yy, yz, zz)
-__device__ __forceinline__ void cov_from_rot_scale(const float *R, const float *s, float *c6) {
-    float M[9];
+template <typename F>
+__device__ __forceinline__ void cov_from_rot_scale(const F *R, const F *s, F *c6) {
+    F M[9];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -377,9 +388,9 @@ __device__ __forceinline__ void cov_from_rot_scale(const float *R, const float *
 
 // Adjoint of Sigma = (R S)(R S)^T w.r.t. log-scales and the raw quaternion,
 // given the symmetric adjoint dS (full 3x3, row-major).
-__device__ __forceinline__ void cov_backward(const Rot &rot, const float *s, const float *dS, float *dlog_s,
-                                             float *dq) {
-    float M[9], dM[9];
+template <typename F>
+__device__ __forceinline__ void cov_backward(const RotT<F> &rot, const F *s, const F *dS, F *dlog_s, F *dq) {
+    F M[9], dM[9];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -389,7 +400,7 @@ __device__ __forceinline__ void cov_backward(const Rot &rot, const float *s, con
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            float acc = 0.f;
+            F acc = (F)0;
 #pragma unroll
             for (int k = 0; k < 3; ++k) acc += (dS[3 * i + k] + dS[3 * k + i]) * M[3 * k + j];
             dM[3 * i + j] = acc;
@@ -397,25 +408,25 @@ __device__ __forceinline__ void cov_backward(const Rot &rot, const float *s, con
 #pragma unroll
     for (int k = 0; k < 3; ++k)
         dlog_s[k] = s[k] * (rot.R[k] * dM[k] + rot.R[3 + k] * dM[3 + k] + rot.R[6 + k] * dM[6 + k]);
-    if (rot.inv_n == 0.f) {
-        dq[0] = dq[1] = dq[2] = dq[3] = 0.f;
+    if (rot.inv_n == (F)0) {
+        dq[0] = dq[1] = dq[2] = dq[3] = (F)0;
         return;
     }
-    float dR[9];
+    F dR[9];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j) dR[3 * i + j] = dM[3 * i + j] * s[j];
-    const float w = rot.q[0], x = rot.q[1], y = rot.q[2], z = rot.q[3];
-    float g[4];
-    g[0] = 2.f * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
-    g[1] = 2.f * (y * dR[1] + z * dR[2] + y * dR[3] - 2.f * x * dR[4] - w * dR[5] + z * dR[6] + w * dR[7] -
-                  2.f * x * dR[8]);
-    g[2] = 2.f * (-2.f * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] + z * dR[7] -
-                  2.f * y * dR[8]);
-    g[3] = 2.f * (-2.f * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.f * z * dR[4] + y * dR[5] + x * dR[6] +
-                  y * dR[7]);
-    const float qd = w * g[0] + x * g[1] + y * g[2] + z * g[3];
+    const F w = rot.q[0], x = rot.q[1], y = rot.q[2], z = rot.q[3];
+    F g[4];
+    g[0] = (F)2 * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+    g[1] = (F)2 * (y * dR[1] + z * dR[2] + y * dR[3] - (F)2 * x * dR[4] - w * dR[5] + z * dR[6] + w * dR[7] -
+                   (F)2 * x * dR[8]);
+    g[2] = (F)2 * (-(F)2 * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] + z * dR[7] -
+                   (F)2 * y * dR[8]);
+    g[3] = (F)2 * (-(F)2 * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - (F)2 * z * dR[4] + y * dR[5] + x * dR[6] +
+                   y * dR[7]);
+    const F qd = w * g[0] + x * g[1] + y * g[2] + z * g[3];
 #pragma unroll
     for (int c = 0; c < 4; ++c) dq[c] = (g[c] - rot.q[c] * qd) * rot.inv_n;
 }

@@ -317,8 +317,6 @@ def test_segmented_backward_with_a_short_checkpoint_buffer(dev, orc):
     r = render.Renderer(W, H, capacity=1 << 18, device=dev, checkpoints=True)
     f = r.render([tg], cams, [[0]])
     K = int(f.num.item())
-    f.ckpt = f.ckpt[:B.checkpoint_floats(K // 3)]
-    say("short checkpoint buffer: %d keys, checkpoints for %d" % (K, K // 3))
     full = f.ckpt
     d_full = {k: v.clone() for k, v in r.backward([tg], cams, [[0]], f, *G)[0].items()}
     f.ckpt = full[:B.checkpoint_floats(K // 3)]
