@@ -228,7 +228,8 @@ def bench_fwd_bwd(args, dev, steps, want_pairs=True):
     """Forward + backward of one 256x256 view of a 500k-Gaussian SH3 room:
     L = sum |rgb - rgb*|^2 + sum (D - D*)^2 against the render of the
     perturbed parameters; one step = forward (recording segment checkpoints),
-    loss adjoint, backward with dense gradients of every parameter."""
+    loss adjoint, backward with dense gradients of every parameter, replayed
+    from one HIP graph."""
     import torch
     from paper_2604_12626_amd import render, synth
     cfg = synth.config(2)
@@ -246,14 +247,15 @@ def bench_fwd_bwd(args, dev, steps, want_pairs=True):
     d_rgb, d_depth = torch.empty_like(ft.rgb), torch.empty_like(ft.depth)
     r.render(segs, cams, vs)  # sizes the key capacity for the timed parameters
 
-    def step():
-        f2 = r.render(segs, cams, vs, sync_check=False)
+    def after(f2):
         torch.add(neg2_rgb_t, f2.rgb, alpha=2.0, out=d_rgb)
         torch.add(neg2_depth_t, f2.depth, alpha=2.0, out=d_depth)
-        r.backward(segs, cams, vs, f2, d_rgb, d_depth, None)
+        return r.backward(segs, cams, vs, f2, d_rgb, d_depth, None)
 
-    ms = _time_seq(step, max(2, args.warmup // 2), steps)
-    assert int(r._bufs["ovf"][0].item()) == 0
+    # the whole step -- forward, loss adjoint, backward -- replayed from one graph
+    cap = render.CapturedRender(r, segs, cams, vs, checkpoints="auto", after=after)
+    ms = _time_seq(cap.replay, max(2, args.warmup // 2), steps)
+    assert not cap.overflowed()
     f = r.render(segs, cams, vs)
     torch.cuda.synchronize()
     c = _frame_counts(f, 1, r.T, W * H, g["sh_degree"], len(g["means"]), len(g["means"]))
@@ -318,8 +320,8 @@ def bench_avatars(args, dev, steps, want_pairs=True):
     avatar Gaussians, then all views of room + posed avatars in one call
     (forward, captured with the skinning into one HIP graph), and the same
     with the backward through the renderer and LBS to the canonical avatar
-    parameters (fwd+bwd; checkpoints "auto", which leaves them off for 19200
-    tile lists)."""
+    parameters (fwd+bwd, also one graph; checkpoints "auto", which leaves
+    them off for 19200 tile lists)."""
     import torch
     from paper_2604_12626_amd import autotune, binding as B, render
     from paper_2604_12626_amd import synth
@@ -356,18 +358,23 @@ def bench_avatars(args, dev, steps, want_pairs=True):
                                 before=lbs)
     ms = _time_seq(cap.replay, args.warmup, steps)
     assert not cap.overflowed()
-    rb = render.Renderer(W, H, capacity=1 << 24, device=dev, checkpoints="auto")
-    fb = rb.render([room, posed], cams, vs)
+    rb = render.Renderer(W, H, capacity=r.capacity, device=dev, checkpoints="auto")
+    neg2_target = -2.0 * target
+    d_rgb = torch.empty_like(target)
 
-    def frame_bwd():
-        lbs()
-        rb.enqueue([room, posed], cams, vs, fb)
-        gr = rb.backward([room, posed], cams, vs, fb, 2.0 * (fb.rgb - target), None, None)
+    def after(fb):
+        # loss adjoint 2 (rgb - target), backward through the renderer, then LBS
+        torch.add(neg2_target, fb.rgb, alpha=2.0, out=d_rgb)
+        gr = rb.backward([room, posed], cams, vs, fb, d_rgb, None, None)
         B.deform_lbs_backward(av["means"], av["log_scales"], av["quats"], av["joint_idx"], av["weights"],
                               av["avatar_of"], skin, gr[1]["means"], gr[1]["cov6"], d_means, d_ls, d_q)
+        return gr
 
-    ms_b = _time_seq(frame_bwd, max(2, args.warmup // 2), max(3, steps // 2))
-    assert int(f.overflow.item()) == 0 and int(fb.overflow.item()) == 0
+    # skinning, forward, loss adjoint and the whole backward replayed from one graph
+    cap_b = render.CapturedRender(rb, [room, posed], cams, vs, checkpoints="auto", before=lbs, after=after)
+    ms_b = _time_seq(cap_b.replay, max(2, args.warmup // 2), max(3, steps // 2))
+    fb = cap_b.frame
+    assert int(f.overflow.item()) == 0 and not cap_b.overflowed()
     N_room = int(room["means"].shape[0])
     counts = _frame_counts(f, len(vs), r.T, W * H, 3, N_room + n_av, len(vs) * (N_room + n_av))
     counts["n_av"] = int(n_av)

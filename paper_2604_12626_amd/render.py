@@ -221,8 +221,9 @@ def observation_two_pass(scene, avatars, out=None):
 
 class CapturedRender:
     """A forward frame (optionally preceded by other launches, e.g. the
-    skinning of avatar Gaussians) captured once into a HIP graph and
-    replayed with no host work per frame.
+    skinning of avatar Gaussians, and followed by others, e.g. a loss
+    adjoint and the backward) captured once into a HIP graph and replayed
+    with no host work per frame.
 
     The captured kernels hold raw device pointers: to the renderer's
     buffers, to the frame's outputs and to the inputs (segments, cameras,
@@ -238,9 +239,14 @@ class CapturedRender:
     The key capacity is sized by an eager render first (growing on
     overflow).  A replay cannot grow it: after replays, `overflowed()`
     synchronises and reports whether any frame needed more keys than the
-    capacity (its image is then incomplete; capture again)."""
+    capacity (its image is then incomplete; capture again).
 
-    def __init__(self, renderer, segs, cams, view_segs=None, checkpoints=False, before=None):
+    after(frame), when given, is called after the forward's launches, in
+    the capture and in its eager warm-up; what it returns (say, the
+    gradient tensors of a backward) is kept as `self.after_out`, the
+    tensors the replays write."""
+
+    def __init__(self, renderer, segs, cams, view_segs=None, checkpoints=False, before=None, after=None):
         if view_segs is None:
             view_segs = [list(range(len(segs)))] * int(cams.shape[0])
         self.renderer = renderer
@@ -248,6 +254,8 @@ class CapturedRender:
         self.cams = cams
         self.view_segs = [list(v) for v in view_segs]
         self.before = before
+        self.after = after
+        self.after_out = None
         if before is not None:
             before()
         self.frame = renderer.render(self.segs, cams, self.view_segs, checkpoints=checkpoints)
@@ -262,13 +270,14 @@ class CapturedRender:
         torch.cuda.synchronize()
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph):
-            self._enqueue()
+            self.after_out = self._enqueue()
         torch.cuda.synchronize()
 
     def _enqueue(self):
         if self.before is not None:
             self.before()
         self.renderer.enqueue(self.segs, self.cams, self.view_segs, self.frame)
+        return self.after(self.frame) if self.after is not None else None
 
     def replay(self):
         """Enqueue one frame on torch's current stream; outputs in self.frame."""

@@ -130,3 +130,54 @@ def test_captured_avatar_frame_with_skinning_replays_bit_exact():
     ref = [t.clone() for t in (f.rgb, f.depth, f.alpha, f.n_contrib)]
     _replays_equal_eager(cap, ref, between=lambda: eager.render([room, posed], cams, vs))
     say("  3 replays after a pose change equal the eager frame")
+
+
+def test_captured_forward_backward_step_replays():
+    """The whole training step of the 500k-Gaussian view at 1/10 of its size
+    -- forward with segment checkpoints, the L2 loss adjoint, the backward to
+    every parameter -- captured into one graph: each replay reproduces the
+    eager step's images bit for bit and its gradients up to the order of the
+    FP64 accumulators' atomic additions (1e-6 of each block's largest)."""
+    import torch
+    from paper_2604_12626_amd import binding as B, render
+    B.load()
+    dev = torch.device("cuda:0")
+    cfg = synth.config(2, scale=0.1)
+    W, H = cfg["W"], cfg["H"]
+    say("graph capture: forward + loss adjoint + backward, 256x256")
+    segs = [to_dev(cfg["segments"][0], dev)]
+    cams = torch.from_numpy(cfg["cams"]).to(dev)
+    target = torch.rand(1, H, W, 3, device=dev)
+    neg2_t = -2.0 * target
+    d_rgb = torch.empty_like(target)
+    eager = render.Renderer(W, H, capacity=1 << 20, device=dev, checkpoints="auto")
+    fe = eager.render(segs, cams, [[0]])
+    ge = eager.backward(segs, cams, [[0]], fe, 2.0 * (fe.rgb - target), None, None)[0]
+    ref_img = [t.clone() for t in (fe.rgb, fe.depth, fe.alpha)]
+    ref_g = {k: v.clone() for k, v in ge.items()}
+    rc = render.Renderer(W, H, capacity=1 << 20, device=dev, checkpoints="auto")
+
+    def after(f):
+        torch.add(neg2_t, f.rgb, alpha=2.0, out=d_rgb)
+        return rc.backward(segs, cams, [[0]], f, d_rgb, None, None)
+
+    cap = render.CapturedRender(rc, segs, cams, [[0]], checkpoints="auto", after=after)
+    gc.collect()
+    torch.cuda.empty_cache()
+    for k in range(3):
+        for t in (cap.frame.rgb, cap.frame.depth, cap.frame.alpha):
+            t.fill_(-1.0)
+        for t in cap.after_out[0].values():
+            t.fill_(float("nan"))
+        cap.replay()
+        torch.cuda.synchronize()
+        for a, b in zip((cap.frame.rgb, cap.frame.depth, cap.frame.alpha), ref_img):
+            assert torch.equal(a, b), k
+        for name, ref in ref_g.items():
+            got = cap.after_out[0][name]
+            err = float((got - ref).abs().max() / ref.abs().max())
+            assert err <= 1e-6, (k, name, err)
+        eager.render(segs, cams, [[0]])  # eager work between replays
+        torch.cuda.synchronize()
+        say("  replay %d: images equal, gradients within 1e-6" % k)
+    assert not cap.overflowed()
