@@ -592,7 +592,28 @@ gs_status gs_render_backward(const gs_gaussians *segs, int32_t n_segs, const gs_
     b.bg0 = p->bg[0];
     b.bg1 = p->bg[1];
     b.bg2 = p->bg[2];
+    // the tile pass also clears the dense gradient planes of the first
+    // segments (as many as its arguments hold); B2 clears the others itself
+    std::vector<int> zeroed(n_segs, 0);
     if (proj->n_instances > 0) {
+        for (int s = 0; s < n_segs; ++s) {
+            if (segs[s].n == 0) continue;
+            const gs_gaussians_grad &g = grads[s];
+            const int64_t n = segs[s].n, K = (int64_t)(segs[s].sh_degree + 1) * (segs[s].sh_degree + 1);
+            float *ptr[6] = {g.means, g.opacity, g.sh, segs[s].cov6 ? g.cov6 : nullptr,
+                             segs[s].cov6 ? nullptr : g.log_scales, segs[s].cov6 ? nullptr : g.quats};
+            const int64_t w[6] = {3, 1, 3 * K, 6, 3, 4};
+            int need = 0;
+            for (int k = 0; k < 6; ++k) need += ptr[k] ? 1 : 0;
+            if (b.n_zero + need > gs::kZeroPlanes) break;
+            for (int k = 0; k < 6; ++k)
+                if (ptr[k]) {
+                    b.zero_ptr[b.n_zero] = ptr[k];
+                    b.zero_n[b.n_zero] = w[k] * n;
+                    ++b.n_zero;
+                }
+            zeroed[s] = 1;
+        }
         e = gs::launch_backward_tiles(b, cu_count(), sm);
         if (e != hipSuccess) return hip_fail(e, "gs_render_backward (tiles)");
     }
@@ -615,6 +636,7 @@ gs_status gs_render_backward(const gs_gaussians *segs, int32_t n_segs, const gs_
                 a.base[k] = off[v] + seg_offset_in_view(segs, view_seg_mask[v], s);
             }
             a.first = (c == 0) ? 1 : 0;
+            a.zeroed = zeroed[s];
             a.W = p->width;
             a.H = p->height;
             a.near_plane = p->near_plane;

@@ -50,6 +50,23 @@ __device__ __forceinline__ float wave_sum_to_last(float v) {
     return v;
 }
 
+// zeros for p[0, n) by the whole grid: 16-byte stores on the 16-byte aligned
+// stretch, the single floats at its ends by workgroup 0
+__device__ __forceinline__ void zero_span_grid(float *p, int64_t n) {
+    const uint64_t base = (uint64_t)(uintptr_t)p;  // 4-byte aligned (floats)
+    int64_t v0 = 0, v1 = n;
+    while (((base + 4u * (uint64_t)v0) & 15u) && v0 < n) ++v0;
+    while (((base + 4u * (uint64_t)v1) & 15u) && v1 > v0) --v1;
+    if (blockIdx.x == 0) {
+        for (int64_t f = threadIdx.x; f < v0; f += blockDim.x) p[f] = 0.0f;
+        for (int64_t f = v1 + threadIdx.x; f < n; f += blockDim.x) p[f] = 0.0f;
+    }
+    float4 *q = reinterpret_cast<float4 *>(p + v0);
+    const int64_t m = (v1 - v0) / 4, stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m; k += stride)
+        q[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+
 // SEG: the work is the listed (tile, segment) pairs (checkpoint mode); else
 // one whole list per workgroup, its quadrant sums through LDS (WLDS) or
 // added to HBM by each wave.
@@ -313,6 +330,9 @@ __global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const Backwa
     }
     }  // this wave's walk
     }  // work loop
+    // the dense gradient planes, cleared by each workgroup once its walks
+    // are done (their stores drain while later workgroups still walk)
+    for (int z = 0; z < a.n_zero; ++z) zero_span_grid(a.zero_ptr[z], a.zero_n[z]);
 }
 
 // The backward's work list (one workgroup): for every (view, tile) list of
@@ -406,7 +426,7 @@ __global__ void __launch_bounds__(1024) zero_and_list_kernel(const BackwardProje
     bool vis = false;
     if (i < a.seg.n)
         for (int vi = 0; vi < a.nv && !vis; ++vi) vis = a.tiles_touched[a.base[vi] + i] != 0u;
-    if (a.first) {
+    if (a.first && !a.zeroed) {
         const int64_t g0 = (int64_t)blockIdx.x * 1024, g1 = g0 + 1024 < a.seg.n ? g0 + 1024 : a.seg.n;
         const gs_gaussians_grad &G = a.grad;
         zero_plane(G.means, 3, g0, g1);
@@ -501,7 +521,9 @@ __global__ void __launch_bounds__(256) backward_project_kernel(const BackwardPro
 
     for (int vi = 0; vi < a.nv; ++vi) {
         const int64_t inst = a.base[vi] + i;
-        if (a.tiles_touched[inst] == 0u) continue;
+        // a listed Gaussian is drawn by one of the launch's views: with one
+        // view, by that one
+        if (a.nv > 1 && a.tiles_touched[inst] == 0u) continue;
         const double *g = a.g2d + (size_t)inst * kG2D;
         double gl[kG2D];
 #pragma unroll

@@ -46,6 +46,7 @@ struct BackwardProjectArgs {
     int32_t view[kProjViews];
     int32_t nv;
     int32_t first;     // 1: overwrite the gradients, 0: accumulate (later chunk of views)
+    int32_t zeroed;    // the planes are zeroed already (by B1): list only
     int32_t W, H;
     float near_plane, lowpass, sigma_cut, fov_clamp;
     uint32_t *list;   // [seg.n]: Gaussians with an instance drawn in one of the views (compacted)
@@ -94,6 +95,8 @@ __host__ __device__ inline uint64_t ckpt_index(uint64_t slot, int quad, int val,
     return ((slot * 4 + (uint64_t)quad) * kCkptVals + (uint64_t)val) * 64 + (uint64_t)lane;
 }
 
+constexpr int kZeroPlanes = 12;  // two segments' gradient planes
+
 struct BackwardTileArgs {
     const float4 *rec;
     const uint32_t *vals;
@@ -110,6 +113,11 @@ struct BackwardTileArgs {
     int32_t W, H, TX, T;
     float alpha_max, alpha_min;
     float bg0, bg1, bg2;
+    // dense gradient planes to zero while the tiles are walked (the
+    // gradients' first writer, B2, then only overwrites the drawn Gaussians)
+    float *zero_ptr[kZeroPlanes];
+    int64_t zero_n[kZeroPlanes];  // floats
+    int32_t n_zero;
 };
 
 struct LbsArgs {
