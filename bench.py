@@ -122,7 +122,7 @@ def stage_roofline(c):
     if c.get("pairs_b") is not None:
         st["bwd_composite"] = (c["V"] * c["HW"] * 28 + c["K"] * 52 + c["n_vis"] * 80,
                                BWD_FLOPS_PER_PAIR * c["pairs_b"], 2 * c["pairs_b"])
-        st["bwd_project"] = (c["n_drawn"] * (32 + sh + 40 + 48) + c["N_grad"] * 4 * (11 + 3 * (D + 1) ** 2),
+        st["bwd_project"] = (c["n_drawn"] * (32 + sh + 80 + 48) + c["N_grad"] * 4 * (11 + 3 * (D + 1) ** 2),
                              600 * c["n_drawn"], 0)
     if c.get("n_av"):
         st["lbs"] = (c["n_av"] * 96, 90 * c["n_av"], 0)

@@ -167,11 +167,13 @@ void gs_default_params(gs_params *p, int32_t width, int32_t height);
  *    8192, default 4096).
  *  sort_lookback: predecessor partitions read per round trip of the onesweep
  *    look-back (16, 32 or 64, default 16).
- *  sort_algorithm: 0 (default) sorts by tile buckets when the launch has at
- *    most 4096 tiles over all views (count per tile, scatter into buckets,
- *    sort each bucket by (depth, instance) in LDS) and with the onesweep
- *    radix sort otherwise; 1 always uses the onesweep radix sort.  Both give
- *    the same keys, values and ranges.
+ *  sort_algorithm: 0 (default) sorts by tile buckets (count per tile,
+ *    scatter into buckets, sort each bucket by (depth, instance) in LDS)
+ *    when every view has at most 4096 tiles and the launch at most 2^18
+ *    tiles over all views (beyond 4096 in all, the counts are taken in a
+ *    sliding window of whole views), and with the onesweep radix sort
+ *    otherwise; 1 always uses the onesweep radix sort.  Both give the same
+ *    keys, values, ranges and work order.
  * gs_set_tuning(NULL) restores the defaults; invalid values return
  * GS_ERR_INVALID_ARGUMENT and change nothing.  Meant for an autotuner that
  * times the candidates on the target workload.
