@@ -174,6 +174,11 @@ void gs_default_params(gs_params *p, int32_t width, int32_t height);
  *    sliding window of whole views), and with the onesweep radix sort
  *    otherwise; 1 always uses the onesweep radix sort.  Both give the same
  *    keys, values, ranges and work order.
+ *  composite_pairs: 0 (default) lets gs_composite walk each quadrant's list
+ *    with a pair of waves (one evaluates the alphas of a chunk while the
+ *    other accumulates the previous chunk) when the launch has at most
+ *    16 x (compute units) quadrant items, and with one wave otherwise; 1
+ *    always uses one wave, 2 always a pair.  The images are bit-identical.
  * gs_set_tuning(NULL) restores the defaults; invalid values return
  * GS_ERR_INVALID_ARGUMENT and change nothing.  Meant for an autotuner that
  * times the candidates on the target workload.
@@ -188,7 +193,8 @@ typedef struct gs_tuning {
     int32_t sort_partition_keys;
     int32_t sort_lookback;
     int32_t sort_algorithm;
-    int32_t reserved[4];
+    int32_t composite_pairs;
+    int32_t reserved[3];
 } gs_tuning;
 gs_status gs_set_tuning(const gs_tuning *t);
 void gs_get_tuning(gs_tuning *t);

@@ -2,9 +2,10 @@
 
 The wave schedule of `gs_composite` (how many persistent four-wave groups
 each compute unit runs, i.e. how the (view, tile, quadrant) work items are
-spread and how much gather latency other waves hide) has no single best value:
-few long lists favour many resident waves, many short lists favour fewer,
-dynamically balanced ones.  `tune_composite` times each candidate on the
+spread and how much gather latency other waves hide, or whether each
+quadrant's list is walked by a producer / consumer pair of waves) has no
+single best value: few long lists favour pairs or many resident waves, many
+short lists favour fewer, dynamically balanced ones.  `tune_composite` times each candidate on the
 caller's workload with HIP events on the launch stream (the projected and
 binned frame is reused, so only compositing is timed) and leaves the fastest
 one set.  Results are cached per shape class in memory (and optionally in a
@@ -20,7 +21,7 @@ import torch
 
 from . import binding as B
 
-CANDIDATES = (2, 3, 4, 5, 6, 8)
+CANDIDATES = (2, 3, 4, 5, 6, 8, "pairs")
 _cache: dict = {}
 
 
@@ -30,24 +31,39 @@ def shape_class(n_views, width, height, n_keys):
     return "v%d_%dx%d_k2^%d" % (n_views, width, height, int(math.log2(per_view)))
 
 
+def _apply(c, with_pairs):
+    """Set candidate c: a number of four-wave groups per CU (one wave per
+    quadrant when pairs are among the candidates, else the current pair
+    setting), or "pairs"."""
+    if c == "pairs":
+        B.set_tuning(composite_pairs=2)
+    elif with_pairs:
+        B.set_tuning(int(c), composite_pairs=1)
+    else:
+        B.set_tuning(int(c))
+
+
 def tune_composite(renderer, frame, n_views, candidates=CANDIDATES, reps=10, cache_path=None):
     """Time gs_composite on `frame` (already projected and binned) for every
-    candidate and keep the fastest.  Returns (best, {candidate: ms})."""
+    candidate (groups per CU, or "pairs") and keep the fastest.  Returns
+    (best, {candidate: ms})."""
+    with_pairs = "pairs" in candidates
     n_keys = int(frame.num.item())
     key = shape_class(n_views, renderer.W, renderer.H, n_keys)
     if key in _cache:
-        B.set_tuning(_cache[key])
+        _apply(_cache[key], with_pairs)
         return _cache[key], {}
     if cache_path and os.path.exists(cache_path):
         with open(cache_path) as fh:
             disk = json.load(fh)
         if key in disk:
-            _cache[key] = int(disk[key])
-            B.set_tuning(_cache[key])
+            v = disk[key]
+            _cache[key] = v if v == "pairs" else int(v)
+            _apply(_cache[key], with_pairs)
             return _cache[key], {}
     times = {}
     for c in candidates:
-        B.set_tuning(c)
+        _apply(c, with_pairs)
         for _ in range(2):
             renderer.composite(frame, n_views)
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -58,7 +74,7 @@ def tune_composite(renderer, frame, n_views, candidates=CANDIDATES, reps=10, cac
         torch.cuda.synchronize()
         times[c] = a.elapsed_time(b) / reps
     best = min(times, key=times.get)
-    B.set_tuning(best)
+    _apply(best, with_pairs)
     _cache[key] = best
     if cache_path:
         disk = {}

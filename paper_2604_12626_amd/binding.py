@@ -52,10 +52,12 @@ class Projected(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("composite_groups_per_cu", ctypes.c_int32), ("sort_partition_keys", ctypes.c_int32),
-                ("sort_lookback", ctypes.c_int32), ("sort_algorithm", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("sort_lookback", ctypes.c_int32), ("sort_algorithm", ctypes.c_int32),
+                ("composite_pairs", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
-TUNING_FIELDS = ("composite_groups_per_cu", "sort_partition_keys", "sort_lookback", "sort_algorithm")
+TUNING_FIELDS = ("composite_groups_per_cu", "sort_partition_keys", "sort_lookback", "sort_algorithm",
+                 "composite_pairs")
 
 
 EXPORTS = ["gs_status_string", "gs_last_error", "gs_version", "gs_default_params", "gs_set_tuning", "gs_get_tuning",

@@ -109,6 +109,7 @@ std::atomic<int> g_comp_groups{3};
 std::atomic<int> g_sort_part_keys{4096};
 std::atomic<int> g_sort_lookback{16};
 std::atomic<int> g_sort_algorithm{0};
+std::atomic<int> g_comp_pairs{0};
 
 std::mutex g_dev_mu;
 int g_cu_count[64] = {0};
@@ -131,6 +132,8 @@ int cu_count() {
 // held until the process ends; its device address is looked up once per
 // device, with that device current, and used for every launch argument.
 constexpr size_t kCompCounterBytes = 2048;
+constexpr int kPairsPerCu = 4;  // two-wave compositing workgroups per CU in pair mode (their LDS)
+constexpr int kPairsAutoItemsPerCu = 16;  // quadrant items per CU up to which the default takes pairs
 constexpr size_t kNoallocScratchBytes =
     kCompCounterBytes + (size_t)gs::kOrderQueues * gs::order_stride(GS_NOALLOC_MAX_ITEMS) * sizeof(uint32_t);
 static_assert(kNoallocScratchBytes == GS_NOALLOC_SCRATCH_BYTES, "gs.h states the scratch size");
@@ -196,6 +199,7 @@ gs_status gs_set_tuning(const gs_tuning *t) {
         g_sort_part_keys.store(4096);
         g_sort_lookback.store(16);
         g_sort_algorithm.store(0);
+        g_comp_pairs.store(0);
         return GS_OK;
     }
     if (t->composite_groups_per_cu < 1 || t->composite_groups_per_cu > 32)
@@ -206,10 +210,13 @@ gs_status gs_set_tuning(const gs_tuning *t) {
         return fail(GS_ERR_INVALID_ARGUMENT, "sort_lookback=%d (16, 32 or 64)", t->sort_lookback);
     if (t->sort_algorithm != 0 && t->sort_algorithm != 1)
         return fail(GS_ERR_INVALID_ARGUMENT, "sort_algorithm=%d (0 or 1)", t->sort_algorithm);
+    if (t->composite_pairs < 0 || t->composite_pairs > 2)
+        return fail(GS_ERR_INVALID_ARGUMENT, "composite_pairs=%d (0, 1 or 2)", t->composite_pairs);
     g_comp_groups.store(t->composite_groups_per_cu);
     g_sort_part_keys.store(t->sort_partition_keys);
     g_sort_lookback.store(t->sort_lookback);
     g_sort_algorithm.store(t->sort_algorithm);
+    g_comp_pairs.store(t->composite_pairs);
     return GS_OK;
 }
 
@@ -220,6 +227,7 @@ void gs_get_tuning(gs_tuning *t) {
     t->sort_partition_keys = g_sort_part_keys.load();
     t->sort_lookback = g_sort_lookback.load();
     t->sort_algorithm = g_sort_algorithm.load();
+    t->composite_pairs = g_comp_pairs.load();
 }
 
 gs_status gs_instance_offsets(const gs_gaussians *segs, int32_t n_segs, int32_t n_views,
@@ -459,15 +467,22 @@ gs_status composite_launch(const char *who, const gs_projected *proj, const uint
     a.ckpt = a.ckpt_slots ? ckpt : nullptr;
     hipError_t e;
     // persistent waves: a tunable number of four-wave groups per CU, never
-    // more waves than quadrant work items
-    int64_t grid = (int64_t)cu_count() * g_comp_groups.load();
-    if (grid > a.n_items) grid = a.n_items;
+    // more waves than quadrant work items; or, with few items, pairs of
+    // waves (the LDS of a pair allows four per CU), whose shorter walks win
+    // while the longest lists bound the kernel (measured: 256 x 256 views,
+    // 1024 to 4096 quadrant items, 0.72-0.75 of the single-wave time; a
+    // 640 x 480 view, 4800 items, 1.35 of it)
+    const int pairs_mode = g_comp_pairs.load();
+    const bool pairs =
+        pairs_mode == 2 || (pairs_mode == 0 && 4 * a.n_items <= (int64_t)kPairsAutoItemsPerCu * cu_count());
+    int64_t grid = (int64_t)cu_count() * (pairs ? kPairsPerCu : g_comp_groups.load());
+    if (grid > (pairs ? 4 : 1) * a.n_items) grid = (pairs ? 4 : 1) * a.n_items;
     if (clear_counters &&
         (e = gs::launch_fill_u32(counter, 0u, (int64_t)(kCompCounterBytes / sizeof(uint32_t)), stream)) != hipSuccess)
         return hip_fail(e, who);
     if (!tile_order && (e = gs::launch_tile_order(tile_ranges, a.n_items, own_order, stream)) != hipSuccess)
         return hip_fail(e, who);
-    e = gs::launch_composite(a, (int)grid, stream);
+    e = pairs ? gs::launch_composite_pairs(a, (int)grid, stream) : gs::launch_composite(a, (int)grid, stream);
     return e == hipSuccess ? GS_OK : hip_fail(e, who);
 }
 

@@ -695,14 +695,19 @@ __global__ void __launch_bounds__(256) backward_project_kernel(const BackwardPro
 __global__ void __launch_bounds__(256) clear_g2d_kernel(const uint32_t *tt, int64_t n, double *g2d,
                                                         uint32_t *counts, int n_counts) {
     static_assert(kG2D % 2 == 0, "two accumulators per 16-B store");
+    constexpr uint32_t P = kG2D / 2;  // 16-B pieces per instance
     if (blockIdx.x == 0)
         for (int k = threadIdx.x; k < n_counts; k += 256) counts[k] = 0u;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-        if (tt[i]) {
-            double2 *g = reinterpret_cast<double2 *>(g2d + (size_t)i * kG2D);
+    // a block of 256 instances at a time, its 256 P pieces spread over the
+    // threads, so that each store instruction writes consecutive 16-B pieces
+    for (int64_t base = (int64_t)blockIdx.x * 256; base < n; base += (int64_t)gridDim.x * 256) {
+        double2 *g = reinterpret_cast<double2 *>(g2d + (size_t)base * kG2D);
 #pragma unroll
-            for (int k = 0; k < kG2D / 2; ++k) g[k] = make_double2(0.0, 0.0);
+        for (uint32_t r = 0; r < P; ++r) {
+            const uint32_t k = r * 256u + threadIdx.x, li = k / P;
+            if (base + li < n && tt[base + li]) g[k] = make_double2(0.0, 0.0);
         }
+    }
 }
 
 hipError_t launch_clear_g2d(const uint32_t *tiles_touched, int64_t n_instances, double *g2d, uint32_t *counts,

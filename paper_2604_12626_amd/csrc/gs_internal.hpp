@@ -209,6 +209,7 @@ constexpr int kOrderQueues = 8, kOrderBins = 64;
 __host__ __device__ constexpr int64_t order_stride(int64_t n_items) { return (n_items + kOrderQueues - 1) / kOrderQueues; }
 hipError_t launch_tile_order(const uint32_t *ranges, int64_t n_items, uint32_t *order, hipStream_t s);
 hipError_t launch_composite(CompositeArgs a, int grid, hipStream_t s);
+hipError_t launch_composite_pairs(CompositeArgs a, int grid, hipStream_t s);  // grid: 2-wave workgroups
 hipError_t launch_backward_tiles(BackwardTileArgs a, int n_cu, hipStream_t s);
 hipError_t launch_backward_project(const BackwardProjectArgs &a, hipStream_t s);
 // zeroes the screen-space accumulators of the drawn instances (tiles_touched

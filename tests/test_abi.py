@@ -242,17 +242,18 @@ def test_tuning_validation():
     prev = B.get_tuning()
     try:
         for bad in ({"composite_groups_per_cu": 0}, {"composite_groups_per_cu": 33},
-                    {"sort_partition_keys": 2048}, {"sort_lookback": 8}, {"sort_algorithm": 2}):
+                    {"sort_partition_keys": 2048}, {"sort_lookback": 8}, {"sort_algorithm": 2},
+                    {"composite_pairs": 3}, {"composite_pairs": -1}):
             before = B.get_tuning()
             with pytest.raises(B.GSError):
                 B.set_tuning(**bad)
             assert B.get_tuning() == before
-        B.set_tuning(5, sort_partition_keys=8192, sort_lookback=64, sort_algorithm=1)
+        B.set_tuning(5, sort_partition_keys=8192, sort_lookback=64, sort_algorithm=1, composite_pairs=2)
         assert B.get_tuning() == {"composite_groups_per_cu": 5, "sort_partition_keys": 8192, "sort_lookback": 64,
-                                  "sort_algorithm": 1}
+                                  "sort_algorithm": 1, "composite_pairs": 2}
         B.set_tuning()
         assert B.get_tuning() == {"composite_groups_per_cu": 3, "sort_partition_keys": 4096, "sort_lookback": 16,
-                                  "sort_algorithm": 0}
+                                  "sort_algorithm": 0, "composite_pairs": 0}
     finally:
         B.set_tuning(**prev)
 

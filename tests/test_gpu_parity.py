@@ -232,8 +232,20 @@ COMPOSITE_CASES = [
 ]
 
 
+@pytest.mark.parametrize("pairs", [1, 2], ids=["one_wave", "wave_pairs"])
 @pytest.mark.parametrize("name,counts,W,H,rmed,aniso", COMPOSITE_CASES, ids=[c[0] for c in COMPOSITE_CASES])
-def test_composite_parity(dev, orc, name, counts, W, H, rmed, aniso):
+def test_composite_parity(dev, orc, name, counts, W, H, rmed, aniso, pairs):
+    """Both compositing walks (one wave per quadrant, and a producer /
+    consumer pair of waves) against the oracle."""
+    from paper_2604_12626_amd import binding as B
+    prev = B.set_tuning(composite_pairs=pairs)
+    try:
+        _composite_parity_case(dev, orc, name, counts, W, H, rmed, aniso)
+    finally:
+        B.set_tuning(**prev)
+
+
+def _composite_parity_case(dev, orc, name, counts, W, H, rmed, aniso):
     import torch
     from paper_2604_12626_amd import binding as B
     rng = np.random.default_rng(zlib.crc32(name.encode()))
@@ -366,6 +378,54 @@ def test_composite_schedule_does_not_change_results(dev):
         assert torch.equal(f.rgb, ref[0]) and torch.equal(f.depth, ref[1]) and torch.equal(f.n_contrib, ref[2])
         best, times = autotune.tune_composite(r, f, len(vs), candidates=(2, 8), reps=2)
         assert best in (2, 8) and B.get_tuning()["composite_groups_per_cu"] == best
+    finally:
+        B.set_tuning(**prev)
+
+
+def test_composite_pairs_bit_identical(dev):
+    """The pair walk (one wave evaluates a chunk's alphas, the other
+    accumulates the chunk before) gives the single wave's results bit for
+    bit: images, T_final, n_contrib and the segment checkpoints.  On the
+    500k-Gaussian 256x256 view (1024 quadrant items: one pair each, lists of
+    many chunks, early stops) and on 12 views of 256x256 with pairs forced,
+    so that every pair walks many items in turn."""
+    import torch
+    from paper_2604_12626_amd import binding as B, render
+    prev = B.get_tuning()
+    try:
+        cfg = synth.config(2)
+        cases = [("500k_256x256", cfg, [to_dev(cfg["segments"][0], dev)], cfg["cams"], [[0]], True)]
+        c3 = synth.config(3, scale=0.02)
+        cases.append(("12views_256x256", c3, [to_dev(g, dev) for g in c3["segments"]], c3["cams"][:12],
+                      c3["view_segs"][:12], False))
+        for name, c, segs, cams_np, vs, ck in cases:
+            W, H = c["W"], c["H"]
+            say("pairs vs one wave:", name)
+            r = render.Renderer(W, H, capacity=1 << 21, device=dev)
+            f = r.render(segs, torch.from_numpy(np.ascontiguousarray(cams_np)).to(dev), vs, checkpoints=ck)
+            torch.cuda.synchronize()
+            lens = (f.ranges[:, 1] - f.ranges[:, 0]).cpu().numpy()
+            out = {}
+            for mode in (1, 2):
+                B.set_tuning(composite_pairs=mode)
+                if f.ckpt is not None:
+                    f.ckpt.fill_(-7.0)
+                f.rgb.fill_(-1.0)
+                f.n_contrib.fill_(-1)
+                r.composite(f, len(vs))
+                torch.cuda.synchronize()
+                out[mode] = [f.rgb.clone(), f.depth.clone(), f.alpha.clone(), f.t_final.clone(), f.n_contrib.clone()]
+                if f.ckpt is not None:
+                    out[mode].append(f.ckpt.clone())
+            for a, b in zip(out[1], out[2]):
+                assert torch.equal(a, b), name
+            # the paths this reached
+            if ck:  # lists of several chunks, opaque pixels, checkpoints written
+                assert lens.max() > 4 * 64, lens.max()
+                assert (out[1][3].cpu().numpy() < 1e-3).any() and out[1][4].cpu().numpy().max() > 64
+                assert (out[1][5] != -7.0).any()
+            else:  # many more quadrant items than pairs of waves
+                assert 4 * len(lens) > 4 * 256 * 4 and (lens > 64).any()
     finally:
         B.set_tuning(**prev)
 
