@@ -242,7 +242,8 @@ def bench_fwd_bwd(args, dev, steps, want_pairs=True):
     r = render.Renderer(W, H, capacity=1 << 21, device=dev, checkpoints="auto")
     ft = r.render(tgt, cams, vs)
     # the loss adjoint 2 (x - x*) as one fused kernel per output: -2 x* is
-    # formed once, then d = -2 x* + 2 x into buffers of their own
+    # formed once, then d = -2 x* + 2 x into buffers of their own (measured:
+    # one multi-tensor launch for both outputs took longer than the two)
     neg2_rgb_t, neg2_depth_t = -2.0 * ft.rgb, -2.0 * ft.depth
     d_rgb, d_depth = torch.empty_like(ft.rgb), torch.empty_like(ft.depth)
     r.render(segs, cams, vs)  # sizes the key capacity for the timed parameters

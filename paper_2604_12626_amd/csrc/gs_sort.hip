@@ -935,7 +935,7 @@ constexpr int kSortClasses = 5;
 // of the four shorter classes, longest class first; sort_ctl holds the five
 // counts, the number of tiles of more than kTileSortCap keys and of their runs
 // of up to kTileSortCap keys, which run_list holds as {tile, run}.  Counts are read coalesced, a chunk of
-// kScanChunk tiles at a time, into LDS.
+// up to kScanChunk tiles at a time, into LDS.
 constexpr int kScanChunk = 16384;
 constexpr int kSortBins = 64;
 constexpr int kHugeBins = kSortBins - kTileSortCap / 1024;  // the bins of the tiles longer than kTileSortCap
@@ -967,20 +967,21 @@ __device__ __forceinline__ uint32_t wave_append(uint32_t *counter, bool active) 
     return b + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
 }
 
+template <int PER>
 __global__ void __launch_bounds__(1024) bucket_tilescan_kernel(const uint32_t *tile_count, const uint32_t *tile_over,
                                                                int64_t n_tiles, int64_t capacity, uint32_t *tile_start,
                                                                uint32_t *ranges, uint32_t *order, uint32_t *sort_list,
                                                                uint32_t *sort_ctl, uint2 *run_list, int64_t *d_num,
                                                                int32_t *d_overflow) {
-    constexpr int PER = kScanChunk / 1024;
+    constexpr int CH = PER * 1024;  // tiles per chunk
     __shared__ uint32_t s_runs;
-    __shared__ uint32_t s_c[kScanChunk];
-    __shared__ uint32_t s_st[kScanChunk];  // first keys of the chunk's tiles
+    __shared__ uint32_t s_c[CH];
+    __shared__ uint32_t s_st[CH];  // first keys of the chunk's tiles
     __shared__ uint64_t s_w[16];
     __shared__ uint32_t s_cnt[kOrderQueues][kOrderBins];
     __shared__ uint32_t s_big[kSortBins + kSortClasses - 1];  // long tiles by bin, then the shorter classes
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t n_chunks = (n_tiles + kScanChunk - 1) / kScanChunk;
+    const int64_t n_chunks = (n_tiles + CH - 1) / CH;
     // keys per tile: the counted ones, plus those counted outside a window;
     // s_c[k] = count of tile cb + k (0 past the end), loads in flight together
     int64_t loaded = -1;
@@ -1008,7 +1009,7 @@ __global__ void __launch_bounds__(1024) bucket_tilescan_kernel(const uint32_t *t
     // (one chunk: the scan below finds it before its first store)
     uint64_t total = 0u;
     for (int64_t ch = 0; n_chunks > 1 && ch < n_chunks; ++ch) {
-        load_chunk(ch * kScanChunk);
+        load_chunk(ch * CH);
         uint64_t sum = 0u;
 #pragma unroll
         for (int k = 0; k < PER; ++k) sum += s_c[k * 1024 + tid];
@@ -1025,7 +1026,7 @@ __global__ void __launch_bounds__(1024) bucket_tilescan_kernel(const uint32_t *t
     // bins spread over the lanes)
     uint64_t carry = 0u;
     for (int64_t ch = 0; ch < n_chunks; ++ch) {
-        const int64_t cb = ch * kScanChunk;
+        const int64_t cb = ch * CH;
         load_chunk(cb);
         uint32_t c[PER];
         uint64_t sum = 0u;
@@ -1116,7 +1117,7 @@ __global__ void __launch_bounds__(1024) bucket_tilescan_kernel(const uint32_t *t
     __syncthreads();
     const int64_t qs = order_stride(n_tiles);
     for (int64_t ch = 0; ch < n_chunks; ++ch) {
-        const int64_t cb = ch * kScanChunk;
+        const int64_t cb = ch * CH;
         load_chunk(cb);
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
@@ -1144,6 +1145,23 @@ __global__ void __launch_bounds__(1024) bucket_tilescan_kernel(const uint32_t *t
     }
     __syncthreads();
     if (tid == 0) sort_ctl[kSortClasses + 1] = s_runs;
+}
+
+
+// the tile scan with chunks of PER * 1024 tiles: the smallest that holds
+// every tile, up to kScanChunk
+static hipError_t launch_tilescan(const uint32_t *tile_count, const uint32_t *tile_over, int64_t n_tiles,
+                                  int64_t capacity, uint32_t *tile_start, uint32_t *ranges, uint32_t *order,
+                                  uint32_t *sort_list, uint32_t *sort_ctl, uint2 *run_list, int64_t *d_num,
+                                  int32_t *d_overflow, hipStream_t s) {
+#define GS_TILESCAN(P)                                                                                          \
+    launch_kernel(bucket_tilescan_kernel<P>, dim3(1), dim3(1024), s, tile_count, tile_over, n_tiles, capacity, \
+                  tile_start, ranges, order, sort_list, sort_ctl, run_list, d_num, d_overflow)
+    if (n_tiles <= 1024) return GS_TILESCAN(1);
+    if (n_tiles <= 2048) return GS_TILESCAN(2);
+    if (n_tiles <= 4096) return GS_TILESCAN(4);
+    return GS_TILESCAN(kScanChunk / 1024);
+#undef GS_TILESCAN
 }
 
 __device__ __forceinline__ void lds_wave_sync() {
@@ -1610,9 +1628,8 @@ static hipError_t run_bucket_sort(const SortPlan &P, const uint32_t *tt, const f
         if ((e = launch_kernel(emit_kernel<kEmitCountWin>, dim3((unsigned)P.bucket_blocks), dim3(kEmitBlock), s,
                                A)) != hipSuccess)
             return e;
-        if ((e = launch_kernel(bucket_tilescan_kernel, dim3(1), dim3(1024), s, (const uint32_t *)tcount,
-                               (const uint32_t *)A.tile_over, P.n_tiles_total, P.capacity, tstart, ranges, order,
-                               slist, sctl, rlist, d_num, d_overflow)) != hipSuccess)
+        if ((e = launch_tilescan(tcount, A.tile_over, P.n_tiles_total, P.capacity, tstart, ranges, order, slist,
+                                 sctl, rlist, d_num, d_overflow, s)) != hipSuccess)
             return e;
         if ((e = launch_kernel(emit_kernel<kEmitScatterWin>, dim3((unsigned)P.bucket_blocks), dim3(kEmitBlock), s,
                                A)) != hipSuccess)
@@ -1624,9 +1641,8 @@ static hipError_t run_bucket_sort(const SortPlan &P, const uint32_t *tt, const f
         if ((e = launch_kernel(bucket_colscan_kernel, dim3((unsigned)((P.n_tiles_total + 3) / 4)), dim3(256), s,
                                A.tile_cnt, (int)P.bucket_blocks, P.n_tiles_total, tcount)) != hipSuccess)
             return e;
-        if ((e = launch_kernel(bucket_tilescan_kernel, dim3(1), dim3(1024), s, (const uint32_t *)tcount,
-                               (const uint32_t *)nullptr, P.n_tiles_total, P.capacity, tstart, ranges, order, slist,
-                               sctl, rlist, d_num, d_overflow)) != hipSuccess)
+        if ((e = launch_tilescan(tcount, nullptr, P.n_tiles_total, P.capacity, tstart, ranges, order, slist, sctl,
+                                 rlist, d_num, d_overflow, s)) != hipSuccess)
             return e;
         if ((e = launch_kernel(emit_kernel<kEmitScatterTiles>, dim3((unsigned)P.bucket_blocks), dim3(kEmitBlock), s,
                                A)) != hipSuccess)
