@@ -69,9 +69,11 @@ __device__ __forceinline__ void zero_span_grid(float *p, int64_t n) {
 
 // SEG: the work is the listed (tile, segment) pairs (checkpoint mode); else
 // one whole list per workgroup, its quadrant sums through LDS (WLDS) or
-// added to HBM by each wave.
+// added to HBM by each wave.  Bounded to five waves per SIMD (a few
+// registers spill): the walk is bound by latency, so one more workgroup in
+// flight per CU pays.
 template <bool SEG, bool WLDS>
-__global__ void __launch_bounds__(kTilePixels) backward_tile_kernel(const BackwardTileArgs a) {
+__global__ void __launch_bounds__(kTilePixels, 5) backward_tile_kernel(const BackwardTileArgs a) {
     constexpr bool kLds = SEG || WLDS;
     __shared__ float4 s_e0[4][64], s_e1[4][64], s_e2[4][64], s_q[4][64];
     // 64 list positions: each quadrant wave stores its per-entry sums in its
@@ -418,16 +420,25 @@ __device__ __forceinline__ void zero_plane(float *p, int w, int64_t i0, int64_t 
 // (the drawn Gaussians are overwritten by B2b; later chunks add to what the
 // first wrote); the drawn Gaussians appended to a.list, positions inside the
 // workgroup from ballots and one atomic per workgroup (order of arrival: each
-// Gaussian is handled on its own)
+// Gaussian is handled on its own).  A workgroup takes kListSpan Gaussians, so
+// that few atomics meet on the one counter (they serialise there).
+constexpr int kListChunks = 4, kListSpan = 1024 * kListChunks;
 __global__ void __launch_bounds__(1024) zero_and_list_kernel(const BackwardProjectArgs a, int sh_floats) {
-    __shared__ uint32_t s_cnt[16], s_base;
-    const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+    __shared__ uint32_t s_cnt[kListChunks][16], s_base;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    bool vis = false;
-    if (i < a.seg.n)
-        for (int vi = 0; vi < a.nv && !vis; ++vi) vis = a.tiles_touched[a.base[vi] + i] != 0u;
+    const int64_t g0 = (int64_t)blockIdx.x * kListSpan, g1 = g0 + kListSpan < a.seg.n ? g0 + kListSpan : a.seg.n;
+    bool vis[kListChunks];
+    uint64_t bal[kListChunks];
+#pragma unroll
+    for (int c = 0; c < kListChunks; ++c) {
+        const int64_t i = g0 + c * 1024 + threadIdx.x;
+        vis[c] = false;
+        if (i < g1)
+            for (int vi = 0; vi < a.nv && !vis[c]; ++vi) vis[c] = a.tiles_touched[a.base[vi] + i] != 0u;
+        bal[c] = __ballot(vis[c]);
+        if (lane == 0) s_cnt[c][wave] = (uint32_t)__popcll(bal[c]);
+    }
     if (a.first && !a.zeroed) {
-        const int64_t g0 = (int64_t)blockIdx.x * 1024, g1 = g0 + 1024 < a.seg.n ? g0 + 1024 : a.seg.n;
         const gs_gaussians_grad &G = a.grad;
         zero_plane(G.means, 3, g0, g1);
         zero_plane(G.opacity, 1, g0, g1);
@@ -439,20 +450,23 @@ __global__ void __launch_bounds__(1024) zero_and_list_kernel(const BackwardProje
             zero_plane(G.quats, 4, g0, g1);
         }
     }
-    const uint64_t bal = __ballot(vis);
-    if (lane == 0) s_cnt[wave] = (uint32_t)__popcll(bal);
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t total = 0u;
-        for (int w = 0; w < 16; ++w) {
-            const uint32_t c = s_cnt[w];
-            s_cnt[w] = total;
-            total += c;
-        }
+        for (int c = 0; c < kListChunks; ++c)
+            for (int w = 0; w < 16; ++w) {
+                const uint32_t k = s_cnt[c][w];
+                s_cnt[c][w] = total;
+                total += k;
+            }
         s_base = total ? atomicAdd(a.count, total) : 0u;
     }
     __syncthreads();
-    if (vis) a.list[s_base + s_cnt[wave] + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull))] = (uint32_t)i;
+#pragma unroll
+    for (int c = 0; c < kListChunks; ++c)
+        if (vis[c])
+            a.list[s_base + s_cnt[c][wave] + (uint32_t)__popcll(bal[c] & ((1ull << lane) - 1ull))] =
+                (uint32_t)(g0 + c * 1024 + threadIdx.x);
 }
 
 // B2b: one thread per listed Gaussian
@@ -723,8 +737,8 @@ hipError_t launch_backward_project(const BackwardProjectArgs &a, hipStream_t s) 
     if (a.seg.n == 0) return hipSuccess;
     const int K = (a.seg.sh_degree + 1) * (a.seg.sh_degree + 1);
     hipError_t e;
-    if ((e = launch_kernel(zero_and_list_kernel, dim3((unsigned)((a.seg.n + 1023) / 1024)), dim3(1024), s, a, 3 * K)) !=
-        hipSuccess)
+    if ((e = launch_kernel(zero_and_list_kernel, dim3((unsigned)((a.seg.n + kListSpan - 1) / kListSpan)), dim3(1024), s,
+                           a, 3 * K)) != hipSuccess)
         return e;
     if (a.nv == 0) return hipSuccess;
     const unsigned grid = (unsigned)((a.seg.n + 255) / 256);

@@ -1388,9 +1388,10 @@ __device__ __forceinline__ void merge_tile_runs(uint64_t *bucket, uint64_t *keys
 // entries sorted in LDS, its keys (tile << 32 | depth bits) and values
 // (instance) written to the tile's range.  Besides the five classes, two
 // groupings for launches of few tiles, where one launch for several classes
-// keeps every tile in flight at once: kSortShort (classes 2..4, 256 threads)
-// and kSortLong (classes 0 and 1, 1024 threads, a tile longer than CAP sorted
-// as runs and merged by its own workgroup).  With sixteen
+// keeps every tile in flight at once: kSortShort (classes 3 and 4, up to 2048
+// entries, 256 threads: their 18 KB of LDS let eight workgroups share a CU,
+// so 2048 tiles sort in one round) and kSortLong (classes 0..2, 1024 threads,
+// a tile longer than CAP sorted as runs and merged by its own workgroup).  With sixteen
 // entries per thread, a bucket that fits eight per thread takes eight (more
 // threads at work).
 constexpr int kSortShort = 5, kSortLong = 6;
@@ -1407,8 +1408,8 @@ __global__ void __launch_bounds__(THREADS) tile_sort_kernel(uint64_t *bucket, co
     // into the key array; the merge kernel finishes those tiles), then the
     // other tiles
     constexpr bool SMALL = CLASS != 0;
-    constexpr int C0 = CLASS == kSortShort ? 2 : CLASS == kSortLong ? 0 : CLASS;
-    constexpr int C1 = CLASS == kSortShort ? 4 : CLASS == kSortLong ? 1 : CLASS;
+    constexpr int C0 = CLASS == kSortShort ? 3 : CLASS == kSortLong ? 0 : CLASS;
+    constexpr int C1 = CLASS == kSortShort ? 4 : CLASS == kSortLong ? 2 : CLASS;
     uint32_t first = 0u, n_tiles = 0u;
     for (int c = 0; c < C0; ++c) first += sort_ctl[c];
     for (int c = C0; c <= C1; ++c) n_tiles += sort_ctl[c];
@@ -1662,7 +1663,7 @@ static hipError_t run_bucket_sort(const SortPlan &P, const uint32_t *tt, const f
     };
     const int64_t nt = P.n_tiles_total;
     if (!P.windowed) {
-        if ((e = launch_kernel(tile_sort_kernel<kSmallSortBlock, kMidSortCap, kSortShort>, dim3(grid(8, nt)),
+        if ((e = launch_kernel(tile_sort_kernel<kSmallSortBlock, kSmallSortCap, kSortShort>, dim3(grid(8, nt)),
                                dim3(kSmallSortBlock), s, A.bucket, rg, cl, cc, rl, keys, vals, ov)) != hipSuccess)
             return e;
         return launch_kernel(tile_sort_kernel<kTileSortBlock, kTileSortCap, kSortLong>, dim3(grid(1, nt)),

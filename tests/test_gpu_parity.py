@@ -151,28 +151,48 @@ def test_bin_sort_bit_exact(dev, orc, name, counts, W, H):
         B.set_tuning(**prev)
 
 
-def test_bin_sort_long_buckets_bit_exact(dev, orc):
+LONG_BUCKET_CASES = [
+    # 20 views of 256x256: 5120 tiles, the windowed counters and the five
+    # sort classes with the run merge kernel
+    ("windowed_20views", [80000, 30000] + [2000] * 18, 20),
+    # 4 views: 1024 tiles, the two-launch sort (up to 2048 entries; longer,
+    # with runs merged by their own workgroup)
+    ("two_launch_4views", [80000, 39000, 2000, 2000], 4),
+]
+
+
+@pytest.mark.parametrize("name,counts,V", LONG_BUCKET_CASES, ids=[c[0] for c in LONG_BUCKET_CASES])
+def test_bin_sort_long_buckets_bit_exact(dev, orc, name, counts, V):
     """Buckets longer than one LDS sort (16384 entries): sorted as runs and
-    merged, one with two runs, one with four and a ragged fifth; 20 views of
-    256x256 (5120 tiles, the windowed counters)."""
+    merged, one with two runs, one with four and a ragged fifth, next to
+    buckets of every shorter class."""
     from paper_2604_12626_amd import binding as B
     rng = np.random.default_rng(77)
     W = H = 256
-    counts = [80000, 30000] + [2000] * 18
     rec, vis = synth.synthetic_records(rng, counts, W, H)
-    # view 0: every instance in tile 0; view 1: every instance in tile 5
-    for v, (tx, ty) in ((0, (0, 0)), (1, (5, 0))):
-        sel = rec[:, 11].view(np.int32) == v
-        k = int(sel.sum())
-        rec[sel, 0] = 16 * tx + rng.uniform(4.0, 12.0, k)
-        rec[sel, 1] = 16 * ty + rng.uniform(4.0, 12.0, k)
-        rec[sel, 3] = np.ones(k, np.int32).view(np.float32)
-    V = len(counts)
+    # view 0: every instance in tile 0; view 1: 30000 in tile 5, then (if
+    # there are more) 3000 in tile 9 and 6000 in tile 12
+    place = {0: [((0, 0), None)], 1: [((5, 0), 30000), ((9, 0), 3000), ((12, 0), 6000)]}
+    for v, spots in place.items():
+        idx = np.flatnonzero(rec[:, 11].view(np.int32) == v)
+        at = 0
+        for (tx, ty), k in spots:
+            sel = idx[at:] if k is None else idx[at:at + k]
+            at += len(sel)
+            n = len(sel)
+            if n == 0:
+                continue
+            rec[sel, 0] = 16 * tx + rng.uniform(4.0, 12.0, n)
+            rec[sel, 1] = 16 * ty + rng.uniform(4.0, 12.0, n)
+            rec[sel, 3] = np.ones(n, np.int32).view(np.float32)
+    assert len(counts) == V
     tt_o, keys_o, vals_o, ranges_o, K = orc.bin_records(rec, vis, W, H, V)
     lens = ranges_o.reshape(-1, 2).astype(np.int64)
     lens = lens[:, 1] - lens[:, 0]
-    say("long buckets: K %d, longest lists %s" % (K, np.sort(lens)[-3:]))
+    say("long buckets %s: K %d, longest lists %s" % (name, K, np.sort(lens)[-5:]))
     assert lens[0] > 4 * 16384 and 16384 < lens[256 + 5] <= 2 * 16384
+    if V * 256 <= 4096:  # the classes between: (2048, 4096] and (4096, 8192]
+        assert 2048 < lens[256 + 9] <= 4096 and 4096 < lens[256 + 12] <= 8192
     prm = B.make_params(W, H)
     prev = B.get_tuning()
     try:
