@@ -75,6 +75,166 @@ __device__ __forceinline__ void leave(const CompositeArgs &a) {
     }
 }
 
+// One quadrant item walked by one wave (its staging rows e0s, e1s, e2s in
+// LDS): gathers, culls and stages the list 64 entries at a time and
+// composites the survivors front to back.
+__device__ __forceinline__ void walk_one(const CompositeArgs &a, long long item, float4 *e0s, float4 *e1s,
+                                         float4 *e2s, int lane, uint64_t lt_mask) {
+    const int64_t titem = item >> 2;
+    const int quad = (int)(item & 3);
+    const int view = (int)(titem / a.T);
+    const int tile = (int)(titem - (int64_t)view * a.T);
+    const int qx0 = (tile % a.TX) * kTile + ((quad & 1) << 3);
+    const int qy0 = (tile / a.TX) * kTile + ((quad >> 1) << 3);
+    const int px = qx0 + (lane & 7), py = qy0 + (lane >> 3);
+    const bool inside = px < a.W && py < a.H;
+    const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+    const float bx0 = (float)qx0 + 0.5f, by0 = (float)qy0 + 0.5f;
+    const uint2 range = a.ranges[titem];
+    // Waves of long lists get a higher issue priority on their SIMD: the
+    // longest lists bound the kernel's duration, and shorter ones fill
+    // the issue slots those leave while they wait on memory.
+    set_wave_priority(range.y - range.x);
+    float T = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f, dd = 0.0f;
+    const float amax = __builtin_canonicalizef(a.alpha_max);  // keeps the clamp's operand out of the loop
+    uint32_t last = 0;
+    uint32_t done_end = 0;  // list position after the last chunk walked
+    bool done = !inside;
+    // software pipeline over the list chunks, two deep: the records of
+    // chunks c and c + 1 sit in two register sets and the list values of
+    // c + 2 and c + 3 are in flight; once chunk c's records have been
+    // culled and staged, its set is refilled in place with chunk c + 2
+    float4 qa0, qa1, qa2, qb0, qb1, qb2;  // records of this lane's entry in chunks c, c + 1
+    uint32_t ga = 0u, gb = 0u;            // list values of its entries in chunks c + 2, c + 3
+    // every load is unconditional: a lane past the list's end reads the
+    // list's last entry again (a cache hit), so a refill overwrites its
+    // whole register set and needs no merge with the old contents
+    const uint32_t jl = range.y > range.x ? range.y - 1u : range.x;
+    if (range.y > range.x) {
+        const uint32_t j0 = range.x + lane;
+        const uint32_t g0 = a.vals[min(j0, jl)], g1 = a.vals[min(j0 + 64u, jl)];
+        // issued in the order the loop refills them
+        qa0 = a.rec[3 * (size_t)g0];
+        qa1 = a.rec[3 * (size_t)g0 + 1];
+        qa2 = a.rec[3 * (size_t)g0 + 2];
+        ga = a.vals[min(j0 + 128u, jl)];
+        qb0 = a.rec[3 * (size_t)g1];
+        qb1 = a.rec[3 * (size_t)g1 + 1];
+        qb2 = a.rec[3 * (size_t)g1 + 2];
+        gb = a.vals[min(j0 + 192u, jl)];
+    }
+    // one chunk of 64 list entries starting at b0 whose records are in
+    // (q0, q1, q2); returns true once every pixel of the quadrant stopped
+    auto chunk = [&](uint32_t b0, float4 &q0, float4 &q1, float4 &q2, uint32_t &gn) -> bool {
+        const uint32_t j = b0 + lane;
+        const bool hit = (j < range.y) && entry_reaches_box(q0.x, q0.y, q1.x, q1.y, q1.z, q1.w, a.alpha_min,
+                                                           bx0, by0, bx0 + 7.0f, by0 + 7.0f);
+        // the whole record set has arrived here on every path, so the
+        // in-place refill below never waits on its old loads
+        asm volatile("" ::"v"(q0.z), "v"(q0.w), "v"(q2.x), "v"(q2.y), "v"(q2.z));
+        const uint64_t bal = __ballot(hit);
+        if (hit) {
+            const int pos = __popcll(bal & lt_mask);
+            const Entry e = make_entry(q0, q1, q2);
+            e0s[pos] = make_float4(e.u, e.v, e.a, e.b);
+            e1s[pos] = make_float4(e.c, e.o, e.z, e.r);
+            e2s[pos] = make_float4(e.g, e.bl, __uint_as_float(b0 - range.x + (uint32_t)lane + 1u), 0.0f);
+        }
+        // refill: the records of chunk c + 2, the list values of c + 4
+        q0 = a.rec[3 * (size_t)gn];
+        q1 = a.rec[3 * (size_t)gn + 1];
+        q2 = a.rec[3 * (size_t)gn + 2];
+        gn = a.vals[min(j + 256u, jl)];
+        __builtin_amdgcn_wave_barrier();
+        const int n = __popcll(bal);
+        // pad the list to a multiple of 4 with entries of zero opacity
+        // (alpha 0: always skipped)
+        if (lane < ((4 - (n & 3)) & 3)) {
+            e0s[n + lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            e1s[n + lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            e2s[n + lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
+        __builtin_amdgcn_wave_barrier();
+        // Uniform trip count, four entries per step (their LDS reads are
+        // issued together, ahead of the arithmetic); the per-lane skip /
+        // stop / done decisions are predicates, with no divergent exits.
+        // T (1 - alpha) is one fused multiply-add, fma(-alpha, T, T): a
+        // single rounding of the exact product, where T - (alpha T) would
+        // round alpha T first and lose up to alpha / (1 - alpha) ulps
+        // (99 at the alpha clamp) -- error the backward's recovery
+        // T_i = T_{i+1} / (1 - alpha_i) would carry over whole lists.
+        for (int q = 0; q < n; q += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const float4 e0 = e0s[q + u], e1 = e1s[q + u], e2 = e2s[q + u];
+                const float dx = fx - e0.x, dy = fy - e0.y;
+                const float p2 = entry_power2(e0.z, e0.w, e1.x, dx, dy);
+                const float al = fminf(amax, e1.y * fast_exp2(p2));
+                const float w = al * T;
+                const float Tn = fmaf(-al, T, T);
+                const bool take = !done && !(al < a.alpha_min);
+                const bool stop = take && (Tn < a.t_min);
+                const bool use = take && !stop;
+                const float ws = use ? w : 0.0f;
+                cr = fmaf(ws, e1.w, cr);
+                cg = fmaf(ws, e2.x, cg);
+                cb = fmaf(ws, e2.y, cb);
+                dd = fmaf(ws, e1.z, dd);
+                T = use ? Tn : T;
+                last = use ? __float_as_uint(e2.z) : last;
+                done = done || stop;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        // segment checkpoint at the end of this chunk (a multiple of the
+        // segment length inside the list): T and the colour so far
+        done_end = b0 - range.x + 64u;
+        if (a.ckpt && done_end % kSegment == 0u && done_end < range.y - range.x) {
+            const uint64_t slot = (range.x + done_end) / kSegment;
+            if (slot < a.ckpt_slots) {
+                a.ckpt[ckpt_index(slot, quad, 0, lane)] = T;
+                a.ckpt[ckpt_index(slot, quad, 1, lane)] = cr;
+                a.ckpt[ckpt_index(slot, quad, 2, lane)] = cg;
+                a.ckpt[ckpt_index(slot, quad, 3, lane)] = cb;
+                a.ckpt[ckpt_index(slot, quad, 4, lane)] = dd;
+            }
+        }
+        return __ballot(!done) == 0ull;
+    };
+    for (uint32_t b0 = range.x; b0 < range.y; b0 += 128) {
+        if (chunk(b0, qa0, qa1, qa2, ga)) break;
+        if (b0 + 64 >= range.y) break;
+        if (chunk(b0 + 64, qb0, qb1, qb2, gb)) break;
+    }
+    // the checkpoints crossed become (T_b, what is still to come behind b
+    // -- the final colour, background included, minus the colour so far --
+    // divided by T_b)
+    if (a.ckpt) {
+        for (uint32_t b = kSegment; b < done_end && b < range.y - range.x; b += kSegment) {
+            const uint64_t slot = (range.x + b) / kSegment;
+            if (slot >= a.ckpt_slots) break;
+            float *c = a.ckpt;
+            const float tb = c[ckpt_index(slot, quad, 0, lane)];
+            const float inv = 1.0f / tb;
+            c[ckpt_index(slot, quad, 1, lane)] = (cr - c[ckpt_index(slot, quad, 1, lane)] + T * a.bg0) * inv;
+            c[ckpt_index(slot, quad, 2, lane)] = (cg - c[ckpt_index(slot, quad, 2, lane)] + T * a.bg1) * inv;
+            c[ckpt_index(slot, quad, 3, lane)] = (cb - c[ckpt_index(slot, quad, 3, lane)] + T * a.bg2) * inv;
+            c[ckpt_index(slot, quad, 4, lane)] = (dd - c[ckpt_index(slot, quad, 4, lane)]) * inv;
+        }
+    }
+    if (inside) {
+        const size_t pix = ((size_t)view * a.H + py) * a.W + px;
+        a.rgb[3 * pix + 0] = cr + T * a.bg0;
+        a.rgb[3 * pix + 1] = cg + T * a.bg1;
+        a.rgb[3 * pix + 2] = cb + T * a.bg2;
+        a.depth[pix] = dd;
+        a.alpha[pix] = 1.0f - T;
+        if (a.t_final) a.t_final[pix] = T;
+        if (a.n_contrib) a.n_contrib[pix] = last;
+    }
+    __builtin_amdgcn_s_setprio(0);
+}
+
 __global__ void __launch_bounds__(64 * kWavesPerGroup) composite_kernel(const CompositeArgs a) {
     __shared__ float4 s_e0[kWavesPerGroup][64], s_e1[kWavesPerGroup][64], s_e2[kWavesPerGroup][64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -86,159 +246,7 @@ __global__ void __launch_bounds__(64 * kWavesPerGroup) composite_kernel(const Co
         long long item = lane == 0 ? pop_item(a, home, visited) : -1;
         item = __shfl(item, 0, 64);
         if (item < 0) break;
-        const int64_t titem = item >> 2;
-        const int quad = (int)(item & 3);
-        const int view = (int)(titem / a.T);
-        const int tile = (int)(titem - (int64_t)view * a.T);
-        const int qx0 = (tile % a.TX) * kTile + ((quad & 1) << 3);
-        const int qy0 = (tile / a.TX) * kTile + ((quad >> 1) << 3);
-        const int px = qx0 + (lane & 7), py = qy0 + (lane >> 3);
-        const bool inside = px < a.W && py < a.H;
-        const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
-        const float bx0 = (float)qx0 + 0.5f, by0 = (float)qy0 + 0.5f;
-        const uint2 range = a.ranges[titem];
-        // Waves of long lists get a higher issue priority on their SIMD: the
-        // longest lists bound the kernel's duration, and shorter ones fill
-        // the issue slots those leave while they wait on memory.
-        set_wave_priority(range.y - range.x);
-        float T = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f, dd = 0.0f;
-        const float amax = __builtin_canonicalizef(a.alpha_max);  // keeps the clamp's operand out of the loop
-        uint32_t last = 0;
-        uint32_t done_end = 0;  // list position after the last chunk walked
-        bool done = !inside;
-        // software pipeline over the list chunks, two deep: the records of
-        // chunks c and c + 1 sit in two register sets and the list values of
-        // c + 2 and c + 3 are in flight; once chunk c's records have been
-        // culled and staged, its set is refilled in place with chunk c + 2
-        float4 qa0, qa1, qa2, qb0, qb1, qb2;  // records of this lane's entry in chunks c, c + 1
-        uint32_t ga = 0u, gb = 0u;            // list values of its entries in chunks c + 2, c + 3
-        // every load is unconditional: a lane past the list's end reads the
-        // list's last entry again (a cache hit), so a refill overwrites its
-        // whole register set and needs no merge with the old contents
-        const uint32_t jl = range.y > range.x ? range.y - 1u : range.x;
-        if (range.y > range.x) {
-            const uint32_t j0 = range.x + lane;
-            const uint32_t g0 = a.vals[min(j0, jl)], g1 = a.vals[min(j0 + 64u, jl)];
-            // issued in the order the loop refills them
-            qa0 = a.rec[3 * (size_t)g0];
-            qa1 = a.rec[3 * (size_t)g0 + 1];
-            qa2 = a.rec[3 * (size_t)g0 + 2];
-            ga = a.vals[min(j0 + 128u, jl)];
-            qb0 = a.rec[3 * (size_t)g1];
-            qb1 = a.rec[3 * (size_t)g1 + 1];
-            qb2 = a.rec[3 * (size_t)g1 + 2];
-            gb = a.vals[min(j0 + 192u, jl)];
-        }
-        // one chunk of 64 list entries starting at b0 whose records are in
-        // (q0, q1, q2); returns true once every pixel of the quadrant stopped
-        auto chunk = [&](uint32_t b0, float4 &q0, float4 &q1, float4 &q2, uint32_t &gn) -> bool {
-            const uint32_t j = b0 + lane;
-            const bool hit = (j < range.y) && entry_reaches_box(q0.x, q0.y, q1.x, q1.y, q1.z, q1.w, a.alpha_min,
-                                                               bx0, by0, bx0 + 7.0f, by0 + 7.0f);
-            // the whole record set has arrived here on every path, so the
-            // in-place refill below never waits on its old loads
-            asm volatile("" ::"v"(q0.z), "v"(q0.w), "v"(q2.x), "v"(q2.y), "v"(q2.z));
-            const uint64_t bal = __ballot(hit);
-            if (hit) {
-                const int pos = __popcll(bal & lt_mask);
-                const Entry e = make_entry(q0, q1, q2);
-                e0s[pos] = make_float4(e.u, e.v, e.a, e.b);
-                e1s[pos] = make_float4(e.c, e.o, e.z, e.r);
-                e2s[pos] = make_float4(e.g, e.bl, __uint_as_float(b0 - range.x + (uint32_t)lane + 1u), 0.0f);
-            }
-            // refill: the records of chunk c + 2, the list values of c + 4
-            q0 = a.rec[3 * (size_t)gn];
-            q1 = a.rec[3 * (size_t)gn + 1];
-            q2 = a.rec[3 * (size_t)gn + 2];
-            gn = a.vals[min(j + 256u, jl)];
-            __builtin_amdgcn_wave_barrier();
-            const int n = __popcll(bal);
-            // pad the list to a multiple of 4 with entries of zero opacity
-            // (alpha 0: always skipped)
-            if (lane < ((4 - (n & 3)) & 3)) {
-                e0s[n + lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                e1s[n + lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                e2s[n + lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            }
-            __builtin_amdgcn_wave_barrier();
-            // Uniform trip count, four entries per step (their LDS reads are
-            // issued together, ahead of the arithmetic); the per-lane skip /
-            // stop / done decisions are predicates, with no divergent exits.
-            // T (1 - alpha) is one fused multiply-add, fma(-alpha, T, T): a
-            // single rounding of the exact product, where T - (alpha T) would
-            // round alpha T first and lose up to alpha / (1 - alpha) ulps
-            // (99 at the alpha clamp) -- error the backward's recovery
-            // T_i = T_{i+1} / (1 - alpha_i) would carry over whole lists.
-            for (int q = 0; q < n; q += 4) {
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const float4 e0 = e0s[q + u], e1 = e1s[q + u], e2 = e2s[q + u];
-                    const float dx = fx - e0.x, dy = fy - e0.y;
-                    const float p2 = entry_power2(e0.z, e0.w, e1.x, dx, dy);
-                    const float al = fminf(amax, e1.y * fast_exp2(p2));
-                    const float w = al * T;
-                    const float Tn = fmaf(-al, T, T);
-                    const bool take = !done && !(al < a.alpha_min);
-                    const bool stop = take && (Tn < a.t_min);
-                    const bool use = take && !stop;
-                    const float ws = use ? w : 0.0f;
-                    cr = fmaf(ws, e1.w, cr);
-                    cg = fmaf(ws, e2.x, cg);
-                    cb = fmaf(ws, e2.y, cb);
-                    dd = fmaf(ws, e1.z, dd);
-                    T = use ? Tn : T;
-                    last = use ? __float_as_uint(e2.z) : last;
-                    done = done || stop;
-                }
-            }
-            __builtin_amdgcn_wave_barrier();
-            // segment checkpoint at the end of this chunk (a multiple of the
-            // segment length inside the list): T and the colour so far
-            done_end = b0 - range.x + 64u;
-            if (a.ckpt && done_end % kSegment == 0u && done_end < range.y - range.x) {
-                const uint64_t slot = (range.x + done_end) / kSegment;
-                if (slot < a.ckpt_slots) {
-                    a.ckpt[ckpt_index(slot, quad, 0, lane)] = T;
-                    a.ckpt[ckpt_index(slot, quad, 1, lane)] = cr;
-                    a.ckpt[ckpt_index(slot, quad, 2, lane)] = cg;
-                    a.ckpt[ckpt_index(slot, quad, 3, lane)] = cb;
-                    a.ckpt[ckpt_index(slot, quad, 4, lane)] = dd;
-                }
-            }
-            return __ballot(!done) == 0ull;
-        };
-        for (uint32_t b0 = range.x; b0 < range.y; b0 += 128) {
-            if (chunk(b0, qa0, qa1, qa2, ga)) break;
-            if (b0 + 64 >= range.y) break;
-            if (chunk(b0 + 64, qb0, qb1, qb2, gb)) break;
-        }
-        // the checkpoints crossed become (T_b, what is still to come behind b
-        // -- the final colour, background included, minus the colour so far --
-        // divided by T_b)
-        if (a.ckpt) {
-            for (uint32_t b = kSegment; b < done_end && b < range.y - range.x; b += kSegment) {
-                const uint64_t slot = (range.x + b) / kSegment;
-                if (slot >= a.ckpt_slots) break;
-                float *c = a.ckpt;
-                const float tb = c[ckpt_index(slot, quad, 0, lane)];
-                const float inv = 1.0f / tb;
-                c[ckpt_index(slot, quad, 1, lane)] = (cr - c[ckpt_index(slot, quad, 1, lane)] + T * a.bg0) * inv;
-                c[ckpt_index(slot, quad, 2, lane)] = (cg - c[ckpt_index(slot, quad, 2, lane)] + T * a.bg1) * inv;
-                c[ckpt_index(slot, quad, 3, lane)] = (cb - c[ckpt_index(slot, quad, 3, lane)] + T * a.bg2) * inv;
-                c[ckpt_index(slot, quad, 4, lane)] = (dd - c[ckpt_index(slot, quad, 4, lane)]) * inv;
-            }
-        }
-        if (inside) {
-            const size_t pix = ((size_t)view * a.H + py) * a.W + px;
-            a.rgb[3 * pix + 0] = cr + T * a.bg0;
-            a.rgb[3 * pix + 1] = cg + T * a.bg1;
-            a.rgb[3 * pix + 2] = cb + T * a.bg2;
-            a.depth[pix] = dd;
-            a.alpha[pix] = 1.0f - T;
-            if (a.t_final) a.t_final[pix] = T;
-            if (a.n_contrib) a.n_contrib[pix] = last;
-        }
-        __builtin_amdgcn_s_setprio(0);
+        walk_one(a, item, e0s, e1s, e2s, lane, lt_mask);
     }
     leave(a);
 }
