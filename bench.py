@@ -220,7 +220,8 @@ def bench_forward(args, dev):
     stages["composite"] = composite_ms
     counts = _frame_counts(f, 1, r.T, W * H, D, N, N)
     info = {"stage_ms": stages, "counts": counts, "ms_eager": ms_eager,
-            "n_contrib_sum": int(f.n_contrib.to(torch.int64).sum().item())}
+            "n_contrib_sum": int(f.n_contrib.to(torch.int64).sum().item()),
+            "layout_ab": layout_ab(r, g, cams, vs, f, dev)}
     return ms_graph, info
 
 
@@ -411,6 +412,34 @@ def bench_avatars(args, dev, steps, want_pairs=True):
     lbs_ms = {k: _event_ms(fn, 20 * steps) for k, fn in (("fixed", lbs), ("clip", lbs_clip))}
     return {"ms": ms, "ms_eager": ms_eager, "ms_bwd": ms_b, "n_views": len(vs), "lbs_ms": lbs_ms, "n_av": n_av,
             "roofline_fwd": roof_f, "roofline_fwd_bwd": roof_b}
+
+
+def _planar(g):
+    """The segment g (numpy rows) component-major, every attribute [components][n]."""
+    n = len(g["means"])
+    out = {"sh_degree": g["sh_degree"], "layout": "planes"}
+    for k in ("means", "log_scales", "quats", "cov6", "opacity", "sh"):
+        if g.get(k) is not None:
+            a = np.asarray(g[k], np.float32).reshape(n, -1)
+            out[k] = np.ascontiguousarray(a.T if a.shape[1] > 1 else a[:, 0])
+    return out
+
+
+def layout_ab(r, g, cams, vs, f, dev, reps=20):
+    """Projection of the same Gaussians stored in rows and in planes (device
+    time per launch, HIP events); the records must agree bit for bit."""
+    import torch
+    rows, planes = [to_dev(g, dev)], [to_dev(_planar(g), dev)]
+    r.project(rows, cams, vs, f)
+    tt0, rec0 = f.tiles_touched.clone(), f.rec.clone()
+    r.project(planes, cams, vs, f)
+    torch.cuda.synchronize()
+    vis = (tt0 > 0).nonzero().squeeze(1)
+    assert torch.equal(tt0, f.tiles_touched) and torch.equal(rec0[vis], f.rec[vis])
+    ms_r = _event_ms(lambda: r.project(rows, cams, vs, f), reps)
+    ms_p = _event_ms(lambda: r.project(planes, cams, vs, f), reps)
+    r.project(rows, cams, vs, f)
+    return {"rows_ms": ms_r, "planes_ms": ms_p}
 
 
 def _event_ms(fn, reps):
@@ -645,7 +674,8 @@ def main():
     extras = {"stage_ms": st, "eager_fps": 1e3 / info["ms_eager"], "N": counts["N"], "visible": counts["n_vis"],
               "tile_instances": counts["K"],
               "stage_hbm_frac": {k: stages_alg[k]["bytes"] / (st[k] * 1e-3) / 1e9 / HBM_PEAK_GBS for k in st},
-              "frame_roofline": roofline_block(counts, ms, pair_src)}
+              "frame_roofline": roofline_block(counts, ms, pair_src),
+              "project_layout_ab": info["layout_ab"]}
     if not args.profile and not args.no_extras:
         steps2 = max(5, args.steps // 5)
         log("fwd+bwd: 256x256, 500k Gaussians")

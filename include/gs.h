@@ -51,7 +51,11 @@
  *  - Layouts.  Row-major, one row per Gaussian: means [n][3],
  *    log_scales [n][3], quats [n][4] as (w, x, y, z), opacity [n] (activated,
  *    in (0,1)), sh [n][(D+1)^2][3] (real SH, Condon-Shortley phase, l-major,
- *    m = -l..l), cov6 [n][6] as (xx, xy, xz, yy, yz, zz).  Images are
+ *    m = -l..l), cov6 [n][6] as (xx, xy, xz, yy, yz, zz).  gs_project
+ *    also takes a segment in planes (layout GS_LAYOUT_PLANES), component-
+ *    major: means [3][n], log_scales [3][n], quats [4][n], cov6 [6][n],
+ *    opacity [n], sh [3 (D+1)^2][n] (plane 3 k + channel); gs_render_backward
+ *    returns GS_ERR_UNSUPPORTED for such a segment.  Images are
  *    [view][y][x] with RGB interleaved: rgb [V][H][W][3], depth [V][H][W],
  *    alpha [V][H][W].  Dtypes are FP32 except where noted.
  *  - Instances.  One call renders V views.  Each view draws a set of
@@ -121,11 +125,16 @@ typedef struct gs_params {
 } gs_params;
 
 /* One gaussian segment (device pointers).  If cov6 is non-NULL it gives the
- * 3D covariance directly (posed avatars) and log_scales/quats are ignored. */
+ * 3D covariance directly (posed avatars) and log_scales/quats are ignored.
+ * layout: GS_LAYOUT_ROWS (0, one row per Gaussian) or GS_LAYOUT_PLANES (1,
+ * one plane per component; gs_project only), see Layouts above; any other
+ * value is GS_ERR_INVALID_ARGUMENT. */
+#define GS_LAYOUT_ROWS 0
+#define GS_LAYOUT_PLANES 1
 typedef struct gs_gaussians {
     int64_t n;
     int32_t sh_degree; /* 0..3 */
-    int32_t reserved;
+    int32_t layout;
     const float *means, *log_scales, *quats, *cov6, *opacity, *sh;
 } gs_gaussians;
 

@@ -38,7 +38,7 @@ class Params(ctypes.Structure):
 
 
 class Gaussians(ctypes.Structure):
-    _fields_ = [("n", ctypes.c_int64), ("sh_degree", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    _fields_ = [("n", ctypes.c_int64), ("sh_degree", ctypes.c_int32), ("layout", ctypes.c_int32),
                 ("means", P), ("log_scales", P), ("quats", P), ("cov6", P), ("opacity", P), ("sh", P)]
 
 
@@ -170,11 +170,15 @@ def _req(t, dtype, what):
 
 
 def make_segment(g):
-    """gs_gaussians for a dict of device tensors (means, log_scales, quats, opacity, sh[, cov6], sh_degree)."""
+    """gs_gaussians for a dict of device tensors (means, log_scales, quats,
+    opacity, sh[, cov6], sh_degree[, layout]).  layout "planes" (gs_project
+    only): every attribute component-major, means [3][n], sh [3 (D+1)^2][n]."""
     for k in ("means", "log_scales", "quats", "opacity", "sh", "cov6"):
         _req(g.get(k), torch.float32, k)
+    planes = g.get("layout", "rows") == "planes"
     s = Gaussians()
-    s.n = int(g["means"].shape[0])
+    s.n = int(g["means"].shape[1] if planes else g["means"].shape[0])
+    s.layout = 1 if planes else 0
     s.sh_degree = int(g["sh_degree"])
     s.means = ptr(g["means"])
     s.log_scales = ptr(g.get("log_scales"))

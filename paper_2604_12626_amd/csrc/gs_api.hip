@@ -58,17 +58,21 @@ gs_status check_segments(const gs_gaussians *segs, int32_t n_segs) {
         if (g.n < 0) return fail(GS_ERR_INVALID_ARGUMENT, "segment %d: n < 0", s);
         if (g.sh_degree < 0 || g.sh_degree > GS_MAX_SH_DEGREE)
             return fail(GS_ERR_INVALID_ARGUMENT, "segment %d: sh_degree %d outside [0, 3]", s, g.sh_degree);
+        if (g.layout != GS_LAYOUT_ROWS && g.layout != GS_LAYOUT_PLANES)
+            return fail(GS_ERR_INVALID_ARGUMENT, "segment %d: layout %d (rows 0 or planes 1)", s, g.layout);
         if (g.n == 0) continue;
         if (!g.means || !g.opacity || !g.sh)
             return fail(GS_ERR_INVALID_ARGUMENT, "segment %d: means/opacity/sh is NULL", s);
         if (!g.cov6 && (!g.log_scales || !g.quats))
             return fail(GS_ERR_INVALID_ARGUMENT, "segment %d: needs cov6 or log_scales + quats", s);
-        if (!g.cov6 && !aligned(g.quats, 16))
+        const bool rows = g.layout == GS_LAYOUT_ROWS;
+        if (rows && !g.cov6 && !aligned(g.quats, 16))
             return fail(GS_ERR_INVALID_ARGUMENT, "segment %d: quats must be 16-byte aligned", s);
         const int K3 = 3 * (g.sh_degree + 1) * (g.sh_degree + 1);
-        if (K3 % 4 == 0 && !aligned(g.sh, 16))
+        if (rows && K3 % 4 == 0 && !aligned(g.sh, 16))
             return fail(GS_ERR_INVALID_ARGUMENT, "segment %d: sh must be 16-byte aligned", s);
-        if (!aligned(g.means, 4) || !aligned(g.opacity, 4) || !aligned(g.sh, 4) || (g.cov6 && !aligned(g.cov6, 4)))
+        if (!aligned(g.means, 4) || !aligned(g.opacity, 4) || !aligned(g.sh, 4) || (g.cov6 && !aligned(g.cov6, 4)) ||
+            (!g.cov6 && (!aligned(g.quats, 4) || !aligned(g.log_scales, 4))))
             return fail(GS_ERR_INVALID_ARGUMENT, "segment %d: arrays must be 4-byte aligned", s);
     }
     return GS_OK;
@@ -564,6 +568,9 @@ gs_status gs_render_backward(const gs_gaussians *segs, int32_t n_segs, const gs_
         return fail(GS_ERR_INVALID_ARGUMENT, "proj->n_instances does not match the views");
     if (ws_bytes < gs_render_backward_workspace(proj->n_instances))
         return fail(GS_ERR_WORKSPACE_TOO_SMALL, "workspace too small");
+    for (int s = 0; s < n_segs; ++s)
+        if (segs[s].layout != GS_LAYOUT_ROWS)
+            return fail(GS_ERR_UNSUPPORTED, "segment %d: the backward takes rows (layout 0)", s);
     for (int s = 0; s < n_segs; ++s) {
         if (segs[s].n == 0) continue;
         const gs_gaussians_grad &g = grads[s];

@@ -5,12 +5,14 @@
 // HBM once.  Attribute reads are row-per-Gaussian (means 12 B, scales 12 B,
 // quats 16 B, SH 12 (D+1)^2 B contiguous), so a Gaussian culled in every view
 // never pulls its SH rows (the 32 B of rotation, scales and opacity are read
-// with the mean, to overlap their latency).
+// with the mean, to overlap their latency).  PLANES: the same reads from a
+// segment stored component-major (plane k of an attribute at k n), where
+// each load of a wave is one coalesced stretch of a plane.
 #include "gs_ewa.hpp"
 
 namespace gs {
 
-template <int D>
+template <int D, bool PLANES>
 __global__ void __launch_bounds__(256) project_kernel(const ProjectArgs a) {
     constexpr int K = (D + 1) * (D + 1);
     __shared__ float s_cam[kProjViews * kCamStride];
@@ -28,9 +30,12 @@ __global__ void __launch_bounds__(256) project_kernel(const ProjectArgs a) {
     __syncthreads();
 
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= a.seg.n) return;
+    const int64_t n = a.seg.n;
+    if (i >= n) return;
+    // component k of Gaussian i in an attribute of w components
+    auto at = [&](const float *p, int w, int k) { return PLANES ? p[(int64_t)k * n + i] : p[w * i + k]; };
 
-    const float mx = a.seg.means[3 * i + 0], my = a.seg.means[3 * i + 1], mz = a.seg.means[3 * i + 2];
+    const float mx = at(a.seg.means, 3, 0), my = at(a.seg.means, 3, 1), mz = at(a.seg.means, 3, 2);
     // the small attribute rows (rotation, scales, opacity: 32 B) are requested
     // together with the mean, so their latency overlaps; the SH rows are read
     // only once the Gaussian is known to land in a view
@@ -39,11 +44,14 @@ __global__ void __launch_bounds__(256) project_kernel(const ProjectArgs a) {
     float S[6];
     if (a.seg.cov6) {
 #pragma unroll
-        for (int k = 0; k < 6; ++k) S[k] = a.seg.cov6[6 * i + k];
+        for (int k = 0; k < 6; ++k) S[k] = at(a.seg.cov6, 6, k);
     } else {
-        q4 = reinterpret_cast<const float4 *>(a.seg.quats)[i];
+        if (PLANES)
+            q4 = make_float4(at(a.seg.quats, 4, 0), at(a.seg.quats, 4, 1), at(a.seg.quats, 4, 2), at(a.seg.quats, 4, 3));
+        else
+            q4 = reinterpret_cast<const float4 *>(a.seg.quats)[i];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) ls[k] = a.seg.log_scales[3 * i + k];
+        for (int k = 0; k < 3; ++k) ls[k] = at(a.seg.log_scales, 3, k);
     }
     const float opac = a.seg.opacity[i];
     // near-plane test from the mean alone: a Gaussian behind every camera of
@@ -70,7 +78,7 @@ __global__ void __launch_bounds__(256) project_kernel(const ProjectArgs a) {
         return;
     }
 
-    const float *shp = a.seg.sh + (size_t)(3 * K) * i;
+    const float *shp = a.seg.sh + (PLANES ? (size_t)i : (size_t)(3 * K) * i);
     for (int vi = 0; vi < a.nv; ++vi) {
         const int64_t inst = a.base[vi] + i;
         const float *cam = s_cam + vi * kCamStride;
@@ -92,7 +100,10 @@ __global__ void __launch_bounds__(256) project_kernel(const ProjectArgs a) {
         // later views of the same Gaussian hit the caches), accumulated per
         // channel in basis order
         float col[3] = {0.0f, 0.0f, 0.0f};
-        if ((3 * K) % 4 == 0) {
+        if (PLANES) {
+#pragma unroll
+            for (int f = 0; f < 3 * K; ++f) col[f % 3] += Y[f / 3] * shp[(int64_t)f * n];
+        } else if ((3 * K) % 4 == 0) {
 #pragma unroll
             for (int k4 = 0; k4 < 3 * K / 4; ++k4) {
                 const float4 t = reinterpret_cast<const float4 *>(shp)[k4];
@@ -120,11 +131,19 @@ __global__ void __launch_bounds__(256) project_kernel(const ProjectArgs a) {
 hipError_t launch_project(const ProjectArgs &a, hipStream_t s) {
     if (a.seg.n == 0 || a.nv == 0) return hipSuccess;
     const unsigned grid = (unsigned)((a.seg.n + 255) / 256);
+    if (a.seg.layout == GS_LAYOUT_PLANES) {
+        switch (a.seg.sh_degree) {
+            case 0: return launch_kernel(project_kernel<0, true>, dim3(grid), dim3(256), s, a);
+            case 1: return launch_kernel(project_kernel<1, true>, dim3(grid), dim3(256), s, a);
+            case 2: return launch_kernel(project_kernel<2, true>, dim3(grid), dim3(256), s, a);
+            default: return launch_kernel(project_kernel<3, true>, dim3(grid), dim3(256), s, a);
+        }
+    }
     switch (a.seg.sh_degree) {
-        case 0: return launch_kernel(project_kernel<0>, dim3(grid), dim3(256), s, a);
-        case 1: return launch_kernel(project_kernel<1>, dim3(grid), dim3(256), s, a);
-        case 2: return launch_kernel(project_kernel<2>, dim3(grid), dim3(256), s, a);
-        default: return launch_kernel(project_kernel<3>, dim3(grid), dim3(256), s, a);
+        case 0: return launch_kernel(project_kernel<0, false>, dim3(grid), dim3(256), s, a);
+        case 1: return launch_kernel(project_kernel<1, false>, dim3(grid), dim3(256), s, a);
+        case 2: return launch_kernel(project_kernel<2, false>, dim3(grid), dim3(256), s, a);
+        default: return launch_kernel(project_kernel<3, false>, dim3(grid), dim3(256), s, a);
     }
 }
 

@@ -91,6 +91,11 @@ def test_validation_rejects_bad_arguments_without_a_gpu(lib):
     p2 = B.make_params(0, 64)
     assert lib.gs_project(ctypes.byref(seg), 1, cams, 1, mask, ctypes.byref(p2), ctypes.byref(out), None) == \
         B.GS_ERR_INVALID_ARGUMENT
+    # an unknown layout
+    seg.layout = 2
+    assert lib.gs_project(ctypes.byref(seg), 1, cams, 1, mask, ctypes.byref(p), ctypes.byref(out), None) == \
+        B.GS_ERR_INVALID_ARGUMENT
+    assert "layout" in _err(lib)
 
 
 def test_bin_sort_capacity_and_workspace_errors(lib):

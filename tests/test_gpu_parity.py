@@ -450,6 +450,55 @@ def test_composite_pairs_bit_identical(dev):
         B.set_tuning(**prev)
 
 
+def _planes(g):
+    """The same segment component-major: every attribute [components][n]."""
+    n = len(g["means"])
+    out = {"sh_degree": g["sh_degree"], "layout": "planes"}
+    for k in ("means", "log_scales", "quats", "cov6", "opacity", "sh"):
+        if g.get(k) is not None:
+            a = np.asarray(g[k], np.float32).reshape(n, -1)
+            out[k] = np.ascontiguousarray(a.T if a.shape[1] > 1 else a[:, 0])
+    return out
+
+
+def test_project_planes_equals_rows(dev):
+    """A segment stored component-major (planes) projects to exactly the
+    records of the same segment stored in rows -- a scene with rotations and
+    scales and a segment given by covariances -- and so renders the same
+    images; the backward refuses a planar segment."""
+    import torch
+    from paper_2604_12626_amd import binding as B, render
+    rng = np.random.default_rng(91)
+    W, H = 256, 192
+    scene = synth.gaussians_room(30000, rng, sh_degree=3)
+    n2 = 5000
+    A = rng.normal(0.0, 0.03, (n2, 3, 3)).astype(np.float64)
+    S = A @ np.transpose(A, (0, 2, 1)) + 1e-5 * np.eye(3)
+    cov = np.stack([S[:, 0, 0], S[:, 0, 1], S[:, 0, 2], S[:, 1, 1], S[:, 1, 2], S[:, 2, 2]], 1).astype(np.float32)
+    other = synth.gaussians_room(n2, rng, sh_degree=1)
+    covseg = {"means": other["means"], "cov6": cov, "opacity": other["opacity"], "sh": other["sh"], "sh_degree": 1}
+    cams = torch.from_numpy(np.stack([synth.camera_room(rng, W, H) for _ in range(2)])).to(dev)
+    vs = [[0, 1], [0, 1]]
+    out = []
+    for layout in ("rows", "planes"):
+        segs = [scene, covseg] if layout == "rows" else [_planes(scene), _planes(covseg)]
+        r = render.Renderer(W, H, capacity=1 << 20, device=dev)
+        f = r.render([to_dev(g, dev) for g in segs], cams, vs)
+        torch.cuda.synchronize()
+        out.append((f.tiles_touched.clone(), f.rec.clone(), f.rgb.clone(), f.depth.clone(), f.n_contrib.clone(), r, f))
+    tt0 = out[0][0]
+    assert int((tt0 > 0).sum().item()) > 1000
+    vis = (tt0 > 0).nonzero().squeeze(1)
+    assert torch.equal(out[0][0], out[1][0])
+    assert torch.equal(out[0][1][vis], out[1][1][vis])
+    for a, b in zip(out[0][2:5], out[1][2:5]):
+        assert torch.equal(a, b)
+    r, f = out[1][5], out[1][6]
+    planar = [to_dev(g, dev) for g in (_planes(scene), _planes(covseg))]
+    with pytest.raises(B.GSError):
+        r.backward(planar, cams, vs, f, torch.zeros_like(f.rgb), None, None)
+
+
 def test_union_equals_concatenation(dev):
     import torch
     from paper_2604_12626_amd import render
