@@ -584,10 +584,7 @@ gs_status gs_render_backward(const gs_gaussians *segs, int32_t n_segs, const gs_
     double *g2d = static_cast<double *>(ws);
     uint32_t *list = reinterpret_cast<uint32_t *>(static_cast<char *>(ws) + bwd_list_offset(proj->n_instances));
     uint32_t *counts = reinterpret_cast<uint32_t *>(static_cast<char *>(ws) + bwd_count_offset(proj->n_instances));
-    // only the drawn instances' accumulators are used, so only those are
-    // cleared, together with the list counters
-    hipError_t e = gs::launch_clear_g2d(proj->tiles_touched, proj->n_instances, g2d, counts, kBwdMaxLaunches, sm);
-    if (e != hipSuccess) return hip_fail(e, "gs_render_backward");
+    hipError_t e;
     int launch_no = 0;
     gs::BackwardTileArgs b = {};
     b.rec = reinterpret_cast<const float4 *>(proj->rec);
@@ -609,6 +606,13 @@ gs_status gs_render_backward(const gs_gaussians *segs, int32_t n_segs, const gs_
     b.TX = tiles_x(p);
     b.T = tiles_x(p) * tiles_y(p);
     b.n_items = (int64_t)b.T * n_views;
+    if (b.seg_list && b.n_items >= (int64_t)1 << 26) b.seg_list = nullptr;  // item ids need 26 bits
+    // only the drawn instances' accumulators are used, so only those are
+    // cleared, together with the list counters; the same launch builds the
+    // tile pass's segment list
+    e = gs::launch_clear_g2d(proj->tiles_touched, proj->n_instances, g2d, counts, kBwdMaxLaunches, b.ranges,
+                             b.n_items, b.seg_list, (uint64_t)(b.ckpt_slots * gs::kListPerSlot), sm);
+    if (e != hipSuccess) return hip_fail(e, "gs_render_backward");
     b.alpha_max = p->alpha_max;
     b.alpha_min = p->alpha_min;
     b.bg0 = p->bg[0];

@@ -337,14 +337,16 @@ __global__ void __launch_bounds__(kTilePixels, 5) backward_tile_kernel(const Bac
     for (int z = 0; z < a.n_zero; ++z) zero_span_grid(a.zero_ptr[z], a.zero_n[z]);
 }
 
-// The backward's work list (one workgroup): for every (view, tile) list of
-// L > 0 entries its ceil(L / seg_len_of(L)) <= kMaxSegments segments, as
-// (item << 6 | segment) in item order, after their count; at most `cap`.
-__global__ void __launch_bounds__(1024) segment_list_kernel(const uint2 *ranges, int64_t n_items, uint32_t *list,
-                                                            uint64_t cap) {
-    __shared__ uint32_t s_w[16];
+// The backward's work list, built by one workgroup of NT threads: for every
+// (view, tile) list of L > 0 entries its ceil(L / seg_len_of(L)) <=
+// kMaxSegments segments, as (item << 6 | segment) in item order, after their
+// count; at most `cap`.
+template <int NT>
+__device__ __forceinline__ void build_segment_list(const uint2 *ranges, int64_t n_items, uint32_t *list,
+                                                   uint64_t cap) {
+    __shared__ uint32_t s_w[NT / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t per = (n_items + 1023) / 1024;
+    const int64_t per = (n_items + NT - 1) / NT;
     const int64_t t0 = (int64_t)tid * per, t1 = (t0 + per < n_items) ? t0 + per : n_items;
     auto n_seg = [](uint2 r) -> uint32_t {
         const uint32_t L = r.y - r.x;
@@ -361,7 +363,7 @@ __global__ void __launch_bounds__(1024) segment_list_kernel(const uint2 *ranges,
     if (lane == 63) s_w[wave] = incl;
     __syncthreads();
     uint64_t pos = incl - cnt, total = 0u;
-    for (int k = 0; k < 16; ++k) {
+    for (int k = 0; k < NT / 64; ++k) {
         if (k < wave) pos += s_w[k];
         total += s_w[k];
     }
@@ -375,7 +377,6 @@ __global__ void __launch_bounds__(1024) segment_list_kernel(const uint2 *ranges,
 
 hipError_t launch_backward_tiles(BackwardTileArgs a, int n_cu, hipStream_t s) {
     if (a.n_items == 0) return hipSuccess;
-    if (a.seg_list && a.n_items >= (int64_t)1 << 26) a.seg_list = nullptr;  // item ids need 26 bits
     if (!a.seg_list) {  // one workgroup per list
         a.n_groups = (uint32_t)a.n_items;
         // many lists (more than the GPU holds at once): fewer global atomics
@@ -385,9 +386,7 @@ hipError_t launch_backward_tiles(BackwardTileArgs a, int n_cu, hipStream_t s) {
                                  a);
         return launch_kernel(backward_tile_kernel<false, false>, dim3((unsigned)a.n_items), dim3(kTilePixels), s, a);
     }
-    hipError_t e = launch_kernel(segment_list_kernel, dim3(1), dim3(1024), s, a.ranges, a.n_items, a.seg_list,
-                                 (uint64_t)(a.ckpt_slots * kListPerSlot));
-    if (e != hipSuccess) return e;
+    // the work list was built by the accumulator clear (launch_clear_g2d)
     a.n_groups = (uint32_t)(6 * n_cu);  // persistent: about what the CUs hold at once
     return launch_kernel(backward_tile_kernel<true, true>, dim3(a.n_groups), dim3(kTilePixels), s, a);
 }
@@ -705,13 +704,17 @@ __global__ void __launch_bounds__(256) backward_project_kernel(const BackwardPro
 }
 
 // The screen-space accumulators of the drawn instances start at zero; B1
-// adds only to those and B2 reads only those.
+// adds only to those and B2 reads only those.  Workgroup 0 also zeroes the
+// list counters and, with checkpoints, builds the tile pass's segment list.
 __global__ void __launch_bounds__(256) clear_g2d_kernel(const uint32_t *tt, int64_t n, double *g2d,
-                                                        uint32_t *counts, int n_counts) {
+                                                        uint32_t *counts, int n_counts, const uint2 *ranges,
+                                                        int64_t n_items, uint32_t *seg_list, uint64_t seg_cap) {
     static_assert(kG2D % 2 == 0, "two accumulators per 16-B store");
     constexpr uint32_t P = kG2D / 2;  // 16-B pieces per instance
-    if (blockIdx.x == 0)
+    if (blockIdx.x == 0) {
         for (int k = threadIdx.x; k < n_counts; k += 256) counts[k] = 0u;
+        if (seg_list) build_segment_list<256>(ranges, n_items, seg_list, seg_cap);
+    }
     // a block of 256 instances at a time, its 256 P pieces spread over the
     // threads, so that each store instruction writes consecutive 16-B pieces
     for (int64_t base = (int64_t)blockIdx.x * 256; base < n; base += (int64_t)gridDim.x * 256) {
@@ -725,12 +728,13 @@ __global__ void __launch_bounds__(256) clear_g2d_kernel(const uint32_t *tt, int6
 }
 
 hipError_t launch_clear_g2d(const uint32_t *tiles_touched, int64_t n_instances, double *g2d, uint32_t *counts,
-                            int n_counts, hipStream_t s) {
+                            int n_counts, const uint2 *ranges, int64_t n_items, uint32_t *seg_list, uint64_t seg_cap,
+                            hipStream_t s) {
     int64_t grid = (n_instances + 255) / 256;
     if (grid > 8192) grid = 8192;
     if (grid < 1) grid = 1;
     return launch_kernel(clear_g2d_kernel, dim3((unsigned)grid), dim3(256), s, tiles_touched, n_instances, g2d,
-                         counts, n_counts);
+                         counts, n_counts, ranges, n_items, seg_list, seg_cap);
 }
 
 hipError_t launch_backward_project(const BackwardProjectArgs &a, hipStream_t s) {

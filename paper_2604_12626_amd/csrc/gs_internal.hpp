@@ -215,7 +215,8 @@ hipError_t launch_backward_project(const BackwardProjectArgs &a, hipStream_t s);
 // zeroes the screen-space accumulators of the drawn instances (tiles_touched
 // > 0) and the n_counts list counters
 hipError_t launch_clear_g2d(const uint32_t *tiles_touched, int64_t n_instances, double *g2d, uint32_t *counts,
-                            int n_counts, hipStream_t s);
+                            int n_counts, const uint2 *ranges, int64_t n_items, uint32_t *seg_list, uint64_t seg_cap,
+                            hipStream_t s);  // seg_list: the tile pass's work list, built too when non-NULL
 hipError_t launch_lbs(const LbsArgs &a, bool backward, hipStream_t s);
 hipError_t launch_lbs_joint_grad(const LbsArgs &a, float *d_skin, int n_cu, hipStream_t s);
 hipError_t launch_fk(const FkArgs &a, hipStream_t s);
