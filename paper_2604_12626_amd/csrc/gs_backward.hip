@@ -532,11 +532,23 @@ __global__ void __launch_bounds__(256) backward_project_kernel(const BackwardPro
         for (int k = 0; k < 3 * K; ++k) sh[k] = src[k];
     }
 
-    for (int vi = 0; vi < a.nv; ++vi) {
+    // the views that draw it, their counts requested together (a listed
+    // Gaussian is drawn by one of the launch's views: with one view, by that
+    // one); then the drawn views in ascending order
+    uint64_t drawn = 1u;
+    if (a.nv > 1) {
+        drawn = 0u;
+        for (int v0 = 0; v0 < a.nv; v0 += 16) {
+            uint32_t t[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) t[k] = v0 + k < a.nv ? a.tiles_touched[a.base[v0 + k] + i] : 0u;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) drawn |= (uint64_t)(t[k] != 0u) << (v0 + k);
+        }
+    }
+    for (uint64_t m = drawn; m; m &= m - 1u) {
+        const int vi = __ffsll((unsigned long long)m) - 1;
         const int64_t inst = a.base[vi] + i;
-        // a listed Gaussian is drawn by one of the launch's views: with one
-        // view, by that one
-        if (a.nv > 1 && a.tiles_touched[inst] == 0u) continue;
         const double *g = a.g2d + (size_t)inst * kG2D;
         double gl[kG2D];
 #pragma unroll
