@@ -341,6 +341,9 @@ __global__ void __launch_bounds__(kTilePixels, 5) backward_tile_kernel(const Bac
 // (view, tile) list of L > 0 entries its ceil(L / seg_len_of(L)) <=
 // kMaxSegments segments, as (item << 6 | segment) in item order, after their
 // count; at most `cap`.
+// lists up to which the accumulator clear's first workgroup (256 threads)
+// builds the segment list; more get a 1024-thread launch of their own
+constexpr int64_t kListInClear = 2048;
 template <int NT>
 __device__ __forceinline__ void build_segment_list(const uint2 *ranges, int64_t n_items, uint32_t *list,
                                                    uint64_t cap) {
@@ -375,6 +378,12 @@ __device__ __forceinline__ void build_segment_list(const uint2 *ranges, int64_t 
     if (tid == 0) list[0] = (uint32_t)(total < cap ? total : cap);
 }
 
+// the segment list of a launch with many lists: one 1024-thread workgroup
+__global__ void __launch_bounds__(1024) segment_list_kernel(const uint2 *ranges, int64_t n_items, uint32_t *list,
+                                                            uint64_t cap) {
+    build_segment_list<1024>(ranges, n_items, list, cap);
+}
+
 hipError_t launch_backward_tiles(BackwardTileArgs a, int n_cu, hipStream_t s) {
     if (a.n_items == 0) return hipSuccess;
     if (!a.seg_list) {  // one workgroup per list
@@ -386,7 +395,13 @@ hipError_t launch_backward_tiles(BackwardTileArgs a, int n_cu, hipStream_t s) {
                                  a);
         return launch_kernel(backward_tile_kernel<false, false>, dim3((unsigned)a.n_items), dim3(kTilePixels), s, a);
     }
-    // the work list was built by the accumulator clear (launch_clear_g2d)
+    // the work list: built by the accumulator clear for up to kListInClear
+    // lists, else here
+    if (a.n_items > kListInClear) {
+        const hipError_t e = launch_kernel(segment_list_kernel, dim3(1), dim3(1024), s, a.ranges, a.n_items,
+                                           a.seg_list, (uint64_t)(a.ckpt_slots * kListPerSlot));
+        if (e != hipSuccess) return e;
+    }
     a.n_groups = (uint32_t)(6 * n_cu);  // persistent: about what the CUs hold at once
     return launch_kernel(backward_tile_kernel<true, true>, dim3(a.n_groups), dim3(kTilePixels), s, a);
 }
@@ -717,7 +732,8 @@ __global__ void __launch_bounds__(256) backward_project_kernel(const BackwardPro
 
 // The screen-space accumulators of the drawn instances start at zero; B1
 // adds only to those and B2 reads only those.  Workgroup 0 also zeroes the
-// list counters and, with checkpoints, builds the tile pass's segment list.
+// list counters and, with checkpoints and at most kListInClear lists, builds
+// the tile pass's segment list.
 __global__ void __launch_bounds__(256) clear_g2d_kernel(const uint32_t *tt, int64_t n, double *g2d,
                                                         uint32_t *counts, int n_counts, const uint2 *ranges,
                                                         int64_t n_items, uint32_t *seg_list, uint64_t seg_cap) {
@@ -725,7 +741,7 @@ __global__ void __launch_bounds__(256) clear_g2d_kernel(const uint32_t *tt, int6
     constexpr uint32_t P = kG2D / 2;  // 16-B pieces per instance
     if (blockIdx.x == 0) {
         for (int k = threadIdx.x; k < n_counts; k += 256) counts[k] = 0u;
-        if (seg_list) build_segment_list<256>(ranges, n_items, seg_list, seg_cap);
+        if (seg_list && n_items <= kListInClear) build_segment_list<256>(ranges, n_items, seg_list, seg_cap);
     }
     // a block of 256 instances at a time, its 256 P pieces spread over the
     // threads, so that each store instruction writes consecutive 16-B pieces

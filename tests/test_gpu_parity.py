@@ -594,6 +594,36 @@ def test_segmented_backward_matches_whole_lists(dev):
     grad_check(say, out[True][1], ref, ("means", "log_scales", "quats", "opacity", "sh"), label="segmented vs oracle")
 
 
+def test_segmented_backward_many_lists(dev):
+    """Checkpoints forced on a launch of more than 2048 lists (9 views of
+    256x256: the segment list gets a launch of its own instead of being built
+    by the accumulator clear): the segmented backward equals the whole-list
+    walk up to rounding."""
+    import torch
+    from paper_2604_12626_amd import render
+    cfg = synth.config(2, scale=0.2)
+    W, H = cfg["W"], cfg["H"]
+    g = to_dev(cfg["segments"][0], dev)
+    rng = np.random.default_rng(33)
+    V = 9
+    cams = torch.from_numpy(np.stack([synth.camera_room(rng, W, H, fx=128.0) for _ in range(V)]).astype(F32)).to(dev)
+    G = [torch.from_numpy(rng.standard_normal(sh).astype(F32)).to(dev) for sh in ((V, H, W, 3), (V, H, W), (V, H, W))]
+    out = {}
+    for ck in (False, True):
+        r = render.Renderer(W, H, capacity=1 << 21, device=dev, checkpoints=ck)
+        f = r.render([g], cams, [[0]] * V)
+        assert (f.ckpt is not None) == ck
+        d = r.backward([g], cams, [[0]] * V, f, *G)[0]
+        torch.cuda.synchronize()
+        out[ck] = {k: v.cpu().numpy().astype(np.float64) for k, v in d.items()}
+        lens = (f.ranges[:, 1] - f.ranges[:, 0]).cpu().numpy()
+    assert len(lens) > 2048 and lens.max() > 64
+    for k, ref in out[False].items():
+        err = np.abs(out[True][k] - ref).max() / max(np.abs(ref).max(), 1e-30)
+        say("  %s: max |seg - whole| / max |whole| = %.2e" % (k, err))
+        assert err <= 1e-4, (k, err)
+
+
 def test_lbs_parity(dev, orc):
     import torch
     from paper_2604_12626_amd import binding as B
