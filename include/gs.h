@@ -452,6 +452,11 @@ size_t gs_render_backward_workspace(int64_t n_instances);
  *  sized for a smaller capacity than the binning's) walks from the end of
  *  its list instead, adding only its own entries: the same gradients,
  *  slower.
+ *  tile_order: the work order gs_bin_sort wrote for tile_ranges, or NULL.
+ *  Without checkpoints each list is walked by one workgroup; with the order
+ *  the workgroups take the lists longest first (queue by queue), so that the
+ *  longest walks start at once; NULL takes them in (view, tile) order.  The
+ *  gradients do not depend on it.
  *  grads: host array of n_segs gradient descriptors (device pointers),
  *  overwritten (zeros for a Gaussian no view draws).  ws: per-instance
  *  screen-space accumulators (FP64, 16-byte aligned: a large Gaussian sums
@@ -460,10 +465,10 @@ size_t gs_render_backward_workspace(int64_t n_instances);
  * Errors: as gs_project, plus GS_ERR_WORKSPACE_TOO_SMALL. */
 gs_status gs_render_backward(const gs_gaussians *segs, int32_t n_segs, const gs_camera *cams, int32_t n_views,
                              const uint32_t *view_seg_mask, const gs_params *p, const gs_projected *proj,
-                             const uint32_t *vals, const uint32_t *tile_ranges, const float *t_final,
-                             const uint32_t *n_contrib, float *ckpt, size_t ckpt_floats, const float *d_rgb,
-                             const float *d_depth, const float *d_alpha, void *ws, size_t ws_bytes,
-                             const gs_gaussians_grad *grads, gs_stream_t stream);
+                             const uint32_t *vals, const uint32_t *tile_ranges, const uint32_t *tile_order,
+                             const float *t_final, const uint32_t *n_contrib, float *ckpt, size_t ckpt_floats,
+                             const float *d_rgb, const float *d_depth, const float *d_alpha, void *ws,
+                             size_t ws_bytes, const gs_gaussians_grad *grads, gs_stream_t stream);
 
 /* ---------------------------------------------------------------------- */
 /* avatar capsule queries (Sec. 3.3 dynamic NavMesh blocking, Sec. 3.4)    */

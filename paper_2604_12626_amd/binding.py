@@ -116,7 +116,7 @@ def load():
     lib.gs_render_backward_workspace.restype = sz
     lib.gs_render_backward_workspace.argtypes = [i64]
     lib.gs_render_backward.argtypes = [ctypes.POINTER(Gaussians), i32, P, i32, P, ctypes.POINTER(Params),
-                                       ctypes.POINTER(Projected), P, P, P, P, P, sz, P, P, P, P, sz,
+                                       ctypes.POINTER(Projected), P, P, P, P, P, P, sz, P, P, P, P, sz,
                                        ctypes.POINTER(GaussiansGrad), P]
     lib.gs_sensor_compose.argtypes = [i32, i32, i32, P, P, P, P, P, P, P, P]
     f32 = ctypes.c_float
@@ -276,7 +276,7 @@ def render_backward_workspace(n_instances):
 
 
 def render_backward(segs, cams, view_segs, params, tiles_touched, rec, vals, ranges, t_final, n_contrib, d_rgb,
-                    d_depth, d_alpha, ws, grads, ckpt=None):
+                    d_depth, d_alpha, ws, grads, ckpt=None, order=None):
     """grads: list (per segment) of dicts of output tensors (means, log_scales, quats, cov6, opacity, sh)."""
     lib = load()
     arr = seg_array(segs)
@@ -287,7 +287,8 @@ def render_backward(segs, cams, view_segs, params, tiles_touched, rec, vals, ran
                                 ptr(g.get("opacity")), ptr(g.get("sh")))
     proj = Projected(int(rec.shape[0]), ptr(tiles_touched), ptr(rec))
     _check(lib.gs_render_backward(arr, len(segs), ptr(cams), len(view_segs), masks, ctypes.byref(params),
-                                  ctypes.byref(proj), ptr(vals), ptr(ranges), ptr(t_final), ptr(n_contrib), ptr(ckpt),
+                                  ctypes.byref(proj), ptr(vals), ptr(ranges), ptr(order), ptr(t_final),
+                                  ptr(n_contrib), ptr(ckpt),
                                   0 if ckpt is None else ckpt.numel(), ptr(d_rgb), ptr(d_depth), ptr(d_alpha), ptr(ws),
                                   ws.numel() * ws.element_size(), garr, stream_handle()))
 

@@ -550,10 +550,10 @@ size_t gs_render_backward_workspace(int64_t n_instances) {
 
 gs_status gs_render_backward(const gs_gaussians *segs, int32_t n_segs, const gs_camera *cams, int32_t n_views,
                              const uint32_t *view_seg_mask, const gs_params *p, const gs_projected *proj,
-                             const uint32_t *vals, const uint32_t *tile_ranges, const float *t_final,
-                             const uint32_t *n_contrib, float *ckpt, size_t ckpt_floats, const float *d_rgb,
-                             const float *d_depth, const float *d_alpha, void *ws, size_t ws_bytes,
-                             const gs_gaussians_grad *grads, gs_stream_t stream) {
+                             const uint32_t *vals, const uint32_t *tile_ranges, const uint32_t *tile_order,
+                             const float *t_final, const uint32_t *n_contrib, float *ckpt, size_t ckpt_floats,
+                             const float *d_rgb, const float *d_depth, const float *d_alpha, void *ws,
+                             size_t ws_bytes, const gs_gaussians_grad *grads, gs_stream_t stream) {
     clear_error();
     gs_status st;
     if ((st = check_params(p)) != GS_OK) return st;
@@ -561,7 +561,8 @@ gs_status gs_render_backward(const gs_gaussians *segs, int32_t n_segs, const gs_
     if ((st = check_views(cams, n_views, view_seg_mask, n_segs)) != GS_OK) return st;
     if (!proj || !vals || !tile_ranges || !t_final || !n_contrib || !ws || !grads)
         return fail(GS_ERR_INVALID_ARGUMENT, "NULL argument");
-    if (!aligned(ckpt, 4) || !aligned(ws, 16)) return fail(GS_ERR_INVALID_ARGUMENT, "ckpt or ws misaligned");
+    if (!aligned(ckpt, 4) || !aligned(ws, 16) || !aligned(tile_order, 4))
+        return fail(GS_ERR_INVALID_ARGUMENT, "ckpt, tile_order or ws misaligned");
     std::vector<int64_t> off(n_views + 1);
     instance_offsets(segs, n_segs, n_views, view_seg_mask, off.data());
     if (proj->n_instances != off[n_views])
@@ -601,6 +602,7 @@ gs_status gs_render_backward(const gs_gaussians *segs, int32_t n_segs, const gs_
     // the work list lives behind the checkpoints (the backward's own part of the buffer)
     b.seg_list = b.ckpt ? reinterpret_cast<uint32_t *>(ckpt + b.ckpt_slots * gs::kCkptSlotFloats)
                         : nullptr;
+    b.order = tile_order;
     b.W = p->width;
     b.H = p->height;
     b.TX = tiles_x(p);

@@ -96,7 +96,13 @@ __global__ void __launch_bounds__(kTilePixels, 5) backward_tile_kernel(const Bac
     }
     for (uint32_t wk = blockIdx.x; wk < n_work; wk += a.n_groups) {
     const uint32_t entry = a.seg_list ? a.seg_list[1 + wk] : 0u;
-    const int64_t item = a.seg_list ? (int64_t)(entry >> 6) : (int64_t)wk;
+    // whole lists with the work order: workgroup wk takes entry wk / 8 of
+    // queue wk mod 8 (queue q holds the lists t = q mod 8, longest first, so
+    // this maps the workgroups one to one onto the lists)
+    const int64_t item = a.seg_list ? (int64_t)(entry >> 6)
+                         : a.order  ? (int64_t)a.order[(int64_t)(wk % kOrderQueues) * order_stride(a.n_items) +
+                                                       wk / kOrderQueues]
+                                    : (int64_t)wk;
     const uint32_t s = a.seg_list ? (entry & 63u) : 0u;
     const int view = (int)(item / a.T);
     const int tile = (int)(item - (int64_t)view * a.T);

@@ -108,6 +108,7 @@ struct BackwardTileArgs {
     const float *ckpt;   // segment checkpoints, or null (one walk per list)
     uint64_t ckpt_slots;
     uint32_t *seg_list;  // (item << 6 | segment) of every segment to walk, after a count
+    const uint32_t *order;  // whole lists: the binning's work order (longest first per queue), or null
     uint32_t n_groups;   // workgroups of the persistent grid (set by the launcher)
     int64_t n_items;
     int32_t W, H, TX, T;

@@ -157,7 +157,7 @@ class Renderer:
             grads.append(d)
         ws = self._buf("bwd_ws", ((B.render_backward_workspace(f.n_inst) + 3) // 4,), torch.float32)
         B.render_backward(segs, cams, view_segs, self.params, f.tiles_touched, f.rec, f.vals, f.ranges, f.t_final,
-                          f.n_contrib, d_rgb, d_depth, d_alpha, ws, grads, ckpt=f.ckpt)
+                          f.n_contrib, d_rgb, d_depth, d_alpha, ws, grads, ckpt=f.ckpt, order=f.order)
         return grads
 
 

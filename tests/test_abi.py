@@ -98,6 +98,20 @@ def test_validation_rejects_bad_arguments_without_a_gpu(lib):
     assert "layout" in _err(lib)
 
 
+def test_render_backward_validation(lib):
+    """The backward's argument list as the header declares it (the work
+    order after the ranges), and its host validation, without a GPU."""
+    from paper_2604_12626_amd import binding as B
+    p = B.make_params(64, 64)
+    out = B.Projected(10, ctypes.c_void_p(0x5000), ctypes.c_void_p(0x6000))
+    mask = (ctypes.c_uint32 * 1)(1)
+    args = [None, 0, ctypes.c_void_p(0x4000), 1, mask, ctypes.byref(p), ctypes.byref(out), None, None, None, None,
+            None, None, 0, None, None, None, None, 0, None, None]
+    assert lib.gs_render_backward(*args) == B.GS_ERR_INVALID_ARGUMENT
+    with pytest.raises(TypeError):
+        lib.gs_render_backward(*args[:-1])
+
+
 def test_bin_sort_capacity_and_workspace_errors(lib):
     from paper_2604_12626_amd import binding as B
     p = B.make_params(640, 480)
