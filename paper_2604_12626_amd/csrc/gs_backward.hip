@@ -489,227 +489,255 @@ __global__ void __launch_bounds__(1024) zero_and_list_kernel(const BackwardProje
                 (uint32_t)(g0 + c * 1024 + threadIdx.x);
 }
 
-// B2b: one thread per listed Gaussian
+// B2b: a workgroup of two waves per 64 listed Gaussians.  Wave 0 takes the
+// geometry (the FP32 projection repeated for its clamp decisions, then the
+// chain in FP64 to the mean and covariance, and the opacity), wave 1 the
+// colour (SH coefficients, and the view direction's share of the mean's
+// gradient, handed to wave 0 through LDS): two chains of half the length,
+// each holding about half the registers.
 template <int D>
-__global__ void __launch_bounds__(256) backward_project_kernel(const BackwardProjectArgs a) {
+__global__ void __launch_bounds__(128) backward_project_kernel(const BackwardProjectArgs a) {
     constexpr int K = (D + 1) * (D + 1);
     __shared__ float s_cam[kProjViews * kCamStride];
-    for (int k = threadIdx.x; k < a.nv * 16; k += 256) {
+    __shared__ double s_dmu[3][64];
+    const uint32_t count = *a.count;
+    if ((int64_t)blockIdx.x * 64 >= (int64_t)count) return;  // uniform per workgroup
+    for (int k = threadIdx.x; k < a.nv * 16; k += 128) {
         const int vi = k >> 4, f = k & 15;
         s_cam[vi * kCamStride + f] = reinterpret_cast<const float *>(a.cams + a.view[vi])[f];
     }
     __syncthreads();
-    for (int vi = threadIdx.x; vi < a.nv; vi += 256) {
+    for (int vi = threadIdx.x; vi < a.nv; vi += 128) {
         float *c = s_cam + vi * kCamStride;
 #pragma unroll
         for (int j = 0; j < 3; ++j) c[16 + j] = -(c[j] * c[9] + c[3 + j] * c[10] + c[6 + j] * c[11]);
     }
     __syncthreads();
-    const int64_t li = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (li >= (int64_t)*a.count) return;
-    const int64_t i = a.list[li];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t li = (int64_t)blockIdx.x * 64 + lane;
+    const bool valid = li < (int64_t)count;
+    const int64_t i = valid ? (int64_t)a.list[li] : 0;
     const bool use_cov6 = a.seg.cov6 != nullptr;
-
-    // FP32 as in the forward where its decisions are repeated (projection,
-    // clamps, colour clamp, SH); FP64 along the chain from the conic back to
-    // the covariance and the mean, where an elongated Gaussian's adjoints
-    // cancel strongly
-    const float mx = a.seg.means[3 * i + 0], my = a.seg.means[3 * i + 1], mz = a.seg.means[3 * i + 2];
-    float S[6];
-    double Sd[6], scd[3] = {0.0, 0.0, 0.0};
-    RotT<double> rotd;
-    if (use_cov6) {
-#pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            S[k] = a.seg.cov6[6 * i + k];
-            Sd[k] = (double)S[k];
-        }
-    } else {
-        const float4 q = reinterpret_cast<const float4 *>(a.seg.quats)[i];
-        const Rot rot = quat_rot(q.x, q.y, q.z, q.w);
-        float sc[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const float ls = a.seg.log_scales[3 * i + k];
-            sc[k] = expf(ls);
-            scd[k] = exp((double)ls);
-        }
-        cov_from_rot_scale(rot.R, sc, S);
-        rotd = quat_rot_t<double>((double)q.x, (double)q.y, (double)q.z, (double)q.w);
-        cov_from_rot_scale(rotd.R, scd, Sd);
-    }
-
-    double dmu[3] = {0.0, 0.0, 0.0};
-    double dS[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // symmetric adjoint of Sigma (xx, xy, xz, yy, yz, zz)
-    float dsh[3 * K];
-#pragma unroll
-    for (int k = 0; k < 3 * K; ++k) dsh[k] = 0.f;
-    float dop = 0.f;
-    // every listed Gaussian is drawn: its SH rows are requested with the rest
-    float sh[3 * K];
-    {
-        const float *src = a.seg.sh + (size_t)(3 * K) * i;
-#pragma unroll
-        for (int k = 0; k < 3 * K; ++k) sh[k] = src[k];
-    }
-
-    // the views that draw it, their counts requested together (a listed
-    // Gaussian is drawn by one of the launch's views: with one view, by that
-    // one); then the drawn views in ascending order
-    uint64_t drawn = 1u;
-    if (a.nv > 1) {
-        drawn = 0u;
-        for (int v0 = 0; v0 < a.nv; v0 += 16) {
-            uint32_t t[16];
-#pragma unroll
-            for (int k = 0; k < 16; ++k) t[k] = v0 + k < a.nv ? a.tiles_touched[a.base[v0 + k] + i] : 0u;
-#pragma unroll
-            for (int k = 0; k < 16; ++k) drawn |= (uint64_t)(t[k] != 0u) << (v0 + k);
-        }
-    }
-    for (uint64_t m = drawn; m; m &= m - 1u) {
-        const int vi = __ffsll((unsigned long long)m) - 1;
-        const int64_t inst = a.base[vi] + i;
-        const double *g = a.g2d + (size_t)inst * kG2D;
-        double gl[kG2D];
-#pragma unroll
-        for (int k = 0; k < kG2D; ++k) gl[k] = g[k];
-        const float *cam = s_cam + vi * kCamStride;
-        ViewProj p;
-        // the same FP32 projection as the forward; the instance is known to be
-        // visible (tiles_touched > 0), so every field used below is computed
-        const int TX = (a.W + kTile - 1) / kTile, TY = (a.H + kTile - 1) / kTile;
-        (void)ewa_project(cam, mx, my, mz, S, a.W, a.H, TX, TY, a.near_plane, a.lowpass, a.sigma_cut, a.fov_clamp, p);
-        dop += (float)gl[kGO];
-        // ---- colour -> SH coefficients and view direction
-        float dx0 = mx - cam[16], dy0 = my - cam[17], dz0 = mz - cam[18];
-        const float inv_dist = 1.0f / sqrtf(dx0 * dx0 + dy0 * dy0 + dz0 * dz0);
-        const float x = dx0 * inv_dist, y = dy0 * inv_dist, z = dz0 * inv_dist;
-        float Y[K];
-        float3 dY[K];
-        sh_basis<D>(x, y, z, Y);
-        sh_basis_grad<D>(x, y, z, dY);
-        float dc[3] = {(float)gl[kGR], (float)gl[kGG], (float)gl[kGBl]};
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-            float acc = 0.0f;  // same accumulation order as the forward
-#pragma unroll
-            for (int k = 0; k < K; ++k) acc += Y[k] * sh[3 * k + ch];
-            if (!(acc + 0.5f > 0.0f)) dc[ch] = 0.0f;
-        }
-        float ddx = 0.f, ddy = 0.f, ddz = 0.f;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const float cdot = dc[0] * sh[3 * k] + dc[1] * sh[3 * k + 1] + dc[2] * sh[3 * k + 2];
-            ddx += cdot * dY[k].x;
-            ddy += cdot * dY[k].y;
-            ddz += cdot * dY[k].z;
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) dsh[3 * k + ch] += dc[ch] * Y[k];
-        }
-        const float dd = x * ddx + y * ddy + z * ddz;
-        dmu[0] += (double)((ddx - x * dd) * inv_dist);
-        dmu[1] += (double)((ddy - y * dd) * inv_dist);
-        dmu[2] += (double)((ddz - z * dd) * inv_dist);
-        // ---- the projection in FP64, with the forward's clamp decisions
-        double R[9];
-#pragma unroll
-        for (int k = 0; k < 9; ++k) R[k] = (double)cam[k];
-        const double fxc = (double)cam[12], fyc = (double)cam[13];
-        const double tx = R[0] * mx + R[1] * my + R[2] * mz + (double)cam[9];
-        const double ty = R[3] * mx + R[4] * my + R[5] * mz + (double)cam[10];
-        const double tz = R[6] * mx + R[7] * my + R[8] * mz + (double)cam[11];
-        const double iz = 1.0 / tz, iz2 = iz * iz;
-        const double limx = (double)a.fov_clamp * (0.5 * (double)a.W / fxc);
-        const double limy = (double)a.fov_clamp * (0.5 * (double)a.H / fyc);
-        const double xr = p.clx ? (tx * iz < 0.0 ? -limx : limx) : tx * iz;
-        const double yr = p.cly ? (ty * iz < 0.0 ? -limy : limy) : ty * iz;
-        const double j00 = fxc * iz, j02 = -fxc * xr * iz, j11 = fyc * iz, j12 = -fyc * yr * iz;
-        double T0[3], T1[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            T0[k] = j00 * R[k] + j02 * R[6 + k];
-            T1[k] = j11 * R[3 + k] + j12 * R[6 + k];
-        }
-        double TS0[3], TS1[3];  // T Sigma
-        TS0[0] = T0[0] * Sd[0] + T0[1] * Sd[1] + T0[2] * Sd[2];
-        TS0[1] = T0[0] * Sd[1] + T0[1] * Sd[3] + T0[2] * Sd[4];
-        TS0[2] = T0[0] * Sd[2] + T0[1] * Sd[4] + T0[2] * Sd[5];
-        TS1[0] = T1[0] * Sd[0] + T1[1] * Sd[1] + T1[2] * Sd[2];
-        TS1[1] = T1[0] * Sd[1] + T1[1] * Sd[3] + T1[2] * Sd[4];
-        TS1[2] = T1[0] * Sd[2] + T1[1] * Sd[4] + T1[2] * Sd[5];
-        const double lp = (double)a.lowpass;
-        const double ca = TS0[0] * T0[0] + TS0[1] * T0[1] + TS0[2] * T0[2] + lp;
-        const double cb = TS0[0] * T1[0] + TS0[1] * T1[1] + TS0[2] * T1[2];
-        const double cc = TS1[0] * T1[0] + TS1[1] * T1[1] + TS1[2] * T1[2] + lp;
-        const double idet = 1.0 / (ca * cc - cb * cb);
-        const double qa = cc * idet, qb = -cb * idet, qc = ca * idet;
-        // ---- conic -> 2D covariance: dS2 = -Q Gm Q, Gm = [[gA, gB/2], [gB/2, gC]]
-        const double ga = gl[kGA], gbh = 0.5 * gl[kGB], gc = gl[kGC];
-        const double m00 = qa * ga + qb * gbh, m01 = qa * gbh + qb * gc;
-        const double m10 = qb * ga + qc * gbh, m11 = qb * gbh + qc * gc;
-        const double s00 = -(m00 * qa + m01 * qb);
-        const double s01 = -(m00 * qb + m01 * qc);
-        const double s11 = -(m10 * qb + m11 * qc);
-        // ---- 2D covariance -> Sigma and T:  S2 = T Sigma T^T + lp I; dSigma += T^T dS2 T
-        double U[3][2];
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            U[r][0] = T0[r] * s00 + T1[r] * s01;
-            U[r][1] = T0[r] * s01 + T1[r] * s11;
-        }
-        dS[0] += U[0][0] * T0[0] + U[0][1] * T1[0];
-        dS[1] += U[0][0] * T0[1] + U[0][1] * T1[1];
-        dS[2] += U[0][0] * T0[2] + U[0][1] * T1[2];
-        dS[3] += U[1][0] * T0[1] + U[1][1] * T1[1];
-        dS[4] += U[1][0] * T0[2] + U[1][1] * T1[2];
-        dS[5] += U[2][0] * T0[2] + U[2][1] * T1[2];
-        // dT = 2 dS2 T Sigma
-        double dT0[3], dT1[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            dT0[c] = 2.0 * (s00 * TS0[c] + s01 * TS1[c]);
-            dT1[c] = 2.0 * (s01 * TS0[c] + s11 * TS1[c]);
-        }
-        // T = J W: dJ = dT W^T;  J00 = fx/z, J02 = -fx xr/z, J11 = fy/z, J12 = -fy yr/z
-        const double dJ00 = dT0[0] * R[0] + dT0[1] * R[1] + dT0[2] * R[2];
-        const double dJ02 = dT0[0] * R[6] + dT0[1] * R[7] + dT0[2] * R[8];
-        const double dJ11 = dT1[0] * R[3] + dT1[1] * R[4] + dT1[2] * R[5];
-        const double dJ12 = dT1[0] * R[6] + dT1[1] * R[7] + dT1[2] * R[8];
-        double dtx = 0.0, dty = 0.0, dtz = 0.0;
-        dtz += -fxc * iz2 * dJ00 - fyc * iz2 * dJ11;
-        dtz += dJ02 * fxc * xr * iz2 + dJ12 * fyc * yr * iz2;
-        if (!p.clx) {
-            dtx += dJ02 * (-fxc * iz) * iz;
-            dtz += dJ02 * (-fxc * iz) * (-tx * iz2);
-        }
-        if (!p.cly) {
-            dty += dJ12 * (-fyc * iz) * iz;
-            dtz += dJ12 * (-fyc * iz) * (-ty * iz2);
-        }
-        // ---- projected mean and depth
-        dtx += gl[kGU] * fxc * iz;
-        dty += gl[kGV] * fyc * iz;
-        dtz += -gl[kGU] * fxc * tx * iz2 - gl[kGV] * fyc * ty * iz2 + gl[kGZ];
-        dmu[0] += R[0] * dtx + R[3] * dty + R[6] * dtz;
-        dmu[1] += R[1] * dtx + R[4] * dty + R[7] * dtz;
-        dmu[2] += R[2] * dtx + R[5] * dty + R[8] * dtz;
-    }
-
     const gs_gaussians_grad &G = a.grad;
     const bool first = a.first != 0;
     auto put = [&](float *dst, float v) {
         if (first) *dst = v;
         else *dst += v;
     };
+    // FP32 as in the forward where its decisions are repeated (projection,
+    // clamps, colour clamp, SH); FP64 along the chain from the conic back to
+    // the covariance and the mean, where an elongated Gaussian's adjoints
+    // cancel strongly
+    float mx = 0.f, my = 0.f, mz = 0.f;
+    // the views that draw it, their counts requested together (a listed
+    // Gaussian is drawn by one of the launch's views: with one view, by that
+    // one); then the drawn views in ascending order
+    uint64_t drawn = 0u;
+    if (valid) {
+        mx = a.seg.means[3 * i + 0];
+        my = a.seg.means[3 * i + 1];
+        mz = a.seg.means[3 * i + 2];
+        drawn = 1u;
+        if (a.nv > 1) {
+            drawn = 0u;
+            for (int v0 = 0; v0 < a.nv; v0 += 16) {
+                uint32_t t[16];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) put(&G.means[3 * i + k], (float)dmu[k]);
-    put(&G.opacity[i], dop);
-    {
-        float *dst = G.sh + (size_t)(3 * K) * i;
+                for (int k = 0; k < 16; ++k) t[k] = v0 + k < a.nv ? a.tiles_touched[a.base[v0 + k] + i] : 0u;
 #pragma unroll
-        for (int k = 0; k < 3 * K; ++k) put(&dst[k], dsh[k]);
+                for (int k = 0; k < 16; ++k) drawn |= (uint64_t)(t[k] != 0u) << (v0 + k);
+            }
+        }
     }
+    if (wave == 1) {
+        // ---- colour -> SH coefficients and view direction
+        float dsh[3 * K];
+#pragma unroll
+        for (int k = 0; k < 3 * K; ++k) dsh[k] = 0.f;
+        double dmd[3] = {0.0, 0.0, 0.0};
+        float sh[3 * K];
+#pragma unroll
+        for (int k = 0; k < 3 * K; ++k) sh[k] = 0.f;
+        if (valid) {
+            const float *src = a.seg.sh + (size_t)(3 * K) * i;
+#pragma unroll
+            for (int k = 0; k < 3 * K; ++k) sh[k] = src[k];
+        }
+        for (uint64_t m = drawn; m; m &= m - 1u) {
+            const int vi = __ffsll((unsigned long long)m) - 1;
+            const double *g = a.g2d + (size_t)(a.base[vi] + i) * kG2D;
+            float dc[3] = {(float)g[kGR], (float)g[kGG], (float)g[kGBl]};
+            const float *cam = s_cam + vi * kCamStride;
+            float dx0 = mx - cam[16], dy0 = my - cam[17], dz0 = mz - cam[18];
+            const float inv_dist = 1.0f / sqrtf(dx0 * dx0 + dy0 * dy0 + dz0 * dz0);
+            const float x = dx0 * inv_dist, y = dy0 * inv_dist, z = dz0 * inv_dist;
+            float Y[K];
+            float3 dY[K];
+            sh_basis<D>(x, y, z, Y);
+            sh_basis_grad<D>(x, y, z, dY);
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                float acc = 0.0f;  // same accumulation order as the forward
+#pragma unroll
+                for (int k = 0; k < K; ++k) acc += Y[k] * sh[3 * k + ch];
+                if (!(acc + 0.5f > 0.0f)) dc[ch] = 0.0f;
+            }
+            float ddx = 0.f, ddy = 0.f, ddz = 0.f;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const float cdot = dc[0] * sh[3 * k] + dc[1] * sh[3 * k + 1] + dc[2] * sh[3 * k + 2];
+                ddx += cdot * dY[k].x;
+                ddy += cdot * dY[k].y;
+                ddz += cdot * dY[k].z;
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) dsh[3 * k + ch] += dc[ch] * Y[k];
+            }
+            const float dd = x * ddx + y * ddy + z * ddz;
+            dmd[0] += (double)((ddx - x * dd) * inv_dist);
+            dmd[1] += (double)((ddy - y * dd) * inv_dist);
+            dmd[2] += (double)((ddz - z * dd) * inv_dist);
+        }
+        if (valid) {
+            float *dst = G.sh + (size_t)(3 * K) * i;
+#pragma unroll
+            for (int k = 0; k < 3 * K; ++k) put(&dst[k], dsh[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) s_dmu[k][lane] = dmd[k];
+    }
+    double dmu[3] = {0.0, 0.0, 0.0};
+    double dS[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // symmetric adjoint of Sigma (xx, xy, xz, yy, yz, zz)
+    float dop = 0.f;
+    double scd[3] = {0.0, 0.0, 0.0};
+    RotT<double> rotd;
+    if (wave == 0 && valid) {
+        float S[6];
+        double Sd[6];
+        if (use_cov6) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                S[k] = a.seg.cov6[6 * i + k];
+                Sd[k] = (double)S[k];
+            }
+        } else {
+            const float4 q = reinterpret_cast<const float4 *>(a.seg.quats)[i];
+            const Rot rot = quat_rot(q.x, q.y, q.z, q.w);
+            float sc[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const float ls = a.seg.log_scales[3 * i + k];
+                sc[k] = expf(ls);
+                scd[k] = exp((double)ls);
+            }
+            cov_from_rot_scale(rot.R, sc, S);
+            rotd = quat_rot_t<double>((double)q.x, (double)q.y, (double)q.z, (double)q.w);
+            cov_from_rot_scale(rotd.R, scd, Sd);
+        }
+        for (uint64_t m = drawn; m; m &= m - 1u) {
+            const int vi = __ffsll((unsigned long long)m) - 1;
+            const double *g = a.g2d + (size_t)(a.base[vi] + i) * kG2D;
+            double gl[kG2D];
+#pragma unroll
+            for (int k = 0; k < kG2D; ++k) gl[k] = g[k];
+            const float *cam = s_cam + vi * kCamStride;
+            ViewProj p;
+            // the same FP32 projection as the forward; the instance is known to
+            // be visible (tiles_touched > 0), so every field used below is
+            // computed
+            const int TX = (a.W + kTile - 1) / kTile, TY = (a.H + kTile - 1) / kTile;
+            (void)ewa_project(cam, mx, my, mz, S, a.W, a.H, TX, TY, a.near_plane, a.lowpass, a.sigma_cut, a.fov_clamp,
+                              p);
+            dop += (float)gl[kGO];
+            // ---- the projection in FP64, with the forward's clamp decisions
+            double R[9];
+    #pragma unroll
+            for (int k = 0; k < 9; ++k) R[k] = (double)cam[k];
+            const double fxc = (double)cam[12], fyc = (double)cam[13];
+            const double tx = R[0] * mx + R[1] * my + R[2] * mz + (double)cam[9];
+            const double ty = R[3] * mx + R[4] * my + R[5] * mz + (double)cam[10];
+            const double tz = R[6] * mx + R[7] * my + R[8] * mz + (double)cam[11];
+            const double iz = 1.0 / tz, iz2 = iz * iz;
+            const double limx = (double)a.fov_clamp * (0.5 * (double)a.W / fxc);
+            const double limy = (double)a.fov_clamp * (0.5 * (double)a.H / fyc);
+            const double xr = p.clx ? (tx * iz < 0.0 ? -limx : limx) : tx * iz;
+            const double yr = p.cly ? (ty * iz < 0.0 ? -limy : limy) : ty * iz;
+            const double j00 = fxc * iz, j02 = -fxc * xr * iz, j11 = fyc * iz, j12 = -fyc * yr * iz;
+            double T0[3], T1[3];
+    #pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                T0[k] = j00 * R[k] + j02 * R[6 + k];
+                T1[k] = j11 * R[3 + k] + j12 * R[6 + k];
+            }
+            double TS0[3], TS1[3];  // T Sigma
+            TS0[0] = T0[0] * Sd[0] + T0[1] * Sd[1] + T0[2] * Sd[2];
+            TS0[1] = T0[0] * Sd[1] + T0[1] * Sd[3] + T0[2] * Sd[4];
+            TS0[2] = T0[0] * Sd[2] + T0[1] * Sd[4] + T0[2] * Sd[5];
+            TS1[0] = T1[0] * Sd[0] + T1[1] * Sd[1] + T1[2] * Sd[2];
+            TS1[1] = T1[0] * Sd[1] + T1[1] * Sd[3] + T1[2] * Sd[4];
+            TS1[2] = T1[0] * Sd[2] + T1[1] * Sd[4] + T1[2] * Sd[5];
+            const double lp = (double)a.lowpass;
+            const double ca = TS0[0] * T0[0] + TS0[1] * T0[1] + TS0[2] * T0[2] + lp;
+            const double cb = TS0[0] * T1[0] + TS0[1] * T1[1] + TS0[2] * T1[2];
+            const double cc = TS1[0] * T1[0] + TS1[1] * T1[1] + TS1[2] * T1[2] + lp;
+            const double idet = 1.0 / (ca * cc - cb * cb);
+            const double qa = cc * idet, qb = -cb * idet, qc = ca * idet;
+            // ---- conic -> 2D covariance: dS2 = -Q Gm Q, Gm = [[gA, gB/2], [gB/2, gC]]
+            const double ga = gl[kGA], gbh = 0.5 * gl[kGB], gc = gl[kGC];
+            const double m00 = qa * ga + qb * gbh, m01 = qa * gbh + qb * gc;
+            const double m10 = qb * ga + qc * gbh, m11 = qb * gbh + qc * gc;
+            const double s00 = -(m00 * qa + m01 * qb);
+            const double s01 = -(m00 * qb + m01 * qc);
+            const double s11 = -(m10 * qb + m11 * qc);
+            // ---- 2D covariance -> Sigma and T:  S2 = T Sigma T^T + lp I; dSigma += T^T dS2 T
+            double U[3][2];
+    #pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                U[r][0] = T0[r] * s00 + T1[r] * s01;
+                U[r][1] = T0[r] * s01 + T1[r] * s11;
+            }
+            dS[0] += U[0][0] * T0[0] + U[0][1] * T1[0];
+            dS[1] += U[0][0] * T0[1] + U[0][1] * T1[1];
+            dS[2] += U[0][0] * T0[2] + U[0][1] * T1[2];
+            dS[3] += U[1][0] * T0[1] + U[1][1] * T1[1];
+            dS[4] += U[1][0] * T0[2] + U[1][1] * T1[2];
+            dS[5] += U[2][0] * T0[2] + U[2][1] * T1[2];
+            // dT = 2 dS2 T Sigma
+            double dT0[3], dT1[3];
+    #pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                dT0[c] = 2.0 * (s00 * TS0[c] + s01 * TS1[c]);
+                dT1[c] = 2.0 * (s01 * TS0[c] + s11 * TS1[c]);
+            }
+            // T = J W: dJ = dT W^T;  J00 = fx/z, J02 = -fx xr/z, J11 = fy/z, J12 = -fy yr/z
+            const double dJ00 = dT0[0] * R[0] + dT0[1] * R[1] + dT0[2] * R[2];
+            const double dJ02 = dT0[0] * R[6] + dT0[1] * R[7] + dT0[2] * R[8];
+            const double dJ11 = dT1[0] * R[3] + dT1[1] * R[4] + dT1[2] * R[5];
+            const double dJ12 = dT1[0] * R[6] + dT1[1] * R[7] + dT1[2] * R[8];
+            double dtx = 0.0, dty = 0.0, dtz = 0.0;
+            dtz += -fxc * iz2 * dJ00 - fyc * iz2 * dJ11;
+            dtz += dJ02 * fxc * xr * iz2 + dJ12 * fyc * yr * iz2;
+            if (!p.clx) {
+                dtx += dJ02 * (-fxc * iz) * iz;
+                dtz += dJ02 * (-fxc * iz) * (-tx * iz2);
+            }
+            if (!p.cly) {
+                dty += dJ12 * (-fyc * iz) * iz;
+                dtz += dJ12 * (-fyc * iz) * (-ty * iz2);
+            }
+            // ---- projected mean and depth
+            dtx += gl[kGU] * fxc * iz;
+            dty += gl[kGV] * fyc * iz;
+            dtz += -gl[kGU] * fxc * tx * iz2 - gl[kGV] * fyc * ty * iz2 + gl[kGZ];
+            dmu[0] += R[0] * dtx + R[3] * dty + R[6] * dtz;
+            dmu[1] += R[1] * dtx + R[4] * dty + R[7] * dtz;
+            dmu[2] += R[2] * dtx + R[5] * dty + R[8] * dtz;
+        }
+    }
+    __syncthreads();  // the colour wave's share of the mean's gradient is in LDS
+    if (wave != 0 || !valid) return;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) put(&G.means[3 * i + k], (float)(dmu[k] + s_dmu[k][lane]));
+    put(&G.opacity[i], dop);
     if (use_cov6) {
         if (G.cov6) {
             // an off-diagonal cov6 entry stands for both symmetric entries
@@ -779,12 +807,12 @@ hipError_t launch_backward_project(const BackwardProjectArgs &a, hipStream_t s) 
                            a, 3 * K)) != hipSuccess)
         return e;
     if (a.nv == 0) return hipSuccess;
-    const unsigned grid = (unsigned)((a.seg.n + 255) / 256);
+    const unsigned grid = (unsigned)((a.seg.n + 63) / 64);  // 64 listed Gaussians per two-wave workgroup
     switch (a.seg.sh_degree) {
-        case 0: return launch_kernel(backward_project_kernel<0>, dim3(grid), dim3(256), s, a);
-        case 1: return launch_kernel(backward_project_kernel<1>, dim3(grid), dim3(256), s, a);
-        case 2: return launch_kernel(backward_project_kernel<2>, dim3(grid), dim3(256), s, a);
-        default: return launch_kernel(backward_project_kernel<3>, dim3(grid), dim3(256), s, a);
+        case 0: return launch_kernel(backward_project_kernel<0>, dim3(grid), dim3(128), s, a);
+        case 1: return launch_kernel(backward_project_kernel<1>, dim3(grid), dim3(128), s, a);
+        case 2: return launch_kernel(backward_project_kernel<2>, dim3(grid), dim3(128), s, a);
+        default: return launch_kernel(backward_project_kernel<3>, dim3(grid), dim3(128), s, a);
     }
 }
 
