@@ -1307,11 +1307,11 @@ __device__ __forceinline__ void copy_block(const uint64_t *src, uint32_t cnt, ui
 // into dst[0, la + lb) with NT threads, CHUNK outputs at a time: the next
 // CHUNK entries of each run are staged in LDS (s holds 2 CHUNK), every
 // thread finds where its stretch of the chunk starts on the merge path by a
-// binary search in LDS and merges it, and thread 0 finds how far the chunk
-// got into A.
-template <int NT, int CHUNK>
+// binary search in LDS and merges it (store(k, entry) for output k), and the
+// thread whose stretch ends the chunk tells how far the chunk got into A.
+template <int NT, int CHUNK, typename Store>
 __device__ __forceinline__ void merge_runs(const uint64_t *A, uint32_t la, const uint64_t *Bv, uint32_t lb,
-                                           uint64_t *dst, uint64_t *s, uint32_t *s_take, uint32_t tid) {
+                                           Store &&store, uint64_t *s, uint32_t *s_take, uint32_t tid) {
     constexpr uint32_t PER = CHUNK / NT;
     uint64_t *sA = s, *sB = s + CHUNK;
     // i = how many of the first d merged entries come from sA[0, na): the
@@ -1337,10 +1337,10 @@ __device__ __forceinline__ void merge_runs(const uint64_t *A, uint32_t la, const
             uint32_t i = split(d0, na, nb), j = d0 - i;
             for (uint32_t d = d0; d < d1; ++d) {
                 const bool take_a = j >= nb || (i < na && sA[i] < sB[j]);
-                dst[i0 + j0 + d] = take_a ? sA[i++] : sB[j++];
+                store(i0 + j0 + d, take_a ? sA[i++] : sB[j++]);
             }
+            if (d1 == m) *s_take = i;  // the thread that ends the chunk knows how far it got into A
         }
-        if (tid == 0) *s_take = split(m, na, nb);
         __syncthreads();
         const uint32_t ta = *s_take;
         i0 += ta;
@@ -1349,23 +1349,46 @@ __device__ __forceinline__ void merge_runs(const uint64_t *A, uint32_t la, const
     }
 }
 
+// Levels of pairwise merging a tile of L > CAP entries takes (runs of CAP
+// entries); with an odd count the runs are sorted into the bucket, else into
+// the key array, so that the last level reads the bucket and writes the keys.
+template <int CAP>
+__device__ __forceinline__ bool runs_in_bucket(uint32_t L) {
+    int levels = 0;
+    for (uint32_t w = (uint32_t)CAP; w < L; w <<= 1) ++levels;
+    return levels & 1;
+}
+
 // A tile of L > CAP entries whose runs of CAP entries are sorted, raw, at
-// keys[b ..]: runs merged pairwise by the workgroup, ping-ponging between the
-// key array and the bucket, then written as keys (tile << 32 | depth bits)
-// and values (s: CAP entries of LDS).
+// bucket[b ..] or keys[b ..] (runs_in_bucket): runs merged pairwise by the
+// workgroup, ping-ponging between the two, the last level writing keys
+// (tile << 32 | depth bits) and values (s: CAP entries of LDS).
 template <int THREADS, int CAP>
 __device__ __forceinline__ void merge_tile_runs(uint64_t *bucket, uint64_t *keys, uint32_t *vals, uint32_t tile,
                                                 uint32_t b, uint32_t L, uint64_t *s, uint32_t *s_take) {
     const uint64_t thi = (uint64_t)tile << 32;
-    uint64_t *src = keys + b, *dst = bucket + b;
+    const bool in_bucket = runs_in_bucket<CAP>(L);
+    uint64_t *src = in_bucket ? bucket + b : keys + b, *dst = in_bucket ? keys + b : bucket + b;
+    uint64_t *kk = keys + b;
+    uint32_t *vv = vals + b;
     for (uint32_t w = (uint32_t)CAP; w < L; w <<= 1) {
+        const bool last = 2u * w >= L;  // one pair left: its merge writes the keys
         for (uint32_t a0 = 0; a0 < L; a0 += 2 * w) {
             const uint32_t la = min(w, L - a0), lb = min(w, L - a0 - la);
-            if (lb == 0u) {
+            if (lb == 0u) {  // never on the last level
                 uint64_t *d = dst + a0;
                 copy_block<THREADS>(src + a0, la, threadIdx.x, [&](uint32_t i, uint64_t x) { d[i] = x; });
+            } else if (last) {
+                merge_runs<THREADS, CAP / 2>(src + a0, la, src + a0 + la, lb,
+                                             [&](uint32_t k, uint64_t c) {
+                                                 kk[a0 + k] = thi | (c >> 32);
+                                                 vv[a0 + k] = (uint32_t)c;
+                                             },
+                                             s, s_take, threadIdx.x);
             } else {
-                merge_runs<THREADS, CAP / 2>(src + a0, la, src + a0 + la, lb, dst + a0, s, s_take, threadIdx.x);
+                uint64_t *d = dst + a0;
+                merge_runs<THREADS, CAP / 2>(src + a0, la, src + a0 + la, lb,
+                                             [&](uint32_t k, uint64_t x) { d[k] = x; }, s, s_take, threadIdx.x);
             }
         }
         __syncthreads();
@@ -1373,14 +1396,6 @@ __device__ __forceinline__ void merge_tile_runs(uint64_t *bucket, uint64_t *keys
         src = dst;
         dst = t;
     }
-    // in place when it ended in the key array: each entry is read before the
-    // same thread rewrites it
-    uint64_t *kk = keys + b;
-    uint32_t *vv = vals + b;
-    copy_block<THREADS>(src, L, threadIdx.x, [&](uint32_t i, uint64_t c) {
-        kk[i] = thi | (c >> 32);
-        vv[i] = (uint32_t)c;
-    });
 }
 
 // One workgroup per item, items taken in rounds from the part of the list
@@ -1425,7 +1440,9 @@ __global__ void __launch_bounds__(THREADS) tile_sort_kernel(uint64_t *bucket, co
             const uint2 tr = run_list[idx];
             const uint32_t b = ranges[2 * tr.x], L = ranges[2 * tr.x + 1] - b, off = tr.y * (uint32_t)CAP;
             merge_sort_lds<THREADS, CAP / THREADS, false>(s, bucket + b + off, min((uint32_t)CAP, L - off), 0ull,
-                                                          nullptr, nullptr, keys + b + off, threadIdx.x);
+                                                          nullptr, nullptr,
+                                                          (runs_in_bucket<CAP>(L) ? bucket : keys) + b + off,
+                                                          threadIdx.x);
         } else {
             const uint32_t tile = sort_list[first + n_huge + (idx - n_runs)];
             const uint32_t b = ranges[2 * tile], L = ranges[2 * tile + 1] - b;
@@ -1433,7 +1450,8 @@ __global__ void __launch_bounds__(THREADS) tile_sort_kernel(uint64_t *bucket, co
             if (CLASS == kSortLong && L > (uint32_t)CAP) {
                 for (uint32_t off = 0; off < L; off += (uint32_t)CAP) {
                     merge_sort_lds<THREADS, IT, false>(s, bucket + b + off, min((uint32_t)CAP, L - off), 0ull, nullptr,
-                                                       nullptr, keys + b + off, threadIdx.x);
+                                                       nullptr, (runs_in_bucket<CAP>(L) ? bucket : keys) + b + off,
+                                                       threadIdx.x);
                     __syncthreads();  // s is reused by the next run
                 }
                 merge_tile_runs<THREADS, CAP>(bucket, keys, vals, tile, b, L, s, &s_take);
